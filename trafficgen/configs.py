@@ -1,0 +1,53 @@
+"""Named synthetic workloads: a stream recipe plus a monitor geometry.
+
+The paper measures on two one-hour CERNET backbone traces that are not
+public here; these seeded streams stand in for them with the paper's known
+shape (theta = 1024, 1-second slices, window k = 300, u = 4 rows, g = 8 SRE
+DRs, g' = 1024 LE DRs) and the sizes of the workloads this library is
+measured on.
+
+Geometry reading: "SRE R x C" means u = R rows of C = v_re * g cells;
+"SLE N cells" means N = u * v_le * g' cells in total.
+"""
+from . import StreamSpec, loguniform_ints
+
+STREAM_SEED = 180310369
+HASH_SEED = 0x5EED000000000000
+
+
+def _monitor(k, theta, u, v_re, g, v_le, G, cfg_no):
+    return dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G,
+                hash_seed=HASH_SEED + cfg_no)
+
+
+def workload(name):
+    """Returns (stream, monitor_kwargs, n_slices) of a named workload."""
+    if name in ("tiny", "tiny_coupled"):
+        # 1 monitor, window 8, 100k pairs/slice for 16 slices, Zipf(1.1) over
+        # 65,536 hosts, 4 planted super points with 2,000 distinct dsts,
+        # SRE 4 x 16,384 cells, SLE 65,536 cells (the coupled companion uses
+        # v_le = v_re so the LE does not saturate)
+        stream = StreamSpec(n_pairs=100_000, n_ranks=65_536, alpha=1.1,
+                            planted=[2000] * 4, window=8, seed=STREAM_SEED + 1)
+        v_le = 16 if name == "tiny" else 2048
+        return stream, _monitor(8, 1024, 4, 2048, 8, v_le, 1024, 1), 16
+    if name in ("backbone", "backbone_paper", "backbone_k16"):
+        # 1 monitor, window 300 slices, 8M pairs/slice, Zipf(1.05) over 2^24
+        # hosts, 200 planted super points with 1k-200k dsts,
+        # SRE 8 x 2^20 cells and SLE 2^24 cells
+        planted = loguniform_ints(1000, 200_000, 200, STREAM_SEED + 2)
+        k = 16 if name == "backbone_k16" else 300
+        stream = StreamSpec(n_pairs=8_000_000, n_ranks=1 << 24, alpha=1.05,
+                            planted=planted, window=k, seed=STREAM_SEED + 2)
+        if name == "backbone_paper":
+            mon = _monitor(k, 1024, 4, 65_536, 8, 65_536, 1024, 2)
+        else:
+            mon = _monitor(k, 1024, 8, 131_072, 8, 2048, 1024, 2)
+        return stream, mon, 320
+    raise KeyError(name)
+
+
+def scaled(stream, n_pairs):
+    """The same stream recipe with fewer pairs per slice (planted kept)."""
+    return StreamSpec(n_pairs=n_pairs, n_ranks=stream.n_ranks, alpha=stream.alpha,
+                      planted=list(stream.planted), window=stream.window, seed=stream.seed)
