@@ -1,0 +1,199 @@
+/*
+ * srla.h -- C ABI of the MI355X (gfx950) SRLA library.
+ *
+ * SRLA (arXiv 1803.10369) detects super points -- hosts of network A that
+ * talk to at least theta distinct hosts of network B inside a sliding window
+ * of k time slices (Section 3.1, Definitions 1-2) -- and estimates their
+ * cardinality.  Every (aip, bip) pair of a slice (Definition "IPpair",
+ * Section 3.2) is scanned into an array of sliding estimators (the SEA of
+ * Section 4.1: u rows of SE, each SE holding a sliding rough estimator SRE
+ * of g distance recorders, a 16-bit super point indicator SI, and a linear
+ * estimator LE of g' distance recorders).  At the end of every slice the
+ * candidate list is finished, every candidate's cardinality is estimated
+ * with the noise-corrected union estimate (Eq8-Eq9, Section 4.2), and the
+ * array is prepared for the next slice (Algorithm 3).
+ *
+ * Every function returns an int status (SRLA_OK or a negative SRLA_E_*) and
+ * never throws.  A monitor is not thread-safe; separate monitors are
+ * independent.  All device work of a monitor is issued on one HIP stream.
+ */
+#ifndef SRLA_H
+#define SRLA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SRLA_OK = 0,
+    SRLA_E_INVAL = -1,     /* bad argument; nothing was changed */
+    SRLA_E_NOMEM = -2,     /* a device or pinned host allocation failed */
+    SRLA_E_CAPACITY = -3,  /* the candidate list outgrew max_candidates */
+    SRLA_E_STATE = -4,     /* the monitor is poisoned by an earlier error */
+    SRLA_E_DEVICE = -5     /* a HIP runtime call failed */
+};
+
+/* srla_dump_state: which array */
+enum { SRLA_DUMP_LE = 0, SRLA_DUMP_RE = 1, SRLA_DUMP_SI = 2 };
+
+/* per-candidate report flags */
+enum {
+    SRLA_FLAG_SUPER = 1,  /* estimate >= threshold: a detected super point */
+    SRLA_FLAG_SAT = 2,    /* Eq9 undefined (union LE full); estimate is +inf */
+    SRLA_FLAG_NEW = 4,    /* inserted into the candidate list in this slice */
+    SRLA_FLAG_KEEP = 8    /* carried into the next slice by Algorithm 3 */
+};
+
+/* srla_config_t.flags */
+enum {
+    SRLA_CFG_TIMING = 1   /* record HIP events around every stage */
+};
+
+/*
+ * SEA geometry (Section 4.1).  Row i of the array holds v_re SEs worth of SI
+ * and SRE and v_le SEs worth of LE; the paper's SE is v_re == v_le.  The
+ * distance recorders are z = 16 bits wide (Section 3.2).
+ *   u        rows, 1..16 (the paper uses 4)
+ *   v_re     SI/SRE columns per row, >= 1
+ *   g        DRs per SRE, 1..64 (the paper: 8 is enough for IPv4)
+ *   v_le     LE columns per row, >= 1
+ *   g_le     DRs per LE (the paper's g'), a positive multiple of 64
+ *   hash_seed  seed of every hash function of the monitor
+ */
+typedef struct {
+    uint32_t u, v_re, g, v_le, g_le;
+    uint64_t hash_seed;
+} srla_geometry_t;
+
+/*
+ *   window_slices   k, the sliding window W(t, k) in slices, 1..32767
+ *                   (Section 3.1; a 16-bit DR allows k < 2^16, and the
+ *                   library keeps half of that range as aging slack)
+ *   threshold       theta >= 1 (Definition 2)
+ *   max_candidates  capacity of the candidate list, >= 1
+ *   flags           SRLA_CFG_* bits
+ */
+typedef struct {
+    uint32_t window_slices;
+    uint32_t threshold;
+    srla_geometry_t geom;
+    uint64_t max_candidates;
+    uint32_t flags;
+} srla_config_t;
+
+typedef struct srla_monitor srla_monitor_t;
+
+/*
+ * The report of one closed slice e, covering the window [e-k+1, e]
+ * (window_full == 0 while e < k-1).  Arrays are host memory owned by the
+ * library and stay valid until the next srla_estimate or srla_destroy.
+ *   ip            the candidate list CSIP (Algorithms 2-3), ascending
+ *   est           Eq9 estimate of |OP(ip, e-k+1, k)| (FP64; +inf with SAT)
+ *   flags         SRLA_FLAG_* of each candidate
+ *   union_weight  |ULE(ip)|^k, union LE DRs inside the window (Algorithm 1)
+ *   re_weight     |URE(ip)|^k before the slide
+ *   row_fill      |LDR(i)|^k for i < u: LE DRs of row i inside the window
+ *   up            Eq8
+ *   n_touched     distinct sources with at least one SRE-sampled pair in e
+ *   n_new         candidates inserted in e
+ */
+typedef struct {
+    uint64_t slice;
+    uint32_t window_full;
+    uint64_t n;
+    const uint32_t *ip;
+    const double *est;
+    const uint8_t *flags;
+    const uint32_t *union_weight;
+    const uint8_t *re_weight;
+    const uint64_t *row_fill;
+    double up;
+    uint64_t n_touched;
+    uint64_t n_new;
+} srla_report_t;
+
+/* Accumulated stage times (milliseconds, HIP events on the monitor's stream)
+   since the last reset; all zero unless SRLA_CFG_TIMING was set. */
+typedef struct {
+    double scan_ms;        /* Algorithm 2 scan kernels */
+    uint64_t scan_launches;
+    uint64_t scan_pairs;
+    double sweep_ms;       /* row fills |LDR(i)|^k and the LE activity bitmap */
+    double finalize_ms;    /* candidate check of the slice's sampled sources */
+    double estimate_ms;    /* merge, Eq8-Eq9 and the Algorithm 3 re-check */
+    double slide_ms;       /* SI rebuild and carried-list compaction */
+    double report_ms;      /* device-to-host copy of the report */
+    uint64_t estimates;
+} srla_timings_t;
+
+/*
+ * Device bytes a monitor of this configuration allocates (DR arrays, SI,
+ * activity bitmap, candidate buffers; the slice's sampled-source list grows
+ * with the pairs scanned and is not included).  0 for an invalid config.
+ */
+uint64_t srla_footprint_bytes(const srla_config_t *cfg);
+
+/*
+ * Creates a monitor on the current HIP device.  hip_stream is a hipStream_t
+ * on which every operation of the monitor is issued; NULL makes the library
+ * create (and later destroy) its own stream.  All DRs start as DRinit (never
+ * set), all SI bits as 0, the open slice is 0.  *out is set only on success.
+ * Errors: SRLA_E_INVAL (cfg out of range, NULL out), SRLA_E_NOMEM,
+ * SRLA_E_DEVICE.
+ */
+int srla_create(const srla_config_t *cfg, void *hip_stream, srla_monitor_t **out);
+
+/*
+ * Scans n pairs into the open slice (Algorithm 2, Section 4.1): every pair
+ * sets one LE DR in each row; pairs whose bip hashes to LSB(H1(bip)) >= tau
+ * (Eq1) also set one SRE DR per row and mark aip as sampled in this slice.
+ * pairs: 2n uint32 values, interleaved (aip, bip), host byte order.
+ * on_device != 0: pairs is device memory readable on the monitor's stream;
+ *   the caller keeps it alive until the work has run (the next
+ *   srla_estimate returns after it).
+ * on_device == 0: pairs is host memory, copied before this call returns.
+ * May be called any number of times per slice; the order of pairs does not
+ * change any result.  Errors: SRLA_E_INVAL (NULL pairs with n > 0),
+ * SRLA_E_STATE (poisoned), SRLA_E_NOMEM, SRLA_E_DEVICE.
+ */
+int srla_scan(srla_monitor_t *m, const uint32_t *pairs, uint64_t n, int on_device);
+
+/*
+ * Closes the open slice e and fills *out with its report (Section 4.2 and
+ * Algorithm 3): the candidate check of every source sampled in e against the
+ * union SRE and union SI, the union-LE estimate (Eq8-Eq9) of every candidate,
+ * then the slide -- SI cleared, every DR one slice older, candidates whose
+ * union SRE still passes carried into slice e+1 with their SI bits set.
+ * Blocks until the report is in host memory.  Errors: SRLA_E_CAPACITY (more
+ * than max_candidates candidates; the monitor is then poisoned), SRLA_E_STATE,
+ * SRLA_E_INVAL (NULL out), SRLA_E_NOMEM, SRLA_E_DEVICE.
+ */
+int srla_estimate(srla_monitor_t *m, srla_report_t *out);
+
+/*
+ * Copies one state array to host memory, as of the open slice.
+ * which = SRLA_DUMP_LE: u*v_le*g_le values, layout [row][column][DR];
+ *         SRLA_DUMP_RE: u*v_re*g values, layout [row][column][DR];
+ *   each value is the DR's distance in slices (Section 3.2), with distances
+ *   of 32768 and more (and never-set DRs) written as 65535.
+ * which = SRLA_DUMP_SI: u*v_re raw 16-bit SI words, layout [row][column].
+ * cells must equal the array's size.  Blocks until the copy is done.
+ */
+int srla_dump_state(srla_monitor_t *m, int which, uint16_t *host_out, uint64_t cells);
+
+/* Stage times since the last reset (reset != 0 clears them after reading). */
+int srla_timings(srla_monitor_t *m, srla_timings_t *out, int reset);
+
+/* Waits for the monitor's stream and frees everything it owns. NULL is ok. */
+int srla_destroy(srla_monitor_t *m);
+
+/* Text of the monitor's last error ("" if none); static text for NULL. */
+const char *srla_last_error(const srla_monitor_t *m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRLA_H */

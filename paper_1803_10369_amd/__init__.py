@@ -1,0 +1,12 @@
+"""SRLA sliding super-point cardinality estimation on MI355X (gfx950).
+
+The hot path -- Algorithm 2's scan of (aip, bip) pairs into the SEA's
+distance recorders and the end-of-slice candidate check, Eq8-Eq9 estimate and
+Algorithm 3 slide of arXiv 1803.10369 -- runs in the HIP kernels of
+``libsrla.so`` behind the C ABI of ``include/srla.h``; ``srla`` is its
+ctypes binding.
+"""
+from .srla import (Monitor, Report, SrlaError, make_config, srla_create, srla_destroy,  # noqa: F401
+                   srla_dump_state, srla_estimate, srla_footprint_bytes, srla_last_error,
+                   srla_scan, srla_timings, SRLA_DUMP_LE, SRLA_DUMP_RE, SRLA_DUMP_SI,
+                   SRLA_FLAG_SUPER, SRLA_FLAG_SAT, SRLA_FLAG_NEW, SRLA_FLAG_KEEP, EXPORTS)

@@ -1,0 +1,130 @@
+// Internal declarations of the gfx950 SRLA library: the per-monitor constant
+// block that every kernel receives by value, the device-side hash and stamp
+// helpers, and the launchers the host runtime calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srla {
+
+constexpr int kMaxU = 16;
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+// DR cells hold slice stamps instead of distances: 0 = never set (or scrubbed),
+// otherwise code(s) = (s mod 65535) + 1 of the last slice s that set the cell.
+// At open slice t the cell's distance (Section 3.2) is
+// (code(t) - cell) mod 65535, so DRslide is free and DRset is one plain store.
+// Stamps whose distance reaches kScrubAge are zeroed before they can alias.
+constexpr uint32_t kStampPeriod = 65535;
+constexpr uint32_t kScrubAge = 32768;
+
+__host__ __device__ inline uint16_t stamp_code(uint64_t slice) {
+  return (uint16_t)(slice % kStampPeriod + 1);
+}
+
+// Hash function of the multiply-add-shift family:
+// h(x) = ((a*x + b) mod 2^64) >> 32.
+struct HashFn {
+  uint64_t a, b;
+};
+
+// Everything a kernel needs to know about one monitor.
+struct Geo {
+  uint32_t u, v_re, g, v_le, G;  // G = g' (DRs per LE)
+  uint32_t k;                    // window in slices
+  uint32_t theta;
+  uint32_t tau_mask;             // LSB(h) >= tau  <=>  (h & tau_mask) == 0
+  uint32_t t_re;                 // ceil(rho * g)
+  uint32_t words;                // G / 64 bitmap words per LE
+  HashFn rh[kMaxU];              // RH_0 .. RH_{u-1}
+  HashFn h1, h2, h3, h4;
+};
+
+__device__ __forceinline__ uint32_t mas(const HashFn& f, uint32_t x) {
+  return (uint32_t)((f.a * (uint64_t)x + f.b) >> 32);
+}
+
+// maps a 32-bit hash to [0, m)
+__device__ __forceinline__ uint32_t hrange(uint32_t h, uint32_t m) {
+  return (uint32_t)(((uint64_t)h * (uint64_t)m) >> 32);
+}
+
+// distance of a nonzero stamp at open-slice code `now`
+__device__ __forceinline__ uint32_t stamp_age(uint32_t now, uint32_t cell) {
+  int32_t d = (int32_t)now - (int32_t)cell;
+  return (uint32_t)(d < 0 ? d + (int32_t)kStampPeriod : d);
+}
+
+// "DR < k": set inside the window that ends at the slice whose code is `now`
+__device__ __forceinline__ bool in_window(uint32_t now, uint32_t cell, uint32_t k) {
+  return cell != 0 && stamp_age(now, cell) < k;
+}
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Device counters of one slice's end-of-slice pipeline.
+struct Counters {
+  uint32_t touched;      // sampled-source appends in the open slice
+  uint32_t n_unique;     // distinct sampled sources
+  uint32_t n_new;        // new candidates N_t
+  uint32_t n_cand;       // |CSIP_t| (clamped to capacity)
+  uint32_t n_keep;       // |NCSIP_t|
+  uint32_t overflow;     // CSIP_t exceeded capacity
+  uint32_t pad[2];
+};
+
+// ---------------------------------------------------------------- launchers
+// All launchers enqueue on `st` and return the launch status.
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t st);
+
+hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
+                       uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
+                       hipStream_t st);
+
+hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
+                           const Geo& geo, uint16_t now, hipStream_t st);
+
+hipError_t launch_scrub(uint16_t* cells, uint64_t n, uint16_t now, hipStream_t st);
+
+// keys-only LSD radix sort of n uint32 keys; returns the buffer holding the
+// sorted keys (keys or tmp).  block_hist needs radix_hist_words(n) words.
+uint64_t radix_hist_words(uint64_t n);
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* tmp, uint64_t n, uint32_t* block_hist,
+                          uint32_t** sorted, hipStream_t st);
+
+// exclusive-scan helper storage for compaction of up to n elements
+uint64_t compact_block_words(uint64_t n);
+
+hipError_t launch_finalize(const uint32_t* sorted, uint64_t n_max, const uint16_t* re,
+                           const uint16_t* si, const Geo& geo, uint16_t now,
+                           uint8_t* mark, Counters* cnt, hipStream_t st);
+
+// stable compaction of vals[i] with (flags[i] & mask) != 0, i < *n_dev (or
+// n_host if n_dev is null); n_max bounds the grid; result count -> *out_count
+hipError_t compact_u32(const uint8_t* flags, uint8_t mask, const uint32_t* vals,
+                       const uint32_t* n_dev, uint64_t n_max, uint32_t* out,
+                       uint32_t* out_count, uint32_t* block_words, hipStream_t st);
+
+hipError_t launch_merge(const uint32_t* ncsip, uint32_t n_old, const uint32_t* news,
+                        uint64_t n_new_max, Counters* cnt, uint64_t cap, uint32_t* csip,
+                        uint8_t* cflags, hipStream_t st);
+
+hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
+                             double* up, hipStream_t st);
+
+hipError_t launch_estimate(const uint32_t* csip, uint64_t n_max, const Counters* cnt,
+                           const uint64_t* bitmap, const uint16_t* re, const double* up,
+                           const Geo& geo, uint16_t now, double* est, uint8_t* cflags,
+                           uint32_t* U, uint8_t* W, hipStream_t st);
+
+hipError_t launch_si_mark(const uint32_t* cands, const uint32_t* n_dev, uint64_t n_max,
+                          uint32_t* si_words, const Geo& geo, hipStream_t st);
+
+}  // namespace srla

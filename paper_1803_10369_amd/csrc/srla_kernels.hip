@@ -1,0 +1,486 @@
+// gfx950 kernels of the SRLA hot path (arXiv 1803.10369, Sections 4.1-4.2).
+//
+// Memory layout (all device-resident for the monitor's lifetime):
+//   LE     uint16 stamps [u][v_le][G]     one LE of G DRs per (row, column)
+//   RE     uint16 stamps [u][v_re][g]     one SRE of g DRs per (row, column)
+//   SI     uint16        [u][v_re]        super point indicators
+//   bitmap uint64        [u][v_le][G/64]  LE DRs inside the window, rebuilt
+//                                         at every slice end
+// A DR is a 16-bit slice stamp (see srla_internal.h): setting it (DRset) is a
+// plain idempotent store of the open slice's code, so concurrent pairs need
+// no atomics (Section 4.3 makes the same observation for distances), and the
+// slide of Algorithm 3 costs nothing.  No kernel contains a dense
+// contraction, so nothing here uses MFMA; the scan is bound by random 2-byte
+// stores and the sweep by streaming HBM bandwidth.
+#include "srla_internal.h"
+
+namespace srla {
+
+// ------------------------------------------------------------------ fill
+
+__global__ __launch_bounds__(kBlock) void k_fill_u32(uint32_t* __restrict__ p, uint32_t v,
+                                                    uint64_t n) {
+  uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(kBlock), 0, st, p, value, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scan
+// Algorithm 2 for every pair.  One thread owns two adjacent pairs per step
+// (a 16-byte load), kScanSteps steps per block; all loads of a thread are
+// issued before its stores.  Sampled sources are appended to `touched` with
+// one atomic per wavefront (ballot + lane rank).
+
+constexpr int kScanSteps = 4;
+constexpr uint64_t kScanTile = (uint64_t)kBlock * 2 * kScanSteps;  // pairs per block
+
+template <int U>
+__device__ __forceinline__ void scan_one(uint32_t a, uint32_t b, bool valid, const Geo& geo,
+                                         uint16_t code, uint16_t* __restrict__ le,
+                                         uint16_t* __restrict__ re,
+                                         uint32_t* __restrict__ touched,
+                                         Counters* __restrict__ cnt) {
+  const uint32_t nu = U > 0 ? (uint32_t)U : geo.u;
+  bool sampled = false;
+  if (valid) {
+    // every pair sets one LE DR per row: H3(bip) picks the DR, RH_i(aip) the LE
+    const uint32_t lei = hrange(mas(geo.h3, b), geo.G);
+#pragma unroll
+    for (uint32_t i = 0; i < nu; ++i) {
+      const uint32_t col = hrange(mas(geo.rh[i], a), geo.v_le);
+      le[((uint64_t)i * geo.v_le + col) * geo.G + lei] = code;
+    }
+    // only pairs with LSB(H1(bip)) >= tau reach the SRE
+    sampled = (mas(geo.h1, b) & geo.tau_mask) == 0u;
+    if (sampled) {
+      const uint32_t rei = hrange(mas(geo.h2, b), geo.g);
+#pragma unroll
+      for (uint32_t i = 0; i < nu; ++i) {
+        const uint32_t col = hrange(mas(geo.rh[i], a), geo.v_re);
+        re[((uint64_t)i * geo.v_re + col) * geo.g + rei] = code;
+      }
+    }
+  }
+  // the candidate check of sampled sources happens at the end of the slice
+  const uint64_t mask = __ballot(sampled);
+  if (mask != 0ull) {
+    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
+    uint32_t base = 0;
+    if (__lane_id() == leader) base = atomicAdd(&cnt->touched, (uint32_t)__popcll(mask));
+    base = __shfl(base, (int)leader);
+    if (sampled) touched[base + lane_rank(mask)] = a;
+  }
+}
+
+template <int U, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_scan(const uint32_t* __restrict__ pairs, uint64_t n,
+                                                Geo geo, uint16_t code,
+                                                uint16_t* __restrict__ le,
+                                                uint16_t* __restrict__ re,
+                                                uint32_t* __restrict__ touched,
+                                                Counters* __restrict__ cnt) {
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint32_t a[kScanSteps][2], b[kScanSteps][2];
+  bool v[kScanSteps][2];
+#pragma unroll
+  for (int s = 0; s < kScanSteps; ++s) {
+    const uint64_t p = base + (uint64_t)s * (2 * kBlock) + 2u * threadIdx.x;
+    v[s][0] = p < n;
+    v[s][1] = p + 1 < n;
+    if (VEC && v[s][1]) {
+      const uint4 q = *reinterpret_cast<const uint4*>(pairs + 2 * p);
+      a[s][0] = q.x; b[s][0] = q.y; a[s][1] = q.z; b[s][1] = q.w;
+    } else {
+      a[s][0] = v[s][0] ? pairs[2 * p] : 0u;
+      b[s][0] = v[s][0] ? pairs[2 * p + 1] : 0u;
+      a[s][1] = v[s][1] ? pairs[2 * p + 2] : 0u;
+      b[s][1] = v[s][1] ? pairs[2 * p + 3] : 0u;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kScanSteps; ++s) {
+    scan_one<U>(a[s][0], b[s][0], v[s][0], geo, code, le, re, touched, cnt);
+    scan_one<U>(a[s][1], b[s][1], v[s][1], geo, code, le, re, touched, cnt);
+  }
+}
+
+template <int U>
+static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
+                                uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
+                                hipStream_t st) {
+  const uint64_t blocks = (n + kScanTile - 1) / kScanTile;
+  const bool vec = ((uintptr_t)pairs & 15u) == 0;
+  if (vec)
+    hipLaunchKernelGGL((k_scan<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
+                       geo, code, le, re, touched, cnt);
+  else
+    hipLaunchKernelGGL((k_scan<U, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
+                       geo, code, le, re, touched, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
+                       uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
+                       hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  switch (geo.u) {
+    case 4: return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, cnt, st);
+    case 8: return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, cnt, st);
+    default: return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, cnt, st);
+  }
+}
+
+// ------------------------------------------------------------------ sweep
+// |LDR(i)|^k of Section 4.2 for every row, the LE activity bitmap that the
+// estimate kernel ANDs across rows, and the scrub of stamps about to alias.
+// One thread reads 8 DRs (16 bytes); 8 neighbouring lanes OR their 8-bit
+// masks into one 64-bit bitmap word.  Grid: x = chunks of a row, y = row.
+
+constexpr int kSweepSteps = 4;
+constexpr uint64_t kSweepTile = (uint64_t)kBlock * 8 * kSweepSteps;  // DRs per block
+
+__global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
+                                                    uint64_t* __restrict__ bitmap,
+                                                    unsigned long long* __restrict__ row_fill,
+                                                    uint64_t row_cells, uint32_t now,
+                                                    uint32_t k) {
+  const uint32_t row = blockIdx.y;
+  uint16_t* rowp = le + (uint64_t)row * row_cells;
+  uint64_t* bmp = bitmap + (uint64_t)row * (row_cells / 64);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  uint32_t count = 0;
+#pragma unroll
+  for (int s = 0; s < kSweepSteps; ++s) {
+    const uint64_t c8 = ((uint64_t)blockIdx.x * kSweepTile) + ((uint64_t)s * kBlock + threadIdx.x) * 8;
+    const bool valid = c8 < row_cells;
+    uint32_t m8 = 0;
+    if (valid) {
+      uint4 q = *reinterpret_cast<const uint4*>(rowp + c8);
+      uint32_t w[4] = {q.x, q.y, q.z, q.w};
+      bool dirty = false;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        uint32_t lo = w[j] & 0xFFFFu, hi = w[j] >> 16;
+        if (lo) {
+          const uint32_t age = stamp_age(now, lo);
+          if (age < k) m8 |= 1u << (2 * j);
+          if (age >= kScrubAge) { lo = 0; dirty = true; }
+        }
+        if (hi) {
+          const uint32_t age = stamp_age(now, hi);
+          if (age < k) m8 |= 1u << (2 * j + 1);
+          if (age >= kScrubAge) { hi = 0; dirty = true; }
+        }
+        w[j] = lo | (hi << 16);
+      }
+      if (dirty) *reinterpret_cast<uint4*>(rowp + c8) = make_uint4(w[0], w[1], w[2], w[3]);
+      count += __popc(m8);
+    }
+    // lanes 8q..8q+7 cover 64 consecutive DRs: bit 8*(lane%8)+x is DR c8+x
+    uint32_t lo32 = (lane & 4) ? 0u : m8 << (8 * (lane & 3));
+    uint32_t hi32 = (lane & 4) ? m8 << (8 * (lane & 3)) : 0u;
+    lo32 |= __shfl_xor(lo32, 1); hi32 |= __shfl_xor(hi32, 1);
+    lo32 |= __shfl_xor(lo32, 2); hi32 |= __shfl_xor(hi32, 2);
+    lo32 |= __shfl_xor(lo32, 4); hi32 |= __shfl_xor(hi32, 4);
+    if (valid && (lane & 7) == 0) bmp[c8 / 64] = ((uint64_t)hi32 << 32) | lo32;
+  }
+  // block total -> one 64-bit atomic per block
+  for (int off = kWave / 2; off > 0; off >>= 1) count += __shfl_xor(count, off);
+  __shared__ uint32_t part[kBlock / kWave];
+  if (lane == 0) part[threadIdx.x / kWave] = count;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+    if (t) atomicAdd(&row_fill[row], t);
+  }
+}
+
+hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
+                           const Geo& geo, uint16_t now, hipStream_t st) {
+  const uint64_t row_cells = (uint64_t)geo.v_le * geo.G;
+  const uint64_t bx = (row_cells + kSweepTile - 1) / kSweepTile;
+  hipLaunchKernelGGL(k_sweep_le, dim3((uint32_t)bx, geo.u), dim3(kBlock), 0, st, le, bitmap,
+                     row_fill, row_cells, (uint32_t)now, geo.k);
+  return hipGetLastError();
+}
+
+// Zeroes stamps whose distance reached kScrubAge (any array of stamps).
+__global__ __launch_bounds__(kBlock) void k_scrub(uint16_t* __restrict__ cells, uint64_t n,
+                                                 uint32_t now) {
+  uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (; i < n; i += stride) {
+    const uint32_t c = cells[i];
+    if (c != 0 && stamp_age(now, c) >= kScrubAge) cells[i] = 0;
+  }
+}
+
+hipError_t launch_scrub(uint16_t* cells, uint64_t n, uint16_t now, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_scrub, dim3((uint32_t)blocks), dim3(kBlock), 0, st, cells, n,
+                     (uint32_t)now);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ finalize
+// Algorithm 2's candidate check under the slice-synchronous reading: every
+// distinct source sampled in the slice (sorted[] is sorted, so the first of
+// each run stands for the source) is a new candidate iff its union SRE has
+// at least ceil(rho*g) DRs inside the window (Algorithm 1, DRjoin = max over
+// rows, so "all rows inside") and its own bit of the union SI (AND over rows)
+// is still clear.  SI is exactly as the previous slide left it.
+
+__global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict__ sorted,
+                                                    const uint16_t* __restrict__ re,
+                                                    const uint16_t* __restrict__ si, Geo geo,
+                                                    uint32_t now, uint8_t* __restrict__ mark,
+                                                    Counters* __restrict__ cnt) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t n = cnt->touched;
+  bool first = false;
+  uint8_t f = 0;
+  if (i < n) {
+    const uint32_t a = sorted[i];
+    first = (i == 0) || (sorted[i - 1] != a);
+    if (first) {
+      uint32_t w = 0;
+      for (uint32_t c = 0; c < geo.g; ++c) {
+        bool all = true;
+        for (uint32_t r = 0; r < geo.u; ++r) {
+          const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
+          all = all && in_window(now, re[((uint64_t)r * geo.v_re + col) * geo.g + c], geo.k);
+        }
+        w += all ? 1u : 0u;
+      }
+      uint32_t usi = 0xFFFFu;
+      for (uint32_t r = 0; r < geo.u; ++r) {
+        const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
+        usi &= si[(uint64_t)r * geo.v_re + col];
+      }
+      const uint32_t bit = hrange(mas(geo.h4, a), 16u);
+      f = (w >= geo.t_re && ((usi >> bit) & 1u) == 0u) ? 1 : 0;
+    }
+    mark[i] = f;
+  }
+  const uint64_t firsts = __ballot(first);
+  if (__lane_id() == 0 && firsts) atomicAdd(&cnt->n_unique, (uint32_t)__popcll(firsts));
+}
+
+hipError_t launch_finalize(const uint32_t* sorted, uint64_t n_max, const uint16_t* re,
+                           const uint16_t* si, const Geo& geo, uint16_t now, uint8_t* mark,
+                           Counters* cnt, hipStream_t st) {
+  if (n_max == 0) return hipSuccess;
+  const uint64_t blocks = (n_max + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_finalize, dim3((uint32_t)blocks), dim3(kBlock), 0, st, sorted, re, si,
+                     geo, (uint32_t)now, mark, cnt);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ merge
+// CSIP_t = NCSIP_{t-1} u N_t, both ascending and disjoint (every carried
+// candidate has its own SI bit set, so it cannot be new): each element's
+// output position is its own index plus its rank in the other list.
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ v, uint32_t n,
+                                                    uint32_t x) {
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (v[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge(const uint32_t* __restrict__ ncsip,
+                                                 uint32_t n_old,
+                                                 const uint32_t* __restrict__ news,
+                                                 Counters* __restrict__ cnt, uint64_t cap,
+                                                 uint32_t* __restrict__ csip,
+                                                 uint8_t* __restrict__ cflags) {
+  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t n_new = cnt->n_new;
+  if (t == 0) {
+    const uint64_t total = (uint64_t)n_old + n_new;
+    cnt->n_cand = (uint32_t)(total < cap ? total : cap);
+    cnt->overflow = total > cap ? 1u : 0u;
+  }
+  if (t < n_old) {
+    const uint32_t x = ncsip[t];
+    const uint64_t pos = t + lower_bound_u32(news, n_new, x);
+    if (pos < cap) { csip[pos] = x; cflags[pos] = 0; }
+  }
+  if (t < n_new) {
+    const uint32_t y = news[t];
+    const uint64_t pos = t + lower_bound_u32(ncsip, n_old, y);
+    if (pos < cap) { csip[pos] = y; cflags[pos] = 4; /* SRLA_FLAG_NEW */ }
+  }
+}
+
+hipError_t launch_merge(const uint32_t* ncsip, uint32_t n_old, const uint32_t* news,
+                        uint64_t n_new_max, Counters* cnt, uint64_t cap, uint32_t* csip,
+                        uint8_t* cflags, hipStream_t st) {
+  uint64_t n = n_old > n_new_max ? n_old : n_new_max;
+  if (n == 0) n = 1;  // thread 0 still publishes the counts
+  const uint64_t blocks = (n + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_merge, dim3((uint32_t)blocks), dim3(kBlock), 0, st, ncsip, n_old, news,
+                     cnt, cap, csip, cflags);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Eq8
+// UP = prod_i |LDR(i)|^k / (g' * v), in this order, in FP64.
+
+__global__ void k_union_prob(const unsigned long long* __restrict__ row_fill, Geo geo,
+                             double* __restrict__ up) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double p = 1.0;
+    for (uint32_t i = 0; i < geo.u; ++i)
+      p = p * ((double)row_fill[i] / ((double)geo.G * (double)geo.v_le));
+    *up = p;
+  }
+}
+
+hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo, double* up,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_union_prob, dim3(1), dim3(1), 0, st, row_fill, geo, up);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ estimate
+// For every candidate: |ULE|^k from the activity bitmap (AND over the u
+// rows, popcount), |URE|^k now and after the slide from the stamps, Eq9 in
+// FP64, and the flags.  A group of 2^lg_log2 lanes owns one candidate; its
+// lanes split the G/64 bitmap words (16 lanes read one 128-byte line per row
+// when G = 1024) and the g SRE DRs, then reduce with cross-lane shuffles.
+
+__global__ __launch_bounds__(kBlock) void k_estimate(const uint32_t* __restrict__ csip,
+                                                    const Counters* __restrict__ cnt,
+                                                    const uint64_t* __restrict__ bitmap,
+                                                    const uint16_t* __restrict__ re,
+                                                    const double* __restrict__ up_p, Geo geo,
+                                                    uint32_t now, uint32_t lg_log2,
+                                                    double* __restrict__ est,
+                                                    uint8_t* __restrict__ cflags,
+                                                    uint32_t* __restrict__ U_out,
+                                                    uint8_t* __restrict__ W_out) {
+  const uint32_t lg = 1u << lg_log2;
+  const uint64_t gid = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> lg_log2;
+  const uint32_t sub = threadIdx.x & (lg - 1u);
+  const uint32_t n = cnt->n_cand;
+  const bool valid = gid < n;
+  const uint32_t a = valid ? csip[gid] : 0u;
+  uint32_t ucount = 0, w_now = 0, w_next = 0;
+  if (valid) {
+    for (uint32_t x = sub; x < geo.words; x += lg) {
+      uint64_t acc = ~0ull;
+      for (uint32_t r = 0; r < geo.u; ++r) {
+        const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_le);
+        acc &= bitmap[((uint64_t)r * geo.v_le + col) * geo.words + x];
+      }
+      ucount += (uint32_t)__popcll(acc);
+    }
+    for (uint32_t c = sub; c < geo.g; c += lg) {
+      bool all_now = true, all_next = true;
+      for (uint32_t r = 0; r < geo.u; ++r) {
+        const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
+        const uint32_t cell = re[((uint64_t)r * geo.v_re + col) * geo.g + c];
+        const uint32_t age = cell ? stamp_age(now, cell) : 0xFFFFFFFFu;
+        all_now = all_now && age < geo.k;
+        all_next = all_next && age + 1u < geo.k;   // after the slide of Algorithm 3
+      }
+      w_now += all_now ? 1u : 0u;
+      w_next += all_next ? 1u : 0u;
+    }
+  }
+  for (uint32_t off = lg >> 1; off > 0; off >>= 1) {
+    ucount += __shfl_xor(ucount, (int)off);
+    w_now += __shfl_xor(w_now, (int)off);
+    w_next += __shfl_xor(w_next, (int)off);
+  }
+  if (valid && sub == 0) {
+    // Eq9, operation by operation, no contraction (built with -ffp-contract=off)
+    const double G = (double)geo.G;
+    const double up = *up_p;
+    const double num = (double)ucount - G * up;
+    const double den = G * (1.0 - up);
+    double e;
+    uint8_t fl = cflags[gid] & 4u;   // NEW, written by the merge
+    if (den == 0.0) {
+      e = __builtin_inf();
+      fl |= 2u;
+    } else {
+      const double y = 1.0 - num / den;
+      if (y <= 0.0) {
+        e = __builtin_inf();
+        fl |= 2u;
+      } else {
+        e = -G * log(y);
+      }
+    }
+    if (e >= (double)geo.theta) fl |= 1u;
+    if (w_next >= geo.t_re) fl |= 8u;   // carried by Algorithm 3
+    est[gid] = e;
+    cflags[gid] = fl;
+    U_out[gid] = ucount;
+    W_out[gid] = (uint8_t)w_now;
+  }
+}
+
+static uint32_t est_lg_log2(const Geo& geo) {
+  uint32_t l = 2;  // at least 4 lanes per candidate
+  while ((1u << l) < geo.words && l < 6) ++l;
+  return l;
+}
+
+hipError_t launch_estimate(const uint32_t* csip, uint64_t n_max, const Counters* cnt,
+                           const uint64_t* bitmap, const uint16_t* re, const double* up,
+                           const Geo& geo, uint16_t now, double* est, uint8_t* cflags,
+                           uint32_t* U, uint8_t* W, hipStream_t st) {
+  if (n_max == 0) return hipSuccess;
+  const uint32_t lgl = est_lg_log2(geo);
+  const uint64_t threads = n_max << lgl;
+  const uint64_t blocks = (threads + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_estimate, dim3((uint32_t)blocks), dim3(kBlock), 0, st, csip, cnt, bitmap,
+                     re, up, geo, (uint32_t)now, lgl, est, cflags, U, W);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ SI
+// Algorithm 3's marking: bit H4(aip) of SI[i][RH_i(aip)] for every carried
+// candidate and every row.  SI is uint16 [u][v_re], addressed here as 32-bit
+// words so that the OR is a native atomic.
+
+__global__ __launch_bounds__(kBlock) void k_si_mark(const uint32_t* __restrict__ cands,
+                                                   const uint32_t* __restrict__ n_dev,
+                                                   uint32_t* __restrict__ si_words, Geo geo) {
+  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= *n_dev) return;
+  const uint32_t a = cands[t];
+  const uint32_t bit = hrange(mas(geo.h4, a), 16u);
+  for (uint32_t r = 0; r < geo.u; ++r) {
+    const uint64_t idx = (uint64_t)r * geo.v_re + hrange(mas(geo.rh[r], a), geo.v_re);
+    atomicOr(&si_words[idx >> 1], 1u << (bit + 16u * (uint32_t)(idx & 1u)));
+  }
+}
+
+hipError_t launch_si_mark(const uint32_t* cands, const uint32_t* n_dev, uint64_t n_max,
+                          uint32_t* si_words, const Geo& geo, hipStream_t st) {
+  if (n_max == 0) return hipSuccess;
+  const uint64_t blocks = (n_max + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_si_mark, dim3((uint32_t)blocks), dim3(kBlock), 0, st, cands, n_dev,
+                     si_words, geo);
+  return hipGetLastError();
+}
+
+}  // namespace srla

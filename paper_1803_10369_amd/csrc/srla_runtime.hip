@@ -1,0 +1,600 @@
+// Host runtime of the gfx950 SRLA library: the C ABI of include/srla.h.
+//
+// One monitor = one SEA (Section 4.1) resident in device memory plus the
+// buffers of the end-of-slice pipeline.  srla_scan enqueues Algorithm 2 for
+// a batch of pairs; srla_estimate runs, on the same stream,
+//   sweep    -> |LDR(i)|^k and the LE activity bitmap (Section 4.2)
+//   finalize -> sort + unique of the slice's sampled sources, candidate check
+//   merge    -> CSIP_t = NCSIP_{t-1} u N_t, ascending
+//   estimate -> Eq8, then per candidate |ULE|^k, |URE|^k, Eq9, Algorithm 3 test
+//   slide    -> SI cleared, NCSIP_t compacted, its SI bits set; t <- t + 1
+//   report   -> device-to-host copy into pinned buffers
+// with one host wait early on (the sampled-source count sizes the sort) and
+// two at the end (the candidate count sizes the report copy).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/srla.h"
+#include "srla_internal.h"
+
+using namespace srla;
+
+namespace {
+
+// Hash parameters: SplitMix64 (Steele, Lea and Flood 2014) started at the
+// hash seed; function f takes outputs 2f and 2f+1 as (a, b), in the order
+// RH_0..RH_{u-1}, H1, H2, H3, H4.
+struct SplitMix64 {
+  uint64_t s;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+};
+
+// smallest tau >= 0 with g * 2^tau >= theta: Eq1's ceil(log2(theta / g))
+uint32_t eq1_tau(uint32_t theta, uint32_t g) {
+  uint32_t tau = 0;
+  while (((uint64_t)g << tau) < (uint64_t)theta) ++tau;
+  return tau;
+}
+
+// ceil(rho * g) with rho = 0.99 (1 - e^(-1/3)) (Section 3.2)
+uint32_t detect_threshold(uint32_t g) {
+  const double rho = 0.99 * (1.0 - std::exp(-1.0 / 3.0));
+  return (uint32_t)std::ceil(rho * (double)g);
+}
+
+bool config_ok(const srla_config_t* c) {
+  if (!c) return false;
+  const srla_geometry_t& g = c->geom;
+  if (g.u < 1 || g.u > (uint32_t)kMaxU) return false;
+  if (g.g < 1 || g.g > 64) return false;
+  if (g.g_le < 64 || g.g_le % 64 != 0) return false;
+  if (g.v_re < 1 || g.v_le < 1) return false;
+  if (c->window_slices < 1 || c->window_slices > 32767) return false;
+  if (c->threshold < 1) return false;
+  if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
+  if ((c->flags & ~(uint32_t)SRLA_CFG_TIMING) != 0) return false;
+  const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
+  const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
+  if (le / g.u / g.g_le != g.v_le || re / g.u / g.g != g.v_re) return false;
+  if (le > (1ull << 40) || re > (1ull << 40)) return false;
+  return true;
+}
+
+enum Stage { ST_SCAN, ST_SWEEP, ST_FINALIZE, ST_ESTIMATE, ST_SLIDE, ST_REPORT, ST_N };
+
+struct TimedSpan {
+  int stage;
+  hipEvent_t a, b;
+};
+
+constexpr uint64_t kStageChunk = 1ull << 22;  // pairs per host-ingest chunk
+constexpr uint64_t kRescrubPeriod = 4096;     // slices between RE/SI scrubs
+
+}  // namespace
+
+struct srla_monitor {
+  srla_config_t cfg{};
+  Geo geo{};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint64_t slice = 0;
+  bool poisoned = false;
+  std::string err;
+
+  // SEA
+  uint16_t* le = nullptr;
+  uint16_t* re = nullptr;
+  uint16_t* si = nullptr;
+  uint64_t n_le = 0, n_re = 0, n_si = 0, si_words = 0;
+  uint64_t* bitmap = nullptr;
+  unsigned long long* row_fill = nullptr;
+  double* up = nullptr;
+  Counters* cnt = nullptr;
+
+  // sources sampled in the open slice
+  uint32_t* touched = nullptr;
+  uint32_t* touched_tmp = nullptr;
+  uint8_t* mark = nullptr;
+  uint32_t* news = nullptr;
+  uint32_t* hist = nullptr;
+  uint32_t* blockw = nullptr;
+  uint64_t touched_cap = 0;
+  uint64_t slice_pairs = 0;
+
+  // candidate lists
+  uint32_t* csip = nullptr;
+  uint32_t* ncsip = nullptr;
+  uint32_t* ncsip_next = nullptr;
+  uint8_t* cflags = nullptr;
+  double* est = nullptr;
+  uint32_t* U = nullptr;
+  uint8_t* W = nullptr;
+  uint32_t* cblockw = nullptr;
+  uint64_t cap = 0;
+  uint32_t n_ncsip = 0;
+
+  // pinned host side
+  Counters* h_cnt = nullptr;
+  unsigned long long* h_row_fill = nullptr;
+  double* h_up = nullptr;
+  uint64_t* h_row_fill64 = nullptr;
+  uint32_t* h_ip = nullptr;
+  double* h_est = nullptr;
+  uint8_t* h_flags = nullptr;
+  uint32_t* h_U = nullptr;
+  uint8_t* h_W = nullptr;
+  hipEvent_t ev_count = nullptr;
+
+  // host-input ring: two pinned chunks, two device chunks
+  uint32_t* h_stage[2] = {nullptr, nullptr};
+  uint32_t* d_stage[2] = {nullptr, nullptr};
+  hipEvent_t stage_ev[2] = {nullptr, nullptr};
+  bool stage_busy[2] = {false, false};
+  int stage_next = 0;
+
+  // timing
+  bool timing = false;
+  std::vector<TimedSpan> spans;
+  double acc_ms[ST_N] = {0, 0, 0, 0, 0, 0};
+  uint64_t scan_launches = 0, scan_pairs = 0, estimates = 0;
+};
+
+namespace {
+
+int fail(srla_monitor* m, int code, const std::string& what) {
+  if (m) m->err = what;
+  return code;
+}
+
+int hip_fail(srla_monitor* m, hipError_t e, const char* where) {
+  std::string s = std::string(where) + ": " + hipGetErrorString(e);
+  if (m) m->poisoned = true;
+  return fail(m, SRLA_E_DEVICE, s);
+}
+
+#define HIP_TRY(m, expr)                                   \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return hip_fail((m), e_, #expr); \
+  } while (0)
+
+template <class T>
+hipError_t dalloc(T** p, uint64_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void**)p, count * sizeof(T));
+}
+
+template <class T>
+hipError_t halloc(T** p, uint64_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipHostMalloc((void**)p, count * sizeof(T), hipHostMallocDefault);
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+void hfree(void* p) {
+  if (p) (void)hipHostFree(p);
+}
+
+uint64_t candidate_bytes(uint64_t cap) {
+  // csip, ncsip, ncsip_next (u32), cflags, W (u8), est (f64), U (u32), block words
+  return cap * (4 + 4 + 4 + 1 + 1 + 8 + 4) + 4 * compact_block_words(cap);
+}
+
+void span_begin(srla_monitor* m, int stage, hipEvent_t* a) {
+  *a = nullptr;
+  if (!m->timing) return;
+  if (hipEventCreate(a) != hipSuccess) { *a = nullptr; return; }
+  (void)hipEventRecord(*a, m->stream);
+}
+
+void span_end(srla_monitor* m, int stage, hipEvent_t a) {
+  if (!m->timing || !a) return;
+  hipEvent_t b;
+  if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+  (void)hipEventRecord(b, m->stream);
+  m->spans.push_back({stage, a, b});
+}
+
+void collect_spans(srla_monitor* m) {
+  for (auto& s : m->spans) {
+    float ms = 0.f;
+    if (hipEventSynchronize(s.b) == hipSuccess && hipEventElapsedTime(&ms, s.a, s.b) == hipSuccess)
+      m->acc_ms[s.stage] += ms;
+    (void)hipEventDestroy(s.a);
+    (void)hipEventDestroy(s.b);
+  }
+  m->spans.clear();
+}
+
+// Grows the per-slice sampled-source buffers to hold `need` entries.
+int reserve_touched(srla_monitor* m, uint64_t need) {
+  if (need <= m->touched_cap) return SRLA_OK;
+  uint64_t cap = std::max<uint64_t>(need, m->touched_cap ? 2 * m->touched_cap : (1u << 20));
+  if (cap > 0xFFFFFFF0ull) cap = std::max<uint64_t>(need, 0xFFFFFFF0ull);
+  if (need > 0xFFFFFFF0ull) return fail(m, SRLA_E_NOMEM, "slice holds more than 2^32 pairs");
+  uint32_t *t = nullptr, *tt = nullptr, *nw = nullptr, *h = nullptr, *bw = nullptr;
+  uint8_t* mk = nullptr;
+  if (dalloc(&t, cap) != hipSuccess || dalloc(&tt, cap) != hipSuccess ||
+      dalloc(&nw, cap) != hipSuccess || dalloc(&mk, cap) != hipSuccess ||
+      dalloc(&h, radix_hist_words(cap)) != hipSuccess ||
+      dalloc(&bw, compact_block_words(cap)) != hipSuccess) {
+    dfree(t); dfree(tt); dfree(nw); dfree(mk); dfree(h); dfree(bw);
+    (void)hipGetLastError();
+    return fail(m, SRLA_E_NOMEM, "cannot grow the sampled-source buffers");
+  }
+  if (m->touched && m->slice_pairs) {
+    // entries appended so far in this slice (at most slice_pairs of them)
+    HIP_TRY(m, hipMemcpyAsync(t, m->touched, m->slice_pairs * sizeof(uint32_t),
+                              hipMemcpyDeviceToDevice, m->stream));
+  }
+  HIP_TRY(m, hipStreamSynchronize(m->stream));
+  dfree(m->touched); dfree(m->touched_tmp); dfree(m->news); dfree(m->mark);
+  dfree(m->hist); dfree(m->blockw);
+  m->touched = t; m->touched_tmp = tt; m->news = nw; m->mark = mk; m->hist = h; m->blockw = bw;
+  m->touched_cap = cap;
+  return SRLA_OK;
+}
+
+void release(srla_monitor* m) {
+  if (!m) return;
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  collect_spans(m);
+  dfree(m->le); dfree(m->re); dfree(m->si); dfree(m->bitmap); dfree(m->row_fill);
+  dfree(m->up); dfree(m->cnt);
+  dfree(m->touched); dfree(m->touched_tmp); dfree(m->mark); dfree(m->news);
+  dfree(m->hist); dfree(m->blockw);
+  dfree(m->csip); dfree(m->ncsip); dfree(m->ncsip_next); dfree(m->cflags); dfree(m->est);
+  dfree(m->U); dfree(m->W); dfree(m->cblockw);
+  hfree(m->h_cnt); hfree(m->h_row_fill); hfree(m->h_up); hfree(m->h_ip); hfree(m->h_est);
+  hfree(m->h_flags); hfree(m->h_U); hfree(m->h_W);
+  delete[] m->h_row_fill64;
+  for (int i = 0; i < 2; ++i) {
+    hfree(m->h_stage[i]);
+    dfree(m->d_stage[i]);
+    if (m->stage_ev[i]) (void)hipEventDestroy(m->stage_ev[i]);
+  }
+  if (m->ev_count) (void)hipEventDestroy(m->ev_count);
+  if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
+  delete m;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
+  if (!config_ok(cfg)) return 0;
+  const srla_geometry_t& g = cfg->geom;
+  const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
+  const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
+  const uint64_t si = (uint64_t)g.u * g.v_re;
+  return 2 * le + le / 8 + 2 * re + 2 * ((si + 1) & ~1ull) + 8 * g.u + 8 + sizeof(Counters) +
+         candidate_bytes(cfg->max_candidates);
+}
+
+int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out) {
+  if (!out) return SRLA_E_INVAL;
+  if (!config_ok(cfg)) return SRLA_E_INVAL;
+  srla_monitor* m = new (std::nothrow) srla_monitor();
+  if (!m) return SRLA_E_NOMEM;
+  m->cfg = *cfg;
+  m->timing = (cfg->flags & SRLA_CFG_TIMING) != 0;
+
+  const srla_geometry_t& g = cfg->geom;
+  Geo& geo = m->geo;
+  geo.u = g.u; geo.v_re = g.v_re; geo.g = g.g; geo.v_le = g.v_le; geo.G = g.g_le;
+  geo.k = cfg->window_slices;
+  geo.theta = cfg->threshold;
+  const uint32_t tau = eq1_tau(cfg->threshold, g.g);
+  geo.tau_mask = tau >= 32 ? 0xFFFFFFFFu : ((1u << tau) - 1u);
+  geo.t_re = detect_threshold(g.g);
+  geo.words = g.g_le / 64;
+  SplitMix64 sm{g.hash_seed};
+  for (uint32_t f = 0; f < g.u + 4; ++f) {
+    HashFn h;
+    h.a = sm.next();
+    h.b = sm.next();
+    if (f < g.u) geo.rh[f] = h;
+    else if (f == g.u) geo.h1 = h;
+    else if (f == g.u + 1) geo.h2 = h;
+    else if (f == g.u + 2) geo.h3 = h;
+    else geo.h4 = h;
+  }
+
+  int rc = SRLA_OK;
+  auto nomem = [&](hipError_t e) {
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      rc = SRLA_E_NOMEM;
+    }
+  };
+  if (hip_stream) {
+    m->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking) != hipSuccess) {
+      release(m);
+      return SRLA_E_DEVICE;
+    }
+    m->own_stream = true;
+  }
+  m->n_le = (uint64_t)g.u * g.v_le * g.g_le;
+  m->n_re = (uint64_t)g.u * g.v_re * g.g;
+  m->n_si = (uint64_t)g.u * g.v_re;
+  m->si_words = (m->n_si + 1) / 2;
+  m->cap = cfg->max_candidates;
+  nomem(dalloc(&m->le, m->n_le));
+  if (!rc) nomem(dalloc(&m->re, m->n_re));
+  if (!rc) nomem(dalloc(&m->si, 2 * m->si_words));
+  if (!rc) nomem(dalloc(&m->bitmap, m->n_le / 64));
+  if (!rc) nomem(dalloc(&m->row_fill, g.u));
+  if (!rc) nomem(dalloc(&m->up, 1));
+  if (!rc) nomem(dalloc(&m->cnt, 1));
+  if (!rc) nomem(dalloc(&m->csip, m->cap));
+  if (!rc) nomem(dalloc(&m->ncsip, m->cap));
+  if (!rc) nomem(dalloc(&m->ncsip_next, m->cap));
+  if (!rc) nomem(dalloc(&m->cflags, m->cap));
+  if (!rc) nomem(dalloc(&m->est, m->cap));
+  if (!rc) nomem(dalloc(&m->U, m->cap));
+  if (!rc) nomem(dalloc(&m->W, m->cap));
+  if (!rc) nomem(dalloc(&m->cblockw, compact_block_words(m->cap)));
+  if (!rc) nomem(halloc(&m->h_cnt, 1));
+  if (!rc) nomem(halloc(&m->h_row_fill, g.u));
+  if (!rc) nomem(halloc(&m->h_up, 1));
+  if (!rc) nomem(halloc(&m->h_ip, m->cap));
+  if (!rc) nomem(halloc(&m->h_est, m->cap));
+  if (!rc) nomem(halloc(&m->h_flags, m->cap));
+  if (!rc) nomem(halloc(&m->h_U, m->cap));
+  if (!rc) nomem(halloc(&m->h_W, m->cap));
+  if (!rc) {
+    m->h_row_fill64 = new (std::nothrow) uint64_t[g.u];
+    if (!m->h_row_fill64) rc = SRLA_E_NOMEM;
+  }
+  if (!rc && hipEventCreateWithFlags(&m->ev_count, hipEventDisableTiming) != hipSuccess)
+    rc = SRLA_E_DEVICE;
+  if (rc) {
+    release(m);
+    return rc;
+  }
+  // DRinit for every DR (stamp 0 = never set), SI = 0, counters = 0
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->le, 0u, m->n_le / 2, m->stream);
+  if (e == hipSuccess && (m->n_le & 1)) e = hipMemsetAsync(m->le + m->n_le - 1, 0, 2, m->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(m->re, 0, m->n_re * 2, m->stream);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->si, 0u, m->si_words, m->stream);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->cnt, 0u, sizeof(Counters) / 4, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e != hipSuccess) {
+    release(m);
+    return SRLA_E_DEVICE;
+  }
+  if (reserve_touched(m, 1u << 16) != SRLA_OK) {
+    release(m);
+    return SRLA_E_NOMEM;
+  }
+  *out = m;
+  return SRLA_OK;
+}
+
+int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_device) {
+  if (!m) return SRLA_E_INVAL;
+  if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
+  if (n == 0) return SRLA_OK;
+  if (!pairs) return fail(m, SRLA_E_INVAL, "pairs is NULL");
+  int rc = reserve_touched(m, m->slice_pairs + n);
+  if (rc) return rc;
+  const uint16_t code = stamp_code(m->slice);
+  if (on_device) {
+    hipEvent_t a;
+    span_begin(m, ST_SCAN, &a);
+    HIP_TRY(m, launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched, m->cnt, m->stream));
+    span_end(m, ST_SCAN, a);
+    m->slice_pairs += n;
+    m->scan_launches++;
+    m->scan_pairs += n;
+    return SRLA_OK;
+  }
+  // host input: copy chunk by chunk through two pinned buffers
+  for (int i = 0; i < 2; ++i) {
+    if (!m->h_stage[i]) {
+      if (halloc(&m->h_stage[i], 2 * kStageChunk) != hipSuccess ||
+          dalloc(&m->d_stage[i], 2 * kStageChunk) != hipSuccess ||
+          hipEventCreateWithFlags(&m->stage_ev[i], hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(m, SRLA_E_NOMEM, "cannot allocate the host-ingest ring");
+      }
+    }
+  }
+  for (uint64_t off = 0; off < n; off += kStageChunk) {
+    const uint64_t cnt = std::min(kStageChunk, n - off);
+    const int b = m->stage_next;
+    m->stage_next ^= 1;
+    if (m->stage_busy[b]) HIP_TRY(m, hipEventSynchronize(m->stage_ev[b]));
+    std::memcpy(m->h_stage[b], pairs + 2 * off, cnt * 2 * sizeof(uint32_t));
+    HIP_TRY(m, hipMemcpyAsync(m->d_stage[b], m->h_stage[b], cnt * 2 * sizeof(uint32_t),
+                              hipMemcpyHostToDevice, m->stream));
+    HIP_TRY(m, hipEventRecord(m->stage_ev[b], m->stream));
+    m->stage_busy[b] = true;
+    hipEvent_t a;
+    span_begin(m, ST_SCAN, &a);
+    HIP_TRY(m, launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched, m->cnt,
+                           m->stream));
+    span_end(m, ST_SCAN, a);
+    m->slice_pairs += cnt;
+    m->scan_launches++;
+    m->scan_pairs += cnt;
+  }
+  return SRLA_OK;
+}
+
+int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
+  if (!m || !out) return m ? fail(m, SRLA_E_INVAL, "out is NULL") : SRLA_E_INVAL;
+  if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
+  const uint16_t now = stamp_code(m->slice);
+  const Geo& geo = m->geo;
+  hipStream_t st = m->stream;
+  hipEvent_t ta;
+
+  // the sampled-source count, fetched while the sweep runs
+  HIP_TRY(m, hipMemcpyAsync(m->h_cnt, m->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIP_TRY(m, hipEventRecord(m->ev_count, st));
+
+  span_begin(m, ST_SWEEP, &ta);
+  HIP_TRY(m, launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st));
+  HIP_TRY(m, launch_sweep_le(m->le, m->bitmap, m->row_fill, geo, now, st));
+  if (m->slice % kRescrubPeriod == 0) HIP_TRY(m, launch_scrub(m->re, m->n_re, now, st));
+  HIP_TRY(m, launch_union_prob(m->row_fill, geo, m->up, st));
+  span_end(m, ST_SWEEP, ta);
+
+  HIP_TRY(m, hipEventSynchronize(m->ev_count));
+  const uint64_t n_raw = m->h_cnt->touched;
+  if (n_raw > m->slice_pairs) {
+    m->poisoned = true;
+    return fail(m, SRLA_E_DEVICE, "sampled-source count exceeds the pairs scanned");
+  }
+
+  // finalize: sort + unique the sampled sources, candidate check, N_t
+  span_begin(m, ST_FINALIZE, &ta);
+  uint32_t* sorted = m->touched;
+  if (n_raw > 0) {
+    HIP_TRY(m, radix_sort_u32(m->touched, m->touched_tmp, n_raw, m->hist, &sorted, st));
+    HIP_TRY(m, launch_finalize(sorted, n_raw, m->re, m->si, geo, now, m->mark, m->cnt, st));
+    HIP_TRY(m, compact_u32(m->mark, 1u, sorted, &m->cnt->touched, n_raw, m->news,
+                           &m->cnt->n_new, m->blockw, st));
+  }
+  span_end(m, ST_FINALIZE, ta);
+
+  // merge + per-candidate estimate
+  span_begin(m, ST_ESTIMATE, &ta);
+  const uint32_t n_old = m->n_ncsip;
+  uint64_t n_max = (uint64_t)n_old + n_raw;
+  if (n_max > m->cap) n_max = m->cap;
+  HIP_TRY(m, launch_merge(m->ncsip, n_old, m->news, n_raw, m->cnt, m->cap, m->csip, m->cflags, st));
+  HIP_TRY(m, launch_estimate(m->csip, n_max, m->cnt, m->bitmap, m->re, m->up, geo, now, m->est,
+                             m->cflags, m->U, m->W, st));
+  span_end(m, ST_ESTIMATE, ta);
+
+  // Algorithm 3: SI <- 0, carried list compacted in order, its SI bits set
+  span_begin(m, ST_SLIDE, &ta);
+  HIP_TRY(m, launch_fill_u32((uint32_t*)m->si, 0u, m->si_words, st));
+  HIP_TRY(m, compact_u32(m->cflags, 8u, m->csip, &m->cnt->n_cand, n_max, m->ncsip_next,
+                         &m->cnt->n_keep, m->cblockw, st));
+  HIP_TRY(m, launch_si_mark(m->ncsip_next, &m->cnt->n_keep, n_max, (uint32_t*)m->si, geo, st));
+  span_end(m, ST_SLIDE, ta);
+
+  span_begin(m, ST_REPORT, &ta);
+  HIP_TRY(m, hipMemcpyAsync(m->h_cnt, m->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
+  HIP_TRY(m, hipMemcpyAsync(m->h_row_fill, m->row_fill, geo.u * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, st));
+  HIP_TRY(m, hipMemcpyAsync(m->h_up, m->up, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(m, hipStreamSynchronize(st));
+  const Counters c = *m->h_cnt;
+  const uint64_t n = c.n_cand;
+  if (c.overflow) {
+    m->poisoned = true;
+    collect_spans(m);
+    return fail(m, SRLA_E_CAPACITY, "candidate list exceeds max_candidates");
+  }
+  if (n) {
+    HIP_TRY(m, hipMemcpyAsync(m->h_ip, m->csip, n * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(m, hipMemcpyAsync(m->h_est, m->est, n * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(m, hipMemcpyAsync(m->h_flags, m->cflags, n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(m, hipMemcpyAsync(m->h_U, m->U, n * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(m, hipMemcpyAsync(m->h_W, m->W, n, hipMemcpyDeviceToHost, st));
+  }
+  // the next slice starts with empty counters
+  HIP_TRY(m, launch_fill_u32((uint32_t*)m->cnt, 0u, sizeof(Counters) / 4, st));
+  span_end(m, ST_REPORT, ta);
+  HIP_TRY(m, hipStreamSynchronize(st));
+
+  std::swap(m->ncsip, m->ncsip_next);
+  m->n_ncsip = c.n_keep;
+  const uint64_t closed = m->slice;
+  m->slice++;
+  m->slice_pairs = 0;
+  m->estimates++;
+  if (m->timing) collect_spans(m);
+
+  for (uint32_t i = 0; i < geo.u; ++i) m->h_row_fill64[i] = m->h_row_fill[i];
+  out->slice = closed;
+  out->window_full = closed >= (uint64_t)(geo.k - 1) ? 1u : 0u;
+  out->n = n;
+  out->ip = m->h_ip;
+  out->est = m->h_est;
+  out->flags = m->h_flags;
+  out->union_weight = m->h_U;
+  out->re_weight = m->h_W;
+  out->row_fill = m->h_row_fill64;
+  out->up = *m->h_up;
+  out->n_touched = c.n_unique;
+  out->n_new = c.n_new;
+  return SRLA_OK;
+}
+
+int srla_dump_state(srla_monitor_t* m, int which, uint16_t* host_out, uint64_t cells) {
+  if (!m || !host_out) return m ? fail(m, SRLA_E_INVAL, "host_out is NULL") : SRLA_E_INVAL;
+  const uint16_t* src;
+  uint64_t n;
+  if (which == SRLA_DUMP_LE) { src = m->le; n = m->n_le; }
+  else if (which == SRLA_DUMP_RE) { src = m->re; n = m->n_re; }
+  else if (which == SRLA_DUMP_SI) { src = m->si; n = m->n_si; }
+  else return fail(m, SRLA_E_INVAL, "unknown state array");
+  if (cells != n) return fail(m, SRLA_E_INVAL, "cells does not match the array size");
+  HIP_TRY(m, hipMemcpyAsync(host_out, src, n * 2, hipMemcpyDeviceToHost, m->stream));
+  HIP_TRY(m, hipStreamSynchronize(m->stream));
+  if (which == SRLA_DUMP_SI) return SRLA_OK;
+  const int32_t now = stamp_code(m->slice);
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint16_t c = host_out[i];
+    if (c == 0) { host_out[i] = 65535; continue; }
+    int32_t d = now - (int32_t)c;
+    if (d < 0) d += (int32_t)kStampPeriod;
+    host_out[i] = d >= (int32_t)kScrubAge ? 65535 : (uint16_t)d;
+  }
+  return SRLA_OK;
+}
+
+int srla_timings(srla_monitor_t* m, srla_timings_t* out, int reset) {
+  if (!m || !out) return SRLA_E_INVAL;
+  HIP_TRY(m, hipStreamSynchronize(m->stream));
+  collect_spans(m);
+  out->scan_ms = m->acc_ms[ST_SCAN];
+  out->scan_launches = m->scan_launches;
+  out->scan_pairs = m->scan_pairs;
+  out->sweep_ms = m->acc_ms[ST_SWEEP];
+  out->finalize_ms = m->acc_ms[ST_FINALIZE];
+  out->estimate_ms = m->acc_ms[ST_ESTIMATE];
+  out->slide_ms = m->acc_ms[ST_SLIDE];
+  out->report_ms = m->acc_ms[ST_REPORT];
+  out->estimates = m->estimates;
+  if (reset) {
+    for (double& x : m->acc_ms) x = 0;
+    m->scan_launches = m->scan_pairs = m->estimates = 0;
+  }
+  return SRLA_OK;
+}
+
+int srla_destroy(srla_monitor_t* m) {
+  release(m);
+  return SRLA_OK;
+}
+
+const char* srla_last_error(const srla_monitor_t* m) {
+  if (!m) return "no monitor";
+  return m->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,232 @@
+"""ctypes binding of libsrla.so (include/srla.h), argument marshalling only.
+
+Every step of the SRLA path runs in the library's HIP kernels; this module
+only converts arguments.  PyTorch is imported first so that the library and
+torch share one HIP runtime (device tensors and streams cross the boundary as
+raw pointers).  If the library has not been built, loading fails loudly:
+there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime this library links against)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsrla.so")
+
+SRLA_OK, SRLA_E_INVAL, SRLA_E_NOMEM, SRLA_E_CAPACITY, SRLA_E_STATE, SRLA_E_DEVICE = 0, -1, -2, -3, -4, -5
+SRLA_DUMP_LE, SRLA_DUMP_RE, SRLA_DUMP_SI = 0, 1, 2
+SRLA_FLAG_SUPER, SRLA_FLAG_SAT, SRLA_FLAG_NEW, SRLA_FLAG_KEEP = 1, 2, 4, 8
+SRLA_CFG_TIMING = 1
+
+
+class srla_geometry_t(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_uint32), ("v_re", ctypes.c_uint32), ("g", ctypes.c_uint32),
+                ("v_le", ctypes.c_uint32), ("g_le", ctypes.c_uint32),
+                ("hash_seed", ctypes.c_uint64)]
+
+
+class srla_config_t(ctypes.Structure):
+    _fields_ = [("window_slices", ctypes.c_uint32), ("threshold", ctypes.c_uint32),
+                ("geom", srla_geometry_t), ("max_candidates", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32)]
+
+
+class srla_report_t(ctypes.Structure):
+    _fields_ = [("slice", ctypes.c_uint64), ("window_full", ctypes.c_uint32),
+                ("n", ctypes.c_uint64),
+                ("ip", ctypes.POINTER(ctypes.c_uint32)),
+                ("est", ctypes.POINTER(ctypes.c_double)),
+                ("flags", ctypes.POINTER(ctypes.c_uint8)),
+                ("union_weight", ctypes.POINTER(ctypes.c_uint32)),
+                ("re_weight", ctypes.POINTER(ctypes.c_uint8)),
+                ("row_fill", ctypes.POINTER(ctypes.c_uint64)),
+                ("up", ctypes.c_double), ("n_touched", ctypes.c_uint64),
+                ("n_new", ctypes.c_uint64)]
+
+
+class srla_timings_t(ctypes.Structure):
+    _fields_ = [("scan_ms", ctypes.c_double), ("scan_launches", ctypes.c_uint64),
+                ("scan_pairs", ctypes.c_uint64), ("sweep_ms", ctypes.c_double),
+                ("finalize_ms", ctypes.c_double), ("estimate_ms", ctypes.c_double),
+                ("slide_ms", ctypes.c_double), ("report_ms", ctypes.c_double),
+                ("estimates", ctypes.c_uint64)]
+
+
+EXPORTS = ["srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
+           "srla_dump_state", "srla_timings", "srla_destroy", "srla_last_error"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsrla.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.srla_footprint_bytes.restype = ctypes.c_uint64
+        L.srla_footprint_bytes.argtypes = [ctypes.POINTER(srla_config_t)]
+        L.srla_create.restype = ctypes.c_int
+        L.srla_create.argtypes = [ctypes.POINTER(srla_config_t), vp, ctypes.POINTER(vp)]
+        L.srla_scan.restype = ctypes.c_int
+        L.srla_scan.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_int]
+        L.srla_estimate.restype = ctypes.c_int
+        L.srla_estimate.argtypes = [vp, ctypes.POINTER(srla_report_t)]
+        L.srla_dump_state.restype = ctypes.c_int
+        L.srla_dump_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_uint64]
+        L.srla_timings.restype = ctypes.c_int
+        L.srla_timings.argtypes = [vp, ctypes.POINTER(srla_timings_t), ctypes.c_int]
+        L.srla_destroy.restype = ctypes.c_int
+        L.srla_destroy.argtypes = [vp]
+        L.srla_last_error.restype = ctypes.c_char_p
+        L.srla_last_error.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- C names
+
+def make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22, flags=0):
+    return srla_config_t(k, theta, srla_geometry_t(u, v_re, g, v_le, G, hash_seed),
+                         max_candidates, flags)
+
+
+def srla_footprint_bytes(cfg):
+    return lib().srla_footprint_bytes(ctypes.byref(cfg))
+
+
+def srla_create(cfg, hip_stream=None):
+    """Returns (status, handle)."""
+    h = ctypes.c_void_p()
+    rc = lib().srla_create(ctypes.byref(cfg), hip_stream, ctypes.byref(h))
+    return rc, h
+
+
+def srla_scan(handle, pairs_ptr, n, on_device):
+    return lib().srla_scan(handle, pairs_ptr, n, int(on_device))
+
+
+def srla_estimate(handle, report):
+    return lib().srla_estimate(handle, ctypes.byref(report))
+
+
+def srla_dump_state(handle, which, out_ptr, cells):
+    return lib().srla_dump_state(handle, which, out_ptr, cells)
+
+
+def srla_timings(handle, out, reset):
+    return lib().srla_timings(handle, ctypes.byref(out), int(reset))
+
+
+def srla_destroy(handle):
+    return lib().srla_destroy(handle)
+
+
+def srla_last_error(handle):
+    s = lib().srla_last_error(handle)
+    return s.decode() if s else ""
+
+
+# ---------------------------------------------------------------- convenience
+
+class SrlaError(RuntimeError):
+    def __init__(self, rc, msg):
+        super().__init__("srla status %d: %s" % (rc, msg))
+        self.rc = rc
+
+
+class Report:
+    """Copy of one slice's report as numpy arrays."""
+
+    def __init__(self, r, u):
+        n = r.n
+
+        def arr(p, dt):
+            return np.ctypeslib.as_array(p, (n,)).copy() if n else np.zeros(0, dt)
+
+        self.slice = r.slice
+        self.window_full = bool(r.window_full)
+        self.n = n
+        self.ip = arr(r.ip, np.uint32)
+        self.est = arr(r.est, np.float64)
+        self.flags = arr(r.flags, np.uint8)
+        self.union_weight = arr(r.union_weight, np.uint32)
+        self.re_weight = arr(r.re_weight, np.uint8)
+        self.row_fill = np.ctypeslib.as_array(r.row_fill, (u,)).copy()
+        self.up = r.up
+        self.n_touched = r.n_touched
+        self.n_new = r.n_new
+
+
+class Monitor:
+    """One SRLA monitor on the current HIP device.
+
+    stream: a torch.cuda.Stream (or None for the library's own stream)."""
+
+    def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22,
+                 timing=False, stream=None):
+        self.cfg = make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates,
+                               SRLA_CFG_TIMING if timing else 0)
+        self.stream = stream
+        hs = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        rc, h = srla_create(self.cfg, hs)
+        if rc != SRLA_OK:
+            raise SrlaError(rc, "srla_create failed")
+        self._h = h
+
+    def _check(self, rc):
+        if rc != SRLA_OK:
+            raise SrlaError(rc, srla_last_error(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            srla_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def scan(self, pairs):
+        """pairs: torch uint32/int32 CUDA tensor or numpy uint32 array, 2n values
+        (aip, bip interleaved) or shape (n, 2)."""
+        if isinstance(pairs, torch.Tensor):
+            if not pairs.is_cuda:
+                pairs = pairs.numpy()
+            else:
+                assert pairs.is_contiguous() and pairs.element_size() == 4
+                n = pairs.numel() // 2
+                self._check(srla_scan(self._h, ctypes.c_void_p(pairs.data_ptr()), n, True))
+                return
+        p = np.ascontiguousarray(pairs, dtype=np.uint32).reshape(-1)
+        self._check(srla_scan(self._h, ctypes.c_void_p(p.ctypes.data), p.size // 2, False))
+
+    def estimate(self):
+        r = srla_report_t()
+        self._check(srla_estimate(self._h, r))
+        return Report(r, self.cfg.geom.u)
+
+    def cells(self, which):
+        g = self.cfg.geom
+        return {SRLA_DUMP_LE: g.u * g.v_le * g.g_le, SRLA_DUMP_RE: g.u * g.v_re * g.g,
+                SRLA_DUMP_SI: g.u * g.v_re}[which]
+
+    def dump(self, which):
+        n = self.cells(which)
+        out = np.empty(n, dtype=np.uint16)
+        self._check(srla_dump_state(self._h, which, ctypes.c_void_p(out.ctypes.data), n))
+        return out
+
+    def timings(self, reset=False):
+        t = srla_timings_t()
+        self._check(srla_timings(self._h, t, reset))
+        return {f: getattr(t, f) for f, _ in srla_timings_t._fields_}
+
+    @property
+    def footprint_bytes(self):
+        return srla_footprint_bytes(self.cfg)

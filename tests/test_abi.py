@@ -1,0 +1,111 @@
+"""The C-ABI library loads and exports what include/srla.h declares; host-side
+validation needs no GPU.  No test here launches device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "srla.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(srla_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1803_10369_amd as P
+    P.srla.lib()
+    return P
+
+
+def test_every_declared_symbol_is_exported(P):
+    names = _declared_functions()
+    assert set(names) == {"srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
+                          "srla_dump_state", "srla_timings", "srla_destroy", "srla_last_error"}
+    L = ctypes.CDLL(P.srla.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(P.EXPORTS) == set(names)
+
+
+def test_binding_struct_layouts_match_header(P, tmp_path):
+    """ctypes layouts against what a C compiler makes of include/srla.h."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    src.write_text('''
+#include <stddef.h>
+#include <stdio.h>
+#include "srla.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\\n", sizeof(srla_geometry_t), sizeof(srla_config_t),
+         sizeof(srla_report_t), sizeof(srla_timings_t));
+  printf("%zu %zu %zu %zu\\n", offsetof(srla_config_t, max_candidates),
+         offsetof(srla_report_t, row_fill), offsetof(srla_report_t, up),
+         offsetof(srla_timings_t, estimates));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    S = P.srla
+    want = [ctypes.sizeof(S.srla_geometry_t), ctypes.sizeof(S.srla_config_t),
+            ctypes.sizeof(S.srla_report_t), ctypes.sizeof(S.srla_timings_t),
+            S.srla_config_t.max_candidates.offset, S.srla_report_t.row_fill.offset,
+            S.srla_report_t.up.offset, S.srla_timings_t.estimates.offset]
+    assert [int(x) for x in out] == want
+
+
+BAD = [
+    dict(k=0), dict(k=32768), dict(theta=0), dict(u=0), dict(u=17), dict(g=0), dict(g=65),
+    dict(G=0), dict(G=100), dict(G=32), dict(v_re=0), dict(v_le=0),
+]
+
+
+@pytest.mark.parametrize("bad", BAD)
+def test_invalid_configs_are_rejected_without_a_device(P, bad):
+    base = dict(k=8, theta=1024, u=4, v_re=2048, g=8, v_le=16, G=1024, hash_seed=1)
+    base.update(bad)
+    cfg = P.make_config(**base)
+    assert P.srla_footprint_bytes(cfg) == 0
+    rc, h = P.srla_create(cfg)
+    assert rc == -1 and not h.value
+
+
+def test_bad_flags_and_capacity_rejected(P):
+    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, max_candidates=0)
+    assert P.srla_create(cfg)[0] == -1
+    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=2)
+    assert P.srla_create(cfg)[0] == -1
+
+
+def test_footprint_counts_dr_arrays(P):
+    # backbone-shaped monitor: SRE 8 x 2^20 cells, SLE 2^24 cells
+    cfg = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1)
+    fp = P.srla_footprint_bytes(cfg)
+    le, re, si = 2 * (1 << 24), 2 * (1 << 23), 2 * 8 * 131072
+    assert le + re + si + (1 << 24) // 8 <= fp < le + re + si + (1 << 24) // 8 + 4096
+
+
+def test_null_handles(P):
+    L = P.srla.lib()
+    assert L.srla_destroy(None) == 0
+    assert L.srla_last_error(None) == b"no monitor"
+    assert L.srla_scan(None, None, 0, 0) == -1
+    assert L.srla_estimate(None, None) == -1
+
+
+def test_product_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1803_10369_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "srla_oracle" not in text, f

@@ -1,0 +1,218 @@
+"""HIP path against the oracle, element by element, on the same seeded pairs.
+
+DR dumps, SI words, candidate lists, flags and integer counts must match
+bit for bit; FP64 estimates within 1e-12 relative.  Sizes span many scan,
+sort and compaction tiles with ragged tails.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1803_10369_amd as srla
+from trafficgen.configs import workload, scaled
+
+from gpu_helpers import compare_dumps, compare_reports, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    torch.cuda.set_device(0)
+
+
+def _run(stream, mon, slices, max_candidates=1 << 16, dump_every=1, split=None, host=False):
+    g = srla.Monitor(**mon, max_candidates=max_candidates)
+    o = oracle.Monitor(**mon)
+    for s in slices:
+        pairs = stream.slice(s) if hasattr(stream, "slice") else stream(s)
+        print("slice", s, "pairs", len(pairs), flush=True)
+        if split:
+            for lo in range(0, len(pairs), split):
+                part = pairs[lo:lo + split]
+                g.scan(part if host else to_device(part))
+        else:
+            g.scan(pairs if host else to_device(pairs))
+        o.scan(pairs)
+        rg, rc = g.estimate(), o.estimate()
+        compare_reports(rg, rc, mon["theta"], ctx="slice %d" % s)
+        if dump_every and (s % dump_every == 0):
+            compare_dumps(g, o, ctx="slice %d" % s)
+    compare_dumps(g, o, ctx="end")
+    g.close()
+    return rg
+
+
+def test_tiny_workload_full_run():
+    stream, mon, n = workload("tiny")
+    r = _run(stream, mon, range(n))
+    assert r.window_full and r.n > 0
+
+
+def test_tiny_coupled_workload_full_run():
+    stream, mon, n = workload("tiny_coupled")
+    r = _run(stream, mon, range(n), dump_every=4)
+    assert r.n > 0 and np.isfinite(r.est).all()
+
+
+def _rand_stream(seed, n, n_src, heavy_theta):
+    def gen(s):
+        rng = np.random.default_rng(seed * 1000 + s)
+        w = 1.0 / np.arange(1, n_src + 1) ** 1.1
+        src = rng.choice(n_src, size=n, p=w / w.sum()).astype(np.uint32) * np.uint32(2654435761)
+        dst = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
+        p = np.stack([src, dst], 1)
+        if s < 3:
+            h = np.stack([np.full(heavy_theta, 7, np.uint32),
+                          rng.integers(0, 2 ** 32, size=heavy_theta, dtype=np.uint64).astype(np.uint32)], 1)
+            p = np.concatenate([p, h])
+        if s == 2:
+            p = p[:0]
+        return p
+    return gen
+
+
+SMALL = [
+    # k, theta, u, v_re, g, v_le, G, pairs/slice, sources, slices
+    (3, 64, 3, 64, 8, 8, 128, 30000, 2000, 8),
+    (1, 64, 2, 32, 8, 4, 64, 15000, 1000, 5),
+    (5, 16, 1, 16, 4, 16, 64, 8000, 600, 9),
+    (4, 4, 4, 128, 8, 32, 64, 6000, 3000, 7),
+    (6, 4096, 2, 64, 16, 8, 192, 40000, 500, 8),
+    (2, 256, 5, 33, 3, 7, 64, 20000, 1200, 6),
+    (7, 1024, 8, 4096, 8, 64, 1024, 50000, 20000, 9),
+    (3, 300, 16, 97, 64, 5, 4096, 12000, 800, 5),
+]
+
+
+@pytest.mark.parametrize("case", SMALL)
+def test_small_geometries(case):
+    k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
+    mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=1000 + k + u)
+    _run(_rand_stream(k + u, n, n_src, 3 * theta // 2), mon, range(slices))
+
+
+def test_host_input_chunked_and_unaligned_device_input():
+    stream, mon, _ = workload("tiny")
+    stream = scaled(stream, 77_777)
+    # host pointers, several scans per slice
+    _run(stream, mon, range(10), host=True, split=20_001, dump_every=3)
+    # device pointers that are 4- but not 16-byte aligned
+    g = srla.Monitor(**mon, max_candidates=1 << 16)
+    o = oracle.Monitor(**mon)
+    for s in range(6):
+        p = stream.slice(s)
+        flat = to_device(np.concatenate([np.zeros(1, np.uint32), p.reshape(-1)]))
+        g.scan(flat[1:])
+        o.scan(p)
+        compare_reports(g.estimate(), o.estimate(), mon["theta"], "unaligned %d" % s)
+    compare_dumps(g, o)
+    g.close()
+
+
+def test_pair_order_and_repeat_runs_are_identical():
+    stream, mon, _ = workload("tiny")
+    reps = []
+    for variant in range(3):
+        g = srla.Monitor(**mon, max_candidates=1 << 16)
+        out = []
+        for s in range(10):
+            p = stream.slice(s)
+            if variant == 2:
+                p = p[np.random.default_rng(s).permutation(len(p))]
+            g.scan(to_device(p))
+            r = g.estimate()
+            out.append((r.ip, r.est, r.flags, r.union_weight, r.re_weight, r.row_fill))
+        out.append(tuple(g.dump(w) for w in (0, 1, 2)))
+        reps.append(out)
+        g.close()
+    for other in reps[1:]:
+        for x, y in zip(reps[0], other):
+            for a, b in zip(x, y):
+                assert np.array_equal(a, b)
+
+
+def test_empty_slices_and_silence():
+    stream, mon, _ = workload("tiny")
+    g = srla.Monitor(**mon, max_candidates=1 << 16)
+    o = oracle.Monitor(**mon)
+    for s in range(12):
+        if s in (0, 3, 4, 9, 10, 11):
+            g.scan(to_device(np.zeros((0, 2), np.uint32)))
+        else:
+            p = stream.slice(s)
+            g.scan(to_device(p))
+            o.scan(p)
+        compare_reports(g.estimate(), o.estimate(), mon["theta"], "slice %d" % s)
+    compare_dumps(g, o)
+    g.close()
+
+
+def test_capacity_overflow_is_reported_and_poisons():
+    stream, mon, _ = workload("tiny")
+    g = srla.Monitor(**mon, max_candidates=5)
+    g.scan(to_device(stream.slice(0)))
+    with pytest.raises(srla.SrlaError) as e:
+        g.estimate()
+    assert e.value.rc == -3
+    with pytest.raises(srla.SrlaError) as e:
+        g.scan(to_device(stream.slice(1)))
+    assert e.value.rc == -4
+    g.close()
+
+
+def test_backbone_workload_prefix_full_size():
+    """The backbone-shaped workload (8M pairs per slice, SRE 8 x 2^20 cells,
+    SLE 2^24 cells, k = 300) in the launch configuration the bench times: one
+    device-pointer scan per slice."""
+    stream, mon, _ = workload("backbone")
+    _run(stream, mon, range(3), max_candidates=1 << 22)
+
+
+def test_backbone_short_window_expiry():
+    """Backbone geometry with k = 16 over 40 slices, so DRs leave the window
+    and carried candidates are dropped at full column counts."""
+    stream, mon, _ = workload("backbone_k16")
+    stream = scaled(stream, 600_000)
+    _run(stream, mon, range(40), max_candidates=1 << 22, dump_every=13)
+
+
+def test_paper_geometry_prefix():
+    """u = 4, v = 65,536, g' = 1,024 (the paper's chosen parameters): a 512 MB
+    LE array, far beyond the last-level cache."""
+    stream, mon, _ = workload("backbone_paper")
+    stream = scaled(stream, 2_000_000)
+    _run(stream, mon, range(3), max_candidates=1 << 22)
+
+
+def test_device_generator_matches_host_twin():
+    from trafficgen.device import DeviceStream
+    stream, _, _ = workload("tiny")
+    ds = DeviceStream(stream)
+    for s in (0, 1, 7):
+        d = ds.generate(s).cpu().numpy().view(np.uint32).reshape(-1, 2)
+        assert np.array_equal(d, stream.slice(s))
+    big, _, _ = workload("backbone")
+    dsb = DeviceStream(big)
+    d = dsb.generate(5).cpu().numpy().view(np.uint32).reshape(-1, 2)
+    idx = np.random.default_rng(0).integers(0, big.n_pairs, size=20000)
+    idx.sort()
+    host = np.concatenate([big.slice(5, i, i + 1) for i in idx[:200]])
+    assert np.array_equal(d[idx[:200]], host)
+    lo = 3_000_000
+    assert np.array_equal(d[lo:lo + 50_000], big.slice(5, lo, lo + 50_000))
+
+
+def test_timings_are_recorded():
+    stream, mon, _ = workload("tiny")
+    g = srla.Monitor(**mon, max_candidates=1 << 16, timing=True)
+    for s in range(3):
+        g.scan(to_device(stream.slice(s)))
+        g.estimate()
+    t = g.timings(reset=True)
+    assert t["scan_ms"] > 0 and t["scan_launches"] == 3 and t["scan_pairs"] == 300_000
+    assert t["sweep_ms"] > 0 and t["estimate_ms"] > 0 and t["estimates"] == 3
+    assert g.timings()["scan_ms"] == 0
+    g.close()
