@@ -1,0 +1,195 @@
+"""Throughput and slice-end latency of the SRLA hot path on one MI355X.
+
+One step = one time slice of the backbone-shaped workload: 8M (aip, bip)
+pairs scanned into the SEA (Algorithm 2), then the slice closed (candidate
+check, Eq8-Eq9 estimate of every candidate, Algorithm 3 slide) and its report
+copied to host memory.  Window k = 300 slices, SRE 8 x 2^20 DR cells, SLE
+2^24 DR cells, theta = 1024.  Warm-up steps run first so that the timed
+slices see a full window; the timed slices' pairs are generated into device
+memory before the timed region starts.
+
+Prints one JSON line (rank 0).  `value` is pairs (packets) scanned per second
+over the whole timed region; `p99_ms` is the 99th percentile of the slice-end
+estimate latency (host time from the end of a slice's scan to its report in
+host memory).
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "packets/s scanned + p99 slice-end estimate latency (ms), 1 MI355X"
+HBM_PEAK_GBS = 8000.0
+
+
+def scan_bytes_per_pair(u, tau):
+    """Algorithmic bytes of Algorithm 2 per pair: the 8-byte pair, u 2-byte LE
+    DR stores, and with probability 2^-tau u 2-byte SRE DR stores plus a
+    4-byte sampled-source append."""
+    return 8.0 + 2.0 * u + (2.0 * u + 4.0) * 2.0 ** (-tau)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def oracle_baseline(stream, mon, slices):
+    """Times the oracle (single-threaded C) on the first `slices` slices."""
+    import oracle
+    o = oracle.Monitor(**mon)
+    pairs = [stream.slice(s) for s in range(slices)]
+    t0 = time.perf_counter()
+    for p in pairs:
+        o.scan(p)
+        o.estimate()
+    dt = time.perf_counter() - t0
+    n = sum(len(p) for p in pairs)
+    o.close()
+    return n / dt, dt, n
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--workload", default="backbone")
+    ap.add_argument("--cpu-slices", type=int, default=2,
+                    help="slices of the same workload the oracle baseline scans")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-candidates", type=int, default=1 << 25)
+    ap.add_argument("--scan-flat", action="store_true",
+                    help="scan without per-XCD row ownership (A/B of the scan kernels)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1803_10369_amd as srla
+    from trafficgen.configs import workload
+    from trafficgen.device import DeviceStream
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream, mon, _ = workload(args.workload)
+    n_pairs = stream.n_pairs
+    ds = DeviceStream(stream)
+    st = torch.cuda.Stream()
+    torch.cuda.set_stream(st)     # generation, scan and estimate share one stream
+
+    m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
+                     scan_flat=args.scan_flat)
+    buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
+    t_w = time.perf_counter()
+    for s in range(args.warmup):
+        ds.generate(s, out=buf, stream=st)
+        m.scan(buf)
+        m.estimate()
+        if s % 50 == 0:
+            print("warmup slice %d (%.1fs)" % (s, time.perf_counter() - t_w), file=sys.stderr,
+                  flush=True)
+    # the timed slices' pairs, resident in HBM before the timed region
+    timed = [ds.generate(args.warmup + i, stream=st) for i in range(args.steps)]
+    torch.cuda.synchronize()
+    m.timings(reset=True)
+
+    lat = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        m.scan(timed[i])
+        st.synchronize()           # the slice's last pair is scanned
+        ts = time.perf_counter()
+        r = m.estimate(copy=False)   # returns with the report in host memory
+        lat.append((time.perf_counter() - ts) * 1e3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tm = m.timings(reset=True)
+
+    total_s = t1 - t0
+    pairs = args.steps * n_pairs
+    value = pairs / total_s
+    lat = np.array(lat)
+    g = mon
+    tau = 0
+    while g["g"] * (1 << tau) < g["theta"]:
+        tau += 1
+    scan_ms = tm["scan_ms"] / max(1, tm["scan_launches"])
+    per_launch_bytes = scan_bytes_per_pair(g["u"], tau) * n_pairs
+    achieved = per_launch_bytes / (scan_ms * 1e-3) / 1e9
+    stages = {k: tm[k] / args.steps for k in
+              ("scan_ms", "sweep_ms", "finalize_ms", "estimate_ms", "slide_ms", "report_ms")}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_s * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u16",
+        "data": "synthetic",
+        "config": {
+            "workload": ("%s: 1 monitor, window %d slices, %d pairs/slice, Zipf(%g) sources "
+                         "over %d hosts, %d planted super points, SRE %d x %d DR cells, "
+                         "SLE %d DR cells (uint16 slice stamps), theta %d"
+                         % (args.workload, g["k"], n_pairs, stream.alpha, stream.n_ranks,
+                            len(stream.planted), g["u"], g["v_re"] * g["g"],
+                            g["u"] * g["v_le"] * g["G"], g["theta"])),
+            "u": g["u"], "v_re": g["v_re"], "g": g["g"], "v_le": g["v_le"], "g_le": g["G"],
+            "window": g["k"], "theta": g["theta"], "pairs_per_slice": n_pairs,
+            "slices_timed": [args.warmup, args.warmup + args.steps - 1],
+        },
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "stage_ms_per_slice": stages,
+        "state": {"candidates": int(r.n), "up": r.up,
+                  "row_fill_frac": [float(x) / (g["v_le"] * g["G"]) for x in r.row_fill],
+                  "n_touched": int(r.n_touched), "n_new": int(r.n_new)},
+        "roofline": {
+            "kernel": "k_scan_flat (Algorithm 2)" if args.scan_flat else "k_scan_xcd (Algorithm 2)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_pair": scan_bytes_per_pair(g["u"], tau),
+            "launch_ms": scan_ms,
+            "random_stores_per_s": g["u"] * (1 + 2.0 ** -tau) * n_pairs / (scan_ms * 1e-3),
+        },
+    }
+    if not args.no_cpu_baseline:
+        rate, dt, n = oracle_baseline(stream, mon, args.cpu_slices)
+        out["cpu_baseline"] = {
+            "value": rate, "unit": "packets/s", "cores": 1, "kind": "oracle",
+            "sample": ("first %d slices (%d pairs) of the same workload, scan + end-of-slice "
+                       "estimate, single-threaded C oracle, %.1f s on %s (nproc %d)"
+                       % (args.cpu_slices, n, dt, cpu_model(), os.cpu_count())),
+        }
+    print(json.dumps(out), flush=True)
+    m.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -48,7 +48,10 @@ enum {
 
 /* srla_config_t.flags */
 enum {
-    SRLA_CFG_TIMING = 1   /* record HIP events around every stage */
+    SRLA_CFG_TIMING = 1,    /* record HIP events around every stage */
+    SRLA_CFG_SCAN_FLAT = 2  /* scan without the per-XCD row ownership (for a
+                               GPU partitioned so that one device is one XCD);
+                               results are identical either way */
 };
 
 /*

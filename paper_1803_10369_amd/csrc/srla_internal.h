@@ -86,7 +86,7 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t 
 
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                        uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
-                       hipStream_t st);
+                       bool xcd_aware, hipStream_t st);
 
 hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
                            const Geo& geo, uint16_t now, hipStream_t st);
@@ -124,7 +124,9 @@ hipError_t launch_estimate(const uint32_t* csip, uint64_t n_max, const Counters*
                            const Geo& geo, uint16_t now, double* est, uint8_t* cflags,
                            uint32_t* U, uint8_t* W, hipStream_t st);
 
-hipError_t launch_si_mark(const uint32_t* cands, const uint32_t* n_dev, uint64_t n_max,
-                          uint32_t* si_words, const Geo& geo, hipStream_t st);
+// Algorithm 3's SI step (after the KEEP flags and n_keep are final)
+hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
+                            uint64_t n_max, uint32_t* si_words, uint64_t n_words, const Geo& geo,
+                            hipStream_t st);
 
 }  // namespace srla

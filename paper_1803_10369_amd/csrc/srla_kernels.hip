@@ -81,7 +81,7 @@ __device__ __forceinline__ void scan_one(uint32_t a, uint32_t b, bool valid, con
 }
 
 template <int U, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_scan(const uint32_t* __restrict__ pairs, uint64_t n,
+__global__ __launch_bounds__(kBlock) void k_scan_flat(const uint32_t* __restrict__ pairs, uint64_t n,
                                                 Geo geo, uint16_t code,
                                                 uint16_t* __restrict__ le,
                                                 uint16_t* __restrict__ re,
@@ -112,6 +112,90 @@ __global__ __launch_bounds__(kBlock) void k_scan(const uint32_t* __restrict__ pa
   }
 }
 
+// XCD-aware form.  Workgroups are dispatched to the 8 XCDs round-robin, so
+// block b runs on XCD b % 8 and only ever touches the SEA rows that XCD owns:
+// with u >= 8, XCD x owns rows x, x+8, ...; with u in {1, 2, 4}, XCD x owns
+// row x % u and every u-th XCD takes the next tile.  Each XCD's L2 then sees
+// one LE row (4 MiB for 2048 x 1024 DRs) instead of all of them.  Each
+// (pair, row) is still stored exactly once, and the sampled-source append is
+// done by the owner of row 0; results do not depend on the actual placement.
+constexpr int kXcds = 8;
+
+template <int U>
+__global__ __launch_bounds__(kBlock) void k_scan_xcd(const uint32_t* __restrict__ pairs,
+                                                    uint64_t n, Geo geo, uint16_t code,
+                                                    uint16_t* __restrict__ le,
+                                                    uint16_t* __restrict__ re,
+                                                    uint32_t* __restrict__ touched,
+                                                    Counters* __restrict__ cnt) {
+  constexpr int kParts = U >= kXcds ? 1 : kXcds / U;      // tiles per XCD group
+  constexpr int kRowsPerXcd = U >= kXcds ? U / kXcds : 1;
+  const uint32_t xcd = blockIdx.x % kXcds;
+  const uint32_t group = blockIdx.x / kXcds;
+  const uint32_t row0 = U >= kXcds ? xcd : xcd % U;
+  const uint64_t tile = (uint64_t)group * kParts + (U >= kXcds ? 0u : xcd / U);
+  const bool appender = row0 == 0;
+  const uint64_t base = tile * kScanTile;
+  uint32_t a[kScanSteps][2], b[kScanSteps][2];
+  bool v[kScanSteps][2];
+#pragma unroll
+  for (int s = 0; s < kScanSteps; ++s) {
+    const uint64_t p = base + (uint64_t)s * (2 * kBlock) + 2u * threadIdx.x;
+    v[s][0] = p < n;
+    v[s][1] = p + 1 < n;
+    if (v[s][1]) {
+      const uint4 q = *reinterpret_cast<const uint4*>(pairs + 2 * p);
+      a[s][0] = q.x; b[s][0] = q.y; a[s][1] = q.z; b[s][1] = q.w;
+    } else {
+      a[s][0] = v[s][0] ? pairs[2 * p] : 0u;
+      b[s][0] = v[s][0] ? pairs[2 * p + 1] : 0u;
+      a[s][1] = 0u; b[s][1] = 0u;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kScanSteps; ++s) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const uint32_t aa = a[s][h], bb = b[s][h];
+      bool sampled = false;
+      if (v[s][h]) {
+        const uint32_t lei = hrange(mas(geo.h3, bb), geo.G);
+        sampled = (mas(geo.h1, bb) & geo.tau_mask) == 0u;
+        const uint32_t rei = sampled ? hrange(mas(geo.h2, bb), geo.g) : 0u;
+#pragma unroll
+        for (int j = 0; j < kRowsPerXcd; ++j) {
+          const uint32_t r = row0 + (uint32_t)j * kXcds;
+          const uint32_t hr = mas(geo.rh[r], aa);
+          le[((uint64_t)r * geo.v_le + hrange(hr, geo.v_le)) * geo.G + lei] = code;
+          if (sampled) re[((uint64_t)r * geo.v_re + hrange(hr, geo.v_re)) * geo.g + rei] = code;
+        }
+      }
+      if (appender) {
+        const uint64_t mask = __ballot(sampled);
+        if (mask != 0ull) {
+          const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
+          uint32_t slot = 0;
+          if (__lane_id() == leader) slot = atomicAdd(&cnt->touched, (uint32_t)__popcll(mask));
+          slot = __shfl(slot, (int)leader);
+          if (sampled) touched[slot + lane_rank(mask)] = aa;
+        }
+      }
+    }
+  }
+}
+
+template <int U>
+static hipError_t launch_scan_xcd(const uint32_t* pairs, uint64_t n, const Geo& geo,
+                                  uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
+                                  Counters* cnt, hipStream_t st) {
+  constexpr uint64_t kParts = U >= kXcds ? 1 : kXcds / U;
+  const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+  const uint64_t blocks = kXcds * ((tiles + kParts - 1) / kParts);
+  hipLaunchKernelGGL((k_scan_xcd<U>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n, geo,
+                     code, le, re, touched, cnt);
+  return hipGetLastError();
+}
+
 template <int U>
 static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                                 uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
@@ -119,18 +203,28 @@ static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& ge
   const uint64_t blocks = (n + kScanTile - 1) / kScanTile;
   const bool vec = ((uintptr_t)pairs & 15u) == 0;
   if (vec)
-    hipLaunchKernelGGL((k_scan<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
+    hipLaunchKernelGGL((k_scan_flat<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
                        geo, code, le, re, touched, cnt);
   else
-    hipLaunchKernelGGL((k_scan<U, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
+    hipLaunchKernelGGL((k_scan_flat<U, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
                        geo, code, le, re, touched, cnt);
   return hipGetLastError();
 }
 
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                        uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
-                       hipStream_t st) {
+                       bool xcd_aware, hipStream_t st) {
   if (n == 0) return hipSuccess;
+  if (xcd_aware && ((uintptr_t)pairs & 15u) == 0) {
+    switch (geo.u) {
+      case 1: return launch_scan_xcd<1>(pairs, n, geo, code, le, re, touched, cnt, st);
+      case 2: return launch_scan_xcd<2>(pairs, n, geo, code, le, re, touched, cnt, st);
+      case 4: return launch_scan_xcd<4>(pairs, n, geo, code, le, re, touched, cnt, st);
+      case 8: return launch_scan_xcd<8>(pairs, n, geo, code, le, re, touched, cnt, st);
+      case 16: return launch_scan_xcd<16>(pairs, n, geo, code, le, re, touched, cnt, st);
+      default: break;
+    }
+  }
   switch (geo.u) {
     case 4: return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, cnt, st);
     case 8: return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, cnt, st);
@@ -395,7 +489,8 @@ __global__ __launch_bounds__(kBlock) void k_estimate(const uint32_t* __restrict_
       for (uint32_t r = 0; r < geo.u; ++r) {
         const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
         const uint32_t cell = re[((uint64_t)r * geo.v_re + col) * geo.g + c];
-        const uint32_t age = cell ? stamp_age(now, cell) : 0xFFFFFFFFu;
+        // a never-set DR is older than any window, also after the slide
+        const uint32_t age = cell ? stamp_age(now, cell) : kStampPeriod;
         all_now = all_now && age < geo.k;
         all_next = all_next && age + 1u < geo.k;   // after the slide of Algorithm 3
       }
@@ -457,16 +552,34 @@ hipError_t launch_estimate(const uint32_t* csip, uint64_t n_max, const Counters*
 }
 
 // ------------------------------------------------------------------ SI
-// Algorithm 3's marking: bit H4(aip) of SI[i][RH_i(aip)] for every carried
-// candidate and every row.  SI is uint16 [u][v_re], addressed here as 32-bit
-// words so that the OR is a native atomic.
+// Algorithm 3: SI <- 0, then bit H4(aip) of SI[i][RH_i(aip)] for every
+// carried candidate and every row.  SI before this step holds exactly the
+// bits of NCSIP_{t-1} (finalize only reads it), so when no candidate of CSIP_t
+// is dropped -- NCSIP_t = NCSIP_{t-1} u N_t -- the new SI is the old one with
+// the bits of N_t added.  Only when a candidate is dropped is SI cleared and
+// rebuilt from all of NCSIP_t.  The choice is made on the device from the
+// slice's counters.  SI is uint16 [u][v_re], addressed as 32-bit words so
+// that the OR is a native atomic.
 
-__global__ __launch_bounds__(kBlock) void k_si_mark(const uint32_t* __restrict__ cands,
-                                                   const uint32_t* __restrict__ n_dev,
+__global__ __launch_bounds__(kBlock) void k_si_clear_if_dropped(uint32_t* __restrict__ si_words,
+                                                               uint64_t n_words,
+                                                               const Counters* __restrict__ cnt) {
+  if (cnt->n_keep == cnt->n_cand) return;
+  uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (; i < n_words; i += stride) si_words[i] = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_si_mark(const uint32_t* __restrict__ csip,
+                                                   const uint8_t* __restrict__ cflags,
+                                                   const Counters* __restrict__ cnt,
                                                    uint32_t* __restrict__ si_words, Geo geo) {
   const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= *n_dev) return;
-  const uint32_t a = cands[t];
+  if (t >= cnt->n_cand) return;
+  const uint32_t f = cflags[t];
+  const bool rebuild = cnt->n_keep != cnt->n_cand;
+  if (!(f & 8u) || !(rebuild || (f & 4u))) return;   // KEEP, and NEW unless rebuilding
+  const uint32_t a = csip[t];
   const uint32_t bit = hrange(mas(geo.h4, a), 16u);
   for (uint32_t r = 0; r < geo.u; ++r) {
     const uint64_t idx = (uint64_t)r * geo.v_re + hrange(mas(geo.rh[r], a), geo.v_re);
@@ -474,12 +587,19 @@ __global__ __launch_bounds__(kBlock) void k_si_mark(const uint32_t* __restrict__
   }
 }
 
-hipError_t launch_si_mark(const uint32_t* cands, const uint32_t* n_dev, uint64_t n_max,
-                          uint32_t* si_words, const Geo& geo, hipStream_t st) {
-  if (n_max == 0) return hipSuccess;
-  const uint64_t blocks = (n_max + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_si_mark, dim3((uint32_t)blocks), dim3(kBlock), 0, st, cands, n_dev,
-                     si_words, geo);
+hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
+                            uint64_t n_max, uint32_t* si_words, uint64_t n_words, const Geo& geo,
+                            hipStream_t st) {
+  uint64_t cb = (n_words + kBlock - 1) / kBlock;
+  if (cb > 4096) cb = 4096;
+  if (cb == 0) cb = 1;
+  hipLaunchKernelGGL(k_si_clear_if_dropped, dim3((uint32_t)cb), dim3(kBlock), 0, st, si_words,
+                     n_words, cnt);
+  if (n_max) {
+    const uint64_t blocks = (n_max + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_si_mark, dim3((uint32_t)blocks), dim3(kBlock), 0, st, csip, cflags, cnt,
+                       si_words, geo);
+  }
   return hipGetLastError();
 }
 

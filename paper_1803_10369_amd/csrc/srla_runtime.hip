@@ -62,7 +62,7 @@ bool config_ok(const srla_config_t* c) {
   if (c->window_slices < 1 || c->window_slices > 32767) return false;
   if (c->threshold < 1) return false;
   if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
-  if ((c->flags & ~(uint32_t)SRLA_CFG_TIMING) != 0) return false;
+  if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_FLAT)) != 0) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   if (le / g.u / g.g_le != g.v_le || re / g.u / g.g != g.v_re) return false;
@@ -144,7 +144,9 @@ struct srla_monitor {
 
   // timing
   bool timing = false;
+  bool xcd_scan = true;
   std::vector<TimedSpan> spans;
+  std::vector<hipEvent_t> ev_pool;
   double acc_ms[ST_N] = {0, 0, 0, 0, 0, 0};
   uint64_t scan_launches = 0, scan_pairs = 0, estimates = 0;
 };
@@ -194,17 +196,29 @@ uint64_t candidate_bytes(uint64_t cap) {
   return cap * (4 + 4 + 4 + 1 + 1 + 8 + 4) + 4 * compact_block_words(cap);
 }
 
+hipEvent_t pooled_event(srla_monitor* m) {
+  if (!m->ev_pool.empty()) {
+    hipEvent_t e = m->ev_pool.back();
+    m->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
 void span_begin(srla_monitor* m, int stage, hipEvent_t* a) {
+  (void)stage;
   *a = nullptr;
   if (!m->timing) return;
-  if (hipEventCreate(a) != hipSuccess) { *a = nullptr; return; }
-  (void)hipEventRecord(*a, m->stream);
+  *a = pooled_event(m);
+  if (*a) (void)hipEventRecord(*a, m->stream);
 }
 
 void span_end(srla_monitor* m, int stage, hipEvent_t a) {
   if (!m->timing || !a) return;
-  hipEvent_t b;
-  if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+  hipEvent_t b = pooled_event(m);
+  if (!b) { m->ev_pool.push_back(a); return; }
   (void)hipEventRecord(b, m->stream);
   m->spans.push_back({stage, a, b});
 }
@@ -214,8 +228,8 @@ void collect_spans(srla_monitor* m) {
     float ms = 0.f;
     if (hipEventSynchronize(s.b) == hipSuccess && hipEventElapsedTime(&ms, s.a, s.b) == hipSuccess)
       m->acc_ms[s.stage] += ms;
-    (void)hipEventDestroy(s.a);
-    (void)hipEventDestroy(s.b);
+    m->ev_pool.push_back(s.a);
+    m->ev_pool.push_back(s.b);
   }
   m->spans.clear();
 }
@@ -267,6 +281,7 @@ void release(srla_monitor* m) {
     dfree(m->d_stage[i]);
     if (m->stage_ev[i]) (void)hipEventDestroy(m->stage_ev[i]);
   }
+  for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   if (m->ev_count) (void)hipEventDestroy(m->ev_count);
   if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
   delete m;
@@ -293,6 +308,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!m) return SRLA_E_NOMEM;
   m->cfg = *cfg;
   m->timing = (cfg->flags & SRLA_CFG_TIMING) != 0;
+  m->xcd_scan = (cfg->flags & SRLA_CFG_SCAN_FLAT) == 0;
 
   const srla_geometry_t& g = cfg->geom;
   Geo& geo = m->geo;
@@ -400,7 +416,8 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   if (on_device) {
     hipEvent_t a;
     span_begin(m, ST_SCAN, &a);
-    HIP_TRY(m, launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched, m->cnt, m->stream));
+    HIP_TRY(m, launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched, m->cnt, m->xcd_scan,
+                           m->stream));
     span_end(m, ST_SCAN, a);
     m->slice_pairs += n;
     m->scan_launches++;
@@ -431,7 +448,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     hipEvent_t a;
     span_begin(m, ST_SCAN, &a);
     HIP_TRY(m, launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched, m->cnt,
-                           m->stream));
+                           m->xcd_scan, m->stream));
     span_end(m, ST_SCAN, a);
     m->slice_pairs += cnt;
     m->scan_launches++;
@@ -489,10 +506,10 @@ int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
 
   // Algorithm 3: SI <- 0, carried list compacted in order, its SI bits set
   span_begin(m, ST_SLIDE, &ta);
-  HIP_TRY(m, launch_fill_u32((uint32_t*)m->si, 0u, m->si_words, st));
   HIP_TRY(m, compact_u32(m->cflags, 8u, m->csip, &m->cnt->n_cand, n_max, m->ncsip_next,
                          &m->cnt->n_keep, m->cblockw, st));
-  HIP_TRY(m, launch_si_mark(m->ncsip_next, &m->cnt->n_keep, n_max, (uint32_t*)m->si, geo, st));
+  HIP_TRY(m, launch_si_update(m->csip, m->cflags, m->cnt, n_max, (uint32_t*)m->si, m->si_words,
+                              geo, st));
   span_end(m, ST_SLIDE, ta);
 
   span_begin(m, ST_REPORT, &ta);

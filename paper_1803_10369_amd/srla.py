@@ -19,6 +19,7 @@ SRLA_OK, SRLA_E_INVAL, SRLA_E_NOMEM, SRLA_E_CAPACITY, SRLA_E_STATE, SRLA_E_DEVIC
 SRLA_DUMP_LE, SRLA_DUMP_RE, SRLA_DUMP_SI = 0, 1, 2
 SRLA_FLAG_SUPER, SRLA_FLAG_SAT, SRLA_FLAG_NEW, SRLA_FLAG_KEEP = 1, 2, 4, 8
 SRLA_CFG_TIMING = 1
+SRLA_CFG_SCAN_FLAT = 2
 
 
 class srla_geometry_t(ctypes.Structure):
@@ -139,13 +140,17 @@ class SrlaError(RuntimeError):
 
 
 class Report:
-    """Copy of one slice's report as numpy arrays."""
+    """One slice's report as numpy arrays: copies, or (copy=False) views of the
+    library's report buffers that stay valid until the next estimate."""
 
-    def __init__(self, r, u):
+    def __init__(self, r, u, copy=True):
         n = r.n
 
         def arr(p, dt):
-            return np.ctypeslib.as_array(p, (n,)).copy() if n else np.zeros(0, dt)
+            if not n:
+                return np.zeros(0, dt)
+            a = np.ctypeslib.as_array(p, (n,))
+            return a.copy() if copy else a
 
         self.slice = r.slice
         self.window_full = bool(r.window_full)
@@ -164,15 +169,17 @@ class Report:
 class Monitor:
     """One SRLA monitor on the current HIP device.
 
-    stream: a torch.cuda.Stream (or None for the library's own stream)."""
+    stream: the torch.cuda.Stream the monitor's work is issued on (a new
+    stream when None).  Device tensors handed to scan() are ordered after the
+    caller's current stream and kept alive for the monitor's stream."""
 
     def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22,
-                 timing=False, stream=None):
-        self.cfg = make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates,
-                               SRLA_CFG_TIMING if timing else 0)
-        self.stream = stream
-        hs = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
-        rc, h = srla_create(self.cfg, hs)
+                 timing=False, stream=None, scan_flat=False):
+        flags = (SRLA_CFG_TIMING if timing else 0) | (SRLA_CFG_SCAN_FLAT if scan_flat else 0)
+        self.cfg = make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates, flags)
+        self._h = None
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        rc, h = srla_create(self.cfg, ctypes.c_void_p(self.stream.cuda_stream))
         if rc != SRLA_OK:
             raise SrlaError(rc, "srla_create failed")
         self._h = h
@@ -201,15 +208,19 @@ class Monitor:
             else:
                 assert pairs.is_contiguous() and pairs.element_size() == 4
                 n = pairs.numel() // 2
+                cur = torch.cuda.current_stream()
+                if cur != self.stream:
+                    self.stream.wait_stream(cur)
+                    pairs.record_stream(self.stream)
                 self._check(srla_scan(self._h, ctypes.c_void_p(pairs.data_ptr()), n, True))
                 return
         p = np.ascontiguousarray(pairs, dtype=np.uint32).reshape(-1)
         self._check(srla_scan(self._h, ctypes.c_void_p(p.ctypes.data), p.size // 2, False))
 
-    def estimate(self):
+    def estimate(self, copy=True):
         r = srla_report_t()
         self._check(srla_estimate(self._h, r))
-        return Report(r, self.cfg.geom.u)
+        return Report(r, self.cfg.geom.u, copy)
 
     def cells(self, which):
         g = self.cfg.geom
