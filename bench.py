@@ -70,8 +70,11 @@ def main():
                     help="slices of the same workload the oracle baseline scans")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-candidates", type=int, default=1 << 25)
-    ap.add_argument("--scan-flat", action="store_true",
-                    help="scan without per-XCD row ownership (A/B of the scan kernels)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (a known-size "
+                         "reference for the HBM traffic counters)")
+    ap.add_argument("--scan-xcd", action="store_true",
+                    help="scan with per-XCD row ownership (A/B of the scan kernels)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -94,8 +97,15 @@ def main():
     st = torch.cuda.Stream()
     torch.cuda.set_stream(st)     # generation, scan and estimate share one stream
 
+    if args.calib_copy_mb:
+        src = torch.empty(args.calib_copy_mb << 20, dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
-                     scan_flat=args.scan_flat)
+                     scan_xcd=args.scan_xcd)
     buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
     t_w = time.perf_counter()
     for s in range(args.warmup):
@@ -167,7 +177,7 @@ def main():
                   "row_fill_frac": [float(x) / (g["v_le"] * g["G"]) for x in r.row_fill],
                   "n_touched": int(r.n_touched), "n_new": int(r.n_new)},
         "roofline": {
-            "kernel": "k_scan_flat (Algorithm 2)" if args.scan_flat else "k_scan_xcd (Algorithm 2)",
+            "kernel": "k_scan_xcd (Algorithm 2)" if args.scan_xcd else "k_scan_flat (Algorithm 2)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

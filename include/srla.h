@@ -48,10 +48,10 @@ enum {
 
 /* srla_config_t.flags */
 enum {
-    SRLA_CFG_TIMING = 1,    /* record HIP events around every stage */
-    SRLA_CFG_SCAN_FLAT = 2  /* scan without the per-XCD row ownership (for a
-                               GPU partitioned so that one device is one XCD);
-                               results are identical either way */
+    SRLA_CFG_TIMING = 1,   /* record HIP events around every stage */
+    SRLA_CFG_SCAN_XCD = 2  /* scan with per-XCD row ownership (each XCD stores
+                              into its own SEA rows); results are identical
+                              either way, only the speed differs */
 };
 
 /*
@@ -132,9 +132,10 @@ typedef struct {
 } srla_timings_t;
 
 /*
- * Device bytes a monitor of this configuration allocates (DR arrays, SI,
- * activity bitmap, candidate buffers; the slice's sampled-source list grows
- * with the pairs scanned and is not included).  0 for an invalid config.
+ * Device bytes a monitor of this configuration allocates (DR arrays, SI
+ * counters, activity bitmaps, candidate buffers; the slice's sampled-source
+ * list grows with the pairs scanned and is not included).  0 for an invalid
+ * config.
  */
 uint64_t srla_footprint_bytes(const srla_config_t *cfg);
 

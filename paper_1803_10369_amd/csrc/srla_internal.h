@@ -79,6 +79,22 @@ struct Counters {
   uint32_t pad[2];
 };
 
+// Pinned host block the status kernel fills at the end of every slice.
+struct HostStatus {
+  Counters cnt;
+  double up;
+  unsigned long long row_fill[kMaxU];
+};
+
+// Report arrays in pinned host memory, as device-visible pointers.
+struct ReportPtrs {
+  uint32_t* ip;
+  double* est;
+  uint8_t* flags;
+  uint32_t* U;
+  uint8_t* W;
+};
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return the launch status.
 
@@ -91,7 +107,9 @@ hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16
 hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
                            const Geo& geo, uint16_t now, hipStream_t st);
 
-hipError_t launch_scrub(uint16_t* cells, uint64_t n, uint16_t now, hipStream_t st);
+// SRE DR activity bitmaps (inside the window now / after the slide) + scrub
+hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act_now, uint64_t* act_next,
+                           const Geo& geo, uint16_t now, hipStream_t st);
 
 // keys-only LSD radix sort of n uint32 keys; returns the buffer holding the
 // sorted keys (keys or tmp).  block_hist needs radix_hist_words(n) words.
@@ -102,9 +120,9 @@ hipError_t radix_sort_u32(uint32_t* keys, uint32_t* tmp, uint64_t n, uint32_t* b
 // exclusive-scan helper storage for compaction of up to n elements
 uint64_t compact_block_words(uint64_t n);
 
-hipError_t launch_finalize(const uint32_t* sorted, uint64_t n_max, const uint16_t* re,
-                           const uint16_t* si, const Geo& geo, uint16_t now,
-                           uint8_t* mark, Counters* cnt, hipStream_t st);
+hipError_t launch_finalize(const uint32_t* sorted, uint64_t n_max, const uint64_t* act_now,
+                           const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
+                           hipStream_t st);
 
 // stable compaction of vals[i] with (flags[i] & mask) != 0, i < *n_dev (or
 // n_host if n_dev is null); n_max bounds the grid; result count -> *out_count
@@ -120,13 +138,15 @@ hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
                              double* up, hipStream_t st);
 
 hipError_t launch_estimate(const uint32_t* csip, uint64_t n_max, const Counters* cnt,
-                           const uint64_t* bitmap, const uint16_t* re, const double* up,
-                           const Geo& geo, uint16_t now, double* est, uint8_t* cflags,
-                           uint32_t* U, uint8_t* W, hipStream_t st);
+                           const uint64_t* bitmap, const uint64_t* act_now,
+                           const uint64_t* act_next, const double* up, const Geo& geo,
+                           uint8_t* cflags, const ReportPtrs& out, hipStream_t st);
 
-// Algorithm 3's SI step (after the KEEP flags and n_keep are final)
+// Algorithm 3's SI step on the per-bit counters (after the KEEP flags are final)
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
-                            uint64_t n_max, uint32_t* si_words, uint64_t n_words, const Geo& geo,
-                            hipStream_t st);
+                            uint64_t n_max, uint32_t* si_cnt, const Geo& geo, hipStream_t st);
+
+hipError_t launch_status(const Counters* cnt, const double* up, const unsigned long long* row_fill,
+                         uint32_t u, HostStatus* out, hipStream_t st);
 
 }  // namespace srla

@@ -307,63 +307,127 @@ hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* r
   return hipGetLastError();
 }
 
-// Zeroes stamps whose distance reached kScrubAge (any array of stamps).
-__global__ __launch_bounds__(kBlock) void k_scrub(uint16_t* __restrict__ cells, uint64_t n,
-                                                 uint32_t now) {
-  uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (; i < n; i += stride) {
-    const uint32_t c = cells[i];
-    if (c != 0 && stamp_age(now, c) >= kScrubAge) cells[i] = 0;
+
+// RE activity: every SRE DR of the array (flat index i over [u][v_re][g]) as
+// two bitmaps -- bit i of `now` = DR inside the window ending at this slice,
+// bit i of `next` = still inside after Algorithm 3's slide (distance + 1 < k).
+// The finalize and estimate kernels read g bits per (row, column) from these
+// (L2-resident) maps instead of g scattered stamps.  Old stamps are scrubbed
+// here as in the LE sweep.  Handles any cell count (ragged last word).
+
+__global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, uint64_t n,
+                                                    uint64_t* __restrict__ act_now,
+                                                    uint64_t* __restrict__ act_next,
+                                                    uint32_t now, uint32_t k) {
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint64_t c8 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 8;
+  uint32_t m_now = 0, m_next = 0;
+  if (c8 < n) {
+    uint32_t cell[8];
+    const bool full = c8 + 8 <= n;
+    if (full) {
+      const uint4 q = *reinterpret_cast<const uint4*>(re + c8);
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) { cell[2 * j] = w[j] & 0xFFFFu; cell[2 * j + 1] = w[j] >> 16; }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) cell[j] = c8 + j < n ? re[c8 + j] : 0u;
+    }
+    bool dirty = false;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (cell[j]) {
+        const uint32_t age = stamp_age(now, cell[j]);
+        if (age < k) m_now |= 1u << j;
+        if (age + 1u < k) m_next |= 1u << j;
+        if (age >= kScrubAge) { cell[j] = 0; dirty = true; }
+      }
+    }
+    if (dirty) {
+      if (full) {
+        *reinterpret_cast<uint4*>(re + c8) =
+            make_uint4(cell[0] | (cell[1] << 16), cell[2] | (cell[3] << 16),
+                       cell[4] | (cell[5] << 16), cell[6] | (cell[7] << 16));
+      } else {
+        for (int j = 0; j < 8; ++j)
+          if (c8 + j < n) re[c8 + j] = (uint16_t)cell[j];
+      }
+    }
+  }
+  const uint32_t sh = 8 * (lane & 3);
+  uint32_t a_lo = (lane & 4) ? 0u : m_now << sh, a_hi = (lane & 4) ? m_now << sh : 0u;
+  uint32_t b_lo = (lane & 4) ? 0u : m_next << sh, b_hi = (lane & 4) ? m_next << sh : 0u;
+#pragma unroll
+  for (int off = 1; off < 8; off <<= 1) {
+    a_lo |= __shfl_xor(a_lo, off); a_hi |= __shfl_xor(a_hi, off);
+    b_lo |= __shfl_xor(b_lo, off); b_hi |= __shfl_xor(b_hi, off);
+  }
+  if (c8 < n && (lane & 7) == 0) {
+    act_now[c8 / 64] = ((uint64_t)a_hi << 32) | a_lo;
+    act_next[c8 / 64] = ((uint64_t)b_hi << 32) | b_lo;
   }
 }
 
-hipError_t launch_scrub(uint16_t* cells, uint64_t n, uint16_t now, hipStream_t st) {
+hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act_now, uint64_t* act_next,
+                           const Geo& geo, uint16_t now, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  uint64_t blocks = (n + kBlock - 1) / kBlock;
-  if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(k_scrub, dim3((uint32_t)blocks), dim3(kBlock), 0, st, cells, n,
-                     (uint32_t)now);
+  const uint64_t blocks = (n + 8 * kBlock - 1) / (8 * kBlock);
+  hipLaunchKernelGGL(k_sweep_re, dim3((uint32_t)blocks), dim3(kBlock), 0, st, re, n, act_now,
+                     act_next, (uint32_t)now, geo.k);
   return hipGetLastError();
+}
+
+// g activity bits of the SRE in row r, column col (g <= 64)
+__device__ __forceinline__ uint64_t sre_bits(const uint64_t* __restrict__ act, const Geo& geo,
+                                             uint32_t r, uint32_t col) {
+  const uint64_t off = ((uint64_t)r * geo.v_re + col) * geo.g;
+  const uint64_t w = off >> 6;
+  const uint32_t sh = (uint32_t)(off & 63u);
+  uint64_t bits = act[w] >> sh;
+  if (sh + geo.g > 64u) bits |= act[w + 1] << (64u - sh);
+  return geo.g == 64u ? bits : (bits & ((1ull << geo.g) - 1ull));
+}
+
+// SI as per-bit counters: counter (r, col, b) = number of carried candidates
+// whose row-r column is col and whose own SI bit H4(aip) is b, so SI bit
+// (r, col, b) of the paper is "counter > 0" (Section 4.1: the bit is set for
+// every carried candidate, Algorithm 3).
+__device__ __forceinline__ uint64_t si_slot(const Geo& geo, uint32_t r, uint32_t col,
+                                            uint32_t bit) {
+  return ((uint64_t)r * geo.v_re + col) * 16u + bit;
 }
 
 // ------------------------------------------------------------------ finalize
 // Algorithm 2's candidate check under the slice-synchronous reading: every
 // distinct source sampled in the slice (sorted[] is sorted, so the first of
 // each run stands for the source) is a new candidate iff its union SRE has
-// at least ceil(rho*g) DRs inside the window (Algorithm 1, DRjoin = max over
-// rows, so "all rows inside") and its own bit of the union SI (AND over rows)
-// is still clear.  SI is exactly as the previous slide left it.
+// at least ceil(rho*g) DRs inside the window (Algorithm 1 with DRjoin = max:
+// a union DR is inside iff it is inside in every row) and its own bit of the
+// union SI (AND over rows) is still clear.  SI is as the previous slide left it.
 
 __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict__ sorted,
-                                                    const uint16_t* __restrict__ re,
-                                                    const uint16_t* __restrict__ si, Geo geo,
-                                                    uint32_t now, uint8_t* __restrict__ mark,
+                                                    const uint64_t* __restrict__ act_now,
+                                                    const uint32_t* __restrict__ si_cnt,
+                                                    Geo geo, uint8_t* __restrict__ mark,
                                                     Counters* __restrict__ cnt) {
   const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   const uint32_t n = cnt->touched;
   bool first = false;
-  uint8_t f = 0;
   if (i < n) {
     const uint32_t a = sorted[i];
     first = (i == 0) || (sorted[i - 1] != a);
+    uint8_t f = 0;
     if (first) {
-      uint32_t w = 0;
-      for (uint32_t c = 0; c < geo.g; ++c) {
-        bool all = true;
-        for (uint32_t r = 0; r < geo.u; ++r) {
-          const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
-          all = all && in_window(now, re[((uint64_t)r * geo.v_re + col) * geo.g + c], geo.k);
-        }
-        w += all ? 1u : 0u;
-      }
-      uint32_t usi = 0xFFFFu;
+      const uint32_t bit = hrange(mas(geo.h4, a), 16u);
+      uint64_t ure = ~0ull;
+      bool usi = true;
       for (uint32_t r = 0; r < geo.u; ++r) {
         const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
-        usi &= si[(uint64_t)r * geo.v_re + col];
+        ure &= sre_bits(act_now, geo, r, col);
+        usi = usi && si_cnt[si_slot(geo, r, col, bit)] != 0u;
       }
-      const uint32_t bit = hrange(mas(geo.h4, a), 16u);
-      f = (w >= geo.t_re && ((usi >> bit) & 1u) == 0u) ? 1 : 0;
+      f = ((uint32_t)__popcll(ure) >= geo.t_re && !usi) ? 1 : 0;
     }
     mark[i] = f;
   }
@@ -371,13 +435,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict_
   if (__lane_id() == 0 && firsts) atomicAdd(&cnt->n_unique, (uint32_t)__popcll(firsts));
 }
 
-hipError_t launch_finalize(const uint32_t* sorted, uint64_t n_max, const uint16_t* re,
-                           const uint16_t* si, const Geo& geo, uint16_t now, uint8_t* mark,
-                           Counters* cnt, hipStream_t st) {
+hipError_t launch_finalize(const uint32_t* sorted, uint64_t n_max, const uint64_t* act_now,
+                           const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
+                           hipStream_t st) {
   if (n_max == 0) return hipSuccess;
   const uint64_t blocks = (n_max + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_finalize, dim3((uint32_t)blocks), dim3(kBlock), 0, st, sorted, re, si,
-                     geo, (uint32_t)now, mark, cnt);
+  hipLaunchKernelGGL(k_finalize, dim3((uint32_t)blocks), dim3(kBlock), 0, st, sorted, act_now,
+                     si_cnt, geo, mark, cnt);
   return hipGetLastError();
 }
 
@@ -451,155 +515,183 @@ hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ estimate
-// For every candidate: |ULE|^k from the activity bitmap (AND over the u
-// rows, popcount), |URE|^k now and after the slide from the stamps, Eq9 in
-// FP64, and the flags.  A group of 2^lg_log2 lanes owns one candidate; its
-// lanes split the G/64 bitmap words (16 lanes read one 128-byte line per row
-// when G = 1024) and the g SRE DRs, then reduce with cross-lane shuffles.
 
-__global__ __launch_bounds__(kBlock) void k_estimate(const uint32_t* __restrict__ csip,
-                                                    const Counters* __restrict__ cnt,
-                                                    const uint64_t* __restrict__ bitmap,
-                                                    const uint16_t* __restrict__ re,
-                                                    const double* __restrict__ up_p, Geo geo,
-                                                    uint32_t now, uint32_t lg_log2,
-                                                    double* __restrict__ est,
-                                                    uint8_t* __restrict__ cflags,
-                                                    uint32_t* __restrict__ U_out,
-                                                    uint8_t* __restrict__ W_out) {
+// ------------------------------------------------------------------ estimate
+// For every candidate: |ULE|^k from the LE activity bitmap (AND over the u
+// rows, popcount), |URE|^k now and after the slide from the RE activity
+// bitmaps, Eq9 in FP64, and the flags.  A group of 2^lg_log2 lanes owns one
+// candidate; its lanes split the G/64 bitmap words (16 lanes read one
+// 128-byte line per row when G = 1024) and the u rows of the SRE, then
+// reduce with cross-lane shuffles.  A block finishes 64 candidates, stages
+// them in LDS, and writes the report entries with one coalesced store per
+// array straight into the pinned host buffers (mapped into the GPU's address
+// space), so no separate device-to-host copy is needed.
+
+constexpr uint32_t kEstPerBlock = 64;
+
+__global__ __launch_bounds__(kBlock) void k_estimate(
+    const uint32_t* __restrict__ csip, const Counters* __restrict__ cnt,
+    const uint64_t* __restrict__ bitmap, const uint64_t* __restrict__ act_now,
+    const uint64_t* __restrict__ act_next, const double* __restrict__ up_p, Geo geo,
+    uint32_t lg_log2, uint8_t* __restrict__ cflags, uint32_t* __restrict__ out_ip,
+    double* __restrict__ out_est, uint8_t* __restrict__ out_flags, uint32_t* __restrict__ out_U,
+    uint8_t* __restrict__ out_W) {
+  __shared__ double s_est[kEstPerBlock];
+  __shared__ uint32_t s_ip[kEstPerBlock], s_U[kEstPerBlock];
+  __shared__ uint8_t s_W[kEstPerBlock], s_f[kEstPerBlock];
   const uint32_t lg = 1u << lg_log2;
-  const uint64_t gid = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) >> lg_log2;
+  const uint32_t per_round = kBlock >> lg_log2;          // candidates per round
   const uint32_t sub = threadIdx.x & (lg - 1u);
   const uint32_t n = cnt->n_cand;
-  const bool valid = gid < n;
-  const uint32_t a = valid ? csip[gid] : 0u;
-  uint32_t ucount = 0, w_now = 0, w_next = 0;
-  if (valid) {
-    for (uint32_t x = sub; x < geo.words; x += lg) {
-      uint64_t acc = ~0ull;
-      for (uint32_t r = 0; r < geo.u; ++r) {
-        const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_le);
-        acc &= bitmap[((uint64_t)r * geo.v_le + col) * geo.words + x];
+  const uint64_t base = (uint64_t)blockIdx.x * kEstPerBlock;
+  const uint64_t gmask = geo.g == 64u ? ~0ull : ((1ull << geo.g) - 1ull);
+  const double up = *up_p;
+  const double G = (double)geo.G;
+  for (uint32_t round = 0; round * per_round < kEstPerBlock; ++round) {
+    const uint32_t local = round * per_round + (threadIdx.x >> lg_log2);
+    const uint64_t gid = base + local;
+    const bool valid = local < kEstPerBlock && gid < n;
+    const uint32_t a = valid ? csip[gid] : 0u;
+    uint32_t ucount = 0;
+    uint64_t m_now = ~0ull, m_next = ~0ull;
+    if (valid) {
+      for (uint32_t x = sub; x < geo.words; x += lg) {
+        uint64_t acc = ~0ull;
+        for (uint32_t r = 0; r < geo.u; ++r) {
+          const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_le);
+          acc &= bitmap[((uint64_t)r * geo.v_le + col) * geo.words + x];
+        }
+        ucount += (uint32_t)__popcll(acc);
       }
-      ucount += (uint32_t)__popcll(acc);
-    }
-    for (uint32_t c = sub; c < geo.g; c += lg) {
-      bool all_now = true, all_next = true;
-      for (uint32_t r = 0; r < geo.u; ++r) {
+      for (uint32_t r = sub; r < geo.u; r += lg) {
         const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
-        const uint32_t cell = re[((uint64_t)r * geo.v_re + col) * geo.g + c];
-        // a never-set DR is older than any window, also after the slide
-        const uint32_t age = cell ? stamp_age(now, cell) : kStampPeriod;
-        all_now = all_now && age < geo.k;
-        all_next = all_next && age + 1u < geo.k;   // after the slide of Algorithm 3
+        m_now &= sre_bits(act_now, geo, r, col);
+        m_next &= sre_bits(act_next, geo, r, col);
       }
-      w_now += all_now ? 1u : 0u;
-      w_next += all_next ? 1u : 0u;
     }
-  }
-  for (uint32_t off = lg >> 1; off > 0; off >>= 1) {
-    ucount += __shfl_xor(ucount, (int)off);
-    w_now += __shfl_xor(w_now, (int)off);
-    w_next += __shfl_xor(w_next, (int)off);
-  }
-  if (valid && sub == 0) {
-    // Eq9, operation by operation, no contraction (built with -ffp-contract=off)
-    const double G = (double)geo.G;
-    const double up = *up_p;
-    const double num = (double)ucount - G * up;
-    const double den = G * (1.0 - up);
-    double e;
-    uint8_t fl = cflags[gid] & 4u;   // NEW, written by the merge
-    if (den == 0.0) {
-      e = __builtin_inf();
-      fl |= 2u;
-    } else {
-      const double y = 1.0 - num / den;
-      if (y <= 0.0) {
+    uint32_t now_lo = (uint32_t)m_now, now_hi = (uint32_t)(m_now >> 32);
+    uint32_t nx_lo = (uint32_t)m_next, nx_hi = (uint32_t)(m_next >> 32);
+    for (uint32_t off = lg >> 1; off > 0; off >>= 1) {
+      ucount += __shfl_xor(ucount, (int)off);
+      now_lo &= __shfl_xor(now_lo, (int)off);
+      now_hi &= __shfl_xor(now_hi, (int)off);
+      nx_lo &= __shfl_xor(nx_lo, (int)off);
+      nx_hi &= __shfl_xor(nx_hi, (int)off);
+    }
+    if (valid && sub == 0) {
+      const uint32_t w_now = (uint32_t)__popcll((((uint64_t)now_hi << 32) | now_lo) & gmask);
+      const uint32_t w_next = (uint32_t)__popcll((((uint64_t)nx_hi << 32) | nx_lo) & gmask);
+      // Eq9, operation by operation, no contraction (built with -ffp-contract=off)
+      const double num = (double)ucount - G * up;
+      const double den = G * (1.0 - up);
+      double e;
+      uint8_t fl = cflags[gid] & 4u;   // NEW, written by the merge
+      if (den == 0.0) {
         e = __builtin_inf();
         fl |= 2u;
       } else {
-        e = -G * log(y);
+        const double y = 1.0 - num / den;
+        if (y <= 0.0) {
+          e = __builtin_inf();
+          fl |= 2u;
+        } else {
+          e = -G * log(y);
+        }
       }
+      if (e >= (double)geo.theta) fl |= 1u;
+      if (w_next >= geo.t_re) fl |= 8u;   // carried by Algorithm 3
+      s_est[local] = e;
+      s_ip[local] = a;
+      s_U[local] = ucount;
+      s_W[local] = (uint8_t)w_now;
+      s_f[local] = fl;
     }
-    if (e >= (double)geo.theta) fl |= 1u;
-    if (w_next >= geo.t_re) fl |= 8u;   // carried by Algorithm 3
-    est[gid] = e;
-    cflags[gid] = fl;
-    U_out[gid] = ucount;
-    W_out[gid] = (uint8_t)w_now;
+  }
+  __syncthreads();
+  if (threadIdx.x < kEstPerBlock) {
+    const uint64_t gid = base + threadIdx.x;
+    if (gid < n) {
+      cflags[gid] = s_f[threadIdx.x];
+      out_ip[gid] = s_ip[threadIdx.x];
+      out_est[gid] = s_est[threadIdx.x];
+      out_flags[gid] = s_f[threadIdx.x];
+      out_U[gid] = s_U[threadIdx.x];
+      out_W[gid] = s_W[threadIdx.x];
+    }
   }
 }
 
 static uint32_t est_lg_log2(const Geo& geo) {
+  uint32_t need = geo.words > geo.u ? geo.words : geo.u;
   uint32_t l = 2;  // at least 4 lanes per candidate
-  while ((1u << l) < geo.words && l < 6) ++l;
+  while ((1u << l) < need && l < 6) ++l;
   return l;
 }
 
 hipError_t launch_estimate(const uint32_t* csip, uint64_t n_max, const Counters* cnt,
-                           const uint64_t* bitmap, const uint16_t* re, const double* up,
-                           const Geo& geo, uint16_t now, double* est, uint8_t* cflags,
-                           uint32_t* U, uint8_t* W, hipStream_t st) {
+                           const uint64_t* bitmap, const uint64_t* act_now,
+                           const uint64_t* act_next, const double* up, const Geo& geo,
+                           uint8_t* cflags, const ReportPtrs& out, hipStream_t st) {
   if (n_max == 0) return hipSuccess;
-  const uint32_t lgl = est_lg_log2(geo);
-  const uint64_t threads = n_max << lgl;
-  const uint64_t blocks = (threads + kBlock - 1) / kBlock;
+  const uint64_t blocks = (n_max + kEstPerBlock - 1) / kEstPerBlock;
   hipLaunchKernelGGL(k_estimate, dim3((uint32_t)blocks), dim3(kBlock), 0, st, csip, cnt, bitmap,
-                     re, up, geo, (uint32_t)now, lgl, est, cflags, U, W);
+                     act_now, act_next, up, geo, est_lg_log2(geo), cflags, out.ip, out.est,
+                     out.flags, out.U, out.W);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ SI
-// Algorithm 3: SI <- 0, then bit H4(aip) of SI[i][RH_i(aip)] for every
-// carried candidate and every row.  SI before this step holds exactly the
-// bits of NCSIP_{t-1} (finalize only reads it), so when no candidate of CSIP_t
-// is dropped -- NCSIP_t = NCSIP_{t-1} u N_t -- the new SI is the old one with
-// the bits of N_t added.  Only when a candidate is dropped is SI cleared and
-// rebuilt from all of NCSIP_t.  The choice is made on the device from the
-// slice's counters.  SI is uint16 [u][v_re], addressed as 32-bit words so
-// that the OR is a native atomic.
+// Algorithm 3's SI step as counter updates: a new candidate that is carried
+// adds 1 to its u counters, a carried candidate of the previous slice that is
+// dropped subtracts 1.  Afterwards every counter equals its count over
+// NCSIP_t, so "counter > 0" is exactly the SI bit that clearing SI and
+// marking every carried candidate would produce, at a cost proportional to
+// the candidates that entered or left.
 
-__global__ __launch_bounds__(kBlock) void k_si_clear_if_dropped(uint32_t* __restrict__ si_words,
-                                                               uint64_t n_words,
-                                                               const Counters* __restrict__ cnt) {
-  if (cnt->n_keep == cnt->n_cand) return;
-  uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (; i < n_words; i += stride) si_words[i] = 0u;
-}
-
-__global__ __launch_bounds__(kBlock) void k_si_mark(const uint32_t* __restrict__ csip,
-                                                   const uint8_t* __restrict__ cflags,
-                                                   const Counters* __restrict__ cnt,
-                                                   uint32_t* __restrict__ si_words, Geo geo) {
+__global__ __launch_bounds__(kBlock) void k_si_update(const uint32_t* __restrict__ csip,
+                                                     const uint8_t* __restrict__ cflags,
+                                                     const Counters* __restrict__ cnt,
+                                                     uint32_t* __restrict__ si_cnt, Geo geo) {
   const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= cnt->n_cand) return;
   const uint32_t f = cflags[t];
-  const bool rebuild = cnt->n_keep != cnt->n_cand;
-  if (!(f & 8u) || !(rebuild || (f & 4u))) return;   // KEEP, and NEW unless rebuilding
+  const bool is_new = f & 4u, keep = f & 8u;
+  uint32_t delta;
+  if (is_new && keep) delta = 1u;                 // enters NCSIP_t
+  else if (!is_new && !keep) delta = 0xFFFFFFFFu;  // leaves: -1
+  else return;                                     // stays, or never counted
   const uint32_t a = csip[t];
   const uint32_t bit = hrange(mas(geo.h4, a), 16u);
-  for (uint32_t r = 0; r < geo.u; ++r) {
-    const uint64_t idx = (uint64_t)r * geo.v_re + hrange(mas(geo.rh[r], a), geo.v_re);
-    atomicOr(&si_words[idx >> 1], 1u << (bit + 16u * (uint32_t)(idx & 1u)));
-  }
+  for (uint32_t r = 0; r < geo.u; ++r)
+    atomicAdd(&si_cnt[si_slot(geo, r, hrange(mas(geo.rh[r], a), geo.v_re), bit)], delta);
 }
 
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
-                            uint64_t n_max, uint32_t* si_words, uint64_t n_words, const Geo& geo,
-                            hipStream_t st) {
-  uint64_t cb = (n_words + kBlock - 1) / kBlock;
-  if (cb > 4096) cb = 4096;
-  if (cb == 0) cb = 1;
-  hipLaunchKernelGGL(k_si_clear_if_dropped, dim3((uint32_t)cb), dim3(kBlock), 0, st, si_words,
-                     n_words, cnt);
-  if (n_max) {
-    const uint64_t blocks = (n_max + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_si_mark, dim3((uint32_t)blocks), dim3(kBlock), 0, st, csip, cflags, cnt,
-                       si_words, geo);
-  }
+                            uint64_t n_max, uint32_t* si_cnt, const Geo& geo, hipStream_t st) {
+  if (n_max == 0) return hipSuccess;
+  const uint64_t blocks = (n_max + kBlock - 1) / kBlock;
+  hipLaunchKernelGGL(k_si_update, dim3((uint32_t)blocks), dim3(kBlock), 0, st, csip, cflags, cnt,
+                     si_cnt, geo);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ status
+// The slice's counters, Eq8 and the row fills, written into the pinned host
+// status block so the host reads everything after one stream wait.
+
+__global__ void k_status(const Counters* __restrict__ cnt, const double* __restrict__ up,
+                         const unsigned long long* __restrict__ row_fill, uint32_t u,
+                         HostStatus* __restrict__ out) {
+  if (blockIdx.x != 0) return;
+  const uint32_t t = threadIdx.x;
+  if (t < sizeof(Counters) / 4) ((uint32_t*)&out->cnt)[t] = ((const uint32_t*)cnt)[t];
+  if (t < u) out->row_fill[t] = row_fill[t];
+  if (t == 0) out->up = *up;
+}
+
+hipError_t launch_status(const Counters* cnt, const double* up, const unsigned long long* row_fill,
+                         uint32_t u, HostStatus* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, cnt, up, row_fill, u, out);
   return hipGetLastError();
 }
 

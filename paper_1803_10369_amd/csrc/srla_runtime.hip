@@ -3,14 +3,14 @@
 // One monitor = one SEA (Section 4.1) resident in device memory plus the
 // buffers of the end-of-slice pipeline.  srla_scan enqueues Algorithm 2 for
 // a batch of pairs; srla_estimate runs, on the same stream,
-//   sweep    -> |LDR(i)|^k and the LE activity bitmap (Section 4.2)
+//   sweep    -> |LDR(i)|^k, the LE activity bitmap, the SRE activity bitmaps
 //   finalize -> sort + unique of the slice's sampled sources, candidate check
 //   merge    -> CSIP_t = NCSIP_{t-1} u N_t, ascending
-//   estimate -> Eq8, then per candidate |ULE|^k, |URE|^k, Eq9, Algorithm 3 test
-//   slide    -> SI cleared, NCSIP_t compacted, its SI bits set; t <- t + 1
-//   report   -> device-to-host copy into pinned buffers
+//   estimate -> Eq8, then per candidate |ULE|^k, |URE|^k, Eq9, Algorithm 3's
+//               test; the report goes straight into pinned host memory
+//   slide    -> NCSIP_t compacted, SI counters updated; t <- t + 1
 // with one host wait early on (the sampled-source count sizes the sort) and
-// two at the end (the candidate count sizes the report copy).
+// one at the end.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -62,7 +62,7 @@ bool config_ok(const srla_config_t* c) {
   if (c->window_slices < 1 || c->window_slices > 32767) return false;
   if (c->threshold < 1) return false;
   if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
-  if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_FLAT)) != 0) return false;
+  if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD)) != 0) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   if (le / g.u / g.g_le != g.v_le || re / g.u / g.g != g.v_re) return false;
@@ -78,7 +78,6 @@ struct TimedSpan {
 };
 
 constexpr uint64_t kStageChunk = 1ull << 22;  // pairs per host-ingest chunk
-constexpr uint64_t kRescrubPeriod = 4096;     // slices between RE/SI scrubs
 
 }  // namespace
 
@@ -91,12 +90,14 @@ struct srla_monitor {
   bool poisoned = false;
   std::string err;
 
-  // SEA
+  // SEA and its per-slice views
   uint16_t* le = nullptr;
   uint16_t* re = nullptr;
-  uint16_t* si = nullptr;
-  uint64_t n_le = 0, n_re = 0, n_si = 0, si_words = 0;
-  uint64_t* bitmap = nullptr;
+  uint32_t* si_cnt = nullptr;    // [u][v_re][16] counters; SI bit = counter > 0
+  uint64_t n_le = 0, n_re = 0, n_si = 0;
+  uint64_t* bitmap = nullptr;    // LE DRs inside the window
+  uint64_t* act_now = nullptr;   // SRE DRs inside the window
+  uint64_t* act_next = nullptr;  // SRE DRs inside after the slide
   unsigned long long* row_fill = nullptr;
   double* up = nullptr;
   Counters* cnt = nullptr;
@@ -116,23 +117,22 @@ struct srla_monitor {
   uint32_t* ncsip = nullptr;
   uint32_t* ncsip_next = nullptr;
   uint8_t* cflags = nullptr;
-  double* est = nullptr;
-  uint32_t* U = nullptr;
-  uint8_t* W = nullptr;
   uint32_t* cblockw = nullptr;
   uint64_t cap = 0;
   uint32_t n_ncsip = 0;
 
-  // pinned host side
+  // pinned host side (the report arrays and the status block are written by
+  // kernels through their device-visible addresses)
   Counters* h_cnt = nullptr;
-  unsigned long long* h_row_fill = nullptr;
-  double* h_up = nullptr;
+  HostStatus* h_status = nullptr;
+  HostStatus* d_status = nullptr;
   uint64_t* h_row_fill64 = nullptr;
   uint32_t* h_ip = nullptr;
   double* h_est = nullptr;
   uint8_t* h_flags = nullptr;
   uint32_t* h_U = nullptr;
   uint8_t* h_W = nullptr;
+  ReportPtrs d_report{};
   hipEvent_t ev_count = nullptr;
 
   // host-input ring: two pinned chunks, two device chunks
@@ -144,7 +144,7 @@ struct srla_monitor {
 
   // timing
   bool timing = false;
-  bool xcd_scan = true;
+  bool xcd_scan = false;
   std::vector<TimedSpan> spans;
   std::vector<hipEvent_t> ev_pool;
   double acc_ms[ST_N] = {0, 0, 0, 0, 0, 0};
@@ -184,6 +184,11 @@ hipError_t halloc(T** p, uint64_t count) {
   return hipHostMalloc((void**)p, count * sizeof(T), hipHostMallocDefault);
 }
 
+template <class T>
+hipError_t dev_view(T* host, T** dev) {
+  return hipHostGetDevicePointer((void**)dev, (void*)host, 0);
+}
+
 void dfree(void* p) {
   if (p) (void)hipFree(p);
 }
@@ -192,9 +197,11 @@ void hfree(void* p) {
 }
 
 uint64_t candidate_bytes(uint64_t cap) {
-  // csip, ncsip, ncsip_next (u32), cflags, W (u8), est (f64), U (u32), block words
-  return cap * (4 + 4 + 4 + 1 + 1 + 8 + 4) + 4 * compact_block_words(cap);
+  // csip, ncsip, ncsip_next (u32), cflags (u8), block words
+  return cap * (4 + 4 + 4 + 1) + 4 * compact_block_words(cap);
 }
+
+uint64_t bitmap_words(uint64_t cells) { return (cells + 63) / 64 + 1; }
 
 hipEvent_t pooled_event(srla_monitor* m) {
   if (!m->ev_pool.empty()) {
@@ -207,8 +214,7 @@ hipEvent_t pooled_event(srla_monitor* m) {
   return e;
 }
 
-void span_begin(srla_monitor* m, int stage, hipEvent_t* a) {
-  (void)stage;
+void span_begin(srla_monitor* m, hipEvent_t* a) {
   *a = nullptr;
   if (!m->timing) return;
   *a = pooled_event(m);
@@ -237,9 +243,9 @@ void collect_spans(srla_monitor* m) {
 // Grows the per-slice sampled-source buffers to hold `need` entries.
 int reserve_touched(srla_monitor* m, uint64_t need) {
   if (need <= m->touched_cap) return SRLA_OK;
-  uint64_t cap = std::max<uint64_t>(need, m->touched_cap ? 2 * m->touched_cap : (1u << 20));
-  if (cap > 0xFFFFFFF0ull) cap = std::max<uint64_t>(need, 0xFFFFFFF0ull);
   if (need > 0xFFFFFFF0ull) return fail(m, SRLA_E_NOMEM, "slice holds more than 2^32 pairs");
+  uint64_t cap = std::max<uint64_t>(need, m->touched_cap ? 2 * m->touched_cap : (1u << 20));
+  cap = std::min<uint64_t>(cap, 0xFFFFFFF0ull);
   uint32_t *t = nullptr, *tt = nullptr, *nw = nullptr, *h = nullptr, *bw = nullptr;
   uint8_t* mk = nullptr;
   if (dalloc(&t, cap) != hipSuccess || dalloc(&tt, cap) != hipSuccess ||
@@ -267,14 +273,13 @@ void release(srla_monitor* m) {
   if (!m) return;
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   collect_spans(m);
-  dfree(m->le); dfree(m->re); dfree(m->si); dfree(m->bitmap); dfree(m->row_fill);
-  dfree(m->up); dfree(m->cnt);
+  dfree(m->le); dfree(m->re); dfree(m->si_cnt); dfree(m->bitmap); dfree(m->act_now);
+  dfree(m->act_next); dfree(m->row_fill); dfree(m->up); dfree(m->cnt);
   dfree(m->touched); dfree(m->touched_tmp); dfree(m->mark); dfree(m->news);
   dfree(m->hist); dfree(m->blockw);
-  dfree(m->csip); dfree(m->ncsip); dfree(m->ncsip_next); dfree(m->cflags); dfree(m->est);
-  dfree(m->U); dfree(m->W); dfree(m->cblockw);
-  hfree(m->h_cnt); hfree(m->h_row_fill); hfree(m->h_up); hfree(m->h_ip); hfree(m->h_est);
-  hfree(m->h_flags); hfree(m->h_U); hfree(m->h_W);
+  dfree(m->csip); dfree(m->ncsip); dfree(m->ncsip_next); dfree(m->cflags); dfree(m->cblockw);
+  hfree(m->h_cnt); hfree(m->h_status); hfree(m->h_ip); hfree(m->h_est); hfree(m->h_flags);
+  hfree(m->h_U); hfree(m->h_W);
   delete[] m->h_row_fill64;
   for (int i = 0; i < 2; ++i) {
     hfree(m->h_stage[i]);
@@ -297,8 +302,8 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   const uint64_t si = (uint64_t)g.u * g.v_re;
-  return 2 * le + le / 8 + 2 * re + 2 * ((si + 1) & ~1ull) + 8 * g.u + 8 + sizeof(Counters) +
-         candidate_bytes(cfg->max_candidates);
+  return 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
+         8 * g.u + 8 + sizeof(Counters) + candidate_bytes(cfg->max_candidates);
 }
 
 int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out) {
@@ -308,7 +313,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!m) return SRLA_E_NOMEM;
   m->cfg = *cfg;
   m->timing = (cfg->flags & SRLA_CFG_TIMING) != 0;
-  m->xcd_scan = (cfg->flags & SRLA_CFG_SCAN_FLAT) == 0;
+  m->xcd_scan = (cfg->flags & SRLA_CFG_SCAN_XCD) != 0;
 
   const srla_geometry_t& g = cfg->geom;
   Geo& geo = m->geo;
@@ -350,12 +355,13 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->n_le = (uint64_t)g.u * g.v_le * g.g_le;
   m->n_re = (uint64_t)g.u * g.v_re * g.g;
   m->n_si = (uint64_t)g.u * g.v_re;
-  m->si_words = (m->n_si + 1) / 2;
   m->cap = cfg->max_candidates;
   nomem(dalloc(&m->le, m->n_le));
-  if (!rc) nomem(dalloc(&m->re, m->n_re));
-  if (!rc) nomem(dalloc(&m->si, 2 * m->si_words));
-  if (!rc) nomem(dalloc(&m->bitmap, m->n_le / 64));
+  if (!rc) nomem(dalloc(&m->re, m->n_re + 8));
+  if (!rc) nomem(dalloc(&m->si_cnt, 16 * m->n_si));
+  if (!rc) nomem(dalloc(&m->bitmap, bitmap_words(m->n_le)));
+  if (!rc) nomem(dalloc(&m->act_now, bitmap_words(m->n_re)));
+  if (!rc) nomem(dalloc(&m->act_next, bitmap_words(m->n_re)));
   if (!rc) nomem(dalloc(&m->row_fill, g.u));
   if (!rc) nomem(dalloc(&m->up, 1));
   if (!rc) nomem(dalloc(&m->cnt, 1));
@@ -363,13 +369,9 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!rc) nomem(dalloc(&m->ncsip, m->cap));
   if (!rc) nomem(dalloc(&m->ncsip_next, m->cap));
   if (!rc) nomem(dalloc(&m->cflags, m->cap));
-  if (!rc) nomem(dalloc(&m->est, m->cap));
-  if (!rc) nomem(dalloc(&m->U, m->cap));
-  if (!rc) nomem(dalloc(&m->W, m->cap));
   if (!rc) nomem(dalloc(&m->cblockw, compact_block_words(m->cap)));
   if (!rc) nomem(halloc(&m->h_cnt, 1));
-  if (!rc) nomem(halloc(&m->h_row_fill, g.u));
-  if (!rc) nomem(halloc(&m->h_up, 1));
+  if (!rc) nomem(halloc(&m->h_status, 1));
   if (!rc) nomem(halloc(&m->h_ip, m->cap));
   if (!rc) nomem(halloc(&m->h_est, m->cap));
   if (!rc) nomem(halloc(&m->h_flags, m->cap));
@@ -379,6 +381,13 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     m->h_row_fill64 = new (std::nothrow) uint64_t[g.u];
     if (!m->h_row_fill64) rc = SRLA_E_NOMEM;
   }
+  if (!rc && (dev_view(m->h_status, &m->d_status) != hipSuccess ||
+              dev_view(m->h_ip, &m->d_report.ip) != hipSuccess ||
+              dev_view(m->h_est, &m->d_report.est) != hipSuccess ||
+              dev_view(m->h_flags, &m->d_report.flags) != hipSuccess ||
+              dev_view(m->h_U, &m->d_report.U) != hipSuccess ||
+              dev_view(m->h_W, &m->d_report.W) != hipSuccess))
+    rc = SRLA_E_DEVICE;
   if (!rc && hipEventCreateWithFlags(&m->ev_count, hipEventDisableTiming) != hipSuccess)
     rc = SRLA_E_DEVICE;
   if (rc) {
@@ -388,9 +397,8 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   // DRinit for every DR (stamp 0 = never set), SI = 0, counters = 0
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->le, 0u, m->n_le / 2, m->stream);
-  if (e == hipSuccess && (m->n_le & 1)) e = hipMemsetAsync(m->le + m->n_le - 1, 0, 2, m->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(m->re, 0, m->n_re * 2, m->stream);
-  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->si, 0u, m->si_words, m->stream);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->re, 0u, (m->n_re + 8) / 2, m->stream);
+  if (e == hipSuccess) e = launch_fill_u32(m->si_cnt, 0u, 16 * m->n_si, m->stream);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->cnt, 0u, sizeof(Counters) / 4, m->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) {
@@ -415,7 +423,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   const uint16_t code = stamp_code(m->slice);
   if (on_device) {
     hipEvent_t a;
-    span_begin(m, ST_SCAN, &a);
+    span_begin(m, &a);
     HIP_TRY(m, launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched, m->cnt, m->xcd_scan,
                            m->stream));
     span_end(m, ST_SCAN, a);
@@ -446,7 +454,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     HIP_TRY(m, hipEventRecord(m->stage_ev[b], m->stream));
     m->stage_busy[b] = true;
     hipEvent_t a;
-    span_begin(m, ST_SCAN, &a);
+    span_begin(m, &a);
     HIP_TRY(m, launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched, m->cnt,
                            m->xcd_scan, m->stream));
     span_end(m, ST_SCAN, a);
@@ -465,14 +473,14 @@ int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
   hipStream_t st = m->stream;
   hipEvent_t ta;
 
-  // the sampled-source count, fetched while the sweep runs
+  // the sampled-source count, fetched while the sweeps run
   HIP_TRY(m, hipMemcpyAsync(m->h_cnt, m->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
   HIP_TRY(m, hipEventRecord(m->ev_count, st));
 
-  span_begin(m, ST_SWEEP, &ta);
+  span_begin(m, &ta);
   HIP_TRY(m, launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st));
   HIP_TRY(m, launch_sweep_le(m->le, m->bitmap, m->row_fill, geo, now, st));
-  if (m->slice % kRescrubPeriod == 0) HIP_TRY(m, launch_scrub(m->re, m->n_re, now, st));
+  HIP_TRY(m, launch_sweep_re(m->re, m->n_re, m->act_now, m->act_next, geo, now, st));
   HIP_TRY(m, launch_union_prob(m->row_fill, geo, m->up, st));
   span_end(m, ST_SWEEP, ta);
 
@@ -484,59 +492,47 @@ int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
   }
 
   // finalize: sort + unique the sampled sources, candidate check, N_t
-  span_begin(m, ST_FINALIZE, &ta);
+  span_begin(m, &ta);
   uint32_t* sorted = m->touched;
   if (n_raw > 0) {
     HIP_TRY(m, radix_sort_u32(m->touched, m->touched_tmp, n_raw, m->hist, &sorted, st));
-    HIP_TRY(m, launch_finalize(sorted, n_raw, m->re, m->si, geo, now, m->mark, m->cnt, st));
+    HIP_TRY(m, launch_finalize(sorted, n_raw, m->act_now, m->si_cnt, geo, m->mark, m->cnt, st));
     HIP_TRY(m, compact_u32(m->mark, 1u, sorted, &m->cnt->touched, n_raw, m->news,
                            &m->cnt->n_new, m->blockw, st));
   }
   span_end(m, ST_FINALIZE, ta);
 
-  // merge + per-candidate estimate
-  span_begin(m, ST_ESTIMATE, &ta);
+  // merge + per-candidate estimate, written into the pinned report buffers
+  span_begin(m, &ta);
   const uint32_t n_old = m->n_ncsip;
   uint64_t n_max = (uint64_t)n_old + n_raw;
   if (n_max > m->cap) n_max = m->cap;
   HIP_TRY(m, launch_merge(m->ncsip, n_old, m->news, n_raw, m->cnt, m->cap, m->csip, m->cflags, st));
-  HIP_TRY(m, launch_estimate(m->csip, n_max, m->cnt, m->bitmap, m->re, m->up, geo, now, m->est,
-                             m->cflags, m->U, m->W, st));
+  HIP_TRY(m, launch_estimate(m->csip, n_max, m->cnt, m->bitmap, m->act_now, m->act_next, m->up,
+                             geo, m->cflags, m->d_report, st));
   span_end(m, ST_ESTIMATE, ta);
 
-  // Algorithm 3: SI <- 0, carried list compacted in order, its SI bits set
-  span_begin(m, ST_SLIDE, &ta);
+  // Algorithm 3: carried list compacted in order, SI counters updated
+  span_begin(m, &ta);
   HIP_TRY(m, compact_u32(m->cflags, 8u, m->csip, &m->cnt->n_cand, n_max, m->ncsip_next,
                          &m->cnt->n_keep, m->cblockw, st));
-  HIP_TRY(m, launch_si_update(m->csip, m->cflags, m->cnt, n_max, (uint32_t*)m->si, m->si_words,
-                              geo, st));
+  HIP_TRY(m, launch_si_update(m->csip, m->cflags, m->cnt, n_max, m->si_cnt, geo, st));
   span_end(m, ST_SLIDE, ta);
 
-  span_begin(m, ST_REPORT, &ta);
-  HIP_TRY(m, hipMemcpyAsync(m->h_cnt, m->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
-  HIP_TRY(m, hipMemcpyAsync(m->h_row_fill, m->row_fill, geo.u * sizeof(unsigned long long),
-                            hipMemcpyDeviceToHost, st));
-  HIP_TRY(m, hipMemcpyAsync(m->h_up, m->up, sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(m, hipStreamSynchronize(st));
-  const Counters c = *m->h_cnt;
-  const uint64_t n = c.n_cand;
-  if (c.overflow) {
-    m->poisoned = true;
-    collect_spans(m);
-    return fail(m, SRLA_E_CAPACITY, "candidate list exceeds max_candidates");
-  }
-  if (n) {
-    HIP_TRY(m, hipMemcpyAsync(m->h_ip, m->csip, n * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(m, hipMemcpyAsync(m->h_est, m->est, n * 8, hipMemcpyDeviceToHost, st));
-    HIP_TRY(m, hipMemcpyAsync(m->h_flags, m->cflags, n, hipMemcpyDeviceToHost, st));
-    HIP_TRY(m, hipMemcpyAsync(m->h_U, m->U, n * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(m, hipMemcpyAsync(m->h_W, m->W, n, hipMemcpyDeviceToHost, st));
-  }
+  span_begin(m, &ta);
+  HIP_TRY(m, launch_status(m->cnt, m->up, m->row_fill, geo.u, m->d_status, st));
   // the next slice starts with empty counters
   HIP_TRY(m, launch_fill_u32((uint32_t*)m->cnt, 0u, sizeof(Counters) / 4, st));
   span_end(m, ST_REPORT, ta);
   HIP_TRY(m, hipStreamSynchronize(st));
 
+  const HostStatus& hs = *m->h_status;
+  const Counters c = hs.cnt;
+  if (c.overflow) {
+    m->poisoned = true;
+    collect_spans(m);
+    return fail(m, SRLA_E_CAPACITY, "candidate list exceeds max_candidates");
+  }
   std::swap(m->ncsip, m->ncsip_next);
   m->n_ncsip = c.n_keep;
   const uint64_t closed = m->slice;
@@ -545,17 +541,17 @@ int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
   m->estimates++;
   if (m->timing) collect_spans(m);
 
-  for (uint32_t i = 0; i < geo.u; ++i) m->h_row_fill64[i] = m->h_row_fill[i];
+  for (uint32_t i = 0; i < geo.u; ++i) m->h_row_fill64[i] = hs.row_fill[i];
   out->slice = closed;
   out->window_full = closed >= (uint64_t)(geo.k - 1) ? 1u : 0u;
-  out->n = n;
+  out->n = c.n_cand;
   out->ip = m->h_ip;
   out->est = m->h_est;
   out->flags = m->h_flags;
   out->union_weight = m->h_U;
   out->re_weight = m->h_W;
   out->row_fill = m->h_row_fill64;
-  out->up = *m->h_up;
+  out->up = hs.up;
   out->n_touched = c.n_unique;
   out->n_new = c.n_new;
   return SRLA_OK;
@@ -563,16 +559,28 @@ int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
 
 int srla_dump_state(srla_monitor_t* m, int which, uint16_t* host_out, uint64_t cells) {
   if (!m || !host_out) return m ? fail(m, SRLA_E_INVAL, "host_out is NULL") : SRLA_E_INVAL;
+  if (which == SRLA_DUMP_SI) {
+    if (cells != m->n_si) return fail(m, SRLA_E_INVAL, "cells does not match the array size");
+    std::vector<uint32_t> c(16 * m->n_si);
+    HIP_TRY(m, hipMemcpyAsync(c.data(), m->si_cnt, c.size() * 4, hipMemcpyDeviceToHost,
+                              m->stream));
+    HIP_TRY(m, hipStreamSynchronize(m->stream));
+    for (uint64_t i = 0; i < m->n_si; ++i) {
+      uint16_t w = 0;
+      for (int b = 0; b < 16; ++b)
+        if (c[16 * i + b]) w = (uint16_t)(w | (1u << b));
+      host_out[i] = w;
+    }
+    return SRLA_OK;
+  }
   const uint16_t* src;
   uint64_t n;
   if (which == SRLA_DUMP_LE) { src = m->le; n = m->n_le; }
   else if (which == SRLA_DUMP_RE) { src = m->re; n = m->n_re; }
-  else if (which == SRLA_DUMP_SI) { src = m->si; n = m->n_si; }
   else return fail(m, SRLA_E_INVAL, "unknown state array");
   if (cells != n) return fail(m, SRLA_E_INVAL, "cells does not match the array size");
   HIP_TRY(m, hipMemcpyAsync(host_out, src, n * 2, hipMemcpyDeviceToHost, m->stream));
   HIP_TRY(m, hipStreamSynchronize(m->stream));
-  if (which == SRLA_DUMP_SI) return SRLA_OK;
   const int32_t now = stamp_code(m->slice);
   for (uint64_t i = 0; i < n; ++i) {
     const uint16_t c = host_out[i];

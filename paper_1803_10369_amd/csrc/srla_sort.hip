@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
                                                       uint32_t nblocks) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wcnt[kWaves][256];
-  const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const uint32_t wave = threadIdx.x / kWave;
   base[threadIdx.x] = hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x];
   for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
   __syncthreads();

@@ -19,7 +19,7 @@ SRLA_OK, SRLA_E_INVAL, SRLA_E_NOMEM, SRLA_E_CAPACITY, SRLA_E_STATE, SRLA_E_DEVIC
 SRLA_DUMP_LE, SRLA_DUMP_RE, SRLA_DUMP_SI = 0, 1, 2
 SRLA_FLAG_SUPER, SRLA_FLAG_SAT, SRLA_FLAG_NEW, SRLA_FLAG_KEEP = 1, 2, 4, 8
 SRLA_CFG_TIMING = 1
-SRLA_CFG_SCAN_FLAT = 2
+SRLA_CFG_SCAN_XCD = 2
 
 
 class srla_geometry_t(ctypes.Structure):
@@ -174,8 +174,8 @@ class Monitor:
     caller's current stream and kept alive for the monitor's stream."""
 
     def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22,
-                 timing=False, stream=None, scan_flat=False):
-        flags = (SRLA_CFG_TIMING if timing else 0) | (SRLA_CFG_SCAN_FLAT if scan_flat else 0)
+                 timing=False, stream=None, scan_xcd=False):
+        flags = (SRLA_CFG_TIMING if timing else 0) | (SRLA_CFG_SCAN_XCD if scan_xcd else 0)
         self.cfg = make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates, flags)
         self._h = None
         self.stream = stream if stream is not None else torch.cuda.Stream()

@@ -24,8 +24,8 @@ def _gpu():
 
 
 def _run(stream, mon, slices, max_candidates=1 << 16, dump_every=1, split=None, host=False,
-         scan_flat=False):
-    g = srla.Monitor(**mon, max_candidates=max_candidates, scan_flat=scan_flat)
+         scan_xcd=False):
+    g = srla.Monitor(**mon, max_candidates=max_candidates, scan_xcd=scan_xcd)
     o = oracle.Monitor(**mon)
     for s in slices:
         pairs = stream.slice(s) if hasattr(stream, "slice") else stream(s)
@@ -46,10 +46,10 @@ def _run(stream, mon, slices, max_candidates=1 << 16, dump_every=1, split=None, 
     return rg
 
 
-@pytest.mark.parametrize("scan_flat", [False, True])
-def test_tiny_workload_full_run(scan_flat):
+@pytest.mark.parametrize("scan_xcd", [False, True])
+def test_tiny_workload_full_run(scan_xcd):
     stream, mon, n = workload("tiny")
-    r = _run(stream, mon, range(n), scan_flat=scan_flat)
+    r = _run(stream, mon, range(n), scan_xcd=scan_xcd)
     assert r.window_full and r.n > 0
 
 
@@ -90,11 +90,11 @@ SMALL = [
 
 
 @pytest.mark.parametrize("case", SMALL)
-@pytest.mark.parametrize("scan_flat", [False, True])
-def test_small_geometries(case, scan_flat):
+@pytest.mark.parametrize("scan_xcd", [False, True])
+def test_small_geometries(case, scan_xcd):
     k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
     mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=1000 + k + u)
-    _run(_rand_stream(k + u, n, n_src, 3 * theta // 2), mon, range(slices), scan_flat=scan_flat)
+    _run(_rand_stream(k + u, n, n_src, 3 * theta // 2), mon, range(slices), scan_xcd=scan_xcd)
 
 
 def test_host_input_chunked_and_unaligned_device_input():
@@ -174,13 +174,13 @@ def test_backbone_workload_prefix_full_size():
     _run(stream, mon, range(3), max_candidates=1 << 22)
 
 
-@pytest.mark.parametrize("scan_flat", [False, True])
-def test_backbone_short_window_expiry(scan_flat):
+@pytest.mark.parametrize("scan_xcd", [False, True])
+def test_backbone_short_window_expiry(scan_xcd):
     """Backbone geometry with k = 16 over 40 slices, so DRs leave the window
     and carried candidates are dropped at full column counts."""
     stream, mon, _ = workload("backbone_k16")
     stream = scaled(stream, 600_000)
-    _run(stream, mon, range(40), max_candidates=1 << 22, dump_every=13, scan_flat=scan_flat)
+    _run(stream, mon, range(40), max_candidates=1 << 22, dump_every=13, scan_xcd=scan_xcd)
 
 
 def test_paper_geometry_prefix():
