@@ -34,6 +34,22 @@ def scan_bytes_per_pair(u, tau):
     return 8.0 + 2.0 * u + (2.0 * u + 4.0) * 2.0 ** (-tau)
 
 
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on exactly the current scan source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for p in rec["sources"]:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return rec["bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -73,6 +89,8 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a known-size "
                          "reference for the HBM traffic counters)")
+    ap.add_argument("--probe-mib", default="",
+                    help="comma-separated extra footprints (MiB) for the random-store probe")
     ap.add_argument("--scan-xcd", action="store_true",
                     help="scan with per-XCD row ownership (A/B of the scan kernels)")
     args = ap.parse_args()
@@ -183,12 +201,25 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic("k_scan_xcd" if args.scan_xcd else "k_scan_flat",
+                                        args.workload),
             "bytes_per_pair": scan_bytes_per_pair(g["u"], tau),
             "launch_ms": scan_ms,
             "random_stores_per_s": g["u"] * (1 + 2.0 ** -tau) * n_pairs / (scan_ms * 1e-3),
         },
     }
+    # achievable rate of random 2-byte stores over the scan's own footprint
+    # (LE + RE stamp arrays), measured with the same store pattern and nothing else
+    import probe
+    footprint = 2 * g["u"] * (g["v_le"] * g["G"] + g["v_re"] * g["g"])
+    ceiling = probe.random_store_rate(footprint)
+    stores_per_s = out["roofline"]["random_stores_per_s"]
+    out["roofline"]["random_store_ceiling_per_s"] = ceiling
+    out["roofline"]["frac_of_random_store_ceiling"] = stores_per_s / ceiling
+    out["roofline"]["footprint_bytes"] = footprint
+    if args.probe_mib:
+        out["random_store_rates_per_s"] = {
+            mib: probe.random_store_rate(int(mib) << 20) for mib in args.probe_mib.split(",")}
     if not args.no_cpu_baseline:
         rate, dt, n = oracle_baseline(stream, mon, args.cpu_slices)
         out["cpu_baseline"] = {

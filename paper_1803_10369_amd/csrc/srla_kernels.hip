@@ -1,17 +1,18 @@
-// gfx950 kernels of the SRLA hot path (arXiv 1803.10369, Sections 4.1-4.2).
+// gfx950 end-of-slice kernels of the SRLA hot path (arXiv 1803.10369,
+// Section 4.2 and Algorithm 3): the LE and SRE sweeps, the candidate check,
+// the merge, Eq8-Eq9 and the SI update.  (The scan is in srla_scan.hip, the
+// sort and compaction primitives in srla_sort.hip.)
 //
 // Memory layout (all device-resident for the monitor's lifetime):
-//   LE     uint16 stamps [u][v_le][G]     one LE of G DRs per (row, column)
-//   RE     uint16 stamps [u][v_re][g]     one SRE of g DRs per (row, column)
-//   SI     uint16        [u][v_re]        super point indicators
-//   bitmap uint64        [u][v_le][G/64]  LE DRs inside the window, rebuilt
-//                                         at every slice end
-// A DR is a 16-bit slice stamp (see srla_internal.h): setting it (DRset) is a
-// plain idempotent store of the open slice's code, so concurrent pairs need
-// no atomics (Section 4.3 makes the same observation for distances), and the
-// slide of Algorithm 3 costs nothing.  No kernel contains a dense
-// contraction, so nothing here uses MFMA; the scan is bound by random 2-byte
-// stores and the sweep by streaming HBM bandwidth.
+//   LE      uint16 stamps [u][v_le][G]     one LE of G DRs per (row, column)
+//   RE      uint16 stamps [u][v_re][g]     one SRE of g DRs per (row, column)
+//   SI      uint32 counters [u][v_re][16]  SI bit = counter > 0
+//   bitmap  uint64 [u][v_le][G/64]         LE DRs inside the window
+//   act_*   uint64, 1 bit per SRE DR       inside now / after the slide
+// A DR is a 16-bit slice stamp (see srla_internal.h), so Algorithm 3's slide
+// of every DR costs nothing.  No kernel here contains a dense contraction, so
+// nothing uses MFMA; the sweeps stream HBM, the estimate gathers from the
+// L2-resident bitmaps.
 #include "srla_internal.h"
 
 namespace srla {
@@ -31,205 +32,6 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t 
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)blocks), dim3(kBlock), 0, st, p, value, n);
   return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ scan
-// Algorithm 2 for every pair.  One thread owns two adjacent pairs per step
-// (a 16-byte load), kScanSteps steps per block; all loads of a thread are
-// issued before its stores.  Sampled sources are appended to `touched` with
-// one atomic per wavefront (ballot + lane rank).
-
-constexpr int kScanSteps = 4;
-constexpr uint64_t kScanTile = (uint64_t)kBlock * 2 * kScanSteps;  // pairs per block
-
-template <int U>
-__device__ __forceinline__ void scan_one(uint32_t a, uint32_t b, bool valid, const Geo& geo,
-                                         uint16_t code, uint16_t* __restrict__ le,
-                                         uint16_t* __restrict__ re,
-                                         uint32_t* __restrict__ touched,
-                                         Counters* __restrict__ cnt) {
-  const uint32_t nu = U > 0 ? (uint32_t)U : geo.u;
-  bool sampled = false;
-  if (valid) {
-    // every pair sets one LE DR per row: H3(bip) picks the DR, RH_i(aip) the LE
-    const uint32_t lei = hrange(mas(geo.h3, b), geo.G);
-#pragma unroll
-    for (uint32_t i = 0; i < nu; ++i) {
-      const uint32_t col = hrange(mas(geo.rh[i], a), geo.v_le);
-      le[((uint64_t)i * geo.v_le + col) * geo.G + lei] = code;
-    }
-    // only pairs with LSB(H1(bip)) >= tau reach the SRE
-    sampled = (mas(geo.h1, b) & geo.tau_mask) == 0u;
-    if (sampled) {
-      const uint32_t rei = hrange(mas(geo.h2, b), geo.g);
-#pragma unroll
-      for (uint32_t i = 0; i < nu; ++i) {
-        const uint32_t col = hrange(mas(geo.rh[i], a), geo.v_re);
-        re[((uint64_t)i * geo.v_re + col) * geo.g + rei] = code;
-      }
-    }
-  }
-  // the candidate check of sampled sources happens at the end of the slice
-  const uint64_t mask = __ballot(sampled);
-  if (mask != 0ull) {
-    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
-    uint32_t base = 0;
-    if (__lane_id() == leader) base = atomicAdd(&cnt->touched, (uint32_t)__popcll(mask));
-    base = __shfl(base, (int)leader);
-    if (sampled) touched[base + lane_rank(mask)] = a;
-  }
-}
-
-template <int U, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_scan_flat(const uint32_t* __restrict__ pairs, uint64_t n,
-                                                Geo geo, uint16_t code,
-                                                uint16_t* __restrict__ le,
-                                                uint16_t* __restrict__ re,
-                                                uint32_t* __restrict__ touched,
-                                                Counters* __restrict__ cnt) {
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
-  uint32_t a[kScanSteps][2], b[kScanSteps][2];
-  bool v[kScanSteps][2];
-#pragma unroll
-  for (int s = 0; s < kScanSteps; ++s) {
-    const uint64_t p = base + (uint64_t)s * (2 * kBlock) + 2u * threadIdx.x;
-    v[s][0] = p < n;
-    v[s][1] = p + 1 < n;
-    if (VEC && v[s][1]) {
-      const uint4 q = *reinterpret_cast<const uint4*>(pairs + 2 * p);
-      a[s][0] = q.x; b[s][0] = q.y; a[s][1] = q.z; b[s][1] = q.w;
-    } else {
-      a[s][0] = v[s][0] ? pairs[2 * p] : 0u;
-      b[s][0] = v[s][0] ? pairs[2 * p + 1] : 0u;
-      a[s][1] = v[s][1] ? pairs[2 * p + 2] : 0u;
-      b[s][1] = v[s][1] ? pairs[2 * p + 3] : 0u;
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < kScanSteps; ++s) {
-    scan_one<U>(a[s][0], b[s][0], v[s][0], geo, code, le, re, touched, cnt);
-    scan_one<U>(a[s][1], b[s][1], v[s][1], geo, code, le, re, touched, cnt);
-  }
-}
-
-// XCD-aware form.  Workgroups are dispatched to the 8 XCDs round-robin, so
-// block b runs on XCD b % 8 and only ever touches the SEA rows that XCD owns:
-// with u >= 8, XCD x owns rows x, x+8, ...; with u in {1, 2, 4}, XCD x owns
-// row x % u and every u-th XCD takes the next tile.  Each XCD's L2 then sees
-// one LE row (4 MiB for 2048 x 1024 DRs) instead of all of them.  Each
-// (pair, row) is still stored exactly once, and the sampled-source append is
-// done by the owner of row 0; results do not depend on the actual placement.
-constexpr int kXcds = 8;
-
-template <int U>
-__global__ __launch_bounds__(kBlock) void k_scan_xcd(const uint32_t* __restrict__ pairs,
-                                                    uint64_t n, Geo geo, uint16_t code,
-                                                    uint16_t* __restrict__ le,
-                                                    uint16_t* __restrict__ re,
-                                                    uint32_t* __restrict__ touched,
-                                                    Counters* __restrict__ cnt) {
-  constexpr int kParts = U >= kXcds ? 1 : kXcds / U;      // tiles per XCD group
-  constexpr int kRowsPerXcd = U >= kXcds ? U / kXcds : 1;
-  const uint32_t xcd = blockIdx.x % kXcds;
-  const uint32_t group = blockIdx.x / kXcds;
-  const uint32_t row0 = U >= kXcds ? xcd : xcd % U;
-  const uint64_t tile = (uint64_t)group * kParts + (U >= kXcds ? 0u : xcd / U);
-  const bool appender = row0 == 0;
-  const uint64_t base = tile * kScanTile;
-  uint32_t a[kScanSteps][2], b[kScanSteps][2];
-  bool v[kScanSteps][2];
-#pragma unroll
-  for (int s = 0; s < kScanSteps; ++s) {
-    const uint64_t p = base + (uint64_t)s * (2 * kBlock) + 2u * threadIdx.x;
-    v[s][0] = p < n;
-    v[s][1] = p + 1 < n;
-    if (v[s][1]) {
-      const uint4 q = *reinterpret_cast<const uint4*>(pairs + 2 * p);
-      a[s][0] = q.x; b[s][0] = q.y; a[s][1] = q.z; b[s][1] = q.w;
-    } else {
-      a[s][0] = v[s][0] ? pairs[2 * p] : 0u;
-      b[s][0] = v[s][0] ? pairs[2 * p + 1] : 0u;
-      a[s][1] = 0u; b[s][1] = 0u;
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < kScanSteps; ++s) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const uint32_t aa = a[s][h], bb = b[s][h];
-      bool sampled = false;
-      if (v[s][h]) {
-        const uint32_t lei = hrange(mas(geo.h3, bb), geo.G);
-        sampled = (mas(geo.h1, bb) & geo.tau_mask) == 0u;
-        const uint32_t rei = sampled ? hrange(mas(geo.h2, bb), geo.g) : 0u;
-#pragma unroll
-        for (int j = 0; j < kRowsPerXcd; ++j) {
-          const uint32_t r = row0 + (uint32_t)j * kXcds;
-          const uint32_t hr = mas(geo.rh[r], aa);
-          le[((uint64_t)r * geo.v_le + hrange(hr, geo.v_le)) * geo.G + lei] = code;
-          if (sampled) re[((uint64_t)r * geo.v_re + hrange(hr, geo.v_re)) * geo.g + rei] = code;
-        }
-      }
-      if (appender) {
-        const uint64_t mask = __ballot(sampled);
-        if (mask != 0ull) {
-          const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
-          uint32_t slot = 0;
-          if (__lane_id() == leader) slot = atomicAdd(&cnt->touched, (uint32_t)__popcll(mask));
-          slot = __shfl(slot, (int)leader);
-          if (sampled) touched[slot + lane_rank(mask)] = aa;
-        }
-      }
-    }
-  }
-}
-
-template <int U>
-static hipError_t launch_scan_xcd(const uint32_t* pairs, uint64_t n, const Geo& geo,
-                                  uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
-                                  Counters* cnt, hipStream_t st) {
-  constexpr uint64_t kParts = U >= kXcds ? 1 : kXcds / U;
-  const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
-  const uint64_t blocks = kXcds * ((tiles + kParts - 1) / kParts);
-  hipLaunchKernelGGL((k_scan_xcd<U>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n, geo,
-                     code, le, re, touched, cnt);
-  return hipGetLastError();
-}
-
-template <int U>
-static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
-                                uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
-                                hipStream_t st) {
-  const uint64_t blocks = (n + kScanTile - 1) / kScanTile;
-  const bool vec = ((uintptr_t)pairs & 15u) == 0;
-  if (vec)
-    hipLaunchKernelGGL((k_scan_flat<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
-                       geo, code, le, re, touched, cnt);
-  else
-    hipLaunchKernelGGL((k_scan_flat<U, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
-                       geo, code, le, re, touched, cnt);
-  return hipGetLastError();
-}
-
-hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
-                       uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
-                       bool xcd_aware, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  if (xcd_aware && ((uintptr_t)pairs & 15u) == 0) {
-    switch (geo.u) {
-      case 1: return launch_scan_xcd<1>(pairs, n, geo, code, le, re, touched, cnt, st);
-      case 2: return launch_scan_xcd<2>(pairs, n, geo, code, le, re, touched, cnt, st);
-      case 4: return launch_scan_xcd<4>(pairs, n, geo, code, le, re, touched, cnt, st);
-      case 8: return launch_scan_xcd<8>(pairs, n, geo, code, le, re, touched, cnt, st);
-      case 16: return launch_scan_xcd<16>(pairs, n, geo, code, le, re, touched, cnt, st);
-      default: break;
-    }
-  }
-  switch (geo.u) {
-    case 4: return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, cnt, st);
-    case 8: return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, cnt, st);
-    default: return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, cnt, st);
-  }
 }
 
 // ------------------------------------------------------------------ sweep

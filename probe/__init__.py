@@ -1,0 +1,60 @@
+"""Memory-system probes that calibrate the SRLA kernels' ceilings.
+
+``random_store_rate(bytes)`` measures random 2-byte stores per second over a
+footprint of ``bytes`` (the scan's access pattern without its pair loads and
+hashing).  Measurement infrastructure only; the SRLA library does not use it.
+"""
+import ctypes
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libprobe.so")
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+_lib = None
+
+
+def build():
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           os.path.join(HERE, "random_store.hip"), "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("probe build failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (shares torch's HIP runtime)
+        if not os.path.exists(LIB):
+            raise RuntimeError("libprobe.so is not built")
+        L = ctypes.CDLL(LIB)
+        L.probe_random_store.restype = ctypes.c_double
+        L.probe_random_store.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                         ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
+        _lib = L
+    return _lib
+
+
+def random_store_rate(nbytes, stores=1 << 27, repeats=3):
+    """Best-of-`repeats` random 2-byte stores per second over `nbytes`."""
+    import torch
+    L = _load()
+    buf = torch.zeros(nbytes // 2, dtype=torch.int16, device="cuda")
+    per_lane = 64
+    blocks = max(1, stores // (256 * per_lane))
+    st = torch.cuda.current_stream()
+    best = None
+    for r in range(repeats + 1):
+        ms = L.probe_random_store(ctypes.c_void_p(buf.data_ptr()), buf.numel() * 2, blocks,
+                                  per_lane, 1234 + r, ctypes.c_void_p(st.cuda_stream))
+        if ms <= 0:
+            raise RuntimeError("probe failed (%g)" % ms)
+        if r > 0:   # the first launch warms the footprint
+            best = ms if best is None else min(best, ms)
+    del buf
+    return blocks * 256 * per_lane / (best * 1e-3)

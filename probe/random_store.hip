@@ -1,0 +1,48 @@
+// Memory-system probe: the rate of random 2-byte stores, one per lane,
+// uniform over a footprint of F bytes -- the access pattern of the SRLA scan
+// with nothing else (no pair loads, no hashing beyond the address).  Used to
+// calibrate the scan kernel's achievable ceiling per footprint.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// every lane stores `per_lane` 2-byte values at uniform random cells
+__global__ __launch_bounds__(256) void k_random_store(uint16_t* __restrict__ buf, uint64_t cells,
+                                                     uint32_t per_lane, uint64_t seed,
+                                                     uint16_t value) {
+  const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  uint64_t s = mix64(seed ^ (t * 0x9E3779B97F4A7C15ull));
+  for (uint32_t i = 0; i < per_lane; ++i) {
+    s = mix64(s + 0x9E3779B97F4A7C15ull);
+    const uint64_t cell = (uint64_t)(((unsigned __int128)s * cells) >> 64);
+    buf[cell] = value;
+  }
+}
+
+}  // namespace
+
+// Returns the kernel time in ms (HIP events) or a negative value on error.
+extern "C" double probe_random_store(void* buf, uint64_t bytes, uint64_t blocks, uint32_t per_lane,
+                                     uint64_t seed, void* stream) {
+  if (!buf || bytes < 2 || blocks == 0) return -1.0;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -2.0;
+  hipEventRecord(a, st);
+  hipLaunchKernelGGL(k_random_store, dim3((uint32_t)blocks), dim3(256), 0, st, (uint16_t*)buf,
+                     bytes / 2, per_lane, seed, (uint16_t)(seed | 1));
+  hipEventRecord(b, st);
+  float ms = -3.f;
+  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+    ms = -4.f;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms;
+}
