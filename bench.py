@@ -3,15 +3,19 @@
 One step = one time slice of the backbone-shaped workload: 8M (aip, bip)
 pairs scanned into the SEA (Algorithm 2), then the slice closed (candidate
 check, Eq8-Eq9 estimate of every candidate, Algorithm 3 slide) and its report
-copied to host memory.  Window k = 300 slices, SRE 8 x 2^20 DR cells, SLE
+delivered to host memory.  Window k = 300 slices, SRE 8 x 2^20 DR cells, SLE
 2^24 DR cells, theta = 1024.  Warm-up steps run first so that the timed
 slices see a full window; the timed slices' pairs are generated into device
-memory before the timed region starts.
+memory before each timed segment starts.
+
+--mode plain (default): each slice is scanned, then estimated; the latency
+  is the host time from the end of the slice's scan to its report.
+--mode streaming: the scan of slice t+1 runs on the GPU while slice t is
+  being estimated (two HIP streams, the end-of-slice pipeline replayed as HIP
+  graphs); the latency is the host time from closing slice t to its report.
 
 Prints one JSON line (rank 0).  `value` is pairs (packets) scanned per second
-over the whole timed region; `p99_ms` is the 99th percentile of the slice-end
-estimate latency (host time from the end of a slice's scan to its report in
-host memory).
+over the timed slices; `p99_ms` is the 99th percentile of the latency.
 """
 import argparse
 import json
@@ -79,6 +83,11 @@ def oracle_baseline(stream, mon, slices):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--mode", choices=("plain", "streaming"), default="plain")
+    ap.add_argument("--graph", type=int, default=-1,
+                    help="replay the end-of-slice pipeline as HIP graphs (default: streaming only)")
+    ap.add_argument("--segment", type=int, default=200,
+                    help="timed slices whose inputs are generated into HBM at a time")
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--workload", default="backbone")
@@ -122,35 +131,63 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    graph = (args.mode == "streaming") if args.graph < 0 else bool(args.graph)
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
-                     scan_xcd=args.scan_xcd)
+                     scan_xcd=args.scan_xcd, graph=graph)
     buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
     t_w = time.perf_counter()
     for s in range(args.warmup):
         ds.generate(s, out=buf, stream=st)
         m.scan(buf)
-        m.estimate()
+        m.estimate(copy=False)
         if s % 50 == 0:
             print("warmup slice %d (%.1fs)" % (s, time.perf_counter() - t_w), file=sys.stderr,
                   flush=True)
-    # the timed slices' pairs, resident in HBM before the timed region
-    timed = [ds.generate(args.warmup + i, stream=st) for i in range(args.steps)]
-    torch.cuda.synchronize()
-    m.timings(reset=True)
 
     lat = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        m.scan(timed[i])
-        st.synchronize()           # the slice's last pair is scanned
-        ts = time.perf_counter()
-        r = m.estimate(copy=False)   # returns with the report in host memory
-        lat.append((time.perf_counter() - ts) * 1e3)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    total_s = 0.0
+    done = 0
+    seg_bufs = []
+    tm = None
+    while done < args.steps:
+        seg = min(args.segment, args.steps - done)
+        # the segment's pairs, resident in HBM before its timed region
+        while len(seg_bufs) < seg:
+            seg_bufs.append(torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda"))
+        for i in range(seg):
+            ds.generate(args.warmup + done + i, out=seg_bufs[i], stream=st)
+        torch.cuda.synchronize()
+        if tm is None:
+            m.timings(reset=True)
+        t0 = time.perf_counter()
+        if args.mode == "plain":
+            for i in range(seg):
+                m.scan(seg_bufs[i])
+                st.synchronize()             # the slice's last pair is scanned
+                ts = time.perf_counter()
+                r = m.estimate(copy=False)   # returns with the report in host memory
+                lat.append((time.perf_counter() - ts) * 1e3)
+        else:
+            m.scan(seg_bufs[0])
+            m.close_slice()
+            t_close = time.perf_counter()
+            for i in range(1, seg + 1):
+                if i < seg:
+                    m.scan(seg_bufs[i])      # runs while slice i-1 is estimated
+                r = m.wait_report(copy=False)
+                lat.append((time.perf_counter() - t_close) * 1e3)
+                if i < seg:
+                    m.close_slice()
+                    t_close = time.perf_counter()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        total_s += t1 - t0
+        done += seg
+        print("timed %d/%d slices (%.2fs)" % (done, args.steps, total_s), file=sys.stderr,
+              flush=True)
+        tm = True
     tm = m.timings(reset=True)
 
-    total_s = t1 - t0
     pairs = args.steps * n_pairs
     value = pairs / total_s
     lat = np.array(lat)
@@ -178,15 +215,16 @@ def main():
         "dtype": "u16",
         "data": "synthetic",
         "config": {
-            "workload": ("%s: 1 monitor, window %d slices, %d pairs/slice, Zipf(%g) sources "
-                         "over %d hosts, %d planted super points, SRE %d x %d DR cells, "
+            "workload": ("%s, %s form: 1 monitor, window %d slices, %d pairs/slice, Zipf(%g) "
+                         "sources over %d hosts, %d planted super points, SRE %d x %d DR cells, "
                          "SLE %d DR cells (uint16 slice stamps), theta %d"
-                         % (args.workload, g["k"], n_pairs, stream.alpha, stream.n_ranks,
+                         % (args.workload, args.mode, g["k"], n_pairs, stream.alpha, stream.n_ranks,
                             len(stream.planted), g["u"], g["v_re"] * g["g"],
                             g["u"] * g["v_le"] * g["G"], g["theta"])),
             "u": g["u"], "v_re": g["v_re"], "g": g["g"], "v_le": g["v_le"], "g_le": g["G"],
             "window": g["k"], "theta": g["theta"], "pairs_per_slice": n_pairs,
             "slices_timed": [args.warmup, args.warmup + args.steps - 1],
+            "mode": args.mode, "graph": graph,
         },
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),

@@ -15,7 +15,10 @@
  *
  * Every function returns an int status (SRLA_OK or a negative SRLA_E_*) and
  * never throws.  A monitor is not thread-safe; separate monitors are
- * independent.  All device work of a monitor is issued on one HIP stream.
+ * independent.  Scans run on the monitor's scan stream (the caller's, or one
+ * the library creates); the end-of-slice work runs on a second stream the
+ * library owns, ordered after the slice's scans by HIP events, so that the
+ * next slice can be scanned while the previous one is being estimated.
  */
 #ifndef SRLA_H
 #define SRLA_H
@@ -49,9 +52,12 @@ enum {
 /* srla_config_t.flags */
 enum {
     SRLA_CFG_TIMING = 1,   /* record HIP events around every stage */
-    SRLA_CFG_SCAN_XCD = 2  /* scan with per-XCD row ownership (each XCD stores
+    SRLA_CFG_SCAN_XCD = 2, /* scan with per-XCD row ownership (each XCD stores
                               into its own SEA rows); results are identical
                               either way, only the speed differs */
+    SRLA_CFG_GRAPH = 4     /* record the end-of-slice pipeline once per slice
+                              parity as HIP graphs and replay them; results
+                              are identical either way */
 };
 
 /*
@@ -90,8 +96,9 @@ typedef struct srla_monitor srla_monitor_t;
 
 /*
  * The report of one closed slice e, covering the window [e-k+1, e]
- * (window_full == 0 while e < k-1).  Arrays are host memory owned by the
- * library and stay valid until the next srla_estimate or srla_destroy.
+ * (window_full == 0 while e < k-1).  Arrays are pinned host memory owned by
+ * the library, written by its kernels; they stay valid until the next
+ * srla_close_slice (or srla_estimate) or srla_destroy.
  *   ip            the candidate list CSIP (Algorithms 2-3), ascending
  *   est           Eq9 estimate of |OP(ip, e-k+1, k)| (FP64; +inf with SAT)
  *   flags         SRLA_FLAG_* of each candidate
@@ -117,17 +124,19 @@ typedef struct {
     uint64_t n_new;
 } srla_report_t;
 
-/* Accumulated stage times (milliseconds, HIP events on the monitor's stream)
-   since the last reset; all zero unless SRLA_CFG_TIMING was set. */
+/* Accumulated stage times (milliseconds, HIP events on the stream each stage
+   runs on) since the last reset; all zero unless SRLA_CFG_TIMING was set.
+   With SRLA_CFG_GRAPH the end-of-slice stages after the sweeps are timed as
+   one (estimate_ms). */
 typedef struct {
     double scan_ms;        /* Algorithm 2 scan kernels */
     uint64_t scan_launches;
     uint64_t scan_pairs;
-    double sweep_ms;       /* row fills |LDR(i)|^k and the LE activity bitmap */
+    double sweep_ms;       /* row fills |LDR(i)|^k and the LE/SRE activity bitmaps */
     double finalize_ms;    /* candidate check of the slice's sampled sources */
     double estimate_ms;    /* merge, Eq8-Eq9 and the Algorithm 3 re-check */
-    double slide_ms;       /* SI rebuild and carried-list compaction */
-    double report_ms;      /* device-to-host copy of the report */
+    double slide_ms;       /* carried-list compaction, SI update, status */
+    double report_ms;      /* unused (the estimate writes the report) */
     uint64_t estimates;
 } srla_timings_t;
 
@@ -170,11 +179,27 @@ int srla_scan(srla_monitor_t *m, const uint32_t *pairs, uint64_t n, int on_devic
  * union SRE and union SI, the union-LE estimate (Eq8-Eq9) of every candidate,
  * then the slide -- SI cleared, every DR one slice older, candidates whose
  * union SRE still passes carried into slice e+1 with their SI bits set.
- * Blocks until the report is in host memory.  Errors: SRLA_E_CAPACITY (more
- * than max_candidates candidates; the monitor is then poisoned), SRLA_E_STATE,
+ * Blocks until the report is in host memory.  Same as srla_close_slice
+ * followed by srla_wait_report.  Errors: SRLA_E_CAPACITY (more than
+ * max_candidates candidates; the monitor is then poisoned), SRLA_E_STATE
+ * (poisoned, or an earlier closed slice's report not collected),
  * SRLA_E_INVAL (NULL out), SRLA_E_NOMEM, SRLA_E_DEVICE.
  */
 int srla_estimate(srla_monitor_t *m, srla_report_t *out);
+
+/*
+ * Streaming form of srla_estimate.  srla_close_slice closes the open slice e
+ * without waiting: it enqueues e's end-of-slice work and opens slice e+1 at
+ * once.  Scans of e+1 may be issued right away; on the device they start as
+ * soon as e's DRs have been snapshotted (the LE/SRE activity sweeps), and run
+ * while e is still being estimated.  srla_wait_report then blocks until e's
+ * report is in host memory and fills *out.  Every closed slice must be
+ * collected before the next srla_close_slice (SRLA_E_STATE otherwise).
+ * Results are identical to srla_estimate's.  Errors as for srla_estimate;
+ * SRLA_E_CAPACITY is reported by srla_wait_report.
+ */
+int srla_close_slice(srla_monitor_t *m);
+int srla_wait_report(srla_monitor_t *m, srla_report_t *out);
 
 /*
  * Copies one state array to host memory, as of the open slice.
@@ -190,7 +215,7 @@ int srla_dump_state(srla_monitor_t *m, int which, uint16_t *host_out, uint64_t c
 /* Stage times since the last reset (reset != 0 clears them after reading). */
 int srla_timings(srla_monitor_t *m, srla_timings_t *out, int reset);
 
-/* Waits for the monitor's stream and frees everything it owns. NULL is ok. */
+/* Waits for the monitor's streams and frees everything it owns. NULL is ok. */
 int srla_destroy(srla_monitor_t *m);
 
 /* Text of the monitor's last error ("" if none); static text for NULL. */

@@ -70,7 +70,7 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask) {
 
 // Device counters of one slice's end-of-slice pipeline.
 struct Counters {
-  uint32_t touched;      // sampled-source appends in the open slice
+  uint32_t touched;      // sampled-source appends of the slice (copied in)
   uint32_t n_unique;     // distinct sampled sources
   uint32_t n_new;        // new candidates N_t
   uint32_t n_cand;       // |CSIP_t| (clamped to capacity)
@@ -79,11 +79,20 @@ struct Counters {
   uint32_t pad[2];
 };
 
+// Device-resident state the end-of-slice pipeline reads instead of host
+// arguments, so one recorded pipeline serves every slice of a parity.
+struct PipeState {
+  uint32_t now;          // stamp code of the slice being closed
+  uint32_t n_ncsip;      // |NCSIP| carried into it
+  uint64_t slice;        // its index
+};
+
 // Pinned host block the status kernel fills at the end of every slice.
 struct HostStatus {
   Counters cnt;
   double up;
   unsigned long long row_fill[kMaxU];
+  uint64_t slice;
 };
 
 // Report arrays in pinned host memory, as device-visible pointers.
@@ -95,58 +104,67 @@ struct ReportPtrs {
   uint8_t* W;
 };
 
+// Fixed grids of the end-of-slice kernels (they loop over device counts).
+constexpr uint32_t kPipeBlocks = 1024;
+
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `st` and return the launch status.
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t st);
 
+// Algorithm 2 for n pairs of the open slice (stamp code `code`); sampled
+// sources are appended to `touched`, counted in *tcount
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
-                       uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
+                       uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
                        bool xcd_aware, hipStream_t st);
 
 hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
-                           const Geo& geo, uint16_t now, hipStream_t st);
+                           const Geo& geo, const PipeState* ps, hipStream_t st);
 
 // SRE DR activity bitmaps (inside the window now / after the slide) + scrub
 hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act_now, uint64_t* act_next,
-                           const Geo& geo, uint16_t now, hipStream_t st);
+                           const Geo& geo, const PipeState* ps, hipStream_t st);
 
-// keys-only LSD radix sort of n uint32 keys; returns the buffer holding the
-// sorted keys (keys or tmp).  block_hist needs radix_hist_words(n) words.
+// keys-only LSD radix sort of *n_dev uint32 keys (n_dev <= n_max), in place
+// (tmp is scratch).  block_hist needs radix_hist_words(n_max) words.
 uint64_t radix_hist_words(uint64_t n);
-hipError_t radix_sort_u32(uint32_t* keys, uint32_t* tmp, uint64_t n, uint32_t* block_hist,
-                          uint32_t** sorted, hipStream_t st);
+hipError_t radix_sort_u32(uint32_t* keys, uint32_t* tmp, const uint32_t* n_dev, uint64_t n_max,
+                          uint32_t* block_hist, hipStream_t st);
 
 // exclusive-scan helper storage for compaction of up to n elements
 uint64_t compact_block_words(uint64_t n);
 
-hipError_t launch_finalize(const uint32_t* sorted, uint64_t n_max, const uint64_t* act_now,
-                           const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
-                           hipStream_t st);
-
-// stable compaction of vals[i] with (flags[i] & mask) != 0, i < *n_dev (or
-// n_host if n_dev is null); n_max bounds the grid; result count -> *out_count
+// stable compaction of vals[i] with (flags[i] & mask) != 0, i < *n_dev
+// (n_dev <= n_max); result count -> *out_count
 hipError_t compact_u32(const uint8_t* flags, uint8_t mask, const uint32_t* vals,
                        const uint32_t* n_dev, uint64_t n_max, uint32_t* out,
                        uint32_t* out_count, uint32_t* block_words, hipStream_t st);
 
-hipError_t launch_merge(const uint32_t* ncsip, uint32_t n_old, const uint32_t* news,
-                        uint64_t n_new_max, Counters* cnt, uint64_t cap, uint32_t* csip,
-                        uint8_t* cflags, hipStream_t st);
+hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const uint64_t* act_now,
+                           const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
+                           hipStream_t st);
+
+hipError_t launch_merge(const uint32_t* ncsip, const PipeState* ps, const uint32_t* news,
+                        Counters* cnt, uint64_t cap, uint32_t* csip, uint8_t* cflags,
+                        hipStream_t st);
 
 hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
                              double* up, hipStream_t st);
 
-hipError_t launch_estimate(const uint32_t* csip, uint64_t n_max, const Counters* cnt,
-                           const uint64_t* bitmap, const uint64_t* act_now,
-                           const uint64_t* act_next, const double* up, const Geo& geo,
-                           uint8_t* cflags, const ReportPtrs& out, hipStream_t st);
+hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
+                           const uint64_t* act_now, const uint64_t* act_next, const double* up,
+                           const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
+                           hipStream_t st);
 
 // Algorithm 3's SI step on the per-bit counters (after the KEEP flags are final)
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
-                            uint64_t n_max, uint32_t* si_cnt, const Geo& geo, hipStream_t st);
+                            uint32_t* si_cnt, const Geo& geo, hipStream_t st);
 
-hipError_t launch_status(const Counters* cnt, const double* up, const unsigned long long* row_fill,
-                         uint32_t u, HostStatus* out, hipStream_t st);
+// publishes the slice's counters, Eq8 and row fills to the host, carries
+// |NCSIP| into the state, advances the state to the next slice, and clears
+// the slice's counters (and the sampled-source count of its parity)
+hipError_t launch_status(Counters* cnt, uint32_t* tcount, const double* up,
+                         const unsigned long long* row_fill, uint32_t u, PipeState* ps,
+                         HostStatus* out, hipStream_t st);
 
 }  // namespace srla

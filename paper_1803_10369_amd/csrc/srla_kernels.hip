@@ -46,8 +46,10 @@ constexpr uint64_t kSweepTile = (uint64_t)kBlock * 8 * kSweepSteps;  // DRs per 
 __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
                                                     uint64_t* __restrict__ bitmap,
                                                     unsigned long long* __restrict__ row_fill,
-                                                    uint64_t row_cells, uint32_t now,
+                                                    uint64_t row_cells,
+                                                    const PipeState* __restrict__ ps,
                                                     uint32_t k) {
+  const uint32_t now = ps->now;
   const uint32_t row = blockIdx.y;
   uint16_t* rowp = le + (uint64_t)row * row_cells;
   uint64_t* bmp = bitmap + (uint64_t)row * (row_cells / 64);
@@ -101,11 +103,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
 }
 
 hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
-                           const Geo& geo, uint16_t now, hipStream_t st) {
+                           const Geo& geo, const PipeState* ps, hipStream_t st) {
   const uint64_t row_cells = (uint64_t)geo.v_le * geo.G;
   const uint64_t bx = (row_cells + kSweepTile - 1) / kSweepTile;
   hipLaunchKernelGGL(k_sweep_le, dim3((uint32_t)bx, geo.u), dim3(kBlock), 0, st, le, bitmap,
-                     row_fill, row_cells, (uint32_t)now, geo.k);
+                     row_fill, row_cells, ps, geo.k);
   return hipGetLastError();
 }
 
@@ -120,7 +122,9 @@ hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* r
 __global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, uint64_t n,
                                                     uint64_t* __restrict__ act_now,
                                                     uint64_t* __restrict__ act_next,
-                                                    uint32_t now, uint32_t k) {
+                                                    const PipeState* __restrict__ ps,
+                                                    uint32_t k) {
+  const uint32_t now = ps->now;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint64_t c8 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 8;
   uint32_t m_now = 0, m_next = 0;
@@ -172,11 +176,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, 
 }
 
 hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act_now, uint64_t* act_next,
-                           const Geo& geo, uint16_t now, hipStream_t st) {
+                           const Geo& geo, const PipeState* ps, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const uint64_t blocks = (n + 8 * kBlock - 1) / (8 * kBlock);
   hipLaunchKernelGGL(k_sweep_re, dim3((uint32_t)blocks), dim3(kBlock), 0, st, re, n, act_now,
-                     act_next, (uint32_t)now, geo.k);
+                     act_next, ps, geo.k);
   return hipGetLastError();
 }
 
@@ -209,40 +213,44 @@ __device__ __forceinline__ uint64_t si_slot(const Geo& geo, uint32_t r, uint32_t
 // union SI (AND over rows) is still clear.  SI is as the previous slide left it.
 
 __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict__ sorted,
+                                                    const uint32_t* __restrict__ n_dev,
                                                     const uint64_t* __restrict__ act_now,
                                                     const uint32_t* __restrict__ si_cnt,
                                                     Geo geo, uint8_t* __restrict__ mark,
                                                     Counters* __restrict__ cnt) {
-  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  const uint32_t n = cnt->touched;
-  bool first = false;
-  if (i < n) {
-    const uint32_t a = sorted[i];
-    first = (i == 0) || (sorted[i - 1] != a);
-    uint8_t f = 0;
-    if (first) {
-      const uint32_t bit = hrange(mas(geo.h4, a), 16u);
-      uint64_t ure = ~0ull;
-      bool usi = true;
-      for (uint32_t r = 0; r < geo.u; ++r) {
-        const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
-        ure &= sre_bits(act_now, geo, r, col);
-        usi = usi && si_cnt[si_slot(geo, r, col, bit)] != 0u;
+  const uint32_t n = *n_dev;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  uint32_t firsts = 0;
+  // the loop bound is uniform per wavefront, so the ballot below sees all lanes
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < n; base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    bool first = false;
+    if (i < n) {
+      const uint32_t a = sorted[i];
+      first = (i == 0) || (sorted[i - 1] != a);
+      uint8_t f = 0;
+      if (first) {
+        const uint32_t bit = hrange(mas(geo.h4, a), 16u);
+        uint64_t ure = ~0ull;
+        bool usi = true;
+        for (uint32_t r = 0; r < geo.u; ++r) {
+          const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
+          ure &= sre_bits(act_now, geo, r, col);
+          usi = usi && si_cnt[si_slot(geo, r, col, bit)] != 0u;
+        }
+        f = ((uint32_t)__popcll(ure) >= geo.t_re && !usi) ? 1 : 0;
       }
-      f = ((uint32_t)__popcll(ure) >= geo.t_re && !usi) ? 1 : 0;
+      mark[i] = f;
     }
-    mark[i] = f;
+    firsts += (uint32_t)__popcll(__ballot(first));
   }
-  const uint64_t firsts = __ballot(first);
-  if (__lane_id() == 0 && firsts) atomicAdd(&cnt->n_unique, (uint32_t)__popcll(firsts));
+  if (__lane_id() == 0 && firsts) atomicAdd(&cnt->n_unique, firsts);
 }
 
-hipError_t launch_finalize(const uint32_t* sorted, uint64_t n_max, const uint64_t* act_now,
+hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const uint64_t* act_now,
                            const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
                            hipStream_t st) {
-  if (n_max == 0) return hipSuccess;
-  const uint64_t blocks = (n_max + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_finalize, dim3((uint32_t)blocks), dim3(kBlock), 0, st, sorted, act_now,
+  hipLaunchKernelGGL(k_finalize, dim3(kPipeBlocks), dim3(kBlock), 0, st, sorted, n_dev, act_now,
                      si_cnt, geo, mark, cnt);
   return hipGetLastError();
 }
@@ -263,38 +271,40 @@ __device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__
 }
 
 __global__ __launch_bounds__(kBlock) void k_merge(const uint32_t* __restrict__ ncsip,
-                                                 uint32_t n_old,
+                                                 const PipeState* __restrict__ ps,
                                                  const uint32_t* __restrict__ news,
                                                  Counters* __restrict__ cnt, uint64_t cap,
                                                  uint32_t* __restrict__ csip,
                                                  uint8_t* __restrict__ cflags) {
-  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t n_old = ps->n_ncsip;
   const uint32_t n_new = cnt->n_new;
-  if (t == 0) {
+  const uint64_t first = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (first == 0) {
     const uint64_t total = (uint64_t)n_old + n_new;
     cnt->n_cand = (uint32_t)(total < cap ? total : cap);
     cnt->overflow = total > cap ? 1u : 0u;
   }
-  if (t < n_old) {
-    const uint32_t x = ncsip[t];
-    const uint64_t pos = t + lower_bound_u32(news, n_new, x);
-    if (pos < cap) { csip[pos] = x; cflags[pos] = 0; }
-  }
-  if (t < n_new) {
-    const uint32_t y = news[t];
-    const uint64_t pos = t + lower_bound_u32(ncsip, n_old, y);
-    if (pos < cap) { csip[pos] = y; cflags[pos] = 4; /* SRLA_FLAG_NEW */ }
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint64_t top = n_old > n_new ? n_old : n_new;
+  for (uint64_t t = first; t < top; t += stride) {
+    if (t < n_old) {
+      const uint32_t x = ncsip[t];
+      const uint64_t pos = t + lower_bound_u32(news, n_new, x);
+      if (pos < cap) { csip[pos] = x; cflags[pos] = 0; }
+    }
+    if (t < n_new) {
+      const uint32_t y = news[t];
+      const uint64_t pos = t + lower_bound_u32(ncsip, n_old, y);
+      if (pos < cap) { csip[pos] = y; cflags[pos] = 4; /* SRLA_FLAG_NEW */ }
+    }
   }
 }
 
-hipError_t launch_merge(const uint32_t* ncsip, uint32_t n_old, const uint32_t* news,
-                        uint64_t n_new_max, Counters* cnt, uint64_t cap, uint32_t* csip,
-                        uint8_t* cflags, hipStream_t st) {
-  uint64_t n = n_old > n_new_max ? n_old : n_new_max;
-  if (n == 0) n = 1;  // thread 0 still publishes the counts
-  const uint64_t blocks = (n + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_merge, dim3((uint32_t)blocks), dim3(kBlock), 0, st, ncsip, n_old, news,
-                     cnt, cap, csip, cflags);
+hipError_t launch_merge(const uint32_t* ncsip, const PipeState* ps, const uint32_t* news,
+                        Counters* cnt, uint64_t cap, uint32_t* csip, uint8_t* cflags,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(k_merge, dim3(kPipeBlocks), dim3(kBlock), 0, st, ncsip, ps, news, cnt, cap,
+                     csip, cflags);
   return hipGetLastError();
 }
 
@@ -345,10 +355,11 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
   const uint32_t per_round = kBlock >> lg_log2;          // candidates per round
   const uint32_t sub = threadIdx.x & (lg - 1u);
   const uint32_t n = cnt->n_cand;
-  const uint64_t base = (uint64_t)blockIdx.x * kEstPerBlock;
   const uint64_t gmask = geo.g == 64u ? ~0ull : ((1ull << geo.g) - 1ull);
   const double up = *up_p;
   const double G = (double)geo.G;
+  for (uint64_t base = (uint64_t)blockIdx.x * kEstPerBlock; base < n;
+       base += (uint64_t)gridDim.x * kEstPerBlock) {
   for (uint32_t round = 0; round * per_round < kEstPerBlock; ++round) {
     const uint32_t local = round * per_round + (threadIdx.x >> lg_log2);
     const uint64_t gid = base + local;
@@ -421,6 +432,8 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
       out_W[gid] = s_W[threadIdx.x];
     }
   }
+  __syncthreads();
+  }
 }
 
 static uint32_t est_lg_log2(const Geo& geo) {
@@ -430,13 +443,11 @@ static uint32_t est_lg_log2(const Geo& geo) {
   return l;
 }
 
-hipError_t launch_estimate(const uint32_t* csip, uint64_t n_max, const Counters* cnt,
-                           const uint64_t* bitmap, const uint64_t* act_now,
-                           const uint64_t* act_next, const double* up, const Geo& geo,
-                           uint8_t* cflags, const ReportPtrs& out, hipStream_t st) {
-  if (n_max == 0) return hipSuccess;
-  const uint64_t blocks = (n_max + kEstPerBlock - 1) / kEstPerBlock;
-  hipLaunchKernelGGL(k_estimate, dim3((uint32_t)blocks), dim3(kBlock), 0, st, csip, cnt, bitmap,
+hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
+                           const uint64_t* act_now, const uint64_t* act_next, const double* up,
+                           const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_estimate, dim3(2 * kPipeBlocks), dim3(kBlock), 0, st, csip, cnt, bitmap,
                      act_now, act_next, up, geo, est_lg_log2(geo), cflags, out.ip, out.est,
                      out.flags, out.U, out.W);
   return hipGetLastError();
@@ -454,46 +465,64 @@ __global__ __launch_bounds__(kBlock) void k_si_update(const uint32_t* __restrict
                                                      const uint8_t* __restrict__ cflags,
                                                      const Counters* __restrict__ cnt,
                                                      uint32_t* __restrict__ si_cnt, Geo geo) {
-  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= cnt->n_cand) return;
-  const uint32_t f = cflags[t];
-  const bool is_new = f & 4u, keep = f & 8u;
-  uint32_t delta;
-  if (is_new && keep) delta = 1u;                 // enters NCSIP_t
-  else if (!is_new && !keep) delta = 0xFFFFFFFFu;  // leaves: -1
-  else return;                                     // stays, or never counted
-  const uint32_t a = csip[t];
-  const uint32_t bit = hrange(mas(geo.h4, a), 16u);
-  for (uint32_t r = 0; r < geo.u; ++r)
-    atomicAdd(&si_cnt[si_slot(geo, r, hrange(mas(geo.rh[r], a), geo.v_re), bit)], delta);
+  const uint32_t n = cnt->n_cand;
+  for (uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+       t += (uint64_t)gridDim.x * kBlock) {
+    const uint32_t f = cflags[t];
+    const bool is_new = f & 4u, keep = f & 8u;
+    uint32_t delta;
+    if (is_new && keep) delta = 1u;                 // enters NCSIP_t
+    else if (!is_new && !keep) delta = 0xFFFFFFFFu;  // leaves: -1
+    else continue;                                   // stays, or never counted
+    const uint32_t a = csip[t];
+    const uint32_t bit = hrange(mas(geo.h4, a), 16u);
+    for (uint32_t r = 0; r < geo.u; ++r)
+      atomicAdd(&si_cnt[si_slot(geo, r, hrange(mas(geo.rh[r], a), geo.v_re), bit)], delta);
+  }
 }
 
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
-                            uint64_t n_max, uint32_t* si_cnt, const Geo& geo, hipStream_t st) {
-  if (n_max == 0) return hipSuccess;
-  const uint64_t blocks = (n_max + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(k_si_update, dim3((uint32_t)blocks), dim3(kBlock), 0, st, csip, cflags, cnt,
+                            uint32_t* si_cnt, const Geo& geo, hipStream_t st) {
+  hipLaunchKernelGGL(k_si_update, dim3(kPipeBlocks), dim3(kBlock), 0, st, csip, cflags, cnt,
                      si_cnt, geo);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ status
-// The slice's counters, Eq8 and the row fills, written into the pinned host
-// status block so the host reads everything after one stream wait.
+// The slice's counters, Eq8 and the row fills go into the pinned host status
+// block, so the host reads everything after one wait.  Then the state moves
+// to the next slice: |NCSIP_t| is carried, the stamp code advances, and the
+// slice's counters (and the sampled-source count of its parity, which the
+// scans of the slice after next reuse) are cleared.
 
-__global__ void k_status(const Counters* __restrict__ cnt, const double* __restrict__ up,
+__global__ void k_status(Counters* __restrict__ cnt, uint32_t* __restrict__ tcount,
+                         const double* __restrict__ up,
                          const unsigned long long* __restrict__ row_fill, uint32_t u,
-                         HostStatus* __restrict__ out) {
+                         PipeState* __restrict__ ps, HostStatus* __restrict__ out) {
   if (blockIdx.x != 0) return;
   const uint32_t t = threadIdx.x;
-  if (t < sizeof(Counters) / 4) ((uint32_t*)&out->cnt)[t] = ((const uint32_t*)cnt)[t];
+  Counters c = *cnt;
+  c.touched = *tcount;
+  if (t < sizeof(Counters) / 4) ((uint32_t*)&out->cnt)[t] = ((const uint32_t*)&c)[t];
   if (t < u) out->row_fill[t] = row_fill[t];
-  if (t == 0) out->up = *up;
+  if (t == 0) {
+    out->up = *up;
+    out->slice = ps->slice;
+  }
+  __syncthreads();
+  if (t == 0) {
+    ps->n_ncsip = c.n_keep;
+    ps->slice = ps->slice + 1;
+    ps->now = (uint32_t)(ps->slice % kStampPeriod) + 1u;
+    *tcount = 0u;
+  }
+  if (t < sizeof(Counters) / 4) ((uint32_t*)cnt)[t] = 0u;
 }
 
-hipError_t launch_status(const Counters* cnt, const double* up, const unsigned long long* row_fill,
-                         uint32_t u, HostStatus* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, cnt, up, row_fill, u, out);
+hipError_t launch_status(Counters* cnt, uint32_t* tcount, const double* up,
+                         const unsigned long long* row_fill, uint32_t u, PipeState* ps,
+                         HostStatus* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, cnt, tcount, up, row_fill, u, ps, out);
   return hipGetLastError();
 }
 

@@ -1,16 +1,20 @@
 // Host runtime of the gfx950 SRLA library: the C ABI of include/srla.h.
 //
 // One monitor = one SEA (Section 4.1) resident in device memory plus the
-// buffers of the end-of-slice pipeline.  srla_scan enqueues Algorithm 2 for
-// a batch of pairs; srla_estimate runs, on the same stream,
-//   sweep    -> |LDR(i)|^k, the LE activity bitmap, the SRE activity bitmaps
+// buffers of the end-of-slice pipeline.  srla_scan enqueues Algorithm 2 on
+// the scan stream (the caller's).  srla_close_slice enqueues, on the
+// library's pipeline stream, after the slice's last scan:
+//   snapshot -> |LDR(i)|^k, the LE activity bitmap, the SRE activity bitmaps
+//               (the end-of-slice state of every DR; scans of the next slice
+//               may start as soon as this is done)
 //   finalize -> sort + unique of the slice's sampled sources, candidate check
 //   merge    -> CSIP_t = NCSIP_{t-1} u N_t, ascending
 //   estimate -> Eq8, then per candidate |ULE|^k, |URE|^k, Eq9, Algorithm 3's
 //               test; the report goes straight into pinned host memory
-//   slide    -> NCSIP_t compacted, SI counters updated; t <- t + 1
-// with one host wait early on (the sampled-source count sizes the sort) and
-// one at the end.
+//   slide    -> NCSIP_t compacted, SI counters updated, state advanced
+// Every kernel reads its counts from device memory, so nothing waits for the
+// host in between, and the two phases can be replayed as HIP graphs (one
+// pair per slice parity).  srla_wait_report waits for the pipeline's end.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -62,7 +66,8 @@ bool config_ok(const srla_config_t* c) {
   if (c->window_slices < 1 || c->window_slices > 32767) return false;
   if (c->threshold < 1) return false;
   if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
-  if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD)) != 0) return false;
+  if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH)) != 0)
+    return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   if (le / g.u / g.g_le != g.v_le || re / g.u / g.g != g.v_re) return false;
@@ -71,6 +76,9 @@ bool config_ok(const srla_config_t* c) {
 }
 
 enum Stage { ST_SCAN, ST_SWEEP, ST_FINALIZE, ST_ESTIMATE, ST_SLIDE, ST_REPORT, ST_N };
+
+// the end-of-slice pipeline's two phases
+enum Phase { PH_SNAPSHOT = 0, PH_FINISH = 1 };
 
 struct TimedSpan {
   int stage;
@@ -84,9 +92,10 @@ constexpr uint64_t kStageChunk = 1ull << 22;  // pairs per host-ingest chunk
 struct srla_monitor {
   srla_config_t cfg{};
   Geo geo{};
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // scans
+  hipStream_t pipe = nullptr;    // end-of-slice pipeline (library-owned)
   bool own_stream = false;
-  uint64_t slice = 0;
+  uint64_t slice = 0;            // open slice
   bool poisoned = false;
   std::string err;
 
@@ -101,29 +110,28 @@ struct srla_monitor {
   unsigned long long* row_fill = nullptr;
   double* up = nullptr;
   Counters* cnt = nullptr;
+  PipeState* ps = nullptr;
+  uint32_t* tcount = nullptr;    // [2] sampled-source counts by slice parity
 
-  // sources sampled in the open slice
-  uint32_t* touched = nullptr;
+  // sources sampled, by slice parity, and the shared sort/finalize scratch
+  uint32_t* touched[2] = {nullptr, nullptr};
   uint32_t* touched_tmp = nullptr;
   uint8_t* mark = nullptr;
   uint32_t* news = nullptr;
   uint32_t* hist = nullptr;
   uint32_t* blockw = nullptr;
   uint64_t touched_cap = 0;
-  uint64_t slice_pairs = 0;
+  uint64_t slice_pairs[2] = {0, 0};
 
-  // candidate lists
+  // candidate lists: slice parity p merges carried[p] and compacts into carried[p^1]
   uint32_t* csip = nullptr;
-  uint32_t* ncsip = nullptr;
-  uint32_t* ncsip_next = nullptr;
+  uint32_t* carried[2] = {nullptr, nullptr};
   uint8_t* cflags = nullptr;
   uint32_t* cblockw = nullptr;
   uint64_t cap = 0;
-  uint32_t n_ncsip = 0;
 
   // pinned host side (the report arrays and the status block are written by
   // kernels through their device-visible addresses)
-  Counters* h_cnt = nullptr;
   HostStatus* h_status = nullptr;
   HostStatus* d_status = nullptr;
   uint64_t* h_row_fill64 = nullptr;
@@ -133,7 +141,17 @@ struct srla_monitor {
   uint32_t* h_U = nullptr;
   uint8_t* h_W = nullptr;
   ReportPtrs d_report{};
-  hipEvent_t ev_count = nullptr;
+
+  // ordering between the two streams
+  hipEvent_t ev_scan = nullptr;   // after the closing slice's last scan
+  hipEvent_t ev_snap = nullptr;   // after its snapshot phase
+  hipEvent_t ev_done = nullptr;   // after its whole pipeline
+  bool snap_pending = false;      // the open slice's scans still have to wait ev_snap
+  bool report_pending = false;    // a closed slice whose report is not collected
+
+  // replayable pipeline: [phase][parity]
+  bool use_graph = false;
+  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 
   // host-input ring: two pinned chunks, two device chunks
   uint32_t* h_stage[2] = {nullptr, nullptr};
@@ -197,7 +215,7 @@ void hfree(void* p) {
 }
 
 uint64_t candidate_bytes(uint64_t cap) {
-  // csip, ncsip, ncsip_next (u32), cflags (u8), block words
+  // csip, two carried lists (u32), cflags (u8), block words
   return cap * (4 + 4 + 4 + 1) + 4 * compact_block_words(cap);
 }
 
@@ -214,18 +232,18 @@ hipEvent_t pooled_event(srla_monitor* m) {
   return e;
 }
 
-void span_begin(srla_monitor* m, hipEvent_t* a) {
+void span_begin(srla_monitor* m, hipStream_t st, hipEvent_t* a) {
   *a = nullptr;
   if (!m->timing) return;
   *a = pooled_event(m);
-  if (*a) (void)hipEventRecord(*a, m->stream);
+  if (*a) (void)hipEventRecord(*a, st);
 }
 
-void span_end(srla_monitor* m, int stage, hipEvent_t a) {
+void span_end(srla_monitor* m, hipStream_t st, int stage, hipEvent_t a) {
   if (!m->timing || !a) return;
   hipEvent_t b = pooled_event(m);
   if (!b) { m->ev_pool.push_back(a); return; }
-  (void)hipEventRecord(b, m->stream);
+  (void)hipEventRecord(b, st);
   m->spans.push_back({stage, a, b});
 }
 
@@ -240,45 +258,131 @@ void collect_spans(srla_monitor* m) {
   m->spans.clear();
 }
 
-// Grows the per-slice sampled-source buffers to hold `need` entries.
+void drop_graphs(srla_monitor* m) {
+  for (auto& ph : m->graph)
+    for (auto& g : ph)
+      if (g) {
+        (void)hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+}
+
+// Grows the sampled-source buffers (both parities) to hold `need` entries.
 int reserve_touched(srla_monitor* m, uint64_t need) {
   if (need <= m->touched_cap) return SRLA_OK;
   if (need > 0xFFFFFFF0ull) return fail(m, SRLA_E_NOMEM, "slice holds more than 2^32 pairs");
   uint64_t cap = std::max<uint64_t>(need, m->touched_cap ? 2 * m->touched_cap : (1u << 20));
   cap = std::min<uint64_t>(cap, 0xFFFFFFF0ull);
-  uint32_t *t = nullptr, *tt = nullptr, *nw = nullptr, *h = nullptr, *bw = nullptr;
+  uint32_t *t0 = nullptr, *t1 = nullptr, *tt = nullptr, *nw = nullptr, *h = nullptr,
+           *bw = nullptr;
   uint8_t* mk = nullptr;
-  if (dalloc(&t, cap) != hipSuccess || dalloc(&tt, cap) != hipSuccess ||
-      dalloc(&nw, cap) != hipSuccess || dalloc(&mk, cap) != hipSuccess ||
-      dalloc(&h, radix_hist_words(cap)) != hipSuccess ||
+  if (dalloc(&t0, cap) != hipSuccess || dalloc(&t1, cap) != hipSuccess ||
+      dalloc(&tt, cap) != hipSuccess || dalloc(&nw, cap) != hipSuccess ||
+      dalloc(&mk, cap) != hipSuccess || dalloc(&h, radix_hist_words(cap)) != hipSuccess ||
       dalloc(&bw, compact_block_words(cap)) != hipSuccess) {
-    dfree(t); dfree(tt); dfree(nw); dfree(mk); dfree(h); dfree(bw);
+    dfree(t0); dfree(t1); dfree(tt); dfree(nw); dfree(mk); dfree(h); dfree(bw);
     (void)hipGetLastError();
     return fail(m, SRLA_E_NOMEM, "cannot grow the sampled-source buffers");
   }
-  if (m->touched && m->slice_pairs) {
-    // entries appended so far in this slice (at most slice_pairs of them)
-    HIP_TRY(m, hipMemcpyAsync(t, m->touched, m->slice_pairs * sizeof(uint32_t),
-                              hipMemcpyDeviceToDevice, m->stream));
-  }
+  // both streams idle: the pending pipeline may still read the other parity
   HIP_TRY(m, hipStreamSynchronize(m->stream));
-  dfree(m->touched); dfree(m->touched_tmp); dfree(m->news); dfree(m->mark);
-  dfree(m->hist); dfree(m->blockw);
-  m->touched = t; m->touched_tmp = tt; m->news = nw; m->mark = mk; m->hist = h; m->blockw = bw;
+  HIP_TRY(m, hipStreamSynchronize(m->pipe));
+  uint32_t* fresh[2] = {t0, t1};
+  for (int p = 0; p < 2; ++p) {
+    if (m->touched[p] && m->slice_pairs[p])
+      HIP_TRY(m, hipMemcpy(fresh[p], m->touched[p], m->slice_pairs[p] * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice));
+    dfree(m->touched[p]);
+    m->touched[p] = fresh[p];
+  }
+  dfree(m->touched_tmp); dfree(m->news); dfree(m->mark); dfree(m->hist); dfree(m->blockw);
+  m->touched_tmp = tt; m->news = nw; m->mark = mk; m->hist = h; m->blockw = bw;
   m->touched_cap = cap;
+  drop_graphs(m);   // they hold the old buffers
+  return SRLA_OK;
+}
+
+// Enqueues one phase of the end-of-slice pipeline of parity p on the
+// pipeline stream.  Every argument is fixed per (phase, parity), so the
+// sequence can also be recorded once into a graph.
+hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
+  const Geo& geo = m->geo;
+  hipStream_t st = m->pipe;
+  hipError_t e = hipSuccess;
+  if (phase == PH_SNAPSHOT) {
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st);
+    if (e == hipSuccess) e = launch_sweep_le(m->le, m->bitmap, m->row_fill, geo, m->ps, st);
+    if (e == hipSuccess)
+      e = launch_sweep_re(m->re, m->n_re, m->act_now, m->act_next, geo, m->ps, st);
+    if (e == hipSuccess) e = launch_union_prob(m->row_fill, geo, m->up, st);
+    return e;
+  }
+  uint32_t* tc = m->tcount + p;
+  hipEvent_t ta = nullptr;
+  const bool spans = !m->use_graph;
+  if (spans) span_begin(m, st, &ta);
+  if (e == hipSuccess)
+    e = radix_sort_u32(m->touched[p], m->touched_tmp, tc, m->touched_cap, m->hist, st);
+  if (e == hipSuccess)
+    e = launch_finalize(m->touched[p], tc, m->act_now, m->si_cnt, geo, m->mark, m->cnt, st);
+  if (e == hipSuccess)
+    e = compact_u32(m->mark, 1u, m->touched[p], tc, m->touched_cap, m->news, &m->cnt->n_new,
+                    m->blockw, st);
+  if (spans) span_end(m, st, ST_FINALIZE, ta);
+  if (spans) span_begin(m, st, &ta);
+  if (e == hipSuccess)
+    e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
+  if (e == hipSuccess)
+    e = launch_estimate(m->csip, m->cnt, m->bitmap, m->act_now, m->act_next, m->up, geo,
+                        m->cflags, m->d_report, st);
+  if (spans) span_end(m, st, ST_ESTIMATE, ta);
+  if (spans) span_begin(m, st, &ta);
+  if (e == hipSuccess)
+    e = compact_u32(m->cflags, 8u, m->csip, &m->cnt->n_cand, m->cap, m->carried[p ^ 1],
+                    &m->cnt->n_keep, m->cblockw, st);
+  if (e == hipSuccess) e = launch_si_update(m->csip, m->cflags, m->cnt, m->si_cnt, geo, st);
+  if (e == hipSuccess)
+    e = launch_status(m->cnt, tc, m->up, m->row_fill, geo.u, m->ps, m->d_status, st);
+  if (spans) span_end(m, st, ST_SLIDE, ta);
+  return e;
+}
+
+// Runs one phase: directly, or through its graph (recorded on first use).
+int run_phase(srla_monitor* m, int phase, int p) {
+  if (!m->use_graph) {
+    HIP_TRY(m, enqueue_phase(m, phase, p));
+    return SRLA_OK;
+  }
+  hipGraphExec_t& exec = m->graph[phase][p];
+  if (!exec) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(m, hipStreamBeginCapture(m->pipe, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = enqueue_phase(m, phase, p);
+    const hipError_t ec = hipStreamEndCapture(m->pipe, &g);
+    HIP_TRY(m, e);
+    HIP_TRY(m, ec);
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(m, ei);
+  }
+  HIP_TRY(m, hipGraphLaunch(exec, m->pipe));
   return SRLA_OK;
 }
 
 void release(srla_monitor* m) {
   if (!m) return;
   if (m->stream) (void)hipStreamSynchronize(m->stream);
+  if (m->pipe) (void)hipStreamSynchronize(m->pipe);
   collect_spans(m);
+  drop_graphs(m);
   dfree(m->le); dfree(m->re); dfree(m->si_cnt); dfree(m->bitmap); dfree(m->act_now);
-  dfree(m->act_next); dfree(m->row_fill); dfree(m->up); dfree(m->cnt);
-  dfree(m->touched); dfree(m->touched_tmp); dfree(m->mark); dfree(m->news);
-  dfree(m->hist); dfree(m->blockw);
-  dfree(m->csip); dfree(m->ncsip); dfree(m->ncsip_next); dfree(m->cflags); dfree(m->cblockw);
-  hfree(m->h_cnt); hfree(m->h_status); hfree(m->h_ip); hfree(m->h_est); hfree(m->h_flags);
+  dfree(m->act_next); dfree(m->row_fill); dfree(m->up); dfree(m->cnt); dfree(m->ps);
+  dfree(m->tcount);
+  dfree(m->touched[0]); dfree(m->touched[1]); dfree(m->touched_tmp); dfree(m->mark);
+  dfree(m->news); dfree(m->hist); dfree(m->blockw);
+  dfree(m->csip); dfree(m->carried[0]); dfree(m->carried[1]); dfree(m->cflags);
+  dfree(m->cblockw);
+  hfree(m->h_status); hfree(m->h_ip); hfree(m->h_est); hfree(m->h_flags);
   hfree(m->h_U); hfree(m->h_W);
   delete[] m->h_row_fill64;
   for (int i = 0; i < 2; ++i) {
@@ -287,7 +391,10 @@ void release(srla_monitor* m) {
     if (m->stage_ev[i]) (void)hipEventDestroy(m->stage_ev[i]);
   }
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
-  if (m->ev_count) (void)hipEventDestroy(m->ev_count);
+  if (m->ev_scan) (void)hipEventDestroy(m->ev_scan);
+  if (m->ev_snap) (void)hipEventDestroy(m->ev_snap);
+  if (m->ev_done) (void)hipEventDestroy(m->ev_done);
+  if (m->pipe) (void)hipStreamDestroy(m->pipe);
   if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
   delete m;
 }
@@ -303,7 +410,8 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   const uint64_t si = (uint64_t)g.u * g.v_re;
   return 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
-         8 * g.u + 8 + sizeof(Counters) + candidate_bytes(cfg->max_candidates);
+         8 * g.u + 8 + sizeof(Counters) + sizeof(PipeState) + 8 +
+         candidate_bytes(cfg->max_candidates);
 }
 
 int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out) {
@@ -314,6 +422,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->cfg = *cfg;
   m->timing = (cfg->flags & SRLA_CFG_TIMING) != 0;
   m->xcd_scan = (cfg->flags & SRLA_CFG_SCAN_XCD) != 0;
+  m->use_graph = (cfg->flags & SRLA_CFG_GRAPH) != 0;
 
   const srla_geometry_t& g = cfg->geom;
   Geo& geo = m->geo;
@@ -352,6 +461,10 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     }
     m->own_stream = true;
   }
+  if (hipStreamCreateWithFlags(&m->pipe, hipStreamNonBlocking) != hipSuccess) {
+    release(m);
+    return SRLA_E_DEVICE;
+  }
   m->n_le = (uint64_t)g.u * g.v_le * g.g_le;
   m->n_re = (uint64_t)g.u * g.v_re * g.g;
   m->n_si = (uint64_t)g.u * g.v_re;
@@ -365,12 +478,13 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!rc) nomem(dalloc(&m->row_fill, g.u));
   if (!rc) nomem(dalloc(&m->up, 1));
   if (!rc) nomem(dalloc(&m->cnt, 1));
+  if (!rc) nomem(dalloc(&m->ps, 1));
+  if (!rc) nomem(dalloc(&m->tcount, 2));
   if (!rc) nomem(dalloc(&m->csip, m->cap));
-  if (!rc) nomem(dalloc(&m->ncsip, m->cap));
-  if (!rc) nomem(dalloc(&m->ncsip_next, m->cap));
+  if (!rc) nomem(dalloc(&m->carried[0], m->cap));
+  if (!rc) nomem(dalloc(&m->carried[1], m->cap));
   if (!rc) nomem(dalloc(&m->cflags, m->cap));
   if (!rc) nomem(dalloc(&m->cblockw, compact_block_words(m->cap)));
-  if (!rc) nomem(halloc(&m->h_cnt, 1));
   if (!rc) nomem(halloc(&m->h_status, 1));
   if (!rc) nomem(halloc(&m->h_ip, m->cap));
   if (!rc) nomem(halloc(&m->h_est, m->cap));
@@ -388,18 +502,26 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
               dev_view(m->h_U, &m->d_report.U) != hipSuccess ||
               dev_view(m->h_W, &m->d_report.W) != hipSuccess))
     rc = SRLA_E_DEVICE;
-  if (!rc && hipEventCreateWithFlags(&m->ev_count, hipEventDisableTiming) != hipSuccess)
+  if (!rc && (hipEventCreateWithFlags(&m->ev_scan, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&m->ev_snap, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&m->ev_done, hipEventDisableTiming) != hipSuccess))
     rc = SRLA_E_DEVICE;
   if (rc) {
     release(m);
     return rc;
   }
-  // DRinit for every DR (stamp 0 = never set), SI = 0, counters = 0
+  // DRinit for every DR (stamp 0 = never set), SI = 0, counters = 0, slice 0
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->le, 0u, m->n_le / 2, m->stream);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->re, 0u, (m->n_re + 8) / 2, m->stream);
   if (e == hipSuccess) e = launch_fill_u32(m->si_cnt, 0u, 16 * m->n_si, m->stream);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->cnt, 0u, sizeof(Counters) / 4, m->stream);
+  if (e == hipSuccess) e = launch_fill_u32(m->tcount, 0u, 2, m->stream);
+  if (e == hipSuccess) {
+    PipeState ps0{};
+    ps0.now = stamp_code(0);
+    e = hipMemcpyAsync(m->ps, &ps0, sizeof(ps0), hipMemcpyHostToDevice, m->stream);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
   if (e != hipSuccess) {
     release(m);
@@ -418,16 +540,22 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
   if (n == 0) return SRLA_OK;
   if (!pairs) return fail(m, SRLA_E_INVAL, "pairs is NULL");
-  int rc = reserve_touched(m, m->slice_pairs + n);
+  const int p = (int)(m->slice & 1);
+  int rc = reserve_touched(m, m->slice_pairs[p] + n);
   if (rc) return rc;
+  if (m->snap_pending) {
+    // the previous slice's DRs must be snapshotted before this slice stamps them
+    HIP_TRY(m, hipStreamWaitEvent(m->stream, m->ev_snap, 0));
+    m->snap_pending = false;
+  }
   const uint16_t code = stamp_code(m->slice);
   if (on_device) {
     hipEvent_t a;
-    span_begin(m, &a);
-    HIP_TRY(m, launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched, m->cnt, m->xcd_scan,
-                           m->stream));
-    span_end(m, ST_SCAN, a);
-    m->slice_pairs += n;
+    span_begin(m, m->stream, &a);
+    HIP_TRY(m, launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p], m->tcount + p,
+                           m->xcd_scan, m->stream));
+    span_end(m, m->stream, ST_SCAN, a);
+    m->slice_pairs[p] += n;
     m->scan_launches++;
     m->scan_pairs += n;
     return SRLA_OK;
@@ -454,78 +582,54 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     HIP_TRY(m, hipEventRecord(m->stage_ev[b], m->stream));
     m->stage_busy[b] = true;
     hipEvent_t a;
-    span_begin(m, &a);
-    HIP_TRY(m, launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched, m->cnt,
-                           m->xcd_scan, m->stream));
-    span_end(m, ST_SCAN, a);
-    m->slice_pairs += cnt;
+    span_begin(m, m->stream, &a);
+    HIP_TRY(m, launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched[p],
+                           m->tcount + p, m->xcd_scan, m->stream));
+    span_end(m, m->stream, ST_SCAN, a);
+    m->slice_pairs[p] += cnt;
     m->scan_launches++;
     m->scan_pairs += cnt;
   }
   return SRLA_OK;
 }
 
-int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
+int srla_close_slice(srla_monitor_t* m) {
+  if (!m) return SRLA_E_INVAL;
+  if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
+  if (m->report_pending)
+    return fail(m, SRLA_E_STATE, "the previous slice's report has not been collected");
+  const int p = (int)(m->slice & 1);
+  if (m->snap_pending) {
+    // an empty slice: keep the stream order snapshot -> scans -> snapshot
+    HIP_TRY(m, hipStreamWaitEvent(m->stream, m->ev_snap, 0));
+    m->snap_pending = false;
+  }
+  HIP_TRY(m, hipEventRecord(m->ev_scan, m->stream));
+  HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_scan, 0));
+  hipEvent_t ta;
+  span_begin(m, m->pipe, &ta);
+  int rc = run_phase(m, PH_SNAPSHOT, p);
+  if (rc) return rc;
+  span_end(m, m->pipe, ST_SWEEP, ta);
+  HIP_TRY(m, hipEventRecord(m->ev_snap, m->pipe));
+  m->snap_pending = true;
+  if (m->use_graph) span_begin(m, m->pipe, &ta);
+  rc = run_phase(m, PH_FINISH, p);
+  if (rc) return rc;
+  if (m->use_graph) span_end(m, m->pipe, ST_ESTIMATE, ta);
+  HIP_TRY(m, hipEventRecord(m->ev_done, m->pipe));
+  m->report_pending = true;
+  m->slice++;
+  m->slice_pairs[m->slice & 1] = 0;
+  return SRLA_OK;
+}
+
+int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
   if (!m || !out) return m ? fail(m, SRLA_E_INVAL, "out is NULL") : SRLA_E_INVAL;
   if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
-  const uint16_t now = stamp_code(m->slice);
-  const Geo& geo = m->geo;
-  hipStream_t st = m->stream;
-  hipEvent_t ta;
-
-  // the sampled-source count, fetched while the sweeps run
-  HIP_TRY(m, hipMemcpyAsync(m->h_cnt, m->cnt, sizeof(Counters), hipMemcpyDeviceToHost, st));
-  HIP_TRY(m, hipEventRecord(m->ev_count, st));
-
-  span_begin(m, &ta);
-  HIP_TRY(m, launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st));
-  HIP_TRY(m, launch_sweep_le(m->le, m->bitmap, m->row_fill, geo, now, st));
-  HIP_TRY(m, launch_sweep_re(m->re, m->n_re, m->act_now, m->act_next, geo, now, st));
-  HIP_TRY(m, launch_union_prob(m->row_fill, geo, m->up, st));
-  span_end(m, ST_SWEEP, ta);
-
-  HIP_TRY(m, hipEventSynchronize(m->ev_count));
-  const uint64_t n_raw = m->h_cnt->touched;
-  if (n_raw > m->slice_pairs) {
-    m->poisoned = true;
-    return fail(m, SRLA_E_DEVICE, "sampled-source count exceeds the pairs scanned");
-  }
-
-  // finalize: sort + unique the sampled sources, candidate check, N_t
-  span_begin(m, &ta);
-  uint32_t* sorted = m->touched;
-  if (n_raw > 0) {
-    HIP_TRY(m, radix_sort_u32(m->touched, m->touched_tmp, n_raw, m->hist, &sorted, st));
-    HIP_TRY(m, launch_finalize(sorted, n_raw, m->act_now, m->si_cnt, geo, m->mark, m->cnt, st));
-    HIP_TRY(m, compact_u32(m->mark, 1u, sorted, &m->cnt->touched, n_raw, m->news,
-                           &m->cnt->n_new, m->blockw, st));
-  }
-  span_end(m, ST_FINALIZE, ta);
-
-  // merge + per-candidate estimate, written into the pinned report buffers
-  span_begin(m, &ta);
-  const uint32_t n_old = m->n_ncsip;
-  uint64_t n_max = (uint64_t)n_old + n_raw;
-  if (n_max > m->cap) n_max = m->cap;
-  HIP_TRY(m, launch_merge(m->ncsip, n_old, m->news, n_raw, m->cnt, m->cap, m->csip, m->cflags, st));
-  HIP_TRY(m, launch_estimate(m->csip, n_max, m->cnt, m->bitmap, m->act_now, m->act_next, m->up,
-                             geo, m->cflags, m->d_report, st));
-  span_end(m, ST_ESTIMATE, ta);
-
-  // Algorithm 3: carried list compacted in order, SI counters updated
-  span_begin(m, &ta);
-  HIP_TRY(m, compact_u32(m->cflags, 8u, m->csip, &m->cnt->n_cand, n_max, m->ncsip_next,
-                         &m->cnt->n_keep, m->cblockw, st));
-  HIP_TRY(m, launch_si_update(m->csip, m->cflags, m->cnt, n_max, m->si_cnt, geo, st));
-  span_end(m, ST_SLIDE, ta);
-
-  span_begin(m, &ta);
-  HIP_TRY(m, launch_status(m->cnt, m->up, m->row_fill, geo.u, m->d_status, st));
-  // the next slice starts with empty counters
-  HIP_TRY(m, launch_fill_u32((uint32_t*)m->cnt, 0u, sizeof(Counters) / 4, st));
-  span_end(m, ST_REPORT, ta);
-  HIP_TRY(m, hipStreamSynchronize(st));
-
+  if (!m->report_pending) return fail(m, SRLA_E_STATE, "no closed slice is waiting");
+  HIP_TRY(m, hipEventSynchronize(m->ev_done));
+  m->report_pending = false;
   const HostStatus& hs = *m->h_status;
   const Counters c = hs.cnt;
   if (c.overflow) {
@@ -533,17 +637,12 @@ int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
     collect_spans(m);
     return fail(m, SRLA_E_CAPACITY, "candidate list exceeds max_candidates");
   }
-  std::swap(m->ncsip, m->ncsip_next);
-  m->n_ncsip = c.n_keep;
-  const uint64_t closed = m->slice;
-  m->slice++;
-  m->slice_pairs = 0;
   m->estimates++;
   if (m->timing) collect_spans(m);
-
+  const Geo& geo = m->geo;
   for (uint32_t i = 0; i < geo.u; ++i) m->h_row_fill64[i] = hs.row_fill[i];
-  out->slice = closed;
-  out->window_full = closed >= (uint64_t)(geo.k - 1) ? 1u : 0u;
+  out->slice = hs.slice;
+  out->window_full = hs.slice >= (uint64_t)(geo.k - 1) ? 1u : 0u;
   out->n = c.n_cand;
   out->ip = m->h_ip;
   out->est = m->h_est;
@@ -557,14 +656,21 @@ int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
   return SRLA_OK;
 }
 
+int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
+  if (!m || !out) return m ? fail(m, SRLA_E_INVAL, "out is NULL") : SRLA_E_INVAL;
+  const int rc = srla_close_slice(m);
+  if (rc) return rc;
+  return srla_wait_report(m, out);
+}
+
 int srla_dump_state(srla_monitor_t* m, int which, uint16_t* host_out, uint64_t cells) {
   if (!m || !host_out) return m ? fail(m, SRLA_E_INVAL, "host_out is NULL") : SRLA_E_INVAL;
+  HIP_TRY(m, hipStreamSynchronize(m->stream));
+  HIP_TRY(m, hipStreamSynchronize(m->pipe));
   if (which == SRLA_DUMP_SI) {
     if (cells != m->n_si) return fail(m, SRLA_E_INVAL, "cells does not match the array size");
     std::vector<uint32_t> c(16 * m->n_si);
-    HIP_TRY(m, hipMemcpyAsync(c.data(), m->si_cnt, c.size() * 4, hipMemcpyDeviceToHost,
-                              m->stream));
-    HIP_TRY(m, hipStreamSynchronize(m->stream));
+    HIP_TRY(m, hipMemcpy(c.data(), m->si_cnt, c.size() * 4, hipMemcpyDeviceToHost));
     for (uint64_t i = 0; i < m->n_si; ++i) {
       uint16_t w = 0;
       for (int b = 0; b < 16; ++b)
@@ -579,8 +685,7 @@ int srla_dump_state(srla_monitor_t* m, int which, uint16_t* host_out, uint64_t c
   else if (which == SRLA_DUMP_RE) { src = m->re; n = m->n_re; }
   else return fail(m, SRLA_E_INVAL, "unknown state array");
   if (cells != n) return fail(m, SRLA_E_INVAL, "cells does not match the array size");
-  HIP_TRY(m, hipMemcpyAsync(host_out, src, n * 2, hipMemcpyDeviceToHost, m->stream));
-  HIP_TRY(m, hipStreamSynchronize(m->stream));
+  HIP_TRY(m, hipMemcpy(host_out, src, n * 2, hipMemcpyDeviceToHost));
   const int32_t now = stamp_code(m->slice);
   for (uint64_t i = 0; i < n; ++i) {
     const uint16_t c = host_out[i];
@@ -595,6 +700,7 @@ int srla_dump_state(srla_monitor_t* m, int which, uint16_t* host_out, uint64_t c
 int srla_timings(srla_monitor_t* m, srla_timings_t* out, int reset) {
   if (!m || !out) return SRLA_E_INVAL;
   HIP_TRY(m, hipStreamSynchronize(m->stream));
+  HIP_TRY(m, hipStreamSynchronize(m->pipe));
   collect_spans(m);
   out->scan_ms = m->acc_ms[ST_SCAN];
   out->scan_launches = m->scan_launches;

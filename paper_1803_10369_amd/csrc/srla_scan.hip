@@ -25,7 +25,7 @@ __device__ __forceinline__ void scan_one(uint32_t a, uint32_t b, bool valid, con
                                          uint16_t code, uint16_t* __restrict__ le,
                                          uint16_t* __restrict__ re,
                                          uint32_t* __restrict__ touched,
-                                         Counters* __restrict__ cnt) {
+                                         uint32_t* __restrict__ tcount) {
   const uint32_t nu = U > 0 ? (uint32_t)U : geo.u;
   bool sampled = false;
   if (valid) {
@@ -52,7 +52,7 @@ __device__ __forceinline__ void scan_one(uint32_t a, uint32_t b, bool valid, con
   if (mask != 0ull) {
     const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
     uint32_t base = 0;
-    if (__lane_id() == leader) base = atomicAdd(&cnt->touched, (uint32_t)__popcll(mask));
+    if (__lane_id() == leader) base = atomicAdd(tcount, (uint32_t)__popcll(mask));
     base = __shfl(base, (int)leader);
     if (sampled) touched[base + lane_rank(mask)] = a;
   }
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_flat(const uint32_t* __restrict
                                                 uint16_t* __restrict__ le,
                                                 uint16_t* __restrict__ re,
                                                 uint32_t* __restrict__ touched,
-                                                Counters* __restrict__ cnt) {
+                                                uint32_t* __restrict__ tcount) {
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
   uint32_t a[kScanSteps][2], b[kScanSteps][2];
   bool v[kScanSteps][2];
@@ -85,8 +85,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_flat(const uint32_t* __restrict
   }
 #pragma unroll
   for (int s = 0; s < kScanSteps; ++s) {
-    scan_one<U>(a[s][0], b[s][0], v[s][0], geo, code, le, re, touched, cnt);
-    scan_one<U>(a[s][1], b[s][1], v[s][1], geo, code, le, re, touched, cnt);
+    scan_one<U>(a[s][0], b[s][0], v[s][0], geo, code, le, re, touched, tcount);
+    scan_one<U>(a[s][1], b[s][1], v[s][1], geo, code, le, re, touched, tcount);
   }
 }
 
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_xcd(const uint32_t* __restrict_
                                                     uint16_t* __restrict__ le,
                                                     uint16_t* __restrict__ re,
                                                     uint32_t* __restrict__ touched,
-                                                    Counters* __restrict__ cnt) {
+                                                    uint32_t* __restrict__ tcount) {
   constexpr int kParts = U >= kXcds ? 1 : kXcds / U;      // tiles per XCD group
   constexpr int kRowsPerXcd = U >= kXcds ? U / kXcds : 1;
   const uint32_t xcd = blockIdx.x % kXcds;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_xcd(const uint32_t* __restrict_
         if (mask != 0ull) {
           const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
           uint32_t slot = 0;
-          if (__lane_id() == leader) slot = atomicAdd(&cnt->touched, (uint32_t)__popcll(mask));
+          if (__lane_id() == leader) slot = atomicAdd(tcount, (uint32_t)__popcll(mask));
           slot = __shfl(slot, (int)leader);
           if (sampled) touched[slot + lane_rank(mask)] = aa;
         }
@@ -165,48 +165,48 @@ __global__ __launch_bounds__(kBlock) void k_scan_xcd(const uint32_t* __restrict_
 template <int U>
 static hipError_t launch_scan_xcd(const uint32_t* pairs, uint64_t n, const Geo& geo,
                                   uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
-                                  Counters* cnt, hipStream_t st) {
+                                  uint32_t* tcount, hipStream_t st) {
   constexpr uint64_t kParts = U >= kXcds ? 1 : kXcds / U;
   const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
   const uint64_t blocks = kXcds * ((tiles + kParts - 1) / kParts);
   hipLaunchKernelGGL((k_scan_xcd<U>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n, geo,
-                     code, le, re, touched, cnt);
+                     code, le, re, touched, tcount);
   return hipGetLastError();
 }
 
 template <int U>
 static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
-                                uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
+                                uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
                                 hipStream_t st) {
   const uint64_t blocks = (n + kScanTile - 1) / kScanTile;
   const bool vec = ((uintptr_t)pairs & 15u) == 0;
   if (vec)
     hipLaunchKernelGGL((k_scan_flat<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
-                       geo, code, le, re, touched, cnt);
+                       geo, code, le, re, touched, tcount);
   else
     hipLaunchKernelGGL((k_scan_flat<U, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
-                       geo, code, le, re, touched, cnt);
+                       geo, code, le, re, touched, tcount);
   return hipGetLastError();
 }
 
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
-                       uint16_t* le, uint16_t* re, uint32_t* touched, Counters* cnt,
+                       uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
                        bool xcd_aware, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (xcd_aware && ((uintptr_t)pairs & 15u) == 0) {
     switch (geo.u) {
-      case 1: return launch_scan_xcd<1>(pairs, n, geo, code, le, re, touched, cnt, st);
-      case 2: return launch_scan_xcd<2>(pairs, n, geo, code, le, re, touched, cnt, st);
-      case 4: return launch_scan_xcd<4>(pairs, n, geo, code, le, re, touched, cnt, st);
-      case 8: return launch_scan_xcd<8>(pairs, n, geo, code, le, re, touched, cnt, st);
-      case 16: return launch_scan_xcd<16>(pairs, n, geo, code, le, re, touched, cnt, st);
+      case 1: return launch_scan_xcd<1>(pairs, n, geo, code, le, re, touched, tcount, st);
+      case 2: return launch_scan_xcd<2>(pairs, n, geo, code, le, re, touched, tcount, st);
+      case 4: return launch_scan_xcd<4>(pairs, n, geo, code, le, re, touched, tcount, st);
+      case 8: return launch_scan_xcd<8>(pairs, n, geo, code, le, re, touched, tcount, st);
+      case 16: return launch_scan_xcd<16>(pairs, n, geo, code, le, re, touched, tcount, st);
       default: break;
     }
   }
   switch (geo.u) {
-    case 4: return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, cnt, st);
-    case 8: return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, cnt, st);
-    default: return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, cnt, st);
+    case 4: return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, tcount, st);
+    case 8: return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, tcount, st);
+    default: return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, tcount, st);
   }
 }
 

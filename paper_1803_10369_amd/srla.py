@@ -20,6 +20,7 @@ SRLA_DUMP_LE, SRLA_DUMP_RE, SRLA_DUMP_SI = 0, 1, 2
 SRLA_FLAG_SUPER, SRLA_FLAG_SAT, SRLA_FLAG_NEW, SRLA_FLAG_KEEP = 1, 2, 4, 8
 SRLA_CFG_TIMING = 1
 SRLA_CFG_SCAN_XCD = 2
+SRLA_CFG_GRAPH = 4
 
 
 class srla_geometry_t(ctypes.Structure):
@@ -56,7 +57,8 @@ class srla_timings_t(ctypes.Structure):
 
 
 EXPORTS = ["srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
-           "srla_dump_state", "srla_timings", "srla_destroy", "srla_last_error"]
+           "srla_close_slice", "srla_wait_report", "srla_dump_state", "srla_timings",
+           "srla_destroy", "srla_last_error"]
 
 _lib = None
 
@@ -76,6 +78,10 @@ def lib():
         L.srla_scan.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_int]
         L.srla_estimate.restype = ctypes.c_int
         L.srla_estimate.argtypes = [vp, ctypes.POINTER(srla_report_t)]
+        L.srla_close_slice.restype = ctypes.c_int
+        L.srla_close_slice.argtypes = [vp]
+        L.srla_wait_report.restype = ctypes.c_int
+        L.srla_wait_report.argtypes = [vp, ctypes.POINTER(srla_report_t)]
         L.srla_dump_state.restype = ctypes.c_int
         L.srla_dump_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_uint64]
         L.srla_timings.restype = ctypes.c_int
@@ -112,6 +118,14 @@ def srla_scan(handle, pairs_ptr, n, on_device):
 
 def srla_estimate(handle, report):
     return lib().srla_estimate(handle, ctypes.byref(report))
+
+
+def srla_close_slice(handle):
+    return lib().srla_close_slice(handle)
+
+
+def srla_wait_report(handle, report):
+    return lib().srla_wait_report(handle, ctypes.byref(report))
 
 
 def srla_dump_state(handle, which, out_ptr, cells):
@@ -174,8 +188,9 @@ class Monitor:
     caller's current stream and kept alive for the monitor's stream."""
 
     def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22,
-                 timing=False, stream=None, scan_xcd=False):
-        flags = (SRLA_CFG_TIMING if timing else 0) | (SRLA_CFG_SCAN_XCD if scan_xcd else 0)
+                 timing=False, stream=None, scan_xcd=False, graph=False):
+        flags = ((SRLA_CFG_TIMING if timing else 0) | (SRLA_CFG_SCAN_XCD if scan_xcd else 0) |
+                 (SRLA_CFG_GRAPH if graph else 0))
         self.cfg = make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates, flags)
         self._h = None
         self.stream = stream if stream is not None else torch.cuda.Stream()
@@ -220,6 +235,16 @@ class Monitor:
     def estimate(self, copy=True):
         r = srla_report_t()
         self._check(srla_estimate(self._h, r))
+        return Report(r, self.cfg.geom.u, copy)
+
+    def close_slice(self):
+        """Closes the open slice without waiting (see srla_close_slice)."""
+        self._check(srla_close_slice(self._h))
+
+    def wait_report(self, copy=True):
+        """The report of the slice closed by close_slice()."""
+        r = srla_report_t()
+        self._check(srla_wait_report(self._h, r))
         return Report(r, self.cfg.geom.u, copy)
 
     def cells(self, which):

@@ -26,7 +26,8 @@ def P():
 def test_every_declared_symbol_is_exported(P):
     names = _declared_functions()
     assert set(names) == {"srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
-                          "srla_dump_state", "srla_timings", "srla_destroy", "srla_last_error"}
+                          "srla_close_slice", "srla_wait_report", "srla_dump_state",
+                          "srla_timings", "srla_destroy", "srla_last_error"}
     L = ctypes.CDLL(P.srla.LIB_PATH)
     for n in names:
         assert hasattr(L, n), n
@@ -81,7 +82,7 @@ def test_invalid_configs_are_rejected_without_a_device(P, bad):
 def test_bad_flags_and_capacity_rejected(P):
     cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, max_candidates=0)
     assert P.srla_create(cfg)[0] == -1
-    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=4)
+    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=8)
     assert P.srla_create(cfg)[0] == -1
 
 
@@ -104,6 +105,8 @@ def test_null_handles(P):
     assert L.srla_last_error(None) == b"no monitor"
     assert L.srla_scan(None, None, 0, 0) == -1
     assert L.srla_estimate(None, None) == -1
+    assert L.srla_close_slice(None) == -1
+    assert L.srla_wait_report(None, None) == -1
 
 
 def test_product_never_imports_the_oracle():

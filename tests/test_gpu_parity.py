@@ -24,8 +24,8 @@ def _gpu():
 
 
 def _run(stream, mon, slices, max_candidates=1 << 16, dump_every=1, split=None, host=False,
-         scan_xcd=False):
-    g = srla.Monitor(**mon, max_candidates=max_candidates, scan_xcd=scan_xcd)
+         scan_xcd=False, graph=False):
+    g = srla.Monitor(**mon, max_candidates=max_candidates, scan_xcd=scan_xcd, graph=graph)
     o = oracle.Monitor(**mon)
     for s in slices:
         pairs = stream.slice(s) if hasattr(stream, "slice") else stream(s)
@@ -46,10 +46,10 @@ def _run(stream, mon, slices, max_candidates=1 << 16, dump_every=1, split=None, 
     return rg
 
 
-@pytest.mark.parametrize("scan_xcd", [False, True])
-def test_tiny_workload_full_run(scan_xcd):
+@pytest.mark.parametrize("scan_xcd,graph", [(False, False), (True, False), (False, True)])
+def test_tiny_workload_full_run(scan_xcd, graph):
     stream, mon, n = workload("tiny")
-    r = _run(stream, mon, range(n), scan_xcd=scan_xcd)
+    r = _run(stream, mon, range(n), scan_xcd=scan_xcd, graph=graph)
     assert r.window_full and r.n > 0
 
 
@@ -90,11 +90,65 @@ SMALL = [
 
 
 @pytest.mark.parametrize("case", SMALL)
-@pytest.mark.parametrize("scan_xcd", [False, True])
-def test_small_geometries(case, scan_xcd):
+@pytest.mark.parametrize("scan_xcd,graph", [(False, False), (True, True)])
+def test_small_geometries(case, scan_xcd, graph):
     k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
     mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=1000 + k + u)
-    _run(_rand_stream(k + u, n, n_src, 3 * theta // 2), mon, range(slices), scan_xcd=scan_xcd)
+    _run(_rand_stream(k + u, n, n_src, 3 * theta // 2), mon, range(slices), scan_xcd=scan_xcd,
+         graph=graph)
+
+
+def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chunks=1):
+    """The next slice is scanned before the previous slice's report is taken."""
+    g = srla.Monitor(**mon, max_candidates=max_candidates, graph=graph)
+    o = oracle.Monitor(**mon)
+    expected = []
+    slices = list(slices)
+    for i, s in enumerate(slices):
+        pairs = stream.slice(s) if hasattr(stream, "slice") else stream(s)
+        step = -(-len(pairs) // chunks) if len(pairs) else 1
+        for lo in range(0, max(len(pairs), 1), step):
+            g.scan(to_device(pairs[lo:lo + step]))
+        o.scan(pairs)
+        expected.append(o.estimate())
+        if i > 0:
+            compare_reports(g.wait_report(), expected[i - 1], mon["theta"], "slice %d" % (s - 1))
+        g.close_slice()
+    compare_reports(g.wait_report(), expected[-1], mon["theta"], "last slice")
+    compare_dumps(g, o, ctx="end")
+    g.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_streaming_form_matches_oracle(graph):
+    stream, mon, n = workload("tiny")
+    _run_streaming(stream, mon, range(n), graph=graph, chunks=3)
+
+
+@pytest.mark.parametrize("case", SMALL[:4])
+def test_streaming_small_geometries(case):
+    k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
+    mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=1000 + k + u)
+    _run_streaming(_rand_stream(k + u, n, n_src, 3 * theta // 2), mon, range(slices), graph=True)
+
+
+def test_streaming_call_order_errors():
+    stream, mon, _ = workload("tiny")
+    g = srla.Monitor(**mon, max_candidates=1 << 16)
+    with pytest.raises(srla.SrlaError) as e:
+        g.wait_report()
+    assert e.value.rc == -4
+    g.scan(to_device(stream.slice(0)))
+    g.close_slice()
+    with pytest.raises(srla.SrlaError) as e:
+        g.close_slice()
+    assert e.value.rc == -4
+    with pytest.raises(srla.SrlaError) as e:
+        g.estimate()
+    assert e.value.rc == -4
+    r = g.wait_report()
+    assert r.slice == 0
+    g.close()
 
 
 def test_host_input_chunked_and_unaligned_device_input():
@@ -174,13 +228,20 @@ def test_backbone_workload_prefix_full_size():
     _run(stream, mon, range(3), max_candidates=1 << 22)
 
 
-@pytest.mark.parametrize("scan_xcd", [False, True])
-def test_backbone_short_window_expiry(scan_xcd):
+@pytest.mark.parametrize("scan_xcd,graph", [(False, False), (True, True)])
+def test_backbone_short_window_expiry(scan_xcd, graph):
     """Backbone geometry with k = 16 over 40 slices, so DRs leave the window
     and carried candidates are dropped at full column counts."""
     stream, mon, _ = workload("backbone_k16")
     stream = scaled(stream, 600_000)
-    _run(stream, mon, range(40), max_candidates=1 << 22, dump_every=13, scan_xcd=scan_xcd)
+    _run(stream, mon, range(40), max_candidates=1 << 22, dump_every=13, scan_xcd=scan_xcd,
+         graph=graph)
+
+
+def test_backbone_short_window_streaming():
+    stream, mon, _ = workload("backbone_k16")
+    stream = scaled(stream, 600_000)
+    _run_streaming(stream, mon, range(24), max_candidates=1 << 22, graph=True)
 
 
 def test_paper_geometry_prefix():
