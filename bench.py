@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--mode", choices=("plain", "streaming"), default="plain")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay the end-of-slice pipeline as HIP graphs (default: streaming only)")
+    ap.add_argument("--scan-blocks", type=int, default=0,
+                    help="cap on the scan kernel's workgroups (0: one per tile)")
     ap.add_argument("--segment", type=int, default=200,
                     help="timed slices whose inputs are generated into HBM at a time")
     ap.add_argument("--steps", type=int, default=60)
@@ -133,7 +135,7 @@ def main():
         del src, dst
     graph = (args.mode == "streaming") if args.graph < 0 else bool(args.graph)
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
-                     scan_xcd=args.scan_xcd, graph=graph)
+                     scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks)
     buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
     t_w = time.perf_counter()
     for s in range(args.warmup):
@@ -224,7 +226,7 @@ def main():
             "u": g["u"], "v_re": g["v_re"], "g": g["g"], "v_le": g["v_le"], "g_le": g["G"],
             "window": g["k"], "theta": g["theta"], "pairs_per_slice": n_pairs,
             "slices_timed": [args.warmup, args.warmup + args.steps - 1],
-            "mode": args.mode, "graph": graph,
+            "mode": args.mode, "graph": graph, "scan_blocks": args.scan_blocks,
         },
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),

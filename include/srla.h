@@ -83,6 +83,10 @@ typedef struct {
  *   threshold       theta >= 1 (Definition 2)
  *   max_candidates  capacity of the candidate list, >= 1
  *   flags           SRLA_CFG_* bits
+ *   scan_blocks     launch-shape knob of the scan kernel: the most
+ *                   workgroups one scan launch uses (they stride over the
+ *                   pairs); 0 = one workgroup per tile of 2048 pairs.
+ *                   Results do not depend on it.
  */
 typedef struct {
     uint32_t window_slices;
@@ -90,6 +94,7 @@ typedef struct {
     srla_geometry_t geom;
     uint64_t max_candidates;
     uint32_t flags;
+    uint32_t scan_blocks;
 } srla_config_t;
 
 typedef struct srla_monitor srla_monitor_t;

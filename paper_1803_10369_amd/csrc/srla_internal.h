@@ -113,10 +113,11 @@ constexpr uint32_t kPipeBlocks = 1024;
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t st);
 
 // Algorithm 2 for n pairs of the open slice (stamp code `code`); sampled
-// sources are appended to `touched`, counted in *tcount
+// sources are appended to `touched`, counted in *tcount.  max_blocks caps
+// the grid (0: one block per tile of pairs).
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                        uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
-                       bool xcd_aware, hipStream_t st);
+                       bool xcd_aware, uint32_t max_blocks, hipStream_t st);
 
 hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
                            const Geo& geo, const PipeState* ps, hipStream_t st);

@@ -553,7 +553,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     hipEvent_t a;
     span_begin(m, m->stream, &a);
     HIP_TRY(m, launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p], m->tcount + p,
-                           m->xcd_scan, m->stream));
+                           m->xcd_scan, m->cfg.scan_blocks, m->stream));
     span_end(m, m->stream, ST_SCAN, a);
     m->slice_pairs[p] += n;
     m->scan_launches++;
@@ -584,7 +584,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     hipEvent_t a;
     span_begin(m, m->stream, &a);
     HIP_TRY(m, launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched[p],
-                           m->tcount + p, m->xcd_scan, m->stream));
+                           m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream));
     span_end(m, m->stream, ST_SCAN, a);
     m->slice_pairs[p] += cnt;
     m->scan_launches++;

@@ -65,7 +65,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_flat(const uint32_t* __restrict
                                                 uint16_t* __restrict__ re,
                                                 uint32_t* __restrict__ touched,
                                                 uint32_t* __restrict__ tcount) {
-  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  // one tile of kScanTile pairs per iteration; the grid may be smaller than
+  // the tile count (then it strides), leaving wave slots to other streams
+  for (uint64_t base = (uint64_t)blockIdx.x * kScanTile; base < n;
+       base += (uint64_t)gridDim.x * kScanTile) {
   uint32_t a[kScanSteps][2], b[kScanSteps][2];
   bool v[kScanSteps][2];
 #pragma unroll
@@ -88,6 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_flat(const uint32_t* __restrict
     scan_one<U>(a[s][0], b[s][0], v[s][0], geo, code, le, re, touched, tcount);
     scan_one<U>(a[s][1], b[s][1], v[s][1], geo, code, le, re, touched, tcount);
   }
+  }
 }
 
 // XCD-aware form.  Workgroups are dispatched to the 8 XCDs round-robin, so
@@ -109,11 +113,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_xcd(const uint32_t* __restrict_
   constexpr int kParts = U >= kXcds ? 1 : kXcds / U;      // tiles per XCD group
   constexpr int kRowsPerXcd = U >= kXcds ? U / kXcds : 1;
   const uint32_t xcd = blockIdx.x % kXcds;
-  const uint32_t group = blockIdx.x / kXcds;
   const uint32_t row0 = U >= kXcds ? xcd : xcd % U;
-  const uint64_t tile = (uint64_t)group * kParts + (U >= kXcds ? 0u : xcd / U);
   const bool appender = row0 == 0;
+  for (uint64_t group = blockIdx.x / kXcds;; group += gridDim.x / kXcds) {
+  const uint64_t tile = group * kParts + (U >= kXcds ? 0u : xcd / U);
   const uint64_t base = tile * kScanTile;
+  if (base >= n) break;
   uint32_t a[kScanSteps][2], b[kScanSteps][2];
   bool v[kScanSteps][2];
 #pragma unroll
@@ -160,15 +165,17 @@ __global__ __launch_bounds__(kBlock) void k_scan_xcd(const uint32_t* __restrict_
       }
     }
   }
+  }
 }
 
 template <int U>
 static hipError_t launch_scan_xcd(const uint32_t* pairs, uint64_t n, const Geo& geo,
                                   uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
-                                  uint32_t* tcount, hipStream_t st) {
+                                  uint32_t* tcount, uint32_t max_blocks, hipStream_t st) {
   constexpr uint64_t kParts = U >= kXcds ? 1 : kXcds / U;
   const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
-  const uint64_t blocks = kXcds * ((tiles + kParts - 1) / kParts);
+  uint64_t blocks = kXcds * ((tiles + kParts - 1) / kParts);
+  if (max_blocks && blocks > max_blocks) blocks = max_blocks >= kXcds ? max_blocks / kXcds * kXcds : kXcds;
   hipLaunchKernelGGL((k_scan_xcd<U>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n, geo,
                      code, le, re, touched, tcount);
   return hipGetLastError();
@@ -177,8 +184,9 @@ static hipError_t launch_scan_xcd(const uint32_t* pairs, uint64_t n, const Geo& 
 template <int U>
 static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                                 uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
-                                hipStream_t st) {
-  const uint64_t blocks = (n + kScanTile - 1) / kScanTile;
+                                uint32_t max_blocks, hipStream_t st) {
+  uint64_t blocks = (n + kScanTile - 1) / kScanTile;
+  if (max_blocks && blocks > max_blocks) blocks = max_blocks;
   const bool vec = ((uintptr_t)pairs & 15u) == 0;
   if (vec)
     hipLaunchKernelGGL((k_scan_flat<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
@@ -191,22 +199,22 @@ static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& ge
 
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                        uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
-                       bool xcd_aware, hipStream_t st) {
+                       bool xcd_aware, uint32_t max_blocks, hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (xcd_aware && ((uintptr_t)pairs & 15u) == 0) {
     switch (geo.u) {
-      case 1: return launch_scan_xcd<1>(pairs, n, geo, code, le, re, touched, tcount, st);
-      case 2: return launch_scan_xcd<2>(pairs, n, geo, code, le, re, touched, tcount, st);
-      case 4: return launch_scan_xcd<4>(pairs, n, geo, code, le, re, touched, tcount, st);
-      case 8: return launch_scan_xcd<8>(pairs, n, geo, code, le, re, touched, tcount, st);
-      case 16: return launch_scan_xcd<16>(pairs, n, geo, code, le, re, touched, tcount, st);
+      case 1: return launch_scan_xcd<1>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
+      case 2: return launch_scan_xcd<2>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
+      case 4: return launch_scan_xcd<4>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
+      case 8: return launch_scan_xcd<8>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
+      case 16: return launch_scan_xcd<16>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
       default: break;
     }
   }
   switch (geo.u) {
-    case 4: return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, tcount, st);
-    case 8: return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, tcount, st);
-    default: return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, tcount, st);
+    case 4: return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
+    case 8: return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
+    default: return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
   }
 }
 

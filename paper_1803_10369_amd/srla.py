@@ -32,7 +32,7 @@ class srla_geometry_t(ctypes.Structure):
 class srla_config_t(ctypes.Structure):
     _fields_ = [("window_slices", ctypes.c_uint32), ("threshold", ctypes.c_uint32),
                 ("geom", srla_geometry_t), ("max_candidates", ctypes.c_uint64),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("scan_blocks", ctypes.c_uint32)]
 
 
 class srla_report_t(ctypes.Structure):
@@ -96,9 +96,10 @@ def lib():
 
 # ---------------------------------------------------------------- C names
 
-def make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22, flags=0):
+def make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22, flags=0,
+                scan_blocks=0):
     return srla_config_t(k, theta, srla_geometry_t(u, v_re, g, v_le, G, hash_seed),
-                         max_candidates, flags)
+                         max_candidates, flags, scan_blocks)
 
 
 def srla_footprint_bytes(cfg):
@@ -188,10 +189,11 @@ class Monitor:
     caller's current stream and kept alive for the monitor's stream."""
 
     def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22,
-                 timing=False, stream=None, scan_xcd=False, graph=False):
+                 timing=False, stream=None, scan_xcd=False, graph=False, scan_blocks=0):
         flags = ((SRLA_CFG_TIMING if timing else 0) | (SRLA_CFG_SCAN_XCD if scan_xcd else 0) |
                  (SRLA_CFG_GRAPH if graph else 0))
-        self.cfg = make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates, flags)
+        self.cfg = make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates, flags,
+                               scan_blocks)
         self._h = None
         self.stream = stream if stream is not None else torch.cuda.Stream()
         rc, h = srla_create(self.cfg, ctypes.c_void_p(self.stream.cuda_stream))

@@ -45,7 +45,8 @@ def test_binding_struct_layouts_match_header(P, tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(srla_geometry_t), sizeof(srla_config_t),
          sizeof(srla_report_t), sizeof(srla_timings_t));
-  printf("%zu %zu %zu %zu\\n", offsetof(srla_config_t, max_candidates),
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(srla_config_t, max_candidates),
+         offsetof(srla_config_t, scan_blocks),
          offsetof(srla_report_t, row_fill), offsetof(srla_report_t, up),
          offsetof(srla_timings_t, estimates));
   return 0;
@@ -58,7 +59,8 @@ int main(void) {
     S = P.srla
     want = [ctypes.sizeof(S.srla_geometry_t), ctypes.sizeof(S.srla_config_t),
             ctypes.sizeof(S.srla_report_t), ctypes.sizeof(S.srla_timings_t),
-            S.srla_config_t.max_candidates.offset, S.srla_report_t.row_fill.offset,
+            S.srla_config_t.max_candidates.offset, S.srla_config_t.scan_blocks.offset,
+            S.srla_report_t.row_fill.offset,
             S.srla_report_t.up.offset, S.srla_timings_t.estimates.offset]
     assert [int(x) for x in out] == want
 

@@ -53,6 +53,20 @@ def test_tiny_workload_full_run(scan_xcd, graph):
     assert r.window_full and r.n > 0
 
 
+@pytest.mark.parametrize("scan_xcd,blocks", [(False, 7), (True, 16), (True, 5)])
+def test_scan_grid_cap_strides_over_all_pairs(scan_xcd, blocks):
+    stream, mon, n = workload("tiny")
+    g = srla.Monitor(**mon, max_candidates=1 << 16, scan_xcd=scan_xcd, scan_blocks=blocks)
+    o = oracle.Monitor(**mon)
+    for s in range(6):
+        p = stream.slice(s)
+        g.scan(to_device(p))
+        o.scan(p)
+        compare_reports(g.estimate(), o.estimate(), mon["theta"], "slice %d" % s)
+    compare_dumps(g, o)
+    g.close()
+
+
 def test_tiny_coupled_workload_full_run():
     stream, mon, n = workload("tiny_coupled")
     r = _run(stream, mon, range(n), dump_every=4)
