@@ -220,6 +220,27 @@ int srla_dump_state(srla_monitor_t *m, int which, uint16_t *host_out, uint64_t c
 /* Stage times since the last reset (reset != 0 clears them after reading). */
 int srla_timings(srla_monitor_t *m, srla_timings_t *out, int reset);
 
+/*
+ * Monitor groups: many monitors -- each with its own window, DR geometry,
+ * threshold and hash seed -- fed the same pair stream.  srla_group_scan runs
+ * one fused scan kernel that loads every pair once and applies Algorithm 2
+ * of every member; it is equivalent to srla_scan on each member with the
+ * same pairs.  Slices are still closed and reported per member
+ * (srla_close_slice / srla_wait_report / srla_estimate).
+ * srla_group_create: 1..64 distinct monitors that share one scan stream;
+ *   scan_blocks as in srla_config_t.  The group does not own the monitors;
+ *   destroy the group before any member.
+ * srla_group_scan: pairs as for srla_scan, device memory only (on_device
+ *   must be nonzero).  Errors: SRLA_E_INVAL, SRLA_E_STATE (a member is
+ *   poisoned), SRLA_E_NOMEM, SRLA_E_DEVICE.
+ */
+typedef struct srla_group srla_group_t;
+int srla_group_create(srla_monitor_t *const *monitors, uint32_t n, uint32_t scan_blocks,
+                      srla_group_t **out);
+int srla_group_scan(srla_group_t *g, const uint32_t *pairs, uint64_t n, int on_device);
+int srla_group_destroy(srla_group_t *g);
+const char *srla_group_last_error(const srla_group_t *g);
+
 /* Waits for the monitor's streams and frees everything it owns. NULL is ok. */
 int srla_destroy(srla_monitor_t *m);
 

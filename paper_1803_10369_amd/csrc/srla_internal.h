@@ -104,6 +104,24 @@ struct ReportPtrs {
   uint8_t* W;
 };
 
+// One member of a monitor group, as the fused scan kernel sees it.
+struct GroupMember {
+  Geo geo;
+  uint16_t* le;
+  uint16_t* re;
+  uint32_t* touched[2];   // sampled sources, by slice parity
+  uint32_t* tcount;       // [2] their counts
+};
+
+constexpr int kMaxGroup = 64;
+
+// Per-launch arguments of the fused scan: each member's stamp code and slice
+// parity (members may be at different slices).
+struct GroupScanArgs {
+  uint16_t code[kMaxGroup];
+  uint64_t parity;        // bit m = parity of member m's open slice
+};
+
 // Fixed grids of the end-of-slice kernels (they loop over device counts).
 constexpr uint32_t kPipeBlocks = 1024;
 
@@ -118,6 +136,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t 
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                        uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
                        bool xcd_aware, uint32_t max_blocks, hipStream_t st);
+
+// Algorithm 2 of every member of a group for n pairs, each pair loaded once
+hipError_t launch_scan_group(const uint32_t* pairs, uint64_t n, const GroupMember* members,
+                             uint32_t n_members, const GroupScanArgs& args, uint32_t max_blocks,
+                             hipStream_t st);
 
 hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
                            const Geo& geo, const PipeState* ps, hipStream_t st);

@@ -718,6 +718,121 @@ int srla_timings(srla_monitor_t* m, srla_timings_t* out, int reset) {
   return SRLA_OK;
 }
 
+// ------------------------------------------------------------------ groups
+
+}  // extern "C"
+
+struct srla_group {
+  std::vector<srla_monitor*> mons;
+  hipStream_t stream = nullptr;
+  GroupMember* d_members = nullptr;
+  std::vector<GroupMember> uploaded;
+  uint32_t scan_blocks = 0;
+  std::string err;
+};
+
+namespace {
+
+bool same_member(const GroupMember& a, const GroupMember& b) {
+  return std::memcmp(&a, &b, sizeof(GroupMember)) == 0;
+}
+
+int group_fail(srla_group* g, int code, const std::string& what) {
+  if (g) g->err = what;
+  return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+int srla_group_create(srla_monitor_t* const* monitors, uint32_t n, uint32_t scan_blocks,
+                      srla_group_t** out) {
+  if (!out || !monitors || n < 1 || n > (uint32_t)kMaxGroup) return SRLA_E_INVAL;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (!monitors[i] || monitors[i]->stream != monitors[0]->stream) return SRLA_E_INVAL;
+    for (uint32_t j = 0; j < i; ++j)
+      if (monitors[j] == monitors[i]) return SRLA_E_INVAL;
+  }
+  srla_group* g = new (std::nothrow) srla_group();
+  if (!g) return SRLA_E_NOMEM;
+  g->mons.assign(monitors, monitors + n);
+  g->stream = monitors[0]->stream;
+  g->scan_blocks = scan_blocks;
+  if (hipMalloc((void**)&g->d_members, n * sizeof(GroupMember)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete g;
+    return SRLA_E_NOMEM;
+  }
+  *out = g;
+  return SRLA_OK;
+}
+
+int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_device) {
+  if (!g) return SRLA_E_INVAL;
+  if (n == 0) return SRLA_OK;
+  if (!pairs) return group_fail(g, SRLA_E_INVAL, "pairs is NULL");
+  if (!on_device) return group_fail(g, SRLA_E_INVAL, "a group scans device-resident pairs");
+  GroupScanArgs args{};
+  std::vector<GroupMember> table(g->mons.size());
+  for (size_t i = 0; i < g->mons.size(); ++i) {
+    srla_monitor* m = g->mons[i];
+    if (m->poisoned) return group_fail(g, SRLA_E_STATE, "a member monitor is poisoned");
+    const int p = (int)(m->slice & 1);
+    const int rc = reserve_touched(m, m->slice_pairs[p] + n);
+    if (rc) return group_fail(g, rc, m->err);
+    if (m->snap_pending) {
+      const hipError_t e = hipStreamWaitEvent(g->stream, m->ev_snap, 0);
+      if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
+      m->snap_pending = false;
+    }
+    GroupMember& gm = table[i];
+    std::memset(&gm, 0, sizeof(gm));
+    gm.geo = m->geo;
+    gm.le = m->le;
+    gm.re = m->re;
+    gm.touched[0] = m->touched[0];
+    gm.touched[1] = m->touched[1];
+    gm.tcount = m->tcount;
+    args.code[i] = stamp_code(m->slice);
+    args.parity |= (uint64_t)p << i;
+  }
+  bool changed = g->uploaded.size() != table.size();
+  for (size_t i = 0; !changed && i < table.size(); ++i)
+    changed = !same_member(table[i], g->uploaded[i]);
+  if (changed) {
+    // the table is read by earlier fused scans still queued on the stream
+    hipError_t e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess)
+      e = hipMemcpy(g->d_members, table.data(), table.size() * sizeof(GroupMember),
+                    hipMemcpyHostToDevice);
+    if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
+    g->uploaded = table;
+  }
+  const hipError_t e = launch_scan_group(pairs, n, g->d_members, (uint32_t)table.size(), args,
+                                         g->scan_blocks, g->stream);
+  if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
+  for (srla_monitor* m : g->mons) {
+    m->slice_pairs[m->slice & 1] += n;
+    m->scan_launches++;
+    m->scan_pairs += n;
+  }
+  return SRLA_OK;
+}
+
+int srla_group_destroy(srla_group_t* g) {
+  if (!g) return SRLA_OK;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  if (g->d_members) (void)hipFree(g->d_members);
+  delete g;
+  return SRLA_OK;
+}
+
+const char* srla_group_last_error(const srla_group_t* g) {
+  if (!g) return "no group";
+  return g->err.c_str();
+}
+
 int srla_destroy(srla_monitor_t* m) {
   release(m);
   return SRLA_OK;

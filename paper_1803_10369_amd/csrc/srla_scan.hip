@@ -218,4 +218,66 @@ hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16
   }
 }
 
+// ------------------------------------------------------------------ group
+// Fused scan of a monitor group over one pair stream: every pair is loaded
+// once (16-byte loads, two pairs per lane), then each member applies its own
+// Algorithm 2 -- its hash functions, rows, window-agnostic stamp arrays,
+// sampling threshold and sampled-source list -- read from the member table
+// with uniform (scalar) loads.  Equivalent to scanning the same pairs into
+// every member separately.
+
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_scan_group(const uint32_t* __restrict__ pairs,
+                                                      uint64_t n,
+                                                      const GroupMember* __restrict__ members,
+                                                      uint32_t n_members, GroupScanArgs args) {
+  for (uint64_t base = (uint64_t)blockIdx.x * kScanTile; base < n;
+       base += (uint64_t)gridDim.x * kScanTile) {
+    uint32_t a[kScanSteps][2], b[kScanSteps][2];
+    bool v[kScanSteps][2];
+#pragma unroll
+    for (int s = 0; s < kScanSteps; ++s) {
+      const uint64_t p = base + (uint64_t)s * (2 * kBlock) + 2u * threadIdx.x;
+      v[s][0] = p < n;
+      v[s][1] = p + 1 < n;
+      if (VEC && v[s][1]) {
+        const uint4 q = *reinterpret_cast<const uint4*>(pairs + 2 * p);
+        a[s][0] = q.x; b[s][0] = q.y; a[s][1] = q.z; b[s][1] = q.w;
+      } else {
+        a[s][0] = v[s][0] ? pairs[2 * p] : 0u;
+        b[s][0] = v[s][0] ? pairs[2 * p + 1] : 0u;
+        a[s][1] = v[s][1] ? pairs[2 * p + 2] : 0u;
+        b[s][1] = v[s][1] ? pairs[2 * p + 3] : 0u;
+      }
+    }
+    for (uint32_t mi = 0; mi < n_members; ++mi) {
+      const GroupMember& m = members[mi];
+      const uint32_t par = (uint32_t)(args.parity >> mi) & 1u;
+      const uint16_t code = args.code[mi];
+#pragma unroll
+      for (int s = 0; s < kScanSteps; ++s) {
+        scan_one<0>(a[s][0], b[s][0], v[s][0], m.geo, code, m.le, m.re, m.touched[par],
+                    m.tcount + par);
+        scan_one<0>(a[s][1], b[s][1], v[s][1], m.geo, code, m.le, m.re, m.touched[par],
+                    m.tcount + par);
+      }
+    }
+  }
+}
+
+hipError_t launch_scan_group(const uint32_t* pairs, uint64_t n, const GroupMember* members,
+                             uint32_t n_members, const GroupScanArgs& args, uint32_t max_blocks,
+                             hipStream_t st) {
+  if (n == 0 || n_members == 0) return hipSuccess;
+  uint64_t blocks = (n + kScanTile - 1) / kScanTile;
+  if (max_blocks && blocks > max_blocks) blocks = max_blocks;
+  if (((uintptr_t)pairs & 15u) == 0)
+    hipLaunchKernelGGL(k_scan_group<true>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
+                       members, n_members, args);
+  else
+    hipLaunchKernelGGL(k_scan_group<false>, dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
+                       members, n_members, args);
+  return hipGetLastError();
+}
+
 }  // namespace srla

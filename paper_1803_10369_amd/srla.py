@@ -58,7 +58,8 @@ class srla_timings_t(ctypes.Structure):
 
 EXPORTS = ["srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
            "srla_close_slice", "srla_wait_report", "srla_dump_state", "srla_timings",
-           "srla_destroy", "srla_last_error"]
+           "srla_destroy", "srla_last_error", "srla_group_create", "srla_group_scan",
+           "srla_group_destroy", "srla_group_last_error"]
 
 _lib = None
 
@@ -90,6 +91,15 @@ def lib():
         L.srla_destroy.argtypes = [vp]
         L.srla_last_error.restype = ctypes.c_char_p
         L.srla_last_error.argtypes = [vp]
+        L.srla_group_create.restype = ctypes.c_int
+        L.srla_group_create.argtypes = [ctypes.POINTER(vp), ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.POINTER(vp)]
+        L.srla_group_scan.restype = ctypes.c_int
+        L.srla_group_scan.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_int]
+        L.srla_group_destroy.restype = ctypes.c_int
+        L.srla_group_destroy.argtypes = [vp]
+        L.srla_group_last_error.restype = ctypes.c_char_p
+        L.srla_group_last_error.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -143,6 +153,27 @@ def srla_destroy(handle):
 
 def srla_last_error(handle):
     s = lib().srla_last_error(handle)
+    return s.decode() if s else ""
+
+
+def srla_group_create(handles, scan_blocks=0):
+    """Returns (status, group handle)."""
+    arr = (ctypes.c_void_p * len(handles))(*[h.value for h in handles])
+    g = ctypes.c_void_p()
+    rc = lib().srla_group_create(arr, len(handles), scan_blocks, ctypes.byref(g))
+    return rc, g
+
+
+def srla_group_scan(group, pairs_ptr, n, on_device):
+    return lib().srla_group_scan(group, pairs_ptr, n, int(on_device))
+
+
+def srla_group_destroy(group):
+    return lib().srla_group_destroy(group)
+
+
+def srla_group_last_error(group):
+    s = lib().srla_group_last_error(group)
     return s.decode() if s else ""
 
 
@@ -268,3 +299,38 @@ class Monitor:
     @property
     def footprint_bytes(self):
         return srla_footprint_bytes(self.cfg)
+
+
+class Group:
+    """Monitors fed one pair stream through the fused scan kernel.  All
+    members must share one stream; pass it to every Monitor."""
+
+    def __init__(self, monitors, scan_blocks=0):
+        self.monitors = list(monitors)
+        self.stream = self.monitors[0].stream
+        rc, g = srla_group_create([m._h for m in self.monitors], scan_blocks)
+        if rc != SRLA_OK:
+            raise SrlaError(rc, "srla_group_create failed")
+        self._g = g
+
+    def scan(self, pairs):
+        """pairs: a contiguous 32-bit CUDA tensor of 2n values (aip, bip)."""
+        assert isinstance(pairs, torch.Tensor) and pairs.is_cuda and pairs.is_contiguous()
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+            pairs.record_stream(self.stream)
+        rc = srla_group_scan(self._g, ctypes.c_void_p(pairs.data_ptr()), pairs.numel() // 2, True)
+        if rc != SRLA_OK:
+            raise SrlaError(rc, srla_group_last_error(self._g))
+
+    def close(self):
+        if getattr(self, "_g", None):
+            srla_group_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -27,7 +27,9 @@ def test_every_declared_symbol_is_exported(P):
     names = _declared_functions()
     assert set(names) == {"srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
                           "srla_close_slice", "srla_wait_report", "srla_dump_state",
-                          "srla_timings", "srla_destroy", "srla_last_error"}
+                          "srla_timings", "srla_destroy", "srla_last_error",
+                          "srla_group_create", "srla_group_scan", "srla_group_destroy",
+                          "srla_group_last_error"}
     L = ctypes.CDLL(P.srla.LIB_PATH)
     for n in names:
         assert hasattr(L, n), n
@@ -109,6 +111,9 @@ def test_null_handles(P):
     assert L.srla_estimate(None, None) == -1
     assert L.srla_close_slice(None) == -1
     assert L.srla_wait_report(None, None) == -1
+    assert L.srla_group_scan(None, None, 0, 1) == -1
+    assert L.srla_group_destroy(None) == 0
+    assert L.srla_group_last_error(None) == b"no group"
 
 
 def test_product_never_imports_the_oracle():

@@ -295,3 +295,63 @@ def test_timings_are_recorded():
     assert t["sweep_ms"] > 0 and t["estimate_ms"] > 0 and t["estimates"] == 3
     assert g.timings()["scan_ms"] == 0
     g.close()
+
+
+GROUP = [
+    # k, theta, u, v_re, g, v_le, G
+    (3, 64, 3, 64, 8, 8, 128),
+    (1, 256, 4, 128, 8, 16, 1024),
+    (5, 16, 1, 16, 4, 16, 64),
+    (7, 4096, 8, 512, 16, 32, 192),
+    (2, 300, 16, 97, 64, 5, 4096),
+]
+
+
+@pytest.mark.parametrize("streaming", [False, True])
+def test_group_fused_scan_matches_each_members_oracle(streaming):
+    """One pair stream, five monitors of different windows, geometries,
+    thresholds and seeds, scanned by the fused kernel."""
+    st = torch.cuda.Stream()
+    mons = [dict(k=k, theta=t, u=u, v_re=vr, g=g, v_le=vl, G=G, hash_seed=77 + i)
+            for i, (k, t, u, vr, g, vl, G) in enumerate(GROUP)]
+    gms = [srla.Monitor(**m, max_candidates=1 << 16, stream=st, graph=bool(i % 2))
+           for i, m in enumerate(mons)]
+    oms = [oracle.Monitor(**m) for m in mons]
+    grp = srla.Group(gms, scan_blocks=0 if streaming else 9)
+    gen = _rand_stream(5, 30_000, 2500, 400)
+    expected = None
+    for s in range(8):
+        p = gen(s)
+        grp.scan(to_device(p))
+        for o in oms:
+            o.scan(p)
+        if streaming and expected is not None:
+            for gm, e, m in zip(gms, expected, mons):
+                compare_reports(gm.wait_report(), e, m["theta"], "slice %d" % (s - 1))
+        expected = [o.estimate() for o in oms]
+        if streaming:
+            for gm in gms:
+                gm.close_slice()
+        else:
+            for gm, e, m in zip(gms, expected, mons):
+                compare_reports(gm.estimate(), e, m["theta"], "slice %d" % s)
+    if streaming:
+        for gm, e, m in zip(gms, expected, mons):
+            compare_reports(gm.wait_report(), e, m["theta"], "last slice")
+    for gm, o in zip(gms, oms):
+        compare_dumps(gm, o)
+    grp.close()
+    for gm in gms:
+        gm.close()
+
+
+def test_group_rejects_mixed_streams_and_duplicates():
+    stream, mon, _ = workload("tiny")
+    a = srla.Monitor(**mon, max_candidates=1 << 10)
+    b = srla.Monitor(**mon, max_candidates=1 << 10)
+    with pytest.raises(srla.SrlaError):
+        srla.Group([a, b])            # two different streams
+    with pytest.raises(srla.SrlaError):
+        srla.Group([a, a])
+    a.close()
+    b.close()
