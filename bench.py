@@ -80,10 +80,129 @@ def oracle_baseline(stream, mon, slices):
     return n / dt, dt, n
 
 
+def run_batched(args):
+    """The batched workload: 16 monitors of different windows, SLE sizes and
+    thresholds over one 8M pairs/slice stream.  --mode plain: each monitor
+    scans and estimates on its own (one monitor after another); --mode
+    batched: one fused scan for all, then every member's slice closed at once
+    and the reports collected; --mode streaming: batched, with the next
+    slice's fused scan issued before the reports are collected."""
+    import numpy as np
+    import torch
+
+    import paper_1803_10369_amd as srla
+    from trafficgen.configs import batched_monitors, workload
+    from trafficgen.device import DeviceStream
+
+    torch.cuda.set_device(0)
+    stream, _, _ = workload("backbone")
+    n_pairs = stream.n_pairs
+    mons_cfg = batched_monitors(16)
+    ds = DeviceStream(stream)
+    st = torch.cuda.Stream()
+    torch.cuda.set_stream(st)
+    fused = args.mode in ("batched", "streaming")
+    mons = [srla.Monitor(**c, max_candidates=args.max_candidates, stream=st, graph=fused,
+                         scan_blocks=args.scan_blocks) for c in mons_cfg]
+    grp = srla.Group(mons, scan_blocks=args.scan_blocks) if fused else None
+
+    def scan_all(buf):
+        if fused:
+            grp.scan(buf)
+        else:
+            for m in mons:
+                m.scan(buf)
+
+    buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
+    t_w = time.perf_counter()
+    for s in range(args.warmup):
+        ds.generate(s, out=buf, stream=st)
+        scan_all(buf)
+        for m in mons:
+            m.estimate(copy=False)
+        if s % 50 == 0:
+            print("warmup slice %d (%.1fs)" % (s, time.perf_counter() - t_w), file=sys.stderr,
+                  flush=True)
+    lat, total_s, done, seg_bufs = [], 0.0, 0, []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    scan_ms = []
+    while done < args.steps:
+        seg = min(args.segment, args.steps - done)
+        while len(seg_bufs) < seg:
+            seg_bufs.append(torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda"))
+        for i in range(seg):
+            ds.generate(args.warmup + done + i, out=seg_bufs[i], stream=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if args.mode == "streaming":
+            scan_all(seg_bufs[0])
+            for m in mons:
+                m.close_slice()
+            t_close = time.perf_counter()
+            for i in range(1, seg + 1):
+                if i < seg:
+                    scan_all(seg_bufs[i])
+                for m in mons:
+                    m.wait_report(copy=False)
+                lat.append((time.perf_counter() - t_close) * 1e3)
+                if i < seg:
+                    for m in mons:
+                        m.close_slice()
+                    t_close = time.perf_counter()
+        else:
+            for i in range(seg):
+                ev0.record(st)
+                scan_all(seg_bufs[i])
+                ev1.record(st)
+                st.synchronize()
+                scan_ms.append(ev0.elapsed_time(ev1))
+                ts = time.perf_counter()
+                if fused:
+                    for m in mons:
+                        m.close_slice()
+                    for m in mons:
+                        m.wait_report(copy=False)
+                else:
+                    for m in mons:
+                        m.estimate(copy=False)
+                lat.append((time.perf_counter() - ts) * 1e3)
+        torch.cuda.synchronize()
+        total_s += time.perf_counter() - t0
+        done += seg
+        print("timed %d/%d slices (%.2fs)" % (done, args.steps, total_s), file=sys.stderr,
+              flush=True)
+    lat = np.array(lat)
+    value = args.steps * n_pairs / total_s
+    stores = sum(c["u"] for c in mons_cfg)
+    out = {
+        "metric": METRIC, "value": value, "unit": "packets/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_s * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": ("batched16, %s form: 16 monitors over one %d pairs/slice stream "
+                                "(Zipf(%g) over %d hosts), windows {10,60,300,1800}, SLE 2^20..2^25 "
+                                "DR cells, thresholds 256..16384" % (args.mode, n_pairs,
+                                                                    stream.alpha, stream.n_ranks)),
+                   "mode": args.mode, "monitors": len(mons), "pairs_per_slice": n_pairs,
+                   "scan_blocks": args.scan_blocks},
+        "monitor_pairs_per_s": value * len(mons),
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+    }
+    if scan_ms:
+        ms = float(np.mean(scan_ms))
+        out["scan_ms_per_slice"] = ms
+        out["random_stores_per_s"] = stores * n_pairs / (ms * 1e-3)
+    print(json.dumps(out), flush=True)
+    if grp:
+        grp.close()
+    for m in mons:
+        m.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=("plain", "streaming"), default="plain")
+    ap.add_argument("--mode", choices=("plain", "streaming", "batched"), default="plain")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay the end-of-slice pipeline as HIP graphs (default: streaming only)")
     ap.add_argument("--scan-blocks", type=int, default=0,
@@ -110,6 +229,8 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched16":
+        return run_batched(args)
 
     import numpy as np
     import torch

@@ -4,6 +4,8 @@ DR dumps, SI words, candidate lists, flags and integer counts must match
 bit for bit; FP64 estimates within 1e-12 relative.  Sizes span many scan,
 sort and compaction tiles with ragged tails.
 """
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -355,3 +357,29 @@ def test_group_rejects_mixed_streams_and_duplicates():
         srla.Group([a, a])
     a.close()
     b.close()
+
+
+def test_stamps_survive_wraparound_of_the_slice_code():
+    """70,000 slices (past 65,535, where the 16-bit slice code repeats): DRs
+    set long ago must read as outside every window, never as recent."""
+    mon = dict(k=3, theta=8, u=2, v_re=4, g=8, v_le=2, G=64, hash_seed=5)
+    g = srla.Monitor(**mon, max_candidates=64, graph=True)
+    o = oracle.Monitor(**mon)
+    rng = np.random.default_rng(3)
+    burst = {0, 1, 2, 40_000, 65_534, 65_535, 65_536, 65_537, 69_998}
+    pairs_dev = {}
+    t0 = time.time()
+    for s in range(70_000):
+        if s in burst:
+            p = np.stack([np.full(40, 9, np.uint32),
+                          rng.integers(0, 2 ** 32, size=40, dtype=np.uint64).astype(np.uint32)], 1)
+            pairs_dev[s] = to_device(p)
+            g.scan(pairs_dev[s])
+            o.scan(p)
+        rg, rc = g.estimate(copy=False), o.estimate()
+        if s in burst or s % 5000 == 0 or (s - 1) in burst or (s - 3) in burst:
+            compare_reports(rg, rc, mon["theta"], "slice %d" % s)
+            compare_dumps(g, o, ctx="slice %d" % s)
+        if s % 10000 == 0:
+            print("slice", s, "%.1fs" % (time.time() - t0), flush=True)
+    g.close()

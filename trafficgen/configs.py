@@ -51,3 +51,16 @@ def scaled(stream, n_pairs):
     """The same stream recipe with fewer pairs per slice (planted kept)."""
     return StreamSpec(n_pairs=n_pairs, n_ranks=stream.n_ranks, alpha=stream.alpha,
                       planted=list(stream.planted), window=stream.window, seed=stream.seed)
+
+
+def batched_monitors(n=16, cfg_no=4):
+    """Monitors of the batched workload: window [10, 60, 300, 1800][m % 4]
+    slices, threshold 2^(8 + m % 7) (256 .. 16,384), SLE 2^(20 + m % 6) DR
+    cells (u = 4 rows of g' = 1024, so v_le = 256 .. 8,192), SRE 4 x 2^20
+    cells (v_re = 131,072, g = 8), one hash seed per monitor."""
+    out = []
+    for m in range(n):
+        sle = 1 << (20 + m % 6)
+        out.append(_monitor([10, 60, 300, 1800][m % 4], 1 << (8 + m % 7), 4, 131_072, 8,
+                            sle // (4 * 1024), 1024, cfg_no * 1000 + m))
+    return out
