@@ -114,9 +114,15 @@ def run_batched(args):
                 m.scan(buf)
 
     buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
+    tuned = None
     t_w = time.perf_counter()
     for s in range(args.warmup):
         ds.generate(s, out=buf, stream=st)
+        if s == 0 and fused and args.autotune:
+            from paper_1803_10369_amd import autotune
+            tuned = autotune.tune_group(mons, buf)
+            grp.close()
+            grp = srla.Group(mons, scan_blocks=tuned["scan_blocks"])
         scan_all(buf)
         for m in mons:
             m.estimate(copy=False)
@@ -184,7 +190,7 @@ def run_batched(args):
                                 "DR cells, thresholds 256..16384" % (args.mode, n_pairs,
                                                                     stream.alpha, stream.n_ranks)),
                    "mode": args.mode, "monitors": len(mons), "pairs_per_slice": n_pairs,
-                   "scan_blocks": args.scan_blocks},
+                   "scan_blocks": args.scan_blocks, "autotune": tuned},
         "monitor_pairs_per_s": value * len(mons),
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
     }
@@ -199,12 +205,109 @@ def run_batched(args):
         m.close()
 
 
+def run_serving(args):
+    """The serving mix: 64 monitors of uneven sizes (LE 2^24..2^33 DR cells)
+    admitted first-fit under a device-memory budget, over a bursting stream
+    (2M-32M pairs per slice, per-slice Zipf exponent 0.90-1.30, 1,000
+    planted super points).  --mode batched: one fused scan per slice, every
+    member closed at once; --mode plain: each admitted monitor scans and
+    estimates on its own, one after another."""
+    import numpy as np
+    import torch
+
+    import paper_1803_10369_amd as srla
+    from trafficgen.configs import ServingStream, serving_monitors
+    from trafficgen.device import DeviceStream
+
+    torch.cuda.set_device(0)
+    ss = ServingStream()
+    cfg_all = serving_monitors(64)
+    cfgs = [srla.make_config(**c, max_candidates=args.max_candidates) for c in cfg_all]
+    budget = int(args.budget_gb * 1e9)
+    rc, admitted, used = srla.srla_admit(cfgs, budget)
+    assert rc == 0
+    chosen = [c for c, a in zip(cfg_all, admitted) if a]
+    st = torch.cuda.Stream()
+    torch.cuda.set_stream(st)
+    fused = args.mode != "plain"
+    mons = [srla.Monitor(**c, max_candidates=args.max_candidates, stream=st, graph=True)
+            for c in chosen]
+    grp = srla.Group(mons) if fused else None
+    dstreams = {a: DeviceStream(sp) for a, sp in ss.specs.items()}
+    print("admitted %d of %d monitors, %.1f GB of %.1f GB" % (len(mons), len(cfg_all), used / 1e9,
+                                                           budget / 1e9), file=sys.stderr,
+          flush=True)
+
+    def gen(s, out):
+        n, a = ss.params(s)
+        ss.spec(s)
+        dstreams[a].generate(s, out=out, stream=st)
+        return out[:2 * n]
+
+    def one_slice(pairs):
+        if fused:
+            grp.scan(pairs)
+            st.synchronize()
+            ts = time.perf_counter()
+            for m in mons:
+                m.close_slice()
+            for m in mons:
+                m.wait_report(copy=False)
+        else:
+            for m in mons:
+                m.scan(pairs)
+            st.synchronize()
+            ts = time.perf_counter()
+            for m in mons:
+                m.estimate(copy=False)
+        return (time.perf_counter() - ts) * 1e3
+
+    buf = torch.empty(2 * ss.hi, dtype=torch.int32, device="cuda")
+    for s in range(args.warmup):
+        one_slice(gen(s, buf))
+        print("warmup slice %d" % s, file=sys.stderr, flush=True)
+    bufs = [torch.empty(2 * ss.hi, dtype=torch.int32, device="cuda") for _ in range(args.steps)]
+    views = [gen(args.warmup + i, bufs[i]) for i in range(args.steps)]
+    torch.cuda.synchronize()
+    lat, pairs = [], 0
+    t0 = time.perf_counter()
+    for i, v in enumerate(views):
+        lat.append(one_slice(v))
+        pairs += v.numel() // 2
+        print("timed slice %d (%d pairs)" % (i, v.numel() // 2), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    lat = np.array(lat)
+    out = {
+        "metric": METRIC, "value": pairs / total_s, "unit": "packets/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_s * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16",
+        "data": "synthetic",
+        "config": {"workload": ("serving64, %s form: %d of 64 monitors admitted under %.0f GB "
+                                "(LE 2^24..2^33 DR cells, u 4/8, windows 10..1800, thresholds "
+                                "256..16384); 2M-32M pairs/slice, Zipf 0.90-1.30, 1,000 planted"
+                                % (args.mode, len(mons), budget / 1e9)),
+                   "mode": args.mode, "admitted": len(mons),
+                   "rejected": [i for i, a in enumerate(admitted) if not a],
+                   "footprint_gb": used / 1e9},
+        "monitor_pairs_per_s": pairs * len(mons) / total_s,
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+    }
+    print(json.dumps(out), flush=True)
+    if grp:
+        grp.close()
+    for m in mons:
+        m.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", choices=("plain", "streaming", "batched"), default="plain")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay the end-of-slice pipeline as HIP graphs (default: streaming only)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="pick the scan kernel's form and workgroup cap by timing them first")
     ap.add_argument("--scan-blocks", type=int, default=0,
                     help="cap on the scan kernel's workgroups (0: one per tile)")
     ap.add_argument("--segment", type=int, default=200,
@@ -216,6 +319,8 @@ def main():
                     help="slices of the same workload the oracle baseline scans")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-candidates", type=int, default=1 << 25)
+    ap.add_argument("--budget-gb", type=float, default=200.0,
+                    help="device-memory budget for admitting the serving mix's monitors")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run one plain device copy of this many MiB (a known-size "
                          "reference for the HBM traffic counters)")
@@ -231,6 +336,8 @@ def main():
         sys.exit(2)
     if args.workload == "batched16":
         return run_batched(args)
+    if args.workload == "serving64":
+        return run_serving(args)
 
     import numpy as np
     import torch
@@ -255,9 +362,15 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     graph = (args.mode == "streaming") if args.graph < 0 else bool(args.graph)
+    buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
+    tuned = None
+    if args.autotune:
+        from paper_1803_10369_amd import autotune
+        ds.generate(0, out=buf, stream=st)
+        tuned = autotune.tune_scan(mon, buf, cache=None)
+        args.scan_xcd, args.scan_blocks = tuned["scan_xcd"], tuned["scan_blocks"]
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks)
-    buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
     t_w = time.perf_counter()
     for s in range(args.warmup):
         ds.generate(s, out=buf, stream=st)
@@ -348,6 +461,7 @@ def main():
             "window": g["k"], "theta": g["theta"], "pairs_per_slice": n_pairs,
             "slices_timed": [args.warmup, args.warmup + args.steps - 1],
             "mode": args.mode, "graph": graph, "scan_blocks": args.scan_blocks,
+            "scan_xcd": args.scan_xcd, "autotune": tuned,
         },
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),

@@ -154,6 +154,16 @@ typedef struct {
 uint64_t srla_footprint_bytes(const srla_config_t *cfg);
 
 /*
+ * Admission of monitors by device footprint: walks cfgs[0..n) in order and
+ * admits each one whose srla_footprint_bytes still fits in what remains of
+ * budget_bytes (first fit; a rejected monitor does not stop later, smaller
+ * ones).  admitted[i] is set to 1 or 0; *used_bytes to the admitted total.
+ * Host-only.  Errors: SRLA_E_INVAL (NULL arrays, an invalid config).
+ */
+int srla_admit(const srla_config_t *cfgs, uint32_t n, uint64_t budget_bytes, uint8_t *admitted,
+               uint64_t *used_bytes);
+
+/*
  * Creates a monitor on the current HIP device.  hip_stream is a hipStream_t
  * on which every operation of the monitor is issued; NULL makes the library
  * create (and later destroy) its own stream.  All DRs start as DRinit (never

@@ -7,7 +7,7 @@ Algorithm 3 slide of arXiv 1803.10369 -- runs in the HIP kernels of
 ctypes binding.
 """
 from .srla import (Monitor, Report, SrlaError, Group, srla_group_create, srla_group_scan,
-                   srla_group_destroy, srla_group_last_error, make_config, srla_create, srla_destroy,  # noqa: F401
+                   srla_group_destroy, srla_group_last_error, srla_admit, make_config, srla_create, srla_destroy,  # noqa: F401
                    srla_close_slice, srla_wait_report,
                    srla_dump_state, srla_estimate, srla_footprint_bytes, srla_last_error,
                    srla_scan, srla_timings, SRLA_DUMP_LE, SRLA_DUMP_RE, SRLA_DUMP_SI,

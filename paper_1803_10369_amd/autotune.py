@@ -1,0 +1,96 @@
+"""Autotuner for the scan kernel's launch shape.
+
+The scan (Algorithm 2) has two knobs that never change its results: the
+kernel form (flat, or per-XCD row ownership, SRLA_CFG_SCAN_XCD) and the cap
+on its workgroups (srla_config_t.scan_blocks).  tune_scan() times every
+candidate on a scratch monitor of the caller's geometry with the caller's
+pairs (stamp stores are idempotent, so rescanning the same pairs is a fair,
+repeatable measurement), picks the fastest, and caches the choice per
+(geometry, pairs per scan, device) in a JSON file.  tune_group() does the
+same for a monitor group's fused scan, on temporary groups over the caller's
+own monitors during an open slice (rescanning a slice's pairs leaves every
+result unchanged: stores are idempotent and repeated sampled sources are
+removed by the slice-end sort).
+"""
+import json
+import os
+
+import torch
+
+from . import srla
+
+DEFAULT_CANDIDATES = [(False, 0), (False, 1024), (False, 512), (True, 0), (True, 1024)]
+CACHE = os.path.join(os.path.expanduser("~"), ".cache", "srla_autotune.json")
+
+
+def _key(cfg, n_pairs):
+    dev = torch.cuda.get_device_name(0)
+    keys = ("u", "v_re", "g", "v_le", "G")
+    return "%s|%s|%d" % (dev, ",".join("%s=%d" % (k, cfg[k]) for k in keys), n_pairs)
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(path, table):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(table, f, indent=1)
+    os.replace(tmp, path)
+
+
+def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False):
+    """Returns {"scan_xcd": bool, "scan_blocks": int, "ms": float, "all": {...}}
+    for monitors of geometry `cfg` (Monitor keyword arguments) scanning
+    `pairs` (a CUDA tensor of 2n values) per call."""
+    n_pairs = pairs.numel() // 2
+    key = _key(cfg, n_pairs)
+    table = _load(cache) if cache else {}
+    if not refresh and key in table:
+        return table[key]
+    results = {}
+    for xcd, blocks in candidates or DEFAULT_CANDIDATES:
+        m = srla.Monitor(**cfg, max_candidates=64, timing=True, scan_xcd=xcd,
+                         scan_blocks=blocks)
+        m.scan(pairs)                    # warm the footprint
+        m.timings(reset=True)
+        for _ in range(repeats):
+            m.scan(pairs)
+        t = m.timings(reset=True)
+        m.close()
+        results["%s/%d" % ("xcd" if xcd else "flat", blocks)] = t["scan_ms"] / repeats
+    best = min(results, key=results.get)
+    form, blocks = best.split("/")
+    choice = {"scan_xcd": form == "xcd", "scan_blocks": int(blocks), "ms": results[best],
+              "all": results}
+    if cache:
+        table = _load(cache)
+        table[key] = choice
+        _save(cache, table)
+    return choice
+
+
+def tune_group(monitors, pairs, blocks_candidates=(0, 2048, 1024, 512), repeats=2):
+    """Picks scan_blocks for a group of `monitors` by timing the fused scan of
+    `pairs` (their open slice's pairs: call it before closing the slice)."""
+    st = monitors[0].stream
+    results = {}
+    for blocks in blocks_candidates:
+        g = srla.Group(monitors, scan_blocks=blocks)
+        g.scan(pairs)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(st)
+        for _ in range(repeats):
+            g.scan(pairs)
+        b.record(st)
+        b.synchronize()
+        results[blocks] = a.elapsed_time(b) / repeats
+        g.close()
+    best = min(results, key=results.get)
+    return {"scan_blocks": best, "ms": results[best], "all": results}

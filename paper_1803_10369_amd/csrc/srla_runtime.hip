@@ -414,6 +414,21 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
          candidate_bytes(cfg->max_candidates);
 }
 
+int srla_admit(const srla_config_t* cfgs, uint32_t n, uint64_t budget_bytes, uint8_t* admitted,
+               uint64_t* used_bytes) {
+  if ((n && (!cfgs || !admitted)) || !used_bytes) return SRLA_E_INVAL;
+  for (uint32_t i = 0; i < n; ++i)
+    if (!config_ok(&cfgs[i])) return SRLA_E_INVAL;
+  uint64_t used = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint64_t fp = srla_footprint_bytes(&cfgs[i]);
+    admitted[i] = (fp <= budget_bytes - used) ? 1 : 0;   // used <= budget always holds
+    if (admitted[i]) used += fp;
+  }
+  *used_bytes = used;
+  return SRLA_OK;
+}
+
 int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out) {
   if (!out) return SRLA_E_INVAL;
   if (!config_ok(cfg)) return SRLA_E_INVAL;

@@ -59,7 +59,7 @@ class srla_timings_t(ctypes.Structure):
 EXPORTS = ["srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
            "srla_close_slice", "srla_wait_report", "srla_dump_state", "srla_timings",
            "srla_destroy", "srla_last_error", "srla_group_create", "srla_group_scan",
-           "srla_group_destroy", "srla_group_last_error"]
+           "srla_group_destroy", "srla_group_last_error", "srla_admit"]
 
 _lib = None
 
@@ -100,6 +100,9 @@ def lib():
         L.srla_group_destroy.argtypes = [vp]
         L.srla_group_last_error.restype = ctypes.c_char_p
         L.srla_group_last_error.argtypes = [vp]
+        L.srla_admit.restype = ctypes.c_int
+        L.srla_admit.argtypes = [ctypes.POINTER(srla_config_t), ctypes.c_uint32, ctypes.c_uint64,
+                                 ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_uint64)]
         _lib = L
     return _lib
 
@@ -175,6 +178,15 @@ def srla_group_destroy(group):
 def srla_group_last_error(group):
     s = lib().srla_group_last_error(group)
     return s.decode() if s else ""
+
+
+def srla_admit(cfgs, budget_bytes):
+    """Returns (status, admitted flags, used bytes) for a list of srla_config_t."""
+    arr = (srla_config_t * len(cfgs))(*cfgs)
+    flags = (ctypes.c_uint8 * len(cfgs))()
+    used = ctypes.c_uint64()
+    rc = lib().srla_admit(arr, len(cfgs), budget_bytes, flags, ctypes.byref(used))
+    return rc, [bool(x) for x in flags], used.value
 
 
 # ---------------------------------------------------------------- convenience

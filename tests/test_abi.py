@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported(P):
                           "srla_close_slice", "srla_wait_report", "srla_dump_state",
                           "srla_timings", "srla_destroy", "srla_last_error",
                           "srla_group_create", "srla_group_scan", "srla_group_destroy",
-                          "srla_group_last_error"}
+                          "srla_group_last_error", "srla_admit"}
     L = ctypes.CDLL(P.srla.LIB_PATH)
     for n in names:
         assert hasattr(L, n), n
@@ -124,3 +124,26 @@ def test_product_never_imports_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "srla_oracle" not in text, f
+
+
+def test_admission_is_first_fit_under_the_budget(P):
+    from trafficgen.configs import serving_monitors
+    cfgs = [P.make_config(**m, max_candidates=1 << 22) for m in serving_monitors(64)]
+    fps = [P.srla_footprint_bytes(c) for c in cfgs]
+    budget = 200 * 10 ** 9
+    rc, adm, used = P.srla_admit(cfgs, budget)
+    assert rc == 0
+    # first fit, in order, recomputed here
+    left, want = budget, []
+    for fp in fps:
+        want.append(fp <= left)
+        if fp <= left:
+            left -= fp
+    assert adm == want and used == budget - left <= budget
+    assert 0 < sum(adm) < len(cfgs)          # the mix does not fit whole
+    rc, adm, used = P.srla_admit(cfgs, 0)
+    assert rc == 0 and not any(adm) and used == 0
+    rc, adm, used = P.srla_admit(cfgs[:3], 1 << 62)
+    assert all(adm) and used == sum(fps[:3])
+    bad = P.make_config(0, 1, 1, 1, 1, 1, 64, 0)
+    assert P.srla_admit([cfgs[0], bad], budget)[0] == -1

@@ -383,3 +383,30 @@ def test_stamps_survive_wraparound_of_the_slice_code():
         if s % 10000 == 0:
             print("slice", s, "%.1fs" % (time.time() - t0), flush=True)
     g.close()
+
+
+def test_autotuner_picks_a_valid_shape_and_results_do_not_change(tmp_path):
+    from paper_1803_10369_amd import autotune
+    stream, mon, _ = workload("tiny")
+    pairs = to_device(stream.slice(0))
+    cache = str(tmp_path / "tune.json")
+    choice = autotune.tune_scan(mon, pairs, repeats=2, cache=cache)
+    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "xcd/0", "xcd/1024"}
+    assert choice["ms"] == min(choice["all"].values()) > 0
+    assert autotune.tune_scan(mon, pairs, cache=cache) == choice      # served from the cache
+    _run(stream, mon, range(6), scan_xcd=choice["scan_xcd"])
+
+    st = torch.cuda.Stream()
+    gms = [srla.Monitor(**mon, max_candidates=1 << 16, stream=st) for _ in range(2)]
+    o = oracle.Monitor(**mon)
+    g_choice = autotune.tune_group(gms, pairs)
+    assert g_choice["scan_blocks"] in (0, 2048, 1024, 512)
+    grp = srla.Group(gms, scan_blocks=g_choice["scan_blocks"])
+    grp.scan(pairs)                       # the tuning scans were of this same open slice
+    o.scan(stream.slice(0))
+    rc = o.estimate()
+    for gm in gms:
+        compare_reports(gm.estimate(), rc, mon["theta"], "tuned group")
+    grp.close()
+    for gm in gms:
+        gm.close()

@@ -64,3 +64,56 @@ def batched_monitors(n=16, cfg_no=4):
         out.append(_monitor([10, 60, 300, 1800][m % 4], 1 << (8 + m % 7), 4, 131_072, 8,
                             sle // (4 * 1024), 1024, cfg_no * 1000 + m))
     return out
+
+
+ALPHA_GRID = [0.90, 0.95, 1.00, 1.05, 1.10, 1.15, 1.20, 1.25, 1.30]
+
+
+def serving_monitors(n=64, cfg_no=5):
+    """Monitors of the serving mix: LE 2^e DR cells with e drawn from
+    {24..33}, u in {4, 8}, window in {10, 60, 300, 1800}, threshold in
+    {256 .. 16,384}, g' = 1024, g = 8, v_re = 131,072 (seeded draws)."""
+    from . import mix64_int
+    out = []
+    for m in range(n):
+        r = [mix64_int(STREAM_SEED * 31 + cfg_no * 7919 + 97 * m + j) for j in range(4)]
+        e = 24 + r[0] % 10
+        u = 4 if r[1] % 2 == 0 else 8
+        k = [10, 60, 300, 1800][r[2] % 4]
+        theta = 1 << (8 + r[3] % 7)
+        out.append(_monitor(k, theta, u, 131_072, 8, (1 << e) // (u * 1024), 1024,
+                            cfg_no * 1000 + m))
+    return out
+
+
+class ServingStream:
+    """The serving mix's stream: slice s has n_s pairs (log-uniform on
+    [lo, hi]) and a Zipf exponent alpha_s drawn from ALPHA_GRID, over 2^24
+    hosts, with 1,000 planted super points of 1k-200k destinations spread
+    over a 300-slice window.  slice(s) / device generation delegate to one
+    StreamSpec per alpha, resized to n_s."""
+
+    def __init__(self, lo=2_000_000, hi=32_000_000, n_ranks=1 << 24, planted=1000, seed=None):
+        from . import StreamSpec, mix64_int
+        self.seed = STREAM_SEED + 5 if seed is None else seed
+        self.lo, self.hi = lo, hi
+        self.planted = loguniform_ints(1000, 200_000, planted, self.seed)
+        self.specs = {a: StreamSpec(n_pairs=hi, n_ranks=n_ranks, alpha=a, planted=self.planted,
+                                    window=300, seed=self.seed) for a in ALPHA_GRID}
+        self._mix = mix64_int
+
+    def params(self, s):
+        """(n_s, alpha_s) of slice s."""
+        import math
+        r1 = self._mix(self.seed ^ (0xA5A5 + 2 * s))
+        r2 = self._mix(self.seed ^ (0xA5A5 + 2 * s + 1))
+        uu = (r1 >> 11) / float(1 << 53)
+        n = int(round(math.exp(math.log(self.lo) + uu * (math.log(self.hi) - math.log(self.lo)))))
+        return n, ALPHA_GRID[r2 % len(ALPHA_GRID)]
+
+    def spec(self, s):
+        """The StreamSpec that generates slice s (its n_pairs set to n_s)."""
+        n, a = self.params(s)
+        sp = self.specs[a]
+        sp.n_pairs = n
+        return sp
