@@ -25,7 +25,7 @@ class _Config(ctypes.Structure):
                 ("u", ctypes.c_uint32), ("v_re", ctypes.c_uint32),
                 ("g", ctypes.c_uint32), ("v_le", ctypes.c_uint32),
                 ("G", ctypes.c_uint32), ("hash_seed", ctypes.c_uint64),
-                ("max_candidates", ctypes.c_uint64)]
+                ("max_candidates", ctypes.c_uint64), ("sequential", ctypes.c_uint32)]
 
 
 class _Report(ctypes.Structure):
@@ -151,8 +151,10 @@ class OracleError(RuntimeError):
 class Monitor:
     """One SRLA monitor: a SEA of u rows, fed slice by slice."""
 
-    def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 26):
-        self.cfg = _Config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates)
+    def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 26,
+                 sequential=False):
+        self.cfg = _Config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates,
+                           int(bool(sequential)))
         self._h = lib().orc_create(ctypes.byref(self.cfg))
         if not self._h:
             raise ValueError("invalid oracle configuration")

@@ -89,7 +89,8 @@ def lsb_array(x):
 class BruteForce:
     """Last-touch bookkeeping of a whole stream, one closed slice at a time."""
 
-    def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed):
+    def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, sequential=False):
+        self.sequential = sequential
         self.k, self.theta = k, theta
         self.u, self.v_re, self.g, self.v_le, self.G = u, v_re, g, v_le, G
         self.h = Hashes(hash_seed, u, v_re, g, v_le, G)
@@ -154,17 +155,37 @@ class BruteForce:
         sampled = lsb_array(self.h.h1(bip)) >= self.tau
         sa, sb = aip[sampled], bip[sampled]
         reidx = self.h.re_idx(sb)
-        for i in range(self.u):
-            self.last_re[self.re_cells(i, sa, reidx)] = e
         touched = np.unique(sa)
-
         si_start = self._si_bits(self.ncsip)
-        W_t = self._ure(touched, e)
-        usi = np.full(touched.size, 0xFFFF, dtype=np.uint16)
-        for i in range(self.u):
-            usi &= si_start[i * self.v_re + self.h.col_re(i, touched)]
-        bit_clear = ((usi >> self.h.si_idx(touched).astype(np.uint16)) & 1) == 0
-        new = touched[(W_t >= self.t_re) & bit_clear]
+        if self.sequential:
+            # Algorithm 2 literally: after each sampled pair's SRE update, the
+            # host is checked against the state at that moment and, if new,
+            # inserted with its SI bits set at once
+            si = si_start.copy()
+            new = []
+            for a, r in zip(sa.tolist(), reidx.tolist()):
+                a_arr = np.array([a], dtype=np.uint32)
+                for i in range(self.u):
+                    self.last_re[self.re_cells(i, a_arr, np.array([r]))] = e
+                w = self._ure(a_arr, e)[0]
+                bit = int(self.h.si_idx(a_arr)[0])
+                usi = 0xFFFF
+                for i in range(self.u):
+                    usi &= int(si[i * self.v_re + self.h.col_re(i, a_arr)[0]])
+                if w >= self.t_re and not (usi >> bit) & 1:
+                    new.append(a)
+                    for i in range(self.u):
+                        si[i * self.v_re + self.h.col_re(i, a_arr)[0]] |= np.uint16(1 << bit)
+            new = np.unique(np.array(new, dtype=np.uint32))
+        else:
+            for i in range(self.u):
+                self.last_re[self.re_cells(i, sa, reidx)] = e
+            W_t = self._ure(touched, e)
+            usi = np.full(touched.size, 0xFFFF, dtype=np.uint16)
+            for i in range(self.u):
+                usi &= si_start[i * self.v_re + self.h.col_re(i, touched)]
+            bit_clear = ((usi >> self.h.si_idx(touched).astype(np.uint16)) & 1) == 0
+            new = touched[(W_t >= self.t_re) & bit_clear]
         csip = np.union1d(self.ncsip, new).astype(np.uint32)
 
         cells = self.v_le * self.G

@@ -26,7 +26,10 @@
  *  candidates    Slice-synchronous: at the end of slice t every source with at
  *                least one sampled pair in t is checked once against the
  *                end-of-slice SRE and against SI as Algorithm 3 left it; the
- *                candidate list is kept in ascending order.
+ *                candidate list is kept in ascending order.  (With
+ *                cfg.sequential the check runs after every sampled pair in
+ *                stream order instead, inserting and marking SI at once --
+ *                Algorithm 2 taken literally; used to measure the reading.)
  *  union DRs     Algorithm 1 starts the union SRE/LE DRs at 2^z-1 and joins
  *                with max, which would leave them at 2^z-1; the union DR is
  *                read as the max over the u rows (the join's identity is 0).
@@ -56,6 +59,7 @@ struct orc_monitor {
     int poisoned;
 
     uint32_t *touched; uint64_t n_touched, cap_touched;
+    uint32_t *seq_new; uint64_t n_seq_new, cap_seq_new;   /* sequential mode's N_t */
     uint32_t *ncsip;   uint64_t n_ncsip;          /* ascending */
 
     /* report storage, valid until the next estimate */
@@ -216,7 +220,7 @@ void orc_destroy(orc_monitor *m)
 {
     if (!m) return;
     free(m->RE); free(m->LE); free(m->SI);
-    free(m->touched); free(m->ncsip);
+    free(m->touched); free(m->ncsip); free(m->seq_new);
     free(m->r_ip); free(m->r_est); free(m->r_flags); free(m->r_U); free(m->r_W);
     free(m);
 }
@@ -224,6 +228,10 @@ void orc_destroy(orc_monitor *m)
 uint64_t orc_slice(const orc_monitor *m) { return m->slice; }
 
 /* ---------------------------------------------- Algorithm 2: ScanIPpair */
+
+static uint32_t union_re_weight(const orc_monitor *m, uint32_t aip);
+static uint16_t union_si(const orc_monitor *m, uint32_t aip);
+static void set_si_bits(orc_monitor *m, uint32_t aip);
 
 static int scan_pair(orc_monitor *m, uint32_t aip, uint32_t bip)
 {
@@ -241,6 +249,19 @@ static int scan_pair(orc_monitor *m, uint32_t aip, uint32_t bip)
     reidx = H2(m, bip);
     for (i = 0; i < m->cfg.u; i++)
         DRset(&RE_dr(m, i, col_re(m, i, aip))[reidx]);
+
+    /* Algorithm 2 taken literally: check the host right away */
+    if (m->cfg.sequential && union_re_weight(m, aip) >= m->t_re &&
+        ((union_si(m, aip) >> H4(m, aip)) & 1u) == 0) {
+        if (m->n_seq_new == m->cap_seq_new) {
+            uint64_t nc = m->cap_seq_new ? 2 * m->cap_seq_new : 1024;
+            uint32_t *p = (uint32_t *)realloc(m->seq_new, nc * sizeof(uint32_t));
+            if (!p) return -2;
+            m->seq_new = p; m->cap_seq_new = nc;
+        }
+        m->seq_new[m->n_seq_new++] = aip;
+        set_si_bits(m, aip);
+    }
 
     /* the candidate check runs at the end of the slice (slice-synchronous
        reading); remember that aip was sampled in this slice */
@@ -365,11 +386,19 @@ int orc_estimate(orc_monitor *m, orc_report *out)
 
     /* Algorithm 2's candidate check: super by the union SRE, and its own SI
        bit still clear in the union SI left by the previous Algorithm 3 */
-    for (x = 0; x < n_uniq; x++) {
-        uint32_t aip = uniq[x];
-        if (union_re_weight(m, aip) >= m->t_re &&
-            ((union_si(m, aip) >> H4(m, aip)) & 1u) == 0)
-            news[n_new++] = aip;
+    if (m->cfg.sequential) {
+        /* already checked pair by pair; each host was inserted once (its own
+           SI bits were set at insertion) */
+        if (m->n_seq_new > m->n_touched) { rc = -2; goto done; }
+        for (x = 0; x < m->n_seq_new; x++) news[n_new++] = m->seq_new[x];
+        qsort(news, n_new, sizeof(uint32_t), cmp_u32);
+    } else {
+        for (x = 0; x < n_uniq; x++) {
+            uint32_t aip = uniq[x];
+            if (union_re_weight(m, aip) >= m->t_re &&
+                ((union_si(m, aip) >> H4(m, aip)) & 1u) == 0)
+                news[n_new++] = aip;
+        }
     }
 
     /* CSIP of this slice: the carried list plus the new candidates */
@@ -465,6 +494,7 @@ int orc_estimate(orc_monitor *m, orc_report *out)
 
 done:
     m->n_touched = 0;
+    m->n_seq_new = 0;
     free(uniq);
     free(news);
     return rc;

@@ -35,6 +35,9 @@ typedef struct {
     uint32_t G;          /* DRs per LE (the paper's g'), multiple of 64 */
     uint64_t hash_seed;  /* SplitMix64 seed for all hash parameters */
     uint64_t max_candidates;
+    uint32_t sequential; /* 0: slice-synchronous candidate check (the reading
+                            both implementations share); 1: Algorithm 2's
+                            check after every sampled pair, in stream order */
 } orc_config;
 
 /* flags of one reported candidate */

@@ -77,3 +77,20 @@ def test_scan_in_pieces_equals_one_scan():
         assert np.array_equal(ra.ip, rb.ip) and np.array_equal(ra.est, rb.est)
     for w in (0, 1, 2):
         assert np.array_equal(a.dump(w), b.dump(w))
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[5]])
+def test_sequential_mode_matches_brute_force(case):
+    """Algorithm 2's per-pair candidate check in stream order (the oracle's
+    optional sequential mode) against a second, pure-Python implementation."""
+    k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
+    cfg = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=2000 + k)
+    m = oracle.Monitor(**cfg, sequential=True)
+    bf = BruteForce(**cfg, sequential=True)
+    rng = np.random.default_rng(k * 17 + u)
+    for s in range(min(slices, 6)):
+        pairs = _stream(rng, min(n, 1500), n_src, heavy=[(7, 3 * theta // 2)] if s < 3 else ())
+        m.scan(pairs)
+        _compare(m.estimate(), bf.close_slice(pairs))
+        for which in (oracle.LE, oracle.RE, oracle.SI):
+            assert np.array_equal(m.dump(which), bf.dump(which)), which

@@ -16,7 +16,10 @@ and ``j``):
   in the cumulative table ``thr`` (uint64, scaled to 2^63) as the number of
   entries ``<= x``.  Rank r maps to the IPv4 ``(r * 0x9E3779B1 mod 2^32) ^
   0x5A5A5A5A``, a bijection.
-* Second addresses (bip) are uniform 32-bit: the low half of ``sm(DST, c)``.
+* Second addresses (bip) are uniform 32-bit: the low half of ``sm(DST, c)``;
+  with ``dst_pool = q > 0`` an ordinary source of rank r instead draws from
+  its own q addresses ``perm32(key ^ DPOOL, r * q + (sm(DST, c) mod q))``
+  (distinct across sources), so it has at most q distinct peers.
 * Planted super points ``p < P`` use ranks ``N + p`` (outside the Zipf
   support), each with a pool of ``D_p`` distinct second addresses
   ``perm32(key, (p << 18) | x)``.  Slice ``s`` sends ``m_p = ceil(D_p / k)``
@@ -36,6 +39,7 @@ M64 = (1 << 64) - 1
 SRC_SALT = 0x5352435F53524C41
 DST_SALT = 0x4453545F53524C41
 POOL_SALT = 0x504F4F4C53524C41
+DPOOL_XOR = 0x6D2B79F5
 PERM_SALT = 0x5045524D53524C41
 IP_MULT = 0x9E3779B1
 IP_XOR = 0x5A5A5A5A
@@ -98,6 +102,7 @@ class StreamSpec:
     planted: list = field(default_factory=list)   # D_p of each planted host
     window: int = 1                                # k used to spread the pools
     seed: int = 0
+    dst_pool: int = 0                              # 0: uniform destinations
 
     def __post_init__(self):
         assert all(1 <= d < (1 << POOL_BITS) for d in self.planted)
@@ -142,7 +147,12 @@ class StreamSpec:
         x = _sm_at(self.seed ^ SRC_SALT, ctr) >> np.uint64(1)
         rank = np.searchsorted(self.thr, x, side="right")
         out[:, 0] = rank_to_ip(rank)
-        out[:, 1] = (_sm_at(self.seed ^ DST_SALT, ctr) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+        dst = _sm_at(self.seed ^ DST_SALT, ctr) & np.uint64(0xFFFFFFFF)
+        if self.dst_pool:
+            q = np.uint64(self.dst_pool)
+            idx = (rank.astype(np.uint64) * q + dst % q) & np.uint64(0xFFFFFFFF)
+            dst = _perm32(self.pool_key ^ DPOOL_XOR, idx.astype(np.uint32)).astype(np.uint64)
+        out[:, 1] = dst.astype(np.uint32)
         pl = i < np.uint64(self.n_planted_pairs)
         if pl.any():
             ii = i[pl].astype(np.int64)

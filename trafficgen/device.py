@@ -19,7 +19,8 @@ def _load():
         L = ctypes.CDLL(LIB)
         u64, u32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p
         L.tg_generate.restype = ctypes.c_int
-        L.tg_generate.argtypes = [vp, u64, u64, u64, u64, u64, vp, u32, vp, vp, vp, u32, u32, vp]
+        L.tg_generate.argtypes = [vp, u64, u64, u64, u64, u64, vp, u32, vp, vp, vp, u32, u32, u32,
+                                  vp]
         _lib = L
     return _lib
 
@@ -54,7 +55,7 @@ class DeviceStream:
             ctypes.c_void_p(self.off.data_ptr()) if self.P else None,
             ctypes.c_void_p(self.mp.data_ptr()) if self.P else None,
             ctypes.c_void_p(self.dp.data_ptr()) if self.P else None,
-            self.P, self.spec.pool_key, ctypes.c_void_p(st.cuda_stream))
+            self.P, self.spec.pool_key, self.spec.dst_pool, ctypes.c_void_p(st.cuda_stream))
         if rc != 0:
             raise RuntimeError("tg_generate failed with %d" % rc)
         return out

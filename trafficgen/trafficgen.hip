@@ -12,6 +12,7 @@ constexpr uint64_t kDstSalt = 0x4453545F53524C41ull;
 constexpr uint32_t kIpMult = 0x9E3779B1u;
 constexpr uint32_t kIpXor = 0x5A5A5A5Au;
 constexpr uint32_t kPoolBits = 18;
+constexpr uint32_t kDstPoolXor = 0x6D2B79F5u;
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -45,7 +46,7 @@ __global__ __launch_bounds__(256) void k_generate(uint32_t* __restrict__ out, ui
                                                  const uint32_t* __restrict__ off,
                                                  const uint32_t* __restrict__ mp,
                                                  const uint32_t* __restrict__ dp, uint32_t P,
-                                                 uint32_t pool_key) {
+                                                 uint32_t pool_key, uint32_t dst_pool) {
   const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= n) return;
   const uint64_t i = (pa * j + pb) % n;
@@ -72,6 +73,7 @@ __global__ __launch_bounds__(256) void k_generate(uint32_t* __restrict__ out, ui
     }
     src = rank_to_ip(lo);
     dst = (uint32_t)sm_at(seed ^ kDstSalt, ctr);
+    if (dst_pool) dst = perm32(pool_key ^ kDstPoolXor, lo * dst_pool + dst % dst_pool);
   }
   out[2 * j] = src;
   out[2 * j + 1] = dst;
@@ -82,12 +84,13 @@ __global__ __launch_bounds__(256) void k_generate(uint32_t* __restrict__ out, ui
 extern "C" int tg_generate(uint32_t* out_pairs, uint64_t n, uint64_t slice, uint64_t seed,
                            uint64_t perm_a, uint64_t perm_b, const uint64_t* thr,
                            uint32_t n_ranks, const uint32_t* off, const uint32_t* mp,
-                           const uint32_t* dp, uint32_t P, uint32_t pool_key, void* stream) {
+                           const uint32_t* dp, uint32_t P, uint32_t pool_key, uint32_t dst_pool,
+                           void* stream) {
   if (n == 0) return 0;
   if (!out_pairs || !thr || n_ranks == 0 || (P && (!off || !mp || !dp))) return -1;
   const uint64_t blocks = (n + 255) / 256;
   hipLaunchKernelGGL(k_generate, dim3((uint32_t)blocks), dim3(256), 0, (hipStream_t)stream,
                      out_pairs, n, slice, seed, perm_a, perm_b, thr, n_ranks, off, mp, dp, P,
-                     pool_key);
+                     pool_key, dst_pool);
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
