@@ -44,6 +44,18 @@ def workload(name):
         else:
             mon = _monitor(k, 1024, 8, 131_072, 8, 2048, 1024, 2)
         return stream, mon, 320
+    if name in ("accuracy", "accuracy_small"):
+        # unsaturated backbone-shaped stream for detection accuracy: ordinary
+        # sources draw from 4 destinations each, 100 planted super points of
+        # 1k-50k destinations; the paper's SEA (u = 4, v = 65,536, g' = 1024)
+        small = name == "accuracy_small"
+        planted = loguniform_ints(1000, 50_000, 100, STREAM_SEED + 6)
+        k = 8 if small else 30
+        stream = StreamSpec(n_pairs=200_000 if small else 1_000_000,
+                            n_ranks=1 << (18 if small else 20), alpha=1.05,
+                            planted=planted, window=k, seed=STREAM_SEED + 6, dst_pool=4)
+        v = 4096 if small else 65_536
+        return stream, _monitor(k, 1024, 4, v, 8, v, 1024, 6), (3 * k if small else 90)
     raise KeyError(name)
 
 
