@@ -55,9 +55,17 @@ enum {
     SRLA_CFG_SCAN_XCD = 2, /* scan with per-XCD row ownership (each XCD stores
                               into its own SEA rows); results are identical
                               either way, only the speed differs */
-    SRLA_CFG_GRAPH = 4     /* record the end-of-slice pipeline once per slice
+    SRLA_CFG_GRAPH = 4,    /* record the end-of-slice pipeline once per slice
                               parity as HIP graphs and replay them; results
                               are identical either way */
+    SRLA_CFG_DISCRETE = 8  /* the discrete-window form (Section 3.2: with
+                              k = 1 a one-bit DR suffices; Section 5.1 runs
+                              it with z = 1): every DR is one bit, set by the
+                              scan and cleared at the slice's end.  Requires
+                              window_slices == 1; reports are identical to
+                              the 16-bit form's at k = 1.  SRLA_CFG_SCAN_XCD
+                              has no effect; such monitors cannot join a
+                              group */
 };
 
 /*
@@ -187,6 +195,8 @@ int srla_create(const srla_config_t *cfg, void *hip_stream, srla_monitor_t **out
  * SRLA_E_STATE (poisoned), SRLA_E_NOMEM, SRLA_E_DEVICE.
  */
 int srla_scan(srla_monitor_t *m, const uint32_t *pairs, uint64_t n, int on_device);
+/* (In the discrete form the SRE and LE of the open slice are fresh bit
+   arrays; the scan ORs bits into them.) */
 
 /*
  * Closes the open slice e and fills *out with its report (Section 4.2 and
@@ -223,6 +233,8 @@ int srla_wait_report(srla_monitor_t *m, srla_report_t *out);
  *   each value is the DR's distance in slices (Section 3.2), with distances
  *   of 32768 and more (and never-set DRs) written as 65535.
  * which = SRLA_DUMP_SI: u*v_re raw 16-bit SI words, layout [row][column].
+ * In the discrete form a DR is one bit and its distance is written as 0
+ * (set in the open slice), 1 (set only in the slice closed last) or 65535.
  * cells must equal the array's size.  Blocks until the copy is done.
  */
 int srla_dump_state(srla_monitor_t *m, int which, uint16_t *host_out, uint64_t cells);
@@ -237,8 +249,8 @@ int srla_timings(srla_monitor_t *m, srla_timings_t *out, int reset);
  * of every member; it is equivalent to srla_scan on each member with the
  * same pairs.  Slices are still closed and reported per member
  * (srla_close_slice / srla_wait_report / srla_estimate).
- * srla_group_create: 1..64 distinct monitors that share one scan stream;
- *   scan_blocks as in srla_config_t.  The group does not own the monitors;
+ * srla_group_create: 1..64 distinct monitors that share one scan stream,
+ *   none of them in the discrete form; scan_blocks as in srla_config_t.  The group does not own the monitors;
  *   destroy the group before any member.
  * srla_group_scan: pairs as for srla_scan, device memory only (on_device
  *   must be nonzero).  Errors: SRLA_E_INVAL, SRLA_E_STATE (a member is

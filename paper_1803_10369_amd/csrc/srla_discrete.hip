@@ -1,0 +1,161 @@
+// gfx950 kernels of the discrete-window form of the SRLA hot path (arXiv
+// 1803.10369): k = 1 with one-bit DRs.  Section 3.2 notes that one bit per DR
+// is enough when the window is a single slice, and Section 5.1 runs the
+// discrete-window experiments so (z = 1); the SE array then holds bit arrays,
+// the slide clears them, and the LE becomes the classic linear counter of
+// Eq6.  Only the scan and the row fills differ from the 16-bit stamp form:
+// the bit arrays have exactly the layout of the activity bitmaps that the
+// end-of-slice kernels (finalize, estimate) read, so those run unchanged.
+#include "srla_discrete.h"
+
+namespace srla {
+
+constexpr int kBitSteps = 4;
+constexpr uint64_t kBitTile = (uint64_t)kBlock * 2 * kBitSteps;  // pairs per block
+
+// ------------------------------------------------------------------ scan
+// Algorithm 2 with one-bit DRs.  A DR is set by an atomic OR into 32-bit words of a flat bit array over [u][v][G] (LE) or
+// [u][v_re][g] (SRE) -- the same layout as the activity bitmaps that the
+// end-of-slice kernels read, so those kernels read these arrays directly.
+// Bits from different pairs share words, hence the atomics (device scope,
+// relaxed: only the kernel boundary orders them with the readers).
+
+__device__ __forceinline__ void set_bit(uint64_t* __restrict__ bits, uint64_t i) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(bits) + (i >> 5);
+  __hip_atomic_fetch_or(w, 1u << (uint32_t)(i & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int U>
+__device__ __forceinline__ void scan_one_bits(uint32_t a, uint32_t b, bool valid, const Geo& geo,
+                                              uint64_t* __restrict__ lebits,
+                                              uint64_t* __restrict__ rebits,
+                                              uint32_t* __restrict__ touched,
+                                              uint32_t* __restrict__ tcount) {
+  const uint32_t nu = U > 0 ? (uint32_t)U : geo.u;
+  bool sampled = false;
+  if (valid) {
+    const uint32_t lei = hrange(mas(geo.h3, b), geo.G);
+#pragma unroll
+    for (uint32_t i = 0; i < nu; ++i) {
+      const uint32_t col = hrange(mas(geo.rh[i], a), geo.v_le);
+      set_bit(lebits, ((uint64_t)i * geo.v_le + col) * geo.G + lei);
+    }
+    sampled = (mas(geo.h1, b) & geo.tau_mask) == 0u;
+    if (sampled) {
+      const uint32_t rei = hrange(mas(geo.h2, b), geo.g);
+#pragma unroll
+      for (uint32_t i = 0; i < nu; ++i) {
+        const uint32_t col = hrange(mas(geo.rh[i], a), geo.v_re);
+        set_bit(rebits, ((uint64_t)i * geo.v_re + col) * geo.g + rei);
+      }
+    }
+  }
+  const uint64_t mask = __ballot(sampled);
+  if (mask != 0ull) {
+    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
+    uint32_t base = 0;
+    if (__lane_id() == leader) base = atomicAdd(tcount, (uint32_t)__popcll(mask));
+    base = __shfl(base, (int)leader);
+    if (sampled) touched[base + lane_rank(mask)] = a;
+  }
+}
+
+template <int U, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_scan_bits(const uint32_t* __restrict__ pairs,
+                                                     uint64_t n, Geo geo,
+                                                     uint64_t* __restrict__ lebits,
+                                                     uint64_t* __restrict__ rebits,
+                                                     uint32_t* __restrict__ touched,
+                                                     uint32_t* __restrict__ tcount) {
+  for (uint64_t base = (uint64_t)blockIdx.x * kBitTile; base < n;
+       base += (uint64_t)gridDim.x * kBitTile) {
+    uint32_t a[kBitSteps][2], b[kBitSteps][2];
+    bool v[kBitSteps][2];
+#pragma unroll
+    for (int s = 0; s < kBitSteps; ++s) {
+      const uint64_t p = base + (uint64_t)s * (2 * kBlock) + 2u * threadIdx.x;
+      v[s][0] = p < n;
+      v[s][1] = p + 1 < n;
+      if (VEC && v[s][1]) {
+        const uint4 q = *reinterpret_cast<const uint4*>(pairs + 2 * p);
+        a[s][0] = q.x; b[s][0] = q.y; a[s][1] = q.z; b[s][1] = q.w;
+      } else {
+        a[s][0] = v[s][0] ? pairs[2 * p] : 0u;
+        b[s][0] = v[s][0] ? pairs[2 * p + 1] : 0u;
+        a[s][1] = v[s][1] ? pairs[2 * p + 2] : 0u;
+        b[s][1] = v[s][1] ? pairs[2 * p + 3] : 0u;
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kBitSteps; ++s) {
+      scan_one_bits<U>(a[s][0], b[s][0], v[s][0], geo, lebits, rebits, touched, tcount);
+      scan_one_bits<U>(a[s][1], b[s][1], v[s][1], geo, lebits, rebits, touched, tcount);
+    }
+  }
+}
+
+template <int U>
+static hipError_t launch_scan_bits_u(const uint32_t* pairs, uint64_t n, const Geo& geo,
+                                     uint64_t* lebits, uint64_t* rebits, uint32_t* touched,
+                                     uint32_t* tcount, uint32_t max_blocks, hipStream_t st) {
+  uint64_t blocks = (n + kBitTile - 1) / kBitTile;
+  if (max_blocks && blocks > max_blocks) blocks = max_blocks;
+  if (((uintptr_t)pairs & 15u) == 0)
+    hipLaunchKernelGGL((k_scan_bits<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st,
+                       pairs, n, geo, lebits, rebits, touched, tcount);
+  else
+    hipLaunchKernelGGL((k_scan_bits<U, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, st,
+                       pairs, n, geo, lebits, rebits, touched, tcount);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_bits(const uint32_t* pairs, uint64_t n, const Geo& geo, uint64_t* lebits,
+                            uint64_t* rebits, uint32_t* touched, uint32_t* tcount,
+                            uint32_t max_blocks, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  switch (geo.u) {
+    case 4: return launch_scan_bits_u<4>(pairs, n, geo, lebits, rebits, touched, tcount, max_blocks, st);
+    case 8: return launch_scan_bits_u<8>(pairs, n, geo, lebits, rebits, touched, tcount, max_blocks, st);
+    default: return launch_scan_bits_u<0>(pairs, n, geo, lebits, rebits, touched, tcount, max_blocks, st);
+  }
+}
+
+// ------------------------------------------------------------------ row fills
+// |LDR(i)|^k: the LE is already a bit array
+// (one bit per DR, rows of v_le*G bits = whole 64-bit words), so the row
+// fill is a popcount.  Grid: x = chunks of a row, y = row.
+constexpr int kPopSteps = 4;
+
+__global__ __launch_bounds__(kBlock) void k_row_popcount(const uint64_t* __restrict__ bits,
+                                                        uint64_t row_words,
+                                                        unsigned long long* __restrict__ row_fill) {
+  const uint32_t row = blockIdx.y;
+  const uint64_t* rowp = bits + (uint64_t)row * row_words;
+  uint32_t count = 0;
+#pragma unroll
+  for (int s = 0; s < kPopSteps; ++s) {
+    const uint64_t w = (uint64_t)blockIdx.x * (kBlock * kPopSteps) + (uint64_t)s * kBlock + threadIdx.x;
+    if (w < row_words) count += (uint32_t)__popcll(rowp[w]);
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) count += __shfl_xor(count, off);
+  __shared__ uint32_t part[kBlock / kWave];
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  if (lane == 0) part[threadIdx.x / kWave] = count;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+    if (t) atomicAdd(&row_fill[row], t);
+  }
+}
+
+hipError_t launch_row_popcount(const uint64_t* bits, unsigned long long* row_fill,
+                               const Geo& geo, hipStream_t st) {
+  const uint64_t row_words = (uint64_t)geo.v_le * geo.G / 64;
+  const uint64_t bx = (row_words + kBlock * kPopSteps - 1) / (kBlock * kPopSteps);
+  hipLaunchKernelGGL(k_row_popcount, dim3((uint32_t)bx, geo.u), dim3(kBlock), 0, st, bits,
+                     row_words, row_fill);
+  return hipGetLastError();
+}
+
+}  // namespace srla

@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/srla.h"
+#include "srla_discrete.h"
 #include "srla_internal.h"
 
 using namespace srla;
@@ -66,8 +67,10 @@ bool config_ok(const srla_config_t* c) {
   if (c->window_slices < 1 || c->window_slices > 32767) return false;
   if (c->threshold < 1) return false;
   if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
-  if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH)) != 0)
+  if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH |
+                              SRLA_CFG_DISCRETE)) != 0)
     return false;
+  if ((c->flags & SRLA_CFG_DISCRETE) && c->window_slices != 1) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   if (le / g.u / g.g_le != g.v_le || re / g.u / g.g != g.v_re) return false;
@@ -100,8 +103,11 @@ struct srla_monitor {
   std::string err;
 
   // SEA and its per-slice views
-  uint16_t* le = nullptr;
+  uint16_t* le = nullptr;        // stamps (not allocated in the discrete form)
   uint16_t* re = nullptr;
+  bool discrete = false;         // k = 1 with one bit per DR
+  uint64_t* lebits[2] = {nullptr, nullptr};  // discrete form: LE / SRE bits by slice parity
+  uint64_t* rebits[2] = {nullptr, nullptr};
   uint32_t* si_cnt = nullptr;    // [u][v_re][16] counters; SI bit = counter > 0
   uint64_t n_le = 0, n_re = 0, n_si = 0;
   uint64_t* bitmap = nullptr;    // LE DRs inside the window
@@ -309,6 +315,18 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
   const Geo& geo = m->geo;
   hipStream_t st = m->pipe;
   hipError_t e = hipSuccess;
+  if (phase == PH_SNAPSHOT && m->discrete) {
+    // the closing slice's bits are its activity maps already; the other
+    // parity's (the previous slice's) are cleared for the next slice's scans
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st);
+    if (e == hipSuccess) e = launch_row_popcount(m->lebits[p], m->row_fill, geo, st);
+    if (e == hipSuccess) e = launch_union_prob(m->row_fill, geo, m->up, st);
+    if (e == hipSuccess)
+      e = launch_fill_u32((uint32_t*)m->lebits[p ^ 1], 0u, 2 * bitmap_words(m->n_le), st);
+    if (e == hipSuccess)
+      e = launch_fill_u32((uint32_t*)m->rebits[p ^ 1], 0u, 2 * bitmap_words(m->n_re), st);
+    return e;
+  }
   if (phase == PH_SNAPSHOT) {
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st);
     if (e == hipSuccess) e = launch_sweep_le(m->le, m->bitmap, m->row_fill, geo, m->ps, st);
@@ -318,13 +336,15 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
     return e;
   }
   uint32_t* tc = m->tcount + p;
+  const uint64_t* le_act = m->discrete ? m->lebits[p] : m->bitmap;
+  const uint64_t* re_act = m->discrete ? m->rebits[p] : m->act_now;
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
   if (e == hipSuccess)
     e = radix_sort_u32(m->touched[p], m->touched_tmp, tc, m->touched_cap, m->hist, st);
   if (e == hipSuccess)
-    e = launch_finalize(m->touched[p], tc, m->act_now, m->si_cnt, geo, m->mark, m->cnt, st);
+    e = launch_finalize(m->touched[p], tc, re_act, m->si_cnt, geo, m->mark, m->cnt, st);
   if (e == hipSuccess)
     e = compact_u32(m->mark, 1u, m->touched[p], tc, m->touched_cap, m->news, &m->cnt->n_new,
                     m->blockw, st);
@@ -333,8 +353,8 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
   if (e == hipSuccess)
     e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
   if (e == hipSuccess)
-    e = launch_estimate(m->csip, m->cnt, m->bitmap, m->act_now, m->act_next, m->up, geo,
-                        m->cflags, m->d_report, st);
+    e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->act_next, m->up, geo, m->cflags,
+                        m->d_report, st);
   if (spans) span_end(m, st, ST_ESTIMATE, ta);
   if (spans) span_begin(m, st, &ta);
   if (e == hipSuccess)
@@ -375,7 +395,8 @@ void release(srla_monitor* m) {
   if (m->pipe) (void)hipStreamSynchronize(m->pipe);
   collect_spans(m);
   drop_graphs(m);
-  dfree(m->le); dfree(m->re); dfree(m->si_cnt); dfree(m->bitmap); dfree(m->act_now);
+  dfree(m->le); dfree(m->re); dfree(m->si_cnt);
+  for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); } dfree(m->bitmap); dfree(m->act_now);
   dfree(m->act_next); dfree(m->row_fill); dfree(m->up); dfree(m->cnt); dfree(m->ps);
   dfree(m->tcount);
   dfree(m->touched[0]); dfree(m->touched[1]); dfree(m->touched_tmp); dfree(m->mark);
@@ -409,6 +430,9 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   const uint64_t si = (uint64_t)g.u * g.v_re;
+  if (cfg->flags & SRLA_CFG_DISCRETE)
+    return 16 * bitmap_words(le) + 24 * bitmap_words(re) + 64 * si + 8 * g.u + 8 +
+           sizeof(Counters) + sizeof(PipeState) + 8 + candidate_bytes(cfg->max_candidates);
   return 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
          8 * g.u + 8 + sizeof(Counters) + sizeof(PipeState) + 8 +
          candidate_bytes(cfg->max_candidates);
@@ -438,6 +462,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->timing = (cfg->flags & SRLA_CFG_TIMING) != 0;
   m->xcd_scan = (cfg->flags & SRLA_CFG_SCAN_XCD) != 0;
   m->use_graph = (cfg->flags & SRLA_CFG_GRAPH) != 0;
+  m->discrete = (cfg->flags & SRLA_CFG_DISCRETE) != 0;
 
   const srla_geometry_t& g = cfg->geom;
   Geo& geo = m->geo;
@@ -484,11 +509,18 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->n_re = (uint64_t)g.u * g.v_re * g.g;
   m->n_si = (uint64_t)g.u * g.v_re;
   m->cap = cfg->max_candidates;
-  nomem(dalloc(&m->le, m->n_le));
-  if (!rc) nomem(dalloc(&m->re, m->n_re + 8));
+  if (m->discrete) {
+    for (int i = 0; i < 2 && !rc; ++i) {
+      nomem(dalloc(&m->lebits[i], bitmap_words(m->n_le)));
+      if (!rc) nomem(dalloc(&m->rebits[i], bitmap_words(m->n_re)));
+    }
+  } else {
+    nomem(dalloc(&m->le, m->n_le));
+    if (!rc) nomem(dalloc(&m->re, m->n_re + 8));
+    if (!rc) nomem(dalloc(&m->bitmap, bitmap_words(m->n_le)));
+    if (!rc) nomem(dalloc(&m->act_now, bitmap_words(m->n_re)));
+  }
   if (!rc) nomem(dalloc(&m->si_cnt, 16 * m->n_si));
-  if (!rc) nomem(dalloc(&m->bitmap, bitmap_words(m->n_le)));
-  if (!rc) nomem(dalloc(&m->act_now, bitmap_words(m->n_re)));
   if (!rc) nomem(dalloc(&m->act_next, bitmap_words(m->n_re)));
   if (!rc) nomem(dalloc(&m->row_fill, g.u));
   if (!rc) nomem(dalloc(&m->up, 1));
@@ -527,8 +559,20 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   }
   // DRinit for every DR (stamp 0 = never set), SI = 0, counters = 0, slice 0
   hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->le, 0u, m->n_le / 2, m->stream);
-  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->re, 0u, (m->n_re + 8) / 2, m->stream);
+  if (m->discrete) {
+    // every bit clear; act_next stays clear for good (at k = 1 no DR is
+    // inside the window after the slide)
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+      e = launch_fill_u32((uint32_t*)m->lebits[i], 0u, 2 * bitmap_words(m->n_le), m->stream);
+      if (e == hipSuccess)
+        e = launch_fill_u32((uint32_t*)m->rebits[i], 0u, 2 * bitmap_words(m->n_re), m->stream);
+    }
+    if (e == hipSuccess)
+      e = launch_fill_u32((uint32_t*)m->act_next, 0u, 2 * bitmap_words(m->n_re), m->stream);
+  } else {
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->le, 0u, m->n_le / 2, m->stream);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->re, 0u, (m->n_re + 8) / 2, m->stream);
+  }
   if (e == hipSuccess) e = launch_fill_u32(m->si_cnt, 0u, 16 * m->n_si, m->stream);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->cnt, 0u, sizeof(Counters) / 4, m->stream);
   if (e == hipSuccess) e = launch_fill_u32(m->tcount, 0u, 2, m->stream);
@@ -567,8 +611,11 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   if (on_device) {
     hipEvent_t a;
     span_begin(m, m->stream, &a);
-    HIP_TRY(m, launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p], m->tcount + p,
-                           m->xcd_scan, m->cfg.scan_blocks, m->stream));
+    HIP_TRY(m, m->discrete
+                   ? launch_scan_bits(pairs, n, m->geo, m->lebits[p], m->rebits[p],
+                                      m->touched[p], m->tcount + p, m->cfg.scan_blocks, m->stream)
+                   : launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
+                                 m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream));
     span_end(m, m->stream, ST_SCAN, a);
     m->slice_pairs[p] += n;
     m->scan_launches++;
@@ -598,8 +645,11 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     m->stage_busy[b] = true;
     hipEvent_t a;
     span_begin(m, m->stream, &a);
-    HIP_TRY(m, launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched[p],
-                           m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream));
+    HIP_TRY(m, m->discrete
+                   ? launch_scan_bits(m->d_stage[b], cnt, m->geo, m->lebits[p], m->rebits[p],
+                                      m->touched[p], m->tcount + p, m->cfg.scan_blocks, m->stream)
+                   : launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched[p],
+                                 m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream));
     span_end(m, m->stream, ST_SCAN, a);
     m->slice_pairs[p] += cnt;
     m->scan_launches++;
@@ -694,6 +744,24 @@ int srla_dump_state(srla_monitor_t* m, int which, uint16_t* host_out, uint64_t c
     }
     return SRLA_OK;
   }
+  if (m->discrete) {
+    // a DR is one bit: distance 0 if set in the open slice, 1 if set in the
+    // slice closed last, beyond the window (all ones) otherwise
+    const uint64_t n = which == SRLA_DUMP_LE ? m->n_le : which == SRLA_DUMP_RE ? m->n_re : 0;
+    if (!n) return fail(m, SRLA_E_INVAL, "unknown state array");
+    if (cells != n) return fail(m, SRLA_E_INVAL, "cells does not match the array size");
+    const int p = (int)(m->slice & 1);
+    uint64_t* const* bits = which == SRLA_DUMP_LE ? m->lebits : m->rebits;
+    const uint64_t words = bitmap_words(n);
+    std::vector<uint64_t> open(words), last(words);
+    HIP_TRY(m, hipMemcpy(open.data(), bits[p], words * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(m, hipMemcpy(last.data(), bits[p ^ 1], words * 8, hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) {
+      const bool o = (open[i >> 6] >> (i & 63)) & 1u, l = (last[i >> 6] >> (i & 63)) & 1u;
+      host_out[i] = o ? 0 : (l && m->slice > 0 ? 1 : 65535);
+    }
+    return SRLA_OK;
+  }
   const uint16_t* src;
   uint64_t n;
   if (which == SRLA_DUMP_LE) { src = m->le; n = m->n_le; }
@@ -766,6 +834,7 @@ int srla_group_create(srla_monitor_t* const* monitors, uint32_t n, uint32_t scan
   if (!out || !monitors || n < 1 || n > (uint32_t)kMaxGroup) return SRLA_E_INVAL;
   for (uint32_t i = 0; i < n; ++i) {
     if (!monitors[i] || monitors[i]->stream != monitors[0]->stream) return SRLA_E_INVAL;
+    if (monitors[i]->discrete) return SRLA_E_INVAL;
     for (uint32_t j = 0; j < i; ++j)
       if (monitors[j] == monitors[i]) return SRLA_E_INVAL;
   }

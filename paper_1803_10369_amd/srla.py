@@ -21,6 +21,7 @@ SRLA_FLAG_SUPER, SRLA_FLAG_SAT, SRLA_FLAG_NEW, SRLA_FLAG_KEEP = 1, 2, 4, 8
 SRLA_CFG_TIMING = 1
 SRLA_CFG_SCAN_XCD = 2
 SRLA_CFG_GRAPH = 4
+SRLA_CFG_DISCRETE = 8
 
 
 class srla_geometry_t(ctypes.Structure):
@@ -232,9 +233,10 @@ class Monitor:
     caller's current stream and kept alive for the monitor's stream."""
 
     def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22,
-                 timing=False, stream=None, scan_xcd=False, graph=False, scan_blocks=0):
+                 timing=False, stream=None, scan_xcd=False, graph=False, scan_blocks=0,
+                 discrete=False):
         flags = ((SRLA_CFG_TIMING if timing else 0) | (SRLA_CFG_SCAN_XCD if scan_xcd else 0) |
-                 (SRLA_CFG_GRAPH if graph else 0))
+                 (SRLA_CFG_GRAPH if graph else 0) | (SRLA_CFG_DISCRETE if discrete else 0))
         self.cfg = make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates, flags,
                                scan_blocks)
         self._h = None

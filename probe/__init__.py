@@ -2,7 +2,9 @@
 
 ``random_store_rate(bytes)`` measures random 2-byte stores per second over a
 footprint of ``bytes`` (the scan's access pattern without its pair loads and
-hashing).  Measurement infrastructure only; the SRLA library does not use it.
+hashing); ``random_or_rate(bytes)`` the same for one-bit atomic ORs into
+32-bit words (the discrete-window scan's pattern).  Measurement
+infrastructure only; the SRLA library does not use it.
 """
 import ctypes
 import os
@@ -36,22 +38,33 @@ def _load():
         L.probe_random_store.restype = ctypes.c_double
         L.probe_random_store.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
                                          ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
+        L.probe_random_or.restype = ctypes.c_double
+        L.probe_random_or.argtypes = L.probe_random_store.argtypes
         _lib = L
     return _lib
 
 
 def random_store_rate(nbytes, stores=1 << 27, repeats=3):
     """Best-of-`repeats` random 2-byte stores per second over `nbytes`."""
+    return _rate("probe_random_store", nbytes, stores, repeats)
+
+
+def random_or_rate(nbytes, ops=1 << 27, repeats=3):
+    """Best-of-`repeats` random one-bit atomic ORs per second over `nbytes`."""
+    return _rate("probe_random_or", nbytes, ops, repeats)
+
+
+def _rate(fn, nbytes, stores, repeats):
     import torch
     L = _load()
-    buf = torch.zeros(nbytes // 2, dtype=torch.int16, device="cuda")
+    buf = torch.zeros(max(nbytes, 4) // 4, dtype=torch.int32, device="cuda")
     per_lane = 64
     blocks = max(1, stores // (256 * per_lane))
     st = torch.cuda.current_stream()
     best = None
     for r in range(repeats + 1):
-        ms = L.probe_random_store(ctypes.c_void_p(buf.data_ptr()), buf.numel() * 2, blocks,
-                                  per_lane, 1234 + r, ctypes.c_void_p(st.cuda_stream))
+        ms = getattr(L, fn)(ctypes.c_void_p(buf.data_ptr()), buf.numel() * 4, blocks,
+                            per_lane, 1234 + r, ctypes.c_void_p(st.cuda_stream))
         if ms <= 0:
             raise RuntimeError("probe failed (%g)" % ms)
         if r > 0:   # the first launch warms the footprint

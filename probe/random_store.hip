@@ -1,7 +1,9 @@
-// Memory-system probe: the rate of random 2-byte stores, one per lane,
-// uniform over a footprint of F bytes -- the access pattern of the SRLA scan
-// with nothing else (no pair loads, no hashing beyond the address).  Used to
-// calibrate the scan kernel's achievable ceiling per footprint.
+// Memory-system probes: the rate of random 2-byte stores (or of random
+// one-bit atomic ORs into 32-bit words), one per lane, uniform over a
+// footprint of F bytes -- the access pattern of the SRLA scan (16-bit stamp
+// form, resp. one-bit discrete form) with nothing else (no pair loads, no
+// hashing beyond the address).  Used to calibrate the scan kernels'
+// achievable ceilings per footprint.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -26,7 +28,39 @@ __global__ __launch_bounds__(256) void k_random_store(uint16_t* __restrict__ buf
   }
 }
 
+// every lane sets `per_lane` random bits with device-scope atomic ORs
+__global__ __launch_bounds__(256) void k_random_or(uint32_t* __restrict__ buf, uint64_t words,
+                                                  uint32_t per_lane, uint64_t seed) {
+  const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  uint64_t s = mix64(seed ^ (t * 0x9E3779B97F4A7C15ull));
+  for (uint32_t i = 0; i < per_lane; ++i) {
+    s = mix64(s + 0x9E3779B97F4A7C15ull);
+    const uint64_t w = (uint64_t)(((unsigned __int128)s * words) >> 64);
+    __hip_atomic_fetch_or(buf + w, 1u << (uint32_t)(s & 31u), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 }  // namespace
+
+// Same for the atomic-OR pattern (footprint in bytes, a multiple of 4).
+extern "C" double probe_random_or(void* buf, uint64_t bytes, uint64_t blocks, uint32_t per_lane,
+                                  uint64_t seed, void* stream) {
+  if (!buf || bytes < 4 || blocks == 0) return -1.0;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -2.0;
+  hipEventRecord(a, st);
+  hipLaunchKernelGGL(k_random_or, dim3((uint32_t)blocks), dim3(256), 0, st, (uint32_t*)buf,
+                     bytes / 4, per_lane, seed);
+  hipEventRecord(b, st);
+  float ms = -3.f;
+  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+    ms = -4.f;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms;
+}
 
 // Returns the kernel time in ms (HIP events) or a negative value on error.
 extern "C" double probe_random_store(void* buf, uint64_t bytes, uint64_t blocks, uint32_t per_lane,

@@ -86,8 +86,11 @@ def test_invalid_configs_are_rejected_without_a_device(P, bad):
 def test_bad_flags_and_capacity_rejected(P):
     cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, max_candidates=0)
     assert P.srla_create(cfg)[0] == -1
-    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=8)
+    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=16)
     assert P.srla_create(cfg)[0] == -1
+    # the discrete (one-bit DR) form exists only for k = 1
+    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=P.srla.SRLA_CFG_DISCRETE)
+    assert P.srla_footprint_bytes(cfg) == 0 and P.srla_create(cfg)[0] == -1
 
 
 def test_footprint_counts_dr_arrays(P):
@@ -101,6 +104,19 @@ def test_footprint_counts_dr_arrays(P):
     assert want <= fp < want + 4096
     big = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1 << 20)
     assert P.srla_footprint_bytes(big) - fp >= 13 * ((1 << 20) - 1)
+
+
+def test_discrete_footprint_is_bits(P):
+    cfg = P.make_config(1, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1,
+                        flags=P.srla.SRLA_CFG_DISCRETE)
+    fp = P.srla_footprint_bytes(cfg)
+    le_cells, re_cells, ses = 1 << 24, 1 << 23, 8 * 131072
+    # two bit arrays (slice parities) per DR array, one all-clear SRE map,
+    # the SI counters
+    want = 2 * le_cells // 8 + 3 * re_cells // 8 + 64 * ses
+    assert want <= fp < want + 4096
+    stamps = P.make_config(1, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1)
+    assert P.srla_footprint_bytes(stamps) - fp > 2 * le_cells
 
 
 def test_null_handles(P):

@@ -26,8 +26,9 @@ def _gpu():
 
 
 def _run(stream, mon, slices, max_candidates=1 << 16, dump_every=1, split=None, host=False,
-         scan_xcd=False, graph=False):
-    g = srla.Monitor(**mon, max_candidates=max_candidates, scan_xcd=scan_xcd, graph=graph)
+         scan_xcd=False, graph=False, discrete=False):
+    g = srla.Monitor(**mon, max_candidates=max_candidates, scan_xcd=scan_xcd, graph=graph,
+                     discrete=discrete)
     o = oracle.Monitor(**mon)
     for s in slices:
         pairs = stream.slice(s) if hasattr(stream, "slice") else stream(s)
@@ -42,8 +43,8 @@ def _run(stream, mon, slices, max_candidates=1 << 16, dump_every=1, split=None, 
         rg, rc = g.estimate(), o.estimate()
         compare_reports(rg, rc, mon["theta"], ctx="slice %d" % s)
         if dump_every and (s % dump_every == 0):
-            compare_dumps(g, o, ctx="slice %d" % s)
-    compare_dumps(g, o, ctx="end")
+            compare_dumps(g, o, ctx="slice %d" % s, discrete=discrete)
+    compare_dumps(g, o, ctx="end", discrete=discrete)
     g.close()
     return rg
 
@@ -114,9 +115,10 @@ def test_small_geometries(case, scan_xcd, graph):
          graph=graph)
 
 
-def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chunks=1):
+def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chunks=1,
+                   discrete=False):
     """The next slice is scanned before the previous slice's report is taken."""
-    g = srla.Monitor(**mon, max_candidates=max_candidates, graph=graph)
+    g = srla.Monitor(**mon, max_candidates=max_candidates, graph=graph, discrete=discrete)
     o = oracle.Monitor(**mon)
     expected = []
     slices = list(slices)
@@ -131,7 +133,7 @@ def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chu
             compare_reports(g.wait_report(), expected[i - 1], mon["theta"], "slice %d" % (s - 1))
         g.close_slice()
     compare_reports(g.wait_report(), expected[-1], mon["theta"], "last slice")
-    compare_dumps(g, o, ctx="end")
+    compare_dumps(g, o, ctx="end", discrete=discrete)
     g.close()
 
 
@@ -410,3 +412,40 @@ def test_autotuner_picks_a_valid_shape_and_results_do_not_change(tmp_path):
     grp.close()
     for gm in gms:
         gm.close()
+
+
+# ------------------------------------------------------------ discrete window
+# k = 1 with one bit per DR (SRLA_CFG_DISCRETE): reports must equal the
+# oracle's k = 1 reports bit for bit; dumps agree up to distance 1.
+
+@pytest.mark.parametrize("case", SMALL)
+@pytest.mark.parametrize("graph", [False, True])
+def test_discrete_form_small_geometries(case, graph):
+    _, theta, u, v_re, g, v_le, G, n, n_src, slices = case
+    mon = dict(k=1, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=3000 + u)
+    _run(_rand_stream(u + 11, n, n_src, 3 * theta // 2), mon, range(slices), graph=graph,
+         discrete=True)
+
+
+def test_discrete_form_tiny_workload_host_input_and_streaming():
+    stream, mon, n = workload("tiny_coupled")
+    mon = dict(mon, k=1)
+    _run(stream, mon, range(6), discrete=True, host=True, split=30001)
+    _run_streaming(stream, mon, range(6), graph=True, chunks=3, discrete=True)
+
+
+def test_discrete_form_backbone_full_size():
+    stream, mon, _ = workload("backbone")
+    mon = dict(mon, k=1)
+    r = _run(stream, mon, range(3), max_candidates=1 << 22, dump_every=0, discrete=True)
+    assert r.n > 0
+
+
+def test_discrete_form_rejects_longer_windows_and_groups():
+    stream, mon, _ = workload("tiny")
+    with pytest.raises(srla.SrlaError):
+        srla.Monitor(**mon, discrete=True)                    # k = 8
+    m = srla.Monitor(**dict(mon, k=1), discrete=True)
+    with pytest.raises(srla.SrlaError):
+        srla.Group([m])
+    m.close()

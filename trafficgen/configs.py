@@ -56,7 +56,23 @@ def workload(name):
                             planted=planted, window=k, seed=STREAM_SEED + 6, dst_pool=4)
         v = 4096 if small else 65_536
         return stream, _monitor(k, 1024, 4, v, 8, v, 1024, 6), (3 * k if small else 90)
+    if name == "discrete_paper":
+        # the paper's discrete-window run (Section 5.1): k = 1, one-bit DRs,
+        # u = 4, v = 65,536, g' = 1024, theta = 1024, one 300-second window of
+        # a ~4.5 Mpps link per slice.  The stream is produced in chunks of 8M
+        # pairs (DISCRETE_CHUNKS chunks = 1.352 G pairs per slice; chunk c of
+        # slice s is stream slice s * DISCRETE_CHUNKS + c); sources draw from 4
+        # destinations each, 200 planted super points with 1k-200k dsts spread
+        # evenly over a slice's chunks
+        planted = loguniform_ints(1000, 200_000, 200, STREAM_SEED + 7)
+        stream = StreamSpec(n_pairs=8_000_000, n_ranks=1 << 24, alpha=1.05, planted=planted,
+                            window=DISCRETE_CHUNKS, seed=STREAM_SEED + 7, dst_pool=4)
+        return stream, _monitor(1, 1024, 4, 65_536, 8, 65_536, 1024, 7), 4
     raise KeyError(name)
+
+
+# chunks of 8M pairs per slice of the discrete-window workload: 300 s x 4.5 Mpps
+DISCRETE_CHUNKS = 169
 
 
 def scaled(stream, n_pairs):
