@@ -103,7 +103,8 @@ def run_batched(args):
     torch.cuda.set_stream(st)
     fused = args.mode in ("batched", "streaming")
     mons = [srla.Monitor(**c, max_candidates=args.max_candidates, stream=st, graph=fused,
-                         scan_blocks=args.scan_blocks) for c in mons_cfg]
+                         scan_blocks=args.scan_blocks, lean_report=not args.full_report)
+            for c in mons_cfg]
     grp = srla.Group(mons, scan_blocks=args.scan_blocks) if fused else None
 
     def scan_all(buf):
@@ -205,6 +206,125 @@ def run_batched(args):
         m.close()
 
 
+def bits_bytes_per_pair(u, tau):
+    """Algorithmic bytes of the discrete-window scan per pair: the 8-byte pair,
+    u 32-bit atomic ORs into the LE bit array, and with probability 2^-tau u
+    atomic ORs into the SRE bit array plus a 4-byte sampled-source append."""
+    return 8.0 + 4.0 * u + (4.0 * u + 4.0) * 2.0 ** (-tau)
+
+
+def run_discrete(args):
+    """The paper's discrete-window run: k = 1 with one-bit DRs, the paper's SEA
+    (u = 4, v = 65,536, g' = 1024), one slice = one 300-second window of a
+    4.5 Mpps link = 169 chunks of 8M pairs (1.352 G pairs).  Each timed
+    slice's pairs are generated into HBM (10.8 GB) before its timed region;
+    the region covers its 169 scans and its end-of-slice report."""
+    import numpy as np
+    import torch
+
+    import paper_1803_10369_amd as srla
+    import probe
+    from trafficgen.configs import DISCRETE_CHUNKS, workload
+    from trafficgen.device import DeviceStream
+
+    torch.cuda.set_device(0)
+    stream, mon, _ = workload(args.workload)
+    C, n = DISCRETE_CHUNKS, stream.n_pairs
+    ds = DeviceStream(stream)
+    st = torch.cuda.Stream()
+    torch.cuda.set_stream(st)
+    m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
+                     discrete=True, graph=args.graph > 0, scan_blocks=args.scan_blocks,
+                     lean_report=not args.full_report)
+    buf = torch.empty((C, 2 * n), dtype=torch.int32, device="cuda")
+
+    def fill(s):
+        for c in range(C):
+            ds.generate(s * C + c, out=buf[c], stream=st)
+        torch.cuda.synchronize()
+
+    for s in range(args.warmup):
+        fill(s)
+        for c in range(C):
+            m.scan(buf[c])
+        m.estimate(copy=False)
+        print("warmup slice %d" % s, file=sys.stderr, flush=True)
+    m.timings(reset=True)
+    lat, total_s = [], 0.0
+    for i in range(args.steps):
+        fill(args.warmup + i)
+        t0 = time.perf_counter()
+        for c in range(C):
+            m.scan(buf[c])
+        st.synchronize()
+        ts = time.perf_counter()
+        r = m.estimate(copy=False)
+        t1 = time.perf_counter()
+        lat.append((t1 - ts) * 1e3)
+        total_s += t1 - t0
+        print("timed slice %d: %.1f ms, %d candidates" % (i, (t1 - t0) * 1e3, r.n),
+              file=sys.stderr, flush=True)
+    tm = m.timings(reset=True)
+    tau = 0
+    while mon["g"] * (1 << tau) < mon["theta"]:
+        tau += 1
+    pairs = args.steps * C * n
+    scan_ms = tm["scan_ms"] / max(1, tm["scan_launches"])
+    bpp = bits_bytes_per_pair(mon["u"], tau)
+    achieved = bpp * n / (scan_ms * 1e-3) / 1e9
+    ors = mon["u"] * (1 + 2.0 ** -tau) * n / (scan_ms * 1e-3)
+    footprint = (mon["u"] * (mon["v_le"] * mon["G"] + mon["v_re"] * mon["g"])) // 8
+    ceiling = probe.random_or_rate(footprint)
+    lat = np.array(lat)
+    out = {
+        "metric": METRIC, "value": pairs / total_s, "unit": "packets/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_s * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u1",
+        "data": "synthetic",
+        "config": {
+            "workload": ("%s: discrete window (k = 1, one-bit DRs), %d chunks of %d pairs per "
+                         "slice, Zipf(%g) sources over %d hosts with 4 destinations each, %d "
+                         "planted super points, u %d, v %d, g %d, g' %d, theta %d"
+                         % (args.workload, C, n, stream.alpha, stream.n_ranks,
+                            len(stream.planted), mon["u"], mon["v_le"], mon["g"], mon["G"],
+                            mon["theta"])),
+            "pairs_per_slice": C * n, "scan_blocks": args.scan_blocks},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "stage_ms_per_slice": {k: tm[k] / args.steps for k in
+                               ("scan_ms", "sweep_ms", "finalize_ms", "estimate_ms", "slide_ms")},
+        "state": {"candidates": int(r.n), "up": r.up,
+                  "row_fill_frac": [float(x) / (mon["v_le"] * mon["G"]) for x in r.row_fill],
+                  "n_touched": int(r.n_touched), "n_new": int(r.n_new),
+                  "super": int(((r.flags & 1) != 0).sum())},
+        "roofline": {
+            "kernel": "k_scan_bits (Algorithm 2, one-bit DRs)", "bound": "hbm",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_pair": bpp,
+            "launch_ms": scan_ms, "random_ors_per_s": ors,
+            "random_or_ceiling_per_s": ceiling, "frac_of_random_or_ceiling": ors / ceiling,
+            "footprint_bytes": footprint},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.Monitor(**mon)
+        ps = [stream.slice(c) for c in range(args.cpu_slices)]
+        t0 = time.perf_counter()
+        for p in ps:
+            o.scan(p)
+        o.estimate()
+        dt = time.perf_counter() - t0
+        cnt = sum(len(p) for p in ps)
+        o.close()
+        out["cpu_baseline"] = {
+            "value": cnt / dt, "unit": "packets/s", "cores": 1, "kind": "oracle",
+            "sample": ("the first %d chunks (%d pairs) of the same workload as one k = 1 slice, "
+                       "scan + end-of-slice estimate, single-threaded C oracle (16-bit DRs), "
+                       "%.1f s on %s (nproc %d)" % (args.cpu_slices, cnt, dt, cpu_model(),
+                                                     os.cpu_count()))}
+    print(json.dumps(out), flush=True)
+    m.close()
+
+
 def run_serving(args):
     """The serving mix: 64 monitors of uneven sizes (LE 2^24..2^33 DR cells)
     admitted first-fit under a device-memory budget, over a bursting stream
@@ -230,7 +350,8 @@ def run_serving(args):
     st = torch.cuda.Stream()
     torch.cuda.set_stream(st)
     fused = args.mode != "plain"
-    mons = [srla.Monitor(**c, max_candidates=args.max_candidates, stream=st, graph=True)
+    mons = [srla.Monitor(**c, max_candidates=args.max_candidates, stream=st, graph=True,
+                         lean_report=not args.full_report)
             for c in chosen]
     grp = srla.Group(mons) if fused else None
     dstreams = {a: DeviceStream(sp) for a, sp in ss.specs.items()}
@@ -326,6 +447,9 @@ def main():
                          "reference for the HBM traffic counters)")
     ap.add_argument("--probe-mib", default="",
                     help="comma-separated extra footprints (MiB) for the random-store probe")
+    ap.add_argument("--full-report", action="store_true",
+                    help="also deliver |ULE|^k and |URE|^k per candidate (18 instead of 13 "
+                         "bytes per candidate to host memory)")
     ap.add_argument("--scan-xcd", action="store_true",
                     help="scan with per-XCD row ownership (A/B of the scan kernels)")
     args = ap.parse_args()
@@ -338,6 +462,8 @@ def main():
         return run_batched(args)
     if args.workload == "serving64":
         return run_serving(args)
+    if args.workload == "discrete_paper":
+        return run_discrete(args)
 
     import numpy as np
     import torch
@@ -370,7 +496,8 @@ def main():
         tuned = autotune.tune_scan(mon, buf, cache=None)
         args.scan_xcd, args.scan_blocks = tuned["scan_xcd"], tuned["scan_blocks"]
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
-                     scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks)
+                     scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks,
+                     lean_report=not args.full_report)
     t_w = time.perf_counter()
     for s in range(args.warmup):
         ds.generate(s, out=buf, stream=st)
@@ -462,6 +589,8 @@ def main():
             "slices_timed": [args.warmup, args.warmup + args.steps - 1],
             "mode": args.mode, "graph": graph, "scan_blocks": args.scan_blocks,
             "scan_xcd": args.scan_xcd, "autotune": tuned,
+            "report": ("full: ip, est, flags, |ULE|^k, |URE|^k (18 B/candidate)"
+                       if args.full_report else "ip, est, flags (13 B/candidate)"),
         },
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),

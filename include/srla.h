@@ -58,7 +58,7 @@ enum {
     SRLA_CFG_GRAPH = 4,    /* record the end-of-slice pipeline once per slice
                               parity as HIP graphs and replay them; results
                               are identical either way */
-    SRLA_CFG_DISCRETE = 8  /* the discrete-window form (Section 3.2: with
+    SRLA_CFG_DISCRETE = 8, /* the discrete-window form (Section 3.2: with
                               k = 1 a one-bit DR suffices; Section 5.1 runs
                               it with z = 1): every DR is one bit, set by the
                               scan and cleared at the slice's end.  Requires
@@ -66,6 +66,10 @@ enum {
                               the 16-bit form's at k = 1.  SRLA_CFG_SCAN_XCD
                               has no effect; such monitors cannot join a
                               group */
+    SRLA_CFG_LEAN_REPORT = 16  /* reports carry ip, est and flags only
+                                  (union_weight and re_weight are NULL):
+                                  13 instead of 18 bytes per candidate cross
+                                  PCIe at every slice end */
 };
 
 /*
@@ -117,6 +121,7 @@ typedef struct srla_monitor srla_monitor_t;
  *   flags         SRLA_FLAG_* of each candidate
  *   union_weight  |ULE(ip)|^k, union LE DRs inside the window (Algorithm 1)
  *   re_weight     |URE(ip)|^k before the slide
+ *                 (both NULL with SRLA_CFG_LEAN_REPORT)
  *   row_fill      |LDR(i)|^k for i < u: LE DRs of row i inside the window
  *   up            Eq8
  *   n_touched     distinct sources with at least one SRE-sampled pair in e

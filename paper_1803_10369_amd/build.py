@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsrla.so")
-SOURCES = ["srla_runtime.hip", "srla_scan.hip", "srla_kernels.hip", "srla_sort.hip"]
+SOURCES = ["srla_runtime.hip", "srla_scan.hip", "srla_kernels.hip", "srla_sort.hip",
+           "srla_discrete.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

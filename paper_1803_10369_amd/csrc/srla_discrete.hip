@@ -14,40 +14,50 @@ constexpr int kBitSteps = 4;
 constexpr uint64_t kBitTile = (uint64_t)kBlock * 2 * kBitSteps;  // pairs per block
 
 // ------------------------------------------------------------------ scan
-// Algorithm 2 with one-bit DRs.  A DR is set by an atomic OR into 32-bit words of a flat bit array over [u][v][G] (LE) or
-// [u][v_re][g] (SRE) -- the same layout as the activity bitmaps that the
-// end-of-slice kernels read, so those kernels read these arrays directly.
-// Bits from different pairs share words, hence the atomics (device scope,
-// relaxed: only the kernel boundary orders them with the readers).
+// Algorithm 2 with one-bit DRs.  A DR is set by an atomic OR into a 32-bit
+// word of a flat bit array over [u][v_le][G] (LE) or [u][v_re][g] (SRE) --
+// the layout of the activity bitmaps that the end-of-slice kernels read, so
+// those kernels read these arrays directly.  Bits of different pairs share
+// words, hence atomics; device-scope atomics run at the memory side and cost
+// several plain stores each, while most DRs of a slice are set many times
+// (every repeat of a flow, every pair of a hot source).  So each DR is first
+// tested with a plain cached load and the atomic is issued only if the bit
+// is still clear.  A stale clear bit only costs a redundant OR (idempotent);
+// a stale set bit cannot occur, since bits are only set within the kernel and
+// caches are invalidated at its start.  The loads of a thread's 8 pairs are
+// all issued before any of its atomics.
 
-__device__ __forceinline__ void set_bit(uint64_t* __restrict__ bits, uint64_t i) {
-  uint32_t* w = reinterpret_cast<uint32_t*>(bits) + (i >> 5);
-  __hip_atomic_fetch_or(w, 1u << (uint32_t)(i & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint32_t peek_word(const uint64_t* __restrict__ bits, uint64_t i) {
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(bits) + (i >> 5);
+  return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
-template <int U>
-__device__ __forceinline__ void scan_one_bits(uint32_t a, uint32_t b, bool valid, const Geo& geo,
-                                              uint64_t* __restrict__ lebits,
-                                              uint64_t* __restrict__ rebits,
-                                              uint32_t* __restrict__ touched,
-                                              uint32_t* __restrict__ tcount) {
-  const uint32_t nu = U > 0 ? (uint32_t)U : geo.u;
-  bool sampled = false;
-  if (valid) {
-    const uint32_t lei = hrange(mas(geo.h3, b), geo.G);
-#pragma unroll
-    for (uint32_t i = 0; i < nu; ++i) {
-      const uint32_t col = hrange(mas(geo.rh[i], a), geo.v_le);
-      set_bit(lebits, ((uint64_t)i * geo.v_le + col) * geo.G + lei);
-    }
-    sampled = (mas(geo.h1, b) & geo.tau_mask) == 0u;
-    if (sampled) {
-      const uint32_t rei = hrange(mas(geo.h2, b), geo.g);
-#pragma unroll
-      for (uint32_t i = 0; i < nu; ++i) {
-        const uint32_t col = hrange(mas(geo.rh[i], a), geo.v_re);
-        set_bit(rebits, ((uint64_t)i * geo.v_re + col) * geo.g + rei);
-      }
+__device__ __forceinline__ void set_bit_if_clear(uint64_t* __restrict__ bits, uint64_t i,
+                                                 uint32_t seen) {
+  const uint32_t m = 1u << (uint32_t)(i & 31u);
+  if ((seen & m) == 0u)
+    __hip_atomic_fetch_or(reinterpret_cast<uint32_t*>(bits) + (i >> 5), m, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t le_bit(const Geo& geo, uint32_t row, uint32_t a,
+                                           uint32_t lei) {
+  return ((uint64_t)row * geo.v_le + hrange(mas(geo.rh[row], a), geo.v_le)) * geo.G + lei;
+}
+
+// the SRE half of Algorithm 2 for one pair (2^-tau of the pairs), and the
+// wave-aggregated append of its source to the slice's sampled list
+__device__ __forceinline__ void sample_bits(uint32_t a, uint32_t b, bool valid, const Geo& geo,
+                                            uint64_t* __restrict__ rebits,
+                                            uint32_t* __restrict__ touched,
+                                            uint32_t* __restrict__ tcount) {
+  const bool sampled = valid && (mas(geo.h1, b) & geo.tau_mask) == 0u;
+  if (sampled) {
+    const uint32_t rei = hrange(mas(geo.h2, b), geo.g);
+    for (uint32_t i = 0; i < geo.u; ++i) {
+      const uint64_t bit =
+          ((uint64_t)i * geo.v_re + hrange(mas(geo.rh[i], a), geo.v_re)) * geo.g + rei;
+      set_bit_if_clear(rebits, bit, peek_word(rebits, bit));
     }
   }
   const uint64_t mask = __ballot(sampled);
@@ -86,10 +96,45 @@ __global__ __launch_bounds__(kBlock) void k_scan_bits(const uint32_t* __restrict
         b[s][1] = v[s][1] ? pairs[2 * p + 3] : 0u;
       }
     }
+    if constexpr (U > 0) {
+      // LE: every test load first, then the ORs of the bits still clear
+      uint32_t seen[kBitSteps][2][U];
+#pragma unroll
+      for (int s = 0; s < kBitSteps; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t lei = hrange(mas(geo.h3, b[s][h]), geo.G);
+#pragma unroll
+          for (int i = 0; i < U; ++i)
+            seen[s][h][i] = v[s][h] ? peek_word(lebits, le_bit(geo, i, a[s][h], lei)) : ~0u;
+        }
+#pragma unroll
+      for (int s = 0; s < kBitSteps; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (!v[s][h]) continue;
+          const uint32_t lei = hrange(mas(geo.h3, b[s][h]), geo.G);
+#pragma unroll
+          for (int i = 0; i < U; ++i)
+            set_bit_if_clear(lebits, le_bit(geo, i, a[s][h], lei), seen[s][h][i]);
+        }
+    } else {
+#pragma unroll
+      for (int s = 0; s < kBitSteps; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          if (!v[s][h]) continue;
+          const uint32_t lei = hrange(mas(geo.h3, b[s][h]), geo.G);
+          for (uint32_t i = 0; i < geo.u; ++i) {
+            const uint64_t bit = le_bit(geo, i, a[s][h], lei);
+            set_bit_if_clear(lebits, bit, peek_word(lebits, bit));
+          }
+        }
+    }
 #pragma unroll
     for (int s = 0; s < kBitSteps; ++s) {
-      scan_one_bits<U>(a[s][0], b[s][0], v[s][0], geo, lebits, rebits, touched, tcount);
-      scan_one_bits<U>(a[s][1], b[s][1], v[s][1], geo, lebits, rebits, touched, tcount);
+      sample_bits(a[s][0], b[s][0], v[s][0], geo, rebits, touched, tcount);
+      sample_bits(a[s][1], b[s][1], v[s][1], geo, rebits, touched, tcount);
     }
   }
 }

@@ -334,12 +334,23 @@ hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
 // bitmaps, Eq9 in FP64, and the flags.  A group of 2^lg_log2 lanes owns one
 // candidate; its lanes split the G/64 bitmap words (16 lanes read one
 // 128-byte line per row when G = 1024) and the u rows of the SRE, then
-// reduce with cross-lane shuffles.  A block finishes 64 candidates, stages
+// reduce with cross-lane shuffles.  A block finishes 256 candidates, stages
 // them in LDS, and writes the report entries with one coalesced store per
 // array straight into the pinned host buffers (mapped into the GPU's address
-// space), so no separate device-to-host copy is needed.
+// space), so no separate device-to-host copy is needed.  The report is
+// PCIe-bound: the block barriers order LDS only, so a block's host writes stay
+// in flight while it gathers its next candidates; U and W are written only
+// when their buffers are given (the lean report leaves them out).
 
-constexpr uint32_t kEstPerBlock = 64;
+constexpr uint32_t kEstPerBlock = kBlock;
+
+// a workgroup barrier that orders LDS accesses only (global stores issued
+// before it may still be in flight)
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __global__ __launch_bounds__(kBlock) void k_estimate(
     const uint32_t* __restrict__ csip, const Counters* __restrict__ cnt,
@@ -420,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
       s_f[local] = fl;
     }
   }
-  __syncthreads();
+  lds_barrier();
   if (threadIdx.x < kEstPerBlock) {
     const uint64_t gid = base + threadIdx.x;
     if (gid < n) {
@@ -428,11 +439,11 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
       out_ip[gid] = s_ip[threadIdx.x];
       out_est[gid] = s_est[threadIdx.x];
       out_flags[gid] = s_f[threadIdx.x];
-      out_U[gid] = s_U[threadIdx.x];
-      out_W[gid] = s_W[threadIdx.x];
+      if (out_U) out_U[gid] = s_U[threadIdx.x];
+      if (out_W) out_W[gid] = s_W[threadIdx.x];
     }
   }
-  __syncthreads();
+  lds_barrier();
   }
 }
 

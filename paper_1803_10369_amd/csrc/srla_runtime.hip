@@ -68,7 +68,7 @@ bool config_ok(const srla_config_t* c) {
   if (c->threshold < 1) return false;
   if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
   if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH |
-                              SRLA_CFG_DISCRETE)) != 0)
+                              SRLA_CFG_DISCRETE | SRLA_CFG_LEAN_REPORT)) != 0)
     return false;
   if ((c->flags & SRLA_CFG_DISCRETE) && c->window_slices != 1) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
@@ -536,8 +536,9 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!rc) nomem(halloc(&m->h_ip, m->cap));
   if (!rc) nomem(halloc(&m->h_est, m->cap));
   if (!rc) nomem(halloc(&m->h_flags, m->cap));
-  if (!rc) nomem(halloc(&m->h_U, m->cap));
-  if (!rc) nomem(halloc(&m->h_W, m->cap));
+  const bool weights = (cfg->flags & SRLA_CFG_LEAN_REPORT) == 0;
+  if (!rc && weights) nomem(halloc(&m->h_U, m->cap));
+  if (!rc && weights) nomem(halloc(&m->h_W, m->cap));
   if (!rc) {
     m->h_row_fill64 = new (std::nothrow) uint64_t[g.u];
     if (!m->h_row_fill64) rc = SRLA_E_NOMEM;
@@ -546,8 +547,8 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
               dev_view(m->h_ip, &m->d_report.ip) != hipSuccess ||
               dev_view(m->h_est, &m->d_report.est) != hipSuccess ||
               dev_view(m->h_flags, &m->d_report.flags) != hipSuccess ||
-              dev_view(m->h_U, &m->d_report.U) != hipSuccess ||
-              dev_view(m->h_W, &m->d_report.W) != hipSuccess))
+              (weights && dev_view(m->h_U, &m->d_report.U) != hipSuccess) ||
+              (weights && dev_view(m->h_W, &m->d_report.W) != hipSuccess)))
     rc = SRLA_E_DEVICE;
   if (!rc && (hipEventCreateWithFlags(&m->ev_scan, hipEventDisableTiming) != hipSuccess ||
               hipEventCreateWithFlags(&m->ev_snap, hipEventDisableTiming) != hipSuccess ||

@@ -22,6 +22,7 @@ SRLA_CFG_TIMING = 1
 SRLA_CFG_SCAN_XCD = 2
 SRLA_CFG_GRAPH = 4
 SRLA_CFG_DISCRETE = 8
+SRLA_CFG_LEAN_REPORT = 16
 
 
 class srla_geometry_t(ctypes.Structure):
@@ -206,6 +207,8 @@ class Report:
         n = r.n
 
         def arr(p, dt):
+            if not p:
+                return None          # left out of a lean report
             if not n:
                 return np.zeros(0, dt)
             a = np.ctypeslib.as_array(p, (n,))
@@ -234,9 +237,10 @@ class Monitor:
 
     def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22,
                  timing=False, stream=None, scan_xcd=False, graph=False, scan_blocks=0,
-                 discrete=False):
+                 discrete=False, lean_report=False):
         flags = ((SRLA_CFG_TIMING if timing else 0) | (SRLA_CFG_SCAN_XCD if scan_xcd else 0) |
-                 (SRLA_CFG_GRAPH if graph else 0) | (SRLA_CFG_DISCRETE if discrete else 0))
+                 (SRLA_CFG_GRAPH if graph else 0) | (SRLA_CFG_DISCRETE if discrete else 0) |
+                 (SRLA_CFG_LEAN_REPORT if lean_report else 0))
         self.cfg = make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates, flags,
                                scan_blocks)
         self._h = None

@@ -449,3 +449,18 @@ def test_discrete_form_rejects_longer_windows_and_groups():
     with pytest.raises(srla.SrlaError):
         srla.Group([m])
     m.close()
+
+
+def test_lean_report_carries_ip_est_flags_of_the_full_report():
+    stream, mon, n = workload("tiny_coupled")
+    lean = srla.Monitor(**mon, max_candidates=1 << 16, lean_report=True, graph=True)
+    o = oracle.Monitor(**mon)
+    for s in range(n):
+        p = stream.slice(s)
+        lean.scan(to_device(p))
+        o.scan(p)
+        rl, rc = lean.estimate(), o.estimate()
+        assert rl.union_weight is None and rl.re_weight is None
+        rl.union_weight, rl.re_weight = rc.union_weight, rc.re_weight
+        compare_reports(rl, rc, mon["theta"], "slice %d" % s)
+    lean.close()
