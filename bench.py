@@ -450,6 +450,8 @@ def main():
     ap.add_argument("--full-report", action="store_true",
                     help="also deliver |ULE|^k and |URE|^k per candidate (18 instead of 13 "
                          "bytes per candidate to host memory)")
+    ap.add_argument("--scan-dedup", action="store_true",
+                    help="scan in read-before-write form (A/B of the scan kernels)")
     ap.add_argument("--scan-xcd", action="store_true",
                     help="scan with per-XCD row ownership (A/B of the scan kernels)")
     args = ap.parse_args()
@@ -495,9 +497,10 @@ def main():
         ds.generate(0, out=buf, stream=st)
         tuned = autotune.tune_scan(mon, buf, cache=None)
         args.scan_xcd, args.scan_blocks = tuned["scan_xcd"], tuned["scan_blocks"]
+        args.scan_dedup = tuned["scan_dedup"]
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks,
-                     lean_report=not args.full_report)
+                     lean_report=not args.full_report, scan_dedup=args.scan_dedup)
     t_w = time.perf_counter()
     for s in range(args.warmup):
         ds.generate(s, out=buf, stream=st)
@@ -561,6 +564,8 @@ def main():
     scan_ms = tm["scan_ms"] / max(1, tm["scan_launches"])
     per_launch_bytes = scan_bytes_per_pair(g["u"], tau) * n_pairs
     achieved = per_launch_bytes / (scan_ms * 1e-3) / 1e9
+    scan_kernel = ("k_scan_dedup" if args.scan_dedup else
+                   "k_scan_xcd" if args.scan_xcd else "k_scan_flat")
     stages = {k: tm[k] / args.steps for k in
               ("scan_ms", "sweep_ms", "finalize_ms", "estimate_ms", "slide_ms", "report_ms")}
 
@@ -588,7 +593,7 @@ def main():
             "window": g["k"], "theta": g["theta"], "pairs_per_slice": n_pairs,
             "slices_timed": [args.warmup, args.warmup + args.steps - 1],
             "mode": args.mode, "graph": graph, "scan_blocks": args.scan_blocks,
-            "scan_xcd": args.scan_xcd, "autotune": tuned,
+            "scan_xcd": args.scan_xcd, "scan_dedup": args.scan_dedup, "autotune": tuned,
             "report": ("full: ip, est, flags, |ULE|^k, |URE|^k (18 B/candidate)"
                        if args.full_report else "ip, est, flags (13 B/candidate)"),
         },
@@ -599,14 +604,13 @@ def main():
                   "row_fill_frac": [float(x) / (g["v_le"] * g["G"]) for x in r.row_fill],
                   "n_touched": int(r.n_touched), "n_new": int(r.n_new)},
         "roofline": {
-            "kernel": "k_scan_xcd (Algorithm 2)" if args.scan_xcd else "k_scan_flat (Algorithm 2)",
+            "kernel": "%s (Algorithm 2)" % scan_kernel,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic("k_scan_xcd" if args.scan_xcd else "k_scan_flat",
-                                        args.workload),
+            "traffic": measured_traffic(scan_kernel, args.workload),
             "bytes_per_pair": scan_bytes_per_pair(g["u"], tau),
             "launch_ms": scan_ms,
             "random_stores_per_s": g["u"] * (1 + 2.0 ** -tau) * n_pairs / (scan_ms * 1e-3),

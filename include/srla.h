@@ -66,10 +66,16 @@ enum {
                               the 16-bit form's at k = 1.  SRLA_CFG_SCAN_XCD
                               has no effect; such monitors cannot join a
                               group */
-    SRLA_CFG_LEAN_REPORT = 16  /* reports carry ip, est and flags only
+    SRLA_CFG_LEAN_REPORT = 16, /* reports carry ip, est and flags only
                                   (union_weight and re_weight are NULL):
                                   13 instead of 18 bytes per candidate cross
                                   PCIe at every slice end */
+    SRLA_CFG_SCAN_DEDUP = 32   /* scan in read-before-write form: a DR that
+                                  already holds the open slice's stamp is not
+                                  stored again (DRset is idempotent).  Results
+                                  are identical; faster when pairs repeat DRs
+                                  often.  Takes precedence over
+                                  SRLA_CFG_SCAN_XCD */
 };
 
 /*

@@ -1,12 +1,13 @@
 """Autotuner for the scan kernel's launch shape.
 
 The scan (Algorithm 2) has two knobs that never change its results: the
-kernel form (flat, or per-XCD row ownership, SRLA_CFG_SCAN_XCD) and the cap
-on its workgroups (srla_config_t.scan_blocks).  tune_scan() times every
-candidate on a scratch monitor of the caller's geometry with the caller's
-pairs (stamp stores are idempotent, so rescanning the same pairs is a fair,
-repeatable measurement), picks the fastest, and caches the choice per
-(geometry, pairs per scan, device) in a JSON file.  tune_group() does the
+kernel form (flat; per-XCD row ownership, SRLA_CFG_SCAN_XCD; read-before-write,
+SRLA_CFG_SCAN_DEDUP) and the cap on its workgroups (srla_config_t.scan_blocks).
+tune_scan() times every candidate on a scratch monitor of the caller's
+geometry with the caller's pairs, one scan per slice (each timed scan meets
+the stamps of an earlier slice, as a real slice does, so the read-before-write
+form gets no advantage from rescanning), picks the fastest, and caches the
+choice per (geometry, pairs per scan, device) in a JSON file.  tune_group() does the
 same for a monitor group's fused scan, on temporary groups over the caller's
 own monitors during an open slice (rescanning a slice's pairs leaves every
 result unchanged: stores are idempotent and repeated sampled sources are
@@ -19,7 +20,8 @@ import torch
 
 from . import srla
 
-DEFAULT_CANDIDATES = [(False, 0), (False, 1024), (False, 512), (True, 0), (True, 1024)]
+DEFAULT_CANDIDATES = [("flat", 0), ("flat", 1024), ("flat", 512), ("xcd", 0), ("xcd", 1024),
+                      ("dedup", 0), ("dedup", 1024)]
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "srla_autotune.json")
 
 
@@ -46,7 +48,8 @@ def _save(path, table):
 
 
 def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False):
-    """Returns {"scan_xcd": bool, "scan_blocks": int, "ms": float, "all": {...}}
+    """Returns {"scan_xcd": bool, "scan_dedup": bool, "scan_blocks": int,
+    "ms": float, "all": {...}}
     for monitors of geometry `cfg` (Monitor keyword arguments) scanning
     `pairs` (a CUDA tensor of 2n values) per call."""
     n_pairs = pairs.numel() // 2
@@ -55,20 +58,24 @@ def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False
     if not refresh and key in table:
         return table[key]
     results = {}
-    for xcd, blocks in candidates or DEFAULT_CANDIDATES:
-        m = srla.Monitor(**cfg, max_candidates=64, timing=True, scan_xcd=xcd,
-                         scan_blocks=blocks)
+    for form, blocks in candidates or DEFAULT_CANDIDATES:
+        m = srla.Monitor(**cfg, max_candidates=min(1 << 22, 4 * n_pairs + 64), timing=True,
+                         scan_xcd=form == "xcd", scan_dedup=form == "dedup",
+                         scan_blocks=blocks, lean_report=True)
         m.scan(pairs)                    # warm the footprint
-        m.timings(reset=True)
+        m.estimate(copy=False)
+        ms = 0.0
         for _ in range(repeats):
+            m.timings(reset=True)
             m.scan(pairs)
-        t = m.timings(reset=True)
+            ms += m.timings(reset=True)["scan_ms"]
+            m.estimate(copy=False)       # the next scan meets this slice's stamps
         m.close()
-        results["%s/%d" % ("xcd" if xcd else "flat", blocks)] = t["scan_ms"] / repeats
+        results["%s/%d" % (form, blocks)] = ms / repeats
     best = min(results, key=results.get)
     form, blocks = best.split("/")
-    choice = {"scan_xcd": form == "xcd", "scan_blocks": int(blocks), "ms": results[best],
-              "all": results}
+    choice = {"scan_xcd": form == "xcd", "scan_dedup": form == "dedup",
+              "scan_blocks": int(blocks), "ms": results[best], "all": results}
     if cache:
         table = _load(cache)
         table[key] = choice

@@ -25,6 +25,7 @@
 
 #include "../../include/srla.h"
 #include "srla_discrete.h"
+#include "srla_scan_dedup.h"
 #include "srla_internal.h"
 
 using namespace srla;
@@ -68,7 +69,8 @@ bool config_ok(const srla_config_t* c) {
   if (c->threshold < 1) return false;
   if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
   if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH |
-                              SRLA_CFG_DISCRETE | SRLA_CFG_LEAN_REPORT)) != 0)
+                              SRLA_CFG_DISCRETE | SRLA_CFG_LEAN_REPORT |
+                              SRLA_CFG_SCAN_DEDUP)) != 0)
     return false;
   if ((c->flags & SRLA_CFG_DISCRETE) && c->window_slices != 1) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
@@ -169,6 +171,7 @@ struct srla_monitor {
   // timing
   bool timing = false;
   bool xcd_scan = false;
+  bool dedup_scan = false;
   std::vector<TimedSpan> spans;
   std::vector<hipEvent_t> ev_pool;
   double acc_ms[ST_N] = {0, 0, 0, 0, 0, 0};
@@ -463,6 +466,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->xcd_scan = (cfg->flags & SRLA_CFG_SCAN_XCD) != 0;
   m->use_graph = (cfg->flags & SRLA_CFG_GRAPH) != 0;
   m->discrete = (cfg->flags & SRLA_CFG_DISCRETE) != 0;
+  m->dedup_scan = (cfg->flags & SRLA_CFG_SCAN_DEDUP) != 0;
 
   const srla_geometry_t& g = cfg->geom;
   Geo& geo = m->geo;
@@ -615,6 +619,9 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     HIP_TRY(m, m->discrete
                    ? launch_scan_bits(pairs, n, m->geo, m->lebits[p], m->rebits[p],
                                       m->touched[p], m->tcount + p, m->cfg.scan_blocks, m->stream)
+                   : m->dedup_scan
+                   ? launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
+                                       m->tcount + p, m->cfg.scan_blocks, m->stream)
                    : launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                                  m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream));
     span_end(m, m->stream, ST_SCAN, a);
@@ -649,6 +656,10 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     HIP_TRY(m, m->discrete
                    ? launch_scan_bits(m->d_stage[b], cnt, m->geo, m->lebits[p], m->rebits[p],
                                       m->touched[p], m->tcount + p, m->cfg.scan_blocks, m->stream)
+                   : m->dedup_scan
+                   ? launch_scan_dedup(m->d_stage[b], cnt, m->geo, code, m->le, m->re,
+                                       m->touched[p], m->tcount + p, m->cfg.scan_blocks,
+                                       m->stream)
                    : launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched[p],
                                  m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream));
     span_end(m, m->stream, ST_SCAN, a);

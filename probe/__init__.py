@@ -3,7 +3,8 @@
 ``random_store_rate(bytes)`` measures random 2-byte stores per second over a
 footprint of ``bytes`` (the scan's access pattern without its pair loads and
 hashing); ``random_or_rate(bytes)`` the same for one-bit atomic ORs into
-32-bit words (the discrete-window scan's pattern).  Measurement
+32-bit words (the discrete-window scan's pattern), ``random_load_rate(bytes)``
+for random 2-byte loads.  Measurement
 infrastructure only; the SRLA library does not use it.
 """
 import ctypes
@@ -40,6 +41,8 @@ def _load():
                                          ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
         L.probe_random_or.restype = ctypes.c_double
         L.probe_random_or.argtypes = L.probe_random_store.argtypes
+        L.probe_random_load.restype = ctypes.c_double
+        L.probe_random_load.argtypes = L.probe_random_store.argtypes
         _lib = L
     return _lib
 
@@ -52,6 +55,11 @@ def random_store_rate(nbytes, stores=1 << 27, repeats=3):
 def random_or_rate(nbytes, ops=1 << 27, repeats=3):
     """Best-of-`repeats` random one-bit atomic ORs per second over `nbytes`."""
     return _rate("probe_random_or", nbytes, ops, repeats)
+
+
+def random_load_rate(nbytes, loads=1 << 27, repeats=3):
+    """Best-of-`repeats` random 2-byte loads per second over `nbytes`."""
+    return _rate("probe_random_load", nbytes, loads, repeats)
 
 
 def _rate(fn, nbytes, stores, repeats):

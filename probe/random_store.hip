@@ -41,7 +41,42 @@ __global__ __launch_bounds__(256) void k_random_or(uint32_t* __restrict__ buf, u
   }
 }
 
+// every lane loads `per_lane` random 2-byte cells (the test-before-store
+// pattern's reads); one sum per lane is written so the loads stay live
+__global__ __launch_bounds__(256) void k_random_load(const uint16_t* __restrict__ buf,
+                                                    uint64_t cells, uint32_t per_lane,
+                                                    uint64_t seed, uint32_t* __restrict__ sink) {
+  const uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  uint64_t s = mix64(seed ^ (t * 0x9E3779B97F4A7C15ull));
+  uint32_t acc = 0;
+  for (uint32_t i = 0; i < per_lane; ++i) {
+    s = mix64(s + 0x9E3779B97F4A7C15ull);
+    acc += buf[(uint64_t)(((unsigned __int128)s * cells) >> 64)];
+  }
+  if (acc == 0xFFFFFFFFu) sink[0] = acc;   // practically never; keeps the loads
+}
+
 }  // namespace
+
+// Same for random 2-byte loads (footprint in bytes).
+extern "C" double probe_random_load(void* buf, uint64_t bytes, uint64_t blocks, uint32_t per_lane,
+                                    uint64_t seed, void* stream) {
+  if (!buf || bytes < 8 || blocks == 0) return -1.0;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -2.0;
+  hipEventRecord(a, st);
+  // the sink is the buffer's first word (the cells read are left unchanged)
+  hipLaunchKernelGGL(k_random_load, dim3((uint32_t)blocks), dim3(256), 0, st,
+                     (const uint16_t*)buf, bytes / 2, per_lane, seed, (uint32_t*)buf);
+  hipEventRecord(b, st);
+  float ms = -3.f;
+  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+    ms = -4.f;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms;
+}
 
 // Same for the atomic-OR pattern (footprint in bytes, a multiple of 4).
 extern "C" double probe_random_or(void* buf, uint64_t bytes, uint64_t blocks, uint32_t per_lane,

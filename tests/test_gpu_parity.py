@@ -26,9 +26,9 @@ def _gpu():
 
 
 def _run(stream, mon, slices, max_candidates=1 << 16, dump_every=1, split=None, host=False,
-         scan_xcd=False, graph=False, discrete=False):
+         scan_xcd=False, graph=False, discrete=False, scan_dedup=False):
     g = srla.Monitor(**mon, max_candidates=max_candidates, scan_xcd=scan_xcd, graph=graph,
-                     discrete=discrete)
+                     discrete=discrete, scan_dedup=scan_dedup)
     o = oracle.Monitor(**mon)
     for s in slices:
         pairs = stream.slice(s) if hasattr(stream, "slice") else stream(s)
@@ -116,9 +116,10 @@ def test_small_geometries(case, scan_xcd, graph):
 
 
 def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chunks=1,
-                   discrete=False):
+                   discrete=False, scan_dedup=False):
     """The next slice is scanned before the previous slice's report is taken."""
-    g = srla.Monitor(**mon, max_candidates=max_candidates, graph=graph, discrete=discrete)
+    g = srla.Monitor(**mon, max_candidates=max_candidates, graph=graph, discrete=discrete,
+                     scan_dedup=scan_dedup)
     o = oracle.Monitor(**mon)
     expected = []
     slices = list(slices)
@@ -393,7 +394,8 @@ def test_autotuner_picks_a_valid_shape_and_results_do_not_change(tmp_path):
     pairs = to_device(stream.slice(0))
     cache = str(tmp_path / "tune.json")
     choice = autotune.tune_scan(mon, pairs, repeats=2, cache=cache)
-    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "xcd/0", "xcd/1024"}
+    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "xcd/0", "xcd/1024",
+                                  "dedup/0", "dedup/1024"}
     assert choice["ms"] == min(choice["all"].values()) > 0
     assert autotune.tune_scan(mon, pairs, cache=cache) == choice      # served from the cache
     _run(stream, mon, range(6), scan_xcd=choice["scan_xcd"])
@@ -464,3 +466,28 @@ def test_lean_report_carries_ip_est_flags_of_the_full_report():
         rl.union_weight, rl.re_weight = rc.union_weight, rc.re_weight
         compare_reports(rl, rc, mon["theta"], "slice %d" % s)
     lean.close()
+
+
+# ------------------------------------------------------------ read-before-write scan
+# SRLA_CFG_SCAN_DEDUP skips stores of stamps a DR already holds; every
+# result must stay bit-identical to the oracle.
+
+@pytest.mark.parametrize("case", SMALL)
+def test_dedup_scan_small_geometries(case):
+    k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
+    mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=5000 + k + u)
+    _run(_rand_stream(k + u + 3, n, n_src, 3 * theta // 2), mon, range(slices), scan_dedup=True)
+
+
+def test_dedup_scan_tiny_host_input_and_streaming():
+    stream, mon, n = workload("tiny")
+    _run(stream, mon, range(n), scan_dedup=True, host=True, split=40001)
+    _run_streaming(stream, mon, range(n), graph=True, chunks=3, scan_dedup=True)
+
+
+def test_dedup_scan_backbone_expiry_and_full_size_prefix():
+    stream, mon, _ = workload("backbone_k16")
+    _run(scaled(stream, 600_000), mon, range(40), max_candidates=1 << 22, dump_every=13,
+         scan_dedup=True)
+    stream, mon, _ = workload("backbone")
+    _run(stream, mon, range(3), max_candidates=1 << 22, dump_every=0, scan_dedup=True)
