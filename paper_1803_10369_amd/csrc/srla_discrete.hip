@@ -45,13 +45,50 @@ __device__ __forceinline__ uint64_t le_bit(const Geo& geo, uint32_t row, uint32_
   return ((uint64_t)row * geo.v_le + hrange(mas(geo.rh[row], a), geo.v_le)) * geo.G + lei;
 }
 
+// Sampled sources.  A discrete slice is long (the paper's is 300 s), so
+// most sampled pairs repeat a source already sampled in the slice.  Each
+// source is first inserted into the slice's source set -- open addressing
+// over 64-bit slots holding aip + 1 (0 = empty), probed linearly from a
+// MurmurHash3-finalizer hash, each slot tested with a plain load before any
+// compare-and-swap -- and only appended to the sampled-source list when
+// kSetProbes slots are all taken by other sources.  The slice end drains the
+// set into the list, so the list holds every sampled source at least once
+// (what the candidate check needs) and the sort sees few duplicates.
+constexpr uint32_t kSetProbes = 16;
+
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// true if aip is in the set (now or already), false if its probes are full
+__device__ __forceinline__ bool set_insert(unsigned long long* __restrict__ set,
+                                           uint32_t set_mask, uint32_t a) {
+  const unsigned long long key = (unsigned long long)a + 1ull;
+  uint32_t slot = fmix32(a) & set_mask;
+  for (uint32_t j = 0; j < kSetProbes; ++j, slot = (slot + 1u) & set_mask) {
+    unsigned long long cur =
+        __hip_atomic_load(set + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    if (cur == 0ull) cur = atomicCAS(set + slot, 0ull, key);
+    if (cur == 0ull || cur == key) return true;
+  }
+  return false;
+}
+
 // the SRE half of Algorithm 2 for one pair (2^-tau of the pairs), and the
-// wave-aggregated append of its source to the slice's sampled list
+// recording of its source (set, else a wave-aggregated append)
 __device__ __forceinline__ void sample_bits(uint32_t a, uint32_t b, bool valid, const Geo& geo,
                                             uint64_t* __restrict__ rebits,
+                                            unsigned long long* __restrict__ set,
+                                            uint32_t set_mask,
                                             uint32_t* __restrict__ touched,
                                             uint32_t* __restrict__ tcount) {
   const bool sampled = valid && (mas(geo.h1, b) & geo.tau_mask) == 0u;
+  bool append = false;
   if (sampled) {
     const uint32_t rei = hrange(mas(geo.h2, b), geo.g);
     for (uint32_t i = 0; i < geo.u; ++i) {
@@ -59,14 +96,15 @@ __device__ __forceinline__ void sample_bits(uint32_t a, uint32_t b, bool valid, 
           ((uint64_t)i * geo.v_re + hrange(mas(geo.rh[i], a), geo.v_re)) * geo.g + rei;
       set_bit_if_clear(rebits, bit, peek_word(rebits, bit));
     }
+    append = !set_insert(set, set_mask, a);
   }
-  const uint64_t mask = __ballot(sampled);
+  const uint64_t mask = __ballot(append);
   if (mask != 0ull) {
     const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
     uint32_t base = 0;
     if (__lane_id() == leader) base = atomicAdd(tcount, (uint32_t)__popcll(mask));
     base = __shfl(base, (int)leader);
-    if (sampled) touched[base + lane_rank(mask)] = a;
+    if (append) touched[base + lane_rank(mask)] = a;
   }
 }
 
@@ -75,6 +113,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_bits(const uint32_t* __restrict
                                                      uint64_t n, Geo geo,
                                                      uint64_t* __restrict__ lebits,
                                                      uint64_t* __restrict__ rebits,
+                                                     unsigned long long* __restrict__ set,
+                                                     uint32_t set_mask,
                                                      uint32_t* __restrict__ touched,
                                                      uint32_t* __restrict__ tcount) {
   for (uint64_t base = (uint64_t)blockIdx.x * kBitTile; base < n;
@@ -133,36 +173,84 @@ __global__ __launch_bounds__(kBlock) void k_scan_bits(const uint32_t* __restrict
     }
 #pragma unroll
     for (int s = 0; s < kBitSteps; ++s) {
-      sample_bits(a[s][0], b[s][0], v[s][0], geo, rebits, touched, tcount);
-      sample_bits(a[s][1], b[s][1], v[s][1], geo, rebits, touched, tcount);
+      sample_bits(a[s][0], b[s][0], v[s][0], geo, rebits, set, set_mask, touched, tcount);
+      sample_bits(a[s][1], b[s][1], v[s][1], geo, rebits, set, set_mask, touched, tcount);
     }
   }
 }
 
 template <int U>
 static hipError_t launch_scan_bits_u(const uint32_t* pairs, uint64_t n, const Geo& geo,
-                                     uint64_t* lebits, uint64_t* rebits, uint32_t* touched,
-                                     uint32_t* tcount, uint32_t max_blocks, hipStream_t st) {
+                                     uint64_t* lebits, uint64_t* rebits, uint64_t* set,
+                                     uint32_t set_slots, uint32_t* touched, uint32_t* tcount,
+                                     uint32_t max_blocks, hipStream_t st) {
   uint64_t blocks = (n + kBitTile - 1) / kBitTile;
   if (max_blocks && blocks > max_blocks) blocks = max_blocks;
+  unsigned long long* s = reinterpret_cast<unsigned long long*>(set);
   if (((uintptr_t)pairs & 15u) == 0)
     hipLaunchKernelGGL((k_scan_bits<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st,
-                       pairs, n, geo, lebits, rebits, touched, tcount);
+                       pairs, n, geo, lebits, rebits, s, set_slots - 1u, touched, tcount);
   else
     hipLaunchKernelGGL((k_scan_bits<U, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, st,
-                       pairs, n, geo, lebits, rebits, touched, tcount);
+                       pairs, n, geo, lebits, rebits, s, set_slots - 1u, touched, tcount);
   return hipGetLastError();
 }
 
 hipError_t launch_scan_bits(const uint32_t* pairs, uint64_t n, const Geo& geo, uint64_t* lebits,
-                            uint64_t* rebits, uint32_t* touched, uint32_t* tcount,
-                            uint32_t max_blocks, hipStream_t st) {
+                            uint64_t* rebits, uint64_t* set, uint32_t set_slots,
+                            uint32_t* touched, uint32_t* tcount, uint32_t max_blocks,
+                            hipStream_t st) {
   if (n == 0) return hipSuccess;
+  if (set_slots == 0 || (set_slots & (set_slots - 1u)) != 0) return hipErrorInvalidValue;
   switch (geo.u) {
-    case 4: return launch_scan_bits_u<4>(pairs, n, geo, lebits, rebits, touched, tcount, max_blocks, st);
-    case 8: return launch_scan_bits_u<8>(pairs, n, geo, lebits, rebits, touched, tcount, max_blocks, st);
-    default: return launch_scan_bits_u<0>(pairs, n, geo, lebits, rebits, touched, tcount, max_blocks, st);
+    case 4:
+      return launch_scan_bits_u<4>(pairs, n, geo, lebits, rebits, set, set_slots, touched,
+                                   tcount, max_blocks, st);
+    case 8:
+      return launch_scan_bits_u<8>(pairs, n, geo, lebits, rebits, set, set_slots, touched,
+                                   tcount, max_blocks, st);
+    default:
+      return launch_scan_bits_u<0>(pairs, n, geo, lebits, rebits, set, set_slots, touched,
+                                   tcount, max_blocks, st);
   }
+}
+
+// ------------------------------------------------------------------ set drain
+// Appends every source of the slice's source set to the sampled-source list
+// (after the entries the scans appended on overflow) and empties the set for
+// the slice that will use it next.
+__global__ __launch_bounds__(kBlock) void k_drain_set(unsigned long long* __restrict__ set,
+                                                     uint32_t slots,
+                                                     uint32_t* __restrict__ touched,
+                                                     uint32_t* __restrict__ tcount) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  // the loop bound is uniform per wavefront, so the ballot sees every lane
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < slots; base += stride) {
+    const uint64_t i = base + threadIdx.x;
+    unsigned long long key = 0ull;
+    if (i < slots) {
+      key = set[i];
+      if (key) set[i] = 0ull;
+    }
+    const bool has = key != 0ull;
+    const uint64_t mask = __ballot(has);
+    if (mask != 0ull) {
+      const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
+      uint32_t at = 0;
+      if (__lane_id() == leader) at = atomicAdd(tcount, (uint32_t)__popcll(mask));
+      at = __shfl(at, (int)leader);
+      if (has) touched[at + lane_rank(mask)] = (uint32_t)(key - 1ull);
+    }
+  }
+}
+
+hipError_t launch_drain_set(uint64_t* set, uint32_t set_slots, uint32_t* touched,
+                            uint32_t* tcount, hipStream_t st) {
+  uint64_t blocks = ((uint64_t)set_slots + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_drain_set, dim3((uint32_t)blocks), dim3(kBlock), 0, st,
+                     reinterpret_cast<unsigned long long*>(set), set_slots, touched, tcount);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ row fills

@@ -110,6 +110,8 @@ struct srla_monitor {
   bool discrete = false;         // k = 1 with one bit per DR
   uint64_t* lebits[2] = {nullptr, nullptr};  // discrete form: LE / SRE bits by slice parity
   uint64_t* rebits[2] = {nullptr, nullptr};
+  uint64_t* sset[2] = {nullptr, nullptr};    // discrete form: sampled-source sets by parity
+  uint32_t set_slots = 0;
   uint32_t* si_cnt = nullptr;    // [u][v_re][16] counters; SI bit = counter > 0
   uint64_t n_le = 0, n_re = 0, n_si = 0;
   uint64_t* bitmap = nullptr;    // LE DRs inside the window
@@ -230,6 +232,15 @@ uint64_t candidate_bytes(uint64_t cap) {
 
 uint64_t bitmap_words(uint64_t cells) { return (cells + 63) / 64 + 1; }
 
+// slots of the discrete form's sampled-source set: the power of two at least
+// twice max_candidates (a slice's distinct sampled sources are its new
+// candidates), within [2^12, 2^24]
+uint32_t source_set_slots(uint64_t max_candidates) {
+  uint64_t s = 1u << 12;
+  while (s < 2 * max_candidates && s < (1u << 24)) s <<= 1;
+  return (uint32_t)s;
+}
+
 hipEvent_t pooled_event(srla_monitor* m) {
   if (!m->ev_pool.empty()) {
     hipEvent_t e = m->ev_pool.back();
@@ -344,6 +355,8 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
+  if (e == hipSuccess && m->discrete)
+    e = launch_drain_set(m->sset[p], m->set_slots, m->touched[p], tc, st);
   if (e == hipSuccess)
     e = radix_sort_u32(m->touched[p], m->touched_tmp, tc, m->touched_cap, m->hist, st);
   if (e == hipSuccess)
@@ -399,7 +412,7 @@ void release(srla_monitor* m) {
   collect_spans(m);
   drop_graphs(m);
   dfree(m->le); dfree(m->re); dfree(m->si_cnt);
-  for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); } dfree(m->bitmap); dfree(m->act_now);
+  for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); dfree(m->sset[i]); } dfree(m->bitmap); dfree(m->act_now);
   dfree(m->act_next); dfree(m->row_fill); dfree(m->up); dfree(m->cnt); dfree(m->ps);
   dfree(m->tcount);
   dfree(m->touched[0]); dfree(m->touched[1]); dfree(m->touched_tmp); dfree(m->mark);
@@ -434,7 +447,8 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   const uint64_t si = (uint64_t)g.u * g.v_re;
   if (cfg->flags & SRLA_CFG_DISCRETE)
-    return 16 * bitmap_words(le) + 24 * bitmap_words(re) + 64 * si + 8 * g.u + 8 +
+    return 16 * bitmap_words(le) + 24 * bitmap_words(re) +
+           16 * (uint64_t)source_set_slots(cfg->max_candidates) + 64 * si + 8 * g.u + 8 +
            sizeof(Counters) + sizeof(PipeState) + 8 + candidate_bytes(cfg->max_candidates);
   return 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
          8 * g.u + 8 + sizeof(Counters) + sizeof(PipeState) + 8 +
@@ -514,9 +528,11 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->n_si = (uint64_t)g.u * g.v_re;
   m->cap = cfg->max_candidates;
   if (m->discrete) {
+    m->set_slots = source_set_slots(cfg->max_candidates);
     for (int i = 0; i < 2 && !rc; ++i) {
       nomem(dalloc(&m->lebits[i], bitmap_words(m->n_le)));
       if (!rc) nomem(dalloc(&m->rebits[i], bitmap_words(m->n_re)));
+      if (!rc) nomem(dalloc(&m->sset[i], m->set_slots));
     }
   } else {
     nomem(dalloc(&m->le, m->n_le));
@@ -571,6 +587,8 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
       e = launch_fill_u32((uint32_t*)m->lebits[i], 0u, 2 * bitmap_words(m->n_le), m->stream);
       if (e == hipSuccess)
         e = launch_fill_u32((uint32_t*)m->rebits[i], 0u, 2 * bitmap_words(m->n_re), m->stream);
+      if (e == hipSuccess)
+        e = launch_fill_u32((uint32_t*)m->sset[i], 0u, 2ull * m->set_slots, m->stream);
     }
     if (e == hipSuccess)
       e = launch_fill_u32((uint32_t*)m->act_next, 0u, 2 * bitmap_words(m->n_re), m->stream);
@@ -617,8 +635,9 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     hipEvent_t a;
     span_begin(m, m->stream, &a);
     HIP_TRY(m, m->discrete
-                   ? launch_scan_bits(pairs, n, m->geo, m->lebits[p], m->rebits[p],
-                                      m->touched[p], m->tcount + p, m->cfg.scan_blocks, m->stream)
+                   ? launch_scan_bits(pairs, n, m->geo, m->lebits[p], m->rebits[p], m->sset[p],
+                                      m->set_slots, m->touched[p], m->tcount + p,
+                                      m->cfg.scan_blocks, m->stream)
                    : m->dedup_scan
                    ? launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                                        m->tcount + p, m->cfg.scan_blocks, m->stream)
@@ -655,7 +674,8 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     span_begin(m, m->stream, &a);
     HIP_TRY(m, m->discrete
                    ? launch_scan_bits(m->d_stage[b], cnt, m->geo, m->lebits[p], m->rebits[p],
-                                      m->touched[p], m->tcount + p, m->cfg.scan_blocks, m->stream)
+                                      m->sset[p], m->set_slots, m->touched[p], m->tcount + p,
+                                      m->cfg.scan_blocks, m->stream)
                    : m->dedup_scan
                    ? launch_scan_dedup(m->d_stage[b], cnt, m->geo, code, m->le, m->re,
                                        m->touched[p], m->tcount + p, m->cfg.scan_blocks,
