@@ -7,7 +7,11 @@ tune_scan() times every candidate on a scratch monitor of the caller's
 geometry with the caller's pairs, one scan per slice (each timed scan meets
 the stamps of an earlier slice, as a real slice does, so the read-before-write
 form gets no advantage from rescanning), picks the fastest, and caches the
-choice per (geometry, pairs per scan, device) in a JSON file.  tune_group() does the
+choice per (geometry, pairs per scan, device) in a JSON file.  Given several
+pair buffers whose total exceeds the 256 MB last-level cache, consecutive
+scans read different buffers, so each meets its pairs cold in HBM as a live
+stream does (rescanning one cached buffer would favour forms that read the
+pairs more than once).  tune_group() does the
 same for a monitor group's fused scan, on temporary groups over the caller's
 own monitors during an open slice (rescanning a slice's pairs leaves every
 result unchanged: stores are idempotent and repeated sampled sources are
@@ -51,8 +55,10 @@ def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False
     """Returns {"scan_xcd": bool, "scan_dedup": bool, "scan_blocks": int,
     "ms": float, "all": {...}}
     for monitors of geometry `cfg` (Monitor keyword arguments) scanning
-    `pairs` (a CUDA tensor of 2n values) per call."""
-    n_pairs = pairs.numel() // 2
+    `pairs` (a CUDA tensor of 2n values, or a list of such tensors of equal
+    size, used in turn) per call."""
+    bufs = list(pairs) if isinstance(pairs, (list, tuple)) else [pairs]
+    n_pairs = bufs[0].numel() // 2
     key = _key(cfg, n_pairs)
     table = _load(cache) if cache else {}
     if not refresh and key in table:
@@ -62,12 +68,12 @@ def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False
         m = srla.Monitor(**cfg, max_candidates=min(1 << 22, 4 * n_pairs + 64), timing=True,
                          scan_xcd=form == "xcd", scan_dedup=form == "dedup",
                          scan_blocks=blocks, lean_report=True)
-        m.scan(pairs)                    # warm the footprint
+        m.scan(bufs[0])                  # warm the footprint
         m.estimate(copy=False)
         ms = 0.0
-        for _ in range(repeats):
+        for r in range(repeats):
             m.timings(reset=True)
-            m.scan(pairs)
+            m.scan(bufs[(r + 1) % len(bufs)])
             ms += m.timings(reset=True)["scan_ms"]
             m.estimate(copy=False)       # the next scan meets this slice's stamps
         m.close()

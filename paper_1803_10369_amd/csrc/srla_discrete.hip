@@ -218,37 +218,68 @@ hipError_t launch_scan_bits(const uint32_t* pairs, uint64_t n, const Geo& geo, u
 // ------------------------------------------------------------------ set drain
 // Appends every source of the slice's source set to the sampled-source list
 // (after the entries the scans appended on overflow) and empties the set for
-// the slice that will use it next.
+// the slice that will use it next.  Each block owns a contiguous chunk of
+// slots: it counts the chunk's sources, reserves their places with a single
+// atomic, then writes them in slot order (wave ballots + an LDS prefix over
+// the block's waves) and clears the slots.  One atomic per block, not per
+// wave: the list's counter would otherwise serialize the drain.
+constexpr uint32_t kDrainBlocks = 2048;
+
+__device__ __forceinline__ uint32_t block_prefix(bool flag, uint32_t* s_wave, uint32_t* total) {
+  const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const uint64_t mask = __ballot(flag);
+  if (lane == 0) s_wave[wave] = (uint32_t)__popcll(mask);
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+  for (uint32_t w = 0; w < kBlock / kWave; ++w) {
+    if (w < wave) before += s_wave[w];
+    all += s_wave[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + lane_rank(mask);
+}
+
 __global__ __launch_bounds__(kBlock) void k_drain_set(unsigned long long* __restrict__ set,
                                                      uint32_t slots,
                                                      uint32_t* __restrict__ touched,
                                                      uint32_t* __restrict__ tcount) {
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  // the loop bound is uniform per wavefront, so the ballot sees every lane
-  for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < slots; base += stride) {
+  __shared__ uint32_t s_wave[kBlock / kWave];
+  __shared__ uint32_t s_base;
+  const uint64_t chunk = ((uint64_t)slots + gridDim.x - 1) / gridDim.x;
+  const uint64_t lo = (uint64_t)blockIdx.x * chunk;
+  const uint64_t hi = lo + chunk < slots ? lo + chunk : slots;
+  uint32_t mine = 0;
+  for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) mine += set[i] != 0ull;
+  for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+  if ((threadIdx.x & (kWave - 1)) == 0) s_wave[threadIdx.x / kWave] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (uint32_t w = 0; w < kBlock / kWave; ++w) t += s_wave[w];
+    s_base = t ? atomicAdd(tcount, t) : 0u;
+  }
+  __syncthreads();
+  uint32_t at = s_base;
+  // the loop bound is uniform per block, so every thread reaches the barriers
+  for (uint64_t base = lo; base < hi; base += kBlock) {
     const uint64_t i = base + threadIdx.x;
-    unsigned long long key = 0ull;
-    if (i < slots) {
-      key = set[i];
-      if (key) set[i] = 0ull;
+    const unsigned long long key = i < hi ? set[i] : 0ull;
+    uint32_t step;
+    const uint32_t pos = block_prefix(key != 0ull, s_wave, &step);
+    if (key) {
+      touched[at + pos] = (uint32_t)(key - 1ull);
+      set[i] = 0ull;
     }
-    const bool has = key != 0ull;
-    const uint64_t mask = __ballot(has);
-    if (mask != 0ull) {
-      const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
-      uint32_t at = 0;
-      if (__lane_id() == leader) at = atomicAdd(tcount, (uint32_t)__popcll(mask));
-      at = __shfl(at, (int)leader);
-      if (has) touched[at + lane_rank(mask)] = (uint32_t)(key - 1ull);
-    }
+    at += step;
   }
 }
 
 hipError_t launch_drain_set(uint64_t* set, uint32_t set_slots, uint32_t* touched,
                             uint32_t* tcount, hipStream_t st) {
-  uint64_t blocks = ((uint64_t)set_slots + kBlock - 1) / kBlock;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_drain_set, dim3((uint32_t)blocks), dim3(kBlock), 0, st,
+  const uint32_t blocks = set_slots / kBlock < kDrainBlocks ? (set_slots + kBlock - 1) / kBlock
+                                                             : kDrainBlocks;
+  hipLaunchKernelGGL(k_drain_set, dim3(blocks), dim3(kBlock), 0, st,
                      reinterpret_cast<unsigned long long*>(set), set_slots, touched, tcount);
   return hipGetLastError();
 }
