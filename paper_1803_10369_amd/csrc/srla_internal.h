@@ -133,10 +133,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t 
 // Algorithm 2 for n pairs of the open slice (stamp code `code`); sampled
 // sources are appended to `touched`, counted in *tcount.  max_blocks caps
 // the grid (0: one block per tile of pairs).
-// split: leave XCD 7 to the end-of-slice pipeline (see k_scan_flat)
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                        uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
-                       bool xcd_aware, uint32_t max_blocks, hipStream_t st, bool split = false);
+                       bool xcd_aware, uint32_t max_blocks, hipStream_t st);
 
 // Algorithm 2 of every member of a group for n pairs, each pair loaded once
 hipError_t launch_scan_group(const uint32_t* pairs, uint64_t n, const GroupMember* members,
@@ -176,11 +175,10 @@ hipError_t launch_merge(const uint32_t* ncsip, const PipeState* ps, const uint32
 hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
                              double* up, hipStream_t st);
 
-// split: run on the blocks the dispatch places on XCD 7 only
 hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
                            const uint64_t* act_now, const uint64_t* act_next, const double* up,
                            const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
-                           hipStream_t st, bool split = false);
+                           hipStream_t st);
 
 // Algorithm 3's SI step on the per-bit counters (after the KEEP flags are final)
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,

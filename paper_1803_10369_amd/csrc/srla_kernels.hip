@@ -358,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
     const uint64_t* __restrict__ act_next, const double* __restrict__ up_p, Geo geo,
     uint32_t lg_log2, uint8_t* __restrict__ cflags, uint32_t* __restrict__ out_ip,
     double* __restrict__ out_est, uint8_t* __restrict__ out_flags, uint32_t* __restrict__ out_U,
-    uint8_t* __restrict__ out_W, uint32_t split) {
+    uint8_t* __restrict__ out_W) {
   __shared__ double s_est[kEstPerBlock];
   __shared__ uint32_t s_ip[kEstPerBlock], s_U[kEstPerBlock];
   __shared__ uint8_t s_W[kEstPerBlock], s_f[kEstPerBlock];
@@ -369,15 +369,8 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
   const uint64_t gmask = geo.g == 64u ? ~0ull : ((1ull << geo.g) - 1ull);
   const double up = *up_p;
   const double G = (double)geo.G;
-  // split: only the blocks the round-robin dispatch places on XCD 7 work
-  // (the next slice's scan leaves that XCD and its L2 to this kernel)
-  uint64_t eb = blockIdx.x, eg = gridDim.x;
-  if (split) {
-    if (blockIdx.x % 8u != 7u) return;
-    eb = blockIdx.x / 8u;
-    eg = gridDim.x / 8u;
-  }
-  for (uint64_t base = eb * kEstPerBlock; base < n; base += eg * kEstPerBlock) {
+  for (uint64_t base = (uint64_t)blockIdx.x * kEstPerBlock; base < n;
+       base += (uint64_t)gridDim.x * kEstPerBlock) {
   for (uint32_t round = 0; round * per_round < kEstPerBlock; ++round) {
     const uint32_t local = round * per_round + (threadIdx.x >> lg_log2);
     const uint64_t gid = base + local;
@@ -464,10 +457,10 @@ static uint32_t est_lg_log2(const Geo& geo) {
 hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
                            const uint64_t* act_now, const uint64_t* act_next, const double* up,
                            const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
-                           hipStream_t st, bool split) {
+                           hipStream_t st) {
   hipLaunchKernelGGL(k_estimate, dim3(2 * kPipeBlocks), dim3(kBlock), 0, st, csip, cnt, bitmap,
                      act_now, act_next, up, geo, est_lg_log2(geo), cflags, out.ip, out.est,
-                     out.flags, out.U, out.W, split ? 1u : 0u);
+                     out.flags, out.U, out.W);
   return hipGetLastError();
 }
 

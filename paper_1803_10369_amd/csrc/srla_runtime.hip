@@ -70,7 +70,7 @@ bool config_ok(const srla_config_t* c) {
   if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
   if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH |
                               SRLA_CFG_DISCRETE | SRLA_CFG_LEAN_REPORT |
-                              SRLA_CFG_SCAN_DEDUP | SRLA_CFG_XCD_SPLIT)) != 0)
+                              SRLA_CFG_SCAN_DEDUP)) != 0)
     return false;
   if ((c->flags & SRLA_CFG_DISCRETE) && c->window_slices != 1) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
@@ -174,7 +174,6 @@ struct srla_monitor {
   bool timing = false;
   bool xcd_scan = false;
   bool dedup_scan = false;
-  bool xcd_split = false;
   std::vector<TimedSpan> spans;
   std::vector<hipEvent_t> ev_pool;
   double acc_ms[ST_N] = {0, 0, 0, 0, 0, 0};
@@ -371,7 +370,7 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
     e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
   if (e == hipSuccess)
     e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->act_next, m->up, geo, m->cflags,
-                        m->d_report, st, m->xcd_split);
+                        m->d_report, st);
   if (spans) span_end(m, st, ST_ESTIMATE, ta);
   if (spans) span_begin(m, st, &ta);
   if (e == hipSuccess)
@@ -482,7 +481,6 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->use_graph = (cfg->flags & SRLA_CFG_GRAPH) != 0;
   m->discrete = (cfg->flags & SRLA_CFG_DISCRETE) != 0;
   m->dedup_scan = (cfg->flags & SRLA_CFG_SCAN_DEDUP) != 0;
-  m->xcd_split = (cfg->flags & SRLA_CFG_XCD_SPLIT) != 0;
 
   const srla_geometry_t& g = cfg->geom;
   Geo& geo = m->geo;
@@ -644,8 +642,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
                    ? launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                                        m->tcount + p, m->cfg.scan_blocks, m->stream)
                    : launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
-                                 m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream,
-                                 m->xcd_split));
+                                 m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream));
     span_end(m, m->stream, ST_SCAN, a);
     m->slice_pairs[p] += n;
     m->scan_launches++;
@@ -684,8 +681,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
                                        m->touched[p], m->tcount + p, m->cfg.scan_blocks,
                                        m->stream)
                    : launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched[p],
-                                 m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream,
-                                 m->xcd_split));
+                                 m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream));
     span_end(m, m->stream, ST_SCAN, a);
     m->slice_pairs[p] += cnt;
     m->scan_launches++;

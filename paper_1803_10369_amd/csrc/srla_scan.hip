@@ -58,26 +58,17 @@ __device__ __forceinline__ void scan_one(uint32_t a, uint32_t b, bool valid, con
   }
 }
 
-// SPLIT: the blocks that the round-robin dispatch places on XCD 7 (block
-// ids 7 mod 8) leave at once, so XCD 7 and its L2 stay free for the
-// end-of-slice pipeline of the previous slice running meanwhile; the other
-// blocks cover every tile (the result does not depend on the placement).
-template <int U, bool VEC, bool SPLIT>
+template <int U, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_scan_flat(const uint32_t* __restrict__ pairs, uint64_t n,
                                                 Geo geo, uint16_t code,
                                                 uint16_t* __restrict__ le,
                                                 uint16_t* __restrict__ re,
                                                 uint32_t* __restrict__ touched,
                                                 uint32_t* __restrict__ tcount) {
-  uint64_t eb = blockIdx.x, eg = gridDim.x;
-  if (SPLIT) {
-    if (blockIdx.x % 8u == 7u) return;
-    eb = (uint64_t)(blockIdx.x / 8u) * 7u + blockIdx.x % 8u;
-    eg = (uint64_t)(gridDim.x / 8u) * 7u + (gridDim.x % 8u < 7u ? gridDim.x % 8u : 7u);
-  }
   // one tile of kScanTile pairs per iteration; the grid may be smaller than
   // the tile count (then it strides), leaving wave slots to other streams
-  for (uint64_t base = eb * kScanTile; base < n; base += eg * kScanTile) {
+  for (uint64_t base = (uint64_t)blockIdx.x * kScanTile; base < n;
+       base += (uint64_t)gridDim.x * kScanTile) {
   uint32_t a[kScanSteps][2], b[kScanSteps][2];
   bool v[kScanSteps][2];
 #pragma unroll
@@ -190,34 +181,26 @@ static hipError_t launch_scan_xcd(const uint32_t* pairs, uint64_t n, const Geo& 
   return hipGetLastError();
 }
 
-template <int U, bool SPLIT>
+template <int U>
 static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                                 uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
                                 uint32_t max_blocks, hipStream_t st) {
   uint64_t blocks = (n + kScanTile - 1) / kScanTile;
   if (max_blocks && blocks > max_blocks) blocks = max_blocks;
-  if (SPLIT) blocks = (blocks + 6) / 7 * 8;   // 7 working blocks in every 8
   const bool vec = ((uintptr_t)pairs & 15u) == 0;
   if (vec)
-    hipLaunchKernelGGL((k_scan_flat<U, true, SPLIT>), dim3((uint32_t)blocks), dim3(kBlock), 0, st,
-                       pairs, n, geo, code, le, re, touched, tcount);
+    hipLaunchKernelGGL((k_scan_flat<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
+                       geo, code, le, re, touched, tcount);
   else
-    hipLaunchKernelGGL((k_scan_flat<U, false, SPLIT>), dim3((uint32_t)blocks), dim3(kBlock), 0, st,
-                       pairs, n, geo, code, le, re, touched, tcount);
+    hipLaunchKernelGGL((k_scan_flat<U, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
+                       geo, code, le, re, touched, tcount);
   return hipGetLastError();
 }
 
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                        uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
-                       bool xcd_aware, uint32_t max_blocks, hipStream_t st, bool split) {
+                       bool xcd_aware, uint32_t max_blocks, hipStream_t st) {
   if (n == 0) return hipSuccess;
-  if (split) {
-    switch (geo.u) {
-      case 4: return launch_scan_u<4, true>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
-      case 8: return launch_scan_u<8, true>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
-      default: return launch_scan_u<0, true>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
-    }
-  }
   if (xcd_aware && ((uintptr_t)pairs & 15u) == 0) {
     switch (geo.u) {
       case 1: return launch_scan_xcd<1>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
@@ -229,9 +212,9 @@ hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16
     }
   }
   switch (geo.u) {
-    case 4: return launch_scan_u<4, false>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
-    case 8: return launch_scan_u<8, false>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
-    default: return launch_scan_u<0, false>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
+    case 4: return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
+    case 8: return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
+    default: return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
   }
 }
 

@@ -41,8 +41,6 @@ def _load():
                                          ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
         L.probe_random_or.restype = ctypes.c_double
         L.probe_random_or.argtypes = L.probe_random_store.argtypes
-        L.probe_xcc_of_blocks.restype = ctypes.c_int
-        L.probe_xcc_of_blocks.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
         L.probe_random_load.restype = ctypes.c_double
         L.probe_random_load.argtypes = L.probe_random_store.argtypes
         _lib = L
@@ -57,17 +55,6 @@ def random_store_rate(nbytes, stores=1 << 27, repeats=3):
 def random_or_rate(nbytes, ops=1 << 27, repeats=3):
     """Best-of-`repeats` random one-bit atomic ORs per second over `nbytes`."""
     return _rate("probe_random_or", nbytes, ops, repeats)
-
-
-def xcc_of_blocks(blocks=64):
-    """The XCD each of `blocks` workgroups of one launch ran on (a list)."""
-    import torch
-    out = torch.full((blocks,), 0xFF, dtype=torch.int32, device="cuda")
-    st = torch.cuda.current_stream()
-    if _load().probe_xcc_of_blocks(ctypes.c_void_p(out.data_ptr()), blocks,
-                                   ctypes.c_void_p(st.cuda_stream)) != 0:
-        raise RuntimeError("probe failed")
-    return out.cpu().tolist()
 
 
 def random_load_rate(nbytes, loads=1 << 27, repeats=3):

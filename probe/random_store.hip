@@ -56,20 +56,7 @@ __global__ __launch_bounds__(256) void k_random_load(const uint16_t* __restrict_
   if (acc == 0xFFFFFFFFu) sink[0] = acc;   // practically never; keeps the loads
 }
 
-// block b writes the id of the XCD (XCC) it runs on to out[b]: a read of a
-// hardware register, to check the round-robin placement of workgroups
-__global__ __launch_bounds__(64) void k_xcc_of_block(uint32_t* __restrict__ out) {
-  if (threadIdx.x == 0) out[blockIdx.x] = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;
-}
-
 }  // namespace
-
-extern "C" int probe_xcc_of_blocks(void* out, uint32_t blocks, void* stream) {
-  if (!out || blocks == 0) return -1;
-  hipLaunchKernelGGL(k_xcc_of_block, dim3(blocks), dim3(64), 0, (hipStream_t)stream,
-                     (uint32_t*)out);
-  return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -2;
-}
 
 // Same for random 2-byte loads (footprint in bytes).
 extern "C" double probe_random_load(void* buf, uint64_t bytes, uint64_t blocks, uint32_t per_lane,

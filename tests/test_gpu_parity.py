@@ -116,10 +116,10 @@ def test_small_geometries(case, scan_xcd, graph):
 
 
 def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chunks=1,
-                   discrete=False, scan_dedup=False, xcd_split=False):
+                   discrete=False, scan_dedup=False):
     """The next slice is scanned before the previous slice's report is taken."""
     g = srla.Monitor(**mon, max_candidates=max_candidates, graph=graph, discrete=discrete,
-                     scan_dedup=scan_dedup, xcd_split=xcd_split)
+                     scan_dedup=scan_dedup)
     o = oracle.Monitor(**mon)
     expected = []
     slices = list(slices)
@@ -149,18 +149,6 @@ def test_streaming_small_geometries(case):
     k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
     mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=1000 + k + u)
     _run_streaming(_rand_stream(k + u, n, n_src, 3 * theta // 2), mon, range(slices), graph=True)
-
-
-@pytest.mark.parametrize("case", [SMALL[0], SMALL[6]])
-def test_streaming_xcd_split(case):
-    """The scan leaves XCD 7 to the estimate: same results."""
-    k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
-    mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=1100 + k + u)
-    _run_streaming(_rand_stream(k + u + 7, n, n_src, 3 * theta // 2), mon, range(slices),
-                   graph=True, chunks=2, xcd_split=True)
-    stream, mon, _ = workload("backbone_k16")
-    _run_streaming(scaled(stream, 600_000), mon, range(20), max_candidates=1 << 22,
-                   xcd_split=True)
 
 
 def test_streaming_call_order_errors():
