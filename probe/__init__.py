@@ -41,6 +41,11 @@ def _load():
                                          ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
         L.probe_random_or.restype = ctypes.c_double
         L.probe_random_or.argtypes = L.probe_random_store.argtypes
+        L.probe_host_write.restype = ctypes.c_double
+        L.probe_host_write.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
+                                       ctypes.c_void_p]
+        L.probe_xcc_of_blocks.restype = ctypes.c_int
+        L.probe_xcc_of_blocks.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
         L.probe_random_load.restype = ctypes.c_double
         L.probe_random_load.argtypes = L.probe_random_store.argtypes
         _lib = L
@@ -55,6 +60,53 @@ def random_store_rate(nbytes, stores=1 << 27, repeats=3):
 def random_or_rate(nbytes, ops=1 << 27, repeats=3):
     """Best-of-`repeats` random one-bit atomic ORs per second over `nbytes`."""
     return _rate("probe_random_or", nbytes, ops, repeats)
+
+
+def host_write_rate(nbytes=64 << 20, blocks=2048, repeats=3):
+    """Best-of-`repeats` bytes/s of a kernel's coalesced stores into pinned host
+    memory (through its device-visible address)."""
+    import torch
+    L = _load()
+    host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    st = torch.cuda.current_stream()
+    best = None
+    for r in range(repeats + 1):
+        ms = L.probe_host_write(ctypes.c_void_p(host.data_ptr()), nbytes, blocks,
+                                ctypes.c_void_p(st.cuda_stream))
+        if ms <= 0:
+            raise RuntimeError("probe failed (%g)" % ms)
+        if r > 0:
+            best = ms if best is None else min(best, ms)
+    return nbytes / (best * 1e-3)
+
+
+def dma_d2h_rate(nbytes=64 << 20, repeats=3):
+    """Best-of-`repeats` bytes/s of a device-to-host copy into pinned memory."""
+    import torch
+    dev = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    best = None
+    for r in range(repeats + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        host.copy_(dev, non_blocking=True)
+        b.record()
+        b.synchronize()
+        if r > 0:
+            ms = a.elapsed_time(b)
+            best = ms if best is None else min(best, ms)
+    return nbytes / (best * 1e-3)
+
+
+def xcc_of_blocks(blocks=64):
+    """The XCD each of `blocks` workgroups of one launch ran on (a list)."""
+    import torch
+    out = torch.full((blocks,), 0xFF, dtype=torch.int32, device="cuda")
+    st = torch.cuda.current_stream()
+    if _load().probe_xcc_of_blocks(ctypes.c_void_p(out.data_ptr()), blocks,
+                                   ctypes.c_void_p(st.cuda_stream)) != 0:
+        raise RuntimeError("probe failed")
+    return out.cpu().tolist()
 
 
 def random_load_rate(nbytes, loads=1 << 27, repeats=3):

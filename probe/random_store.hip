@@ -56,7 +56,47 @@ __global__ __launch_bounds__(256) void k_random_load(const uint16_t* __restrict_
   if (acc == 0xFFFFFFFFu) sink[0] = acc;   // practically never; keeps the loads
 }
 
+// block b writes the id of the XCD (XCC) it runs on to out[b]: a read of a
+// hardware register, to check the round-robin placement of workgroups
+__global__ __launch_bounds__(64) void k_xcc_of_block(uint32_t* __restrict__ out) {
+  if (threadIdx.x == 0) out[blockIdx.x] = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;
+}
+
+// grid-stride coalesced 16-byte stores of `bytes` into (pinned, mapped)
+// host memory: the rate a kernel can push results over PCIe
+__global__ __launch_bounds__(256) void k_host_write(uint4* __restrict__ dst, uint64_t n16,
+                                                   uint32_t seed) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride)
+    dst[i] = make_uint4((uint32_t)i, seed, (uint32_t)(i >> 32), ~seed);
+}
+
 }  // namespace
+
+// Returns the kernel time in ms of writing `bytes` (a multiple of 16) to the
+// device-visible address of pinned host memory, or a negative value.
+extern "C" double probe_host_write(void* dst, uint64_t bytes, uint32_t blocks, void* stream) {
+  if (!dst || bytes < 16 || blocks == 0) return -1.0;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -2.0;
+  hipEventRecord(a, st);
+  hipLaunchKernelGGL(k_host_write, dim3(blocks), dim3(256), 0, st, (uint4*)dst, bytes / 16, 7u);
+  hipEventRecord(b, st);
+  float ms = -3.f;
+  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+    ms = -4.f;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms;
+}
+
+extern "C" int probe_xcc_of_blocks(void* out, uint32_t blocks, void* stream) {
+  if (!out || blocks == 0) return -1;
+  hipLaunchKernelGGL(k_xcc_of_block, dim3(blocks), dim3(64), 0, (hipStream_t)stream,
+                     (uint32_t*)out);
+  return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -2;
+}
 
 // Same for random 2-byte loads (footprint in bytes).
 extern "C" double probe_random_load(void* buf, uint64_t bytes, uint64_t blocks, uint32_t per_lane,
