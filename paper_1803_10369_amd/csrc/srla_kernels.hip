@@ -334,22 +334,15 @@ hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
 // bitmaps, Eq9 in FP64, and the flags.  A group of 2^lg_log2 lanes owns one
 // candidate; its lanes split the G/64 bitmap words (16 lanes read one
 // 128-byte line per row when G = 1024) and the u rows of the SRE, then
-// reduce with cross-lane shuffles.
-//
-// The report goes straight into the pinned host arrays (mapped into the
-// GPU's address space), which makes the kernel PCIe-bound -- provided the
-// gathers never wait for host-write completions.  A wave's memory counter
-// covers its loads and its stores alike, so a wave that both gathers and
-// writes to the host stalls its next gathers behind its last PCIe writes.
-// Hence the waves of a block specialize: waves 1..3 gather and evaluate a
-// batch of kEstBatch candidates into one LDS buffer while wave 0 writes the
-// previous batch from the other buffer to the host with 16-byte stores;
-// wave 0 issues no global loads, so its stores never hold anything up.
-// Barriers order LDS only.  U and W are written only when their buffers are
-// given (the lean report leaves them out).
+// reduce with cross-lane shuffles.  A block finishes 256 candidates, stages
+// them in LDS, and writes the report entries with one coalesced store per
+// array straight into the pinned host buffers (mapped into the GPU's address
+// space), so no separate device-to-host copy is needed.  The report is
+// PCIe-bound: the block barriers order LDS only, so a block's host writes stay
+// in flight while it gathers its next candidates; U and W are written only
+// when their buffers are given (the lean report leaves them out).
 
-constexpr uint32_t kEstWorkers = kBlock - kWave;   // threads of the gathering waves
-constexpr uint32_t kEstBatch = kEstWorkers;        // candidates per block batch
+constexpr uint32_t kEstPerBlock = kBlock;
 
 // a workgroup barrier that orders LDS accesses only (global stores issued
 // before it may still be in flight)
@@ -359,24 +352,6 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// one wave copies `bytes` bytes (a multiple of 16 unless it is the last
-// batch) from LDS to global memory
-__device__ __forceinline__ void wave_put(uint8_t* __restrict__ dst, const uint8_t* src,
-                                         uint32_t bytes, uint32_t lane) {
-  const uint32_t n16 = bytes / 16;
-#pragma unroll 1
-  for (uint32_t c = lane; c < n16; c += kWave)
-    reinterpret_cast<uint4*>(dst)[c] = reinterpret_cast<const uint4*>(src)[c];
-#pragma unroll 1
-  for (uint32_t c = n16 * 16 + lane; c < bytes; c += kWave) dst[c] = src[c];
-}
-
-struct __align__(16) EstStage {
-  double est[kEstBatch];
-  uint32_t ip[kEstBatch], U[kEstBatch];
-  uint8_t W[kEstBatch], f[kEstBatch];
-};
-
 __global__ __launch_bounds__(kBlock) void k_estimate(
     const uint32_t* __restrict__ csip, const Counters* __restrict__ cnt,
     const uint64_t* __restrict__ bitmap, const uint64_t* __restrict__ act_now,
@@ -384,98 +359,91 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
     uint32_t lg_log2, uint8_t* __restrict__ cflags, uint32_t* __restrict__ out_ip,
     double* __restrict__ out_est, uint8_t* __restrict__ out_flags, uint32_t* __restrict__ out_U,
     uint8_t* __restrict__ out_W) {
-  __shared__ EstStage stage[2];
+  __shared__ double s_est[kEstPerBlock];
+  __shared__ uint32_t s_ip[kEstPerBlock], s_U[kEstPerBlock];
+  __shared__ uint8_t s_W[kEstPerBlock], s_f[kEstPerBlock];
   const uint32_t lg = 1u << lg_log2;
-  const uint32_t n = cnt->n_cand;
-  const uint64_t first = (uint64_t)blockIdx.x * kEstBatch;
-  const uint64_t step = (uint64_t)gridDim.x * kEstBatch;
-  const uint32_t batches = first < n ? (uint32_t)((n - first + step - 1) / step) : 0u;
-  const bool writer = threadIdx.x < kWave;
-  const uint32_t wt = threadIdx.x - kWave;           // thread index among the gatherers
-  const uint32_t per_round = kEstWorkers >> lg_log2;  // candidates per round
+  const uint32_t per_round = kBlock >> lg_log2;          // candidates per round
   const uint32_t sub = threadIdx.x & (lg - 1u);
+  const uint32_t n = cnt->n_cand;
   const uint64_t gmask = geo.g == 64u ? ~0ull : ((1ull << geo.g) - 1ull);
   const double up = *up_p;
   const double G = (double)geo.G;
-  // batch it is gathered in step it and written in step it + 1
-  for (uint32_t it = 0; it <= batches; ++it) {
-    if (writer) {
-      if (it > 0) {
-        const EstStage& sb = stage[(it - 1) & 1u];
-        const uint64_t base = first + (uint64_t)(it - 1) * step;
-        const uint32_t m = n - base < kEstBatch ? (uint32_t)(n - base) : kEstBatch;
-        wave_put((uint8_t*)(out_ip + base), (const uint8_t*)sb.ip, 4 * m, threadIdx.x);
-        wave_put((uint8_t*)(out_est + base), (const uint8_t*)sb.est, 8 * m, threadIdx.x);
-        wave_put(out_flags + base, sb.f, m, threadIdx.x);
-        if (out_U) wave_put((uint8_t*)(out_U + base), (const uint8_t*)sb.U, 4 * m, threadIdx.x);
-        if (out_W) wave_put(out_W + base, sb.W, m, threadIdx.x);
+  for (uint64_t base = (uint64_t)blockIdx.x * kEstPerBlock; base < n;
+       base += (uint64_t)gridDim.x * kEstPerBlock) {
+  for (uint32_t round = 0; round * per_round < kEstPerBlock; ++round) {
+    const uint32_t local = round * per_round + (threadIdx.x >> lg_log2);
+    const uint64_t gid = base + local;
+    const bool valid = local < kEstPerBlock && gid < n;
+    const uint32_t a = valid ? csip[gid] : 0u;
+    uint32_t ucount = 0;
+    uint64_t m_now = ~0ull, m_next = ~0ull;
+    if (valid) {
+      for (uint32_t x = sub; x < geo.words; x += lg) {
+        uint64_t acc = ~0ull;
+        for (uint32_t r = 0; r < geo.u; ++r) {
+          const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_le);
+          acc &= bitmap[((uint64_t)r * geo.v_le + col) * geo.words + x];
+        }
+        ucount += (uint32_t)__popcll(acc);
       }
-    } else if (it < batches) {
-      EstStage& sb = stage[it & 1u];
-      const uint64_t base = first + (uint64_t)it * step;
-      for (uint32_t round = 0; round * per_round < kEstBatch; ++round) {
-        const uint32_t local = round * per_round + (wt >> lg_log2);
-        const uint64_t gid = base + local;
-        const bool valid = local < kEstBatch && gid < n;
-        const uint32_t a = valid ? csip[gid] : 0u;
-        uint32_t ucount = 0;
-        uint64_t m_now = ~0ull, m_next = ~0ull;
-        if (valid) {
-          for (uint32_t x = sub; x < geo.words; x += lg) {
-            uint64_t acc = ~0ull;
-            for (uint32_t r = 0; r < geo.u; ++r) {
-              const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_le);
-              acc &= bitmap[((uint64_t)r * geo.v_le + col) * geo.words + x];
-            }
-            ucount += (uint32_t)__popcll(acc);
-          }
-          for (uint32_t r = sub; r < geo.u; r += lg) {
-            const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
-            m_now &= sre_bits(act_now, geo, r, col);
-            m_next &= sre_bits(act_next, geo, r, col);
-          }
-        }
-        uint32_t now_lo = (uint32_t)m_now, now_hi = (uint32_t)(m_now >> 32);
-        uint32_t nx_lo = (uint32_t)m_next, nx_hi = (uint32_t)(m_next >> 32);
-        for (uint32_t off = lg >> 1; off > 0; off >>= 1) {
-          ucount += __shfl_xor(ucount, (int)off);
-          now_lo &= __shfl_xor(now_lo, (int)off);
-          now_hi &= __shfl_xor(now_hi, (int)off);
-          nx_lo &= __shfl_xor(nx_lo, (int)off);
-          nx_hi &= __shfl_xor(nx_hi, (int)off);
-        }
-        if (valid && sub == 0) {
-          const uint32_t w_now = (uint32_t)__popcll((((uint64_t)now_hi << 32) | now_lo) & gmask);
-          const uint32_t w_next = (uint32_t)__popcll((((uint64_t)nx_hi << 32) | nx_lo) & gmask);
-          // Eq9, operation by operation, no contraction (built with -ffp-contract=off)
-          const double num = (double)ucount - G * up;
-          const double den = G * (1.0 - up);
-          double e;
-          uint8_t fl = cflags[gid] & 4u;   // NEW, written by the merge
-          if (den == 0.0) {
-            e = __builtin_inf();
-            fl |= 2u;
-          } else {
-            const double y = 1.0 - num / den;
-            if (y <= 0.0) {
-              e = __builtin_inf();
-              fl |= 2u;
-            } else {
-              e = -G * log(y);
-            }
-          }
-          if (e >= (double)geo.theta) fl |= 1u;
-          if (w_next >= geo.t_re) fl |= 8u;   // carried by Algorithm 3
-          cflags[gid] = fl;
-          sb.est[local] = e;
-          sb.ip[local] = a;
-          sb.U[local] = ucount;
-          sb.W[local] = (uint8_t)w_now;
-          sb.f[local] = fl;
-        }
+      for (uint32_t r = sub; r < geo.u; r += lg) {
+        const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
+        m_now &= sre_bits(act_now, geo, r, col);
+        m_next &= sre_bits(act_next, geo, r, col);
       }
     }
-    lds_barrier();
+    uint32_t now_lo = (uint32_t)m_now, now_hi = (uint32_t)(m_now >> 32);
+    uint32_t nx_lo = (uint32_t)m_next, nx_hi = (uint32_t)(m_next >> 32);
+    for (uint32_t off = lg >> 1; off > 0; off >>= 1) {
+      ucount += __shfl_xor(ucount, (int)off);
+      now_lo &= __shfl_xor(now_lo, (int)off);
+      now_hi &= __shfl_xor(now_hi, (int)off);
+      nx_lo &= __shfl_xor(nx_lo, (int)off);
+      nx_hi &= __shfl_xor(nx_hi, (int)off);
+    }
+    if (valid && sub == 0) {
+      const uint32_t w_now = (uint32_t)__popcll((((uint64_t)now_hi << 32) | now_lo) & gmask);
+      const uint32_t w_next = (uint32_t)__popcll((((uint64_t)nx_hi << 32) | nx_lo) & gmask);
+      // Eq9, operation by operation, no contraction (built with -ffp-contract=off)
+      const double num = (double)ucount - G * up;
+      const double den = G * (1.0 - up);
+      double e;
+      uint8_t fl = cflags[gid] & 4u;   // NEW, written by the merge
+      if (den == 0.0) {
+        e = __builtin_inf();
+        fl |= 2u;
+      } else {
+        const double y = 1.0 - num / den;
+        if (y <= 0.0) {
+          e = __builtin_inf();
+          fl |= 2u;
+        } else {
+          e = -G * log(y);
+        }
+      }
+      if (e >= (double)geo.theta) fl |= 1u;
+      if (w_next >= geo.t_re) fl |= 8u;   // carried by Algorithm 3
+      s_est[local] = e;
+      s_ip[local] = a;
+      s_U[local] = ucount;
+      s_W[local] = (uint8_t)w_now;
+      s_f[local] = fl;
+    }
+  }
+  lds_barrier();
+  if (threadIdx.x < kEstPerBlock) {
+    const uint64_t gid = base + threadIdx.x;
+    if (gid < n) {
+      cflags[gid] = s_f[threadIdx.x];
+      out_ip[gid] = s_ip[threadIdx.x];
+      out_est[gid] = s_est[threadIdx.x];
+      out_flags[gid] = s_f[threadIdx.x];
+      if (out_U) out_U[gid] = s_U[threadIdx.x];
+      if (out_W) out_W[gid] = s_W[threadIdx.x];
+    }
+  }
+  lds_barrier();
   }
 }
 
