@@ -466,8 +466,6 @@ def main():
     ap.add_argument("--full-report", action="store_true",
                     help="also deliver |ULE|^k and |URE|^k per candidate (18 instead of 13 "
                          "bytes per candidate to host memory)")
-    ap.add_argument("--staged-report", action="store_true",
-                    help="estimate into device memory, then copy the report to the host")
     ap.add_argument("--scan-dedup", action="store_true",
                     help="scan in read-before-write form (A/B of the scan kernels)")
     ap.add_argument("--scan-xcd", action="store_true",
@@ -518,8 +516,7 @@ def main():
         args.scan_dedup = tuned["scan_dedup"]
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks,
-                     lean_report=not args.full_report, scan_dedup=args.scan_dedup,
-                     staged_report=args.staged_report)
+                     lean_report=not args.full_report, scan_dedup=args.scan_dedup)
     t_w = time.perf_counter()
     for s in range(args.warmup):
         ds.generate(s, out=buf, stream=st)
@@ -612,8 +609,7 @@ def main():
             "window": g["k"], "theta": g["theta"], "pairs_per_slice": n_pairs,
             "slices_timed": [args.warmup, args.warmup + args.steps - 1],
             "mode": args.mode, "graph": graph, "scan_blocks": args.scan_blocks,
-            "scan_xcd": args.scan_xcd, "scan_dedup": args.scan_dedup,
-            "staged_report": args.staged_report, "autotune": tuned,
+            "scan_xcd": args.scan_xcd, "scan_dedup": args.scan_dedup, "autotune": tuned,
             "report": ("full: ip, est, flags, |ULE|^k, |URE|^k (18 B/candidate)"
                        if args.full_report else "ip, est, flags (13 B/candidate)"),
         },

@@ -70,17 +70,12 @@ enum {
                                   (union_weight and re_weight are NULL):
                                   13 instead of 18 bytes per candidate cross
                                   PCIe at every slice end */
-    SRLA_CFG_SCAN_DEDUP = 32,  /* scan in read-before-write form: a DR that
+    SRLA_CFG_SCAN_DEDUP = 32   /* scan in read-before-write form: a DR that
                                   already holds the open slice's stamp is not
                                   stored again (DRset is idempotent).  Results
                                   are identical; faster when pairs repeat DRs
                                   often.  Takes precedence over
                                   SRLA_CFG_SCAN_XCD */
-    SRLA_CFG_STAGED_REPORT = 64 /* the estimate kernel writes the report to
-                                  device memory and a copy kernel moves it to
-                                  the host arrays afterwards (instead of the
-                                  estimate writing the host arrays itself);
-                                  results are identical */
 };
 
 /*

@@ -70,7 +70,7 @@ bool config_ok(const srla_config_t* c) {
   if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
   if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH |
                               SRLA_CFG_DISCRETE | SRLA_CFG_LEAN_REPORT |
-                              SRLA_CFG_SCAN_DEDUP | SRLA_CFG_STAGED_REPORT)) != 0)
+                              SRLA_CFG_SCAN_DEDUP)) != 0)
     return false;
   if ((c->flags & SRLA_CFG_DISCRETE) && c->window_slices != 1) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
@@ -151,8 +151,6 @@ struct srla_monitor {
   uint32_t* h_U = nullptr;
   uint8_t* h_W = nullptr;
   ReportPtrs d_report{};
-  bool staged = false;           // estimate into device staging, then copy to the host
-  ReportPtrs d_staging{};
 
   // ordering between the two streams
   hipEvent_t ev_scan = nullptr;   // after the closing slice's last scan
@@ -372,8 +370,7 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
     e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
   if (e == hipSuccess)
     e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->act_next, m->up, geo, m->cflags,
-                        m->staged ? m->d_staging : m->d_report, st);
-  if (e == hipSuccess && m->staged) e = launch_report_copy(m->cnt, m->d_staging, m->d_report, st);
+                        m->d_report, st);
   if (spans) span_end(m, st, ST_ESTIMATE, ta);
   if (spans) span_begin(m, st, &ta);
   if (e == hipSuccess)
@@ -422,8 +419,6 @@ void release(srla_monitor* m) {
   dfree(m->news); dfree(m->hist); dfree(m->blockw);
   dfree(m->csip); dfree(m->carried[0]); dfree(m->carried[1]); dfree(m->cflags);
   dfree(m->cblockw);
-  dfree(m->d_staging.ip); dfree(m->d_staging.est); dfree(m->d_staging.flags);
-  dfree(m->d_staging.U); dfree(m->d_staging.W);
   hfree(m->h_status); hfree(m->h_ip); hfree(m->h_est); hfree(m->h_flags);
   hfree(m->h_U); hfree(m->h_W);
   delete[] m->h_row_fill64;
@@ -486,7 +481,6 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->use_graph = (cfg->flags & SRLA_CFG_GRAPH) != 0;
   m->discrete = (cfg->flags & SRLA_CFG_DISCRETE) != 0;
   m->dedup_scan = (cfg->flags & SRLA_CFG_SCAN_DEDUP) != 0;
-  m->staged = (cfg->flags & SRLA_CFG_STAGED_REPORT) != 0;
 
   const srla_geometry_t& g = cfg->geom;
   Geo& geo = m->geo;
@@ -558,13 +552,6 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!rc) nomem(dalloc(&m->carried[1], m->cap));
   if (!rc) nomem(dalloc(&m->cflags, m->cap));
   if (!rc) nomem(dalloc(&m->cblockw, compact_block_words(m->cap)));
-  if (!rc && m->staged) {
-    nomem(dalloc(&m->d_staging.ip, m->cap));
-    if (!rc) nomem(dalloc(&m->d_staging.est, m->cap));
-    if (!rc) nomem(dalloc(&m->d_staging.flags, m->cap));
-    if (!rc && !(cfg->flags & SRLA_CFG_LEAN_REPORT)) nomem(dalloc(&m->d_staging.U, m->cap));
-    if (!rc && !(cfg->flags & SRLA_CFG_LEAN_REPORT)) nomem(dalloc(&m->d_staging.W, m->cap));
-  }
   if (!rc) nomem(halloc(&m->h_status, 1));
   if (!rc) nomem(halloc(&m->h_ip, m->cap));
   if (!rc) nomem(halloc(&m->h_est, m->cap));

@@ -453,11 +453,9 @@ def test_discrete_form_rejects_longer_windows_and_groups():
     m.close()
 
 
-@pytest.mark.parametrize("staged", [False, True])
-def test_lean_report_carries_ip_est_flags_of_the_full_report(staged):
+def test_lean_report_carries_ip_est_flags_of_the_full_report():
     stream, mon, n = workload("tiny_coupled")
-    lean = srla.Monitor(**mon, max_candidates=1 << 16, lean_report=True, graph=True,
-                        staged_report=staged)
+    lean = srla.Monitor(**mon, max_candidates=1 << 16, lean_report=True, graph=True)
     o = oracle.Monitor(**mon)
     for s in range(n):
         p = stream.slice(s)
@@ -493,18 +491,3 @@ def test_dedup_scan_backbone_expiry_and_full_size_prefix():
          scan_dedup=True)
     stream, mon, _ = workload("backbone")
     _run(stream, mon, range(3), max_candidates=1 << 22, dump_every=0, scan_dedup=True)
-
-
-@pytest.mark.parametrize("case", [SMALL[0], SMALL[4], SMALL[7]])
-def test_staged_report_full(case):
-    k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
-    mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=7000 + k + u)
-    gm = srla.Monitor(**mon, max_candidates=1 << 16, staged_report=True)
-    o = oracle.Monitor(**mon)
-    gen = _rand_stream(k + u + 9, n, n_src, 3 * theta // 2)
-    for s in range(slices):
-        p = gen(s)
-        gm.scan(to_device(p))
-        o.scan(p)
-        compare_reports(gm.estimate(), o.estimate(), theta, "slice %d" % s)
-    gm.close()
