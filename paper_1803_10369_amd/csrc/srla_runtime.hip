@@ -163,11 +163,16 @@ struct srla_monitor {
   bool use_graph = false;
   hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 
-  // host-input ring: two pinned chunks, two device chunks
+  // host-input ring: H2D copies on their own stream into two device chunks
+  // (through two pinned bounce chunks when the caller's memory is pageable),
+  // scans of the chunks on the scan stream
+  hipStream_t copy = nullptr;
   uint32_t* h_stage[2] = {nullptr, nullptr};
   uint32_t* d_stage[2] = {nullptr, nullptr};
-  hipEvent_t stage_ev[2] = {nullptr, nullptr};
+  hipEvent_t stage_ev[2] = {nullptr, nullptr};    // chunk copied to the device
+  hipEvent_t scanned_ev[2] = {nullptr, nullptr};  // chunk scanned (device chunk free)
   bool stage_busy[2] = {false, false};
+  bool scanned_set[2] = {false, false};
   int stage_next = 0;
 
   // timing
@@ -426,12 +431,17 @@ void release(srla_monitor* m) {
     hfree(m->h_stage[i]);
     dfree(m->d_stage[i]);
     if (m->stage_ev[i]) (void)hipEventDestroy(m->stage_ev[i]);
+    if (m->scanned_ev[i]) (void)hipEventDestroy(m->scanned_ev[i]);
   }
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   if (m->ev_scan) (void)hipEventDestroy(m->ev_scan);
   if (m->ev_snap) (void)hipEventDestroy(m->ev_snap);
   if (m->ev_done) (void)hipEventDestroy(m->ev_done);
   if (m->pipe) (void)hipStreamDestroy(m->pipe);
+  if (m->copy) {
+    (void)hipStreamSynchronize(m->copy);
+    (void)hipStreamDestroy(m->copy);
+  }
   if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
   delete m;
 }
@@ -617,6 +627,39 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   return SRLA_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Algorithm 2 for n device-resident pairs of the open slice (parity p) in the
+// monitor's scan form
+hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int p) {
+  const uint16_t code = stamp_code(m->slice);
+  if (m->discrete)
+    return launch_scan_bits(pairs, n, m->geo, m->lebits[p], m->rebits[p], m->sset[p],
+                            m->set_slots, m->touched[p], m->tcount + p, m->cfg.scan_blocks,
+                            m->stream);
+  if (m->dedup_scan)
+    return launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
+                             m->tcount + p, m->cfg.scan_blocks, m->stream);
+  return launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p], m->tcount + p,
+                     m->xcd_scan, m->cfg.scan_blocks, m->stream);
+}
+
+// true if p is page-locked host memory that the DMA engines can read directly
+bool host_pinned(const void* p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();   // pageable memory: not known to the runtime
+    return false;
+  }
+  return attr.type == hipMemoryTypeHost;
+}
+
+}  // namespace
+
+extern "C" {
+
 int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_device) {
   if (!m) return SRLA_E_INVAL;
   if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
@@ -630,63 +673,69 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     HIP_TRY(m, hipStreamWaitEvent(m->stream, m->ev_snap, 0));
     m->snap_pending = false;
   }
-  const uint16_t code = stamp_code(m->slice);
   if (on_device) {
     hipEvent_t a;
     span_begin(m, m->stream, &a);
-    HIP_TRY(m, m->discrete
-                   ? launch_scan_bits(pairs, n, m->geo, m->lebits[p], m->rebits[p], m->sset[p],
-                                      m->set_slots, m->touched[p], m->tcount + p,
-                                      m->cfg.scan_blocks, m->stream)
-                   : m->dedup_scan
-                   ? launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
-                                       m->tcount + p, m->cfg.scan_blocks, m->stream)
-                   : launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
-                                 m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream));
+    HIP_TRY(m, enqueue_scan(m, pairs, n, p));
     span_end(m, m->stream, ST_SCAN, a);
     m->slice_pairs[p] += n;
     m->scan_launches++;
     m->scan_pairs += n;
     return SRLA_OK;
   }
-  // host input: copy chunk by chunk through two pinned buffers
+  // host input: chunk by chunk, H2D copies on the copy stream overlapping the
+  // scans of earlier chunks on the scan stream
+  if (!m->copy) {
+    if (hipStreamCreateWithFlags(&m->copy, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(m, SRLA_E_DEVICE, "cannot create the host-ingest stream");
+    }
+  }
   for (int i = 0; i < 2; ++i) {
     if (!m->h_stage[i]) {
       if (halloc(&m->h_stage[i], 2 * kStageChunk) != hipSuccess ||
           dalloc(&m->d_stage[i], 2 * kStageChunk) != hipSuccess ||
-          hipEventCreateWithFlags(&m->stage_ev[i], hipEventDisableTiming) != hipSuccess) {
+          hipEventCreateWithFlags(&m->stage_ev[i], hipEventDisableTiming) != hipSuccess ||
+          hipEventCreateWithFlags(&m->scanned_ev[i], hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         return fail(m, SRLA_E_NOMEM, "cannot allocate the host-ingest ring");
       }
     }
   }
+  const bool pinned = host_pinned(pairs);
+  int last = -1;
   for (uint64_t off = 0; off < n; off += kStageChunk) {
     const uint64_t cnt = std::min(kStageChunk, n - off);
+    const uint64_t bytes = cnt * 2 * sizeof(uint32_t);
     const int b = m->stage_next;
     m->stage_next ^= 1;
-    if (m->stage_busy[b]) HIP_TRY(m, hipEventSynchronize(m->stage_ev[b]));
-    std::memcpy(m->h_stage[b], pairs + 2 * off, cnt * 2 * sizeof(uint32_t));
-    HIP_TRY(m, hipMemcpyAsync(m->d_stage[b], m->h_stage[b], cnt * 2 * sizeof(uint32_t),
-                              hipMemcpyHostToDevice, m->stream));
-    HIP_TRY(m, hipEventRecord(m->stage_ev[b], m->stream));
+    // the device chunk is free once its previous scan has run
+    if (m->scanned_set[b]) HIP_TRY(m, hipStreamWaitEvent(m->copy, m->scanned_ev[b], 0));
+    const uint32_t* src = pairs + 2 * off;
+    if (!pinned) {
+      // the pinned bounce chunk is free once its previous copy has run
+      if (m->stage_busy[b]) HIP_TRY(m, hipEventSynchronize(m->stage_ev[b]));
+      std::memcpy(m->h_stage[b], src, bytes);
+      src = m->h_stage[b];
+    }
+    HIP_TRY(m, hipMemcpyAsync(m->d_stage[b], src, bytes, hipMemcpyHostToDevice, m->copy));
+    HIP_TRY(m, hipEventRecord(m->stage_ev[b], m->copy));
     m->stage_busy[b] = true;
+    HIP_TRY(m, hipStreamWaitEvent(m->stream, m->stage_ev[b], 0));
     hipEvent_t a;
     span_begin(m, m->stream, &a);
-    HIP_TRY(m, m->discrete
-                   ? launch_scan_bits(m->d_stage[b], cnt, m->geo, m->lebits[p], m->rebits[p],
-                                      m->sset[p], m->set_slots, m->touched[p], m->tcount + p,
-                                      m->cfg.scan_blocks, m->stream)
-                   : m->dedup_scan
-                   ? launch_scan_dedup(m->d_stage[b], cnt, m->geo, code, m->le, m->re,
-                                       m->touched[p], m->tcount + p, m->cfg.scan_blocks,
-                                       m->stream)
-                   : launch_scan(m->d_stage[b], cnt, m->geo, code, m->le, m->re, m->touched[p],
-                                 m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream));
+    HIP_TRY(m, enqueue_scan(m, m->d_stage[b], cnt, p));
     span_end(m, m->stream, ST_SCAN, a);
+    HIP_TRY(m, hipEventRecord(m->scanned_ev[b], m->stream));
+    m->scanned_set[b] = true;
     m->slice_pairs[p] += cnt;
     m->scan_launches++;
     m->scan_pairs += cnt;
+    last = b;
   }
+  // the caller may reuse its buffer once this returns: wait for the copies
+  // that read it directly
+  if (pinned && last >= 0) HIP_TRY(m, hipEventSynchronize(m->stage_ev[last]));
   return SRLA_OK;
 }
 
