@@ -282,7 +282,10 @@ class Monitor:
                     pairs.record_stream(self.stream)
                 self._check(srla_scan(self._h, ctypes.c_void_p(pairs.data_ptr()), n, True))
                 return
-        p = np.ascontiguousarray(pairs, dtype=np.uint32).reshape(-1)
+        p = np.asarray(pairs)
+        if p.dtype == np.int32:
+            p = p.view(np.uint32)          # no copy: pinned buffers stay pinned
+        p = np.ascontiguousarray(p, dtype=np.uint32).reshape(-1)
         self._check(srla_scan(self._h, ctypes.c_void_p(p.ctypes.data), p.size // 2, False))
 
     def estimate(self, copy=True):
