@@ -391,7 +391,7 @@ int orc_estimate(orc_monitor *m, orc_report *out)
            SI bits were set at insertion) */
         if (m->n_seq_new > m->n_touched) { rc = -2; goto done; }
         for (x = 0; x < m->n_seq_new; x++) news[n_new++] = m->seq_new[x];
-        qsort(news, n_new, sizeof(uint32_t), cmp_u32);
+        if (n_new) qsort(news, n_new, sizeof(uint32_t), cmp_u32);
     } else {
         for (x = 0; x < n_uniq; x++) {
             uint32_t aip = uniq[x];
@@ -446,7 +446,7 @@ int orc_estimate(orc_monitor *m, orc_report *out)
             else est = -G * log(y);
         }
         if (est >= (double)m->cfg.theta) fl |= ORC_SUPER;
-        if (bsearch(&aip, news, n_new, sizeof(uint32_t), cmp_u32)) fl |= ORC_NEW;
+        if (n_new && bsearch(&aip, news, n_new, sizeof(uint32_t), cmp_u32)) fl |= ORC_NEW;
         m->r_est[x] = est;
         m->r_flags[x] = fl;
         m->r_U[x] = U;
