@@ -62,28 +62,60 @@ def evaluate(monitors, stream, k, theta, n_slices, every=1, scan=None):
     return out
 
 
+SWEEP_U = (2, 4)
+SWEEP_V = (16_384, 65_536)
+SWEEP_G = (1024, 2048, 4096, 8192)
+
+
+def sweep_monitors(mon):
+    """The SEA parameter grid of the paper's accuracy comparison (Section 5.1:
+    g' from 1024 to 8192, several u and v): one monitor per (u, v, g'), with
+    the workload's window, threshold and hash seed."""
+    out = []
+    for u in SWEEP_U:
+        for v in SWEEP_V:
+            for G in SWEEP_G:
+                out.append(dict(mon, u=u, v_re=v, v_le=v, G=G))
+    return out
+
+
 def main():
-    """GPU accuracy run: python -m trafficgen.accuracy [workload] [slices]."""
+    """GPU accuracy run:
+    python -m trafficgen.accuracy [workload] [slices] [--sweep]
+    --sweep runs the (u, v, g') grid side by side on the same stream and
+    windows (the precise method is evaluated once per window)."""
     import torch
     import paper_1803_10369_amd as srla
     from trafficgen.configs import workload
 
-    name = sys.argv[1] if len(sys.argv) > 1 else "accuracy"
+    argv = [a for a in sys.argv[1:] if not a.startswith("--")]
+    sweep = "--sweep" in sys.argv
+    name = argv[0] if argv else "accuracy"
     stream, mon, n = workload(name)
-    n = int(sys.argv[2]) if len(sys.argv) > 2 else n
-    gm = srla.Monitor(**mon, max_candidates=1 << 22)
+    n = int(argv[1]) if len(argv) > 1 else n
+    cfgs = sweep_monitors(mon) if sweep else [mon]
+    gms = [srla.Monitor(**c, max_candidates=1 << 22, lean_report=True) for c in cfgs]
 
     def scan(m, pairs):
         flat = np.ascontiguousarray(pairs.reshape(-1))
         m.scan(torch.from_numpy(flat.view(np.int32)).cuda())
 
-    rows = evaluate([gm], stream, mon["k"], mon["theta"], n, every=5, scan=scan)
-    summary = {key: float(np.mean([r["monitor0"][key] for r in rows]))
-               for key in ("FPR", "FNR", "TFR")}
-    summary.update({"worst_FNR": max(r["monitor0"]["FNR"] for r in rows),
-                    "windows": len(rows), "workload": name,
-                    "true_super_points_mean": float(np.mean([r["monitor0"]["N"] for r in rows]))})
-    print(json.dumps({"summary": summary, "windows": rows}), flush=True)
+    rows = evaluate(gms, stream, mon["k"], mon["theta"], n, every=5, scan=scan)
+    results = []
+    for i, c in enumerate(cfgs):
+        key = "monitor%d" % i
+        summary = {k: float(np.mean([r[key][k] for r in rows])) for k in ("FPR", "FNR", "TFR")}
+        summary.update({"u": c["u"], "v": c["v_le"], "g_le": c["G"],
+                        "worst_FNR": max(r[key]["FNR"] for r in rows),
+                        "worst_FPR": max(r[key]["FPR"] for r in rows),
+                        "candidates_mean": float(np.mean([r[key]["candidates"] for r in rows]))})
+        results.append(summary)
+    out = {"workload": name, "windows": len(rows),
+           "true_super_points_mean": float(np.mean([r["monitor0"]["N"] for r in rows])),
+           "summary": results if sweep else results[0]}
+    if not sweep:
+        out["per_window"] = rows
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -56,6 +56,14 @@ def workload(name):
                             planted=planted, window=k, seed=STREAM_SEED + 6, dst_pool=4)
         v = 4096 if small else 65_536
         return stream, _monitor(k, 1024, 4, v, 8, v, 1024, 6), (3 * k if small else 90)
+    if name == "accuracy_boundary":
+        # like "accuracy", but with 400 planted hosts of 256..4096 destinations
+        # (log-uniform around theta = 1024), so that detection errors near the
+        # threshold show how the SEA's size matters
+        planted = loguniform_ints(256, 4096, 400, STREAM_SEED + 8)
+        stream = StreamSpec(n_pairs=1_000_000, n_ranks=1 << 20, alpha=1.05, planted=planted,
+                            window=30, seed=STREAM_SEED + 8, dst_pool=4)
+        return stream, _monitor(30, 1024, 4, 65_536, 8, 65_536, 1024, 8), 90
     if name == "discrete_paper":
         # the paper's discrete-window run (Section 5.1): k = 1, one-bit DRs,
         # u = 4, v = 65,536, g' = 1024, theta = 1024, one 300-second window of
