@@ -200,14 +200,19 @@ int srla_create(const srla_config_t *cfg, void *hip_stream, srla_monitor_t **out
  * on_device != 0: pairs is device memory readable on the monitor's stream;
  *   the caller keeps it alive until the work has run (the next
  *   srla_estimate returns after it).
- * on_device == 0: pairs is host memory, copied before this call returns.
+ * on_device == 0: pairs is host memory, copied before this call returns:
+ *   in chunks of 4M pairs by DMA on a library stream, overlapping the scans
+ *   of earlier chunks; page-locked memory (hipHostMalloc, torch pin_memory)
+ *   is read by the DMA directly, pageable memory through two pinned
+ *   bounce buffers.
  * May be called any number of times per slice; the order of pairs does not
  * change any result.  Errors: SRLA_E_INVAL (NULL pairs with n > 0),
  * SRLA_E_STATE (poisoned), SRLA_E_NOMEM, SRLA_E_DEVICE.
  */
 int srla_scan(srla_monitor_t *m, const uint32_t *pairs, uint64_t n, int on_device);
 /* (In the discrete form the SRE and LE of the open slice are fresh bit
-   arrays; the scan ORs bits into them.) */
+   arrays; the scan ORs bits into them, and sampled sources go into the
+   slice's source set.) */
 
 /*
  * Closes the open slice e and fills *out with its report (Section 4.2 and
