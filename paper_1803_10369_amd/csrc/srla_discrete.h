@@ -1,7 +1,8 @@
 // Launchers of the discrete-window form (k = 1, one-bit DRs); see
-// srla_discrete.hip.  The bit arrays are flat over [u][v_le][G] (LE) and
-// [u][v_re][g] (SRE), 64 bits per word -- the layouts of the stamp form's
-// `bitmap` and `act_now`.
+// srla_discrete.hip.  The LE bit array is flat over [u][v_le][G], 64 bits per
+// word (the stamp form's `bitmap` layout); the SRE bits, flat over
+// [u][v_re][g], fill the even words of an array twice that size (the stamp
+// form's interleaved `act` layout).
 #pragma once
 #include "srla_internal.h"
 

@@ -15,9 +15,11 @@ constexpr uint64_t kBitTile = (uint64_t)kBlock * 2 * kBitSteps;  // pairs per bl
 
 // ------------------------------------------------------------------ scan
 // Algorithm 2 with one-bit DRs.  A DR is set by an atomic OR into a 32-bit
-// word of a flat bit array over [u][v_le][G] (LE) or [u][v_re][g] (SRE) --
-// the layout of the activity bitmaps that the end-of-slice kernels read, so
-// those kernels read these arrays directly.  Bits of different pairs share
+// word of a flat bit array over [u][v_le][G] (LE), or over [u][v_re][g]
+// (SRE) spread over the even 64-bit words of an array twice that size --
+// the layouts of the LE activity bitmap and of the interleaved SRE activity
+// map (whose odd words, "inside after the slide", stay clear at k = 1) that
+// the end-of-slice kernels read, so those kernels read these arrays directly.  Bits of different pairs share
 // words, hence atomics; device-scope atomics run at the memory side and cost
 // several plain stores each, while most DRs of a slice are set many times
 // (every repeat of a flow, every pair of a hot source).  So each DR is first
@@ -38,6 +40,11 @@ __device__ __forceinline__ void set_bit_if_clear(uint64_t* __restrict__ bits, ui
   if ((seen & m) == 0u)
     __hip_atomic_fetch_or(reinterpret_cast<uint32_t*>(bits) + (i >> 5), m, __ATOMIC_RELAXED,
                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// 32-bit word of SRE DR i in the interleaved layout (bit i & 31 of it)
+__device__ __forceinline__ uint64_t re_word32(uint64_t i) {
+  return 4 * (i >> 6) + ((i >> 5) & 1u);
 }
 
 __device__ __forceinline__ uint64_t le_bit(const Geo& geo, uint32_t row, uint32_t a,
@@ -94,7 +101,10 @@ __device__ __forceinline__ void sample_bits(uint32_t a, uint32_t b, bool valid, 
     for (uint32_t i = 0; i < geo.u; ++i) {
       const uint64_t bit =
           ((uint64_t)i * geo.v_re + hrange(mas(geo.rh[i], a), geo.v_re)) * geo.g + rei;
-      set_bit_if_clear(rebits, bit, peek_word(rebits, bit));
+      uint32_t* w = reinterpret_cast<uint32_t*>(rebits) + re_word32(bit);
+      const uint32_t m = 1u << (uint32_t)(bit & 31u);
+      if ((__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT) & m) == 0u)
+        __hip_atomic_fetch_or(w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     append = !set_insert(set, set_mask, a);
   }

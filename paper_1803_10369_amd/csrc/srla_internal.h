@@ -146,8 +146,8 @@ hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* r
                            const Geo& geo, const PipeState* ps, hipStream_t st);
 
 // SRE DR activity bitmaps (inside the window now / after the slide) + scrub
-hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act_now, uint64_t* act_next,
-                           const Geo& geo, const PipeState* ps, hipStream_t st);
+hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act, const Geo& geo,
+                           const PipeState* ps, hipStream_t st);
 
 // keys-only LSD radix sort of *n_dev uint32 keys (n_dev <= n_max), in place
 // (tmp is scratch).  block_hist needs radix_hist_words(n_max) words.
@@ -164,7 +164,7 @@ hipError_t compact_u32(const uint8_t* flags, uint8_t mask, const uint32_t* vals,
                        const uint32_t* n_dev, uint64_t n_max, uint32_t* out,
                        uint32_t* out_count, uint32_t* block_words, hipStream_t st);
 
-hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const uint64_t* act_now,
+hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const uint64_t* act,
                            const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
                            hipStream_t st);
 
@@ -176,7 +176,7 @@ hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
                              double* up, hipStream_t st);
 
 hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
-                           const uint64_t* act_now, const uint64_t* act_next, const double* up,
+                           const uint64_t* act, const double* up,
                            const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
                            hipStream_t st);
 

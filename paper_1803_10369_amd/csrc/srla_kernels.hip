@@ -8,7 +8,8 @@
 //   RE      uint16 stamps [u][v_re][g]     one SRE of g DRs per (row, column)
 //   SI      uint32 counters [u][v_re][16]  SI bit = counter > 0
 //   bitmap  uint64 [u][v_le][G/64]         LE DRs inside the window
-//   act_*   uint64, 1 bit per SRE DR       inside now / after the slide
+//   act     uint64 pairs, 1 bit per SRE DR: word 2w holds bits 64w..64w+63
+//           "inside now", word 2w+1 the same DRs "inside after the slide"
 // A DR is a 16-bit slice stamp (see srla_internal.h), so Algorithm 3's slide
 // of every DR costs nothing.  No kernel here contains a dense contraction, so
 // nothing uses MFMA; the sweeps stream HBM, the estimate gathers from the
@@ -113,15 +114,16 @@ hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* r
 
 
 // RE activity: every SRE DR of the array (flat index i over [u][v_re][g]) as
-// two bitmaps -- bit i of `now` = DR inside the window ending at this slice,
-// bit i of `next` = still inside after Algorithm 3's slide (distance + 1 < k).
-// The finalize and estimate kernels read g bits per (row, column) from these
-// (L2-resident) maps instead of g scattered stamps.  Old stamps are scrubbed
-// here as in the LE sweep.  Handles any cell count (ragged last word).
+// two interleaved bitmaps -- bit i of `now` = DR inside the window ending at
+// this slice, bit i of `next` = still inside after Algorithm 3's slide
+// (distance + 1 < k); the now and next words of the same DRs sit side by
+// side, so a candidate's SRE costs one 16-byte load per row.  The finalize
+// and estimate kernels read g bits per (row, column) from these (L2-resident)
+// maps instead of g scattered stamps.  Old stamps are scrubbed here as in the
+// LE sweep.  Handles any cell count (ragged last word).
 
 __global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, uint64_t n,
-                                                    uint64_t* __restrict__ act_now,
-                                                    uint64_t* __restrict__ act_next,
+                                                    uint64_t* __restrict__ act,
                                                     const PipeState* __restrict__ ps,
                                                     uint32_t k) {
   const uint32_t now = ps->now;
@@ -170,29 +172,40 @@ __global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, 
     b_lo |= __shfl_xor(b_lo, off); b_hi |= __shfl_xor(b_hi, off);
   }
   if (c8 < n && (lane & 7) == 0) {
-    act_now[c8 / 64] = ((uint64_t)a_hi << 32) | a_lo;
-    act_next[c8 / 64] = ((uint64_t)b_hi << 32) | b_lo;
+    act[2 * (c8 / 64)] = ((uint64_t)a_hi << 32) | a_lo;
+    act[2 * (c8 / 64) + 1] = ((uint64_t)b_hi << 32) | b_lo;
   }
 }
 
-hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act_now, uint64_t* act_next,
-                           const Geo& geo, const PipeState* ps, hipStream_t st) {
+hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act, const Geo& geo,
+                           const PipeState* ps, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const uint64_t blocks = (n + 8 * kBlock - 1) / (8 * kBlock);
-  hipLaunchKernelGGL(k_sweep_re, dim3((uint32_t)blocks), dim3(kBlock), 0, st, re, n, act_now,
-                     act_next, ps, geo.k);
+  hipLaunchKernelGGL(k_sweep_re, dim3((uint32_t)blocks), dim3(kBlock), 0, st, re, n, act, ps,
+                     geo.k);
   return hipGetLastError();
 }
 
-// g activity bits of the SRE in row r, column col (g <= 64)
-__device__ __forceinline__ uint64_t sre_bits(const uint64_t* __restrict__ act, const Geo& geo,
-                                             uint32_t r, uint32_t col) {
+// the g "now" and g "next" activity bits of the SRE in row r, column col
+// (g <= 64) from the interleaved map: one 16-byte load, two if the SRE
+// straddles a 64-bit boundary
+__device__ __forceinline__ void sre_bits(const uint64_t* __restrict__ act, const Geo& geo,
+                                         uint32_t r, uint32_t col, uint64_t* now,
+                                         uint64_t* next) {
   const uint64_t off = ((uint64_t)r * geo.v_re + col) * geo.g;
   const uint64_t w = off >> 6;
   const uint32_t sh = (uint32_t)(off & 63u);
-  uint64_t bits = act[w] >> sh;
-  if (sh + geo.g > 64u) bits |= act[w + 1] << (64u - sh);
-  return geo.g == 64u ? bits : (bits & ((1ull << geo.g) - 1ull));
+  const uint4 q = reinterpret_cast<const uint4*>(act)[w];
+  uint64_t a = ((((uint64_t)q.y) << 32) | q.x) >> sh;
+  uint64_t b = ((((uint64_t)q.w) << 32) | q.z) >> sh;
+  if (sh + geo.g > 64u) {
+    const uint4 q2 = reinterpret_cast<const uint4*>(act)[w + 1];
+    a |= ((((uint64_t)q2.y) << 32) | q2.x) << (64u - sh);
+    b |= ((((uint64_t)q2.w) << 32) | q2.z) << (64u - sh);
+  }
+  const uint64_t mask = geo.g == 64u ? ~0ull : ((1ull << geo.g) - 1ull);
+  *now = a & mask;
+  *next = b & mask;
 }
 
 // SI as per-bit counters: counter (r, col, b) = number of carried candidates
@@ -214,7 +227,7 @@ __device__ __forceinline__ uint64_t si_slot(const Geo& geo, uint32_t r, uint32_t
 
 __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict__ sorted,
                                                     const uint32_t* __restrict__ n_dev,
-                                                    const uint64_t* __restrict__ act_now,
+                                                    const uint64_t* __restrict__ act,
                                                     const uint32_t* __restrict__ si_cnt,
                                                     Geo geo, uint8_t* __restrict__ mark,
                                                     Counters* __restrict__ cnt) {
@@ -235,7 +248,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict_
         bool usi = true;
         for (uint32_t r = 0; r < geo.u; ++r) {
           const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
-          ure &= sre_bits(act_now, geo, r, col);
+          uint64_t now, next;
+          sre_bits(act, geo, r, col, &now, &next);
+          ure &= now;
           usi = usi && si_cnt[si_slot(geo, r, col, bit)] != 0u;
         }
         f = ((uint32_t)__popcll(ure) >= geo.t_re && !usi) ? 1 : 0;
@@ -247,10 +262,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict_
   if (__lane_id() == 0 && firsts) atomicAdd(&cnt->n_unique, firsts);
 }
 
-hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const uint64_t* act_now,
+hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const uint64_t* act,
                            const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(kPipeBlocks), dim3(kBlock), 0, st, sorted, n_dev, act_now,
+  hipLaunchKernelGGL(k_finalize, dim3(kPipeBlocks), dim3(kBlock), 0, st, sorted, n_dev, act,
                      si_cnt, geo, mark, cnt);
   return hipGetLastError();
 }
@@ -354,8 +369,8 @@ __device__ __forceinline__ void lds_barrier() {
 
 __global__ __launch_bounds__(kBlock) void k_estimate(
     const uint32_t* __restrict__ csip, const Counters* __restrict__ cnt,
-    const uint64_t* __restrict__ bitmap, const uint64_t* __restrict__ act_now,
-    const uint64_t* __restrict__ act_next, const double* __restrict__ up_p, Geo geo,
+    const uint64_t* __restrict__ bitmap, const uint64_t* __restrict__ act,
+    const double* __restrict__ up_p, Geo geo,
     uint32_t lg_log2, uint8_t* __restrict__ cflags, uint32_t* __restrict__ out_ip,
     double* __restrict__ out_est, uint8_t* __restrict__ out_flags, uint32_t* __restrict__ out_U,
     uint8_t* __restrict__ out_W) {
@@ -389,8 +404,10 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
       }
       for (uint32_t r = sub; r < geo.u; r += lg) {
         const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
-        m_now &= sre_bits(act_now, geo, r, col);
-        m_next &= sre_bits(act_next, geo, r, col);
+        uint64_t now, next;
+        sre_bits(act, geo, r, col, &now, &next);
+        m_now &= now;
+        m_next &= next;
       }
     }
     uint32_t now_lo = (uint32_t)m_now, now_hi = (uint32_t)(m_now >> 32);
@@ -455,11 +472,11 @@ static uint32_t est_lg_log2(const Geo& geo) {
 }
 
 hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
-                           const uint64_t* act_now, const uint64_t* act_next, const double* up,
+                           const uint64_t* act, const double* up,
                            const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
                            hipStream_t st) {
   hipLaunchKernelGGL(k_estimate, dim3(2 * kPipeBlocks), dim3(kBlock), 0, st, csip, cnt, bitmap,
-                     act_now, act_next, up, geo, est_lg_log2(geo), cflags, out.ip, out.est,
+                     act, up, geo, est_lg_log2(geo), cflags, out.ip, out.est,
                      out.flags, out.U, out.W);
   return hipGetLastError();
 }

@@ -115,8 +115,7 @@ struct srla_monitor {
   uint32_t* si_cnt = nullptr;    // [u][v_re][16] counters; SI bit = counter > 0
   uint64_t n_le = 0, n_re = 0, n_si = 0;
   uint64_t* bitmap = nullptr;    // LE DRs inside the window
-  uint64_t* act_now = nullptr;   // SRE DRs inside the window
-  uint64_t* act_next = nullptr;  // SRE DRs inside after the slide
+  uint64_t* act = nullptr;       // SRE DRs inside the window / after the slide, interleaved
   unsigned long long* row_fill = nullptr;
   double* up = nullptr;
   Counters* cnt = nullptr;
@@ -343,20 +342,20 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
     if (e == hipSuccess)
       e = launch_fill_u32((uint32_t*)m->lebits[p ^ 1], 0u, 2 * bitmap_words(m->n_le), st);
     if (e == hipSuccess)
-      e = launch_fill_u32((uint32_t*)m->rebits[p ^ 1], 0u, 2 * bitmap_words(m->n_re), st);
+      e = launch_fill_u32((uint32_t*)m->rebits[p ^ 1], 0u, 4 * bitmap_words(m->n_re), st);
     return e;
   }
   if (phase == PH_SNAPSHOT) {
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st);
     if (e == hipSuccess) e = launch_sweep_le(m->le, m->bitmap, m->row_fill, geo, m->ps, st);
     if (e == hipSuccess)
-      e = launch_sweep_re(m->re, m->n_re, m->act_now, m->act_next, geo, m->ps, st);
+      e = launch_sweep_re(m->re, m->n_re, m->act, geo, m->ps, st);
     if (e == hipSuccess) e = launch_union_prob(m->row_fill, geo, m->up, st);
     return e;
   }
   uint32_t* tc = m->tcount + p;
   const uint64_t* le_act = m->discrete ? m->lebits[p] : m->bitmap;
-  const uint64_t* re_act = m->discrete ? m->rebits[p] : m->act_now;
+  const uint64_t* re_act = m->discrete ? m->rebits[p] : m->act;
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
@@ -374,7 +373,7 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
   if (e == hipSuccess)
     e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
   if (e == hipSuccess)
-    e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->act_next, m->up, geo, m->cflags,
+    e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->up, geo, m->cflags,
                         m->d_report, st);
   if (spans) span_end(m, st, ST_ESTIMATE, ta);
   if (spans) span_begin(m, st, &ta);
@@ -417,8 +416,8 @@ void release(srla_monitor* m) {
   collect_spans(m);
   drop_graphs(m);
   dfree(m->le); dfree(m->re); dfree(m->si_cnt);
-  for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); dfree(m->sset[i]); } dfree(m->bitmap); dfree(m->act_now);
-  dfree(m->act_next); dfree(m->row_fill); dfree(m->up); dfree(m->cnt); dfree(m->ps);
+  for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); dfree(m->sset[i]); } dfree(m->bitmap); dfree(m->act);
+  dfree(m->row_fill); dfree(m->up); dfree(m->cnt); dfree(m->ps);
   dfree(m->tcount);
   dfree(m->touched[0]); dfree(m->touched[1]); dfree(m->touched_tmp); dfree(m->mark);
   dfree(m->news); dfree(m->hist); dfree(m->blockw);
@@ -457,7 +456,7 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   const uint64_t si = (uint64_t)g.u * g.v_re;
   if (cfg->flags & SRLA_CFG_DISCRETE)
-    return 16 * bitmap_words(le) + 24 * bitmap_words(re) +
+    return 16 * bitmap_words(le) + 32 * bitmap_words(re) +
            16 * (uint64_t)source_set_slots(cfg->max_candidates) + 64 * si + 8 * g.u + 8 +
            sizeof(Counters) + sizeof(PipeState) + 8 + candidate_bytes(cfg->max_candidates);
   return 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
@@ -541,17 +540,16 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     m->set_slots = source_set_slots(cfg->max_candidates);
     for (int i = 0; i < 2 && !rc; ++i) {
       nomem(dalloc(&m->lebits[i], bitmap_words(m->n_le)));
-      if (!rc) nomem(dalloc(&m->rebits[i], bitmap_words(m->n_re)));
+      if (!rc) nomem(dalloc(&m->rebits[i], 2 * bitmap_words(m->n_re)));
       if (!rc) nomem(dalloc(&m->sset[i], m->set_slots));
     }
   } else {
     nomem(dalloc(&m->le, m->n_le));
     if (!rc) nomem(dalloc(&m->re, m->n_re + 8));
     if (!rc) nomem(dalloc(&m->bitmap, bitmap_words(m->n_le)));
-    if (!rc) nomem(dalloc(&m->act_now, bitmap_words(m->n_re)));
+    if (!rc) nomem(dalloc(&m->act, 2 * bitmap_words(m->n_re)));
   }
   if (!rc) nomem(dalloc(&m->si_cnt, 16 * m->n_si));
-  if (!rc) nomem(dalloc(&m->act_next, bitmap_words(m->n_re)));
   if (!rc) nomem(dalloc(&m->row_fill, g.u));
   if (!rc) nomem(dalloc(&m->up, 1));
   if (!rc) nomem(dalloc(&m->cnt, 1));
@@ -591,17 +589,15 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   // DRinit for every DR (stamp 0 = never set), SI = 0, counters = 0, slice 0
   hipError_t e = hipSuccess;
   if (m->discrete) {
-    // every bit clear; act_next stays clear for good (at k = 1 no DR is
-    // inside the window after the slide)
+    // every bit clear; the "after the slide" half of each SRE word pair stays
+    // clear for good (at k = 1 no DR is inside the window after the slide)
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
       e = launch_fill_u32((uint32_t*)m->lebits[i], 0u, 2 * bitmap_words(m->n_le), m->stream);
       if (e == hipSuccess)
-        e = launch_fill_u32((uint32_t*)m->rebits[i], 0u, 2 * bitmap_words(m->n_re), m->stream);
+        e = launch_fill_u32((uint32_t*)m->rebits[i], 0u, 4 * bitmap_words(m->n_re), m->stream);
       if (e == hipSuccess)
         e = launch_fill_u32((uint32_t*)m->sset[i], 0u, 2ull * m->set_slots, m->stream);
     }
-    if (e == hipSuccess)
-      e = launch_fill_u32((uint32_t*)m->act_next, 0u, 2 * bitmap_words(m->n_re), m->stream);
   } else {
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->le, 0u, m->n_le / 2, m->stream);
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->re, 0u, (m->n_re + 8) / 2, m->stream);
@@ -832,13 +828,16 @@ int srla_dump_state(srla_monitor_t* m, int which, uint16_t* host_out, uint64_t c
     if (!n) return fail(m, SRLA_E_INVAL, "unknown state array");
     if (cells != n) return fail(m, SRLA_E_INVAL, "cells does not match the array size");
     const int p = (int)(m->slice & 1);
-    uint64_t* const* bits = which == SRLA_DUMP_LE ? m->lebits : m->rebits;
-    const uint64_t words = bitmap_words(n);
+    // the SRE bits sit in the even words of the interleaved activity layout
+    const bool re = which == SRLA_DUMP_RE;
+    uint64_t* const* bits = re ? m->rebits : m->lebits;
+    const uint64_t words = (re ? 2 : 1) * bitmap_words(n);
     std::vector<uint64_t> open(words), last(words);
     HIP_TRY(m, hipMemcpy(open.data(), bits[p], words * 8, hipMemcpyDeviceToHost));
     HIP_TRY(m, hipMemcpy(last.data(), bits[p ^ 1], words * 8, hipMemcpyDeviceToHost));
     for (uint64_t i = 0; i < n; ++i) {
-      const bool o = (open[i >> 6] >> (i & 63)) & 1u, l = (last[i >> 6] >> (i & 63)) & 1u;
+      const uint64_t w = re ? 2 * (i >> 6) : (i >> 6);
+      const bool o = (open[w] >> (i & 63)) & 1u, l = (last[w] >> (i & 63)) & 1u;
       host_out[i] = o ? 0 : (l && m->slice > 0 ? 1 : 65535);
     }
     return SRLA_OK;

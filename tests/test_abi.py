@@ -113,9 +113,10 @@ def test_discrete_footprint_is_bits(P):
                         flags=P.srla.SRLA_CFG_DISCRETE)
     fp = P.srla_footprint_bytes(cfg)
     le_cells, re_cells, ses = 1 << 24, 1 << 23, 8 * 131072
-    # two bit arrays (slice parities) per DR array, one all-clear SRE map,
-    # the SI counters, two sampled-source sets of 2^12 64-bit slots
-    want = 2 * le_cells // 8 + 3 * re_cells // 8 + 64 * ses + 2 * 8 * 4096
+    # two LE bit arrays (slice parities), two interleaved SRE maps (their
+    # "after the slide" halves stay clear), the SI counters, two
+    # sampled-source sets of 2^12 64-bit slots
+    want = 2 * le_cells // 8 + 4 * re_cells // 8 + 64 * ses + 2 * 8 * 4096
     assert want <= fp < want + 4096
     stamps = P.make_config(1, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1)
     assert P.srla_footprint_bytes(stamps) - fp > 2 * le_cells
