@@ -70,12 +70,18 @@ enum {
                                   (union_weight and re_weight are NULL):
                                   13 instead of 18 bytes per candidate cross
                                   PCIe at every slice end */
-    SRLA_CFG_SCAN_DEDUP = 32   /* scan in read-before-write form: a DR that
+    SRLA_CFG_SCAN_DEDUP = 32,  /* scan in read-before-write form: a DR that
                                   already holds the open slice's stamp is not
                                   stored again (DRset is idempotent).  Results
                                   are identical; faster when pairs repeat DRs
                                   often.  Takes precedence over
                                   SRLA_CFG_SCAN_XCD */
+    SRLA_CFG_SCAN_WAVE_DEDUP = 64 /* scan with wavefront deduplication: of
+                                  the lanes of a wavefront that would store
+                                  the same LE DR, one stores (an LDS claim
+                                  per store).  Results are identical.  Below
+                                  SRLA_CFG_SCAN_DEDUP, above
+                                  SRLA_CFG_SCAN_XCD in precedence */
 };
 
 /*
