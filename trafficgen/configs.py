@@ -31,6 +31,14 @@ def workload(name):
                             planted=[2000] * 4, window=8, seed=STREAM_SEED + 1)
         v_le = 16 if name == "tiny" else 2048
         return stream, _monitor(8, 1024, 4, 2048, 8, v_le, 1024, 1), 16
+    if name == "backbone_pool4":
+        # the backbone workload with repeating flows: ordinary sources draw
+        # their destinations from a pool of 4 (so most pairs of a slice repeat
+        # a flow, as on a real link); same monitor as "backbone"
+        planted = loguniform_ints(1000, 200_000, 200, STREAM_SEED + 2)
+        stream = StreamSpec(n_pairs=8_000_000, n_ranks=1 << 24, alpha=1.05, planted=planted,
+                            window=300, seed=STREAM_SEED + 9, dst_pool=4)
+        return stream, _monitor(300, 1024, 8, 131_072, 8, 2048, 1024, 2), 320
     if name in ("backbone", "backbone_paper", "backbone_k16"):
         # 1 monitor, window 300 slices, 8M pairs/slice, Zipf(1.05) over 2^24
         # hosts, 200 planted super points with 1k-200k dsts,
