@@ -469,8 +469,8 @@ def main():
     ap.add_argument("--full-report", action="store_true",
                     help="also deliver |ULE|^k and |URE|^k per candidate (18 instead of 13 "
                          "bytes per candidate to host memory)")
-    ap.add_argument("--scan-wave-dedup", action="store_true",
-                    help="scan with wavefront deduplication of same-DR stores (A/B)")
+    ap.add_argument("--scan-lds-filter", action="store_true",
+                    help="scan with a workgroup filter of repeated DR stores (A/B)")
     ap.add_argument("--scan-dedup", action="store_true",
                     help="scan in read-before-write form (A/B of the scan kernels)")
     ap.add_argument("--scan-xcd", action="store_true",
@@ -519,11 +519,11 @@ def main():
         del tbufs
         args.scan_xcd, args.scan_blocks = tuned["scan_xcd"], tuned["scan_blocks"]
         args.scan_dedup = tuned["scan_dedup"]
-        args.scan_wave_dedup = tuned["scan_wave_dedup"]
+        args.scan_lds_filter = tuned["scan_lds_filter"]
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks,
                      lean_report=not args.full_report, scan_dedup=args.scan_dedup,
-                     scan_wave_dedup=args.scan_wave_dedup)
+                     scan_lds_filter=args.scan_lds_filter)
     t_w = time.perf_counter()
     for s in range(args.warmup):
         ds.generate(s, out=buf, stream=st)
@@ -595,7 +595,7 @@ def main():
     per_launch_bytes = scan_bytes_per_pair(g["u"], tau) * n_pairs
     achieved = per_launch_bytes / (scan_ms * 1e-3) / 1e9
     scan_kernel = ("k_scan_dedup" if args.scan_dedup else
-                   "k_scan_wave_dedup" if args.scan_wave_dedup else
+                   "k_scan_lds_filter" if args.scan_lds_filter else
                    "k_scan_xcd" if args.scan_xcd else "k_scan_flat")
     stages = {k: tm[k] / args.steps for k in
               ("scan_ms", "sweep_ms", "finalize_ms", "estimate_ms", "slide_ms", "report_ms")}
@@ -626,7 +626,7 @@ def main():
             "slices_timed": [args.warmup, args.warmup + args.steps - 1],
             "mode": args.mode, "graph": graph, "scan_blocks": args.scan_blocks,
             "scan_xcd": args.scan_xcd, "scan_dedup": args.scan_dedup,
-            "scan_wave_dedup": args.scan_wave_dedup, "autotune": tuned,
+            "scan_lds_filter": args.scan_lds_filter, "autotune": tuned,
             "report": ("full: ip, est, flags, |ULE|^k, |URE|^k (18 B/candidate)"
                        if args.full_report else "ip, est, flags (13 B/candidate)"),
         },

@@ -76,10 +76,11 @@ enum {
                                   are identical; faster when pairs repeat DRs
                                   often.  Takes precedence over
                                   SRLA_CFG_SCAN_XCD */
-    SRLA_CFG_SCAN_WAVE_DEDUP = 64 /* scan with wavefront deduplication: of
-                                  the lanes of a wavefront that would store
-                                  the same LE DR, one stores (an LDS claim
-                                  per store).  Results are identical.  Below
+    SRLA_CFG_SCAN_LDS_FILTER = 64 /* scan with a workgroup filter of repeated
+                                  stores: each workgroup keeps the LE DRs it
+                                  stored last in an LDS table and skips
+                                  stores it has already issued in this scan.
+                                  Results are identical.  Below
                                   SRLA_CFG_SCAN_DEDUP, above
                                   SRLA_CFG_SCAN_XCD in precedence */
 };

@@ -2,7 +2,7 @@
 
 The scan (Algorithm 2) has two knobs that never change its results: the
 kernel form (flat; per-XCD row ownership, SRLA_CFG_SCAN_XCD; read-before-write,
-SRLA_CFG_SCAN_DEDUP; wavefront deduplication, SRLA_CFG_SCAN_WAVE_DEDUP) and the
+SRLA_CFG_SCAN_DEDUP; a workgroup filter of repeated stores, SRLA_CFG_SCAN_LDS_FILTER) and the
 cap on its workgroups (srla_config_t.scan_blocks).
 tune_scan() times every candidate on a scratch monitor of the caller's
 geometry with the caller's pairs, one scan per slice (each timed scan meets
@@ -26,7 +26,7 @@ import torch
 from . import srla
 
 DEFAULT_CANDIDATES = [("flat", 0), ("flat", 1024), ("flat", 512), ("xcd", 0), ("xcd", 1024),
-                      ("dedup", 0), ("dedup", 1024), ("wave", 0), ("wave", 1024)]
+                      ("dedup", 0), ("dedup", 1024), ("filter", 0), ("filter", 1024)]
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "srla_autotune.json")
 
 
@@ -68,7 +68,7 @@ def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False
     for form, blocks in candidates or DEFAULT_CANDIDATES:
         m = srla.Monitor(**cfg, max_candidates=min(1 << 22, 4 * n_pairs + 64), timing=True,
                          scan_xcd=form == "xcd", scan_dedup=form == "dedup",
-                         scan_wave_dedup=form == "wave",
+                         scan_lds_filter=form == "filter",
                          scan_blocks=blocks, lean_report=True)
         m.scan(bufs[0])                  # warm the footprint
         m.estimate(copy=False)
@@ -83,7 +83,7 @@ def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False
     best = min(results, key=results.get)
     form, blocks = best.split("/")
     choice = {"scan_xcd": form == "xcd", "scan_dedup": form == "dedup",
-              "scan_wave_dedup": form == "wave",
+              "scan_lds_filter": form == "filter",
               "scan_blocks": int(blocks), "ms": results[best], "all": results}
     if cache:
         table = _load(cache)

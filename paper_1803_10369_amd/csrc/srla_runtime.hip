@@ -26,7 +26,7 @@
 #include "../../include/srla.h"
 #include "srla_discrete.h"
 #include "srla_scan_dedup.h"
-#include "srla_scan_wave.h"
+#include "srla_scan_filter.h"
 #include "srla_internal.h"
 
 using namespace srla;
@@ -71,7 +71,7 @@ bool config_ok(const srla_config_t* c) {
   if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
   if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH |
                               SRLA_CFG_DISCRETE | SRLA_CFG_LEAN_REPORT |
-                              SRLA_CFG_SCAN_DEDUP | SRLA_CFG_SCAN_WAVE_DEDUP)) != 0)
+                              SRLA_CFG_SCAN_DEDUP | SRLA_CFG_SCAN_LDS_FILTER)) != 0)
     return false;
   if ((c->flags & SRLA_CFG_DISCRETE) && c->window_slices != 1) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
@@ -179,7 +179,7 @@ struct srla_monitor {
   bool timing = false;
   bool xcd_scan = false;
   bool dedup_scan = false;
-  bool wave_scan = false;
+  bool filter_scan = false;
   std::vector<TimedSpan> spans;
   std::vector<hipEvent_t> ev_pool;
   double acc_ms[ST_N] = {0, 0, 0, 0, 0, 0};
@@ -492,7 +492,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->use_graph = (cfg->flags & SRLA_CFG_GRAPH) != 0;
   m->discrete = (cfg->flags & SRLA_CFG_DISCRETE) != 0;
   m->dedup_scan = (cfg->flags & SRLA_CFG_SCAN_DEDUP) != 0;
-  m->wave_scan = (cfg->flags & SRLA_CFG_SCAN_WAVE_DEDUP) != 0;
+  m->filter_scan = (cfg->flags & SRLA_CFG_SCAN_LDS_FILTER) != 0;
 
   const srla_geometry_t& g = cfg->geom;
   Geo& geo = m->geo;
@@ -641,8 +641,8 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
   if (m->dedup_scan)
     return launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                              m->tcount + p, m->cfg.scan_blocks, m->stream);
-  if (m->wave_scan)
-    return launch_scan_wave_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
+  if (m->filter_scan)
+    return launch_scan_lds_filter(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                                   m->tcount + p, m->cfg.scan_blocks, m->stream);
   return launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p], m->tcount + p,
                      m->xcd_scan, m->cfg.scan_blocks, m->stream);

@@ -26,9 +26,9 @@ def _gpu():
 
 
 def _run(stream, mon, slices, max_candidates=1 << 16, dump_every=1, split=None, host=False,
-         scan_xcd=False, graph=False, discrete=False, scan_dedup=False, scan_wave_dedup=False):
+         scan_xcd=False, graph=False, discrete=False, scan_dedup=False, scan_lds_filter=False):
     g = srla.Monitor(**mon, max_candidates=max_candidates, scan_xcd=scan_xcd, graph=graph,
-                     discrete=discrete, scan_dedup=scan_dedup, scan_wave_dedup=scan_wave_dedup)
+                     discrete=discrete, scan_dedup=scan_dedup, scan_lds_filter=scan_lds_filter)
     o = oracle.Monitor(**mon)
     for s in slices:
         pairs = stream.slice(s) if hasattr(stream, "slice") else stream(s)
@@ -436,7 +436,7 @@ def test_autotuner_picks_a_valid_shape_and_results_do_not_change(tmp_path):
     cache = str(tmp_path / "tune.json")
     choice = autotune.tune_scan(mon, pairs, repeats=2, cache=cache)
     assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "xcd/0", "xcd/1024",
-                                  "dedup/0", "dedup/1024", "wave/0", "wave/1024"}
+                                  "dedup/0", "dedup/1024", "filter/0", "filter/1024"}
     assert choice["ms"] == min(choice["all"].values()) > 0
     assert autotune.tune_scan(mon, pairs, cache=cache) == choice      # served from the cache
     _run(stream, mon, range(6), scan_xcd=choice["scan_xcd"])
@@ -534,19 +534,19 @@ def test_dedup_scan_backbone_expiry_and_full_size_prefix():
     _run(stream, mon, range(3), max_candidates=1 << 22, dump_every=0, scan_dedup=True)
 
 
-# ------------------------------------------------------------ wavefront dedup
-# SRLA_CFG_SCAN_WAVE_DEDUP merges same-DR stores inside a wavefront.
+# ------------------------------------------------------------ workgroup store filter
+# SRLA_CFG_SCAN_LDS_FILTER skips LE stores a workgroup already issued.
 
 @pytest.mark.parametrize("case", SMALL)
-def test_wave_dedup_scan_small_geometries(case):
+def test_lds_filter_scan_small_geometries(case):
     k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
     mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=6000 + k + u)
     _run(_rand_stream(k + u + 5, n, n_src, 3 * theta // 2), mon, range(slices),
-         scan_wave_dedup=True)
+         scan_lds_filter=True)
 
 
-def test_wave_dedup_scan_repeats_and_full_size():
-    """A stream of few flows (every wavefront repeats DRs) and the backbone
+def test_lds_filter_scan_repeats_and_full_size():
+    """A stream of few flows (every workgroup repeats DRs) and the backbone
     workload at full size."""
     stream, mon, n = workload("tiny_coupled")
 
@@ -555,6 +555,6 @@ def test_wave_dedup_scan_repeats_and_full_size():
         src = rng.integers(0, 40, 60_000, dtype=np.uint64).astype(np.uint32) * np.uint32(977)
         dst = rng.integers(0, 8, 60_000, dtype=np.uint64).astype(np.uint32) * np.uint32(131)
         return np.stack([src, dst], 1)
-    _run(few_flows, dict(mon, theta=4), range(6), scan_wave_dedup=True)
+    _run(few_flows, dict(mon, theta=4), range(6), scan_lds_filter=True)
     stream, mon, _ = workload("backbone")
-    _run(stream, mon, range(3), max_candidates=1 << 22, dump_every=0, scan_wave_dedup=True)
+    _run(stream, mon, range(3), max_candidates=1 << 22, dump_every=0, scan_lds_filter=True)
