@@ -2,12 +2,18 @@
 //
 // One monitor = one SEA (Section 4.1) resident in device memory plus the
 // buffers of the end-of-slice pipeline.  srla_scan enqueues Algorithm 2 on
-// the scan stream (the caller's).  srla_close_slice enqueues, on the
-// library's pipeline stream, after the slice's last scan:
-//   snapshot -> |LDR(i)|^k, the LE activity bitmap, the SRE activity bitmaps
+// the scan stream (the caller's), in the form the config picks (flat,
+// per-XCD, read-before-write, LDS-filtered, or the one-bit discrete form);
+// host pairs reach the device by DMA on a third, library-owned stream.
+// srla_close_slice enqueues, on the library's pipeline stream, after the
+// slice's last scan:
+//   snapshot -> |LDR(i)|^k, the LE activity bitmap, the SRE activity map
 //               (the end-of-slice state of every DR; scans of the next slice
-//               may start as soon as this is done)
-//   finalize -> sort + unique of the slice's sampled sources, candidate check
+//               may start as soon as this is done).  In the discrete form
+//               the DR bits are these maps already: only the row fills, and
+//               the clearing of the other parity's bits for the next slice
+//   finalize -> (discrete form: drain of the slice's source set) sort +
+//               unique of the slice's sampled sources, candidate check
 //   merge    -> CSIP_t = NCSIP_{t-1} u N_t, ascending
 //   estimate -> Eq8, then per candidate |ULE|^k, |URE|^k, Eq9, Algorithm 3's
 //               test; the report goes straight into pinned host memory
