@@ -469,6 +469,9 @@ def main():
     ap.add_argument("--full-report", action="store_true",
                     help="also deliver |ULE|^k and |URE|^k per candidate (18 instead of 13 "
                          "bytes per candidate to host memory)")
+    ap.add_argument("--overlap-report", type=int, default=-1,
+                    help="candidate work before the next slice's scans, only the report's "
+                         "PCIe copy alongside them (default: streaming form only)")
     ap.add_argument("--scan-lds-filter", action="store_true",
                     help="scan with a workgroup filter of repeated DR stores (A/B)")
     ap.add_argument("--scan-dedup", action="store_true",
@@ -506,6 +509,7 @@ def main():
     if args.calib_copy_mb:
         calibration_copy(args.calib_copy_mb)
     graph = (args.mode == "streaming") if args.graph < 0 else bool(args.graph)
+    overlap = (args.mode == "streaming") if args.overlap_report < 0 else bool(args.overlap_report)
     buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
     tuned = None
     if args.autotune:
@@ -523,7 +527,7 @@ def main():
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks,
                      lean_report=not args.full_report, scan_dedup=args.scan_dedup,
-                     scan_lds_filter=args.scan_lds_filter)
+                     scan_lds_filter=args.scan_lds_filter, overlap_report=overlap)
     t_w = time.perf_counter()
     for s in range(args.warmup):
         ds.generate(s, out=buf, stream=st)
@@ -626,7 +630,8 @@ def main():
             "slices_timed": [args.warmup, args.warmup + args.steps - 1],
             "mode": args.mode, "graph": graph, "scan_blocks": args.scan_blocks,
             "scan_xcd": args.scan_xcd, "scan_dedup": args.scan_dedup,
-            "scan_lds_filter": args.scan_lds_filter, "autotune": tuned,
+            "scan_lds_filter": args.scan_lds_filter, "overlap_report": overlap,
+            "autotune": tuned,
             "report": ("full: ip, est, flags, |ULE|^k, |URE|^k (18 B/candidate)"
                        if args.full_report else "ip, est, flags (13 B/candidate)"),
         },

@@ -76,13 +76,21 @@ enum {
                                   are identical; faster when pairs repeat DRs
                                   often.  Takes precedence over
                                   SRLA_CFG_SCAN_XCD */
-    SRLA_CFG_SCAN_LDS_FILTER = 64 /* scan with a workgroup filter of repeated
+    SRLA_CFG_SCAN_LDS_FILTER = 64, /* scan with a workgroup filter of repeated
                                   stores: each workgroup keeps the LE DRs it
                                   stored last in an LDS table and skips
                                   stores it has already issued in this scan.
                                   Results are identical.  Below
                                   SRLA_CFG_SCAN_DEDUP, above
                                   SRLA_CFG_SCAN_XCD in precedence */
+    SRLA_CFG_OVERLAP_REPORT = 128 /* for the streaming form: the candidate
+                                  check and the estimate of a closed slice
+                                  run before the next slice's scans may start
+                                  (into device staging arrays), and only the
+                                  PCIe copy of the report runs alongside
+                                  those scans.  Results are identical; costs
+                                  13 (lean) or 18 bytes of device memory per
+                                  max_candidates */
 };
 
 /*
@@ -157,8 +165,10 @@ typedef struct {
 
 /* Accumulated stage times (milliseconds, HIP events on the stream each stage
    runs on) since the last reset; all zero unless SRLA_CFG_TIMING was set.
-   With SRLA_CFG_GRAPH the end-of-slice stages after the sweeps are timed as
-   one (estimate_ms). */
+   With SRLA_CFG_GRAPH each of the two end-of-slice phases is timed as one:
+   the sweeps (sweep_ms, or estimate_ms together with the candidate work when
+   SRLA_CFG_OVERLAP_REPORT moves it there) and the rest (estimate_ms, or
+   report_ms for the overlapped report copy). */
 typedef struct {
     double scan_ms;        /* Algorithm 2 scan kernels */
     uint64_t scan_launches;
@@ -167,7 +177,8 @@ typedef struct {
     double finalize_ms;    /* candidate check of the slice's sampled sources */
     double estimate_ms;    /* merge, Eq8-Eq9 and the Algorithm 3 re-check */
     double slide_ms;       /* carried-list compaction, SI update, status */
-    double report_ms;      /* unused (the estimate writes the report) */
+    double report_ms;      /* report copy to the host (SRLA_CFG_OVERLAP_REPORT) and
+                              the status block */
     uint64_t estimates;
 } srla_timings_t;
 

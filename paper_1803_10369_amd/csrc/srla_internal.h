@@ -180,6 +180,11 @@ hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint
                            const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
                            hipStream_t st);
 
+// copies the first cnt->n_cand report entries from device staging arrays to
+// the host arrays (U and W only where `to` has them)
+hipError_t launch_report_copy(const Counters* cnt, const ReportPtrs& from, const ReportPtrs& to,
+                              hipStream_t st);
+
 // Algorithm 3's SI step on the per-bit counters (after the KEEP flags are final)
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
                             uint32_t* si_cnt, const Geo& geo, hipStream_t st);

@@ -547,6 +547,40 @@ __global__ void k_status(Counters* __restrict__ cnt, uint32_t* __restrict__ tcou
   if (t < sizeof(Counters) / 4) ((uint32_t*)cnt)[t] = 0u;
 }
 
+// ------------------------------------------------------------------ report copy
+// Copies the slice's report from the device staging arrays (written by
+// k_estimate) into the pinned host arrays: 16-byte loads and stores, grid
+// stride, the count read from device memory.  Used when the report's PCIe
+// transfer is to overlap the next slice's scan: this kernel needs little
+// besides PCIe bandwidth, while the gathers of k_estimate have already run.
+
+__device__ __forceinline__ void copy_bytes_16(const uint8_t* __restrict__ src,
+                                              uint8_t* __restrict__ dst, uint64_t bytes) {
+  const uint64_t n16 = bytes / 16;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (uint64_t i = t; i < n16; i += stride)
+    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+  const uint64_t tail = n16 * 16 + t;
+  if (tail < bytes && t < 16) dst[tail] = src[tail];
+}
+
+__global__ __launch_bounds__(kBlock) void k_report_copy(const Counters* __restrict__ cnt,
+                                                       ReportPtrs from, ReportPtrs to) {
+  const uint64_t n = cnt->n_cand;
+  copy_bytes_16((const uint8_t*)from.ip, (uint8_t*)to.ip, 4 * n);
+  copy_bytes_16((const uint8_t*)from.est, (uint8_t*)to.est, 8 * n);
+  copy_bytes_16(from.flags, to.flags, n);
+  if (to.U) copy_bytes_16((const uint8_t*)from.U, (uint8_t*)to.U, 4 * n);
+  if (to.W) copy_bytes_16(from.W, to.W, n);
+}
+
+hipError_t launch_report_copy(const Counters* cnt, const ReportPtrs& from, const ReportPtrs& to,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_report_copy, dim3(kPipeBlocks), dim3(kBlock), 0, st, cnt, from, to);
+  return hipGetLastError();
+}
+
 hipError_t launch_status(Counters* cnt, uint32_t* tcount, const double* up,
                          const unsigned long long* row_fill, uint32_t u, PipeState* ps,
                          HostStatus* out, hipStream_t st) {

@@ -77,7 +77,8 @@ bool config_ok(const srla_config_t* c) {
   if (c->max_candidates < 1 || c->max_candidates > 0xFFFFFFF0ull) return false;
   if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH |
                               SRLA_CFG_DISCRETE | SRLA_CFG_LEAN_REPORT |
-                              SRLA_CFG_SCAN_DEDUP | SRLA_CFG_SCAN_LDS_FILTER)) != 0)
+                              SRLA_CFG_SCAN_DEDUP | SRLA_CFG_SCAN_LDS_FILTER |
+                              SRLA_CFG_OVERLAP_REPORT)) != 0)
     return false;
   if ((c->flags & SRLA_CFG_DISCRETE) && c->window_slices != 1) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
@@ -157,6 +158,8 @@ struct srla_monitor {
   uint32_t* h_U = nullptr;
   uint8_t* h_W = nullptr;
   ReportPtrs d_report{};
+  bool overlap_report = false;   // candidate work before the next slice's scans,
+  ReportPtrs d_staging{};        // report staged here and copied while they run
 
   // ordering between the two streams
   hipEvent_t ev_scan = nullptr;   // after the closing slice's last scan
@@ -240,6 +243,12 @@ void hfree(void* p) {
 uint64_t candidate_bytes(uint64_t cap) {
   // csip, two carried lists (u32), cflags (u8), block words
   return cap * (4 + 4 + 4 + 1) + 4 * compact_block_words(cap);
+}
+
+// device staging of the report when its copy overlaps the next slice's scans
+uint64_t staging_bytes(const srla_config_t* cfg) {
+  if (!(cfg->flags & SRLA_CFG_OVERLAP_REPORT)) return 0;
+  return cfg->max_candidates * ((cfg->flags & SRLA_CFG_LEAN_REPORT) ? 13 : 18);
 }
 
 uint64_t bitmap_words(uint64_t cells) { return (cells + 63) / 64 + 1; }
@@ -337,11 +346,15 @@ int reserve_touched(srla_monitor* m, uint64_t need) {
 // Enqueues one phase of the end-of-slice pipeline of parity p on the
 // pipeline stream.  Every argument is fixed per (phase, parity), so the
 // sequence can also be recorded once into a graph.
-hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
+// The snapshot: |LDR(i)|^k, Eq8 and the activity maps of the closing slice.
+hipError_t enqueue_snapshot(srla_monitor* m, int p) {
   const Geo& geo = m->geo;
   hipStream_t st = m->pipe;
   hipError_t e = hipSuccess;
-  if (phase == PH_SNAPSHOT && m->discrete) {
+  hipEvent_t ta = nullptr;
+  const bool spans = !m->use_graph;
+  if (spans) span_begin(m, st, &ta);
+  if (m->discrete) {
     // the closing slice's bits are its activity maps already; the other
     // parity's (the previous slice's) are cleared for the next slice's scans
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st);
@@ -351,16 +364,23 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
       e = launch_fill_u32((uint32_t*)m->lebits[p ^ 1], 0u, 2 * bitmap_words(m->n_le), st);
     if (e == hipSuccess)
       e = launch_fill_u32((uint32_t*)m->rebits[p ^ 1], 0u, 4 * bitmap_words(m->n_re), st);
-    return e;
-  }
-  if (phase == PH_SNAPSHOT) {
+  } else {
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st);
     if (e == hipSuccess) e = launch_sweep_le(m->le, m->bitmap, m->row_fill, geo, m->ps, st);
-    if (e == hipSuccess)
-      e = launch_sweep_re(m->re, m->n_re, m->act, geo, m->ps, st);
+    if (e == hipSuccess) e = launch_sweep_re(m->re, m->n_re, m->act, geo, m->ps, st);
     if (e == hipSuccess) e = launch_union_prob(m->row_fill, geo, m->up, st);
-    return e;
   }
+  if (spans) span_end(m, st, ST_SWEEP, ta);
+  return e;
+}
+
+// The candidate work of the closing slice: candidate check of its sampled
+// sources, merge with the carried list, Eq9 for every candidate (report
+// entries to `out`), Algorithm 3's carried list and SI counters.
+hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out) {
+  const Geo& geo = m->geo;
+  hipStream_t st = m->pipe;
+  hipError_t e = hipSuccess;
   uint32_t* tc = m->tcount + p;
   const uint64_t* le_act = m->discrete ? m->lebits[p] : m->bitmap;
   const uint64_t* re_act = m->discrete ? m->rebits[p] : m->act;
@@ -381,17 +401,43 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
   if (e == hipSuccess)
     e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
   if (e == hipSuccess)
-    e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->up, geo, m->cflags,
-                        m->d_report, st);
+    e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->up, geo, m->cflags, out, st);
   if (spans) span_end(m, st, ST_ESTIMATE, ta);
   if (spans) span_begin(m, st, &ta);
   if (e == hipSuccess)
     e = compact_u32(m->cflags, 8u, m->csip, &m->cnt->n_cand, m->cap, m->carried[p ^ 1],
                     &m->cnt->n_keep, m->cblockw, st);
   if (e == hipSuccess) e = launch_si_update(m->csip, m->cflags, m->cnt, m->si_cnt, geo, st);
-  if (e == hipSuccess)
-    e = launch_status(m->cnt, tc, m->up, m->row_fill, geo.u, m->ps, m->d_status, st);
   if (spans) span_end(m, st, ST_SLIDE, ta);
+  return e;
+}
+
+// Enqueues one phase of the end-of-slice pipeline of parity p on the
+// pipeline stream.  Every argument is fixed per (phase, parity), so the
+// sequence can also be recorded once into a graph.  The next slice's scans
+// wait for the first phase only.  Normally that is the snapshot, and the
+// candidate work and the report (written by the estimate kernel straight
+// into host memory) overlap those scans.  With SRLA_CFG_OVERLAP_REPORT the
+// first phase also does the candidate work, into device staging arrays, and
+// only the PCIe copy of the report (and the status) overlaps the scans.
+hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
+  hipStream_t st = m->pipe;
+  hipError_t e = hipSuccess;
+  if (phase == PH_SNAPSHOT) {
+    e = enqueue_snapshot(m, p);
+    if (e == hipSuccess && m->overlap_report) e = enqueue_candidates(m, p, m->d_staging);
+    return e;
+  }
+  hipEvent_t ta = nullptr;
+  const bool spans = !m->use_graph;
+  if (!m->overlap_report) e = enqueue_candidates(m, p, m->d_report);
+  if (spans) span_begin(m, st, &ta);
+  if (e == hipSuccess && m->overlap_report)
+    e = launch_report_copy(m->cnt, m->d_staging, m->d_report, st);
+  if (e == hipSuccess)
+    e = launch_status(m->cnt, m->tcount + p, m->up, m->row_fill, m->geo.u, m->ps, m->d_status,
+                      st);
+  if (spans) span_end(m, st, ST_REPORT, ta);
   return e;
 }
 
@@ -431,6 +477,8 @@ void release(srla_monitor* m) {
   dfree(m->news); dfree(m->hist); dfree(m->blockw);
   dfree(m->csip); dfree(m->carried[0]); dfree(m->carried[1]); dfree(m->cflags);
   dfree(m->cblockw);
+  dfree(m->d_staging.ip); dfree(m->d_staging.est); dfree(m->d_staging.flags);
+  dfree(m->d_staging.U); dfree(m->d_staging.W);
   hfree(m->h_status); hfree(m->h_ip); hfree(m->h_est); hfree(m->h_flags);
   hfree(m->h_U); hfree(m->h_W);
   delete[] m->h_row_fill64;
@@ -466,8 +514,9 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
   if (cfg->flags & SRLA_CFG_DISCRETE)
     return 16 * bitmap_words(le) + 32 * bitmap_words(re) +
            16 * (uint64_t)source_set_slots(cfg->max_candidates) + 64 * si + 8 * g.u + 8 +
+           staging_bytes(cfg) +
            sizeof(Counters) + sizeof(PipeState) + 8 + candidate_bytes(cfg->max_candidates);
-  return 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
+  return staging_bytes(cfg) + 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
          8 * g.u + 8 + sizeof(Counters) + sizeof(PipeState) + 8 +
          candidate_bytes(cfg->max_candidates);
 }
@@ -499,6 +548,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->discrete = (cfg->flags & SRLA_CFG_DISCRETE) != 0;
   m->dedup_scan = (cfg->flags & SRLA_CFG_SCAN_DEDUP) != 0;
   m->filter_scan = (cfg->flags & SRLA_CFG_SCAN_LDS_FILTER) != 0;
+  m->overlap_report = (cfg->flags & SRLA_CFG_OVERLAP_REPORT) != 0;
 
   const srla_geometry_t& g = cfg->geom;
   Geo& geo = m->geo;
@@ -569,6 +619,13 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!rc) nomem(dalloc(&m->carried[1], m->cap));
   if (!rc) nomem(dalloc(&m->cflags, m->cap));
   if (!rc) nomem(dalloc(&m->cblockw, compact_block_words(m->cap)));
+  if (!rc && m->overlap_report) {
+    nomem(dalloc(&m->d_staging.ip, m->cap));
+    if (!rc) nomem(dalloc(&m->d_staging.est, m->cap));
+    if (!rc) nomem(dalloc(&m->d_staging.flags, m->cap));
+    if (!rc && !(cfg->flags & SRLA_CFG_LEAN_REPORT)) nomem(dalloc(&m->d_staging.U, m->cap));
+    if (!rc && !(cfg->flags & SRLA_CFG_LEAN_REPORT)) nomem(dalloc(&m->d_staging.W, m->cap));
+  }
   if (!rc) nomem(halloc(&m->h_status, 1));
   if (!rc) nomem(halloc(&m->h_ip, m->cap));
   if (!rc) nomem(halloc(&m->h_est, m->cap));
@@ -760,17 +817,20 @@ int srla_close_slice(srla_monitor_t* m) {
   }
   HIP_TRY(m, hipEventRecord(m->ev_scan, m->stream));
   HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_scan, 0));
+  // with graphs, each phase is timed as a whole: the first as the sweeps
+  // (with the candidate work when the report copy overlaps the next scans),
+  // the second as the estimate (as the report copy when it overlaps)
   hipEvent_t ta;
-  span_begin(m, m->pipe, &ta);
+  if (m->use_graph) span_begin(m, m->pipe, &ta);
   int rc = run_phase(m, PH_SNAPSHOT, p);
   if (rc) return rc;
-  span_end(m, m->pipe, ST_SWEEP, ta);
+  if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_ESTIMATE : ST_SWEEP, ta);
   HIP_TRY(m, hipEventRecord(m->ev_snap, m->pipe));
   m->snap_pending = true;
   if (m->use_graph) span_begin(m, m->pipe, &ta);
   rc = run_phase(m, PH_FINISH, p);
   if (rc) return rc;
-  if (m->use_graph) span_end(m, m->pipe, ST_ESTIMATE, ta);
+  if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
   HIP_TRY(m, hipEventRecord(m->ev_done, m->pipe));
   m->report_pending = true;
   m->slice++;

@@ -116,10 +116,10 @@ def test_small_geometries(case, scan_xcd, graph):
 
 
 def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chunks=1,
-                   discrete=False, scan_dedup=False):
+                   discrete=False, scan_dedup=False, overlap_report=False):
     """The next slice is scanned before the previous slice's report is taken."""
     g = srla.Monitor(**mon, max_candidates=max_candidates, graph=graph, discrete=discrete,
-                     scan_dedup=scan_dedup)
+                     scan_dedup=scan_dedup, overlap_report=overlap_report)
     o = oracle.Monitor(**mon)
     expected = []
     slices = list(slices)
@@ -558,3 +558,39 @@ def test_lds_filter_scan_repeats_and_full_size():
     _run(few_flows, dict(mon, theta=4), range(6), scan_lds_filter=True)
     stream, mon, _ = workload("backbone")
     _run(stream, mon, range(3), max_candidates=1 << 22, dump_every=0, scan_lds_filter=True)
+
+
+# ------------------------------------------------------------ overlapped report copy
+# SRLA_CFG_OVERLAP_REPORT: candidate work before the next slice's scans, the
+# report's PCIe copy alongside them; results identical in both call patterns.
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_overlap_report_streaming_and_plain(graph):
+    stream, mon, n = workload("tiny")
+    _run_streaming(stream, mon, range(n), graph=graph, chunks=2, overlap_report=True)
+    stream, mon, n = workload("tiny_coupled")
+    g = srla.Monitor(**mon, max_candidates=1 << 16, graph=graph, overlap_report=True)
+    o = oracle.Monitor(**mon)
+    for s in range(n):
+        p = stream.slice(s)
+        g.scan(to_device(p))
+        o.scan(p)
+        compare_reports(g.estimate(), o.estimate(), mon["theta"], "slice %d" % s)
+    compare_dumps(g, o)
+    g.close()
+
+
+@pytest.mark.parametrize("case", [SMALL[0], SMALL[5], SMALL[7]])
+def test_overlap_report_small_geometries_and_discrete(case):
+    k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
+    mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=8000 + k + u)
+    _run_streaming(_rand_stream(k + u + 13, n, n_src, 3 * theta // 2), mon, range(slices),
+                   graph=True, overlap_report=True)
+    _run_streaming(_rand_stream(k + u + 14, n, n_src, 3 * theta // 2), dict(mon, k=1),
+                   range(slices), graph=True, discrete=True, overlap_report=True)
+
+
+def test_overlap_report_backbone_full_size_streaming():
+    stream, mon, _ = workload("backbone")
+    _run_streaming(stream, mon, range(3), max_candidates=1 << 22, graph=True,
+                   overlap_report=True)
