@@ -88,9 +88,13 @@ enum {
                                   run before the next slice's scans may start
                                   (into device staging arrays), and only the
                                   PCIe copy of the report runs alongside
-                                  those scans.  Results are identical; costs
-                                  13 (lean) or 18 bytes of device memory per
-                                  max_candidates */
+                                  those scans -- enqueued by the next slice's
+                                  first srla_scan, after that scan has
+                                  started, or by srla_wait_report if it comes
+                                  first.  Results are identical; costs 13
+                                  (lean) or 18 bytes of device memory per
+                                  max_candidates.  Such monitors cannot join
+                                  a group */
 };
 
 /*
@@ -284,7 +288,8 @@ int srla_timings(srla_monitor_t *m, srla_timings_t *out, int reset);
  * same pairs.  Slices are still closed and reported per member
  * (srla_close_slice / srla_wait_report / srla_estimate).
  * srla_group_create: 1..64 distinct monitors that share one scan stream,
- *   none of them in the discrete form; scan_blocks as in srla_config_t.  The group does not own the monitors;
+ *   none of them in the discrete form or with SRLA_CFG_OVERLAP_REPORT;
+ *   scan_blocks as in srla_config_t.  The group does not own the monitors;
  *   destroy the group before any member.
  * srla_group_scan: pairs as for srla_scan, device memory only (on_device
  *   must be nonzero).  Errors: SRLA_E_INVAL, SRLA_E_STATE (a member is

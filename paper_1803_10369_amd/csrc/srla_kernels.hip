@@ -575,9 +575,15 @@ __global__ __launch_bounds__(kBlock) void k_report_copy(const Counters* __restri
   if (to.W) copy_bytes_16(from.W, to.W, n);
 }
 
+// A small grid: 64 workgroups already saturate PCIe writes, and the copy
+// runs beside the next slice's scan, which needs the rest of the GPU's wave
+// slots (a kernel whose workgroups fill every slot keeps a kernel of another
+// stream from starting until its own workgroups retire).
+constexpr uint32_t kCopyBlocks = 128;
+
 hipError_t launch_report_copy(const Counters* cnt, const ReportPtrs& from, const ReportPtrs& to,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_report_copy, dim3(kPipeBlocks), dim3(kBlock), 0, st, cnt, from, to);
+  hipLaunchKernelGGL(k_report_copy, dim3(kCopyBlocks), dim3(kBlock), 0, st, cnt, from, to);
   return hipGetLastError();
 }
 

@@ -167,6 +167,8 @@ struct srla_monitor {
   hipEvent_t ev_done = nullptr;   // after its whole pipeline
   bool snap_pending = false;      // the open slice's scans still have to wait ev_snap
   bool report_pending = false;    // a closed slice whose report is not collected
+  bool finish_deferred = false;   // its report copy is not enqueued yet (overlap_report)
+  hipEvent_t ev_go = nullptr;     // the next slice's first scan is about to start
 
   // replayable pipeline: [phase][parity]
   bool use_graph = false;
@@ -492,6 +494,7 @@ void release(srla_monitor* m) {
   if (m->ev_scan) (void)hipEventDestroy(m->ev_scan);
   if (m->ev_snap) (void)hipEventDestroy(m->ev_snap);
   if (m->ev_done) (void)hipEventDestroy(m->ev_done);
+  if (m->ev_go) (void)hipEventDestroy(m->ev_go);
   if (m->pipe) (void)hipStreamDestroy(m->pipe);
   if (m->copy) {
     (void)hipStreamSynchronize(m->copy);
@@ -646,7 +649,8 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     rc = SRLA_E_DEVICE;
   if (!rc && (hipEventCreateWithFlags(&m->ev_scan, hipEventDisableTiming) != hipSuccess ||
               hipEventCreateWithFlags(&m->ev_snap, hipEventDisableTiming) != hipSuccess ||
-              hipEventCreateWithFlags(&m->ev_done, hipEventDisableTiming) != hipSuccess))
+              hipEventCreateWithFlags(&m->ev_done, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&m->ev_go, hipEventDisableTiming) != hipSuccess))
     rc = SRLA_E_DEVICE;
   if (rc) {
     release(m);
@@ -711,6 +715,30 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
                      m->xcd_scan, m->cfg.scan_blocks, m->stream);
 }
 
+// Enqueues the second phase of the closed slice's pipeline (with
+// overlap_report: the report's copy to host memory, and the status) and its
+// completion event.  after_scan: the next slice's first scan is enqueued on
+// the scan stream right after this call, and the copy waits until that scan
+// is about to start.  A kernel that streams writes into host memory delays
+// the dispatch of kernels of other queues by hundreds of microseconds (the
+// command processor reads queue packets and signals in host memory behind
+// those writes), so the scan has to be under way before the copy begins.
+int enqueue_finish(srla_monitor* m, bool after_scan) {
+  const int pc = (int)((m->slice - 1) & 1);   // parity of the closed slice
+  if (after_scan) {
+    HIP_TRY(m, hipEventRecord(m->ev_go, m->stream));
+    HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_go, 0));
+  }
+  hipEvent_t ta;
+  if (m->use_graph) span_begin(m, m->pipe, &ta);
+  const int rc = run_phase(m, PH_FINISH, pc);
+  if (rc) return rc;
+  if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
+  HIP_TRY(m, hipEventRecord(m->ev_done, m->pipe));
+  m->finish_deferred = false;
+  return SRLA_OK;
+}
+
 // true if p is page-locked host memory that the DMA engines can read directly
 bool host_pinned(const void* p) {
   hipPointerAttribute_t attr;
@@ -737,6 +765,10 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     // the previous slice's DRs must be snapshotted before this slice stamps them
     HIP_TRY(m, hipStreamWaitEvent(m->stream, m->ev_snap, 0));
     m->snap_pending = false;
+  }
+  if (m->finish_deferred) {
+    rc = enqueue_finish(m, true);
+    if (rc) return rc;
   }
   if (on_device) {
     hipEvent_t a;
@@ -827,21 +859,26 @@ int srla_close_slice(srla_monitor_t* m) {
   if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_ESTIMATE : ST_SWEEP, ta);
   HIP_TRY(m, hipEventRecord(m->ev_snap, m->pipe));
   m->snap_pending = true;
-  if (m->use_graph) span_begin(m, m->pipe, &ta);
-  rc = run_phase(m, PH_FINISH, p);
-  if (rc) return rc;
-  if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
-  HIP_TRY(m, hipEventRecord(m->ev_done, m->pipe));
   m->report_pending = true;
   m->slice++;
   m->slice_pairs[m->slice & 1] = 0;
-  return SRLA_OK;
+  // with overlap_report the second phase waits for the next slice's first
+  // scan (or for srla_wait_report, whichever comes first)
+  if (m->overlap_report) {
+    m->finish_deferred = true;
+    return SRLA_OK;
+  }
+  return enqueue_finish(m, false);
 }
 
 int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
   if (!m || !out) return m ? fail(m, SRLA_E_INVAL, "out is NULL") : SRLA_E_INVAL;
   if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
   if (!m->report_pending) return fail(m, SRLA_E_STATE, "no closed slice is waiting");
+  if (m->finish_deferred) {
+    const int rc = enqueue_finish(m, false);
+    if (rc) return rc;
+  }
   HIP_TRY(m, hipEventSynchronize(m->ev_done));
   m->report_pending = false;
   const HostStatus& hs = *m->h_status;
@@ -986,7 +1023,7 @@ int srla_group_create(srla_monitor_t* const* monitors, uint32_t n, uint32_t scan
   if (!out || !monitors || n < 1 || n > (uint32_t)kMaxGroup) return SRLA_E_INVAL;
   for (uint32_t i = 0; i < n; ++i) {
     if (!monitors[i] || monitors[i]->stream != monitors[0]->stream) return SRLA_E_INVAL;
-    if (monitors[i]->discrete) return SRLA_E_INVAL;
+    if (monitors[i]->discrete || monitors[i]->overlap_report) return SRLA_E_INVAL;
     for (uint32_t j = 0; j < i; ++j)
       if (monitors[j] == monitors[i]) return SRLA_E_INVAL;
   }

@@ -44,6 +44,13 @@ def _load():
         L.probe_host_write.restype = ctypes.c_double
         L.probe_host_write.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
                                        ctypes.c_void_p]
+        L.probe_two_streams.restype = ctypes.c_double
+        L.probe_two_streams.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_double)]
+        L.probe_event_order.restype = ctypes.c_double
+        L.probe_event_order.argtypes = L.probe_two_streams.argtypes + [ctypes.c_uint32,
+                                                                        ctypes.c_uint32]
         L.probe_xcc_of_blocks.restype = ctypes.c_int
         L.probe_xcc_of_blocks.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
         L.probe_random_load.restype = ctypes.c_double
@@ -96,6 +103,37 @@ def dma_d2h_rate(nbytes=64 << 20, repeats=3):
             ms = a.elapsed_time(b)
             best = ms if best is None else min(best, ms)
     return nbytes / (best * 1e-3)
+
+
+def two_streams(blocks=512, iters=200_000):
+    """(ms of one spin kernel of `blocks` workgroups alone, ms of two such
+    kernels on two streams released together): equal when they overlap."""
+    import torch
+    buf = torch.empty(2 * blocks * 256, dtype=torch.int32, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    both = ctypes.c_double(0.0)
+    one = _load().probe_two_streams(ctypes.c_void_p(buf.data_ptr()), blocks, iters,
+                                    ctypes.c_void_p(s1.cuda_stream),
+                                    ctypes.c_void_p(s2.cuda_stream), ctypes.byref(both))
+    if one < 0:
+        raise RuntimeError("probe failed (%g)" % one)
+    return one, both.value
+
+
+def event_order(blocks=64, iters=200_000, blocks3=1, iters3=1):
+    """(ms from stream 1's first spin to stream 2's kernel that waits for an
+    event recorded after that spin, ms of stream 1's two spins)."""
+    import torch
+    buf = torch.empty((blocks + (blocks3 & 0x7FFFFFFF)) * 256, dtype=torch.int32, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    both = ctypes.c_double(0.0)
+    t3 = _load().probe_event_order(ctypes.c_void_p(buf.data_ptr()), blocks, iters,
+                                   ctypes.c_void_p(s1.cuda_stream),
+                                   ctypes.c_void_p(s2.cuda_stream), ctypes.byref(both),
+                                   blocks3, iters3)
+    if t3 < 0:
+        raise RuntimeError("probe failed (%g)" % t3)
+    return t3, both.value
 
 
 def xcc_of_blocks(blocks=64):

@@ -71,7 +71,90 @@ __global__ __launch_bounds__(256) void k_host_write(uint4* __restrict__ dst, uin
     dst[i] = make_uint4((uint32_t)i, seed, (uint32_t)(i >> 32), ~seed);
 }
 
+// a fixed amount of ALU work per lane (no memory traffic but one store per
+// lane at the end, so the loop is not optimized away)
+__global__ __launch_bounds__(256) void k_spin(uint32_t* __restrict__ out, uint32_t iters) {
+  uint32_t x = threadIdx.x + 1u;
+  for (uint32_t i = 0; i < iters; ++i) x = x * 1664525u + 1013904223u;
+  out[(uint64_t)blockIdx.x * 256 + threadIdx.x] = x;
+}
+
 }  // namespace
+
+// Two spin kernels of `blocks` workgroups each, on two streams at once, and
+// then one after the other on one stream: returns the ms of both (via *both)
+// and of one alone (the return value), or a negative value on error.  Equal
+// times mean the two streams' kernels ran side by side.
+extern "C" double probe_two_streams(void* buf, uint32_t blocks, uint32_t iters, void* s1,
+                                    void* s2, double* both) {
+  if (!buf || blocks == 0 || !both) return -1.0;
+  hipStream_t a = (hipStream_t)s1, b = (hipStream_t)s2;
+  uint32_t* out = (uint32_t*)buf;
+  hipEvent_t e0, e1, e2, ea, eb;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+      hipEventCreate(&e2) != hipSuccess || hipEventCreate(&ea) != hipSuccess ||
+      hipEventCreate(&eb) != hipSuccess)
+    return -2.0;
+  float one = -1.f, two = -1.f;
+  // one kernel alone
+  hipEventRecord(e0, a);
+  hipLaunchKernelGGL(k_spin, dim3(blocks), dim3(256), 0, a, out, iters);
+  hipEventRecord(e1, a);
+  hipEventSynchronize(e1);
+  hipEventElapsedTime(&one, e0, e1);
+  // two kernels, one per stream, released together
+  hipEventRecord(e0, a);
+  hipStreamWaitEvent(b, e0, 0);
+  hipLaunchKernelGGL(k_spin, dim3(blocks), dim3(256), 0, a, out, iters);
+  hipLaunchKernelGGL(k_spin, dim3(blocks), dim3(256), 0, b, out + (uint64_t)blocks * 256, iters);
+  hipEventRecord(eb, b);
+  hipStreamWaitEvent(a, eb, 0);
+  hipEventRecord(e2, a);
+  hipEventSynchronize(e2);
+  hipEventElapsedTime(&two, e0, e2);
+  hipEventDestroy(e0); hipEventDestroy(e1); hipEventDestroy(e2);
+  hipEventDestroy(ea); hipEventDestroy(eb);
+  *both = two;
+  return one;
+}
+
+// Cross-stream ordering: stream 1 runs spin kernel K1, records event E, runs
+// spin kernel K2; stream 2 waits for E and runs spin kernel K3 (blocks3
+// workgroups of iters3 steps).
+// Returns the ms from before K1 to after K3 (about one spin if K3 ran right
+// after K1, two if it waited for K2), and the ms of stream 1's two spins
+// via *both.
+extern "C" double probe_event_order(void* buf, uint32_t blocks, uint32_t iters, void* s1,
+                                    void* s2, double* both, uint32_t blocks3, uint32_t iters3) {
+  if (!buf || blocks == 0 || !both) return -1.0;
+  hipStream_t a = (hipStream_t)s1, b = (hipStream_t)s2;
+  uint32_t* out = (uint32_t*)buf;
+  hipEvent_t e0, e, ea, eb;
+  const bool untimed = (blocks3 & 0x80000000u) != 0;   // E without timing
+  blocks3 &= 0x7FFFFFFFu;
+  if (hipEventCreate(&e0) != hipSuccess ||
+      (untimed ? hipEventCreateWithFlags(&e, hipEventDisableTiming) : hipEventCreate(&e)) !=
+          hipSuccess ||
+      hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess)
+    return -2.0;
+  hipEventRecord(e0, a);
+  hipLaunchKernelGGL(k_spin, dim3(blocks), dim3(256), 0, a, out, iters);
+  hipEventRecord(e, a);
+  hipLaunchKernelGGL(k_spin, dim3(blocks), dim3(256), 0, a, out, iters);
+  hipEventRecord(ea, a);
+  hipStreamWaitEvent(b, e, 0);
+  hipLaunchKernelGGL(k_spin, dim3(blocks3), dim3(256), 0, b, out + (uint64_t)blocks * 256,
+                     iters3);
+  hipEventRecord(eb, b);
+  hipEventSynchronize(ea);
+  hipEventSynchronize(eb);
+  float t3 = -1.f, t12 = -1.f;
+  hipEventElapsedTime(&t3, e0, eb);
+  hipEventElapsedTime(&t12, e0, ea);
+  hipEventDestroy(e0); hipEventDestroy(e); hipEventDestroy(ea); hipEventDestroy(eb);
+  *both = t12;
+  return t3;
+}
 
 // Returns the kernel time in ms of writing `bytes` (a multiple of 16) to the
 // device-visible address of pinned host memory, or a negative value.
