@@ -8,11 +8,13 @@ delivered to host memory.  Window k = 300 slices, SRE 8 x 2^20 DR cells, SLE
 slices see a full window; the timed slices' pairs are generated into device
 memory before each timed segment starts.
 
---mode plain (default): each slice is scanned, then estimated; the latency
-  is the host time from the end of the slice's scan to its report.
---mode streaming: the scan of slice t+1 runs on the GPU while slice t is
-  being estimated (two HIP streams, the end-of-slice pipeline replayed as HIP
-  graphs); the latency is the host time from closing slice t to its report.
+--mode streaming (default): slice t's candidate check and estimate run first
+  (into device memory), then the scan of slice t+1 runs on the GPU while the
+  report of slice t is copied to host memory (two HIP streams, the
+  end-of-slice pipeline replayed as HIP graphs); the latency is the host time
+  from closing slice t to its report.
+--mode plain: each slice is scanned, then estimated; the latency is the host
+  time from the end of the slice's scan to its report.
 
 Prints one JSON line (rank 0).  `value` is pairs (packets) scanned per second
 over the timed slices; `p99_ms` is the 99th percentile of the latency.
@@ -440,7 +442,7 @@ def run_serving(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--mode", choices=("plain", "streaming", "batched"), default="plain")
+    ap.add_argument("--mode", choices=("plain", "streaming", "batched"), default="streaming")
     ap.add_argument("--graph", type=int, default=-1,
                     help="replay the end-of-slice pipeline as HIP graphs (default: streaming only)")
     ap.add_argument("--autotune", type=int, default=1,

@@ -435,8 +435,8 @@ def test_autotuner_picks_a_valid_shape_and_results_do_not_change(tmp_path):
     pairs = to_device(stream.slice(0))
     cache = str(tmp_path / "tune.json")
     choice = autotune.tune_scan(mon, pairs, repeats=2, cache=cache)
-    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "xcd/0", "xcd/1024",
-                                  "dedup/0", "dedup/1024", "filter/0", "filter/1024"}
+    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "dedup/0", "filter/0",
+                                  "filter/512"}
     assert choice["ms"] == min(choice["all"].values()) > 0
     assert autotune.tune_scan(mon, pairs, cache=cache) == choice      # served from the cache
     _run(stream, mon, range(6), scan_xcd=choice["scan_xcd"])
