@@ -186,26 +186,45 @@ hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act, const Geo& g
   return hipGetLastError();
 }
 
-// the g "now" and g "next" activity bits of the SRE in row r, column col
-// (g <= 64) from the interleaved map: one 16-byte load, two if the SRE
-// straddles a 64-bit boundary
+// The g "now" and g "next" activity bits of the SRE in row r, column col
+// (g <= 64) from the interleaved map, in two steps so that callers can issue
+// the loads early: sre_fetch reads the 16-byte word that holds the SRE's first
+// bit and the one after it (the map is allocated with a spare word, so this
+// stays in bounds); sre_combine extracts the bits, taking the second word
+// only when the SRE straddles a 64-bit boundary.
+struct SreWords {
+  uint4 q0, q1;
+  uint32_t sh;
+};
+
+__device__ __forceinline__ SreWords sre_fetch(const uint64_t* __restrict__ act, const Geo& geo,
+                                              uint32_t r, uint32_t col) {
+  const uint64_t off = ((uint64_t)r * geo.v_re + col) * geo.g;
+  const uint64_t w = off >> 6;
+  SreWords s;
+  s.q0 = reinterpret_cast<const uint4*>(act)[w];
+  s.q1 = reinterpret_cast<const uint4*>(act)[w + 1];
+  s.sh = (uint32_t)(off & 63u);
+  return s;
+}
+
+__device__ __forceinline__ void sre_combine(const SreWords& s, uint32_t g, uint64_t* now,
+                                            uint64_t* next) {
+  uint64_t a = ((((uint64_t)s.q0.y) << 32) | s.q0.x) >> s.sh;
+  uint64_t b = ((((uint64_t)s.q0.w) << 32) | s.q0.z) >> s.sh;
+  if (s.sh + g > 64u) {
+    a |= ((((uint64_t)s.q1.y) << 32) | s.q1.x) << (64u - s.sh);
+    b |= ((((uint64_t)s.q1.w) << 32) | s.q1.z) << (64u - s.sh);
+  }
+  const uint64_t mask = g == 64u ? ~0ull : ((1ull << g) - 1ull);
+  *now = a & mask;
+  *next = b & mask;
+}
+
 __device__ __forceinline__ void sre_bits(const uint64_t* __restrict__ act, const Geo& geo,
                                          uint32_t r, uint32_t col, uint64_t* now,
                                          uint64_t* next) {
-  const uint64_t off = ((uint64_t)r * geo.v_re + col) * geo.g;
-  const uint64_t w = off >> 6;
-  const uint32_t sh = (uint32_t)(off & 63u);
-  const uint4 q = reinterpret_cast<const uint4*>(act)[w];
-  uint64_t a = ((((uint64_t)q.y) << 32) | q.x) >> sh;
-  uint64_t b = ((((uint64_t)q.w) << 32) | q.z) >> sh;
-  if (sh + geo.g > 64u) {
-    const uint4 q2 = reinterpret_cast<const uint4*>(act)[w + 1];
-    a |= ((((uint64_t)q2.y) << 32) | q2.x) << (64u - sh);
-    b |= ((((uint64_t)q2.w) << 32) | q2.z) << (64u - sh);
-  }
-  const uint64_t mask = geo.g == 64u ? ~0ull : ((1ull << geo.g) - 1ull);
-  *now = a & mask;
-  *next = b & mask;
+  sre_combine(sre_fetch(act, geo, r, col), geo.g, now, next);
 }
 
 // SI as per-bit counters: counter (r, col, b) = number of carried candidates
@@ -346,16 +365,21 @@ hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
 // ------------------------------------------------------------------ estimate
 // For every candidate: |ULE|^k from the LE activity bitmap (AND over the u
 // rows, popcount), |URE|^k now and after the slide from the RE activity
-// bitmaps, Eq9 in FP64, and the flags.  A group of 2^lg_log2 lanes owns one
-// candidate; its lanes split the G/64 bitmap words (16 lanes read one
-// 128-byte line per row when G = 1024) and the u rows of the SRE, then
-// reduce with cross-lane shuffles.  A block finishes 256 candidates, stages
-// them in LDS, and writes the report entries with one coalesced store per
-// array straight into the pinned host buffers (mapped into the GPU's address
-// space), so no separate device-to-host copy is needed.  The report is
-// PCIe-bound: the block barriers order LDS only, so a block's host writes stay
-// in flight while it gathers its next candidates; U and W are written only
-// when their buffers are given (the lean report leaves them out).
+// bitmaps, Eq9 in FP64, and the flags.
+//
+// A block takes 256 candidates at a time.  Their addresses are staged in LDS
+// first; then a group of 2^lg_log2 lanes owns one candidate: every lane hashes
+// the address for all u rows in registers and issues its u bitmap loads (the
+// group's 16 lanes read one 128-byte line per row when G = 1024) and, for the
+// lane whose index is a row number, that row's SRE load, all before the first
+// wait, so a candidate costs one cache round trip rather than one per row.
+// Cross-lane shuffles reduce the group; the counts go to LDS.  Eq9 then runs
+// with one thread per candidate, and the report entries leave with one
+// coalesced store per array (into pinned host memory mapped into the GPU's
+// address space, or into device staging).  The block barriers order LDS
+// only, so a block's report stores stay in flight while it gathers its next
+// candidates; U and W are written only when their buffers are given (the lean
+// report leaves them out).
 
 constexpr uint32_t kEstPerBlock = kBlock;
 
@@ -367,6 +391,9 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// kU >= geo.u is the unrolled row count; the launch guarantees 2^lg_log2 >= u
+// (each lane handles at most one SRE row).
+template <int kU>
 __global__ __launch_bounds__(kBlock) void k_estimate(
     const uint32_t* __restrict__ csip, const Counters* __restrict__ cnt,
     const uint64_t* __restrict__ bitmap, const uint64_t* __restrict__ act,
@@ -374,54 +401,69 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
     uint32_t lg_log2, uint8_t* __restrict__ cflags, uint32_t* __restrict__ out_ip,
     double* __restrict__ out_est, uint8_t* __restrict__ out_flags, uint32_t* __restrict__ out_U,
     uint8_t* __restrict__ out_W) {
-  __shared__ double s_est[kEstPerBlock];
   __shared__ uint32_t s_ip[kEstPerBlock], s_U[kEstPerBlock];
-  __shared__ uint8_t s_W[kEstPerBlock], s_f[kEstPerBlock];
+  __shared__ uint8_t s_W[kEstPerBlock], s_Wn[kEstPerBlock];
   const uint32_t lg = 1u << lg_log2;
   const uint32_t per_round = kBlock >> lg_log2;          // candidates per round
   const uint32_t sub = threadIdx.x & (lg - 1u);
   const uint32_t n = cnt->n_cand;
   const uint64_t gmask = geo.g == 64u ? ~0ull : ((1ull << geo.g) - 1ull);
-  const double up = *up_p;
-  const double G = (double)geo.G;
   for (uint64_t base = (uint64_t)blockIdx.x * kEstPerBlock; base < n;
        base += (uint64_t)gridDim.x * kEstPerBlock) {
-  for (uint32_t round = 0; round * per_round < kEstPerBlock; ++round) {
-    const uint32_t local = round * per_round + (threadIdx.x >> lg_log2);
-    const uint64_t gid = base + local;
-    const bool valid = local < kEstPerBlock && gid < n;
-    const uint32_t a = valid ? csip[gid] : 0u;
-    uint32_t ucount = 0;
-    uint64_t m_now = ~0ull, m_next = ~0ull;
-    if (valid) {
-      for (uint32_t x = sub; x < geo.words; x += lg) {
-        uint64_t acc = ~0ull;
-        for (uint32_t r = 0; r < geo.u; ++r) {
-          const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_le);
-          acc &= bitmap[((uint64_t)r * geo.v_le + col) * geo.words + x];
+    const uint32_t in_batch =
+        (uint32_t)(n - base < (uint64_t)kEstPerBlock ? n - base : (uint64_t)kEstPerBlock);
+    if (threadIdx.x < in_batch) s_ip[threadIdx.x] = csip[base + threadIdx.x];
+    lds_barrier();
+    for (uint32_t first = 0; first < in_batch; first += per_round) {
+      const uint32_t local = first + (threadIdx.x >> lg_log2);
+      const bool valid = local < in_batch;
+      const uint32_t a = s_ip[valid ? local : 0u];
+      uint32_t my_h = 0;
+#pragma unroll
+      for (int r = 0; r < kU; ++r)
+        if (r < (int)geo.u && (uint32_t)r == sub) my_h = mas(geo.rh[r], a);
+      uint32_t ucount = 0;
+      uint64_t m_now = ~0ull, m_next = ~0ull;
+      const bool sre_lane = valid && sub < geo.u;
+      SreWords sw;
+      if (sre_lane) sw = sre_fetch(act, geo, sub, hrange(my_h, geo.v_re));
+      if (valid) {
+        for (uint32_t x = sub; x < geo.words; x += lg) {
+          uint64_t w[kU];
+#pragma unroll
+          for (int r = 0; r < kU; ++r)
+            w[r] = r < (int)geo.u
+                       ? bitmap[((uint64_t)r * geo.v_le + hrange(mas(geo.rh[r], a), geo.v_le)) *
+                                    geo.words + x]
+                       : ~0ull;
+          uint64_t acc = ~0ull;
+#pragma unroll
+          for (int r = 0; r < kU; ++r) acc &= w[r];
+          ucount += (uint32_t)__popcll(acc);
         }
-        ucount += (uint32_t)__popcll(acc);
       }
-      for (uint32_t r = sub; r < geo.u; r += lg) {
-        const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
-        uint64_t now, next;
-        sre_bits(act, geo, r, col, &now, &next);
-        m_now &= now;
-        m_next &= next;
+      if (sre_lane) sre_combine(sw, geo.g, &m_now, &m_next);
+      uint32_t now_lo = (uint32_t)m_now, now_hi = (uint32_t)(m_now >> 32);
+      uint32_t nx_lo = (uint32_t)m_next, nx_hi = (uint32_t)(m_next >> 32);
+      for (uint32_t off = lg >> 1; off > 0; off >>= 1) {
+        ucount += __shfl_xor(ucount, (int)off);
+        now_lo &= __shfl_xor(now_lo, (int)off);
+        now_hi &= __shfl_xor(now_hi, (int)off);
+        nx_lo &= __shfl_xor(nx_lo, (int)off);
+        nx_hi &= __shfl_xor(nx_hi, (int)off);
+      }
+      if (valid && sub == 0) {
+        s_U[local] = ucount;
+        s_W[local] = (uint8_t)__popcll((((uint64_t)now_hi << 32) | now_lo) & gmask);
+        s_Wn[local] = (uint8_t)__popcll((((uint64_t)nx_hi << 32) | nx_lo) & gmask);
       }
     }
-    uint32_t now_lo = (uint32_t)m_now, now_hi = (uint32_t)(m_now >> 32);
-    uint32_t nx_lo = (uint32_t)m_next, nx_hi = (uint32_t)(m_next >> 32);
-    for (uint32_t off = lg >> 1; off > 0; off >>= 1) {
-      ucount += __shfl_xor(ucount, (int)off);
-      now_lo &= __shfl_xor(now_lo, (int)off);
-      now_hi &= __shfl_xor(now_hi, (int)off);
-      nx_lo &= __shfl_xor(nx_lo, (int)off);
-      nx_hi &= __shfl_xor(nx_hi, (int)off);
-    }
-    if (valid && sub == 0) {
-      const uint32_t w_now = (uint32_t)__popcll((((uint64_t)now_hi << 32) | now_lo) & gmask);
-      const uint32_t w_next = (uint32_t)__popcll((((uint64_t)nx_hi << 32) | nx_lo) & gmask);
+    lds_barrier();
+    if (threadIdx.x < in_batch) {
+      const uint64_t gid = base + threadIdx.x;
+      const uint32_t ucount = s_U[threadIdx.x];
+      const double up = *up_p;
+      const double G = (double)geo.G;
       // Eq9, operation by operation, no contraction (built with -ffp-contract=off)
       const double num = (double)ucount - G * up;
       const double den = G * (1.0 - up);
@@ -440,27 +482,15 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
         }
       }
       if (e >= (double)geo.theta) fl |= 1u;
-      if (w_next >= geo.t_re) fl |= 8u;   // carried by Algorithm 3
-      s_est[local] = e;
-      s_ip[local] = a;
-      s_U[local] = ucount;
-      s_W[local] = (uint8_t)w_now;
-      s_f[local] = fl;
-    }
-  }
-  lds_barrier();
-  if (threadIdx.x < kEstPerBlock) {
-    const uint64_t gid = base + threadIdx.x;
-    if (gid < n) {
-      cflags[gid] = s_f[threadIdx.x];
+      if (s_Wn[threadIdx.x] >= geo.t_re) fl |= 8u;   // carried by Algorithm 3
+      cflags[gid] = fl;
       out_ip[gid] = s_ip[threadIdx.x];
-      out_est[gid] = s_est[threadIdx.x];
-      out_flags[gid] = s_f[threadIdx.x];
-      if (out_U) out_U[gid] = s_U[threadIdx.x];
+      out_est[gid] = e;
+      out_flags[gid] = fl;
+      if (out_U) out_U[gid] = ucount;
       if (out_W) out_W[gid] = s_W[threadIdx.x];
     }
-  }
-  lds_barrier();
+    lds_barrier();
   }
 }
 
@@ -468,17 +498,46 @@ static uint32_t est_lg_log2(const Geo& geo) {
   uint32_t need = geo.words > geo.u ? geo.words : geo.u;
   uint32_t l = 2;  // at least 4 lanes per candidate
   while ((1u << l) < need && l < 6) ++l;
-  return l;
+  return l;   // 2^l >= u, since u <= kMaxU <= 64
+}
+
+// One resident wave of blocks: every block then runs the same number of
+// grid-stride batches, instead of a second partial wave of blocks starting
+// after the first has finished (the kernel's register use allows fewer
+// blocks per CU than the pipeline's default grid).
+template <int kU>
+static uint32_t est_grid() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_estimate<kU>, (int)kBlock, 0) !=
+          hipSuccess ||
+      cus <= 0 || per_cu <= 0)
+    return 2 * kPipeBlocks;
+  return (uint32_t)cus * (uint32_t)per_cu;
+}
+
+template <int kU>
+static hipError_t launch_estimate_u(const uint32_t* csip, const Counters* cnt,
+                                    const uint64_t* bitmap, const uint64_t* act, const double* up,
+                                    const Geo& geo, uint32_t l, uint8_t* cflags,
+                                    const ReportPtrs& out, hipStream_t st) {
+  static const uint32_t grid = est_grid<kU>();
+  hipLaunchKernelGGL(k_estimate<kU>, dim3(grid), dim3(kBlock), 0, st, csip, cnt, bitmap, act, up,
+                     geo, l, cflags, out.ip, out.est, out.flags, out.U, out.W);
+  return hipGetLastError();
 }
 
 hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
                            const uint64_t* act, const double* up,
                            const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_estimate, dim3(2 * kPipeBlocks), dim3(kBlock), 0, st, csip, cnt, bitmap,
-                     act, up, geo, est_lg_log2(geo), cflags, out.ip, out.est,
-                     out.flags, out.U, out.W);
-  return hipGetLastError();
+  static_assert(kMaxU <= 16, "k_estimate is unrolled for at most 16 rows");
+  const uint32_t l = est_lg_log2(geo);
+  if (geo.u > (1u << l)) return hipErrorInvalidValue;
+  if (geo.u <= 4) return launch_estimate_u<4>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
+  if (geo.u <= 8) return launch_estimate_u<8>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
+  return launch_estimate_u<16>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
 }
 
 // ------------------------------------------------------------------ SI
