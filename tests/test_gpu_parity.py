@@ -594,3 +594,14 @@ def test_overlap_report_backbone_full_size_streaming():
     stream, mon, _ = workload("backbone")
     _run_streaming(stream, mon, range(3), max_candidates=1 << 22, graph=True,
                    overlap_report=True)
+
+
+def test_group_rejects_overlapped_report_monitors():
+    stream, mon, _ = workload("tiny")
+    st = torch.cuda.Stream()
+    a = srla.Monitor(**mon, max_candidates=1 << 10, stream=st)
+    b = srla.Monitor(**mon, max_candidates=1 << 10, stream=st, overlap_report=True)
+    with pytest.raises(srla.SrlaError):
+        srla.Group([a, b])
+    a.close()
+    b.close()
