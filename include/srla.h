@@ -74,8 +74,11 @@ enum {
                                   already holds the open slice's stamp is not
                                   stored again (DRset is idempotent).  Results
                                   are identical; faster when pairs repeat DRs
-                                  often.  Takes precedence over
-                                  SRLA_CFG_SCAN_XCD */
+                                  often.  With SRLA_CFG_SCAN_XCD as well, each
+                                  XCD reads and stamps only its own rows
+                                  (u in {1, 2, 4, 8, 16} and 16-byte aligned
+                                  device pairs; otherwise the flat
+                                  read-before-write form) */
     SRLA_CFG_SCAN_LDS_FILTER = 64, /* scan with a workgroup filter of repeated
                                   stores: each workgroup keeps the LE DRs it
                                   stored last in an LDS table and skips

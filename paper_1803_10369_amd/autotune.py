@@ -2,7 +2,8 @@
 
 The scan (Algorithm 2) has two knobs that never change its results: the
 kernel form (flat; per-XCD row ownership, SRLA_CFG_SCAN_XCD; read-before-write,
-SRLA_CFG_SCAN_DEDUP; a workgroup filter of repeated stores, SRLA_CFG_SCAN_LDS_FILTER) and the
+SRLA_CFG_SCAN_DEDUP; both, per-XCD read-before-write; a workgroup filter of repeated
+stores, SRLA_CFG_SCAN_LDS_FILTER) and the
 cap on its workgroups (srla_config_t.scan_blocks).
 tune_scan() times every candidate on a scratch monitor of the caller's
 geometry with the caller's pairs, one scan per slice (each timed scan meets
@@ -72,7 +73,8 @@ def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False
     results = {}
     for form, blocks in candidates or DEFAULT_CANDIDATES:
         m = srla.Monitor(**cfg, max_candidates=min(1 << 22, 4 * n_pairs + 64), timing=True,
-                         scan_xcd=form == "xcd", scan_dedup=form == "dedup",
+                         scan_xcd=form in ("xcd", "xcd_dedup"),
+                         scan_dedup=form in ("dedup", "xcd_dedup"),
                          scan_lds_filter=form == "filter",
                          scan_blocks=blocks, lean_report=True)
         m.scan(bufs[0])                  # warm the footprint
@@ -87,7 +89,8 @@ def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False
         results["%s/%d" % (form, blocks)] = ms / repeats
     best = min(results, key=results.get)
     form, blocks = best.split("/")
-    choice = {"scan_xcd": form == "xcd", "scan_dedup": form == "dedup",
+    choice = {"scan_xcd": form in ("xcd", "xcd_dedup"),
+              "scan_dedup": form in ("dedup", "xcd_dedup"),
               "scan_lds_filter": form == "filter",
               "scan_blocks": int(blocks), "ms": results[best], "all": results}
     if cache:

@@ -707,7 +707,7 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
                             m->stream);
   if (m->dedup_scan)
     return launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
-                             m->tcount + p, m->cfg.scan_blocks, m->stream);
+                             m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream);
   if (m->filter_scan)
     return launch_scan_lds_filter(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                                   m->tcount + p, m->cfg.scan_blocks, m->stream);

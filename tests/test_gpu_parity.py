@@ -56,10 +56,13 @@ def test_tiny_workload_full_run(scan_xcd, graph):
     assert r.window_full and r.n > 0
 
 
-@pytest.mark.parametrize("scan_xcd,blocks", [(False, 7), (True, 16), (True, 5)])
-def test_scan_grid_cap_strides_over_all_pairs(scan_xcd, blocks):
+@pytest.mark.parametrize("scan_xcd,blocks,dedup", [(False, 7, False), (True, 16, False),
+                                                    (True, 5, False), (True, 24, True),
+                                                    (True, 3, True)])
+def test_scan_grid_cap_strides_over_all_pairs(scan_xcd, blocks, dedup):
     stream, mon, n = workload("tiny")
-    g = srla.Monitor(**mon, max_candidates=1 << 16, scan_xcd=scan_xcd, scan_blocks=blocks)
+    g = srla.Monitor(**mon, max_candidates=1 << 16, scan_xcd=scan_xcd, scan_blocks=blocks,
+                     scan_dedup=dedup)
     o = oracle.Monitor(**mon)
     for s in range(6):
         p = stream.slice(s)
@@ -532,6 +535,42 @@ def test_dedup_scan_backbone_expiry_and_full_size_prefix():
          scan_dedup=True)
     stream, mon, _ = workload("backbone")
     _run(stream, mon, range(3), max_candidates=1 << 22, dump_every=0, scan_dedup=True)
+
+
+# SRLA_CFG_SCAN_DEDUP with SRLA_CFG_SCAN_XCD: each XCD reads and stamps only its
+# own rows (u in {1, 2, 4, 8, 16}; other u and unaligned input fall back).
+
+@pytest.mark.parametrize("case", SMALL)
+def test_xcd_dedup_scan_small_geometries(case):
+    k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
+    mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=5100 + k + u)
+    _run(_rand_stream(k + u + 4, n, n_src, 3 * theta // 2), mon, range(slices), scan_dedup=True,
+         scan_xcd=True)
+
+
+def test_xcd_dedup_scan_tiny_host_input_and_streaming():
+    stream, mon, n = workload("tiny")
+    _run(stream, mon, range(n), scan_dedup=True, scan_xcd=True, host=True, split=40001)
+    _run(stream, mon, range(n), scan_dedup=True, scan_xcd=True, split=33333)
+    g = srla.Monitor(**mon, max_candidates=1 << 16, graph=True, scan_dedup=True, scan_xcd=True)
+    o = oracle.Monitor(**mon)
+    for s in range(n):
+        p = stream.slice(s)
+        for lo in range(0, len(p), 50000):
+            g.scan(to_device(p[lo:lo + 50000]))
+        o.scan(p)
+        compare_reports(g.estimate(), o.estimate(), mon["theta"], "slice %d" % s)
+    compare_dumps(g, o)
+    g.close()
+
+
+def test_xcd_dedup_scan_backbone_expiry_and_full_size_prefix():
+    stream, mon, _ = workload("backbone_k16")
+    _run(scaled(stream, 600_000), mon, range(40), max_candidates=1 << 22, dump_every=13,
+         scan_dedup=True, scan_xcd=True)
+    stream, mon, _ = workload("backbone")
+    _run(stream, mon, range(3), max_candidates=1 << 22, dump_every=0, scan_dedup=True,
+         scan_xcd=True)
 
 
 # ------------------------------------------------------------ workgroup store filter
