@@ -369,10 +369,11 @@ hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
 //
 // A block takes 256 candidates at a time.  Their addresses are staged in LDS
 // first; then a group of 2^lg_log2 lanes owns one candidate: every lane hashes
-// the address for all u rows in registers and issues its u bitmap loads (the
-// group's 16 lanes read one 128-byte line per row when G = 1024) and, for the
-// lane whose index is a row number, that row's SRE load, all before the first
-// wait, so a candidate costs one cache round trip rather than one per row.
+// the address for all u rows in registers and issues its u bitmap loads of
+// kWpl words each (with G = 1024, eight lanes read one 128-byte line per row
+// in 16-byte pieces) and, for the lane whose index is a row number, that
+// row's SRE load, all before the first wait, so a candidate costs one cache
+// round trip rather than one per row.
 // Cross-lane shuffles reduce the group; the counts go to LDS.  Eq9 then runs
 // with one thread per candidate, and the report entries leave with one
 // coalesced store per array (into pinned host memory mapped into the GPU's
@@ -391,9 +392,10 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// kU >= geo.u is the unrolled row count; the launch guarantees 2^lg_log2 >= u
+// kU >= geo.u is the unrolled row count; kWpl (1 or 2) bitmap words per lane
+// and load, 2 only when G / 64 is even; the launch guarantees 2^lg_log2 >= u
 // (each lane handles at most one SRE row).
-template <int kU>
+template <int kU, int kWpl>
 __global__ __launch_bounds__(kBlock) void k_estimate(
     const uint32_t* __restrict__ csip, const Counters* __restrict__ cnt,
     const uint64_t* __restrict__ bitmap, const uint64_t* __restrict__ act,
@@ -428,18 +430,36 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
       SreWords sw;
       if (sre_lane) sw = sre_fetch(act, geo, sub, hrange(my_h, geo.v_re));
       if (valid) {
-        for (uint32_t x = sub; x < geo.words; x += lg) {
-          uint64_t w[kU];
+        for (uint32_t x = kWpl * sub; x < geo.words; x += kWpl * lg) {
+          if constexpr (kWpl == 2) {
+            uint4 w[kU];
 #pragma unroll
-          for (int r = 0; r < kU; ++r)
-            w[r] = r < (int)geo.u
-                       ? bitmap[((uint64_t)r * geo.v_le + hrange(mas(geo.rh[r], a), geo.v_le)) *
-                                    geo.words + x]
-                       : ~0ull;
-          uint64_t acc = ~0ull;
+            for (int r = 0; r < kU; ++r)
+              w[r] = r < (int)geo.u
+                         ? *reinterpret_cast<const uint4*>(
+                               bitmap + ((uint64_t)r * geo.v_le +
+                                         hrange(mas(geo.rh[r], a), geo.v_le)) * geo.words + x)
+                         : make_uint4(~0u, ~0u, ~0u, ~0u);
+            uint32_t acc[4] = {~0u, ~0u, ~0u, ~0u};
 #pragma unroll
-          for (int r = 0; r < kU; ++r) acc &= w[r];
-          ucount += (uint32_t)__popcll(acc);
+            for (int r = 0; r < kU; ++r) {
+              acc[0] &= w[r].x; acc[1] &= w[r].y; acc[2] &= w[r].z; acc[3] &= w[r].w;
+            }
+            ucount += (uint32_t)(__popc(acc[0]) + __popc(acc[1]) + __popc(acc[2]) +
+                                 __popc(acc[3]));
+          } else {
+            uint64_t w[kU];
+#pragma unroll
+            for (int r = 0; r < kU; ++r)
+              w[r] = r < (int)geo.u
+                         ? bitmap[((uint64_t)r * geo.v_le + hrange(mas(geo.rh[r], a), geo.v_le)) *
+                                      geo.words + x]
+                         : ~0ull;
+            uint64_t acc = ~0ull;
+#pragma unroll
+            for (int r = 0; r < kU; ++r) acc &= w[r];
+            ucount += (uint32_t)__popcll(acc);
+          }
         }
       }
       if (sre_lane) sre_combine(sw, geo.g, &m_now, &m_next);
@@ -494,8 +514,11 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
   }
 }
 
+static uint32_t est_wpl(const Geo& geo) { return geo.words % 2 == 0 ? 2u : 1u; }
+
 static uint32_t est_lg_log2(const Geo& geo) {
-  uint32_t need = geo.words > geo.u ? geo.words : geo.u;
+  const uint32_t pieces = geo.words / est_wpl(geo);
+  const uint32_t need = pieces > geo.u ? pieces : geo.u;
   uint32_t l = 2;  // at least 4 lanes per candidate
   while ((1u << l) < need && l < 6) ++l;
   return l;   // 2^l >= u, since u <= kMaxU <= 64
@@ -505,27 +528,37 @@ static uint32_t est_lg_log2(const Geo& geo) {
 // grid-stride batches, instead of a second partial wave of blocks starting
 // after the first has finished (the kernel's register use allows fewer
 // blocks per CU than the pipeline's default grid).
-template <int kU>
+template <int kU, int kWpl>
 static uint32_t est_grid() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_estimate<kU>, (int)kBlock, 0) !=
-          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_estimate<kU, kWpl>, (int)kBlock,
+                                                   0) != hipSuccess ||
       cus <= 0 || per_cu <= 0)
     return 2 * kPipeBlocks;
   return (uint32_t)cus * (uint32_t)per_cu;
 }
 
-template <int kU>
+template <int kU, int kWpl>
 static hipError_t launch_estimate_u(const uint32_t* csip, const Counters* cnt,
                                     const uint64_t* bitmap, const uint64_t* act, const double* up,
                                     const Geo& geo, uint32_t l, uint8_t* cflags,
                                     const ReportPtrs& out, hipStream_t st) {
-  static const uint32_t grid = est_grid<kU>();
-  hipLaunchKernelGGL(k_estimate<kU>, dim3(grid), dim3(kBlock), 0, st, csip, cnt, bitmap, act, up,
-                     geo, l, cflags, out.ip, out.est, out.flags, out.U, out.W);
+  static const uint32_t grid = est_grid<kU, kWpl>();
+  hipLaunchKernelGGL((k_estimate<kU, kWpl>), dim3(grid), dim3(kBlock), 0, st, csip, cnt, bitmap,
+                     act, up, geo, l, cflags, out.ip, out.est, out.flags, out.U, out.W);
   return hipGetLastError();
+}
+
+template <int kU>
+static hipError_t launch_estimate_w(const uint32_t* csip, const Counters* cnt,
+                                    const uint64_t* bitmap, const uint64_t* act, const double* up,
+                                    const Geo& geo, uint32_t l, uint8_t* cflags,
+                                    const ReportPtrs& out, hipStream_t st) {
+  if (est_wpl(geo) == 2)
+    return launch_estimate_u<kU, 2>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
+  return launch_estimate_u<kU, 1>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
 }
 
 hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
@@ -535,9 +568,9 @@ hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint
   static_assert(kMaxU <= 16, "k_estimate is unrolled for at most 16 rows");
   const uint32_t l = est_lg_log2(geo);
   if (geo.u > (1u << l)) return hipErrorInvalidValue;
-  if (geo.u <= 4) return launch_estimate_u<4>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
-  if (geo.u <= 8) return launch_estimate_u<8>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
-  return launch_estimate_u<16>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
+  if (geo.u <= 4) return launch_estimate_w<4>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
+  if (geo.u <= 8) return launch_estimate_w<8>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
+  return launch_estimate_w<16>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
 }
 
 // ------------------------------------------------------------------ SI
