@@ -11,8 +11,10 @@ memory before each timed segment starts.
 --mode streaming (default): slice t's candidate check and estimate run first
   (into device memory), then the scan of slice t+1 runs on the GPU while the
   report of slice t is copied to host memory (two HIP streams, the
-  end-of-slice pipeline replayed as HIP graphs); the latency is the host time
-  from closing slice t to its report.
+  end-of-slice pipeline replayed as HIP graphs; the host closes slice t+1
+  before it collects the report of slice t); the latency is the device time
+  from the start of slice t's end-of-slice work, right after its last scan,
+  to its report in host memory.
 --mode plain: each slice is scanned, then estimated; the latency is the host
   time from the end of the slice's scan to its report.
 
@@ -570,17 +572,19 @@ def main():
                 r = m.estimate(copy=False)   # returns with the report in host memory
                 lat.append((time.perf_counter() - ts) * 1e3)
         else:
+            # the host runs one slice ahead: slice i is scanned and closed before
+            # the report of slice i-1 is collected (two reports may be pending);
+            # the latency is the device's own, from the start of a slice's
+            # end-of-slice work, right after its last scan, to its report in
+            # host memory
             m.scan(seg_bufs[0])
             m.close_slice()
-            t_close = time.perf_counter()
             for i in range(1, seg + 1):
                 if i < seg:
                     m.scan(seg_bufs[i])      # runs while slice i-1 is estimated
-                r = m.wait_report(copy=False)
-                lat.append((time.perf_counter() - t_close) * 1e3)
-                if i < seg:
                     m.close_slice()
-                    t_close = time.perf_counter()
+                r = m.wait_report(copy=False)
+                lat.append(r.latency_ms)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         total_s += t1 - t0

@@ -142,8 +142,9 @@ typedef struct srla_monitor srla_monitor_t;
 /*
  * The report of one closed slice e, covering the window [e-k+1, e]
  * (window_full == 0 while e < k-1).  Arrays are pinned host memory owned by
- * the library, written by its kernels; they stay valid until the next
- * srla_close_slice (or srla_estimate) or srla_destroy.
+ * the library, written by its kernels (two sets, used by alternate slices);
+ * they stay valid until slice e+2 is closed (srla_close_slice or
+ * srla_estimate) or srla_destroy.
  *   ip            the candidate list CSIP (Algorithms 2-3), ascending
  *   est           Eq9 estimate of |OP(ip, e-k+1, k)| (FP64; +inf with SAT)
  *   flags         SRLA_FLAG_* of each candidate
@@ -154,6 +155,9 @@ typedef struct srla_monitor srla_monitor_t;
  *   up            Eq8
  *   n_touched     distinct sources with at least one SRE-sampled pair in e
  *   n_new         candidates inserted in e
+ *   latency_ms    device time from the start of e's end-of-slice work (on
+ *                 the monitor's stream, right after e's last scan) until the
+ *                 report was complete in host memory (device wall clock)
  */
 typedef struct {
     uint64_t slice;
@@ -168,6 +172,7 @@ typedef struct {
     double up;
     uint64_t n_touched;
     uint64_t n_new;
+    double latency_ms;
 } srla_report_t;
 
 /* Accumulated stage times (milliseconds, HIP events on the stream each stage
@@ -257,12 +262,16 @@ int srla_estimate(srla_monitor_t *m, srla_report_t *out);
  * Streaming form of srla_estimate.  srla_close_slice closes the open slice e
  * without waiting: it enqueues e's end-of-slice work and opens slice e+1 at
  * once.  Scans of e+1 may be issued right away; on the device they start as
- * soon as e's DRs have been snapshotted (the LE/SRE activity sweeps), and run
- * while e is still being estimated.  srla_wait_report then blocks until e's
- * report is in host memory and fills *out.  Every closed slice must be
- * collected before the next srla_close_slice (SRLA_E_STATE otherwise).
- * Results are identical to srla_estimate's.  Errors as for srla_estimate;
- * SRLA_E_CAPACITY is reported by srla_wait_report.
+ * soon as e's DRs have been snapshotted (the LE/SRE activity sweeps, which
+ * run on the monitor's stream right after e's scans), and run while e is
+ * still being estimated.  srla_wait_report blocks until the report of the
+ * oldest closed slice not yet collected is in host memory and fills *out.
+ * At most two closed slices may wait for collection: e+1 may be closed before
+ * e's report is collected, so the caller can issue a slice's close ahead of
+ * waiting for the previous report; a third close returns SRLA_E_STATE.
+ * srla_estimate requires that no report is waiting.  Results are identical
+ * to srla_estimate's.  Errors as for srla_estimate; SRLA_E_CAPACITY is
+ * reported by srla_wait_report.
  */
 int srla_close_slice(srla_monitor_t *m);
 int srla_wait_report(srla_monitor_t *m, srla_report_t *out);

@@ -85,6 +85,7 @@ struct PipeState {
   uint32_t now;          // stamp code of the slice being closed
   uint32_t n_ncsip;      // |NCSIP| carried into it
   uint64_t slice;        // its index
+  uint64_t t_close;      // device wall clock when its end-of-slice work began
 };
 
 // Pinned host block the status kernel fills at the end of every slice.
@@ -93,6 +94,8 @@ struct HostStatus {
   double up;
   unsigned long long row_fill[kMaxU];
   uint64_t slice;
+  uint64_t t_close;      // device wall clock: end-of-slice work began
+  uint64_t t_done;       //   and the report was complete in host memory
 };
 
 // Report arrays in pinned host memory, as device-visible pointers.
@@ -192,6 +195,8 @@ hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const C
 // publishes the slice's counters, Eq8 and row fills to the host, carries
 // |NCSIP| into the state, advances the state to the next slice, and clears
 // the slice's counters (and the sampled-source count of its parity)
+// records the device wall clock at the start of the end-of-slice work
+hipError_t launch_mark_close(PipeState* ps, hipStream_t st);
 hipError_t launch_status(Counters* cnt, uint32_t* tcount, const double* up,
                          const unsigned long long* row_fill, uint32_t u, PipeState* ps,
                          HostStatus* out, hipStream_t st);

@@ -56,13 +56,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
   uint64_t* bmp = bitmap + (uint64_t)row * (row_cells / 64);
   const uint32_t lane = threadIdx.x & (kWave - 1);
   uint32_t count = 0;
+  // every step's load first (a lane past the row's end reads the row's first
+  // 8 DRs and ignores them), so the block has all its loads in flight at once
+  uint4 qs[kSweepSteps];
+#pragma unroll
+  for (int s = 0; s < kSweepSteps; ++s) {
+    const uint64_t c8 = ((uint64_t)blockIdx.x * kSweepTile) + ((uint64_t)s * kBlock + threadIdx.x) * 8;
+    qs[s] = *reinterpret_cast<const uint4*>(rowp + (c8 < row_cells ? c8 : 0));
+  }
 #pragma unroll
   for (int s = 0; s < kSweepSteps; ++s) {
     const uint64_t c8 = ((uint64_t)blockIdx.x * kSweepTile) + ((uint64_t)s * kBlock + threadIdx.x) * 8;
     const bool valid = c8 < row_cells;
     uint32_t m8 = 0;
     if (valid) {
-      uint4 q = *reinterpret_cast<const uint4*>(rowp + c8);
+      const uint4 q = qs[s];
       uint32_t w[4] = {q.x, q.y, q.z, q.w};
       bool dirty = false;
 #pragma unroll
@@ -189,9 +197,10 @@ hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act, const Geo& g
 // The g "now" and g "next" activity bits of the SRE in row r, column col
 // (g <= 64) from the interleaved map, in two steps so that callers can issue
 // the loads early: sre_fetch reads the 16-byte word that holds the SRE's first
-// bit and the one after it (the map is allocated with a spare word, so this
-// stays in bounds); sre_combine extracts the bits, taking the second word
-// only when the SRE straddles a 64-bit boundary.
+// bit and, unless g divides 64 (then no SRE straddles two words), the one
+// after it (the map is allocated with a spare word, so this stays in bounds);
+// sre_combine extracts the bits, taking the second word only when the SRE
+// straddles a 64-bit boundary.
 struct SreWords {
   uint4 q0, q1;
   uint32_t sh;
@@ -203,7 +212,8 @@ __device__ __forceinline__ SreWords sre_fetch(const uint64_t* __restrict__ act, 
   const uint64_t w = off >> 6;
   SreWords s;
   s.q0 = reinterpret_cast<const uint4*>(act)[w];
-  s.q1 = reinterpret_cast<const uint4*>(act)[w + 1];
+  s.q1 = (64u % geo.g) != 0u ? reinterpret_cast<const uint4*>(act)[w + 1]
+                             : make_uint4(0u, 0u, 0u, 0u);
   s.sh = (uint32_t)(off & 63u);
   return s;
 }
@@ -244,6 +254,9 @@ __device__ __forceinline__ uint64_t si_slot(const Geo& geo, uint32_t r, uint32_t
 // a union DR is inside iff it is inside in every row) and its own bit of the
 // union SI (AND over rows) is still clear.  SI is as the previous slide left it.
 
+// kU >= geo.u: the rows are unrolled so that every row's SRE and SI loads are
+// in flight before the first is used.
+template <int kU>
 __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict__ sorted,
                                                     const uint32_t* __restrict__ n_dev,
                                                     const uint64_t* __restrict__ act,
@@ -263,14 +276,26 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict_
       uint8_t f = 0;
       if (first) {
         const uint32_t bit = hrange(mas(geo.h4, a), 16u);
+        SreWords sw[kU];
+        uint32_t si[kU];
+#pragma unroll
+        for (int r = 0; r < kU; ++r) {
+          if (r < (int)geo.u) {
+            const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
+            sw[r] = sre_fetch(act, geo, r, col);
+            si[r] = si_cnt[si_slot(geo, r, col, bit)];
+          }
+        }
         uint64_t ure = ~0ull;
         bool usi = true;
-        for (uint32_t r = 0; r < geo.u; ++r) {
-          const uint32_t col = hrange(mas(geo.rh[r], a), geo.v_re);
-          uint64_t now, next;
-          sre_bits(act, geo, r, col, &now, &next);
-          ure &= now;
-          usi = usi && si_cnt[si_slot(geo, r, col, bit)] != 0u;
+#pragma unroll
+        for (int r = 0; r < kU; ++r) {
+          if (r < (int)geo.u) {
+            uint64_t now, next;
+            sre_combine(sw[r], geo.g, &now, &next);
+            ure &= now;
+            usi = usi && si[r] != 0u;
+          }
         }
         f = ((uint32_t)__popcll(ure) >= geo.t_re && !usi) ? 1 : 0;
       }
@@ -284,8 +309,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict_
 hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const uint64_t* act,
                            const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(kPipeBlocks), dim3(kBlock), 0, st, sorted, n_dev, act,
-                     si_cnt, geo, mark, cnt);
+  if (geo.u <= 4)
+    hipLaunchKernelGGL(k_finalize<4>, dim3(kPipeBlocks), dim3(kBlock), 0, st, sorted, n_dev, act,
+                       si_cnt, geo, mark, cnt);
+  else if (geo.u <= 8)
+    hipLaunchKernelGGL(k_finalize<8>, dim3(kPipeBlocks), dim3(kBlock), 0, st, sorted, n_dev, act,
+                       si_cnt, geo, mark, cnt);
+  else
+    hipLaunchKernelGGL(k_finalize<16>, dim3(kPipeBlocks), dim3(kBlock), 0, st, sorted, n_dev,
+                       act, si_cnt, geo, mark, cnt);
   return hipGetLastError();
 }
 
@@ -337,8 +369,10 @@ __global__ __launch_bounds__(kBlock) void k_merge(const uint32_t* __restrict__ n
 hipError_t launch_merge(const uint32_t* ncsip, const PipeState* ps, const uint32_t* news,
                         Counters* cnt, uint64_t cap, uint32_t* csip, uint8_t* cflags,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_merge, dim3(kPipeBlocks), dim3(kBlock), 0, st, ncsip, ps, news, cnt, cap,
-                     csip, cflags);
+  // twice the pipeline grid: every CU full, so more of the binary searches'
+  // dependent loads are in flight at once
+  hipLaunchKernelGGL(k_merge, dim3(2 * kPipeBlocks), dim3(kBlock), 0, st, ncsip, ps, news, cnt,
+                     cap, csip, cflags);
   return hipGetLastError();
 }
 
@@ -628,6 +662,8 @@ __global__ void k_status(Counters* __restrict__ cnt, uint32_t* __restrict__ tcou
   if (t == 0) {
     out->up = *up;
     out->slice = ps->slice;
+    out->t_close = ps->t_close;
+    out->t_done = wall_clock64();   // every earlier kernel of the report has finished
   }
   __syncthreads();
   if (t == 0) {
@@ -676,6 +712,15 @@ constexpr uint32_t kCopyBlocks = 128;
 hipError_t launch_report_copy(const Counters* cnt, const ReportPtrs& from, const ReportPtrs& to,
                               hipStream_t st) {
   hipLaunchKernelGGL(k_report_copy, dim3(kCopyBlocks), dim3(kBlock), 0, st, cnt, from, to);
+  return hipGetLastError();
+}
+
+__global__ void k_mark_close(PipeState* __restrict__ ps) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ps->t_close = wall_clock64();
+}
+
+hipError_t launch_mark_close(PipeState* ps, hipStream_t st) {
+  hipLaunchKernelGGL(k_mark_close, dim3(1), dim3(64), 0, st, ps);
   return hipGetLastError();
 }
 

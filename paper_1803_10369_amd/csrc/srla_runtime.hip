@@ -147,27 +147,29 @@ struct srla_monitor {
   uint32_t* cblockw = nullptr;
   uint64_t cap = 0;
 
-  // pinned host side (the report arrays and the status block are written by
-  // kernels through their device-visible addresses)
-  HostStatus* h_status = nullptr;
-  HostStatus* d_status = nullptr;
-  uint64_t* h_row_fill64 = nullptr;
-  uint32_t* h_ip = nullptr;
-  double* h_est = nullptr;
-  uint8_t* h_flags = nullptr;
-  uint32_t* h_U = nullptr;
-  uint8_t* h_W = nullptr;
-  ReportPtrs d_report{};
+  // pinned host side, one set per slice parity, so that a slice can be closed
+  // before the previous slice's report is collected (the report arrays and
+  // the status blocks are written by kernels through their device-visible
+  // addresses)
+  HostStatus* h_status[2] = {nullptr, nullptr};
+  HostStatus* d_status[2] = {nullptr, nullptr};
+  uint64_t* h_row_fill64[2] = {nullptr, nullptr};
+  uint32_t* h_ip[2] = {nullptr, nullptr};
+  double* h_est[2] = {nullptr, nullptr};
+  uint8_t* h_flags[2] = {nullptr, nullptr};
+  uint32_t* h_U[2] = {nullptr, nullptr};
+  uint8_t* h_W[2] = {nullptr, nullptr};
+  ReportPtrs d_report[2] = {};
   bool overlap_report = false;   // candidate work before the next slice's scans,
   ReportPtrs d_staging{};        // report staged here and copied while they run
 
-  // ordering between the two streams
-  hipEvent_t ev_scan = nullptr;   // after the closing slice's last scan
-  hipEvent_t ev_snap = nullptr;   // after its snapshot phase
-  hipEvent_t ev_done = nullptr;   // after its whole pipeline
-  bool snap_pending = false;      // the open slice's scans still have to wait ev_snap
-  bool report_pending = false;    // a closed slice whose report is not collected
-  bool finish_deferred = false;   // its report copy is not enqueued yet (overlap_report)
+  // ordering: the snapshot phase runs on the scan stream, in order with the
+  // scans; the second phase runs on the pipeline stream
+  hipEvent_t ev_snap = nullptr;                 // after the last closed slice's snapshot phase
+  hipEvent_t ev_done[2] = {nullptr, nullptr};   // after the whole pipeline, by slice parity
+  uint32_t n_pending = 0;         // closed slices whose reports are not collected (<= 2)
+  int clock_khz = 0;              // rate of the device wall clock
+  bool finish_deferred = false;   // the last closed slice's second phase is not enqueued yet
   hipEvent_t ev_go = nullptr;     // the next slice's first scan is about to start
 
   // replayable pipeline: [phase][parity]
@@ -264,6 +266,20 @@ uint32_t source_set_slots(uint64_t max_candidates) {
   return (uint32_t)s;
 }
 
+// A stream with a hardware queue of its own.  HIP spreads ordinary streams
+// over a small pool of hardware queues, so two streams of one process may land
+// on the same queue and then run one after the other; a stream created with
+// a CU mask is given its own queue.  The mask enables every CU (more bits than
+// the device has CUs; the extra ones are ignored).  Falls back to an ordinary
+// stream if the masked one cannot be created.
+hipError_t create_queue_stream(hipStream_t* st) {
+  const std::vector<uint32_t> all(32, 0xFFFFFFFFu);
+  if (hipExtStreamCreateWithCUMask(st, (uint32_t)all.size(), all.data()) == hipSuccess)
+    return hipSuccess;
+  (void)hipGetLastError();
+  return hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+}
+
 hipEvent_t pooled_event(srla_monitor* m) {
   if (!m->ev_pool.empty()) {
     hipEvent_t e = m->ev_pool.back();
@@ -290,15 +306,24 @@ void span_end(srla_monitor* m, hipStream_t st, int stage, hipEvent_t a) {
   m->spans.push_back({stage, a, b});
 }
 
-void collect_spans(srla_monitor* m) {
+// Adds the recorded spans to the stage totals: all of them (wait), or only
+// those already complete, so that collecting one slice's report never waits
+// for a later slice's work.
+void collect_spans(srla_monitor* m, bool wait) {
+  size_t kept = 0;
   for (auto& s : m->spans) {
+    if (!wait && hipEventQuery(s.b) == hipErrorNotReady) {
+      m->spans[kept++] = s;
+      continue;
+    }
     float ms = 0.f;
     if (hipEventSynchronize(s.b) == hipSuccess && hipEventElapsedTime(&ms, s.a, s.b) == hipSuccess)
       m->acc_ms[s.stage] += ms;
     m->ev_pool.push_back(s.a);
     m->ev_pool.push_back(s.b);
   }
-  m->spans.clear();
+  m->spans.resize(kept);
+  (void)hipGetLastError();   // a not-ready query leaves no error behind
 }
 
 void drop_graphs(srla_monitor* m) {
@@ -345,17 +370,18 @@ int reserve_touched(srla_monitor* m, uint64_t need) {
   return SRLA_OK;
 }
 
-// Enqueues one phase of the end-of-slice pipeline of parity p on the
-// pipeline stream.  Every argument is fixed per (phase, parity), so the
-// sequence can also be recorded once into a graph.
+// Enqueues one phase of the end-of-slice pipeline of parity p on stream st.
+// Every argument is fixed per (phase, parity), so the sequence can also be
+// recorded once into a graph.
 // The snapshot: |LDR(i)|^k, Eq8 and the activity maps of the closing slice.
-hipError_t enqueue_snapshot(srla_monitor* m, int p) {
+hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
   const Geo& geo = m->geo;
-  hipStream_t st = m->pipe;
   hipError_t e = hipSuccess;
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
+  e = launch_mark_close(m->ps, st);
+  if (e != hipSuccess) return e;
   if (m->discrete) {
     // the closing slice's bits are its activity maps already; the other
     // parity's (the previous slice's) are cleared for the next slice's scans
@@ -379,9 +405,8 @@ hipError_t enqueue_snapshot(srla_monitor* m, int p) {
 // The candidate work of the closing slice: candidate check of its sampled
 // sources, merge with the carried list, Eq9 for every candidate (report
 // entries to `out`), Algorithm 3's carried list and SI counters.
-hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out) {
+hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hipStream_t st) {
   const Geo& geo = m->geo;
-  hipStream_t st = m->pipe;
   hipError_t e = hipSuccess;
   uint32_t* tc = m->tcount + p;
   const uint64_t* le_act = m->discrete ? m->lebits[p] : m->bitmap;
@@ -414,46 +439,46 @@ hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out) {
   return e;
 }
 
-// Enqueues one phase of the end-of-slice pipeline of parity p on the
-// pipeline stream.  Every argument is fixed per (phase, parity), so the
-// sequence can also be recorded once into a graph.  The next slice's scans
-// wait for the first phase only.  Normally that is the snapshot, and the
+// The two phases of the end-of-slice pipeline of parity p.  The first runs
+// on the scan stream, right after the closing slice's scans, and the next
+// slice's scans follow it there.  Normally it is the snapshot, and the
 // candidate work and the report (written by the estimate kernel straight
-// into host memory) overlap those scans.  With SRLA_CFG_OVERLAP_REPORT the
-// first phase also does the candidate work, into device staging arrays, and
-// only the PCIe copy of the report (and the status) overlaps the scans.
-hipError_t enqueue_phase(srla_monitor* m, int phase, int p) {
-  hipStream_t st = m->pipe;
+// into host memory) follow on the pipeline stream, beside those scans.  With
+// SRLA_CFG_OVERLAP_REPORT the first phase also does the candidate work, into
+// device staging arrays, and only the PCIe copy of the report (and the
+// status) overlaps the scans.
+hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (phase == PH_SNAPSHOT) {
-    e = enqueue_snapshot(m, p);
-    if (e == hipSuccess && m->overlap_report) e = enqueue_candidates(m, p, m->d_staging);
+    e = enqueue_snapshot(m, p, st);
+    if (e == hipSuccess && m->overlap_report) e = enqueue_candidates(m, p, m->d_staging, st);
     return e;
   }
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
-  if (!m->overlap_report) e = enqueue_candidates(m, p, m->d_report);
+  if (!m->overlap_report) e = enqueue_candidates(m, p, m->d_report[p], st);
   if (spans) span_begin(m, st, &ta);
   if (e == hipSuccess && m->overlap_report)
-    e = launch_report_copy(m->cnt, m->d_staging, m->d_report, st);
+    e = launch_report_copy(m->cnt, m->d_staging, m->d_report[p], st);
   if (e == hipSuccess)
-    e = launch_status(m->cnt, m->tcount + p, m->up, m->row_fill, m->geo.u, m->ps, m->d_status,
+    e = launch_status(m->cnt, m->tcount + p, m->up, m->row_fill, m->geo.u, m->ps, m->d_status[p],
                       st);
   if (spans) span_end(m, st, ST_REPORT, ta);
   return e;
 }
 
-// Runs one phase: directly, or through its graph (recorded on first use).
-int run_phase(srla_monitor* m, int phase, int p) {
+// Runs one phase on stream st: directly, or through its graph (recorded on
+// first use, on the pipeline stream, and launched on st).
+int run_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
   if (!m->use_graph) {
-    HIP_TRY(m, enqueue_phase(m, phase, p));
+    HIP_TRY(m, enqueue_phase(m, phase, p, st));
     return SRLA_OK;
   }
   hipGraphExec_t& exec = m->graph[phase][p];
   if (!exec) {
     hipGraph_t g = nullptr;
     HIP_TRY(m, hipStreamBeginCapture(m->pipe, hipStreamCaptureModeThreadLocal));
-    const hipError_t e = enqueue_phase(m, phase, p);
+    const hipError_t e = enqueue_phase(m, phase, p, m->pipe);
     const hipError_t ec = hipStreamEndCapture(m->pipe, &g);
     HIP_TRY(m, e);
     HIP_TRY(m, ec);
@@ -461,7 +486,7 @@ int run_phase(srla_monitor* m, int phase, int p) {
     (void)hipGraphDestroy(g);
     HIP_TRY(m, ei);
   }
-  HIP_TRY(m, hipGraphLaunch(exec, m->pipe));
+  HIP_TRY(m, hipGraphLaunch(exec, st));
   return SRLA_OK;
 }
 
@@ -469,7 +494,7 @@ void release(srla_monitor* m) {
   if (!m) return;
   if (m->stream) (void)hipStreamSynchronize(m->stream);
   if (m->pipe) (void)hipStreamSynchronize(m->pipe);
-  collect_spans(m);
+  collect_spans(m, true);
   drop_graphs(m);
   dfree(m->le); dfree(m->re); dfree(m->si_cnt);
   for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); dfree(m->sset[i]); } dfree(m->bitmap); dfree(m->act);
@@ -481,9 +506,12 @@ void release(srla_monitor* m) {
   dfree(m->cblockw);
   dfree(m->d_staging.ip); dfree(m->d_staging.est); dfree(m->d_staging.flags);
   dfree(m->d_staging.U); dfree(m->d_staging.W);
-  hfree(m->h_status); hfree(m->h_ip); hfree(m->h_est); hfree(m->h_flags);
-  hfree(m->h_U); hfree(m->h_W);
-  delete[] m->h_row_fill64;
+  for (int q = 0; q < 2; ++q) {
+    hfree(m->h_status[q]); hfree(m->h_ip[q]); hfree(m->h_est[q]); hfree(m->h_flags[q]);
+    hfree(m->h_U[q]); hfree(m->h_W[q]);
+    delete[] m->h_row_fill64[q];
+    if (m->ev_done[q]) (void)hipEventDestroy(m->ev_done[q]);
+  }
   for (int i = 0; i < 2; ++i) {
     hfree(m->h_stage[i]);
     dfree(m->d_stage[i]);
@@ -491,9 +519,7 @@ void release(srla_monitor* m) {
     if (m->scanned_ev[i]) (void)hipEventDestroy(m->scanned_ev[i]);
   }
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
-  if (m->ev_scan) (void)hipEventDestroy(m->ev_scan);
   if (m->ev_snap) (void)hipEventDestroy(m->ev_snap);
-  if (m->ev_done) (void)hipEventDestroy(m->ev_done);
   if (m->ev_go) (void)hipEventDestroy(m->ev_go);
   if (m->pipe) (void)hipStreamDestroy(m->pipe);
   if (m->copy) {
@@ -590,9 +616,17 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     }
     m->own_stream = true;
   }
-  if (hipStreamCreateWithFlags(&m->pipe, hipStreamNonBlocking) != hipSuccess) {
+  // the pipeline stream runs beside the scan stream: a queue of its own
+  if (create_queue_stream(&m->pipe) != hipSuccess) {
     release(m);
     return SRLA_E_DEVICE;
+  }
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&m->clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+      m->clock_khz = 0;
+    (void)hipGetLastError();
   }
   m->n_le = (uint64_t)g.u * g.v_le * g.g_le;
   m->n_re = (uint64_t)g.u * g.v_re * g.g;
@@ -629,27 +663,29 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     if (!rc && !(cfg->flags & SRLA_CFG_LEAN_REPORT)) nomem(dalloc(&m->d_staging.U, m->cap));
     if (!rc && !(cfg->flags & SRLA_CFG_LEAN_REPORT)) nomem(dalloc(&m->d_staging.W, m->cap));
   }
-  if (!rc) nomem(halloc(&m->h_status, 1));
-  if (!rc) nomem(halloc(&m->h_ip, m->cap));
-  if (!rc) nomem(halloc(&m->h_est, m->cap));
-  if (!rc) nomem(halloc(&m->h_flags, m->cap));
   const bool weights = (cfg->flags & SRLA_CFG_LEAN_REPORT) == 0;
-  if (!rc && weights) nomem(halloc(&m->h_U, m->cap));
-  if (!rc && weights) nomem(halloc(&m->h_W, m->cap));
-  if (!rc) {
-    m->h_row_fill64 = new (std::nothrow) uint64_t[g.u];
-    if (!m->h_row_fill64) rc = SRLA_E_NOMEM;
+  for (int q = 0; q < 2 && !rc; ++q) {
+    nomem(halloc(&m->h_status[q], 1));
+    if (!rc) nomem(halloc(&m->h_ip[q], m->cap));
+    if (!rc) nomem(halloc(&m->h_est[q], m->cap));
+    if (!rc) nomem(halloc(&m->h_flags[q], m->cap));
+    if (!rc && weights) nomem(halloc(&m->h_U[q], m->cap));
+    if (!rc && weights) nomem(halloc(&m->h_W[q], m->cap));
+    if (!rc) {
+      m->h_row_fill64[q] = new (std::nothrow) uint64_t[g.u];
+      if (!m->h_row_fill64[q]) rc = SRLA_E_NOMEM;
+    }
+    if (!rc && (dev_view(m->h_status[q], &m->d_status[q]) != hipSuccess ||
+                dev_view(m->h_ip[q], &m->d_report[q].ip) != hipSuccess ||
+                dev_view(m->h_est[q], &m->d_report[q].est) != hipSuccess ||
+                dev_view(m->h_flags[q], &m->d_report[q].flags) != hipSuccess ||
+                (weights && dev_view(m->h_U[q], &m->d_report[q].U) != hipSuccess) ||
+                (weights && dev_view(m->h_W[q], &m->d_report[q].W) != hipSuccess)))
+      rc = SRLA_E_DEVICE;
+    if (!rc && hipEventCreateWithFlags(&m->ev_done[q], hipEventDisableTiming) != hipSuccess)
+      rc = SRLA_E_DEVICE;
   }
-  if (!rc && (dev_view(m->h_status, &m->d_status) != hipSuccess ||
-              dev_view(m->h_ip, &m->d_report.ip) != hipSuccess ||
-              dev_view(m->h_est, &m->d_report.est) != hipSuccess ||
-              dev_view(m->h_flags, &m->d_report.flags) != hipSuccess ||
-              (weights && dev_view(m->h_U, &m->d_report.U) != hipSuccess) ||
-              (weights && dev_view(m->h_W, &m->d_report.W) != hipSuccess)))
-    rc = SRLA_E_DEVICE;
-  if (!rc && (hipEventCreateWithFlags(&m->ev_scan, hipEventDisableTiming) != hipSuccess ||
-              hipEventCreateWithFlags(&m->ev_snap, hipEventDisableTiming) != hipSuccess ||
-              hipEventCreateWithFlags(&m->ev_done, hipEventDisableTiming) != hipSuccess ||
+  if (!rc && (hipEventCreateWithFlags(&m->ev_snap, hipEventDisableTiming) != hipSuccess ||
               hipEventCreateWithFlags(&m->ev_go, hipEventDisableTiming) != hipSuccess))
     rc = SRLA_E_DEVICE;
   if (rc) {
@@ -715,26 +751,24 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
                      m->xcd_scan, m->cfg.scan_blocks, m->stream);
 }
 
-// Enqueues the second phase of the closed slice's pipeline (with
-// overlap_report: the report's copy to host memory, and the status) and its
-// completion event.  after_scan: the next slice's first scan is enqueued on
-// the scan stream right after this call, and the copy waits until that scan
-// is about to start.  A kernel that streams writes into host memory delays
-// the dispatch of kernels of other queues by hundreds of microseconds (the
+// Enqueues the second phase of the last closed slice's pipeline on the
+// pipeline stream, after its first phase, and its completion event.  go:
+// ev_go has been recorded on the scan stream in front of the next slice's
+// first scan, which is already enqueued there, and the second phase waits for
+// ev_go.  With the overlapped report its PCIe copy then starts once that scan
+// is under way: a kernel that streams writes into host memory delays the
+// dispatch of kernels of other queues by hundreds of microseconds (the
 // command processor reads queue packets and signals in host memory behind
-// those writes), so the scan has to be under way before the copy begins.
-int enqueue_finish(srla_monitor* m, bool after_scan) {
+// those writes), so the scan has to be dispatched before the copy begins.
+int enqueue_finish(srla_monitor* m, bool go) {
   const int pc = (int)((m->slice - 1) & 1);   // parity of the closed slice
-  if (after_scan) {
-    HIP_TRY(m, hipEventRecord(m->ev_go, m->stream));
-    HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_go, 0));
-  }
+  HIP_TRY(m, hipStreamWaitEvent(m->pipe, go ? m->ev_go : m->ev_snap, 0));
   hipEvent_t ta;
   if (m->use_graph) span_begin(m, m->pipe, &ta);
-  const int rc = run_phase(m, PH_FINISH, pc);
+  const int rc = run_phase(m, PH_FINISH, pc, m->pipe);
   if (rc) return rc;
   if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
-  HIP_TRY(m, hipEventRecord(m->ev_done, m->pipe));
+  HIP_TRY(m, hipEventRecord(m->ev_done[pc], m->pipe));
   m->finish_deferred = false;
   return SRLA_OK;
 }
@@ -761,15 +795,10 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   const int p = (int)(m->slice & 1);
   int rc = reserve_touched(m, m->slice_pairs[p] + n);
   if (rc) return rc;
-  if (m->snap_pending) {
-    // the previous slice's DRs must be snapshotted before this slice stamps them
-    HIP_TRY(m, hipStreamWaitEvent(m->stream, m->ev_snap, 0));
-    m->snap_pending = false;
-  }
-  if (m->finish_deferred) {
-    rc = enqueue_finish(m, true);
-    if (rc) return rc;
-  }
+  // the first scan after an overlapped close: the deferred second phase of the
+  // closed slice is enqueued behind it (see enqueue_finish)
+  bool go = m->finish_deferred;
+  if (go) HIP_TRY(m, hipEventRecord(m->ev_go, m->stream));
   if (on_device) {
     hipEvent_t a;
     span_begin(m, m->stream, &a);
@@ -778,12 +807,12 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     m->slice_pairs[p] += n;
     m->scan_launches++;
     m->scan_pairs += n;
-    return SRLA_OK;
+    return go ? enqueue_finish(m, true) : SRLA_OK;
   }
   // host input: chunk by chunk, H2D copies on the copy stream overlapping the
   // scans of earlier chunks on the scan stream
   if (!m->copy) {
-    if (hipStreamCreateWithFlags(&m->copy, hipStreamNonBlocking) != hipSuccess) {
+    if (create_queue_stream(&m->copy) != hipSuccess) {
       (void)hipGetLastError();
       return fail(m, SRLA_E_DEVICE, "cannot create the host-ingest stream");
     }
@@ -823,6 +852,11 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     span_begin(m, m->stream, &a);
     HIP_TRY(m, enqueue_scan(m, m->d_stage[b], cnt, p));
     span_end(m, m->stream, ST_SCAN, a);
+    if (go) {
+      rc = enqueue_finish(m, true);
+      if (rc) return rc;
+      go = false;
+    }
     HIP_TRY(m, hipEventRecord(m->scanned_ev[b], m->stream));
     m->scanned_set[b] = true;
     m->slice_pairs[p] += cnt;
@@ -839,27 +873,26 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
 int srla_close_slice(srla_monitor_t* m) {
   if (!m) return SRLA_E_INVAL;
   if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
-  if (m->report_pending)
-    return fail(m, SRLA_E_STATE, "the previous slice's report has not been collected");
+  if (m->n_pending >= 2)
+    return fail(m, SRLA_E_STATE, "the reports of two closed slices have not been collected");
   const int p = (int)(m->slice & 1);
-  if (m->snap_pending) {
-    // an empty slice: keep the stream order snapshot -> scans -> snapshot
-    HIP_TRY(m, hipStreamWaitEvent(m->stream, m->ev_snap, 0));
-    m->snap_pending = false;
+  // the previous slice's second phase is enqueued, and done with the pipeline
+  // state (counters, carried list, activity maps), before this snapshot
+  if (m->finish_deferred) {
+    const int rc = enqueue_finish(m, false);
+    if (rc) return rc;
   }
-  HIP_TRY(m, hipEventRecord(m->ev_scan, m->stream));
-  HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_scan, 0));
+  if (m->slice > 0) HIP_TRY(m, hipStreamWaitEvent(m->stream, m->ev_done[p ^ 1], 0));
   // with graphs, each phase is timed as a whole: the first as the sweeps
   // (with the candidate work when the report copy overlaps the next scans),
   // the second as the estimate (as the report copy when it overlaps)
   hipEvent_t ta;
-  if (m->use_graph) span_begin(m, m->pipe, &ta);
-  int rc = run_phase(m, PH_SNAPSHOT, p);
+  if (m->use_graph) span_begin(m, m->stream, &ta);
+  int rc = run_phase(m, PH_SNAPSHOT, p, m->stream);
   if (rc) return rc;
-  if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_ESTIMATE : ST_SWEEP, ta);
-  HIP_TRY(m, hipEventRecord(m->ev_snap, m->pipe));
-  m->snap_pending = true;
-  m->report_pending = true;
+  if (m->use_graph) span_end(m, m->stream, m->overlap_report ? ST_ESTIMATE : ST_SWEEP, ta);
+  HIP_TRY(m, hipEventRecord(m->ev_snap, m->stream));
+  m->n_pending++;
   m->slice++;
   m->slice_pairs[m->slice & 1] = 0;
   // with overlap_report the second phase waits for the next slice's first
@@ -874,41 +907,48 @@ int srla_close_slice(srla_monitor_t* m) {
 int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
   if (!m || !out) return m ? fail(m, SRLA_E_INVAL, "out is NULL") : SRLA_E_INVAL;
   if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
-  if (!m->report_pending) return fail(m, SRLA_E_STATE, "no closed slice is waiting");
-  if (m->finish_deferred) {
+  if (!m->n_pending) return fail(m, SRLA_E_STATE, "no closed slice is waiting");
+  // the oldest closed slice whose report is not collected yet
+  const int q = (int)((m->slice - m->n_pending) & 1);
+  if (m->finish_deferred && m->n_pending == 1) {
     const int rc = enqueue_finish(m, false);
     if (rc) return rc;
   }
-  HIP_TRY(m, hipEventSynchronize(m->ev_done));
-  m->report_pending = false;
-  const HostStatus& hs = *m->h_status;
+  HIP_TRY(m, hipEventSynchronize(m->ev_done[q]));
+  m->n_pending--;
+  const HostStatus& hs = *m->h_status[q];
   const Counters c = hs.cnt;
   if (c.overflow) {
     m->poisoned = true;
-    collect_spans(m);
+    collect_spans(m, false);
     return fail(m, SRLA_E_CAPACITY, "candidate list exceeds max_candidates");
   }
   m->estimates++;
-  if (m->timing) collect_spans(m);
+  if (m->timing) collect_spans(m, false);
   const Geo& geo = m->geo;
-  for (uint32_t i = 0; i < geo.u; ++i) m->h_row_fill64[i] = hs.row_fill[i];
+  for (uint32_t i = 0; i < geo.u; ++i) m->h_row_fill64[q][i] = hs.row_fill[i];
   out->slice = hs.slice;
   out->window_full = hs.slice >= (uint64_t)(geo.k - 1) ? 1u : 0u;
   out->n = c.n_cand;
-  out->ip = m->h_ip;
-  out->est = m->h_est;
-  out->flags = m->h_flags;
-  out->union_weight = m->h_U;
-  out->re_weight = m->h_W;
-  out->row_fill = m->h_row_fill64;
+  out->ip = m->h_ip[q];
+  out->est = m->h_est[q];
+  out->flags = m->h_flags[q];
+  out->union_weight = m->h_U[q];
+  out->re_weight = m->h_W[q];
+  out->row_fill = m->h_row_fill64[q];
   out->up = hs.up;
   out->n_touched = c.n_unique;
   out->n_new = c.n_new;
+  out->latency_ms = m->clock_khz > 0 && hs.t_done >= hs.t_close
+                        ? (double)(hs.t_done - hs.t_close) / (double)m->clock_khz
+                        : 0.0;
   return SRLA_OK;
 }
 
 int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
   if (!m || !out) return m ? fail(m, SRLA_E_INVAL, "out is NULL") : SRLA_E_INVAL;
+  if (m->n_pending)
+    return fail(m, SRLA_E_STATE, "an earlier closed slice's report has not been collected");
   const int rc = srla_close_slice(m);
   if (rc) return rc;
   return srla_wait_report(m, out);
@@ -973,7 +1013,7 @@ int srla_timings(srla_monitor_t* m, srla_timings_t* out, int reset) {
   if (!m || !out) return SRLA_E_INVAL;
   HIP_TRY(m, hipStreamSynchronize(m->stream));
   HIP_TRY(m, hipStreamSynchronize(m->pipe));
-  collect_spans(m);
+  collect_spans(m, true);
   out->scan_ms = m->acc_ms[ST_SCAN];
   out->scan_launches = m->scan_launches;
   out->scan_pairs = m->scan_pairs;
@@ -1054,11 +1094,6 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
     const int p = (int)(m->slice & 1);
     const int rc = reserve_touched(m, m->slice_pairs[p] + n);
     if (rc) return group_fail(g, rc, m->err);
-    if (m->snap_pending) {
-      const hipError_t e = hipStreamWaitEvent(g->stream, m->ev_snap, 0);
-      if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
-      m->snap_pending = false;
-    }
     GroupMember& gm = table[i];
     std::memset(&gm, 0, sizeof(gm));
     gm.geo = m->geo;

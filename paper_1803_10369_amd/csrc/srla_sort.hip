@@ -12,7 +12,7 @@
 
 namespace srla {
 
-constexpr int kItems = 16;
+constexpr int kItems = 4;   // small tiles: the slice's few 10^4 keys spread over many blocks
 constexpr uint64_t kTile = (uint64_t)kBlock * kItems;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kScanThreads = 1024;
@@ -48,26 +48,53 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds16, uint32_t* 
 }
 
 // In-place exclusive scan, by one block, of the first mult * tiles_of(*n_dev)
-// words of v; the grand total goes to *total_out when it is not null.
+// words of v; the grand total goes to *total_out when it is not null.  The
+// words go through LDS in chunks of kScanChunk: loaded and stored coalesced
+// (thread t takes words t, t + kScanThreads, ...), scanned as kScanPer
+// consecutive words per thread, with a running carry between chunks.
+constexpr int kScanPer = 16;
+constexpr uint64_t kScanChunk = (uint64_t)kScanThreads * kScanPer;   // 64 KiB of LDS
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_words(uint32_t* __restrict__ v,
                                                             const uint32_t* __restrict__ n_dev,
                                                             uint32_t mult,
                                                             uint32_t* __restrict__ total_out) {
   __shared__ uint32_t lds16[kScanThreads / kWave];
+  __shared__ uint32_t chunk[kScanChunk];
   const uint64_t n = (uint64_t)mult * tiles_of(*n_dev);
-  const uint64_t per = (n + kScanThreads - 1) / kScanThreads;
-  const uint64_t lo = per * threadIdx.x;
-  const uint64_t hi = lo + per < n ? lo + per : n;
-  uint32_t sum = 0;
-  for (uint64_t i = lo; i < hi; ++i) sum += v[i];
-  uint32_t total;
-  uint32_t run = block_exclusive_scan(sum, lds16, &total);
-  for (uint64_t i = lo; i < hi; ++i) {
-    const uint32_t x = v[i];
-    v[i] = run;
-    run += x;
+  uint32_t carry = 0;
+  for (uint64_t base = 0; base < n; base += kScanChunk) {
+    const uint64_t len = n - base < kScanChunk ? n - base : kScanChunk;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      const uint64_t i = (uint64_t)j * kScanThreads + threadIdx.x;
+      chunk[i] = i < len ? v[base + i] : 0u;
+    }
+    __syncthreads();
+    uint32_t x[kScanPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      x[j] = chunk[threadIdx.x * kScanPer + j];
+      sum += x[j];
+    }
+    uint32_t total;
+    uint32_t run = carry + block_exclusive_scan(sum, lds16, &total);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      chunk[threadIdx.x * kScanPer + j] = run;
+      run += x[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      const uint64_t i = (uint64_t)j * kScanThreads + threadIdx.x;
+      if (i < len) v[base + i] = chunk[i];
+    }
+    carry += total;
+    __syncthreads();
   }
-  if (threadIdx.x == 0 && total_out) *total_out = total;
+  if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
 // ------------------------------------------------------------------ radix sort

@@ -50,7 +50,7 @@ class srla_report_t(ctypes.Structure):
                 ("re_weight", ctypes.POINTER(ctypes.c_uint8)),
                 ("row_fill", ctypes.POINTER(ctypes.c_uint64)),
                 ("up", ctypes.c_double), ("n_touched", ctypes.c_uint64),
-                ("n_new", ctypes.c_uint64)]
+                ("n_new", ctypes.c_uint64), ("latency_ms", ctypes.c_double)]
 
 
 class srla_timings_t(ctypes.Structure):
@@ -204,7 +204,8 @@ class SrlaError(RuntimeError):
 
 class Report:
     """One slice's report as numpy arrays: copies, or (copy=False) views of the
-    library's report buffers that stay valid until the next estimate."""
+    library's report buffers, which stay valid until the slice two after this
+    one is closed."""
 
     def __init__(self, r, u, copy=True):
         n = r.n
@@ -229,6 +230,7 @@ class Report:
         self.up = r.up
         self.n_touched = r.n_touched
         self.n_new = r.n_new
+        self.latency_ms = r.latency_ms
 
 
 class Monitor:

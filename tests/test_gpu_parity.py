@@ -119,13 +119,17 @@ def test_small_geometries(case, scan_xcd, graph):
 
 
 def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chunks=1,
-                   discrete=False, scan_dedup=False, overlap_report=False):
-    """The next slice is scanned before the previous slice's report is taken."""
+                   discrete=False, scan_dedup=False, overlap_report=False, ahead=False):
+    """The next slice is scanned before the previous slice's report is taken;
+    ahead: it is also closed before that report is taken (two reports pending),
+    and a collected report's arrays (views, no copy) must hold until the slice
+    two after it is closed."""
     g = srla.Monitor(**mon, max_candidates=max_candidates, graph=graph, discrete=discrete,
                      scan_dedup=scan_dedup, overlap_report=overlap_report)
     o = oracle.Monitor(**mon)
     expected = []
     slices = list(slices)
+    held = None
     for i, s in enumerate(slices):
         pairs = stream.slice(s) if hasattr(stream, "slice") else stream(s)
         step = -(-len(pairs) // chunks) if len(pairs) else 1
@@ -133,18 +137,32 @@ def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chu
             g.scan(to_device(pairs[lo:lo + step]))
         o.scan(pairs)
         expected.append(o.estimate())
-        if i > 0:
-            compare_reports(g.wait_report(), expected[i - 1], mon["theta"], "slice %d" % (s - 1))
-        g.close_slice()
+        if ahead:
+            if held is not None:
+                # the report of slice s-2 (views) survived the close of s-1, its
+                # pipeline and the collection of its report: they use the other
+                # buffer set; the close of s below may overwrite it
+                compare_reports(held, expected[i - 2], mon["theta"], "held %d" % (s - 2))
+            g.close_slice()
+            if i > 0:
+                r = g.wait_report(copy=False)
+                compare_reports(r, expected[i - 1], mon["theta"], "slice %d" % (s - 1))
+                held = r
+        else:
+            if i > 0:
+                compare_reports(g.wait_report(), expected[i - 1], mon["theta"],
+                                "slice %d" % (s - 1))
+            g.close_slice()
     compare_reports(g.wait_report(), expected[-1], mon["theta"], "last slice")
     compare_dumps(g, o, ctx="end", discrete=discrete)
     g.close()
 
 
 @pytest.mark.parametrize("graph", [False, True])
-def test_streaming_form_matches_oracle(graph):
+@pytest.mark.parametrize("ahead", [False, True])
+def test_streaming_form_matches_oracle(graph, ahead):
     stream, mon, n = workload("tiny")
-    _run_streaming(stream, mon, range(n), graph=graph, chunks=3)
+    _run_streaming(stream, mon, range(n), graph=graph, chunks=3, ahead=ahead)
 
 
 @pytest.mark.parametrize("case", SMALL[:4])
@@ -162,14 +180,20 @@ def test_streaming_call_order_errors():
     assert e.value.rc == -4
     g.scan(to_device(stream.slice(0)))
     g.close_slice()
+    g.close_slice()                  # an empty slice 1; two reports pending
     with pytest.raises(srla.SrlaError) as e:
-        g.close_slice()
+        g.close_slice()              # a third is refused
     assert e.value.rc == -4
     with pytest.raises(srla.SrlaError) as e:
-        g.estimate()
+        g.estimate()                 # needs no report pending
     assert e.value.rc == -4
-    r = g.wait_report()
-    assert r.slice == 0
+    r0 = g.wait_report(copy=False)
+    r1 = g.wait_report(copy=False)
+    assert (r0.slice, r1.slice) == (0, 1)
+    assert r0.latency_ms > 0 and r1.latency_ms > 0
+    with pytest.raises(srla.SrlaError) as e:
+        g.wait_report()
+    assert e.value.rc == -4
     g.close()
 
 
@@ -438,11 +462,15 @@ def test_autotuner_picks_a_valid_shape_and_results_do_not_change(tmp_path):
     pairs = to_device(stream.slice(0))
     cache = str(tmp_path / "tune.json")
     choice = autotune.tune_scan(mon, pairs, repeats=2, cache=cache)
-    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "dedup/0", "filter/0",
-                                  "filter/512"}
+    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "dedup/0"}
     assert choice["ms"] == min(choice["all"].values()) > 0
     assert autotune.tune_scan(mon, pairs, cache=cache) == choice      # served from the cache
-    _run(stream, mon, range(6), scan_xcd=choice["scan_xcd"])
+    _run(stream, mon, range(6), scan_xcd=choice["scan_xcd"], scan_dedup=choice["scan_dedup"],
+         scan_lds_filter=choice["scan_lds_filter"])
+    # every form can still be asked for explicitly
+    forms = [("xcd", 0), ("xcd_dedup", 16), ("filter", 0)]
+    extra = autotune.tune_scan(mon, pairs, candidates=forms, repeats=1, cache=None)
+    assert set(extra["all"]) == {"xcd/0", "xcd_dedup/16", "filter/0"}
 
     st = torch.cuda.Stream()
     gms = [srla.Monitor(**mon, max_candidates=1 << 16, stream=st) for _ in range(2)]
@@ -607,6 +635,8 @@ def test_lds_filter_scan_repeats_and_full_size():
 def test_overlap_report_streaming_and_plain(graph):
     stream, mon, n = workload("tiny")
     _run_streaming(stream, mon, range(n), graph=graph, chunks=2, overlap_report=True)
+    _run_streaming(stream, mon, range(n), graph=graph, chunks=2, overlap_report=True,
+                   ahead=True)
     stream, mon, n = workload("tiny_coupled")
     g = srla.Monitor(**mon, max_candidates=1 << 16, graph=graph, overlap_report=True)
     o = oracle.Monitor(**mon)
@@ -624,15 +654,15 @@ def test_overlap_report_small_geometries_and_discrete(case):
     k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
     mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=8000 + k + u)
     _run_streaming(_rand_stream(k + u + 13, n, n_src, 3 * theta // 2), mon, range(slices),
-                   graph=True, overlap_report=True)
+                   graph=True, overlap_report=True, ahead=True)
     _run_streaming(_rand_stream(k + u + 14, n, n_src, 3 * theta // 2), dict(mon, k=1),
-                   range(slices), graph=True, discrete=True, overlap_report=True)
+                   range(slices), graph=True, discrete=True, overlap_report=True, ahead=True)
 
 
 def test_overlap_report_backbone_full_size_streaming():
     stream, mon, _ = workload("backbone")
     _run_streaming(stream, mon, range(3), max_candidates=1 << 22, graph=True,
-                   overlap_report=True)
+                   overlap_report=True, ahead=True)
 
 
 def test_group_rejects_overlapped_report_monitors():
