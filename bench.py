@@ -607,7 +607,7 @@ def main():
     scan_kernel = ("k_scan_dedup" if args.scan_dedup else
                    "k_scan_lds_filter" if args.scan_lds_filter else
                    "k_scan_xcd" if args.scan_xcd else "k_scan_flat")
-    stages = {k: tm[k] / args.steps for k in
+    stages = {k: tm[k] / max(1, tm["estimates"]) for k in
               ("scan_ms", "sweep_ms", "finalize_ms", "estimate_ms", "slide_ms", "report_ms")}
 
     out = {
@@ -656,7 +656,7 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(scan_kernel, args.workload),
             "bytes_per_pair": scan_bytes_per_pair(g["u"], tau),
-            "launch_ms": scan_ms,
+            "launch_ms": scan_ms, "launches_timed": tm["scan_launches"],
             "random_stores_per_s": g["u"] * (1 + 2.0 ** -tau) * n_pairs / (scan_ms * 1e-3),
         },
     }

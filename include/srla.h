@@ -94,7 +94,8 @@ enum {
                                   those scans -- enqueued by the next slice's
                                   first srla_scan, after that scan has
                                   started, or by srla_wait_report if it comes
-                                  first.  Results are identical; costs 13
+                                  first.  Results are identical; costs two
+                                  staging sets (by slice parity) of 13
                                   (lean) or 18 bytes of device memory per
                                   max_candidates.  Such monitors cannot join
                                   a group */
@@ -176,7 +177,11 @@ typedef struct {
 } srla_report_t;
 
 /* Accumulated stage times (milliseconds, HIP events on the stream each stage
-   runs on) since the last reset; all zero unless SRLA_CFG_TIMING was set.
+   runs on) since the last reset; all zero unless SRLA_CFG_TIMING was set (or
+   timing was switched on with srla_set_timing).  scan_launches and
+   scan_pairs count the scans whose time is included in scan_ms (fused group
+   scans are counted but not timed), estimates the closed slices whose
+   end-of-slice stages are included.
    With SRLA_CFG_GRAPH each of the two end-of-slice phases is timed as one:
    the sweeps (sweep_ms, or estimate_ms together with the candidate work when
    SRLA_CFG_OVERLAP_REPORT moves it there) and the rest (estimate_ms, or
@@ -291,6 +296,16 @@ int srla_dump_state(srla_monitor_t *m, int which, uint16_t *host_out, uint64_t c
 
 /* Stage times since the last reset (reset != 0 clears them after reading). */
 int srla_timings(srla_monitor_t *m, srla_timings_t *out, int reset);
+
+/*
+ * Switches the per-stage timing on (enabled != 0) or off for the calls that
+ * follow: scans issued and slices closed while it is on are timed (a closed
+ * slice's stages are timed as it was when it was closed).  Each timed stage
+ * costs two HIP event records on its stream, so a caller that needs the
+ * times but not for every slice can time a sample of the slices.  Totals
+ * are kept across switches.  Errors: SRLA_E_INVAL (NULL monitor).
+ */
+int srla_set_timing(srla_monitor_t *m, int enabled);
 
 /*
  * Monitor groups: many monitors -- each with its own window, DR geometry,

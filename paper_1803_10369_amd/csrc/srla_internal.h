@@ -183,22 +183,25 @@ hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint
                            const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
                            hipStream_t st);
 
-// copies the first cnt->n_cand report entries from device staging arrays to
-// the host arrays (U and W only where `to` has them)
-hipError_t launch_report_copy(const Counters* cnt, const ReportPtrs& from, const ReportPtrs& to,
+// copies the first *n report entries from device staging arrays to the host
+// arrays (U and W only where `to` has them)
+hipError_t launch_report_copy(const uint32_t* n, const ReportPtrs& from, const ReportPtrs& to,
                               hipStream_t st);
 
 // Algorithm 3's SI step on the per-bit counters (after the KEEP flags are final)
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
                             uint32_t* si_cnt, const Geo& geo, hipStream_t st);
 
-// publishes the slice's counters, Eq8 and row fills to the host, carries
-// |NCSIP| into the state, advances the state to the next slice, and clears
-// the slice's counters (and the sampled-source count of its parity)
 // records the device wall clock at the start of the end-of-slice work
 hipError_t launch_mark_close(PipeState* ps, hipStream_t st);
+// records the device wall clock once the report is complete in host memory
+hipError_t launch_mark_done(HostStatus* out, hipStream_t st);
+// publishes the slice's counters, Eq8 and row fills to the host (and the
+// candidate count to *report_n), carries |NCSIP| into the state, advances the
+// state to the next slice, and clears the slice's counters (and the
+// sampled-source count of its parity)
 hipError_t launch_status(Counters* cnt, uint32_t* tcount, const double* up,
                          const unsigned long long* row_fill, uint32_t u, PipeState* ps,
-                         HostStatus* out, hipStream_t st);
+                         HostStatus* out, uint32_t* report_n, hipStream_t st);
 
 }  // namespace srla

@@ -652,7 +652,8 @@ hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const C
 __global__ void k_status(Counters* __restrict__ cnt, uint32_t* __restrict__ tcount,
                          const double* __restrict__ up,
                          const unsigned long long* __restrict__ row_fill, uint32_t u,
-                         PipeState* __restrict__ ps, HostStatus* __restrict__ out) {
+                         PipeState* __restrict__ ps, HostStatus* __restrict__ out,
+                         uint32_t* __restrict__ report_n) {
   if (blockIdx.x != 0) return;
   const uint32_t t = threadIdx.x;
   Counters c = *cnt;
@@ -664,6 +665,7 @@ __global__ void k_status(Counters* __restrict__ cnt, uint32_t* __restrict__ tcou
     out->slice = ps->slice;
     out->t_close = ps->t_close;
     out->t_done = wall_clock64();   // every earlier kernel of the report has finished
+    if (report_n) *report_n = c.n_cand;
   }
   __syncthreads();
   if (t == 0) {
@@ -693,9 +695,9 @@ __device__ __forceinline__ void copy_bytes_16(const uint8_t* __restrict__ src,
   if (tail < bytes && t < 16) dst[tail] = src[tail];
 }
 
-__global__ __launch_bounds__(kBlock) void k_report_copy(const Counters* __restrict__ cnt,
+__global__ __launch_bounds__(kBlock) void k_report_copy(const uint32_t* __restrict__ n_p,
                                                        ReportPtrs from, ReportPtrs to) {
-  const uint64_t n = cnt->n_cand;
+  const uint64_t n = *n_p;
   copy_bytes_16((const uint8_t*)from.ip, (uint8_t*)to.ip, 4 * n);
   copy_bytes_16((const uint8_t*)from.est, (uint8_t*)to.est, 8 * n);
   copy_bytes_16(from.flags, to.flags, n);
@@ -709,9 +711,9 @@ __global__ __launch_bounds__(kBlock) void k_report_copy(const Counters* __restri
 // stream from starting until its own workgroups retire).
 constexpr uint32_t kCopyBlocks = 128;
 
-hipError_t launch_report_copy(const Counters* cnt, const ReportPtrs& from, const ReportPtrs& to,
+hipError_t launch_report_copy(const uint32_t* n, const ReportPtrs& from, const ReportPtrs& to,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_report_copy, dim3(kCopyBlocks), dim3(kBlock), 0, st, cnt, from, to);
+  hipLaunchKernelGGL(k_report_copy, dim3(kCopyBlocks), dim3(kBlock), 0, st, n, from, to);
   return hipGetLastError();
 }
 
@@ -724,10 +726,20 @@ hipError_t launch_mark_close(PipeState* ps, hipStream_t st) {
   return hipGetLastError();
 }
 
+__global__ void k_mark_done(HostStatus* __restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) out->t_done = wall_clock64();
+}
+
+hipError_t launch_mark_done(HostStatus* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mark_done, dim3(1), dim3(64), 0, st, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_status(Counters* cnt, uint32_t* tcount, const double* up,
                          const unsigned long long* row_fill, uint32_t u, PipeState* ps,
-                         HostStatus* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, cnt, tcount, up, row_fill, u, ps, out);
+                         HostStatus* out, uint32_t* report_n, hipStream_t st) {
+  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, cnt, tcount, up, row_fill, u, ps, out,
+                     report_n);
   return hipGetLastError();
 }
 

@@ -161,7 +161,8 @@ struct srla_monitor {
   uint8_t* h_W[2] = {nullptr, nullptr};
   ReportPtrs d_report[2] = {};
   bool overlap_report = false;   // candidate work before the next slice's scans,
-  ReportPtrs d_staging{};        // report staged here and copied while they run
+  ReportPtrs d_staging[2] = {};  // report staged here (by slice parity) and copied while
+  uint32_t* report_n = nullptr;  // they run; [2] entries in each staged report
 
   // ordering: the snapshot phase runs on the scan stream, in order with the
   // scans; the second phase runs on the pipeline stream
@@ -170,7 +171,6 @@ struct srla_monitor {
   uint32_t n_pending = 0;         // closed slices whose reports are not collected (<= 2)
   int clock_khz = 0;              // rate of the device wall clock
   bool finish_deferred = false;   // the last closed slice's second phase is not enqueued yet
-  hipEvent_t ev_go = nullptr;     // the next slice's first scan is about to start
 
   // replayable pipeline: [phase][parity]
   bool use_graph = false;
@@ -188,8 +188,10 @@ struct srla_monitor {
   bool scanned_set[2] = {false, false};
   int stage_next = 0;
 
-  // timing
+  // timing (switched per call by srla_set_timing); timed[p]: the slice of
+  // parity p was closed with timing on
   bool timing = false;
+  bool timed[2] = {false, false};
   bool xcd_scan = false;
   bool dedup_scan = false;
   bool filter_scan = false;
@@ -250,9 +252,19 @@ uint64_t candidate_bytes(uint64_t cap) {
 }
 
 // device staging of the report when its copy overlaps the next slice's scans
+// (two sets, by slice parity)
 uint64_t staging_bytes(const srla_config_t* cfg) {
   if (!(cfg->flags & SRLA_CFG_OVERLAP_REPORT)) return 0;
-  return cfg->max_candidates * ((cfg->flags & SRLA_CFG_LEAN_REPORT) ? 13 : 18);
+  return 2 * cfg->max_candidates * ((cfg->flags & SRLA_CFG_LEAN_REPORT) ? 13 : 18) + 8;
+}
+
+// Makes stream st wait for ev, unless the host already sees ev complete (a
+// wait costs the command processor a barrier packet even then).
+hipError_t wait_unless_done(hipStream_t st, hipEvent_t ev) {
+  const hipError_t q = hipEventQuery(ev);
+  if (q == hipSuccess) return hipSuccess;
+  (void)hipGetLastError();   // a not-ready query leaves no error behind
+  return hipStreamWaitEvent(st, ev, 0);
 }
 
 uint64_t bitmap_words(uint64_t cells) { return (cells + 63) / 64 + 1; }
@@ -442,27 +454,36 @@ hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hip
 // The two phases of the end-of-slice pipeline of parity p.  The first runs
 // on the scan stream, right after the closing slice's scans, and the next
 // slice's scans follow it there.  Normally it is the snapshot, and the
-// candidate work and the report (written by the estimate kernel straight
-// into host memory) follow on the pipeline stream, beside those scans.  With
-// SRLA_CFG_OVERLAP_REPORT the first phase also does the candidate work, into
-// device staging arrays, and only the PCIe copy of the report (and the
-// status) overlaps the scans.
+// candidate work, the report (written by the estimate kernel straight into
+// host memory) and the status follow on the pipeline stream, beside those
+// scans.  With SRLA_CFG_OVERLAP_REPORT the first phase also does the
+// candidate work, into the parity's device staging arrays, and the status,
+// and only the PCIe copy of the report overlaps the scans.
 hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (phase == PH_SNAPSHOT) {
-    e = enqueue_snapshot(m, p, st);
-    if (e == hipSuccess && m->overlap_report) e = enqueue_candidates(m, p, m->d_staging, st);
-    return e;
-  }
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
+  if (phase == PH_SNAPSHOT) {
+    e = enqueue_snapshot(m, p, st);
+    if (e == hipSuccess && m->overlap_report) {
+      e = enqueue_candidates(m, p, m->d_staging[p], st);
+      if (spans) span_begin(m, st, &ta);
+      if (e == hipSuccess)
+        e = launch_status(m->cnt, m->tcount + p, m->up, m->row_fill, m->geo.u, m->ps,
+                          m->d_status[p], m->report_n + p, st);
+      if (spans) span_end(m, st, ST_SLIDE, ta);
+    }
+    return e;
+  }
   if (!m->overlap_report) e = enqueue_candidates(m, p, m->d_report[p], st);
   if (spans) span_begin(m, st, &ta);
-  if (e == hipSuccess && m->overlap_report)
-    e = launch_report_copy(m->cnt, m->d_staging, m->d_report[p], st);
-  if (e == hipSuccess)
+  if (m->overlap_report) {
+    if (e == hipSuccess) e = launch_report_copy(m->report_n + p, m->d_staging[p], m->d_report[p], st);
+    if (e == hipSuccess) e = launch_mark_done(m->d_status[p], st);
+  } else if (e == hipSuccess) {
     e = launch_status(m->cnt, m->tcount + p, m->up, m->row_fill, m->geo.u, m->ps, m->d_status[p],
-                      st);
+                      nullptr, st);
+  }
   if (spans) span_end(m, st, ST_REPORT, ta);
   return e;
 }
@@ -504,8 +525,10 @@ void release(srla_monitor* m) {
   dfree(m->news); dfree(m->hist); dfree(m->blockw);
   dfree(m->csip); dfree(m->carried[0]); dfree(m->carried[1]); dfree(m->cflags);
   dfree(m->cblockw);
-  dfree(m->d_staging.ip); dfree(m->d_staging.est); dfree(m->d_staging.flags);
-  dfree(m->d_staging.U); dfree(m->d_staging.W);
+  for (auto& sg : m->d_staging) {
+    dfree(sg.ip); dfree(sg.est); dfree(sg.flags); dfree(sg.U); dfree(sg.W);
+  }
+  dfree(m->report_n);
   for (int q = 0; q < 2; ++q) {
     hfree(m->h_status[q]); hfree(m->h_ip[q]); hfree(m->h_est[q]); hfree(m->h_flags[q]);
     hfree(m->h_U[q]); hfree(m->h_W[q]);
@@ -520,7 +543,6 @@ void release(srla_monitor* m) {
   }
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   if (m->ev_snap) (void)hipEventDestroy(m->ev_snap);
-  if (m->ev_go) (void)hipEventDestroy(m->ev_go);
   if (m->pipe) (void)hipStreamDestroy(m->pipe);
   if (m->copy) {
     (void)hipStreamSynchronize(m->copy);
@@ -657,11 +679,14 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!rc) nomem(dalloc(&m->cflags, m->cap));
   if (!rc) nomem(dalloc(&m->cblockw, compact_block_words(m->cap)));
   if (!rc && m->overlap_report) {
-    nomem(dalloc(&m->d_staging.ip, m->cap));
-    if (!rc) nomem(dalloc(&m->d_staging.est, m->cap));
-    if (!rc) nomem(dalloc(&m->d_staging.flags, m->cap));
-    if (!rc && !(cfg->flags & SRLA_CFG_LEAN_REPORT)) nomem(dalloc(&m->d_staging.U, m->cap));
-    if (!rc && !(cfg->flags & SRLA_CFG_LEAN_REPORT)) nomem(dalloc(&m->d_staging.W, m->cap));
+    nomem(dalloc(&m->report_n, 2));
+    for (auto& sg : m->d_staging) {
+      if (!rc) nomem(dalloc(&sg.ip, m->cap));
+      if (!rc) nomem(dalloc(&sg.est, m->cap));
+      if (!rc) nomem(dalloc(&sg.flags, m->cap));
+      if (!rc && !(cfg->flags & SRLA_CFG_LEAN_REPORT)) nomem(dalloc(&sg.U, m->cap));
+      if (!rc && !(cfg->flags & SRLA_CFG_LEAN_REPORT)) nomem(dalloc(&sg.W, m->cap));
+    }
   }
   const bool weights = (cfg->flags & SRLA_CFG_LEAN_REPORT) == 0;
   for (int q = 0; q < 2 && !rc; ++q) {
@@ -685,8 +710,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     if (!rc && hipEventCreateWithFlags(&m->ev_done[q], hipEventDisableTiming) != hipSuccess)
       rc = SRLA_E_DEVICE;
   }
-  if (!rc && (hipEventCreateWithFlags(&m->ev_snap, hipEventDisableTiming) != hipSuccess ||
-              hipEventCreateWithFlags(&m->ev_go, hipEventDisableTiming) != hipSuccess))
+  if (!rc && hipEventCreateWithFlags(&m->ev_snap, hipEventDisableTiming) != hipSuccess)
     rc = SRLA_E_DEVICE;
   if (rc) {
     release(m);
@@ -752,17 +776,24 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
 }
 
 // Enqueues the second phase of the last closed slice's pipeline on the
-// pipeline stream, after its first phase, and its completion event.  go:
-// ev_go has been recorded on the scan stream in front of the next slice's
-// first scan, which is already enqueued there, and the second phase waits for
-// ev_go.  With the overlapped report its PCIe copy then starts once that scan
-// is under way: a kernel that streams writes into host memory delays the
-// dispatch of kernels of other queues by hundreds of microseconds (the
-// command processor reads queue packets and signals in host memory behind
-// those writes), so the scan has to be dispatched before the copy begins.
-int enqueue_finish(srla_monitor* m, bool go) {
+// pipeline stream, after its first phase (ev_snap, recorded on the scan
+// stream), and its completion event.  With the overlapped report this is
+// done once the next slice's first scan is already enqueued on the scan
+// stream, right behind ev_snap, so the report's PCIe copy starts after that
+// scan has been dispatched: a kernel that streams writes into host memory
+// delays the dispatch of kernels of other queues by hundreds of microseconds
+// (the command processor reads queue packets and signals in host memory
+// behind those writes), so the scan has to be under way before the copy.
+int enqueue_finish(srla_monitor* m) {
   const int pc = (int)((m->slice - 1) & 1);   // parity of the closed slice
-  HIP_TRY(m, hipStreamWaitEvent(m->pipe, go ? m->ev_go : m->ev_snap, 0));
+  // timed as the slice was when it was closed
+  struct TimingAs {
+    srla_monitor* m;
+    bool saved;
+    TimingAs(srla_monitor* mm, bool t) : m(mm), saved(mm->timing) { m->timing = t; }
+    ~TimingAs() { m->timing = saved; }
+  } timing_as(m, m->timed[pc]);
+  HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_snap, 0));
   hipEvent_t ta;
   if (m->use_graph) span_begin(m, m->pipe, &ta);
   const int rc = run_phase(m, PH_FINISH, pc, m->pipe);
@@ -798,16 +829,17 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   // the first scan after an overlapped close: the deferred second phase of the
   // closed slice is enqueued behind it (see enqueue_finish)
   bool go = m->finish_deferred;
-  if (go) HIP_TRY(m, hipEventRecord(m->ev_go, m->stream));
   if (on_device) {
     hipEvent_t a;
     span_begin(m, m->stream, &a);
     HIP_TRY(m, enqueue_scan(m, pairs, n, p));
     span_end(m, m->stream, ST_SCAN, a);
     m->slice_pairs[p] += n;
-    m->scan_launches++;
-    m->scan_pairs += n;
-    return go ? enqueue_finish(m, true) : SRLA_OK;
+    if (m->timing) {
+      m->scan_launches++;
+      m->scan_pairs += n;
+    }
+    return go ? enqueue_finish(m) : SRLA_OK;
   }
   // host input: chunk by chunk, H2D copies on the copy stream overlapping the
   // scans of earlier chunks on the scan stream
@@ -853,15 +885,17 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     HIP_TRY(m, enqueue_scan(m, m->d_stage[b], cnt, p));
     span_end(m, m->stream, ST_SCAN, a);
     if (go) {
-      rc = enqueue_finish(m, true);
+      rc = enqueue_finish(m);
       if (rc) return rc;
       go = false;
     }
     HIP_TRY(m, hipEventRecord(m->scanned_ev[b], m->stream));
     m->scanned_set[b] = true;
     m->slice_pairs[p] += cnt;
-    m->scan_launches++;
-    m->scan_pairs += cnt;
+    if (m->timing) {
+      m->scan_launches++;
+      m->scan_pairs += cnt;
+    }
     last = b;
   }
   // the caller may reuse its buffer once this returns: wait for the copies
@@ -876,13 +910,19 @@ int srla_close_slice(srla_monitor_t* m) {
   if (m->n_pending >= 2)
     return fail(m, SRLA_E_STATE, "the reports of two closed slices have not been collected");
   const int p = (int)(m->slice & 1);
-  // the previous slice's second phase is enqueued, and done with the pipeline
-  // state (counters, carried list, activity maps), before this snapshot
+  m->timed[p] = m->timing;
+  // the previous slice's second phase is enqueued first; then the scan stream
+  // waits for the work this slice's first phase would overwrite: without the
+  // overlapped report, the previous slice's second phase (the candidate state:
+  // counters, carried list, activity maps); with it, the report copy of the
+  // slice two back (it reads the staging set this slice writes), normally
+  // long finished
   if (m->finish_deferred) {
-    const int rc = enqueue_finish(m, false);
+    const int rc = enqueue_finish(m);
     if (rc) return rc;
   }
-  if (m->slice > 0) HIP_TRY(m, hipStreamWaitEvent(m->stream, m->ev_done[p ^ 1], 0));
+  if (m->overlap_report ? m->slice >= 2 : m->slice >= 1)
+    HIP_TRY(m, wait_unless_done(m->stream, m->ev_done[m->overlap_report ? p : p ^ 1]));
   // with graphs, each phase is timed as a whole: the first as the sweeps
   // (with the candidate work when the report copy overlaps the next scans),
   // the second as the estimate (as the report copy when it overlaps)
@@ -901,7 +941,7 @@ int srla_close_slice(srla_monitor_t* m) {
     m->finish_deferred = true;
     return SRLA_OK;
   }
-  return enqueue_finish(m, false);
+  return enqueue_finish(m);
 }
 
 int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
@@ -911,7 +951,7 @@ int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
   // the oldest closed slice whose report is not collected yet
   const int q = (int)((m->slice - m->n_pending) & 1);
   if (m->finish_deferred && m->n_pending == 1) {
-    const int rc = enqueue_finish(m, false);
+    const int rc = enqueue_finish(m);
     if (rc) return rc;
   }
   HIP_TRY(m, hipEventSynchronize(m->ev_done[q]));
@@ -923,8 +963,8 @@ int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
     collect_spans(m, false);
     return fail(m, SRLA_E_CAPACITY, "candidate list exceeds max_candidates");
   }
-  m->estimates++;
-  if (m->timing) collect_spans(m, false);
+  if (m->timed[q]) m->estimates++;
+  collect_spans(m, false);
   const Geo& geo = m->geo;
   for (uint32_t i = 0; i < geo.u; ++i) m->h_row_fill64[q][i] = hs.row_fill[i];
   out->slice = hs.slice;
@@ -1006,6 +1046,12 @@ int srla_dump_state(srla_monitor_t* m, int which, uint16_t* host_out, uint64_t c
     if (d < 0) d += (int32_t)kStampPeriod;
     host_out[i] = d >= (int32_t)kScrubAge ? 65535 : (uint16_t)d;
   }
+  return SRLA_OK;
+}
+
+int srla_set_timing(srla_monitor_t* m, int enabled) {
+  if (!m) return SRLA_E_INVAL;
+  m->timing = enabled != 0;
   return SRLA_OK;
 }
 

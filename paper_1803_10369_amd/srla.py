@@ -63,7 +63,7 @@ class srla_timings_t(ctypes.Structure):
 
 EXPORTS = ["srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
            "srla_close_slice", "srla_wait_report", "srla_dump_state", "srla_timings",
-           "srla_destroy", "srla_last_error", "srla_group_create", "srla_group_scan",
+           "srla_set_timing", "srla_destroy", "srla_last_error", "srla_group_create", "srla_group_scan",
            "srla_group_destroy", "srla_group_last_error", "srla_admit"]
 
 _lib = None
@@ -92,6 +92,8 @@ def lib():
         L.srla_dump_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_uint64]
         L.srla_timings.restype = ctypes.c_int
         L.srla_timings.argtypes = [vp, ctypes.POINTER(srla_timings_t), ctypes.c_int]
+        L.srla_set_timing.restype = ctypes.c_int
+        L.srla_set_timing.argtypes = [vp, ctypes.c_int]
         L.srla_destroy.restype = ctypes.c_int
         L.srla_destroy.argtypes = [vp]
         L.srla_last_error.restype = ctypes.c_char_p
@@ -149,6 +151,10 @@ def srla_wait_report(handle, report):
 
 def srla_dump_state(handle, which, out_ptr, cells):
     return lib().srla_dump_state(handle, which, out_ptr, cells)
+
+
+def srla_set_timing(handle, enabled):
+    return lib().srla_set_timing(handle, int(enabled))
 
 
 def srla_timings(handle, out, reset):
@@ -320,6 +326,10 @@ class Monitor:
         out = np.empty(n, dtype=np.uint16)
         self._check(srla_dump_state(self._h, which, ctypes.c_void_p(out.ctypes.data), n))
         return out
+
+    def set_timing(self, enabled):
+        """Times the following scans and closed slices (or not)."""
+        self._check(srla_set_timing(self._h, enabled))
 
     def timings(self, reset=False):
         t = srla_timings_t()

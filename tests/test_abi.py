@@ -27,7 +27,7 @@ def test_every_declared_symbol_is_exported(P):
     names = _declared_functions()
     assert set(names) == {"srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
                           "srla_close_slice", "srla_wait_report", "srla_dump_state",
-                          "srla_timings", "srla_destroy", "srla_last_error",
+                          "srla_timings", "srla_set_timing", "srla_destroy", "srla_last_error",
                           "srla_group_create", "srla_group_scan", "srla_group_destroy",
                           "srla_group_last_error", "srla_admit"}
     L = ctypes.CDLL(P.srla.LIB_PATH)
@@ -106,6 +106,17 @@ def test_footprint_counts_dr_arrays(P):
     assert want <= fp < want + 4096
     big = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1 << 20)
     assert P.srla_footprint_bytes(big) - fp >= 13 * ((1 << 20) - 1)
+
+
+def test_overlap_report_staging_is_counted(P):
+    # two staging sets (by slice parity) of 13 (lean) or 18 bytes per candidate
+    # and the two staged counts
+    n = 1 << 20
+    for lean, per in ((P.srla.SRLA_CFG_LEAN_REPORT, 13), (0, 18)):
+        base = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=n, flags=lean)
+        ov = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=n,
+                           flags=lean | P.srla.SRLA_CFG_OVERLAP_REPORT)
+        assert P.srla_footprint_bytes(ov) - P.srla_footprint_bytes(base) == 2 * per * n + 8
 
 
 def test_discrete_footprint_is_bits(P):

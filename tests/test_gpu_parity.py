@@ -370,6 +370,32 @@ def test_timings_are_recorded():
     g.close()
 
 
+@pytest.mark.parametrize("graph,overlap", [(False, False), (True, True)])
+def test_timing_can_be_sampled(graph, overlap):
+    """Timing switched on for slices 0 and 2 only, in the streaming call order
+    (each slice closed before the previous report is collected): only their
+    scans and stages are counted, and the results do not change."""
+    stream, mon, _ = workload("tiny")
+    g = srla.Monitor(**mon, max_candidates=1 << 16, graph=graph, overlap_report=overlap)
+    o = oracle.Monitor(**mon)
+    for s in range(5):
+        g.set_timing(s % 2 == 0 and s < 4)
+        p = stream.slice(s)
+        g.scan(to_device(p[:50_000]))
+        g.scan(to_device(p[50_000:]))
+        g.close_slice()
+        o.scan(p)
+        exp = o.estimate()
+        if s > 0:
+            compare_reports(g.wait_report(), prev, mon["theta"], "slice %d" % (s - 1))
+        prev = exp
+    compare_reports(g.wait_report(), prev, mon["theta"], "last slice")
+    t = g.timings(reset=True)
+    assert t["scan_launches"] == 4 and t["scan_pairs"] == 2 * len(stream.slice(0))
+    assert t["estimates"] == 2 and t["scan_ms"] > 0 and t["report_ms"] > 0
+    g.close()
+
+
 GROUP = [
     # k, theta, u, v_re, g, v_le, G
     (3, 64, 3, 64, 8, 8, 128),
