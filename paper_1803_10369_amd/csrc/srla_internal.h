@@ -148,9 +148,11 @@ hipError_t launch_scan_group(const uint32_t* pairs, uint64_t n, const GroupMembe
 hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
                            const Geo& geo, const PipeState* ps, hipStream_t st);
 
-// SRE DR activity bitmaps (inside the window now / after the slide) + scrub
+// SRE DR activity bitmaps (inside the window now / after the slide) + scrub,
+// and Eq8 from the row fills (which the LE sweep has completed)
 hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act, const Geo& geo,
-                           const PipeState* ps, hipStream_t st);
+                           const PipeState* ps, const unsigned long long* row_fill, double* up,
+                           hipStream_t st);
 
 // keys-only LSD radix sort of *n_dev uint32 keys (n_dev <= n_max), in place
 // (tmp is scratch).  block_hist needs radix_hist_words(n_max) words.
@@ -192,8 +194,10 @@ hipError_t launch_report_copy(const uint32_t* n, const ReportPtrs& from, const R
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
                             uint32_t* si_cnt, const Geo& geo, hipStream_t st);
 
-// records the device wall clock at the start of the end-of-slice work
-hipError_t launch_mark_close(PipeState* ps, hipStream_t st);
+// records the device wall clock at the start of the end-of-slice work and
+// clears the row fills
+hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t u,
+                              hipStream_t st);
 // records the device wall clock once the report is complete in host memory
 hipError_t launch_mark_done(HostStatus* out, hipStream_t st);
 // publishes the slice's counters, Eq8 and row fills to the host (and the

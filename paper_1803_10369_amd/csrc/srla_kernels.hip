@@ -130,10 +130,24 @@ hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* r
 // maps instead of g scattered stamps.  Old stamps are scrubbed here as in the
 // LE sweep.  Handles any cell count (ragged last word).
 
+// Eq8: UP = prod_i |LDR(i)|^k / (g' * v), in this order, in FP64.
+__device__ __forceinline__ double eq8(const unsigned long long* __restrict__ row_fill, uint32_t u,
+                                     uint32_t G, uint32_t v_le) {
+  double p = 1.0;
+  for (uint32_t i = 0; i < u; ++i) p = p * ((double)row_fill[i] / ((double)G * (double)v_le));
+  return p;
+}
+
+// The LE sweep has finished the row fills when this kernel starts (same
+// stream), so its first thread also evaluates Eq8.
 __global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, uint64_t n,
                                                     uint64_t* __restrict__ act,
                                                     const PipeState* __restrict__ ps,
-                                                    uint32_t k) {
+                                                    uint32_t k,
+                                                    const unsigned long long* __restrict__ row_fill,
+                                                    uint32_t u, uint32_t G, uint32_t v_le,
+                                                    double* __restrict__ up) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *up = eq8(row_fill, u, G, v_le);
   const uint32_t now = ps->now;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint64_t c8 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 8;
@@ -186,11 +200,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, 
 }
 
 hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act, const Geo& geo,
-                           const PipeState* ps, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  const uint64_t blocks = (n + 8 * kBlock - 1) / (8 * kBlock);
+                           const PipeState* ps, const unsigned long long* row_fill, double* up,
+                           hipStream_t st) {
+  const uint64_t blocks = n ? (n + 8 * kBlock - 1) / (8 * kBlock) : 1;
   hipLaunchKernelGGL(k_sweep_re, dim3((uint32_t)blocks), dim3(kBlock), 0, st, re, n, act, ps,
-                     geo.k);
+                     geo.k, row_fill, geo.u, geo.G, geo.v_le, up);
   return hipGetLastError();
 }
 
@@ -323,18 +337,12 @@ hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const 
 
 // ------------------------------------------------------------------ merge
 // CSIP_t = NCSIP_{t-1} u N_t, both ascending and disjoint (every carried
-// candidate has its own SI bit set, so it cannot be new): each element's
-// output position is its own index plus its rank in the other list.
+// candidate has its own SI bit set, so it cannot be new), by merge path:
+// thread q writes outputs [8q, 8q + 8); a binary search along its diagonal
+// finds how many of the first 8q outputs come from NCSIP (the search range is
+// at most |N_t| wide), then it merges its 8 outputs sequentially.
 
-__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ v, uint32_t n,
-                                                    uint32_t x) {
-  uint32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (v[mid] < x) lo = mid + 1; else hi = mid;
-  }
-  return lo;
-}
+constexpr uint32_t kMergePer = 8;
 
 __global__ __launch_bounds__(kBlock) void k_merge(const uint32_t* __restrict__ ncsip,
                                                  const PipeState* __restrict__ ps,
@@ -342,26 +350,33 @@ __global__ __launch_bounds__(kBlock) void k_merge(const uint32_t* __restrict__ n
                                                  Counters* __restrict__ cnt, uint64_t cap,
                                                  uint32_t* __restrict__ csip,
                                                  uint8_t* __restrict__ cflags) {
-  const uint32_t n_old = ps->n_ncsip;
-  const uint32_t n_new = cnt->n_new;
-  const uint64_t first = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (first == 0) {
-    const uint64_t total = (uint64_t)n_old + n_new;
-    cnt->n_cand = (uint32_t)(total < cap ? total : cap);
+  const uint64_t n_old = ps->n_ncsip;
+  const uint64_t n_new = cnt->n_new;
+  const uint64_t total = n_old + n_new;
+  const uint64_t m = total < cap ? total : cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cnt->n_cand = (uint32_t)m;
     cnt->overflow = total > cap ? 1u : 0u;
   }
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  const uint64_t top = n_old > n_new ? n_old : n_new;
-  for (uint64_t t = first; t < top; t += stride) {
-    if (t < n_old) {
-      const uint32_t x = ncsip[t];
-      const uint64_t pos = t + lower_bound_u32(news, n_new, x);
-      if (pos < cap) { csip[pos] = x; cflags[pos] = 0; }
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock * kMergePer;
+  for (uint64_t k0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * kMergePer; k0 < m;
+       k0 += stride) {
+    uint64_t lo = k0 > n_new ? k0 - n_new : 0, hi = k0 < n_old ? k0 : n_old;
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if (ncsip[mid] < news[k0 - mid - 1]) lo = mid + 1; else hi = mid;
     }
-    if (t < n_new) {
-      const uint32_t y = news[t];
-      const uint64_t pos = t + lower_bound_u32(ncsip, n_old, y);
-      if (pos < cap) { csip[pos] = y; cflags[pos] = 4; /* SRLA_FLAG_NEW */ }
+    uint64_t i = lo, j = k0 - lo;
+    const uint64_t kend = k0 + kMergePer < m ? k0 + kMergePer : m;
+    for (uint64_t k = k0; k < kend; ++k) {
+      // i + j = k < n_old + n_new, so with N_t used up NCSIP has one left
+      if (j >= n_new || (i < n_old && ncsip[i] < news[j])) {
+        csip[k] = ncsip[i++];
+        cflags[k] = 0;
+      } else {
+        csip[k] = news[j++];
+        cflags[k] = 4;   // SRLA_FLAG_NEW
+      }
     }
   }
 }
@@ -381,12 +396,7 @@ hipError_t launch_merge(const uint32_t* ncsip, const PipeState* ps, const uint32
 
 __global__ void k_union_prob(const unsigned long long* __restrict__ row_fill, Geo geo,
                              double* __restrict__ up) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double p = 1.0;
-    for (uint32_t i = 0; i < geo.u; ++i)
-      p = p * ((double)row_fill[i] / ((double)geo.G * (double)geo.v_le));
-    *up = p;
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *up = eq8(row_fill, geo.u, geo.G, geo.v_le);
 }
 
 hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo, double* up,
@@ -717,12 +727,16 @@ hipError_t launch_report_copy(const uint32_t* n, const ReportPtrs& from, const R
   return hipGetLastError();
 }
 
-__global__ void k_mark_close(PipeState* __restrict__ ps) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) ps->t_close = wall_clock64();
+__global__ void k_begin_close(PipeState* __restrict__ ps, unsigned long long* __restrict__ row_fill,
+                              uint32_t u) {
+  if (blockIdx.x != 0) return;
+  if (threadIdx.x == 0) ps->t_close = wall_clock64();
+  for (uint32_t i = threadIdx.x; i < u; i += blockDim.x) row_fill[i] = 0ull;
 }
 
-hipError_t launch_mark_close(PipeState* ps, hipStream_t st) {
-  hipLaunchKernelGGL(k_mark_close, dim3(1), dim3(64), 0, st, ps);
+hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t u,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_begin_close, dim3(1), dim3(64), 0, st, ps, row_fill, u);
   return hipGetLastError();
 }
 

@@ -392,12 +392,11 @@ hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
-  e = launch_mark_close(m->ps, st);
+  e = launch_begin_close(m->ps, m->row_fill, geo.u, st);
   if (e != hipSuccess) return e;
   if (m->discrete) {
     // the closing slice's bits are its activity maps already; the other
     // parity's (the previous slice's) are cleared for the next slice's scans
-    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st);
     if (e == hipSuccess) e = launch_row_popcount(m->lebits[p], m->row_fill, geo, st);
     if (e == hipSuccess) e = launch_union_prob(m->row_fill, geo, m->up, st);
     if (e == hipSuccess)
@@ -405,10 +404,9 @@ hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
     if (e == hipSuccess)
       e = launch_fill_u32((uint32_t*)m->rebits[p ^ 1], 0u, 4 * bitmap_words(m->n_re), st);
   } else {
-    if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->row_fill, 0u, 2ull * geo.u, st);
     if (e == hipSuccess) e = launch_sweep_le(m->le, m->bitmap, m->row_fill, geo, m->ps, st);
-    if (e == hipSuccess) e = launch_sweep_re(m->re, m->n_re, m->act, geo, m->ps, st);
-    if (e == hipSuccess) e = launch_union_prob(m->row_fill, geo, m->up, st);
+    if (e == hipSuccess)
+      e = launch_sweep_re(m->re, m->n_re, m->act, geo, m->ps, m->row_fill, m->up, st);
   }
   if (spans) span_end(m, st, ST_SWEEP, ta);
   return e;
