@@ -27,6 +27,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <atomic>
 #include <vector>
 
 #include "../../include/srla.h"
@@ -107,6 +108,7 @@ struct srla_monitor {
   Geo geo{};
   hipStream_t stream = nullptr;  // scans
   hipStream_t pipe = nullptr;    // end-of-slice pipeline (library-owned)
+  bool pipe_own = false, copy_own = false;   // on a hardware queue of their own
   bool own_stream = false;
   uint64_t slice = 0;            // open slice
   bool poisoned = false;
@@ -129,6 +131,8 @@ struct srla_monitor {
   Counters* cnt = nullptr;
   PipeState* ps = nullptr;
   uint32_t* tcount = nullptr;    // [2] sampled-source counts by slice parity
+  uint32_t* claim = nullptr;     // [2] tile-claim counters of the flat scan
+  uint32_t claim_slot = 0;       // the one the next flat scan uses
 
   // sources sampled, by slice parity, and the shared sort/finalize scratch
   uint32_t* touched[2] = {nullptr, nullptr};
@@ -282,14 +286,31 @@ uint32_t source_set_slots(uint64_t max_candidates) {
 // over a small pool of hardware queues, so two streams of one process may land
 // on the same queue and then run one after the other; a stream created with
 // a CU mask is given its own queue.  The mask enables every CU (more bits than
-// the device has CUs; the extra ones are ignored).  Falls back to an ordinary
-// stream if the masked one cannot be created.
-hipError_t create_queue_stream(hipStream_t* st) {
-  const std::vector<uint32_t> all(32, 0xFFFFFFFFu);
-  if (hipExtStreamCreateWithCUMask(st, (uint32_t)all.size(), all.data()) == hipSuccess)
-    return hipSuccess;
-  (void)hipGetLastError();
+// the device has CUs; the extra ones are ignored).  At most kOwnQueues such
+// streams live in a process at once: many more hardware queues than the
+// scheduler maps at a time make it switch between them (a serving mix of 64
+// monitors ran 2.4 times slower with a queue each).  Beyond that, and if the
+// masked stream cannot be created, an ordinary stream.  *own tells which.
+constexpr int kOwnQueues = 8;
+std::atomic<int> g_own_queues{0};
+
+hipError_t create_queue_stream(hipStream_t* st, bool* own) {
+  *own = false;
+  if (g_own_queues.fetch_add(1) < kOwnQueues) {
+    const std::vector<uint32_t> all(32, 0xFFFFFFFFu);
+    if (hipExtStreamCreateWithCUMask(st, (uint32_t)all.size(), all.data()) == hipSuccess) {
+      *own = true;
+      return hipSuccess;
+    }
+    (void)hipGetLastError();
+  }
+  g_own_queues.fetch_sub(1);
   return hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+}
+
+void destroy_queue_stream(hipStream_t st, bool own) {
+  (void)hipStreamDestroy(st);
+  if (own) g_own_queues.fetch_sub(1);
 }
 
 hipEvent_t pooled_event(srla_monitor* m) {
@@ -519,6 +540,7 @@ void release(srla_monitor* m) {
   for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); dfree(m->sset[i]); } dfree(m->bitmap); dfree(m->act);
   dfree(m->row_fill); dfree(m->up); dfree(m->cnt); dfree(m->ps);
   dfree(m->tcount);
+  dfree(m->claim);
   dfree(m->touched[0]); dfree(m->touched[1]); dfree(m->touched_tmp); dfree(m->mark);
   dfree(m->news); dfree(m->hist); dfree(m->blockw);
   dfree(m->csip); dfree(m->carried[0]); dfree(m->carried[1]); dfree(m->cflags);
@@ -541,10 +563,10 @@ void release(srla_monitor* m) {
   }
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   if (m->ev_snap) (void)hipEventDestroy(m->ev_snap);
-  if (m->pipe) (void)hipStreamDestroy(m->pipe);
+  if (m->pipe) destroy_queue_stream(m->pipe, m->pipe_own);
   if (m->copy) {
     (void)hipStreamSynchronize(m->copy);
-    (void)hipStreamDestroy(m->copy);
+    destroy_queue_stream(m->copy, m->copy_own);
   }
   if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
   delete m;
@@ -564,9 +586,9 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
     return 16 * bitmap_words(le) + 32 * bitmap_words(re) +
            16 * (uint64_t)source_set_slots(cfg->max_candidates) + 64 * si + 8 * g.u + 8 +
            staging_bytes(cfg) +
-           sizeof(Counters) + sizeof(PipeState) + 8 + candidate_bytes(cfg->max_candidates);
+           sizeof(Counters) + sizeof(PipeState) + 8 + 8 + candidate_bytes(cfg->max_candidates);
   return staging_bytes(cfg) + 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
-         8 * g.u + 8 + sizeof(Counters) + sizeof(PipeState) + 8 +
+         8 * g.u + 8 + sizeof(Counters) + sizeof(PipeState) + 8 + 8 +
          candidate_bytes(cfg->max_candidates);
 }
 
@@ -637,7 +659,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     m->own_stream = true;
   }
   // the pipeline stream runs beside the scan stream: a queue of its own
-  if (create_queue_stream(&m->pipe) != hipSuccess) {
+  if (create_queue_stream(&m->pipe, &m->pipe_own) != hipSuccess) {
     release(m);
     return SRLA_E_DEVICE;
   }
@@ -671,6 +693,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!rc) nomem(dalloc(&m->cnt, 1));
   if (!rc) nomem(dalloc(&m->ps, 1));
   if (!rc) nomem(dalloc(&m->tcount, 2));
+  if (!rc) nomem(dalloc(&m->claim, 2));
   if (!rc) nomem(dalloc(&m->csip, m->cap));
   if (!rc) nomem(dalloc(&m->carried[0], m->cap));
   if (!rc) nomem(dalloc(&m->carried[1], m->cap));
@@ -733,6 +756,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (e == hipSuccess) e = launch_fill_u32(m->si_cnt, 0u, 16 * m->n_si, m->stream);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->cnt, 0u, sizeof(Counters) / 4, m->stream);
   if (e == hipSuccess) e = launch_fill_u32(m->tcount, 0u, 2, m->stream);
+  if (e == hipSuccess) e = launch_fill_u32(m->claim, 0u, 2, m->stream);
   if (e == hipSuccess) {
     PipeState ps0{};
     ps0.now = stamp_code(0);
@@ -768,9 +792,10 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
                              m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream);
   if (m->filter_scan)
     return launch_scan_lds_filter(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
-                                  m->tcount + p, m->cfg.scan_blocks, m->stream);
+                                  m->tcount + p, m->claim, &m->claim_slot, m->cfg.scan_blocks,
+                                  m->stream);
   return launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p], m->tcount + p,
-                     m->xcd_scan, m->cfg.scan_blocks, m->stream);
+                     m->claim, &m->claim_slot, m->xcd_scan, m->cfg.scan_blocks, m->stream);
 }
 
 // Enqueues the second phase of the last closed slice's pipeline on the
@@ -842,7 +867,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   // host input: chunk by chunk, H2D copies on the copy stream overlapping the
   // scans of earlier chunks on the scan stream
   if (!m->copy) {
-    if (create_queue_stream(&m->copy) != hipSuccess) {
+    if (create_queue_stream(&m->copy, &m->copy_own) != hipSuccess) {
       (void)hipGetLastError();
       return fail(m, SRLA_E_DEVICE, "cannot create the host-ingest stream");
     }

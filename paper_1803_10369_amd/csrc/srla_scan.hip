@@ -58,39 +58,56 @@ __device__ __forceinline__ void scan_one(uint32_t a, uint32_t b, bool valid, con
   }
 }
 
+// Waves claim tiles of kWaveTile pairs from a launch-wide counter, so a wave
+// slowed by other work on its CU (the report copy of the previous slice runs
+// beside the scan) takes fewer tiles instead of holding up the whole launch,
+// as a fixed share of the tiles would.  claim[slot] counts this launch's
+// claims and is zero when it starts; the grid's first thread clears
+// claim[slot ^ 1] for the next launch on the stream.  Each wave asks for its
+// next tile while it works on the current one.
+constexpr uint64_t kWaveTile = (uint64_t)kWave * 2 * kScanSteps;   // 512 pairs
+
 template <int U, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_scan_flat(const uint32_t* __restrict__ pairs, uint64_t n,
                                                 Geo geo, uint16_t code,
                                                 uint16_t* __restrict__ le,
                                                 uint16_t* __restrict__ re,
                                                 uint32_t* __restrict__ touched,
-                                                uint32_t* __restrict__ tcount) {
-  // one tile of kScanTile pairs per iteration; the grid may be smaller than
-  // the tile count (then it strides), leaving wave slots to other streams
-  for (uint64_t base = (uint64_t)blockIdx.x * kScanTile; base < n;
-       base += (uint64_t)gridDim.x * kScanTile) {
-  uint32_t a[kScanSteps][2], b[kScanSteps][2];
-  bool v[kScanSteps][2];
+                                                uint32_t* __restrict__ tcount,
+                                                uint32_t* __restrict__ claim, uint32_t slot) {
+  const uint32_t lane = __lane_id();
+  const uint64_t tiles = (n + kWaveTile - 1) / kWaveTile;
+  if (blockIdx.x == 0 && threadIdx.x == 0) claim[slot ^ 1u] = 0u;
+  uint32_t t = 0;
+  if (lane == 0) t = atomicAdd(claim + slot, 1u);
+  t = __shfl(t, 0);
+  while (t < tiles) {   // uniform per wave: the ballots below see every lane
+    uint32_t next = 0;
+    if (lane == 0) next = atomicAdd(claim + slot, 1u);
+    const uint64_t base = (uint64_t)t * kWaveTile;
+    uint32_t a[kScanSteps][2], b[kScanSteps][2];
+    bool v[kScanSteps][2];
 #pragma unroll
-  for (int s = 0; s < kScanSteps; ++s) {
-    const uint64_t p = base + (uint64_t)s * (2 * kBlock) + 2u * threadIdx.x;
-    v[s][0] = p < n;
-    v[s][1] = p + 1 < n;
-    if (VEC && v[s][1]) {
-      const uint4 q = *reinterpret_cast<const uint4*>(pairs + 2 * p);
-      a[s][0] = q.x; b[s][0] = q.y; a[s][1] = q.z; b[s][1] = q.w;
-    } else {
-      a[s][0] = v[s][0] ? pairs[2 * p] : 0u;
-      b[s][0] = v[s][0] ? pairs[2 * p + 1] : 0u;
-      a[s][1] = v[s][1] ? pairs[2 * p + 2] : 0u;
-      b[s][1] = v[s][1] ? pairs[2 * p + 3] : 0u;
+    for (int s = 0; s < kScanSteps; ++s) {
+      const uint64_t p = base + (uint64_t)s * (2 * kWave) + 2u * lane;
+      v[s][0] = p < n;
+      v[s][1] = p + 1 < n;
+      if (VEC && v[s][1]) {
+        const uint4 q = *reinterpret_cast<const uint4*>(pairs + 2 * p);
+        a[s][0] = q.x; b[s][0] = q.y; a[s][1] = q.z; b[s][1] = q.w;
+      } else {
+        a[s][0] = v[s][0] ? pairs[2 * p] : 0u;
+        b[s][0] = v[s][0] ? pairs[2 * p + 1] : 0u;
+        a[s][1] = v[s][1] ? pairs[2 * p + 2] : 0u;
+        b[s][1] = v[s][1] ? pairs[2 * p + 3] : 0u;
+      }
     }
-  }
 #pragma unroll
-  for (int s = 0; s < kScanSteps; ++s) {
-    scan_one<U>(a[s][0], b[s][0], v[s][0], geo, code, le, re, touched, tcount);
-    scan_one<U>(a[s][1], b[s][1], v[s][1], geo, code, le, re, touched, tcount);
-  }
+    for (int s = 0; s < kScanSteps; ++s) {
+      scan_one<U>(a[s][0], b[s][0], v[s][0], geo, code, le, re, touched, tcount);
+      scan_one<U>(a[s][1], b[s][1], v[s][1], geo, code, le, re, touched, tcount);
+    }
+    t = __shfl(next, 0);
   }
 }
 
@@ -184,22 +201,26 @@ static hipError_t launch_scan_xcd(const uint32_t* pairs, uint64_t n, const Geo& 
 template <int U>
 static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                                 uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
-                                uint32_t max_blocks, hipStream_t st) {
+                                uint32_t* claim, uint32_t* slot, uint32_t max_blocks,
+                                hipStream_t st) {
   uint64_t blocks = (n + kScanTile - 1) / kScanTile;
   if (max_blocks && blocks > max_blocks) blocks = max_blocks;
   const bool vec = ((uintptr_t)pairs & 15u) == 0;
   if (vec)
     hipLaunchKernelGGL((k_scan_flat<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
-                       geo, code, le, re, touched, tcount);
+                       geo, code, le, re, touched, tcount, claim, *slot);
   else
     hipLaunchKernelGGL((k_scan_flat<U, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
-                       geo, code, le, re, touched, tcount);
-  return hipGetLastError();
+                       geo, code, le, re, touched, tcount, claim, *slot);
+  const hipError_t e = hipGetLastError();
+  if (e == hipSuccess) *slot ^= 1u;
+  return e;
 }
 
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                        uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
-                       bool xcd_aware, uint32_t max_blocks, hipStream_t st) {
+                       uint32_t* claim, uint32_t* slot, bool xcd_aware, uint32_t max_blocks,
+                       hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (xcd_aware && ((uintptr_t)pairs & 15u) == 0) {
     switch (geo.u) {
@@ -212,9 +233,15 @@ hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16
     }
   }
   switch (geo.u) {
-    case 4: return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
-    case 8: return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
-    default: return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
+    case 4:
+      return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, tcount, claim, slot,
+                              max_blocks, st);
+    case 8:
+      return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, tcount, claim, slot,
+                              max_blocks, st);
+    default:
+      return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, tcount, claim, slot,
+                              max_blocks, st);
   }
 }
 

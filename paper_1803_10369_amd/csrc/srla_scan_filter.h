@@ -11,6 +11,7 @@ namespace srla {
 // more).
 hipError_t launch_scan_lds_filter(const uint32_t* pairs, uint64_t n, const Geo& geo,
                                   uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
-                                  uint32_t* tcount, uint32_t max_blocks, hipStream_t st);
+                                  uint32_t* tcount, uint32_t* claim, uint32_t* slot,
+                                  uint32_t max_blocks, hipStream_t st);
 
 }  // namespace srla

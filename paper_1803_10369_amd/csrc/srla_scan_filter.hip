@@ -131,11 +131,13 @@ static hipError_t launch_lf_u(const uint32_t* pairs, uint64_t n, const Geo& geo,
 
 hipError_t launch_scan_lds_filter(const uint32_t* pairs, uint64_t n, const Geo& geo,
                                   uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
-                                  uint32_t* tcount, uint32_t max_blocks, hipStream_t st) {
+                                  uint32_t* tcount, uint32_t* claim, uint32_t* slot,
+                                  uint32_t max_blocks, hipStream_t st) {
   if (n == 0) return hipSuccess;
   // 32-bit DR indices (and one spare value for an empty slot)
   if ((uint64_t)geo.u * geo.v_le * geo.G >= (uint64_t)kLfEmpty)
-    return launch_scan(pairs, n, geo, code, le, re, touched, tcount, false, max_blocks, st);
+    return launch_scan(pairs, n, geo, code, le, re, touched, tcount, claim, slot, false,
+                       max_blocks, st);
   switch (geo.u) {
     case 4: return launch_lf_u<4>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
     case 8: return launch_lf_u<8>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
