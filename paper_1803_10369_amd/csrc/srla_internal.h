@@ -190,9 +190,12 @@ hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint
                            hipStream_t st);
 
 // copies the first *n report entries from device staging arrays to the host
-// arrays (U and W only where `to` has them)
+// arrays (U and W only where `to` has them); with expect != 0, only once
+// *started == expect (a bounded wait)
 hipError_t launch_report_copy(const uint32_t* n, const ReportPtrs& from, const ReportPtrs& to,
-                              hipStream_t st);
+                              const uint32_t* started, uint32_t expect, hipStream_t st);
+// sets *started = value: the scan enqueued behind it on the stream is about to start
+hipError_t launch_mark_scan(uint32_t* started, uint32_t value, hipStream_t st);
 
 // Algorithm 3's SI step on the per-bit counters (after the KEEP flags are final)
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,

@@ -705,8 +705,25 @@ __device__ __forceinline__ void copy_bytes_16(const uint8_t* __restrict__ src,
   if (tail < bytes && t < 16) dst[tail] = src[tail];
 }
 
+// expect != 0: the copy waits until *started == expect, i.e. until the next
+// slice's first scan is about to start on the other stream (its streams of
+// host writes would otherwise hold up that scan's dispatch).  The wait is
+// bounded: after kCopyWaitSpins polls the copy proceeds anyway.
+constexpr uint32_t kCopyWaitSpins = 1u << 20;
+
 __global__ __launch_bounds__(kBlock) void k_report_copy(const uint32_t* __restrict__ n_p,
-                                                       ReportPtrs from, ReportPtrs to) {
+                                                       ReportPtrs from, ReportPtrs to,
+                                                       const uint32_t* started, uint32_t expect) {
+  if (expect != 0u) {
+    if (threadIdx.x == 0) {
+      for (uint32_t i = 0; i < kCopyWaitSpins; ++i) {
+        if (__hip_atomic_load(started, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == expect)
+          break;
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __syncthreads();
+  }
   const uint64_t n = *n_p;
   copy_bytes_16((const uint8_t*)from.ip, (uint8_t*)to.ip, 4 * n);
   copy_bytes_16((const uint8_t*)from.est, (uint8_t*)to.est, 8 * n);
@@ -722,8 +739,19 @@ __global__ __launch_bounds__(kBlock) void k_report_copy(const uint32_t* __restri
 constexpr uint32_t kCopyBlocks = 128;
 
 hipError_t launch_report_copy(const uint32_t* n, const ReportPtrs& from, const ReportPtrs& to,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_report_copy, dim3(kCopyBlocks), dim3(kBlock), 0, st, n, from, to);
+                              const uint32_t* started, uint32_t expect, hipStream_t st) {
+  hipLaunchKernelGGL(k_report_copy, dim3(kCopyBlocks), dim3(kBlock), 0, st, n, from, to, started,
+                     expect);
+  return hipGetLastError();
+}
+
+__global__ void k_mark_scan(uint32_t* started, uint32_t value) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    __hip_atomic_store(started, value, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+hipError_t launch_mark_scan(uint32_t* started, uint32_t value, hipStream_t st) {
+  hipLaunchKernelGGL(k_mark_scan, dim3(1), dim3(64), 0, st, started, value);
   return hipGetLastError();
 }
 

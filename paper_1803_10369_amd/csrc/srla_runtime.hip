@@ -92,7 +92,9 @@ bool config_ok(const srla_config_t* c) {
 enum Stage { ST_SCAN, ST_SWEEP, ST_FINALIZE, ST_ESTIMATE, ST_SLIDE, ST_REPORT, ST_N };
 
 // the end-of-slice pipeline's two phases
-enum Phase { PH_SNAPSHOT = 0, PH_FINISH = 1 };
+// PH_FINISH_GO: the second phase when the next slice's first scan is enqueued
+// behind a scan-start mark (the report copy then waits for that mark)
+enum Phase { PH_SNAPSHOT = 0, PH_FINISH = 1, PH_FINISH_GO = 2 };
 
 struct TimedSpan {
   int stage;
@@ -132,6 +134,8 @@ struct srla_monitor {
   PipeState* ps = nullptr;
   uint32_t* tcount = nullptr;    // [2] sampled-source counts by slice parity
   uint32_t* claim = nullptr;     // [2] tile-claim counters of the flat scan
+  uint32_t* started = nullptr;   // scan-start mark: 1 + parity of the slice whose first scan
+                                 // is about to start (overlapped report)
   uint32_t claim_slot = 0;       // the one the next flat scan uses
 
   // sources sampled, by slice parity, and the shared sort/finalize scratch
@@ -178,7 +182,7 @@ struct srla_monitor {
 
   // replayable pipeline: [phase][parity]
   bool use_graph = false;
-  hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t graph[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
 
   // host-input ring: H2D copies on their own stream into two device chunks
   // (through two pinned bounce chunks when the caller's memory is pageable),
@@ -497,7 +501,11 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
   if (!m->overlap_report) e = enqueue_candidates(m, p, m->d_report[p], st);
   if (spans) span_begin(m, st, &ta);
   if (m->overlap_report) {
-    if (e == hipSuccess) e = launch_report_copy(m->report_n + p, m->d_staging[p], m->d_report[p], st);
+    // PH_FINISH_GO: the next slice (parity p ^ 1) has its first scan behind a mark
+    const uint32_t expect = phase == PH_FINISH_GO ? (uint32_t)(p ^ 1) + 1u : 0u;
+    if (e == hipSuccess)
+      e = launch_report_copy(m->report_n + p, m->d_staging[p], m->d_report[p], m->started, expect,
+                             st);
     if (e == hipSuccess) e = launch_mark_done(m->d_status[p], st);
   } else if (e == hipSuccess) {
     e = launch_status(m->cnt, m->tcount + p, m->up, m->row_fill, m->geo.u, m->ps, m->d_status[p],
@@ -541,6 +549,7 @@ void release(srla_monitor* m) {
   dfree(m->row_fill); dfree(m->up); dfree(m->cnt); dfree(m->ps);
   dfree(m->tcount);
   dfree(m->claim);
+  dfree(m->started);
   dfree(m->touched[0]); dfree(m->touched[1]); dfree(m->touched_tmp); dfree(m->mark);
   dfree(m->news); dfree(m->hist); dfree(m->blockw);
   dfree(m->csip); dfree(m->carried[0]); dfree(m->carried[1]); dfree(m->cflags);
@@ -586,9 +595,9 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
     return 16 * bitmap_words(le) + 32 * bitmap_words(re) +
            16 * (uint64_t)source_set_slots(cfg->max_candidates) + 64 * si + 8 * g.u + 8 +
            staging_bytes(cfg) +
-           sizeof(Counters) + sizeof(PipeState) + 8 + 8 + candidate_bytes(cfg->max_candidates);
+           sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 + candidate_bytes(cfg->max_candidates);
   return staging_bytes(cfg) + 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
-         8 * g.u + 8 + sizeof(Counters) + sizeof(PipeState) + 8 + 8 +
+         8 * g.u + 8 + sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 +
          candidate_bytes(cfg->max_candidates);
 }
 
@@ -694,6 +703,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!rc) nomem(dalloc(&m->ps, 1));
   if (!rc) nomem(dalloc(&m->tcount, 2));
   if (!rc) nomem(dalloc(&m->claim, 2));
+  if (!rc) nomem(dalloc(&m->started, 1));
   if (!rc) nomem(dalloc(&m->csip, m->cap));
   if (!rc) nomem(dalloc(&m->carried[0], m->cap));
   if (!rc) nomem(dalloc(&m->carried[1], m->cap));
@@ -757,6 +767,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->cnt, 0u, sizeof(Counters) / 4, m->stream);
   if (e == hipSuccess) e = launch_fill_u32(m->tcount, 0u, 2, m->stream);
   if (e == hipSuccess) e = launch_fill_u32(m->claim, 0u, 2, m->stream);
+  if (e == hipSuccess) e = launch_fill_u32(m->started, 0u, 1, m->stream);
   if (e == hipSuccess) {
     PipeState ps0{};
     ps0.now = stamp_code(0);
@@ -807,7 +818,7 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
 // delays the dispatch of kernels of other queues by hundreds of microseconds
 // (the command processor reads queue packets and signals in host memory
 // behind those writes), so the scan has to be under way before the copy.
-int enqueue_finish(srla_monitor* m) {
+int enqueue_finish(srla_monitor* m, bool go) {
   const int pc = (int)((m->slice - 1) & 1);   // parity of the closed slice
   // timed as the slice was when it was closed
   struct TimingAs {
@@ -819,7 +830,7 @@ int enqueue_finish(srla_monitor* m) {
   HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_snap, 0));
   hipEvent_t ta;
   if (m->use_graph) span_begin(m, m->pipe, &ta);
-  const int rc = run_phase(m, PH_FINISH, pc, m->pipe);
+  const int rc = run_phase(m, go ? PH_FINISH_GO : PH_FINISH, pc, m->pipe);
   if (rc) return rc;
   if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
   HIP_TRY(m, hipEventRecord(m->ev_done[pc], m->pipe));
@@ -849,9 +860,11 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   const int p = (int)(m->slice & 1);
   int rc = reserve_touched(m, m->slice_pairs[p] + n);
   if (rc) return rc;
-  // the first scan after an overlapped close: the deferred second phase of the
-  // closed slice is enqueued behind it (see enqueue_finish)
+  // the first scan after an overlapped close: a scan-start mark and the scan,
+  // then the deferred second phase of the closed slice, whose report copy
+  // waits for the mark (see enqueue_finish)
   bool go = m->finish_deferred;
+  if (go) HIP_TRY(m, launch_mark_scan(m->started, (uint32_t)p + 1u, m->stream));
   if (on_device) {
     hipEvent_t a;
     span_begin(m, m->stream, &a);
@@ -862,7 +875,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
       m->scan_launches++;
       m->scan_pairs += n;
     }
-    return go ? enqueue_finish(m) : SRLA_OK;
+    return go ? enqueue_finish(m, true) : SRLA_OK;
   }
   // host input: chunk by chunk, H2D copies on the copy stream overlapping the
   // scans of earlier chunks on the scan stream
@@ -908,7 +921,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     HIP_TRY(m, enqueue_scan(m, m->d_stage[b], cnt, p));
     span_end(m, m->stream, ST_SCAN, a);
     if (go) {
-      rc = enqueue_finish(m);
+      rc = enqueue_finish(m, true);
       if (rc) return rc;
       go = false;
     }
@@ -941,7 +954,7 @@ int srla_close_slice(srla_monitor_t* m) {
   // slice two back (it reads the staging set this slice writes), normally
   // long finished
   if (m->finish_deferred) {
-    const int rc = enqueue_finish(m);
+    const int rc = enqueue_finish(m, false);
     if (rc) return rc;
   }
   if (m->overlap_report ? m->slice >= 2 : m->slice >= 1)
@@ -964,7 +977,7 @@ int srla_close_slice(srla_monitor_t* m) {
     m->finish_deferred = true;
     return SRLA_OK;
   }
-  return enqueue_finish(m);
+  return enqueue_finish(m, false);
 }
 
 int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
@@ -974,7 +987,7 @@ int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
   // the oldest closed slice whose report is not collected yet
   const int q = (int)((m->slice - m->n_pending) & 1);
   if (m->finish_deferred && m->n_pending == 1) {
-    const int rc = enqueue_finish(m);
+    const int rc = enqueue_finish(m, false);
     if (rc) return rc;
   }
   HIP_TRY(m, hipEventSynchronize(m->ev_done[q]));
