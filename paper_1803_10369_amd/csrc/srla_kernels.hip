@@ -51,6 +51,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
                                                     const PipeState* __restrict__ ps,
                                                     uint32_t k) {
   const uint32_t now = ps->now;
+  // The window's stamp codes form one interval on the circle of codes: a
+  // nonzero cell c is inside iff (c - lo) mod 2^16 <= w, with lo the code of
+  // slice e-k+1 (the interval may pass over the unused code 0, which widens w
+  // by one); the same test with k = kScrubAge tells the cells to keep.
+  const uint32_t lo_w = now > k - 1u ? now - (k - 1u) : now + kStampPeriod - (k - 1u);
+  const uint32_t w_w = (now - lo_w) & 0xFFFFu;
+  const uint32_t lo_s =
+      now > kScrubAge - 1u ? now - (kScrubAge - 1u) : now + kStampPeriod - (kScrubAge - 1u);
+  const uint32_t w_s = (now - lo_s) & 0xFFFFu;
   const uint32_t row = blockIdx.y;
   uint16_t* rowp = le + (uint64_t)row * row_cells;
   uint64_t* bmp = bitmap + (uint64_t)row * (row_cells / 64);
@@ -75,18 +84,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
       bool dirty = false;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        uint32_t lo = w[j] & 0xFFFFu, hi = w[j] >> 16;
-        if (lo) {
-          const uint32_t age = stamp_age(now, lo);
-          if (age < k) m8 |= 1u << (2 * j);
-          if (age >= kScrubAge) { lo = 0; dirty = true; }
-        }
-        if (hi) {
-          const uint32_t age = stamp_age(now, hi);
-          if (age < k) m8 |= 1u << (2 * j + 1);
-          if (age >= kScrubAge) { hi = 0; dirty = true; }
-        }
-        w[j] = lo | (hi << 16);
+        const uint32_t lo = w[j] & 0xFFFFu, hi = w[j] >> 16;
+        const bool in_lo = lo != 0u && ((lo - lo_w) & 0xFFFFu) <= w_w;
+        const bool in_hi = hi != 0u && ((hi - lo_w) & 0xFFFFu) <= w_w;
+        const bool old_lo = lo != 0u && ((lo - lo_s) & 0xFFFFu) > w_s;
+        const bool old_hi = hi != 0u && ((hi - lo_s) & 0xFFFFu) > w_s;
+        m8 |= ((uint32_t)in_lo << (2 * j)) | ((uint32_t)in_hi << (2 * j + 1));
+        dirty |= old_lo | old_hi;
+        w[j] = (old_lo ? 0u : lo) | ((old_hi ? 0u : hi) << 16);
       }
       if (dirty) *reinterpret_cast<uint4*>(rowp + c8) = make_uint4(w[0], w[1], w[2], w[3]);
       count += __popc(m8);
