@@ -138,11 +138,13 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t 
 // the grid (0: one block per tile of pairs).  claim: two device words, zero
 // at first use, for the flat form's tile claims; *slot (host) selects the
 // one a launch uses and is flipped by every launch of that form.  Launches
-// that share claim must be ordered (one stream).
+// that share claim must be ordered (one stream).  mark != 0 (n > 0): *started
+// is set to mark as the scan starts (by the scan kernel itself, or by a
+// marker kernel just before it).
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                        uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
                        uint32_t* claim, uint32_t* slot, bool xcd_aware, uint32_t max_blocks,
-                       hipStream_t st);
+                       hipStream_t st, uint32_t* started = nullptr, uint32_t mark = 0);
 
 // Algorithm 2 of every member of a group for n pairs, each pair loaded once
 hipError_t launch_scan_group(const uint32_t* pairs, uint64_t n, const GroupMember* members,

@@ -792,8 +792,15 @@ namespace {
 
 // Algorithm 2 for n device-resident pairs of the open slice (parity p) in the
 // monitor's scan form
-hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int p) {
+// mark != 0: the scan-start mark to set as this scan starts (by the flat
+// scan kernel itself, else by a marker kernel just before the scan)
+hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int p,
+                        uint32_t mark) {
   const uint16_t code = stamp_code(m->slice);
+  if (mark != 0u && (m->discrete || m->dedup_scan || m->filter_scan)) {
+    const hipError_t e = launch_mark_scan(m->started, mark, m->stream);
+    if (e != hipSuccess) return e;
+  }
   if (m->discrete)
     return launch_scan_bits(pairs, n, m->geo, m->lebits[p], m->rebits[p], m->sset[p],
                             m->set_slots, m->touched[p], m->tcount + p, m->cfg.scan_blocks,
@@ -806,7 +813,8 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
                                   m->tcount + p, m->claim, &m->claim_slot, m->cfg.scan_blocks,
                                   m->stream);
   return launch_scan(pairs, n, m->geo, code, m->le, m->re, m->touched[p], m->tcount + p,
-                     m->claim, &m->claim_slot, m->xcd_scan, m->cfg.scan_blocks, m->stream);
+                     m->claim, &m->claim_slot, m->xcd_scan, m->cfg.scan_blocks, m->stream,
+                     m->started, mark);
 }
 
 // Enqueues the second phase of the last closed slice's pipeline on the
@@ -860,15 +868,15 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   const int p = (int)(m->slice & 1);
   int rc = reserve_touched(m, m->slice_pairs[p] + n);
   if (rc) return rc;
-  // the first scan after an overlapped close: a scan-start mark and the scan,
-  // then the deferred second phase of the closed slice, whose report copy
-  // waits for the mark (see enqueue_finish)
+  // the first scan after an overlapped close sets the scan-start mark; the
+  // deferred second phase of the closed slice is enqueued after it, and its
+  // report copy waits for the mark (see enqueue_finish)
   bool go = m->finish_deferred;
-  if (go) HIP_TRY(m, launch_mark_scan(m->started, (uint32_t)p + 1u, m->stream));
+  const uint32_t mark = go ? (uint32_t)p + 1u : 0u;
   if (on_device) {
     hipEvent_t a;
     span_begin(m, m->stream, &a);
-    HIP_TRY(m, enqueue_scan(m, pairs, n, p));
+    HIP_TRY(m, enqueue_scan(m, pairs, n, p, mark));
     span_end(m, m->stream, ST_SCAN, a);
     m->slice_pairs[p] += n;
     if (m->timing) {
@@ -918,7 +926,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     HIP_TRY(m, hipStreamWaitEvent(m->stream, m->stage_ev[b], 0));
     hipEvent_t a;
     span_begin(m, m->stream, &a);
-    HIP_TRY(m, enqueue_scan(m, m->d_stage[b], cnt, p));
+    HIP_TRY(m, enqueue_scan(m, m->d_stage[b], cnt, p, go ? mark : 0u));
     span_end(m, m->stream, ST_SCAN, a);
     if (go) {
       rc = enqueue_finish(m, true);

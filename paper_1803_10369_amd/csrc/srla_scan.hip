@@ -64,7 +64,9 @@ __device__ __forceinline__ void scan_one(uint32_t a, uint32_t b, bool valid, con
 // as a fixed share of the tiles would.  claim[slot] counts this launch's
 // claims and is zero when it starts; the grid's first thread clears
 // claim[slot ^ 1] for the next launch on the stream.  Each wave asks for its
-// next tile while it works on the current one.
+// next tile while it works on the current one.  mark != 0: the same thread
+// also sets *started = mark, the scan-start mark a report copy on another
+// stream may be waiting for.
 constexpr uint64_t kWaveTile = (uint64_t)kWave * 2 * kScanSteps;   // 512 pairs
 
 template <int U, bool VEC>
@@ -74,10 +76,14 @@ __global__ __launch_bounds__(kBlock) void k_scan_flat(const uint32_t* __restrict
                                                 uint16_t* __restrict__ re,
                                                 uint32_t* __restrict__ touched,
                                                 uint32_t* __restrict__ tcount,
-                                                uint32_t* __restrict__ claim, uint32_t slot) {
+                                                uint32_t* __restrict__ claim, uint32_t slot,
+                                                uint32_t* started, uint32_t mark) {
   const uint32_t lane = __lane_id();
   const uint64_t tiles = (n + kWaveTile - 1) / kWaveTile;
-  if (blockIdx.x == 0 && threadIdx.x == 0) claim[slot ^ 1u] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    claim[slot ^ 1u] = 0u;
+    if (mark != 0u) __hip_atomic_store(started, mark, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   uint32_t t = 0;
   if (lane == 0) t = atomicAdd(claim + slot, 1u);
   t = __shfl(t, 0);
@@ -201,17 +207,17 @@ static hipError_t launch_scan_xcd(const uint32_t* pairs, uint64_t n, const Geo& 
 template <int U>
 static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                                 uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
-                                uint32_t* claim, uint32_t* slot, uint32_t max_blocks,
-                                hipStream_t st) {
+                                uint32_t* claim, uint32_t* slot, uint32_t* started, uint32_t mark,
+                                uint32_t max_blocks, hipStream_t st) {
   uint64_t blocks = (n + kScanTile - 1) / kScanTile;
   if (max_blocks && blocks > max_blocks) blocks = max_blocks;
   const bool vec = ((uintptr_t)pairs & 15u) == 0;
   if (vec)
     hipLaunchKernelGGL((k_scan_flat<U, true>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
-                       geo, code, le, re, touched, tcount, claim, *slot);
+                       geo, code, le, re, touched, tcount, claim, *slot, started, mark);
   else
     hipLaunchKernelGGL((k_scan_flat<U, false>), dim3((uint32_t)blocks), dim3(kBlock), 0, st, pairs, n,
-                       geo, code, le, re, touched, tcount, claim, *slot);
+                       geo, code, le, re, touched, tcount, claim, *slot, started, mark);
   const hipError_t e = hipGetLastError();
   if (e == hipSuccess) *slot ^= 1u;
   return e;
@@ -220,9 +226,13 @@ static hipError_t launch_scan_u(const uint32_t* pairs, uint64_t n, const Geo& ge
 hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                        uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
                        uint32_t* claim, uint32_t* slot, bool xcd_aware, uint32_t max_blocks,
-                       hipStream_t st) {
+                       hipStream_t st, uint32_t* started, uint32_t mark) {
   if (n == 0) return hipSuccess;
   if (xcd_aware && ((uintptr_t)pairs & 15u) == 0) {
+    if (mark != 0u) {
+      const hipError_t e = launch_mark_scan(started, mark, st);
+      if (e != hipSuccess) return e;
+    }
     switch (geo.u) {
       case 1: return launch_scan_xcd<1>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
       case 2: return launch_scan_xcd<2>(pairs, n, geo, code, le, re, touched, tcount, max_blocks, st);
@@ -234,14 +244,14 @@ hipError_t launch_scan(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16
   }
   switch (geo.u) {
     case 4:
-      return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, tcount, claim, slot,
-                              max_blocks, st);
+      return launch_scan_u<4>(pairs, n, geo, code, le, re, touched, tcount, claim, slot, started,
+                              mark, max_blocks, st);
     case 8:
-      return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, tcount, claim, slot,
-                              max_blocks, st);
+      return launch_scan_u<8>(pairs, n, geo, code, le, re, touched, tcount, claim, slot, started,
+                              mark, max_blocks, st);
     default:
-      return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, tcount, claim, slot,
-                              max_blocks, st);
+      return launch_scan_u<0>(pairs, n, geo, code, le, re, touched, tcount, claim, slot, started,
+                              mark, max_blocks, st);
   }
 }
 
