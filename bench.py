@@ -8,13 +8,16 @@ delivered to host memory.  Window k = 300 slices, SRE 8 x 2^20 DR cells, SLE
 slices see a full window; the timed slices' pairs are generated into device
 memory before each timed segment starts.
 
---mode streaming (default): slice t's candidate check and estimate run first
-  (into device memory), then the scan of slice t+1 runs on the GPU while the
-  report of slice t is copied to host memory (two HIP streams, the
-  end-of-slice pipeline replayed as HIP graphs; the host closes slice t+1
-  before it collects the report of slice t); the latency is the device time
-  from the start of slice t's end-of-slice work, right after its last scan,
-  to its report in host memory.
+--mode streaming (default): slice t's DR activity is snapshotted right after
+  its last scan, then the scan of slice t+1 runs on the GPU beside slice t's
+  candidate check and estimate, which write the report to host memory (two
+  HIP streams, the end-of-slice pipeline replayed as HIP graphs; the host
+  closes slice t+1 before it collects the report of slice t).  With a scan
+  form other than the partitioned one (the autotuner picks it), the
+  candidate work runs first (into device memory) and only the report's copy
+  runs beside the next scan (--overlap-report).  The latency is the device
+  time from the start of slice t's end-of-slice work, right after its last
+  scan, to its report in host memory.
 --mode plain: each slice is scanned, then estimated; the latency is the host
   time from the end of the slice's scan to its report.
 
@@ -251,6 +254,11 @@ def run_discrete(args):
     torch.cuda.set_stream(st)
     if args.calib_copy_mb:
         calibration_copy(args.calib_copy_mb)
+    # the streaming form overlaps only the report's PCIe copy with the next
+    # slice's scans when the scan is the flat one; the partitioned scan leaves
+    # the cache to the candidate work, which then runs beside the scans whole
+    overlap = ((args.mode == "streaming" and not args.scan_partition)
+               if args.overlap_report < 0 else bool(args.overlap_report))
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      discrete=True, graph=args.graph > 0, scan_blocks=args.scan_blocks,
                      lean_report=not args.full_report)
@@ -475,7 +483,11 @@ def main():
                          "bytes per candidate to host memory)")
     ap.add_argument("--overlap-report", type=int, default=-1,
                     help="candidate work before the next slice's scans, only the report's "
-                         "PCIe copy alongside them (default: streaming form only)")
+                         "PCIe copy alongside them (default: streaming form with a scan "
+                         "form other than the partitioned one)")
+    ap.add_argument("--scan-partition", action="store_true",
+                    help="scan in partitioned form: LE stores sorted by region in LDS, "
+                         "then stamped a region per workgroup (A/B of the scan kernels)")
     ap.add_argument("--scan-lds-filter", action="store_true",
                     help="scan with a workgroup filter of repeated DR stores (A/B)")
     ap.add_argument("--scan-dedup", action="store_true",
@@ -513,7 +525,6 @@ def main():
     if args.calib_copy_mb:
         calibration_copy(args.calib_copy_mb)
     graph = (args.mode == "streaming") if args.graph < 0 else bool(args.graph)
-    overlap = (args.mode == "streaming") if args.overlap_report < 0 else bool(args.overlap_report)
     buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
     tuned = None
     if args.autotune:
@@ -528,10 +539,12 @@ def main():
         args.scan_xcd, args.scan_blocks = tuned["scan_xcd"], tuned["scan_blocks"]
         args.scan_dedup = tuned["scan_dedup"]
         args.scan_lds_filter = tuned["scan_lds_filter"]
+        args.scan_partition = tuned["scan_partition"]
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks,
                      lean_report=not args.full_report, scan_dedup=args.scan_dedup,
-                     scan_lds_filter=args.scan_lds_filter, overlap_report=overlap)
+                     scan_lds_filter=args.scan_lds_filter, overlap_report=overlap,
+                     scan_partition=args.scan_partition)
     t_w = time.perf_counter()
     for s in range(args.warmup):
         ds.generate(s, out=buf, stream=st)
@@ -604,7 +617,8 @@ def main():
     scan_ms = tm["scan_ms"] / max(1, tm["scan_launches"])
     per_launch_bytes = scan_bytes_per_pair(g["u"], tau) * n_pairs
     achieved = per_launch_bytes / (scan_ms * 1e-3) / 1e9
-    scan_kernel = ("k_scan_dedup" if args.scan_dedup else
+    scan_kernel = ("k_scan_part+k_scan_apply" if args.scan_partition else
+                   "k_scan_dedup" if args.scan_dedup else
                    "k_scan_lds_filter" if args.scan_lds_filter else
                    "k_scan_xcd" if args.scan_xcd else "k_scan_flat")
     stages = {k: tm[k] / max(1, tm["estimates"]) for k in
@@ -637,6 +651,7 @@ def main():
             "mode": args.mode, "graph": graph, "scan_blocks": args.scan_blocks,
             "scan_xcd": args.scan_xcd, "scan_dedup": args.scan_dedup,
             "scan_lds_filter": args.scan_lds_filter, "overlap_report": overlap,
+            "scan_partition": args.scan_partition,
             "autotune": tuned,
             "report": ("full: ip, est, flags, |ULE|^k, |URE|^k (18 B/candidate)"
                        if args.full_report else "ip, est, flags (13 B/candidate)"),

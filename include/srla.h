@@ -98,7 +98,19 @@ enum {
                                   staging sets (by slice parity) of 13
                                   (lean) or 18 bytes of device memory per
                                   max_candidates.  Such monitors cannot join
-                                  a group */
+                                  a group */,
+    SRLA_CFG_SCAN_PARTITION = 256 /* scan in partitioned form: each chunk of
+                                  pairs sorts its LE DR indices by region
+                                  of 2^15 DRs, then one workgroup per region
+                                  stamps the DRs named in it, so the LE
+                                  stores fill whole cache lines instead of
+                                  going out one 2-byte store at a time.
+                                  Results are identical.  Requires at most
+                                  2^25 LE DRs (u * v_le * g_le); costs 128
+                                  MiB of device scratch plus 4 KiB per
+                                  region.  Above every other scan form in
+                                  precedence; no effect in the discrete
+                                  form or in a group's fused scan */
 };
 
 /*

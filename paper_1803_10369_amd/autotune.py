@@ -3,7 +3,8 @@
 The scan (Algorithm 2) has two knobs that never change its results: the
 kernel form (flat; per-XCD row ownership, SRLA_CFG_SCAN_XCD; read-before-write,
 SRLA_CFG_SCAN_DEDUP; both, per-XCD read-before-write; a workgroup filter of repeated
-stores, SRLA_CFG_SCAN_LDS_FILTER) and the
+stores, SRLA_CFG_SCAN_LDS_FILTER; the partitioned form, SRLA_CFG_SCAN_PARTITION,
+tried only where the LE has at most 2^25 DRs) and the
 cap on its workgroups (srla_config_t.scan_blocks).
 tune_scan() times every candidate on a scratch monitor of the caller's
 geometry with the caller's pairs, one scan per slice (each timed scan meets
@@ -31,7 +32,9 @@ from . import srla
 # (per-XCD: 985 us against 710 us for the flat form, as every pair is read
 # once per XCD group; the filter: 870 us against 720 us, though 1 % ahead in
 # the trials).  They stay available as explicit options.
-DEFAULT_CANDIDATES = [("flat", 0), ("flat", 1024), ("flat", 512), ("dedup", 0)]
+DEFAULT_CANDIDATES = [("flat", 0), ("flat", 1024), ("flat", 512), ("dedup", 0),
+                      ("partition", 0)]
+PARTITION_MAX_LE = 1 << 25
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "srla_autotune.json")
 
 
@@ -58,8 +61,8 @@ def _save(path, table):
 
 
 def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False):
-    """Returns {"scan_xcd": bool, "scan_dedup": bool, "scan_blocks": int,
-    "ms": float, "all": {...}}
+    """Returns {"scan_xcd": bool, "scan_dedup": bool, "scan_lds_filter": bool,
+    "scan_partition": bool, "scan_blocks": int, "ms": float, "all": {...}}
     for monitors of geometry `cfg` (Monitor keyword arguments) scanning
     `pairs` (a CUDA tensor of 2n values, or a list of such tensors of equal
     size, used in turn) per call."""
@@ -71,10 +74,13 @@ def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False
         return table[key]
     results = {}
     for form, blocks in candidates or DEFAULT_CANDIDATES:
+        if form == "partition" and cfg["u"] * cfg["v_le"] * cfg["G"] > PARTITION_MAX_LE:
+            continue
         m = srla.Monitor(**cfg, max_candidates=min(1 << 22, 4 * n_pairs + 64), timing=True,
                          scan_xcd=form in ("xcd", "xcd_dedup"),
                          scan_dedup=form in ("dedup", "xcd_dedup"),
                          scan_lds_filter=form == "filter",
+                         scan_partition=form == "partition",
                          scan_blocks=blocks, lean_report=True)
         m.scan(bufs[0])                  # warm the footprint
         m.estimate(copy=False)
@@ -91,6 +97,7 @@ def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False
     choice = {"scan_xcd": form in ("xcd", "xcd_dedup"),
               "scan_dedup": form in ("dedup", "xcd_dedup"),
               "scan_lds_filter": form == "filter",
+              "scan_partition": form == "partition",
               "scan_blocks": int(blocks), "ms": results[best], "all": results}
     if cache:
         table = _load(cache)

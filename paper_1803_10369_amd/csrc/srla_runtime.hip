@@ -34,6 +34,7 @@
 #include "srla_discrete.h"
 #include "srla_scan_dedup.h"
 #include "srla_scan_filter.h"
+#include "srla_scan_part.h"
 #include "srla_internal.h"
 
 using namespace srla;
@@ -79,13 +80,16 @@ bool config_ok(const srla_config_t* c) {
   if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH |
                               SRLA_CFG_DISCRETE | SRLA_CFG_LEAN_REPORT |
                               SRLA_CFG_SCAN_DEDUP | SRLA_CFG_SCAN_LDS_FILTER |
-                              SRLA_CFG_OVERLAP_REPORT)) != 0)
+                              SRLA_CFG_OVERLAP_REPORT | SRLA_CFG_SCAN_PARTITION)) != 0)
     return false;
   if ((c->flags & SRLA_CFG_DISCRETE) && c->window_slices != 1) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   if (le / g.u / g.g_le != g.v_le || re / g.u / g.g != g.v_re) return false;
   if (le > (1ull << 40) || re > (1ull << 40)) return false;
+  if ((c->flags & SRLA_CFG_SCAN_PARTITION) && !(c->flags & SRLA_CFG_DISCRETE) &&
+      !part_scan_fits(le))
+    return false;
   return true;
 }
 
@@ -118,6 +122,9 @@ struct srla_monitor {
 
   // SEA and its per-slice views
   uint16_t* le = nullptr;        // stamps (not allocated in the discrete form)
+  uint16_t* part_entries = nullptr;   // partitioned scan: sorted LE DR indices
+  uint16_t* part_offs = nullptr;      //   their region offsets
+  uint32_t* part_marks = nullptr;     //   and the marking bitmaps
   uint16_t* re = nullptr;
   bool discrete = false;         // k = 1 with one bit per DR
   uint64_t* lebits[2] = {nullptr, nullptr};  // discrete form: LE / SRE bits by slice parity
@@ -203,6 +210,7 @@ struct srla_monitor {
   bool xcd_scan = false;
   bool dedup_scan = false;
   bool filter_scan = false;
+  bool part_scan = false;
   std::vector<TimedSpan> spans;
   std::vector<hipEvent_t> ev_pool;
   double acc_ms[ST_N] = {0, 0, 0, 0, 0, 0};
@@ -545,6 +553,7 @@ void release(srla_monitor* m) {
   collect_spans(m, true);
   drop_graphs(m);
   dfree(m->le); dfree(m->re); dfree(m->si_cnt);
+  dfree(m->part_entries); dfree(m->part_offs); dfree(m->part_marks);
   for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); dfree(m->sset[i]); } dfree(m->bitmap); dfree(m->act);
   dfree(m->row_fill); dfree(m->up); dfree(m->cnt); dfree(m->ps);
   dfree(m->tcount);
@@ -596,7 +605,11 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
            16 * (uint64_t)source_set_slots(cfg->max_candidates) + 64 * si + 8 * g.u + 8 +
            staging_bytes(cfg) +
            sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 + candidate_bytes(cfg->max_candidates);
-  return staging_bytes(cfg) + 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
+  const uint64_t part = (cfg->flags & SRLA_CFG_SCAN_PARTITION)
+                            ? 2 * (part_entry_words() + part_offset_words(le)) +
+                                  4 * part_mark_words(le)
+                            : 0;
+  return part + staging_bytes(cfg) + 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
          8 * g.u + 8 + sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 +
          candidate_bytes(cfg->max_candidates);
 }
@@ -628,6 +641,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->discrete = (cfg->flags & SRLA_CFG_DISCRETE) != 0;
   m->dedup_scan = (cfg->flags & SRLA_CFG_SCAN_DEDUP) != 0;
   m->filter_scan = (cfg->flags & SRLA_CFG_SCAN_LDS_FILTER) != 0;
+  m->part_scan = (cfg->flags & SRLA_CFG_SCAN_PARTITION) != 0 && !m->discrete;
   m->overlap_report = (cfg->flags & SRLA_CFG_OVERLAP_REPORT) != 0;
 
   const srla_geometry_t& g = cfg->geom;
@@ -695,6 +709,9 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     if (!rc) nomem(dalloc(&m->re, m->n_re + 8));
     if (!rc) nomem(dalloc(&m->bitmap, bitmap_words(m->n_le)));
     if (!rc) nomem(dalloc(&m->act, 2 * bitmap_words(m->n_re)));
+    if (!rc && m->part_scan) nomem(dalloc(&m->part_entries, part_entry_words()));
+    if (!rc && m->part_scan) nomem(dalloc(&m->part_offs, part_offset_words(m->n_le)));
+    if (!rc && m->part_scan) nomem(dalloc(&m->part_marks, part_mark_words(m->n_le)));
   }
   if (!rc) nomem(dalloc(&m->si_cnt, 16 * m->n_si));
   if (!rc) nomem(dalloc(&m->row_fill, g.u));
@@ -797,7 +814,7 @@ namespace {
 hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int p,
                         uint32_t mark) {
   const uint16_t code = stamp_code(m->slice);
-  if (mark != 0u && (m->discrete || m->dedup_scan || m->filter_scan)) {
+  if (mark != 0u && (m->discrete || m->part_scan || m->dedup_scan || m->filter_scan)) {
     const hipError_t e = launch_mark_scan(m->started, mark, m->stream);
     if (e != hipSuccess) return e;
   }
@@ -805,6 +822,10 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
     return launch_scan_bits(pairs, n, m->geo, m->lebits[p], m->rebits[p], m->sset[p],
                             m->set_slots, m->touched[p], m->tcount + p, m->cfg.scan_blocks,
                             m->stream);
+  if (m->part_scan)
+    return launch_scan_partition(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
+                                 m->tcount + p, m->part_entries, m->part_offs, m->part_marks,
+                                 m->stream);
   if (m->dedup_scan)
     return launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                              m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream);

@@ -86,7 +86,7 @@ def test_invalid_configs_are_rejected_without_a_device(P, bad):
 def test_bad_flags_and_capacity_rejected(P):
     cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, max_candidates=0)
     assert P.srla_create(cfg)[0] == -1
-    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=256)
+    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=512)
     assert P.srla_create(cfg)[0] == -1
     lean = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=P.srla.SRLA_CFG_LEAN_REPORT)
     assert P.srla_footprint_bytes(lean) > 0
@@ -177,3 +177,21 @@ def test_admission_is_first_fit_under_the_budget(P):
     assert all(adm) and used == sum(fps[:3])
     bad = P.make_config(0, 1, 1, 1, 1, 1, 64, 0)
     assert P.srla_admit([cfgs[0], bad], budget)[0] == -1
+
+
+def test_partition_scan_needs_a_small_enough_le(P):
+    """The partitioned scan takes at most 2^25 LE DRs (1024 regions of 2^15)
+    and counts its scratch in the footprint."""
+    part = P.srla.SRLA_CFG_SCAN_PARTITION
+    plain = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1)
+    cfg = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1, flags=part)
+    extra = P.srla_footprint_bytes(cfg) - P.srla_footprint_bytes(plain)
+    assert extra == 2 * (2048 * 32768 + (512 + 1) * 2048) + 4 * 512 * 16 * 1024
+    big = P.make_config(300, 1024, 4, 65536, 8, 65536, 1024, 1, max_candidates=1, flags=part)
+    assert P.srla_footprint_bytes(big) == 0
+    rc, h = P.srla_create(big)
+    assert rc == -1 and not h.value
+    # the discrete form has no LE stamps: the flag has no effect there
+    disc = P.make_config(1, 1024, 4, 65536, 8, 65536, 1024, 1, max_candidates=1,
+                         flags=part | P.srla.SRLA_CFG_DISCRETE)
+    assert P.srla_footprint_bytes(disc) > 0

@@ -26,9 +26,11 @@ def _gpu():
 
 
 def _run(stream, mon, slices, max_candidates=1 << 16, dump_every=1, split=None, host=False,
-         scan_xcd=False, graph=False, discrete=False, scan_dedup=False, scan_lds_filter=False):
+         scan_xcd=False, graph=False, discrete=False, scan_dedup=False, scan_lds_filter=False,
+         scan_partition=False):
     g = srla.Monitor(**mon, max_candidates=max_candidates, scan_xcd=scan_xcd, graph=graph,
-                     discrete=discrete, scan_dedup=scan_dedup, scan_lds_filter=scan_lds_filter)
+                     discrete=discrete, scan_dedup=scan_dedup, scan_lds_filter=scan_lds_filter,
+                     scan_partition=scan_partition)
     o = oracle.Monitor(**mon)
     for s in slices:
         pairs = stream.slice(s) if hasattr(stream, "slice") else stream(s)
@@ -119,13 +121,15 @@ def test_small_geometries(case, scan_xcd, graph):
 
 
 def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chunks=1,
-                   discrete=False, scan_dedup=False, overlap_report=False, ahead=False):
+                   discrete=False, scan_dedup=False, overlap_report=False, ahead=False,
+                   scan_partition=False):
     """The next slice is scanned before the previous slice's report is taken;
     ahead: it is also closed before that report is taken (two reports pending),
     and a collected report's arrays (views, no copy) must hold until the slice
     two after it is closed."""
     g = srla.Monitor(**mon, max_candidates=max_candidates, graph=graph, discrete=discrete,
-                     scan_dedup=scan_dedup, overlap_report=overlap_report)
+                     scan_dedup=scan_dedup, overlap_report=overlap_report,
+                     scan_partition=scan_partition)
     o = oracle.Monitor(**mon)
     expected = []
     slices = list(slices)
@@ -488,11 +492,14 @@ def test_autotuner_picks_a_valid_shape_and_results_do_not_change(tmp_path):
     pairs = to_device(stream.slice(0))
     cache = str(tmp_path / "tune.json")
     choice = autotune.tune_scan(mon, pairs, repeats=2, cache=cache)
-    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "dedup/0"}
+    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "dedup/0", "partition/0"}
     assert choice["ms"] == min(choice["all"].values()) > 0
     assert autotune.tune_scan(mon, pairs, cache=cache) == choice      # served from the cache
     _run(stream, mon, range(6), scan_xcd=choice["scan_xcd"], scan_dedup=choice["scan_dedup"],
-         scan_lds_filter=choice["scan_lds_filter"])
+         scan_lds_filter=choice["scan_lds_filter"], scan_partition=choice["scan_partition"])
+    # the partitioned form is not tried where the LE is too large for it
+    big = dict(mon, v_le=1 << 14, G=4096)
+    assert "partition/0" not in autotune.tune_scan(big, pairs, repeats=1, cache=None)["all"]
     # every form can still be asked for explicitly
     forms = [("xcd", 0), ("xcd_dedup", 16), ("filter", 0)]
     extra = autotune.tune_scan(mon, pairs, candidates=forms, repeats=1, cache=None)
@@ -700,3 +707,41 @@ def test_group_rejects_overlapped_report_monitors():
         srla.Group([a, b])
     a.close()
     b.close()
+
+
+# ------------------------------------------------------------ partitioned scan
+# SRLA_CFG_SCAN_PARTITION sorts each chunk's LE DR indices by region and
+# stamps every region from one workgroup: same DR arrays, same reports.
+
+@pytest.mark.parametrize("case", SMALL)
+def test_partition_scan_small_geometries(case):
+    k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
+    mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=7000 + k + u)
+    _run(_rand_stream(k + u + 31, n, n_src, 3 * theta // 2), mon, range(slices),
+         scan_partition=True)
+
+
+def test_partition_scan_tiny_host_input_split_and_streaming():
+    stream, mon, n = workload("tiny")
+    _run(stream, mon, range(n), scan_partition=True, host=True, split=40001)
+    _run(stream, mon, range(n), scan_partition=True, split=777)
+    _run_streaming(stream, mon, range(n), graph=True, chunks=3, scan_partition=True,
+                   overlap_report=True, ahead=True)
+
+
+def test_partition_scan_several_rounds_in_one_scan():
+    """u = 16: a chunk holds 2,048 pairs, so 5M pairs in one scan take three
+    partition rounds of at most 2,048 chunks."""
+    mon = dict(k=4, theta=1024, u=16, v_re=4096, g=8, v_le=64, G=1024, hash_seed=77)
+    _run(_rand_stream(99, 5_000_000, 200_000, 1536), mon, range(3), max_candidates=1 << 20,
+         scan_partition=True)
+
+
+def test_partition_scan_backbone_full_size_and_expiry():
+    stream, mon, _ = workload("backbone")
+    _run(stream, mon, range(3), max_candidates=1 << 22, dump_every=0, scan_partition=True)
+    _run_streaming(stream, mon, range(3), max_candidates=1 << 22, graph=True,
+                   overlap_report=True, ahead=True, scan_partition=True)
+    stream, mon, _ = workload("backbone_k16")
+    stream = scaled(stream, 600_000)
+    _run(stream, mon, range(20), max_candidates=1 << 22, dump_every=7, scan_partition=True)
