@@ -254,11 +254,6 @@ def run_discrete(args):
     torch.cuda.set_stream(st)
     if args.calib_copy_mb:
         calibration_copy(args.calib_copy_mb)
-    # the streaming form overlaps only the report's PCIe copy with the next
-    # slice's scans when the scan is the flat one; the partitioned scan leaves
-    # the cache to the candidate work, which then runs beside the scans whole
-    overlap = ((args.mode == "streaming" and not args.scan_partition)
-               if args.overlap_report < 0 else bool(args.overlap_report))
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      discrete=True, graph=args.graph > 0, scan_blocks=args.scan_blocks,
                      lean_report=not args.full_report)
@@ -540,6 +535,11 @@ def main():
         args.scan_dedup = tuned["scan_dedup"]
         args.scan_lds_filter = tuned["scan_lds_filter"]
         args.scan_partition = tuned["scan_partition"]
+    # the streaming form overlaps only the report's PCIe copy with the next
+    # slice's scans when the scan is the flat one; the partitioned scan leaves
+    # the cache to the candidate work, which then runs beside the scans whole
+    overlap = ((args.mode == "streaming" and not args.scan_partition)
+               if args.overlap_report < 0 else bool(args.overlap_report))
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks,
                      lean_report=not args.full_report, scan_dedup=args.scan_dedup,
@@ -617,7 +617,7 @@ def main():
     scan_ms = tm["scan_ms"] / max(1, tm["scan_launches"])
     per_launch_bytes = scan_bytes_per_pair(g["u"], tau) * n_pairs
     achieved = per_launch_bytes / (scan_ms * 1e-3) / 1e9
-    scan_kernel = ("k_scan_part+k_scan_apply" if args.scan_partition else
+    scan_kernel = ("k_scan_partition" if args.scan_partition else
                    "k_scan_dedup" if args.scan_dedup else
                    "k_scan_lds_filter" if args.scan_lds_filter else
                    "k_scan_xcd" if args.scan_xcd else "k_scan_flat")
@@ -663,7 +663,9 @@ def main():
                   "row_fill_frac": [float(x) / (g["v_le"] * g["G"]) for x in r.row_fill],
                   "n_touched": int(r.n_touched), "n_new": int(r.n_new)},
         "roofline": {
-            "kernel": "%s (Algorithm 2)" % scan_kernel,
+            "kernel": ("k_scan_partition (k_scan_part + k_scan_mark + k_scan_stamp, "
+                       "Algorithm 2)" if args.scan_partition else
+                       "%s (Algorithm 2)" % scan_kernel),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

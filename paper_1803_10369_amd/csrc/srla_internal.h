@@ -82,10 +82,15 @@ struct Counters {
 // Device-resident state the end-of-slice pipeline reads instead of host
 // arguments, so one recorded pipeline serves every slice of a parity.
 struct PipeState {
-  uint32_t now;          // stamp code of the slice being closed
+  uint32_t now;          // stamp code of the slice whose candidate work is next
   uint32_t n_ncsip;      // |NCSIP| carried into it
   uint64_t slice;        // its index
-  uint64_t t_close;      // device wall clock when its end-of-slice work began
+  uint64_t t_close[2];   // device wall clock when the end-of-slice work of the
+                         // last closed slice of each parity began
+  uint32_t snap;         // stamp code of the slice snapshotted last (0: none yet);
+                         // the snapshot keeps its own count so that it need not
+                         // wait for the previous slice's candidate work
+  uint32_t pad;
 };
 
 // Pinned host block the status kernel fills at the end of every slice.
@@ -203,10 +208,10 @@ hipError_t launch_mark_scan(uint32_t* started, uint32_t value, hipStream_t st);
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
                             uint32_t* si_cnt, const Geo& geo, hipStream_t st);
 
-// records the device wall clock at the start of the end-of-slice work and
-// clears the row fills
+// records the device wall clock at the start of the end-of-slice work of a
+// slice of parity p, advances the snapshot's stamp code and clears the row fills
 hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t u,
-                              hipStream_t st);
+                              uint32_t p, hipStream_t st);
 // records the device wall clock once the report is complete in host memory
 hipError_t launch_mark_done(HostStatus* out, hipStream_t st);
 // publishes the slice's counters, Eq8 and row fills to the host (and the
@@ -215,6 +220,6 @@ hipError_t launch_mark_done(HostStatus* out, hipStream_t st);
 // sampled-source count of its parity)
 hipError_t launch_status(Counters* cnt, uint32_t* tcount, const double* up,
                          const unsigned long long* row_fill, uint32_t u, PipeState* ps,
-                         HostStatus* out, uint32_t* report_n, hipStream_t st);
+                         uint32_t p, HostStatus* out, uint32_t* report_n, hipStream_t st);
 
 }  // namespace srla

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
                                                     uint64_t row_cells,
                                                     const PipeState* __restrict__ ps,
                                                     uint32_t k) {
-  const uint32_t now = ps->now;
+  const uint32_t now = ps->snap;   // the slice being snapshotted
   // The window's stamp codes form one interval on the circle of codes: a
   // nonzero cell c is inside iff (c - lo) mod 2^16 <= w, with lo the code of
   // slice e-k+1 (the interval may pass over the unused code 0, which widens w
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, 
                                                     uint32_t u, uint32_t G, uint32_t v_le,
                                                     double* __restrict__ up) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *up = eq8(row_fill, u, G, v_le);
-  const uint32_t now = ps->now;
+  const uint32_t now = ps->snap;   // the slice being snapshotted
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint64_t c8 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 8;
   uint32_t m_now = 0, m_next = 0;
@@ -667,7 +667,7 @@ hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const C
 __global__ void k_status(Counters* __restrict__ cnt, uint32_t* __restrict__ tcount,
                          const double* __restrict__ up,
                          const unsigned long long* __restrict__ row_fill, uint32_t u,
-                         PipeState* __restrict__ ps, HostStatus* __restrict__ out,
+                         PipeState* __restrict__ ps, uint32_t p, HostStatus* __restrict__ out,
                          uint32_t* __restrict__ report_n) {
   if (blockIdx.x != 0) return;
   const uint32_t t = threadIdx.x;
@@ -678,7 +678,7 @@ __global__ void k_status(Counters* __restrict__ cnt, uint32_t* __restrict__ tcou
   if (t == 0) {
     out->up = *up;
     out->slice = ps->slice;
-    out->t_close = ps->t_close;
+    out->t_close = ps->t_close[p];
     out->t_done = wall_clock64();   // every earlier kernel of the report has finished
     if (report_n) *report_n = c.n_cand;
   }
@@ -761,15 +761,18 @@ hipError_t launch_mark_scan(uint32_t* started, uint32_t value, hipStream_t st) {
 }
 
 __global__ void k_begin_close(PipeState* __restrict__ ps, unsigned long long* __restrict__ row_fill,
-                              uint32_t u) {
+                              uint32_t u, uint32_t p) {
   if (blockIdx.x != 0) return;
-  if (threadIdx.x == 0) ps->t_close = wall_clock64();
+  if (threadIdx.x == 0) {
+    ps->t_close[p] = wall_clock64();
+    ps->snap = ps->snap % kStampPeriod + 1u;
+  }
   for (uint32_t i = threadIdx.x; i < u; i += blockDim.x) row_fill[i] = 0ull;
 }
 
 hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t u,
-                              hipStream_t st) {
-  hipLaunchKernelGGL(k_begin_close, dim3(1), dim3(64), 0, st, ps, row_fill, u);
+                              uint32_t p, hipStream_t st) {
+  hipLaunchKernelGGL(k_begin_close, dim3(1), dim3(64), 0, st, ps, row_fill, u, p);
   return hipGetLastError();
 }
 
@@ -784,9 +787,9 @@ hipError_t launch_mark_done(HostStatus* out, hipStream_t st) {
 
 hipError_t launch_status(Counters* cnt, uint32_t* tcount, const double* up,
                          const unsigned long long* row_fill, uint32_t u, PipeState* ps,
-                         HostStatus* out, uint32_t* report_n, hipStream_t st) {
-  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, cnt, tcount, up, row_fill, u, ps, out,
-                     report_n);
+                         uint32_t p, HostStatus* out, uint32_t* report_n, hipStream_t st) {
+  hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, cnt, tcount, up, row_fill, u, ps, p,
+                     out, report_n);
   return hipGetLastError();
 }
 

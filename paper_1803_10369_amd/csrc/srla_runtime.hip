@@ -133,10 +133,12 @@ struct srla_monitor {
   uint32_t set_slots = 0;
   uint32_t* si_cnt = nullptr;    // [u][v_re][16] counters; SI bit = counter > 0
   uint64_t n_le = 0, n_re = 0, n_si = 0;
-  uint64_t* bitmap = nullptr;    // LE DRs inside the window
-  uint64_t* act = nullptr;       // SRE DRs inside the window / after the slide, interleaved
-  unsigned long long* row_fill = nullptr;
-  double* up = nullptr;
+  // the snapshot of a closed slice, by slice parity: the next slice's
+  // snapshot may run while this one's candidate work still reads it
+  uint64_t* bitmap[2] = {nullptr, nullptr};   // LE DRs inside the window
+  uint64_t* act[2] = {nullptr, nullptr};      // SRE DRs inside the window / after the slide
+  unsigned long long* row_fill[2] = {nullptr, nullptr};
+  double* up[2] = {nullptr, nullptr};
   Counters* cnt = nullptr;
   PipeState* ps = nullptr;
   uint32_t* tcount = nullptr;    // [2] sampled-source counts by slice parity
@@ -425,21 +427,22 @@ hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
-  e = launch_begin_close(m->ps, m->row_fill, geo.u, st);
+  e = launch_begin_close(m->ps, m->row_fill[p], geo.u, (uint32_t)p, st);
   if (e != hipSuccess) return e;
   if (m->discrete) {
     // the closing slice's bits are its activity maps already; the other
     // parity's (the previous slice's) are cleared for the next slice's scans
-    if (e == hipSuccess) e = launch_row_popcount(m->lebits[p], m->row_fill, geo, st);
-    if (e == hipSuccess) e = launch_union_prob(m->row_fill, geo, m->up, st);
+    if (e == hipSuccess) e = launch_row_popcount(m->lebits[p], m->row_fill[p], geo, st);
+    if (e == hipSuccess) e = launch_union_prob(m->row_fill[p], geo, m->up[p], st);
     if (e == hipSuccess)
       e = launch_fill_u32((uint32_t*)m->lebits[p ^ 1], 0u, 2 * bitmap_words(m->n_le), st);
     if (e == hipSuccess)
       e = launch_fill_u32((uint32_t*)m->rebits[p ^ 1], 0u, 4 * bitmap_words(m->n_re), st);
   } else {
-    if (e == hipSuccess) e = launch_sweep_le(m->le, m->bitmap, m->row_fill, geo, m->ps, st);
     if (e == hipSuccess)
-      e = launch_sweep_re(m->re, m->n_re, m->act, geo, m->ps, m->row_fill, m->up, st);
+      e = launch_sweep_le(m->le, m->bitmap[p], m->row_fill[p], geo, m->ps, st);
+    if (e == hipSuccess)
+      e = launch_sweep_re(m->re, m->n_re, m->act[p], geo, m->ps, m->row_fill[p], m->up[p], st);
   }
   if (spans) span_end(m, st, ST_SWEEP, ta);
   return e;
@@ -452,8 +455,8 @@ hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hip
   const Geo& geo = m->geo;
   hipError_t e = hipSuccess;
   uint32_t* tc = m->tcount + p;
-  const uint64_t* le_act = m->discrete ? m->lebits[p] : m->bitmap;
-  const uint64_t* re_act = m->discrete ? m->rebits[p] : m->act;
+  const uint64_t* le_act = m->discrete ? m->lebits[p] : m->bitmap[p];
+  const uint64_t* re_act = m->discrete ? m->rebits[p] : m->act[p];
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
@@ -471,7 +474,7 @@ hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hip
   if (e == hipSuccess)
     e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
   if (e == hipSuccess)
-    e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->up, geo, m->cflags, out, st);
+    e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->up[p], geo, m->cflags, out, st);
   if (spans) span_end(m, st, ST_ESTIMATE, ta);
   if (spans) span_begin(m, st, &ta);
   if (e == hipSuccess)
@@ -500,7 +503,8 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
       e = enqueue_candidates(m, p, m->d_staging[p], st);
       if (spans) span_begin(m, st, &ta);
       if (e == hipSuccess)
-        e = launch_status(m->cnt, m->tcount + p, m->up, m->row_fill, m->geo.u, m->ps,
+        e = launch_status(m->cnt, m->tcount + p, m->up[p], m->row_fill[p], m->geo.u, m->ps,
+                          (uint32_t)p,
                           m->d_status[p], m->report_n + p, st);
       if (spans) span_end(m, st, ST_SLIDE, ta);
     }
@@ -516,7 +520,8 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
                              st);
     if (e == hipSuccess) e = launch_mark_done(m->d_status[p], st);
   } else if (e == hipSuccess) {
-    e = launch_status(m->cnt, m->tcount + p, m->up, m->row_fill, m->geo.u, m->ps, m->d_status[p],
+    e = launch_status(m->cnt, m->tcount + p, m->up[p], m->row_fill[p], m->geo.u, m->ps,
+                      (uint32_t)p, m->d_status[p],
                       nullptr, st);
   }
   if (spans) span_end(m, st, ST_REPORT, ta);
@@ -554,8 +559,10 @@ void release(srla_monitor* m) {
   drop_graphs(m);
   dfree(m->le); dfree(m->re); dfree(m->si_cnt);
   dfree(m->part_entries); dfree(m->part_offs); dfree(m->part_marks);
-  for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); dfree(m->sset[i]); } dfree(m->bitmap); dfree(m->act);
-  dfree(m->row_fill); dfree(m->up); dfree(m->cnt); dfree(m->ps);
+  for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); dfree(m->sset[i]); } 
+  for (int i = 0; i < 2; ++i) { dfree(m->bitmap[i]); dfree(m->act[i]); }
+  for (int i = 0; i < 2; ++i) { dfree(m->row_fill[i]); dfree(m->up[i]); }
+  dfree(m->cnt); dfree(m->ps);
   dfree(m->tcount);
   dfree(m->claim);
   dfree(m->started);
@@ -602,15 +609,15 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
   const uint64_t si = (uint64_t)g.u * g.v_re;
   if (cfg->flags & SRLA_CFG_DISCRETE)
     return 16 * bitmap_words(le) + 32 * bitmap_words(re) +
-           16 * (uint64_t)source_set_slots(cfg->max_candidates) + 64 * si + 8 * g.u + 8 +
+           16 * (uint64_t)source_set_slots(cfg->max_candidates) + 64 * si + 16 * g.u + 16 +
            staging_bytes(cfg) +
            sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 + candidate_bytes(cfg->max_candidates);
   const uint64_t part = (cfg->flags & SRLA_CFG_SCAN_PARTITION)
                             ? 2 * (part_entry_words() + part_offset_words(le)) +
                                   4 * part_mark_words(le)
                             : 0;
-  return part + staging_bytes(cfg) + 2 * le + 8 * bitmap_words(le) + 2 * (re + 8) + 16 * bitmap_words(re) + 64 * si +
-         8 * g.u + 8 + sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 +
+  return part + staging_bytes(cfg) + 2 * le + 16 * bitmap_words(le) + 2 * (re + 8) +
+         32 * bitmap_words(re) + 64 * si + 16 * g.u + 16 + sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 +
          candidate_bytes(cfg->max_candidates);
 }
 
@@ -707,15 +714,19 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   } else {
     nomem(dalloc(&m->le, m->n_le));
     if (!rc) nomem(dalloc(&m->re, m->n_re + 8));
-    if (!rc) nomem(dalloc(&m->bitmap, bitmap_words(m->n_le)));
-    if (!rc) nomem(dalloc(&m->act, 2 * bitmap_words(m->n_re)));
+    for (int i = 0; i < 2 && !rc; ++i) {
+      nomem(dalloc(&m->bitmap[i], bitmap_words(m->n_le)));
+      if (!rc) nomem(dalloc(&m->act[i], 2 * bitmap_words(m->n_re)));
+    }
     if (!rc && m->part_scan) nomem(dalloc(&m->part_entries, part_entry_words()));
     if (!rc && m->part_scan) nomem(dalloc(&m->part_offs, part_offset_words(m->n_le)));
     if (!rc && m->part_scan) nomem(dalloc(&m->part_marks, part_mark_words(m->n_le)));
   }
   if (!rc) nomem(dalloc(&m->si_cnt, 16 * m->n_si));
-  if (!rc) nomem(dalloc(&m->row_fill, g.u));
-  if (!rc) nomem(dalloc(&m->up, 1));
+  for (int i = 0; i < 2 && !rc; ++i) {
+    nomem(dalloc(&m->row_fill[i], g.u));
+    if (!rc) nomem(dalloc(&m->up[i], 1));
+  }
   if (!rc) nomem(dalloc(&m->cnt, 1));
   if (!rc) nomem(dalloc(&m->ps, 1));
   if (!rc) nomem(dalloc(&m->tcount, 2));
@@ -977,16 +988,17 @@ int srla_close_slice(srla_monitor_t* m) {
   const int p = (int)(m->slice & 1);
   m->timed[p] = m->timing;
   // the previous slice's second phase is enqueued first; then the scan stream
-  // waits for the work this slice's first phase would overwrite: without the
-  // overlapped report, the previous slice's second phase (the candidate state:
-  // counters, carried list, activity maps); with it, the report copy of the
-  // slice two back (it reads the staging set this slice writes), normally
-  // long finished
+  // waits for the work this slice's first phase would overwrite: with the
+  // overlapped report, the report copy of the slice two back (it reads the
+  // staging set this slice writes), normally long finished; in the discrete
+  // form, the previous slice's second phase (the snapshot clears the bits it
+  // reads).  Otherwise the snapshot writes its parity's arrays only, which
+  // the slice two back has finished with (see below), and runs at once.
   if (m->finish_deferred) {
     const int rc = enqueue_finish(m, false);
     if (rc) return rc;
   }
-  if (m->overlap_report ? m->slice >= 2 : m->slice >= 1)
+  if (m->overlap_report ? m->slice >= 2 : (m->discrete && m->slice >= 1))
     HIP_TRY(m, wait_unless_done(m->stream, m->ev_done[m->overlap_report ? p : p ^ 1]));
   // with graphs, each phase is timed as a whole: the first as the sweeps
   // (with the candidate work when the report copy overlaps the next scans),
@@ -997,6 +1009,10 @@ int srla_close_slice(srla_monitor_t* m) {
   if (rc) return rc;
   if (m->use_graph) span_end(m, m->stream, m->overlap_report ? ST_ESTIMATE : ST_SWEEP, ta);
   HIP_TRY(m, hipEventRecord(m->ev_snap, m->stream));
+  // the next slice's scans reuse the sampled-source list and count of the
+  // previous slice's parity: they wait for its second phase
+  if (!m->overlap_report && !m->discrete && m->slice >= 1)
+    HIP_TRY(m, wait_unless_done(m->stream, m->ev_done[p ^ 1]));
   m->n_pending++;
   m->slice++;
   m->slice_pairs[m->slice & 1] = 0;

@@ -100,9 +100,9 @@ def test_footprint_counts_dr_arrays(P):
     cfg = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1)
     fp = P.srla_footprint_bytes(cfg)
     le_cells, re_cells, ses = 1 << 24, 1 << 23, 8 * 131072
-    # uint16 stamps, one activity bit per LE DR, two per SRE DR, 16 x uint32
-    # SI counters per SE
-    want = 2 * le_cells + le_cells // 8 + 2 * re_cells + 2 * re_cells // 8 + 64 * ses
+    # uint16 stamps, one activity bit per LE DR and two per SRE DR for each
+    # slice parity, 16 x uint32 SI counters per SE
+    want = 2 * le_cells + 2 * le_cells // 8 + 2 * re_cells + 4 * re_cells // 8 + 64 * ses
     assert want <= fp < want + 4096
     big = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1 << 20)
     assert P.srla_footprint_bytes(big) - fp >= 13 * ((1 << 20) - 1)
