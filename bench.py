@@ -85,16 +85,18 @@ def cpu_model():
 
 
 def oracle_baseline(stream, mon, slices):
-    """Times the oracle (single-threaded C) on the first `slices` slices."""
+    """Times the oracle (single-threaded C) on the first `slices` slices; each
+    slice's pairs are generated outside the timed calls."""
     import oracle
     o = oracle.Monitor(**mon)
-    pairs = [stream.slice(s) for s in range(slices)]
-    t0 = time.perf_counter()
-    for p in pairs:
+    dt, n = 0.0, 0
+    for s in range(slices):
+        p = stream.slice(s)
+        t0 = time.perf_counter()
         o.scan(p)
         o.estimate()
-    dt = time.perf_counter() - t0
-    n = sum(len(p) for p in pairs)
+        dt += time.perf_counter() - t0
+        n += len(p)
     o.close()
     return n / dt, dt, n
 
@@ -459,8 +461,9 @@ def main():
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--workload", default="backbone")
-    ap.add_argument("--cpu-slices", type=int, default=2,
-                    help="slices of the same workload the oracle baseline scans")
+    ap.add_argument("--cpu-slices", type=int, default=30,
+                    help="slices of the same workload the oracle baseline scans "
+                         "(about 10 s of CPU work for the backbone workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-candidates", type=int, default=1 << 25)
     ap.add_argument("--budget-gb", type=float, default=200.0,
@@ -585,17 +588,21 @@ def main():
                 r = m.estimate(copy=False)   # returns with the report in host memory
                 lat.append((time.perf_counter() - ts) * 1e3)
         else:
-            # the host runs one slice ahead: slice i is scanned and closed before
-            # the report of slice i-1 is collected (two reports may be pending);
-            # the latency is the device's own, from the start of a slice's
+            # the host runs ahead: slice i is closed and slice i+1's scan is
+            # enqueued before the report of slice i-1 is collected (two reports
+            # may be pending), so the device never waits for the host; the
+            # latency is the device's own, from the start of a slice's
             # end-of-slice work, right after its last scan, to its report in
             # host memory
             m.scan(seg_bufs[0])
             m.close_slice()
+            if seg > 1:
+                m.scan(seg_bufs[1])
             for i in range(1, seg + 1):
                 if i < seg:
-                    m.scan(seg_bufs[i])      # runs while slice i-1 is estimated
                     m.close_slice()
+                    if i + 1 < seg:
+                        m.scan(seg_bufs[i + 1])   # runs while slice i is estimated
                 r = m.wait_report(copy=False)
                 lat.append(r.latency_ms)
         torch.cuda.synchronize()

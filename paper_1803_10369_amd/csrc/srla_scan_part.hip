@@ -235,19 +235,25 @@ __global__ __launch_bounds__(kApplyThreads) void k_scan_mark(
     }
     const uint32_t in_group = w_hi - g0 < kWave ? w_hi - g0 : kWave;
     for (uint32_t b0 = 0; b0 < in_group; b0 += kApplySegs) {   // uniform per wave
-      uint32_t slo[kApplySegs], slen[kApplySegs], most = 0;
+      // segment t covers entries [al[t] + off[t], al[t] + end[t]) of the
+      // chunk, al[t] rounded down to 64 entries, so that one load instruction
+      // reads one aligned 128-byte line of a segment
+      uint32_t al[kApplySegs], off[kApplySegs], end[kApplySegs], most = 0;
 #pragma unroll
       for (uint32_t t = 0; t < kApplySegs; ++t) {   // b0 + t < 64; lanes past w_hi have len 0
-        slo[t] = (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)(b0 + t));
-        slen[t] = (uint32_t)__builtin_amdgcn_readlane((int)len, (int)(b0 + t));
-        most = slen[t] > most ? slen[t] : most;
+        const uint32_t slo = (uint32_t)__builtin_amdgcn_readlane((int)lo, (int)(b0 + t));
+        const uint32_t slen = (uint32_t)__builtin_amdgcn_readlane((int)len, (int)(b0 + t));
+        al[t] = slo & ~(kWave - 1u);
+        off[t] = slo - al[t];
+        end[t] = slen ? off[t] + slen : 0u;
+        most = end[t] > most ? end[t] : most;
       }
       for (uint32_t k = lane; k - lane < most; k += kWave) {   // uniform per wave
         uint32_t e[kApplySegs];
 #pragma unroll
         for (uint32_t t = 0; t < kApplySegs; ++t)
-          e[t] = k < slen[t]
-                     ? (uint32_t)entries[(uint64_t)(g0 + b0 + t) * kPartEntries + slo[t] + k]
+          e[t] = (k >= off[t] && k < end[t])
+                     ? (uint32_t)entries[(uint64_t)(g0 + b0 + t) * kPartEntries + al[t] + k]
                      : 0xFFFFFFFFu;
 #pragma unroll
         for (uint32_t t = 0; t < kApplySegs; ++t) {
