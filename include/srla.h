@@ -107,7 +107,7 @@ enum {
                                   going out one 2-byte store at a time.
                                   Results are identical.  Requires at most
                                   2^25 LE DRs (u * v_le * g_le); costs 128
-                                  MiB of device scratch plus 4 KiB per
+                                  MiB of device scratch plus 68 KiB per
                                   region.  Above every other scan form in
                                   precedence; no effect in the discrete
                                   form or in a group's fused scan */
