@@ -189,6 +189,11 @@ def test_partition_scan_needs_a_small_enough_le(P):
     assert extra == 2 * (2048 * 32768 + (512 + 1) * 2048) + 4 * 512 * 16 * 1024
     big = P.make_config(300, 1024, 4, 65536, 8, 65536, 1024, 1, max_candidates=1, flags=part)
     assert P.srla_footprint_bytes(big) == 0
+    # the limit itself: 2^25 LE DRs are accepted, one more LE is not
+    edge = P.make_config(3, 1024, 1, 64, 8, 32768, 1024, 1, max_candidates=1, flags=part)
+    assert P.srla_footprint_bytes(edge) > 0
+    over = P.make_config(3, 1024, 1, 64, 8, 32769, 1024, 1, max_candidates=1, flags=part)
+    assert P.srla_footprint_bytes(over) == 0
     rc, h = P.srla_create(big)
     assert rc == -1 and not h.value
     # the discrete form has no LE stamps: the flag has no effect there

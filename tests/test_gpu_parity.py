@@ -745,3 +745,10 @@ def test_partition_scan_backbone_full_size_and_expiry():
     stream, mon, _ = workload("backbone_k16")
     stream = scaled(stream, 600_000)
     _run(stream, mon, range(20), max_candidates=1 << 22, dump_every=7, scan_partition=True)
+
+
+def test_partition_scan_at_its_largest_le():
+    """2^25 LE DRs: the most regions (1024) the partitioned scan takes."""
+    mon = dict(k=3, theta=1024, u=8, v_re=4096, g=8, v_le=4096, G=1024, hash_seed=4242)
+    _run(_rand_stream(4242, 300_000, 50_000, 1536), mon, range(3), max_candidates=1 << 20,
+         scan_partition=True)
