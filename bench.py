@@ -684,6 +684,13 @@ def main():
             "random_stores_per_s": g["u"] * (1 + 2.0 ** -tau) * n_pairs / (scan_ms * 1e-3),
         },
     }
+    if tuned:
+        # the same launch alone on the GPU: the autotuner's timing of the chosen
+        # form (the timed region's scans share the GPU with the candidate work
+        # of the slice before in the streaming form)
+        alone = per_launch_bytes / (tuned["ms"] * 1e-3) / 1e9
+        out["roofline"]["alone"] = {"launch_ms": tuned["ms"], "achieved": alone,
+                                    "frac": alone / HBM_PEAK_GBS}
     # achievable rate of random 2-byte stores over the scan's own footprint
     # (LE + RE stamp arrays), measured with the same store pattern and nothing else
     import probe
