@@ -90,9 +90,10 @@ __global__ __launch_bounds__(kPartThreads) void k_scan_part(
   hist[tid] = 0u;
   if (tid == 0) n_samp = 0u;
   __syncthreads();
-  // with U > 0 a chunk has at most kPartEntries / 4 pairs, so its sampled
-  // sources fit the entry array, which is free until the placing pass: one
-  // append to the slice's list per chunk instead of one per wavefront
+  // with U >= 2 a chunk has at most kPartEntries / 2 pairs, so its sampled
+  // sources (4 bytes each) fit the entry array, which is free until the
+  // placing pass: one append to the slice's list per chunk instead of one per
+  // wavefront
   static_assert(U == 0 || U >= 2, "the staged sampled sources must fit the entry array");
   uint32_t* stage = U > 0 ? reinterpret_cast<uint32_t*>(ent) : nullptr;
 
