@@ -98,7 +98,10 @@ enum Stage { ST_SCAN, ST_SWEEP, ST_FINALIZE, ST_ESTIMATE, ST_SLIDE, ST_REPORT, S
 // the end-of-slice pipeline's two phases
 // PH_FINISH_GO: the second phase when the next slice's first scan is enqueued
 // behind a scan-start mark (the report copy then waits for that mark)
-enum Phase { PH_SNAPSHOT = 0, PH_FINISH = 1, PH_FINISH_GO = 2 };
+// PH_SORT: without the overlapped report, the sort of the closed slice's
+// sampled sources, which the pipeline stream runs as soon as the slice's
+// scans end (beside the snapshot), ahead of the rest of the second phase
+enum Phase { PH_SNAPSHOT = 0, PH_FINISH = 1, PH_FINISH_GO = 2, PH_SORT = 3 };
 
 struct TimedSpan {
   int stage;
@@ -184,6 +187,7 @@ struct srla_monitor {
   // ordering: the snapshot phase runs on the scan stream, in order with the
   // scans; the second phase runs on the pipeline stream
   hipEvent_t ev_snap = nullptr;                 // after the last closed slice's snapshot phase
+  hipEvent_t ev_scanned = nullptr;              // after the last closed slice's scans
   hipEvent_t ev_done[2] = {nullptr, nullptr};   // after the whole pipeline, by slice parity
   uint32_t n_pending = 0;         // closed slices whose reports are not collected (<= 2)
   int clock_khz = 0;              // rate of the device wall clock
@@ -191,7 +195,8 @@ struct srla_monitor {
 
   // replayable pipeline: [phase][parity]
   bool use_graph = false;
-  hipGraphExec_t graph[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  hipGraphExec_t graph[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr},
+                                {nullptr, nullptr}};
 
   // host-input ring: H2D copies on their own stream into two device chunks
   // (through two pinned bounce chunks when the caller's memory is pageable),
@@ -448,10 +453,27 @@ hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
   return e;
 }
 
+// The sort of the closing slice's sampled sources (drained from the source
+// set first in the discrete form); it needs the slice's scans only.
+hipError_t enqueue_sort(srla_monitor* m, int p, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  uint32_t* tc = m->tcount + p;
+  hipEvent_t ta = nullptr;
+  const bool spans = !m->use_graph;
+  if (spans) span_begin(m, st, &ta);
+  if (m->discrete) e = launch_drain_set(m->sset[p], m->set_slots, m->touched[p], tc, st);
+  if (e == hipSuccess)
+    e = radix_sort_u32(m->touched[p], m->touched_tmp, tc, m->touched_cap, m->hist, st);
+  if (spans) span_end(m, st, ST_FINALIZE, ta);
+  return e;
+}
+
 // The candidate work of the closing slice: candidate check of its sampled
-// sources, merge with the carried list, Eq9 for every candidate (report
-// entries to `out`), Algorithm 3's carried list and SI counters.
-hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hipStream_t st) {
+// sources (sorted first unless `sorted`), merge with the carried list, Eq9
+// for every candidate (report entries to `out`), Algorithm 3's carried list
+// and SI counters.
+hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hipStream_t st,
+                              bool sorted) {
   const Geo& geo = m->geo;
   hipError_t e = hipSuccess;
   uint32_t* tc = m->tcount + p;
@@ -459,11 +481,8 @@ hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hip
   const uint64_t* re_act = m->discrete ? m->rebits[p] : m->act[p];
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
+  if (!sorted) e = enqueue_sort(m, p, st);
   if (spans) span_begin(m, st, &ta);
-  if (e == hipSuccess && m->discrete)
-    e = launch_drain_set(m->sset[p], m->set_slots, m->touched[p], tc, st);
-  if (e == hipSuccess)
-    e = radix_sort_u32(m->touched[p], m->touched_tmp, tc, m->touched_cap, m->hist, st);
   if (e == hipSuccess)
     e = launch_finalize(m->touched[p], tc, re_act, m->si_cnt, geo, m->mark, m->cnt, st);
   if (e == hipSuccess)
@@ -497,10 +516,11 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
   hipError_t e = hipSuccess;
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
+  if (phase == PH_SORT) return enqueue_sort(m, p, st);
   if (phase == PH_SNAPSHOT) {
     e = enqueue_snapshot(m, p, st);
     if (e == hipSuccess && m->overlap_report) {
-      e = enqueue_candidates(m, p, m->d_staging[p], st);
+      e = enqueue_candidates(m, p, m->d_staging[p], st, false);
       if (spans) span_begin(m, st, &ta);
       if (e == hipSuccess)
         e = launch_status(m->cnt, m->tcount + p, m->up[p], m->row_fill[p], m->geo.u, m->ps,
@@ -510,7 +530,7 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
     }
     return e;
   }
-  if (!m->overlap_report) e = enqueue_candidates(m, p, m->d_report[p], st);
+  if (!m->overlap_report) e = enqueue_candidates(m, p, m->d_report[p], st, true);
   if (spans) span_begin(m, st, &ta);
   if (m->overlap_report) {
     // PH_FINISH_GO: the next slice (parity p ^ 1) has its first scan behind a mark
@@ -588,6 +608,7 @@ void release(srla_monitor* m) {
   }
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   if (m->ev_snap) (void)hipEventDestroy(m->ev_snap);
+  if (m->ev_scanned) (void)hipEventDestroy(m->ev_scanned);
   if (m->pipe) destroy_queue_stream(m->pipe, m->pipe_own);
   if (m->copy) {
     (void)hipStreamSynchronize(m->copy);
@@ -769,6 +790,8 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     if (!rc && hipEventCreateWithFlags(&m->ev_done[q], hipEventDisableTiming) != hipSuccess)
       rc = SRLA_E_DEVICE;
   }
+  if (!rc && hipEventCreateWithFlags(&m->ev_scanned, hipEventDisableTiming) != hipSuccess)
+    rc = SRLA_E_DEVICE;
   if (!rc && hipEventCreateWithFlags(&m->ev_snap, hipEventDisableTiming) != hipSuccess)
     rc = SRLA_E_DEVICE;
   if (rc) {
@@ -867,8 +890,16 @@ int enqueue_finish(srla_monitor* m, bool go) {
     TimingAs(srla_monitor* mm, bool t) : m(mm), saved(mm->timing) { m->timing = t; }
     ~TimingAs() { m->timing = saved; }
   } timing_as(m, m->timed[pc]);
-  HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_snap, 0));
   hipEvent_t ta;
+  if (!m->overlap_report) {
+    // the sort needs the slice's scans only: it runs beside the snapshot
+    HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_scanned, 0));
+    if (m->use_graph) span_begin(m, m->pipe, &ta);
+    const int rs = run_phase(m, PH_SORT, pc, m->pipe);
+    if (rs) return rs;
+    if (m->use_graph) span_end(m, m->pipe, ST_FINALIZE, ta);
+  }
+  HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_snap, 0));
   if (m->use_graph) span_begin(m, m->pipe, &ta);
   const int rc = run_phase(m, go ? PH_FINISH_GO : PH_FINISH, pc, m->pipe);
   if (rc) return rc;
@@ -998,6 +1029,8 @@ int srla_close_slice(srla_monitor_t* m) {
     const int rc = enqueue_finish(m, false);
     if (rc) return rc;
   }
+  // the slice's scans are done: the pipeline stream may sort its sampled sources
+  if (!m->overlap_report) HIP_TRY(m, hipEventRecord(m->ev_scanned, m->stream));
   if (m->overlap_report ? m->slice >= 2 : (m->discrete && m->slice >= 1))
     HIP_TRY(m, wait_unless_done(m->stream, m->ev_done[m->overlap_report ? p : p ^ 1]));
   // with graphs, each phase is timed as a whole: the first as the sweeps
