@@ -752,3 +752,31 @@ def test_partition_scan_at_its_largest_le():
     mon = dict(k=3, theta=1024, u=8, v_re=4096, g=8, v_le=4096, G=1024, hash_seed=4242)
     _run(_rand_stream(4242, 300_000, 50_000, 1536), mon, range(3), max_candidates=1 << 20,
          scan_partition=True)
+
+
+def test_partition_monitors_in_a_group_mix_fused_and_own_scans():
+    """Monitors with the partitioned scan in a group: the fused group scan
+    (which has no partitioned form) and each member's own partitioned scans
+    stamp the same arrays within one slice."""
+    st = torch.cuda.Stream()
+    mons = [dict(k=k, theta=t, u=u, v_re=vr, g=g, v_le=vl, G=G, hash_seed=300 + i)
+            for i, (k, t, u, vr, g, vl, G) in enumerate(GROUP)]
+    gms = [srla.Monitor(**m, max_candidates=1 << 16, stream=st, scan_partition=True)
+           for m in mons]
+    oms = [oracle.Monitor(**m) for m in mons]
+    grp = srla.Group(gms)
+    gen = _rand_stream(8, 30_000, 2500, 400)
+    for s in range(6):
+        p = gen(s)
+        half = len(p) // 2
+        grp.scan(to_device(p[:half]))
+        for gm in gms:
+            gm.scan(to_device(p[half:]))
+        for gm, o, m in zip(gms, oms, mons):
+            o.scan(p)
+            compare_reports(gm.estimate(), o.estimate(), m["theta"], "slice %d" % s)
+    for gm, o in zip(gms, oms):
+        compare_dumps(gm, o, ctx="end")
+    grp.close()
+    for gm in gms:
+        gm.close()
