@@ -124,7 +124,8 @@ def run_batched(args):
     torch.cuda.set_stream(st)
     fused = args.mode in ("batched", "streaming")
     mons = [srla.Monitor(**c, max_candidates=args.max_candidates, stream=st, graph=fused,
-                         scan_blocks=args.scan_blocks, lean_report=not args.full_report)
+                         scan_blocks=args.scan_blocks, lean_report=not args.full_report,
+                         scan_partition=args.scan_partition)
             for c in mons_cfg]
     grp = srla.Group(mons, scan_blocks=args.scan_blocks) if fused else None
 

@@ -110,7 +110,9 @@ enum {
                                   MiB of device scratch plus 68 KiB per
                                   region.  Above every other scan form in
                                   precedence; no effect in the discrete
-                                  form or in a group's fused scan */
+                                  form.  A group whose members all have it
+                                  runs each member's partitioned scan over
+                                  the pairs instead of the fused kernel */
 };
 
 /*
@@ -323,8 +325,9 @@ int srla_set_timing(srla_monitor_t *m, int enabled);
  * Monitor groups: many monitors -- each with its own window, DR geometry,
  * threshold and hash seed -- fed the same pair stream.  srla_group_scan runs
  * one fused scan kernel that loads every pair once and applies Algorithm 2
- * of every member; it is equivalent to srla_scan on each member with the
- * same pairs.  Slices are still closed and reported per member
+ * of every member (or, when every member has SRLA_CFG_SCAN_PARTITION,
+ * each member's partitioned scan in turn); it is equivalent to srla_scan on
+ * each member with the same pairs.  Slices are still closed and reported per member
  * (srla_close_slice / srla_wait_report / srla_estimate).
  * srla_group_create: 1..64 distinct monitors that share one scan stream,
  *   none of them in the discrete form or with SRLA_CFG_OVERLAP_REPORT;

@@ -1265,6 +1265,26 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
     args.code[i] = stamp_code(m->slice);
     args.parity |= (uint64_t)p << i;
   }
+  // members that all scan in partitioned form: each member's partitioned scan
+  // over the pairs (the pairs are read once per member, the stores go out in
+  // lines) instead of the fused kernel's random stores
+  bool all_part = true;
+  for (srla_monitor* m : g->mons) all_part = all_part && m->part_scan;
+  if (all_part) {
+    for (srla_monitor* m : g->mons) {
+      const int p = (int)(m->slice & 1);
+      const hipError_t e = launch_scan_partition(
+          pairs, n, m->geo, stamp_code(m->slice), m->le, m->re, m->touched[p], m->tcount + p,
+          m->part_entries, m->part_offs, m->part_marks, g->stream);
+      if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
+    }
+    for (srla_monitor* m : g->mons) {
+      m->slice_pairs[m->slice & 1] += n;
+      m->scan_launches++;
+      m->scan_pairs += n;
+    }
+    return SRLA_OK;
+  }
   bool changed = g->uploaded.size() != table.size();
   for (size_t i = 0; !changed && i < table.size(); ++i)
     changed = !same_member(table[i], g->uploaded[i]);
