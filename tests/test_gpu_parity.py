@@ -754,15 +754,18 @@ def test_partition_scan_at_its_largest_le():
          scan_partition=True)
 
 
-def test_partition_monitors_in_a_group_mix_fused_and_own_scans():
-    """Monitors with the partitioned scan in a group: the fused group scan
-    (which has no partitioned form) and each member's own partitioned scans
-    stamp the same arrays within one slice."""
+@pytest.mark.parametrize("all_partitioned", [True, False])
+def test_partition_monitors_in_a_group_mix_group_and_own_scans(all_partitioned):
+    """Monitors with the partitioned scan in a group: the group scan (each
+    member's partitioned scan when every member has it, else the fused flat
+    kernel) and each member's own scans stamp the same arrays within one
+    slice."""
     st = torch.cuda.Stream()
     mons = [dict(k=k, theta=t, u=u, v_re=vr, g=g, v_le=vl, G=G, hash_seed=300 + i)
             for i, (k, t, u, vr, g, vl, G) in enumerate(GROUP)]
-    gms = [srla.Monitor(**m, max_candidates=1 << 16, stream=st, scan_partition=True)
-           for m in mons]
+    gms = [srla.Monitor(**m, max_candidates=1 << 16, stream=st,
+                        scan_partition=all_partitioned or i > 0)
+           for i, m in enumerate(mons)]
     oms = [oracle.Monitor(**m) for m in mons]
     grp = srla.Group(gms)
     gen = _rand_stream(8, 30_000, 2500, 400)
