@@ -1,11 +1,15 @@
 """Memory-system probes that calibrate the SRLA kernels' ceilings.
 
 ``random_store_rate(bytes)`` measures random 2-byte stores per second over a
-footprint of ``bytes`` (the scan's access pattern without its pair loads and
-hashing); ``random_or_rate(bytes)`` the same for one-bit atomic ORs into
+footprint of ``bytes`` (the flat scan's access pattern without its pair loads
+and hashing); ``random_or_rate(bytes)`` the same for one-bit atomic ORs into
 32-bit words (the discrete-window scan's pattern), ``random_load_rate(bytes)``
-for random 2-byte loads.  Measurement
-infrastructure only; the SRLA library does not use it.
+for random 2-byte loads.  ``stream_read_rate(bytes)`` and
+``stream_copy_rate(bytes)`` measure streaming 16-byte reads (and copies) over
+``bytes`` (the sweeps' and the partitioned scan's pattern), and
+``host_write_rate`` coalesced kernel stores into pinned host memory (the
+report's path over PCIe).  Measurement infrastructure only; the SRLA library
+does not use it.
 """
 import ctypes
 import os
@@ -44,15 +48,9 @@ def _load():
         L.probe_host_write.restype = ctypes.c_double
         L.probe_host_write.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32,
                                        ctypes.c_void_p]
-        L.probe_two_streams.restype = ctypes.c_double
-        L.probe_two_streams.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
-                                        ctypes.c_void_p, ctypes.c_void_p,
-                                        ctypes.POINTER(ctypes.c_double)]
-        L.probe_event_order.restype = ctypes.c_double
-        L.probe_event_order.argtypes = L.probe_two_streams.argtypes + [ctypes.c_uint32,
-                                                                        ctypes.c_uint32]
-        L.probe_xcc_of_blocks.restype = ctypes.c_int
-        L.probe_xcc_of_blocks.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
+        L.probe_stream.restype = ctypes.c_double
+        L.probe_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+                                   ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
         L.probe_random_load.restype = ctypes.c_double
         L.probe_random_load.argtypes = L.probe_random_store.argtypes
         _lib = L
@@ -87,66 +85,6 @@ def host_write_rate(nbytes=64 << 20, blocks=2048, repeats=3):
     return nbytes / (best * 1e-3)
 
 
-def dma_d2h_rate(nbytes=64 << 20, repeats=3):
-    """Best-of-`repeats` bytes/s of a device-to-host copy into pinned memory."""
-    import torch
-    dev = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
-    host = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
-    best = None
-    for r in range(repeats + 1):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        host.copy_(dev, non_blocking=True)
-        b.record()
-        b.synchronize()
-        if r > 0:
-            ms = a.elapsed_time(b)
-            best = ms if best is None else min(best, ms)
-    return nbytes / (best * 1e-3)
-
-
-def two_streams(blocks=512, iters=200_000):
-    """(ms of one spin kernel of `blocks` workgroups alone, ms of two such
-    kernels on two streams released together): equal when they overlap."""
-    import torch
-    buf = torch.empty(2 * blocks * 256, dtype=torch.int32, device="cuda")
-    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
-    both = ctypes.c_double(0.0)
-    one = _load().probe_two_streams(ctypes.c_void_p(buf.data_ptr()), blocks, iters,
-                                    ctypes.c_void_p(s1.cuda_stream),
-                                    ctypes.c_void_p(s2.cuda_stream), ctypes.byref(both))
-    if one < 0:
-        raise RuntimeError("probe failed (%g)" % one)
-    return one, both.value
-
-
-def event_order(blocks=64, iters=200_000, blocks3=1, iters3=1):
-    """(ms from stream 1's first spin to stream 2's kernel that waits for an
-    event recorded after that spin, ms of stream 1's two spins)."""
-    import torch
-    buf = torch.empty((blocks + (blocks3 & 0x7FFFFFFF)) * 256, dtype=torch.int32, device="cuda")
-    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
-    both = ctypes.c_double(0.0)
-    t3 = _load().probe_event_order(ctypes.c_void_p(buf.data_ptr()), blocks, iters,
-                                   ctypes.c_void_p(s1.cuda_stream),
-                                   ctypes.c_void_p(s2.cuda_stream), ctypes.byref(both),
-                                   blocks3, iters3)
-    if t3 < 0:
-        raise RuntimeError("probe failed (%g)" % t3)
-    return t3, both.value
-
-
-def xcc_of_blocks(blocks=64):
-    """The XCD each of `blocks` workgroups of one launch ran on (a list)."""
-    import torch
-    out = torch.full((blocks,), 0xFF, dtype=torch.int32, device="cuda")
-    st = torch.cuda.current_stream()
-    if _load().probe_xcc_of_blocks(ctypes.c_void_p(out.data_ptr()), blocks,
-                                   ctypes.c_void_p(st.cuda_stream)) != 0:
-        raise RuntimeError("probe failed")
-    return out.cpu().tolist()
-
-
 def random_load_rate(nbytes, loads=1 << 27, repeats=3):
     """Best-of-`repeats` random 2-byte loads per second over `nbytes`."""
     return _rate("probe_random_load", nbytes, loads, repeats)
@@ -169,3 +107,37 @@ def _rate(fn, nbytes, stores, repeats):
             best = ms if best is None else min(best, ms)
     del buf
     return blocks * 256 * per_lane / (best * 1e-3)
+
+
+def _stream(nbytes, copy, repeats, blocks):
+    import torch
+    L = _load()
+    n = max(16, nbytes // 16 * 16)
+    src = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(n, dtype=torch.uint8, device="cuda") if copy else None
+    sink = torch.zeros(4, dtype=torch.int32, device="cuda")
+    st = torch.cuda.current_stream()
+    best = None
+    for r in range(repeats + 1):
+        ms = L.probe_stream(ctypes.c_void_p(src.data_ptr()),
+                            ctypes.c_void_p(dst.data_ptr()) if copy else None, n, blocks,
+                            ctypes.c_void_p(sink.data_ptr()), ctypes.c_void_p(st.cuda_stream))
+        if ms <= 0:
+            raise RuntimeError("probe failed (%g)" % ms)
+        if r > 0:   # the first launch warms the footprint
+            best = ms if best is None else min(best, ms)
+    del src, dst, sink
+    return n * (2 if copy else 1) / (best * 1e-3)
+
+
+def stream_read_rate(nbytes, repeats=5, blocks=4096):
+    """Best-of-`repeats` bytes/s of streaming 16-byte reads over `nbytes`
+    (a footprint up to the 256 MB last-level cache stays resident in it
+    between repeats)."""
+    return _stream(nbytes, False, repeats, blocks)
+
+
+def stream_copy_rate(nbytes, repeats=5, blocks=4096):
+    """Best-of-`repeats` bytes/s (read + written) of a streaming copy of
+    `nbytes` into a second buffer of the same size."""
+    return _stream(nbytes, True, repeats, blocks)

@@ -1,9 +1,12 @@
-// Memory-system probes: the rate of random 2-byte stores (or of random
-// one-bit atomic ORs into 32-bit words), one per lane, uniform over a
-// footprint of F bytes -- the access pattern of the SRLA scan (16-bit stamp
-// form, resp. one-bit discrete form) with nothing else (no pair loads, no
-// hashing beyond the address).  Used to calibrate the scan kernels'
-// achievable ceilings per footprint.
+// Memory-system probes that give the SRLA kernels their ceilings:
+// * the rate of random 2-byte stores (or random one-bit atomic ORs into
+//   32-bit words, or random 2-byte loads), one per lane, uniform over a
+//   footprint of F bytes -- the access pattern of the flat scan (16-bit stamp
+//   form, resp. one-bit discrete form) with nothing else;
+// * streaming reads and copies of F bytes with 16-byte accesses, consecutive
+//   lanes on consecutive words -- the pattern of the slice-end sweeps and of
+//   the partitioned scan's passes;
+// * coalesced kernel stores into pinned host memory -- the report's path.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -56,12 +59,6 @@ __global__ __launch_bounds__(256) void k_random_load(const uint16_t* __restrict_
   if (acc == 0xFFFFFFFFu) sink[0] = acc;   // practically never; keeps the loads
 }
 
-// block b writes the id of the XCD (XCC) it runs on to out[b]: a read of a
-// hardware register, to check the round-robin placement of workgroups
-__global__ __launch_bounds__(64) void k_xcc_of_block(uint32_t* __restrict__ out) {
-  if (threadIdx.x == 0) out[blockIdx.x] = __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;
-}
-
 // grid-stride coalesced 16-byte stores of `bytes` into (pinned, mapped)
 // host memory: the rate a kernel can push results over PCIe
 __global__ __launch_bounds__(256) void k_host_write(uint4* __restrict__ dst, uint64_t n16,
@@ -71,89 +68,65 @@ __global__ __launch_bounds__(256) void k_host_write(uint4* __restrict__ dst, uin
     dst[i] = make_uint4((uint32_t)i, seed, (uint32_t)(i >> 32), ~seed);
 }
 
-// a fixed amount of ALU work per lane (no memory traffic but one store per
-// lane at the end, so the loop is not optimized away)
-__global__ __launch_bounds__(256) void k_spin(uint32_t* __restrict__ out, uint32_t iters) {
-  uint32_t x = threadIdx.x + 1u;
-  for (uint32_t i = 0; i < iters; ++i) x = x * 1664525u + 1013904223u;
-  out[(uint64_t)blockIdx.x * 256 + threadIdx.x] = x;
+// streaming reads: every lane reads 16-byte words grid-stride, four in flight;
+// the XOR of what it read goes to the sink only if it matches a value the
+// launch never produces (so the loads stay live)
+__global__ __launch_bounds__(256) void k_stream_read(const uint4* __restrict__ src, uint64_t n16,
+                                                    uint32_t* __restrict__ sink) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  uint32_t acc = 0;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^
+           d.z ^ d.w;
+  }
+  for (; i < n16; i += stride) {
+    const uint4 a = src[i];
+    acc ^= a.x ^ a.y ^ a.z ^ a.w;
+  }
+  if (acc == 0xFFFFFFFFu) sink[0] = acc;   // the buffers hold zeros: never taken
+}
+
+// streaming copy: the same reads, each word stored to the same offset of dst
+__global__ __launch_bounds__(256) void k_stream_copy(const uint4* __restrict__ src,
+                                                    uint4* __restrict__ dst, uint64_t n16) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 }  // namespace
 
-// Two spin kernels of `blocks` workgroups each, on two streams at once, and
-// then one after the other on one stream: returns the ms of both (via *both)
-// and of one alone (the return value), or a negative value on error.  Equal
-// times mean the two streams' kernels ran side by side.
-extern "C" double probe_two_streams(void* buf, uint32_t blocks, uint32_t iters, void* s1,
-                                    void* s2, double* both) {
-  if (!buf || blocks == 0 || !both) return -1.0;
-  hipStream_t a = (hipStream_t)s1, b = (hipStream_t)s2;
-  uint32_t* out = (uint32_t*)buf;
-  hipEvent_t e0, e1, e2, ea, eb;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
-      hipEventCreate(&e2) != hipSuccess || hipEventCreate(&ea) != hipSuccess ||
-      hipEventCreate(&eb) != hipSuccess)
-    return -2.0;
-  float one = -1.f, two = -1.f;
-  // one kernel alone
-  hipEventRecord(e0, a);
-  hipLaunchKernelGGL(k_spin, dim3(blocks), dim3(256), 0, a, out, iters);
-  hipEventRecord(e1, a);
-  hipEventSynchronize(e1);
-  hipEventElapsedTime(&one, e0, e1);
-  // two kernels, one per stream, released together
-  hipEventRecord(e0, a);
-  hipStreamWaitEvent(b, e0, 0);
-  hipLaunchKernelGGL(k_spin, dim3(blocks), dim3(256), 0, a, out, iters);
-  hipLaunchKernelGGL(k_spin, dim3(blocks), dim3(256), 0, b, out + (uint64_t)blocks * 256, iters);
-  hipEventRecord(eb, b);
-  hipStreamWaitEvent(a, eb, 0);
-  hipEventRecord(e2, a);
-  hipEventSynchronize(e2);
-  hipEventElapsedTime(&two, e0, e2);
-  hipEventDestroy(e0); hipEventDestroy(e1); hipEventDestroy(e2);
-  hipEventDestroy(ea); hipEventDestroy(eb);
-  *both = two;
-  return one;
-}
-
-// Cross-stream ordering: stream 1 runs spin kernel K1, records event E, runs
-// spin kernel K2; stream 2 waits for E and runs spin kernel K3 (blocks3
-// workgroups of iters3 steps).
-// Returns the ms from before K1 to after K3 (about one spin if K3 ran right
-// after K1, two if it waited for K2), and the ms of stream 1's two spins
-// via *both.
-extern "C" double probe_event_order(void* buf, uint32_t blocks, uint32_t iters, void* s1,
-                                    void* s2, double* both, uint32_t blocks3, uint32_t iters3) {
-  if (!buf || blocks == 0 || !both) return -1.0;
-  hipStream_t a = (hipStream_t)s1, b = (hipStream_t)s2;
-  uint32_t* out = (uint32_t*)buf;
-  hipEvent_t e0, e, ea, eb;
-  const bool untimed = (blocks3 & 0x80000000u) != 0;   // E without timing
-  blocks3 &= 0x7FFFFFFFu;
-  if (hipEventCreate(&e0) != hipSuccess ||
-      (untimed ? hipEventCreateWithFlags(&e, hipEventDisableTiming) : hipEventCreate(&e)) !=
-          hipSuccess ||
-      hipEventCreate(&ea) != hipSuccess || hipEventCreate(&eb) != hipSuccess)
-    return -2.0;
-  hipEventRecord(e0, a);
-  hipLaunchKernelGGL(k_spin, dim3(blocks), dim3(256), 0, a, out, iters);
-  hipEventRecord(e, a);
-  hipLaunchKernelGGL(k_spin, dim3(blocks), dim3(256), 0, a, out, iters);
-  hipEventRecord(ea, a);
-  hipStreamWaitEvent(b, e, 0);
-  hipLaunchKernelGGL(k_spin, dim3(blocks3), dim3(256), 0, b, out + (uint64_t)blocks * 256,
-                     iters3);
-  hipEventRecord(eb, b);
-  hipEventSynchronize(ea);
-  hipEventSynchronize(eb);
-  float t3 = -1.f, t12 = -1.f;
-  hipEventElapsedTime(&t3, e0, eb);
-  hipEventElapsedTime(&t12, e0, ea);
-  hipEventDestroy(e0); hipEventDestroy(e); hipEventDestroy(ea); hipEventDestroy(eb);
-  *both = t12;
-  return t3;
+// Streaming read (dst == NULL) or copy of `bytes` (a multiple of 16) with
+// `blocks` workgroups; returns the kernel time in ms, or a negative value.
+extern "C" double probe_stream(const void* src, void* dst, uint64_t bytes, uint32_t blocks,
+                               void* sink, void* stream) {
+  if (!src || bytes < 16 || blocks == 0 || (!dst && !sink)) return -1.0;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -2.0;
+  hipEventRecord(a, st);
+  if (dst)
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, st, (const uint4*)src,
+                       (uint4*)dst, bytes / 16);
+  else
+    hipLaunchKernelGGL(k_stream_read, dim3(blocks), dim3(256), 0, st, (const uint4*)src,
+                       bytes / 16, (uint32_t*)sink);
+  hipEventRecord(b, st);
+  float ms = -3.f;
+  if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+    ms = -4.f;
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms;
 }
 
 // Returns the kernel time in ms of writing `bytes` (a multiple of 16) to the
@@ -172,13 +145,6 @@ extern "C" double probe_host_write(void* dst, uint64_t bytes, uint32_t blocks, v
   hipEventDestroy(a);
   hipEventDestroy(b);
   return ms;
-}
-
-extern "C" int probe_xcc_of_blocks(void* out, uint32_t blocks, void* stream) {
-  if (!out || blocks == 0) return -1;
-  hipLaunchKernelGGL(k_xcc_of_block, dim3(blocks), dim3(64), 0, (hipStream_t)stream,
-                     (uint32_t*)out);
-  return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? 0 : -2;
 }
 
 // Same for random 2-byte loads (footprint in bytes).

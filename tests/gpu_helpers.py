@@ -54,3 +54,51 @@ def compare_dumps(gm, om, ctx="", discrete=False):
             bad = np.flatnonzero(a != b)
             raise AssertionError("%s: array %d differs at %d cells, first %d: gpu %d oracle %d"
                                  % (ctx, which, bad.size, bad[0], a[bad[0]], b[bad[0]]))
+
+
+def compare_lean_reports(rg, rc, theta, ctx=""):
+    """compare_reports for a report without the per-candidate weights
+    (SRLA_CFG_LEAN_REPORT): ip, est, flags and the slice's counts."""
+    assert rg.union_weight is None and rg.re_weight is None, ctx
+    assert rg.slice == rc.slice, ctx
+    assert rg.window_full == rc.window_full, ctx
+    assert rg.n == rc.n, (ctx, rg.n, rc.n)
+    assert np.array_equal(rg.ip, rc.ip), ctx
+    assert np.array_equal(rg.row_fill, rc.row_fill), ctx
+    assert rg.up == rc.up, (ctx, rg.up, rc.up)
+    assert rg.n_touched == rc.n_touched and rg.n_new == rc.n_new, ctx
+    fin = np.isfinite(rc.est)
+    assert np.array_equal(np.isfinite(rg.est), fin), ctx
+    assert np.array_equal(np.isposinf(rg.est), np.isposinf(rc.est)), ctx
+    e_g, e_c = rg.est[fin], rc.est[fin]
+    assert np.all(np.abs(e_g - e_c) <= RTOL * np.abs(e_c)), (ctx, np.max(np.abs(e_g - e_c)))
+    other = ~np.uint8(oracle.SUPER)
+    assert np.array_equal(rg.flags & other, rc.flags & other), ctx
+    diff = (rg.flags ^ rc.flags) & oracle.SUPER
+    if diff.any():
+        assert np.all(np.abs(rc.est[diff != 0] - theta) <= RTOL * theta), ctx
+
+
+class OracleThread:
+    """Runs oracle monitors' scan + estimate in a worker thread (the oracle's
+    C calls release the GIL), so the oracle works while the GPU side is
+    driven from the test's own thread."""
+
+    def __init__(self, workers=1):
+        from concurrent.futures import ThreadPoolExecutor
+        self.pool = ThreadPoolExecutor(max_workers=workers)
+
+    def slice(self, om, pairs):
+        """Future of om's report after scanning pairs (host numpy, (n, 2))."""
+        def work():
+            om.scan(pairs)
+            return om.estimate()
+        return self.pool.submit(work)
+
+    def close(self):
+        self.pool.shutdown(wait=True)
+
+
+def host_pairs(dev_pairs, n):
+    """The first n pairs of an int32 CUDA tensor as a host (n, 2) uint32 array."""
+    return dev_pairs[:2 * n].cpu().numpy().view(np.uint32).reshape(-1, 2)
