@@ -4,9 +4,10 @@ One step = one time slice of the backbone-shaped workload: 8M (aip, bip)
 pairs scanned into the SEA (Algorithm 2), then the slice closed (candidate
 check, Eq8-Eq9 estimate of every candidate, Algorithm 3 slide) and its report
 delivered to host memory.  Window k = 300 slices, SRE 8 x 2^20 DR cells, SLE
-2^24 DR cells, theta = 1024.  Warm-up steps run first so that the timed
-slices see a full window; the timed slices' pairs are generated into device
-memory before each timed segment starts.
+2^24 DR cells, theta = 1024.  Slices 0 .. k-2 fill the window first, then
+the warm-up slices run, so every warm-up and timed slice closes a full
+window; the timed slices' pairs are generated into device memory before each
+timed segment starts.
 
 --mode streaming (default): slice t's DR activity is snapshotted right after
   its last scan, then the scan of slice t+1 runs on the GPU beside slice t's
@@ -15,14 +16,15 @@ memory before each timed segment starts.
   closes slice t+1 before it collects the report of slice t).  With a scan
   form other than the partitioned one (the autotuner picks it), the
   candidate work runs first (into device memory) and only the report's copy
-  runs beside the next scan (--overlap-report).  The latency is the device
-  time from the start of slice t's end-of-slice work, right after its last
-  scan, to its report in host memory.
---mode plain: each slice is scanned, then estimated; the latency is the host
-  time from the end of the slice's scan to its report.
+  runs beside the next scan (--overlap-report).  The same number of slices
+  then runs in the plain form on the same monitor (`plain` in the output).
+--mode plain: each slice is scanned, then estimated.
 
-Prints one JSON line (rank 0).  `value` is pairs (packets) scanned per second
-over the timed slices; `p99_ms` is the 99th percentile of the latency.
+In both forms the latency is the device time from the start of a slice's
+end-of-slice work, right after its last scan, to its report complete in host
+memory.  Prints one JSON line (rank 0).  `value` is pairs (packets) scanned
+per second over the timed slices; `p99_ms` is the 99th percentile of the
+latency.
 """
 import argparse
 import json
@@ -89,16 +91,16 @@ def oracle_baseline(stream, mon, slices):
     slice's pairs are generated outside the timed calls."""
     import oracle
     o = oracle.Monitor(**mon)
-    dt, n = 0.0, 0
+    dt, n, r = 0.0, 0, None
     for s in range(slices):
         p = stream.slice(s)
         t0 = time.perf_counter()
         o.scan(p)
-        o.estimate()
+        r = o.estimate()
         dt += time.perf_counter() - t0
         n += len(p)
     o.close()
-    return n / dt, dt, n
+    return n / dt, dt, n, (int(r.n) if r is not None else 0)
 
 
 def run_batched(args):
@@ -460,7 +462,14 @@ def main():
     ap.add_argument("--segment", type=int, default=200,
                     help="timed slices whose inputs are generated into HBM at a time")
     ap.add_argument("--steps", type=int, default=60)
-    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=5,
+                    help="untimed slices in the measured form before the timed ones (after "
+                         "the k - 1 slices that fill the window)")
+    ap.add_argument("--no-prefill", action="store_true",
+                    help="do not fill the window before the warm-up slices")
+    ap.add_argument("--compare-steps", type=int, default=-1,
+                    help="slices of the plain form timed after the streaming form, on the "
+                         "same monitor (default: --steps)")
     ap.add_argument("--workload", default="backbone")
     ap.add_argument("--cpu-slices", type=int, default=30,
                     help="slices of the same workload the oracle baseline scans "
@@ -494,6 +503,8 @@ def main():
     ap.add_argument("--scan-xcd", action="store_true",
                     help="scan with per-XCD row ownership (A/B of the scan kernels)")
     args = ap.parse_args()
+    if args.compare_steps < 0:
+        args.compare_steps = args.steps
 
     if args.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
@@ -549,75 +560,103 @@ def main():
                      lean_report=not args.full_report, scan_dedup=args.scan_dedup,
                      scan_lds_filter=args.scan_lds_filter, overlap_report=overlap,
                      scan_partition=args.scan_partition)
+
+    # the window is filled first: slices 0 .. k-2 build the state, so that
+    # every warm-up and timed slice closes a full window (Section 5.2 reports
+    # the windows W(0,k), W(1,k), ...); they are neither warm-up nor timed
+    prefill = 0 if args.no_prefill else mon["k"] - 1
     t_w = time.perf_counter()
-    for s in range(args.warmup):
+    for s in range(prefill):
         ds.generate(s, out=buf, stream=st)
         m.scan(buf)
         m.estimate(copy=False)
-        if s % 50 == 0:
-            print("warmup slice %d (%.1fs)" % (s, time.perf_counter() - t_w), file=sys.stderr,
+        if s % 100 == 0:
+            print("prefill slice %d (%.1fs)" % (s, time.perf_counter() - t_w), file=sys.stderr,
                   flush=True)
-
-    lat = []
-    total_s = 0.0
-    done = 0
+    del buf
     seg_bufs = []
-    tm = None
-    while done < args.steps:
-        seg = min(args.segment, args.steps - done)
-        # the segment's pairs, resident in HBM (or, for --host-ingest, in
-        # pinned host memory) before its timed region
-        while len(seg_bufs) < seg:
+
+    def segment(mode, first, count):
+        """Runs slices first .. first+count-1 in `mode`, their pairs generated
+        into HBM (or, for --host-ingest, pinned host memory) beforehand.
+        Returns the seconds spent, each slice's slice-end latency on the device
+        clock (from the start of its end-of-slice work, right after its last
+        scan, to its report complete in host memory), the same on the host
+        clock in the plain form (from the scan's end to the report), every
+        report's candidate count and window flag, and the last report."""
+        while len(seg_bufs) < count:
             seg_bufs.append(
                 torch.empty(2 * n_pairs, dtype=torch.int32, pin_memory=True) if args.host_ingest
                 else torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda"))
-        for i in range(seg):
+        for i in range(count):
             if args.host_ingest:
-                ds.generate(args.warmup + done + i, out=buf, stream=st)
-                seg_bufs[i].copy_(buf)
+                tmp = ds.generate(first + i, stream=st)
+                seg_bufs[i].copy_(tmp)
             else:
-                ds.generate(args.warmup + done + i, out=seg_bufs[i], stream=st)
+                ds.generate(first + i, out=seg_bufs[i], stream=st)
         torch.cuda.synchronize()
-        if tm is None:
-            m.timings(reset=True)
+        lat, host_lat, cands, full = [], [], [], []
+        r = None
         t0 = time.perf_counter()
-        if args.mode == "plain":
-            for i in range(seg):
+        if mode == "plain":
+            for i in range(count):
                 m.scan(seg_bufs[i])
                 st.synchronize()             # the slice's last pair is scanned
                 ts = time.perf_counter()
                 r = m.estimate(copy=False)   # returns with the report in host memory
-                lat.append((time.perf_counter() - ts) * 1e3)
+                host_lat.append((time.perf_counter() - ts) * 1e3)
+                lat.append(r.latency_ms)
+                cands.append(int(r.n))
+                full.append(bool(r.window_full))
         else:
             # the host runs ahead: slice i is closed and slice i+1's scan is
             # enqueued before the report of slice i-1 is collected (two reports
-            # may be pending), so the device never waits for the host; the
-            # latency is the device's own, from the start of a slice's
-            # end-of-slice work, right after its last scan, to its report in
-            # host memory
+            # may be pending), so the device never waits for the host
             m.scan(seg_bufs[0])
             m.close_slice()
-            if seg > 1:
+            if count > 1:
                 m.scan(seg_bufs[1])
-            for i in range(1, seg + 1):
-                if i < seg:
+            for i in range(1, count + 1):
+                if i < count:
                     m.close_slice()
-                    if i + 1 < seg:
+                    if i + 1 < count:
                         m.scan(seg_bufs[i + 1])   # runs while slice i is estimated
                 r = m.wait_report(copy=False)
                 lat.append(r.latency_ms)
+                cands.append(int(r.n))
+                full.append(bool(r.window_full))
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        total_s += t1 - t0
-        done += seg
-        print("timed %d/%d slices (%.2fs)" % (done, args.steps, total_s), file=sys.stderr,
-              flush=True)
-        tm = True
+        return time.perf_counter() - t0, lat, host_lat, cands, full, r
+
+    def run_timed(mode, first, steps):
+        total, lat, host_lat, cands, full, r = 0.0, [], [], [], [], None
+        done = 0
+        while done < steps:
+            seg = min(args.segment, steps - done)
+            dt, l, hl, c, f, r = segment(mode, first + done, seg)
+            total += dt
+            lat += l
+            host_lat += hl
+            cands += c
+            full += f
+            done += seg
+            print("%s: timed %d/%d slices (%.2fs)" % (mode, done, steps, total), file=sys.stderr,
+                  flush=True)
+        return total, np.array(lat), np.array(host_lat), cands, full, r
+
+    first = prefill
+    if args.warmup:
+        segment(args.mode, first, args.warmup)
+        print("warm-up: %d slices" % args.warmup, file=sys.stderr, flush=True)
+        first += args.warmup
+    m.timings(reset=True)
+    total_s, lat, host_lat, cands, full, r = run_timed(args.mode, first, args.steps)
     tm = m.timings(reset=True)
+    timed_slices = [first, first + args.steps - 1]
+    first += args.steps
 
     pairs = args.steps * n_pairs
     value = pairs / total_s
-    lat = np.array(lat)
     g = mon
     tau = 0
     while g["g"] * (1 << tau) < g["theta"]:
@@ -631,6 +670,10 @@ def main():
                    "k_scan_xcd" if args.scan_xcd else "k_scan_flat")
     stages = {k: tm[k] / max(1, tm["estimates"]) for k in
               ("scan_ms", "sweep_ms", "finalize_ms", "estimate_ms", "slide_ms", "report_ms")}
+    # the DR arrays the scan stores into: in the 256 MB last-level cache
+    # (Infinity Cache) or beyond it in HBM
+    footprint = 2 * g["u"] * (g["v_le"] * g["G"] + g["v_re"] * g["g"])
+    level = "mall" if footprint <= (256 << 20) else "hbm"
 
     out = {
         "metric": METRIC if not args.host_ingest else
@@ -655,7 +698,8 @@ def main():
                             g["u"] * g["v_le"] * g["G"], g["theta"])),
             "u": g["u"], "v_re": g["v_re"], "g": g["g"], "v_le": g["v_le"], "g_le": g["G"],
             "window": g["k"], "theta": g["theta"], "pairs_per_slice": n_pairs,
-            "slices_timed": [args.warmup, args.warmup + args.steps - 1],
+            "prefill_slices": prefill,
+            "slices_timed": timed_slices,
             "mode": args.mode, "graph": graph, "scan_blocks": args.scan_blocks,
             "scan_xcd": args.scan_xcd, "scan_dedup": args.scan_dedup,
             "scan_lds_filter": args.scan_lds_filter, "overlap_report": overlap,
@@ -664,17 +708,21 @@ def main():
             "report": ("full: ip, est, flags, |ULE|^k, |URE|^k (18 B/candidate)"
                        if args.full_report else "ip, est, flags (13 B/candidate)"),
         },
+        "latency_clock": "device (start of the slice's end-of-slice work to its report in "
+                         "host memory)",
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "stage_ms_per_slice": stages,
-        "state": {"candidates": int(r.n), "up": r.up,
+        "state": {"window_full": bool(all(full)),
+                  "candidates": [min(cands), max(cands)],
+                  "up": r.up,
                   "row_fill_frac": [float(x) / (g["v_le"] * g["G"]) for x in r.row_fill],
                   "n_touched": int(r.n_touched), "n_new": int(r.n_new)},
         "roofline": {
             "kernel": ("k_scan_partition (k_scan_part + k_scan_mark + k_scan_stamp, "
                        "Algorithm 2)" if args.scan_partition else
                        "%s (Algorithm 2)" % scan_kernel),
-            "bound": "hbm",
+            "bound": level,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -682,35 +730,79 @@ def main():
             "traffic": measured_traffic(scan_kernel, args.workload),
             "bytes_per_pair": scan_bytes_per_pair(g["u"], tau),
             "launch_ms": scan_ms, "launches_timed": tm["scan_launches"],
+            "footprint_bytes": footprint,
             "random_stores_per_s": g["u"] * (1 + 2.0 ** -tau) * n_pairs / (scan_ms * 1e-3),
         },
     }
-    if tuned:
-        # the same launch alone on the GPU: the autotuner's timing of the chosen
-        # form (the timed region's scans share the GPU with the candidate work
-        # of the slice before in the streaming form)
-        alone = per_launch_bytes / (tuned["ms"] * 1e-3) / 1e9
-        out["roofline"]["alone"] = {"launch_ms": tuned["ms"], "achieved": alone,
-                                    "frac": alone / HBM_PEAK_GBS}
-    # achievable rate of random 2-byte stores over the scan's own footprint
-    # (LE + RE stamp arrays), measured with the same store pattern and nothing else
+    if args.host_ingest:
+        out["p50_host_ms"] = float(np.percentile(host_lat, 50)) if len(host_lat) else None
+
+    # the report's delivery: the candidate work's phase writes 13 (or 18) bytes
+    # per candidate into pinned host memory over PCIe
+    rep_bytes = (18 if args.full_report else 13) * float(np.mean(cands))
+    est_ms = stages["estimate_ms"]
     import probe
-    footprint = 2 * g["u"] * (g["v_le"] * g["G"] + g["v_re"] * g["g"])
+    pcie = probe.host_write_rate()
+    out["roofline_report"] = {
+        "kernel": "k_estimate (Eq9, report into pinned host memory) with the candidate check "
+                  "before it (one timed phase)",
+        "bound": "pcie", "bytes_per_slice": rep_bytes, "phase_ms": est_ms,
+        "achieved_GBps": rep_bytes / (est_ms * 1e-3) / 1e9 if est_ms > 0 else None,
+        "ceiling_GBps": pcie / 1e9,
+        "ceiling_source": "measured: coalesced kernel stores into pinned host memory",
+        "frac": rep_bytes / (est_ms * 1e-3) / pcie if est_ms > 0 else None}
+
+    # ceilings at the scan's own footprint: random 2-byte stores (the flat
+    # scan's pattern), and a streaming copy over the partitioned scan's working
+    # set (its pairs, DR-index scratch and DR arrays)
     ceiling = probe.random_store_rate(footprint)
     stores_per_s = out["roofline"]["random_stores_per_s"]
     out["roofline"]["random_store_ceiling_per_s"] = ceiling
     out["roofline"]["frac_of_random_store_ceiling"] = stores_per_s / ceiling
-    out["roofline"]["footprint_bytes"] = footprint
+    if args.scan_partition:
+        ws = footprint + 16 * n_pairs
+        copy_rate = probe.stream_copy_rate(ws // 2)
+        out["roofline"]["stream_copy_ceiling_GBps"] = copy_rate / 1e9
+        out["roofline"]["stream_copy_footprint_bytes"] = ws
+        if out["roofline"]["traffic"]:
+            moved = out["roofline"]["traffic"] / (scan_ms * 1e-3)
+            out["roofline"]["traffic_GBps"] = moved / 1e9
+            out["roofline"]["frac_of_stream_copy_ceiling"] = moved / copy_rate
     if args.probe_mib:
         out["random_store_rates_per_s"] = {
             mib: probe.random_store_rate(int(mib) << 20) for mib in args.probe_mib.split(",")}
+
+    if args.mode == "streaming" and args.compare_steps > 0:
+        # the plain form on the same monitor, right after: each slice scanned,
+        # then closed and its report collected before the next slice's scan
+        m.timings(reset=True)
+        p_total, p_lat, p_host, p_cands, p_full, _ = run_timed("plain", first, args.compare_steps)
+        ptm = m.timings(reset=True)
+        p_scan = ptm["scan_ms"] / max(1, ptm["scan_launches"])
+        out["plain"] = {
+            "value": args.compare_steps * n_pairs / p_total,
+            "ms_per_step": p_total * 1e3 / args.compare_steps,
+            "p50_ms": float(np.percentile(p_lat, 50)),
+            "p99_ms": float(np.percentile(p_lat, 99)),
+            "p99_host_ms": float(np.percentile(p_host, 99)),
+            "slices_timed": [first, first + args.compare_steps - 1],
+            "window_full": bool(all(p_full)), "candidates": [min(p_cands), max(p_cands)],
+            "scan_launch_ms": p_scan}
+        out["plain_p99_ms"] = out["plain"]["p99_ms"]
+        alone = per_launch_bytes / (p_scan * 1e-3) / 1e9
+        out["roofline"]["alone"] = {"launch_ms": p_scan, "achieved": alone,
+                                    "frac": alone / HBM_PEAK_GBS,
+                                    "source": "the scans of the plain-form slices, alone on "
+                                              "the GPU"}
     if not args.no_cpu_baseline:
-        rate, dt, n = oracle_baseline(stream, mon, args.cpu_slices)
+        rate, dt, n, ncand = oracle_baseline(stream, mon, args.cpu_slices)
         out["cpu_baseline"] = {
             "value": rate, "unit": "packets/s", "cores": 1, "kind": "oracle",
             "sample": ("first %d slices (%d pairs) of the same workload, scan + end-of-slice "
-                       "estimate, single-threaded C oracle, %.1f s on %s (nproc %d)"
-                       % (args.cpu_slices, n, dt, cpu_model(), os.cpu_count())),
+                       "estimate, single-threaded C oracle, %.1f s on %s (nproc %d); the window "
+                       "is %d/%d slices full at the end of the sample, with %d candidates"
+                       % (args.cpu_slices, n, dt, cpu_model(), os.cpu_count(),
+                          args.cpu_slices, g["k"], ncand)),
         }
     print(json.dumps(out), flush=True)
     m.close()

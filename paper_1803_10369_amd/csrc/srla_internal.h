@@ -191,10 +191,12 @@ hipError_t launch_merge(const uint32_t* ncsip, const PipeState* ps, const uint32
 hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
                              double* up, hipStream_t st);
 
+// Eq9 for every candidate; rows whose row fill is g' * v_le (every LE DR
+// inside the window) are not gathered
 hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
                            const uint64_t* act, const double* up,
-                           const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
-                           hipStream_t st);
+                           const unsigned long long* row_fill, const Geo& geo, uint8_t* cflags,
+                           const ReportPtrs& out, hipStream_t st);
 
 // copies the first *n report entries from device staging arrays to the host
 // arrays (U and W only where `to` has them); with expect != 0, only once
@@ -221,5 +223,14 @@ hipError_t launch_mark_done(HostStatus* out, hipStream_t st);
 hipError_t launch_status(Counters* cnt, uint32_t* tcount, const double* up,
                          const unsigned long long* row_fill, uint32_t u, PipeState* ps,
                          uint32_t p, HostStatus* out, uint32_t* report_n, hipStream_t st);
+// the two halves of launch_status (report_n not written): publish copies the
+// slice's counters, Eq8 and row fills into the host block and reads the
+// clock (the report is complete); advance carries |NCSIP| into the state,
+// moves it to the next slice and clears the counters, once Algorithm 3's
+// carried list is final
+hipError_t launch_publish(const Counters* cnt, const uint32_t* tcount, const double* up,
+                          const unsigned long long* row_fill, uint32_t u, const PipeState* ps,
+                          uint32_t p, HostStatus* out, hipStream_t st);
+hipError_t launch_advance(Counters* cnt, uint32_t* tcount, PipeState* ps, hipStream_t st);
 
 }  // namespace srla

@@ -448,7 +448,7 @@ template <int kU, int kWpl>
 __global__ __launch_bounds__(kBlock) void k_estimate(
     const uint32_t* __restrict__ csip, const Counters* __restrict__ cnt,
     const uint64_t* __restrict__ bitmap, const uint64_t* __restrict__ act,
-    const double* __restrict__ up_p, Geo geo,
+    const double* __restrict__ up_p, const unsigned long long* __restrict__ row_fill, Geo geo,
     uint32_t lg_log2, uint8_t* __restrict__ cflags, uint32_t* __restrict__ out_ip,
     double* __restrict__ out_est, uint8_t* __restrict__ out_flags, uint32_t* __restrict__ out_U,
     uint8_t* __restrict__ out_W) {
@@ -459,6 +459,13 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
   const uint32_t sub = threadIdx.x & (lg - 1u);
   const uint32_t n = cnt->n_cand;
   const uint64_t gmask = geo.g == 64u ? ~0ull : ((1ull << geo.g) - 1ull);
+  // rows whose every LE DR is inside the window (|LDR(i)|^k = g' * v): their
+  // bitmap words are all ones, the identity of the AND, so they are not read
+  uint32_t gather = 0;
+  const unsigned long long row_cells = (unsigned long long)geo.G * geo.v_le;
+#pragma unroll
+  for (int r = 0; r < kU; ++r)
+    if (r < (int)geo.u && row_fill[r] != row_cells) gather |= 1u << r;
   for (uint64_t base = (uint64_t)blockIdx.x * kEstPerBlock; base < n;
        base += (uint64_t)gridDim.x * kEstPerBlock) {
     const uint32_t in_batch =
@@ -478,13 +485,16 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
       const bool sre_lane = valid && sub < geo.u;
       SreWords sw;
       if (sre_lane) sw = sre_fetch(act, geo, sub, hrange(my_h, geo.v_re));
-      if (valid) {
+      if (valid && gather == 0u) {
+        // every row full: the union LE is full as well
+        if (sub == 0) ucount = geo.G;
+      } else if (valid) {
         for (uint32_t x = kWpl * sub; x < geo.words; x += kWpl * lg) {
           if constexpr (kWpl == 2) {
             uint4 w[kU];
 #pragma unroll
             for (int r = 0; r < kU; ++r)
-              w[r] = r < (int)geo.u
+              w[r] = (gather >> r) & 1u
                          ? *reinterpret_cast<const uint4*>(
                                bitmap + ((uint64_t)r * geo.v_le +
                                          hrange(mas(geo.rh[r], a), geo.v_le)) * geo.words + x)
@@ -500,7 +510,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
             uint64_t w[kU];
 #pragma unroll
             for (int r = 0; r < kU; ++r)
-              w[r] = r < (int)geo.u
+              w[r] = (gather >> r) & 1u
                          ? bitmap[((uint64_t)r * geo.v_le + hrange(mas(geo.rh[r], a), geo.v_le)) *
                                       geo.words + x]
                          : ~0ull;
@@ -592,34 +602,40 @@ static uint32_t est_grid() {
 template <int kU, int kWpl>
 static hipError_t launch_estimate_u(const uint32_t* csip, const Counters* cnt,
                                     const uint64_t* bitmap, const uint64_t* act, const double* up,
-                                    const Geo& geo, uint32_t l, uint8_t* cflags,
-                                    const ReportPtrs& out, hipStream_t st) {
+                                    const unsigned long long* row_fill, const Geo& geo,
+                                    uint32_t l, uint8_t* cflags, const ReportPtrs& out,
+                                    hipStream_t st) {
   static const uint32_t grid = est_grid<kU, kWpl>();
   hipLaunchKernelGGL((k_estimate<kU, kWpl>), dim3(grid), dim3(kBlock), 0, st, csip, cnt, bitmap,
-                     act, up, geo, l, cflags, out.ip, out.est, out.flags, out.U, out.W);
+                     act, up, row_fill, geo, l, cflags, out.ip, out.est, out.flags, out.U,
+                     out.W);
   return hipGetLastError();
 }
 
 template <int kU>
 static hipError_t launch_estimate_w(const uint32_t* csip, const Counters* cnt,
                                     const uint64_t* bitmap, const uint64_t* act, const double* up,
-                                    const Geo& geo, uint32_t l, uint8_t* cflags,
-                                    const ReportPtrs& out, hipStream_t st) {
+                                    const unsigned long long* row_fill, const Geo& geo,
+                                    uint32_t l, uint8_t* cflags, const ReportPtrs& out,
+                                    hipStream_t st) {
   if (est_wpl(geo) == 2)
-    return launch_estimate_u<kU, 2>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
-  return launch_estimate_u<kU, 1>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
+    return launch_estimate_u<kU, 2>(csip, cnt, bitmap, act, up, row_fill, geo, l, cflags, out,
+                                    st);
+  return launch_estimate_u<kU, 1>(csip, cnt, bitmap, act, up, row_fill, geo, l, cflags, out, st);
 }
 
 hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
                            const uint64_t* act, const double* up,
-                           const Geo& geo, uint8_t* cflags, const ReportPtrs& out,
-                           hipStream_t st) {
+                           const unsigned long long* row_fill, const Geo& geo, uint8_t* cflags,
+                           const ReportPtrs& out, hipStream_t st) {
   static_assert(kMaxU <= 16, "k_estimate is unrolled for at most 16 rows");
   const uint32_t l = est_lg_log2(geo);
   if (geo.u > (1u << l)) return hipErrorInvalidValue;
-  if (geo.u <= 4) return launch_estimate_w<4>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
-  if (geo.u <= 8) return launch_estimate_w<8>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
-  return launch_estimate_w<16>(csip, cnt, bitmap, act, up, geo, l, cflags, out, st);
+  if (geo.u <= 4)
+    return launch_estimate_w<4>(csip, cnt, bitmap, act, up, row_fill, geo, l, cflags, out, st);
+  if (geo.u <= 8)
+    return launch_estimate_w<8>(csip, cnt, bitmap, act, up, row_fill, geo, l, cflags, out, st);
+  return launch_estimate_w<16>(csip, cnt, bitmap, act, up, row_fill, geo, l, cflags, out, st);
 }
 
 // ------------------------------------------------------------------ SI
@@ -782,6 +798,52 @@ __global__ void k_mark_done(HostStatus* __restrict__ out) {
 
 hipError_t launch_mark_done(HostStatus* out, hipStream_t st) {
   hipLaunchKernelGGL(k_mark_done, dim3(1), dim3(64), 0, st, out);
+  return hipGetLastError();
+}
+
+__global__ void k_publish(const Counters* __restrict__ cnt, const uint32_t* __restrict__ tcount,
+                          const double* __restrict__ up,
+                          const unsigned long long* __restrict__ row_fill, uint32_t u,
+                          const PipeState* __restrict__ ps, uint32_t p,
+                          HostStatus* __restrict__ out) {
+  if (blockIdx.x != 0) return;
+  const uint32_t t = threadIdx.x;
+  Counters c = *cnt;
+  c.touched = *tcount;
+  if (t < sizeof(Counters) / 4) ((uint32_t*)&out->cnt)[t] = ((const uint32_t*)&c)[t];
+  if (t < u) out->row_fill[t] = row_fill[t];
+  if (t == 0) {
+    out->up = *up;
+    out->slice = ps->slice;
+    out->t_close = ps->t_close[p];
+    out->t_done = wall_clock64();   // every earlier kernel of the report has finished
+  }
+}
+
+__global__ void k_advance(Counters* __restrict__ cnt, uint32_t* __restrict__ tcount,
+                          PipeState* __restrict__ ps) {
+  if (blockIdx.x != 0) return;
+  const uint32_t t = threadIdx.x;
+  if (t == 0) {
+    ps->n_ncsip = cnt->n_keep;
+    ps->slice = ps->slice + 1;
+    ps->now = (uint32_t)(ps->slice % kStampPeriod) + 1u;
+    *tcount = 0u;
+  }
+  __syncthreads();
+  if (t < sizeof(Counters) / 4) ((uint32_t*)cnt)[t] = 0u;
+}
+
+hipError_t launch_publish(const Counters* cnt, const uint32_t* tcount, const double* up,
+                          const unsigned long long* row_fill, uint32_t u, const PipeState* ps,
+                          uint32_t p, HostStatus* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, cnt, tcount, up, row_fill, u, ps, p,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(Counters* cnt, uint32_t* tcount, PipeState* ps, hipStream_t st) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, cnt, tcount, ps);
   return hipGetLastError();
 }
 

@@ -101,7 +101,11 @@ enum Stage { ST_SCAN, ST_SWEEP, ST_FINALIZE, ST_ESTIMATE, ST_SLIDE, ST_REPORT, S
 // PH_SORT: without the overlapped report, the sort of the closed slice's
 // sampled sources, which the pipeline stream runs as soon as the slice's
 // scans end (beside the snapshot), ahead of the rest of the second phase
-enum Phase { PH_SNAPSHOT = 0, PH_FINISH = 1, PH_FINISH_GO = 2, PH_SORT = 3 };
+// PH_SLIDE: without the overlapped report, the tail of the second phase that
+// the report does not wait for: Algorithm 3's carried list and SI counters,
+// and the state moved to the next slice
+enum Phase { PH_SNAPSHOT = 0, PH_FINISH = 1, PH_FINISH_GO = 2, PH_SORT = 3, PH_SLIDE = 4,
+             PH_N = 5 };
 
 struct TimedSpan {
   int stage;
@@ -117,6 +121,7 @@ struct srla_monitor {
   Geo geo{};
   hipStream_t stream = nullptr;  // scans
   hipStream_t pipe = nullptr;    // end-of-slice pipeline (library-owned)
+  int device = -1;               // the HIP device the monitor was created on
   bool pipe_own = false, copy_own = false;   // on a hardware queue of their own
   bool own_stream = false;
   uint64_t slice = 0;            // open slice
@@ -189,14 +194,14 @@ struct srla_monitor {
   hipEvent_t ev_snap = nullptr;                 // after the last closed slice's snapshot phase
   hipEvent_t ev_scanned = nullptr;              // after the last closed slice's scans
   hipEvent_t ev_done[2] = {nullptr, nullptr};   // after the whole pipeline, by slice parity
+  hipEvent_t ev_pub[2] = {nullptr, nullptr};    // the report and status are in host memory
   uint32_t n_pending = 0;         // closed slices whose reports are not collected (<= 2)
   int clock_khz = 0;              // rate of the device wall clock
   bool finish_deferred = false;   // the last closed slice's second phase is not enqueued yet
 
   // replayable pipeline: [phase][parity]
   bool use_graph = false;
-  hipGraphExec_t graph[4][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr},
-                                {nullptr, nullptr}};
+  hipGraphExec_t graph[PH_N][2] = {};
 
   // host-input ring: H2D copies on their own stream into two device chunks
   // (through two pinned bounce chunks when the caller's memory is pageable),
@@ -468,12 +473,27 @@ hipError_t enqueue_sort(srla_monitor* m, int p, hipStream_t st) {
   return e;
 }
 
+// Algorithm 3 after the estimate of the slice of parity p: the carried list
+// (the candidates whose SRE is still inside the window after the slide, as
+// k_estimate flagged them) and the SI counters.
+hipError_t enqueue_slide(srla_monitor* m, int p, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  hipEvent_t ta = nullptr;
+  const bool spans = !m->use_graph;
+  if (spans) span_begin(m, st, &ta);
+  e = compact_u32(m->cflags, 8u, m->csip, &m->cnt->n_cand, m->cap, m->carried[p ^ 1],
+                  &m->cnt->n_keep, m->cblockw, st);
+  if (e == hipSuccess) e = launch_si_update(m->csip, m->cflags, m->cnt, m->si_cnt, m->geo, st);
+  if (spans) span_end(m, st, ST_SLIDE, ta);
+  return e;
+}
+
 // The candidate work of the closing slice: candidate check of its sampled
-// sources (sorted first unless `sorted`), merge with the carried list, Eq9
-// for every candidate (report entries to `out`), Algorithm 3's carried list
-// and SI counters.
+// sources (sorted first unless `sorted`), merge with the carried list and
+// Eq9 for every candidate (report entries to `out`); with `slide`, also
+// Algorithm 3's carried list and SI counters.
 hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hipStream_t st,
-                              bool sorted) {
+                              bool sorted, bool slide) {
   const Geo& geo = m->geo;
   hipError_t e = hipSuccess;
   uint32_t* tc = m->tcount + p;
@@ -493,14 +513,10 @@ hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hip
   if (e == hipSuccess)
     e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
   if (e == hipSuccess)
-    e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->up[p], geo, m->cflags, out, st);
+    e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->up[p], m->row_fill[p], geo,
+                        m->cflags, out, st);
   if (spans) span_end(m, st, ST_ESTIMATE, ta);
-  if (spans) span_begin(m, st, &ta);
-  if (e == hipSuccess)
-    e = compact_u32(m->cflags, 8u, m->csip, &m->cnt->n_cand, m->cap, m->carried[p ^ 1],
-                    &m->cnt->n_keep, m->cblockw, st);
-  if (e == hipSuccess) e = launch_si_update(m->csip, m->cflags, m->cnt, m->si_cnt, geo, st);
-  if (spans) span_end(m, st, ST_SLIDE, ta);
+  if (e == hipSuccess && slide) e = enqueue_slide(m, p, st);
   return e;
 }
 
@@ -509,18 +525,25 @@ hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hip
 // slice's scans follow it there.  Normally it is the snapshot, and the
 // candidate work, the report (written by the estimate kernel straight into
 // host memory) and the status follow on the pipeline stream, beside those
-// scans.  With SRLA_CFG_OVERLAP_REPORT the first phase also does the
-// candidate work, into the parity's device staging arrays, and the status,
-// and only the PCIe copy of the report overlaps the scans.
+// scans, and after them (PH_SLIDE) Algorithm 3's carried list and SI, which
+// the report does not wait for.  With SRLA_CFG_OVERLAP_REPORT the first
+// phase also does the candidate work, into the parity's device staging
+// arrays, and the status, and only the PCIe copy of the report overlaps the
+// scans.
 hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
   hipError_t e = hipSuccess;
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (phase == PH_SORT) return enqueue_sort(m, p, st);
+  if (phase == PH_SLIDE) {
+    e = enqueue_slide(m, p, st);
+    if (e == hipSuccess) e = launch_advance(m->cnt, m->tcount + p, m->ps, st);
+    return e;
+  }
   if (phase == PH_SNAPSHOT) {
     e = enqueue_snapshot(m, p, st);
     if (e == hipSuccess && m->overlap_report) {
-      e = enqueue_candidates(m, p, m->d_staging[p], st, false);
+      e = enqueue_candidates(m, p, m->d_staging[p], st, false, true);
       if (spans) span_begin(m, st, &ta);
       if (e == hipSuccess)
         e = launch_status(m->cnt, m->tcount + p, m->up[p], m->row_fill[p], m->geo.u, m->ps,
@@ -530,7 +553,7 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
     }
     return e;
   }
-  if (!m->overlap_report) e = enqueue_candidates(m, p, m->d_report[p], st, true);
+  if (!m->overlap_report) e = enqueue_candidates(m, p, m->d_report[p], st, true, false);
   if (spans) span_begin(m, st, &ta);
   if (m->overlap_report) {
     // PH_FINISH_GO: the next slice (parity p ^ 1) has its first scan behind a mark
@@ -540,9 +563,8 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
                              st);
     if (e == hipSuccess) e = launch_mark_done(m->d_status[p], st);
   } else if (e == hipSuccess) {
-    e = launch_status(m->cnt, m->tcount + p, m->up[p], m->row_fill[p], m->geo.u, m->ps,
-                      (uint32_t)p, m->d_status[p],
-                      nullptr, st);
+    e = launch_publish(m->cnt, m->tcount + p, m->up[p], m->row_fill[p], m->geo.u, m->ps,
+                       (uint32_t)p, m->d_status[p], st);
   }
   if (spans) span_end(m, st, ST_REPORT, ta);
   return e;
@@ -599,6 +621,7 @@ void release(srla_monitor* m) {
     hfree(m->h_U[q]); hfree(m->h_W[q]);
     delete[] m->h_row_fill64[q];
     if (m->ev_done[q]) (void)hipEventDestroy(m->ev_done[q]);
+    if (m->ev_pub[q]) (void)hipEventDestroy(m->ev_pub[q]);
   }
   for (int i = 0; i < 2; ++i) {
     hfree(m->h_stage[i]);
@@ -716,8 +739,12 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   }
   {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&m->clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+    if (hipGetDevice(&dev) != hipSuccess) {
+      release(m);
+      return SRLA_E_DEVICE;
+    }
+    m->device = dev;
+    if (hipDeviceGetAttribute(&m->clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
       m->clock_khz = 0;
     (void)hipGetLastError();
   }
@@ -788,6 +815,8 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
                 (weights && dev_view(m->h_W[q], &m->d_report[q].W) != hipSuccess)))
       rc = SRLA_E_DEVICE;
     if (!rc && hipEventCreateWithFlags(&m->ev_done[q], hipEventDisableTiming) != hipSuccess)
+      rc = SRLA_E_DEVICE;
+    if (!rc && hipEventCreateWithFlags(&m->ev_pub[q], hipEventDisableTiming) != hipSuccess)
       rc = SRLA_E_DEVICE;
   }
   if (!rc && hipEventCreateWithFlags(&m->ev_scanned, hipEventDisableTiming) != hipSuccess)
@@ -901,9 +930,16 @@ int enqueue_finish(srla_monitor* m, bool go) {
   }
   HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_snap, 0));
   if (m->use_graph) span_begin(m, m->pipe, &ta);
-  const int rc = run_phase(m, go ? PH_FINISH_GO : PH_FINISH, pc, m->pipe);
+  int rc = run_phase(m, go ? PH_FINISH_GO : PH_FINISH, pc, m->pipe);
   if (rc) return rc;
   if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
+  HIP_TRY(m, hipEventRecord(m->ev_pub[pc], m->pipe));
+  if (!m->overlap_report) {
+    if (m->use_graph) span_begin(m, m->pipe, &ta);
+    rc = run_phase(m, PH_SLIDE, pc, m->pipe);
+    if (rc) return rc;
+    if (m->use_graph) span_end(m, m->pipe, ST_SLIDE, ta);
+  }
   HIP_TRY(m, hipEventRecord(m->ev_done[pc], m->pipe));
   m->finish_deferred = false;
   return SRLA_OK;
@@ -1068,7 +1104,9 @@ int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
     const int rc = enqueue_finish(m, false);
     if (rc) return rc;
   }
-  HIP_TRY(m, hipEventSynchronize(m->ev_done[q]));
+  // the report is complete once it is published; the carried list and SI
+  // (ev_done) may still be in progress behind it
+  HIP_TRY(m, hipEventSynchronize(m->ev_pub[q]));
   m->n_pending--;
   const HostStatus& hs = *m->h_status[q];
   const Counters c = hs.cnt;

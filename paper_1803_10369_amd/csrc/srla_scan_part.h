@@ -32,10 +32,16 @@ inline uint64_t part_mark_words(uint64_t n_le) {
 // stores sorted by region before they are issued.  Same results as
 // launch_scan.  entries / offs: part_entry_words() and
 // part_offset_words(n_le) uint16 words, marks: part_mark_words(n_le) uint32
-// words of device scratch, reused by every launch on the stream.
+// words of device scratch, reused by every launch on the stream.  A smaller
+// scratch serves fewer chunks per partition round (round_chunks <=
+// kPartChunks: round_chunks * kPartEntries entry words and (regions + 1) *
+// round_chunks offset words) and fewer marking workgroups per region (split
+// <= kPartSplit: regions * split * 1024 mark words).
 hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& geo,
                                  uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
                                  uint32_t* tcount, uint16_t* entries, uint16_t* offs,
-                                 uint32_t* marks, hipStream_t st);
+                                 uint32_t* marks, hipStream_t st,
+                                 uint32_t round_chunks = kPartChunks,
+                                 uint32_t split = kPartSplit);
 
 }  // namespace srla

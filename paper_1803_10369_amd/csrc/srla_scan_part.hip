@@ -69,14 +69,15 @@ __device__ __forceinline__ void sre_pair(uint32_t a, uint32_t b, bool valid, con
 // Chunk c of the round holds pairs [c * ppc, c * ppc + cnt); its LE DR
 // indices (cnt * u <= kPartEntries of them) go to entries[c * kPartEntries
 // ...], region r's at offsets [offs[r][c], offs[r + 1][c]) (offs is region-
-// major with kPartChunks columns, regions + 1 rows).  U > 0: u is U and each
+// major with `stride` >= chunks-per-round columns, regions + 1 rows).  U > 0: u is U and each
 // thread keeps its DR indices in registers between the counting and the
 // placing pass (then ppc * U == kPartEntries); U == 0: any u, recomputed.
 template <int U>
 __global__ __launch_bounds__(kPartThreads) void k_scan_part(
     const uint32_t* __restrict__ pairs, uint64_t n, uint32_t ppc, Geo geo, uint16_t code,
     uint16_t* __restrict__ re, uint32_t* __restrict__ touched, uint32_t* __restrict__ tcount,
-    uint32_t regions, uint16_t* __restrict__ entries, uint16_t* __restrict__ offs) {
+    uint32_t regions, uint16_t* __restrict__ entries, uint16_t* __restrict__ offs,
+    uint32_t stride) {
   __shared__ __align__(16) uint16_t ent[kPartEntries];
   __shared__ uint32_t hist[kPartMaxRegions + 1];
   __shared__ uint32_t cur[kPartMaxRegions];
@@ -193,12 +194,12 @@ __global__ __launch_bounds__(kPartThreads) void k_scan_part(
   const uint4* srcv = reinterpret_cast<const uint4*>(ent);
   for (uint32_t q = tid; q * 8u < total; q += kPartThreads) dst[q] = srcv[q];
   for (uint32_t r = tid; r <= regions; r += kPartThreads)
-    offs[(uint64_t)r * kPartChunks + blockIdx.x] = (uint16_t)hist[r];
+    offs[(uint64_t)r * stride + blockIdx.x] = (uint16_t)hist[r];
 }
 
 // Marking: workgroup (r, q) takes region r's segments of the q-th of
-// kPartSplit equal shares of the chunks, marks the DRs they name in an LDS
-// bitmap and writes the bitmap to its slot of `marks`.  Each wavefront works
+// gridDim.y (at most kPartSplit) equal shares of the chunks, marks the DRs
+// they name in an LDS bitmap and writes the bitmap to its slot of `marks`.  Each wavefront works
 // on 8 chunks' segments at a time, consecutive lanes on consecutive entries.
 // A region that holds a heavy source gets many times the average number of
 // entries; splitting its chunks over kPartSplit workgroups keeps it from
@@ -210,14 +211,14 @@ constexpr uint32_t kWords = kPartRegion / 32;
 
 __global__ __launch_bounds__(kApplyThreads) void k_scan_mark(
     const uint16_t* __restrict__ entries, const uint16_t* __restrict__ offs, uint32_t chunks,
-    uint32_t* __restrict__ marks) {
+    uint32_t stride, uint32_t* __restrict__ marks) {
   __shared__ uint32_t bm[kWords];
   const uint32_t tid = threadIdx.x, lane = __lane_id();
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid / kWave);
   const uint32_t r = blockIdx.x, q = blockIdx.y;
   for (uint32_t w = tid; w < kWords; w += kApplyThreads) bm[w] = 0u;
   __syncthreads();
-  const uint32_t share = (chunks + kPartSplit - 1) / kPartSplit;
+  const uint32_t share = (chunks + gridDim.y - 1) / gridDim.y;
   const uint32_t c_lo = q * share < chunks ? q * share : chunks;
   const uint32_t c_hi = c_lo + share < chunks ? c_lo + share : chunks;
   // this wavefront's chunks: [w_lo, w_hi), their offsets loaded 64 at a time
@@ -225,8 +226,8 @@ __global__ __launch_bounds__(kApplyThreads) void k_scan_mark(
   const uint32_t per_w = (c_hi - c_lo + kApplyWaves - 1) / kApplyWaves;
   const uint32_t w_lo = c_lo + wave * per_w < c_hi ? c_lo + wave * per_w : c_hi;
   const uint32_t w_hi = w_lo + per_w < c_hi ? w_lo + per_w : c_hi;
-  const uint16_t* lo_row = offs + (uint64_t)r * kPartChunks;
-  const uint16_t* hi_row = lo_row + kPartChunks;
+  const uint16_t* lo_row = offs + (uint64_t)r * stride;
+  const uint16_t* hi_row = lo_row + stride;
   for (uint32_t g0 = w_lo; g0 < w_hi; g0 += kWave) {   // uniform per wave
     const uint32_t c = g0 + lane;
     uint32_t lo = 0u, len = 0u;
@@ -271,17 +272,17 @@ __global__ __launch_bounds__(kApplyThreads) void k_scan_mark(
   for (uint32_t w = tid; w < kWords; w += kApplyThreads) out[w] = bm[w];
 }
 
-// Stamping: workgroup r ORs region r's kPartSplit bitmaps and stores the
-// stamp into every marked DR, consecutive lanes on consecutive DRs.
+// Stamping: workgroup r ORs region r's `split` bitmaps and stores the stamp
+// into every marked DR, consecutive lanes on consecutive DRs.
 __global__ __launch_bounds__(kApplyThreads) void k_scan_stamp(const uint32_t* __restrict__ marks,
-                                                             uint32_t regions, uint16_t code,
+                                                             uint32_t regions, uint32_t split,
+                                                             uint16_t code,
                                                              uint16_t* __restrict__ le) {
   __shared__ uint32_t bm[kWords];
   const uint32_t tid = threadIdx.x, r = blockIdx.x;
   for (uint32_t w = tid; w < kWords; w += kApplyThreads) {
     uint32_t x = 0u;
-#pragma unroll
-    for (uint32_t q = 0; q < kPartSplit; ++q) x |= marks[((uint64_t)q * regions + r) * kWords + w];
+    for (uint32_t q = 0; q < split; ++q) x |= marks[((uint64_t)q * regions + r) * kWords + w];
     bm[w] = x;
   }
   __syncthreads();
@@ -293,20 +294,22 @@ __global__ __launch_bounds__(kApplyThreads) void k_scan_stamp(const uint32_t* __
 template <int U>
 hipError_t launch_part_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                          uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
-                         uint16_t* entries, uint16_t* offs, uint32_t* marks, hipStream_t st) {
+                         uint16_t* entries, uint16_t* offs, uint32_t* marks,
+                         uint32_t round_chunks, uint32_t split, hipStream_t st) {
   const uint64_t n_le = (uint64_t)geo.u * geo.v_le * geo.G;
   const uint32_t regions = (uint32_t)((n_le + kPartRegion - 1) >> kPartLog);
   const uint32_t ppc = kPartEntries / geo.u;
-  const uint64_t per_round = (uint64_t)ppc * kPartChunks;
+  const uint64_t per_round = (uint64_t)ppc * round_chunks;
   for (uint64_t p = 0; p < n; p += per_round) {
     const uint64_t np = n - p < per_round ? n - p : per_round;
     const uint32_t chunks = (uint32_t)((np + ppc - 1) / ppc);
     hipLaunchKernelGGL((k_scan_part<U>), dim3(chunks), dim3(kPartThreads), 0, st, pairs + 2 * p,
-                       np, ppc, geo, code, re, touched, tcount, regions, entries, offs);
-    hipLaunchKernelGGL(k_scan_mark, dim3(regions, kPartSplit), dim3(kApplyThreads), 0, st,
-                       entries, offs, chunks, marks);
+                       np, ppc, geo, code, re, touched, tcount, regions, entries, offs,
+                       round_chunks);
+    hipLaunchKernelGGL(k_scan_mark, dim3(regions, split), dim3(kApplyThreads), 0, st,
+                       entries, offs, chunks, round_chunks, marks);
     hipLaunchKernelGGL(k_scan_stamp, dim3(regions), dim3(kApplyThreads), 0, st, marks, regions,
-                       code, le);
+                       split, code, le);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -318,18 +321,25 @@ hipError_t launch_part_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint
 hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& geo,
                                  uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
                                  uint32_t* tcount, uint16_t* entries, uint16_t* offs,
-                                 uint32_t* marks, hipStream_t st) {
+                                 uint32_t* marks, hipStream_t st, uint32_t round_chunks,
+                                 uint32_t split) {
   if (n == 0) return hipSuccess;
   if (!part_scan_fits((uint64_t)geo.u * geo.v_le * geo.G)) return hipErrorInvalidValue;
+  if (round_chunks == 0 || round_chunks > kPartChunks || split == 0 || split > kPartSplit)
+    return hipErrorInvalidValue;
   switch (geo.u) {
     case 4:
-      return launch_part_u<4>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks, st);
+      return launch_part_u<4>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks,
+                              round_chunks, split, st);
     case 8:
-      return launch_part_u<8>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks, st);
+      return launch_part_u<8>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks,
+                              round_chunks, split, st);
     case 16:
-      return launch_part_u<16>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks, st);
+      return launch_part_u<16>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks,
+                               round_chunks, split, st);
     default:
-      return launch_part_u<0>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks, st);
+      return launch_part_u<0>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks,
+                              round_chunks, split, st);
   }
 }
 

@@ -165,10 +165,12 @@ def test_candidates_beyond_one_grid_pass(streaming):
 
 
 def test_merge_beyond_one_grid_pass():
-    """4.3M sources with 4 destinations each (u = 1): more than the 4,194,304
-    candidates one pass of the merge grid writes, carried into the next slice."""
+    """4.5M sources with 5 destinations each (u = 1): about 97 % of them reach
+    W >= 3 (5 draws from g = 8 DRs hit at least 3 of them), more than the
+    4,194,304 candidates one pass of the merge grid writes, carried into the
+    next slice."""
     mon = dict(k=2, theta=8, u=1, v_re=1 << 23, g=8, v_le=1 << 12, G=64, hash_seed=515)
-    gen = _wide_sources(4_300_000, 4, 91)
+    gen = _wide_sources(4_500_000, 5, 91)
     g = srla.Monitor(**mon, max_candidates=1 << 23)
     o = oracle.Monitor(**mon)
     ot = OracleThread()
