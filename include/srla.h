@@ -264,6 +264,29 @@ int srla_scan(srla_monitor_t *m, const uint32_t *pairs, uint64_t n, int on_devic
    slice's source set.) */
 
 /*
+ * srla_scan without allocation, for callers that cannot allocate device
+ * memory (code under HIP stream capture, serving loops that forbid
+ * hipMalloc): the same scan (results identical to srla_scan's), always in
+ * the partitioned form, with its scratch -- DR-index blocks, region offsets,
+ * marking bitmaps -- in one fixed library array of 24.3 MiB per device
+ * (allocated when the library is loaded, held until the process ends)
+ * instead of memory the call or the monitor allocates.  It calls no
+ * allocator, grows no buffer and records no timing events.
+ * pairs: 2n uint32 values (aip, bip) in device memory readable on the
+ *   monitor's stream, kept alive until the scan has run.
+ * Limits (violations return SRLA_E_INVAL and change nothing): at most 2^25
+ *   LE DRs (u * v_le * g_le); the slice's pairs so far plus n within the
+ *   sampled-source capacity the monitor holds (2^20 pairs at creation;
+ *   srla_scan grows it to the largest slice it has scanned); not for
+ *   SRLA_CFG_DISCRETE or SRLA_CFG_OVERLAP_REPORT monitors.
+ * All monitors on a device share its one scratch array and every call
+ * leaves its own contents there: scans that overlap in time on one device
+ * (monitors on different streams) race and must be ordered by the caller.
+ * Errors: SRLA_E_INVAL, SRLA_E_STATE (poisoned), SRLA_E_DEVICE.
+ */
+int srla_scan_noalloc(srla_monitor_t *m, const uint32_t *pairs, uint64_t n);
+
+/*
  * Closes the open slice e and fills *out with its report (Section 4.2 and
  * Algorithm 3): the candidate check of every source sampled in e against the
  * union SRE and union SI, the union-LE estimate (Eq8-Eq9) of every candidate,

@@ -10,6 +10,6 @@ from .srla import (Monitor, Report, SrlaError, Group, srla_group_create, srla_gr
                    srla_group_destroy, srla_group_last_error, srla_admit, make_config, srla_create, srla_destroy,  # noqa: F401
                    srla_close_slice, srla_wait_report,
                    srla_dump_state, srla_estimate, srla_footprint_bytes, srla_last_error,
-                   srla_scan, srla_timings, SRLA_DUMP_LE, SRLA_DUMP_RE, SRLA_DUMP_SI,
+                   srla_scan, srla_scan_noalloc, srla_timings, SRLA_DUMP_LE, SRLA_DUMP_RE, SRLA_DUMP_SI,
                    SRLA_FLAG_SUPER, SRLA_FLAG_SAT, SRLA_FLAG_NEW, SRLA_FLAG_KEEP, EXPORTS,
                    SRLA_OK, SRLA_E_INVAL, SRLA_E_CAPACITY, SRLA_E_STATE)

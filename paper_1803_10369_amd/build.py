@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsrla.so")
 SOURCES = ["srla_runtime.hip", "srla_scan.hip", "srla_kernels.hip", "srla_sort.hip",
            "srla_discrete.hip", "srla_scan_dedup.hip", "srla_scan_filter.hip",
-           "srla_scan_part.hip"]
+           "srla_scan_part.hip", "srla_noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -32,6 +32,7 @@
 
 #include "../../include/srla.h"
 #include "srla_discrete.h"
+#include "srla_noalloc.h"
 #include "srla_scan_dedup.h"
 #include "srla_scan_filter.h"
 #include "srla_scan_part.h"
@@ -747,6 +748,12 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     if (hipDeviceGetAttribute(&m->clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
       m->clock_khz = 0;
     (void)hipGetLastError();
+    // the allocation-free scan's scratch address on this device, looked up once
+    if (noalloc_setup(dev) != hipSuccess) {
+      (void)hipGetLastError();
+      release(m);
+      return SRLA_E_DEVICE;
+    }
   }
   m->n_le = (uint64_t)g.u * g.v_le * g.g_le;
   m->n_re = (uint64_t)g.u * g.v_re * g.g;
@@ -1044,6 +1051,32 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   // the caller may reuse its buffer once this returns: wait for the copies
   // that read it directly
   if (pinned && last >= 0) HIP_TRY(m, hipEventSynchronize(m->stage_ev[last]));
+  return SRLA_OK;
+}
+
+int srla_scan_noalloc(srla_monitor_t* m, const uint32_t* pairs, uint64_t n) {
+  if (!m) return SRLA_E_INVAL;
+  if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
+  if (n == 0) return SRLA_OK;
+  if (!pairs) return fail(m, SRLA_E_INVAL, "pairs is NULL");
+  if (m->discrete || m->overlap_report)
+    return fail(m, SRLA_E_INVAL,
+                "srla_scan_noalloc: not for discrete or overlapped-report monitors");
+  if (!part_scan_fits(m->n_le))
+    return fail(m, SRLA_E_INVAL, "srla_scan_noalloc: the LE has more than 2^25 DRs");
+  const int p = (int)(m->slice & 1);
+  if (m->slice_pairs[p] + n > m->touched_cap)
+    return fail(m, SRLA_E_INVAL,
+                "srla_scan_noalloc: the slice's pairs exceed the sampled-source capacity");
+  uint8_t* base = static_cast<uint8_t*>(noalloc_scratch(m->device));
+  if (!base) return fail(m, SRLA_E_DEVICE, "srla_scan_noalloc: no scratch on this device");
+  uint16_t* entries = reinterpret_cast<uint16_t*>(base);
+  uint32_t* marks = reinterpret_cast<uint32_t*>(base + kNoAllocEntryBytes);
+  uint16_t* offs = reinterpret_cast<uint16_t*>(base + kNoAllocEntryBytes + kNoAllocMarkBytes);
+  HIP_TRY(m, launch_scan_partition(pairs, n, m->geo, stamp_code(m->slice), m->le, m->re,
+                                   m->touched[p], m->tcount + p, entries, offs, marks,
+                                   m->stream, kNoAllocChunks, kNoAllocSplit));
+  m->slice_pairs[p] += n;
   return SRLA_OK;
 }
 

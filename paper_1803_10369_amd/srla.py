@@ -62,7 +62,7 @@ class srla_timings_t(ctypes.Structure):
                 ("estimates", ctypes.c_uint64)]
 
 
-EXPORTS = ["srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
+EXPORTS = ["srla_footprint_bytes", "srla_create", "srla_scan", "srla_scan_noalloc", "srla_estimate",
            "srla_close_slice", "srla_wait_report", "srla_dump_state", "srla_timings",
            "srla_set_timing", "srla_destroy", "srla_last_error", "srla_group_create", "srla_group_scan",
            "srla_group_destroy", "srla_group_last_error", "srla_admit"]
@@ -83,6 +83,8 @@ def lib():
         L.srla_create.argtypes = [ctypes.POINTER(srla_config_t), vp, ctypes.POINTER(vp)]
         L.srla_scan.restype = ctypes.c_int
         L.srla_scan.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_int]
+        L.srla_scan_noalloc.restype = ctypes.c_int
+        L.srla_scan_noalloc.argtypes = [vp, vp, ctypes.c_uint64]
         L.srla_estimate.restype = ctypes.c_int
         L.srla_estimate.argtypes = [vp, ctypes.POINTER(srla_report_t)]
         L.srla_close_slice.restype = ctypes.c_int
@@ -136,6 +138,10 @@ def srla_create(cfg, hip_stream=None):
 
 def srla_scan(handle, pairs_ptr, n, on_device):
     return lib().srla_scan(handle, pairs_ptr, n, int(on_device))
+
+
+def srla_scan_noalloc(handle, pairs_ptr, n):
+    return lib().srla_scan_noalloc(handle, pairs_ptr, n)
 
 
 def srla_estimate(handle, report):

@@ -25,7 +25,8 @@ def P():
 
 def test_every_declared_symbol_is_exported(P):
     names = _declared_functions()
-    assert set(names) == {"srla_footprint_bytes", "srla_create", "srla_scan", "srla_estimate",
+    assert set(names) == {"srla_footprint_bytes", "srla_create", "srla_scan", "srla_scan_noalloc",
+                          "srla_estimate",
                           "srla_close_slice", "srla_wait_report", "srla_dump_state",
                           "srla_timings", "srla_set_timing", "srla_destroy", "srla_last_error",
                           "srla_group_create", "srla_group_scan", "srla_group_destroy",
