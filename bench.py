@@ -459,6 +459,8 @@ def main():
                     help="pick the scan kernel's form and workgroup cap by timing them first")
     ap.add_argument("--scan-blocks", type=int, default=0,
                     help="cap on the scan kernel's workgroups (0: one per tile)")
+    ap.add_argument("--block", type=int, default=20,
+                    help="slices per turn when the streaming and the plain form take turns")
     ap.add_argument("--segment", type=int, default=200,
                     help="timed slices whose inputs are generated into HBM at a time")
     ap.add_argument("--steps", type=int, default=60)
@@ -496,6 +498,9 @@ def main():
     ap.add_argument("--scan-partition", action="store_true",
                     help="scan in partitioned form: LE stores sorted by region in LDS, "
                          "then stamped a region per workgroup (A/B of the scan kernels)")
+    ap.add_argument("--hold-scans", type=int, default=-1,
+                    help="the next slice's scans wait until the closed slice's report is in "
+                         "host memory (default: on in the streaming form)")
     ap.add_argument("--scan-lds-filter", action="store_true",
                     help="scan with a workgroup filter of repeated DR stores (A/B)")
     ap.add_argument("--scan-dedup", action="store_true",
@@ -555,11 +560,15 @@ def main():
     # the cache to the candidate work, which then runs beside the scans whole
     overlap = ((args.mode == "streaming" and not args.scan_partition)
                if args.overlap_report < 0 else bool(args.overlap_report))
+    # the streaming form holds each slice's scans until the previous slice's
+    # report is in host memory (its end-of-slice work then runs alone)
+    hold = (args.mode == "streaming" and not overlap) if args.hold_scans < 0 \
+        else bool(args.hold_scans)
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks,
                      lean_report=not args.full_report, scan_dedup=args.scan_dedup,
                      scan_lds_filter=args.scan_lds_filter, overlap_report=overlap,
-                     scan_partition=args.scan_partition)
+                     scan_partition=args.scan_partition, hold_scans=hold)
 
     # the window is filled first: slices 0 .. k-2 build the state, so that
     # every warm-up and timed slice closes a full window (Section 5.2 reports
@@ -628,32 +637,51 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t0, lat, host_lat, cands, full, r
 
-    def run_timed(mode, first, steps):
-        total, lat, host_lat, cands, full, r = 0.0, [], [], [], [], None
-        done = 0
-        while done < steps:
-            seg = min(args.segment, steps - done)
-            dt, l, hl, c, f, r = segment(mode, first + done, seg)
-            total += dt
-            lat += l
-            host_lat += hl
-            cands += c
-            full += f
-            done += seg
-            print("%s: timed %d/%d slices (%.2fs)" % (mode, done, steps, total), file=sys.stderr,
-                  flush=True)
-        return total, np.array(lat), np.array(host_lat), cands, full, r
+    class Timed:
+        """What one form's timed slices add up to."""
+
+        def __init__(self):
+            self.total, self.lat, self.host_lat, self.cands, self.full = 0.0, [], [], [], []
+            self.r, self.tm, self.done, self.slices = None, {}, 0, []
+
+        def add(self, dt, l, hl, c, f, r, tm, first, n):
+            self.total += dt
+            self.lat += l
+            self.host_lat += hl
+            self.cands += c
+            self.full += f
+            self.r = r
+            for k, v in tm.items():
+                self.tm[k] = self.tm.get(k, 0) + v
+            self.done += n
+            self.slices.append([first, first + n - 1])
 
     first = prefill
     if args.warmup:
         segment(args.mode, first, args.warmup)
         print("warm-up: %d slices" % args.warmup, file=sys.stderr, flush=True)
         first += args.warmup
+    # the streaming form and the plain form take turns in blocks of slices,
+    # so that both meet the same candidate-list sizes (it grows slowly)
+    compare = args.mode == "streaming" and args.compare_steps > 0
+    runs = {args.mode: Timed(), "plain": Timed()}
+    turns = [(args.mode, args.steps)] + ([("plain", args.compare_steps)] if compare else [])
     m.timings(reset=True)
-    total_s, lat, host_lat, cands, full, r = run_timed(args.mode, first, args.steps)
-    tm = m.timings(reset=True)
-    timed_slices = [first, first + args.steps - 1]
-    first += args.steps
+    while any(runs[mode].done < steps for mode, steps in turns):
+        for mode, steps in turns:
+            t = runs[mode]
+            if t.done >= steps:
+                continue
+            n = min(args.block, args.segment, steps - t.done)
+            dt, l, hl, c, f, r = segment(mode, first, n)
+            t.add(dt, l, hl, c, f, r, m.timings(reset=True), first, n)
+            first += n
+            print("%s: timed %d/%d slices (%.2fs)" % (mode, t.done, steps, t.total),
+                  file=sys.stderr, flush=True)
+    main_run = runs[args.mode]
+    total_s, lat, host_lat = main_run.total, np.array(main_run.lat), np.array(main_run.host_lat)
+    cands, full, r, tm = main_run.cands, main_run.full, main_run.r, main_run.tm
+    timed_slices = main_run.slices
 
     pairs = args.steps * n_pairs
     value = pairs / total_s
@@ -700,16 +728,15 @@ def main():
             "window": g["k"], "theta": g["theta"], "pairs_per_slice": n_pairs,
             "prefill_slices": prefill,
             "slices_timed": timed_slices,
+            "block": args.block,
             "mode": args.mode, "graph": graph, "scan_blocks": args.scan_blocks,
             "scan_xcd": args.scan_xcd, "scan_dedup": args.scan_dedup,
             "scan_lds_filter": args.scan_lds_filter, "overlap_report": overlap,
-            "scan_partition": args.scan_partition,
-            "autotune": tuned,
+            "scan_partition": args.scan_partition, "hold_scans": hold, "autotune": tuned,
             "report": ("full: ip, est, flags, |ULE|^k, |URE|^k (18 B/candidate)"
                        if args.full_report else "ip, est, flags (13 B/candidate)"),
         },
-        "latency_clock": "device (start of the slice's end-of-slice work to its report in "
-                         "host memory)",
+        "latency_clock": "device (end of the slice's last scan to its report in host memory)",
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "stage_ms_per_slice": stages,
@@ -760,6 +787,7 @@ def main():
     out["roofline"]["random_store_ceiling_per_s"] = ceiling
     out["roofline"]["frac_of_random_store_ceiling"] = stores_per_s / ceiling
     if args.scan_partition:
+        # the partitioned scan's pairs and DR-index blocks besides the DR arrays
         ws = footprint + 16 * n_pairs
         copy_rate = probe.stream_copy_rate(ws // 2)
         out["roofline"]["stream_copy_ceiling_GBps"] = copy_rate / 1e9
@@ -772,12 +800,13 @@ def main():
         out["random_store_rates_per_s"] = {
             mib: probe.random_store_rate(int(mib) << 20) for mib in args.probe_mib.split(",")}
 
-    if args.mode == "streaming" and args.compare_steps > 0:
-        # the plain form on the same monitor, right after: each slice scanned,
-        # then closed and its report collected before the next slice's scan
-        m.timings(reset=True)
-        p_total, p_lat, p_host, p_cands, p_full, _ = run_timed("plain", first, args.compare_steps)
-        ptm = m.timings(reset=True)
+    if compare:
+        # the plain form on the same monitor, in the blocks between the
+        # streaming ones: each slice scanned, then closed and its report
+        # collected before the next slice's scan
+        pr = runs["plain"]
+        p_total, p_lat, p_host = pr.total, np.array(pr.lat), np.array(pr.host_lat)
+        p_cands, p_full, ptm = pr.cands, pr.full, pr.tm
         p_scan = ptm["scan_ms"] / max(1, ptm["scan_launches"])
         out["plain"] = {
             "value": args.compare_steps * n_pairs / p_total,
@@ -785,7 +814,7 @@ def main():
             "p50_ms": float(np.percentile(p_lat, 50)),
             "p99_ms": float(np.percentile(p_lat, 99)),
             "p99_host_ms": float(np.percentile(p_host, 99)),
-            "slices_timed": [first, first + args.compare_steps - 1],
+            "slices_timed": pr.slices,
             "window_full": bool(all(p_full)), "candidates": [min(p_cands), max(p_cands)],
             "scan_launch_ms": p_scan}
         out["plain_p99_ms"] = out["plain"]["p99_ms"]

@@ -112,7 +112,20 @@ enum {
                                   precedence; no effect in the discrete
                                   form.  A group whose members all have it
                                   runs each member's partitioned scan over
-                                  the pairs instead of the fused kernel */
+                                  the pairs instead of the fused kernel */,
+    SRLA_CFG_HOLD_SCANS = 1024 /* for the streaming form: scans issued after
+                                  srla_close_slice of slice e start on the
+                                  device only once e's report is in host
+                                  memory, so e's end-of-slice work runs
+                                  without a scan beside it (the scans
+                                  overlap only Algorithm 3's carried list
+                                  and SI update, which the report does not
+                                  wait for).  The host can still close e
+                                  and issue e+1's scans at once, so no host
+                                  round trip separates a slice's scans from
+                                  its end-of-slice work.  Results are
+                                  identical; no effect with
+                                  SRLA_CFG_OVERLAP_REPORT */
 };
 
 /*
@@ -170,9 +183,9 @@ typedef struct srla_monitor srla_monitor_t;
  *   up            Eq8
  *   n_touched     distinct sources with at least one SRE-sampled pair in e
  *   n_new         candidates inserted in e
- *   latency_ms    device time from the start of e's end-of-slice work (on
- *                 the monitor's stream, right after e's last scan) until the
- *                 report was complete in host memory (device wall clock)
+ *   latency_ms    device time from the end of e's last scan (for a slice
+ *                 without scans: the start of its end-of-slice work) until
+ *                 the report was complete in host memory (device wall clock)
  */
 typedef struct {
     uint64_t slice;

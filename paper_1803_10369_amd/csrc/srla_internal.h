@@ -85,8 +85,12 @@ struct PipeState {
   uint32_t now;          // stamp code of the slice whose candidate work is next
   uint32_t n_ncsip;      // |NCSIP| carried into it
   uint64_t slice;        // its index
-  uint64_t t_close[2];   // device wall clock when the end-of-slice work of the
-                         // last closed slice of each parity began
+  uint64_t t_close[2];   // device wall clock when the last closed slice of each
+                         // parity ended: its last scan finished (or, for a slice
+                         // without scans, its end-of-slice work began)
+  uint64_t t_scan[2];    // device wall clock at the end of the last scan of the
+                         // open slice of each parity
+  uint32_t scanned[2];   // that slice has had a scan
   uint32_t snap;         // stamp code of the slice snapshotted last (0: none yet);
                          // the snapshot keeps its own count so that it need not
                          // wait for the previous slice's candidate work
@@ -99,7 +103,7 @@ struct HostStatus {
   double up;
   unsigned long long row_fill[kMaxU];
   uint64_t slice;
-  uint64_t t_close;      // device wall clock: end-of-slice work began
+  uint64_t t_close;      // device wall clock: the slice's last scan ended
   uint64_t t_done;       //   and the report was complete in host memory
 };
 
@@ -210,8 +214,12 @@ hipError_t launch_mark_scan(uint32_t* started, uint32_t value, hipStream_t st);
 hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const Counters* cnt,
                             uint32_t* si_cnt, const Geo& geo, hipStream_t st);
 
-// records the device wall clock at the start of the end-of-slice work of a
-// slice of parity p, advances the snapshot's stamp code and clears the row fills
+// records the device wall clock at the end of a scan of the open slice of
+// parity p
+hipError_t launch_scan_end(PipeState* ps, uint32_t p, hipStream_t st);
+// takes the end of the last scan of the closing slice of parity p (or, without
+// scans, the device wall clock now) as the slice's end, advances the
+// snapshot's stamp code and clears the row fills
 hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t u,
                               uint32_t p, hipStream_t st);
 // records the device wall clock once the report is complete in host memory

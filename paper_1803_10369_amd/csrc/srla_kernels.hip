@@ -432,6 +432,12 @@ hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
 // report leaves them out).
 
 constexpr uint32_t kEstPerBlock = kBlock;
+// workgroups that work when no LE row needs gathering (every row full): four
+// per CU keep the report's PCIe writes near their ceiling (measured on the
+// backbone workload, 2M candidates: 0.53 ms with 1024 workgroups, 0.56 ms
+// with 512, 0.61 ms with 256) and leave room on every CU for a scan running
+// beside the estimate
+constexpr uint32_t kEstBlocksNoGather = 1024;
 
 // a workgroup barrier that orders LDS accesses only (global stores issued
 // before it may still be in flight)
@@ -454,6 +460,8 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
     uint8_t* __restrict__ out_W) {
   __shared__ uint32_t s_ip[kEstPerBlock], s_U[kEstPerBlock];
   __shared__ uint8_t s_W[kEstPerBlock], s_Wn[kEstPerBlock];
+  __shared__ __align__(16) double s_e[kEstPerBlock];
+  __shared__ __align__(16) uint8_t s_f[kEstPerBlock];
   const uint32_t lg = 1u << lg_log2;
   const uint32_t per_round = kBlock >> lg_log2;          // candidates per round
   const uint32_t sub = threadIdx.x & (lg - 1u);
@@ -466,8 +474,14 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
 #pragma unroll
   for (int r = 0; r < kU; ++r)
     if (r < (int)geo.u && row_fill[r] != row_cells) gather |= 1u << r;
+  // with nothing to gather from the LE the kernel is bound by its report
+  // stores into host memory, which a few workgroups saturate: the rest exit
+  // at once and leave their CUs to a scan running beside it
+  const uint32_t active =
+      gather == 0u && gridDim.x > kEstBlocksNoGather ? kEstBlocksNoGather : gridDim.x;
+  if (blockIdx.x >= active) return;
   for (uint64_t base = (uint64_t)blockIdx.x * kEstPerBlock; base < n;
-       base += (uint64_t)gridDim.x * kEstPerBlock) {
+       base += (uint64_t)active * kEstPerBlock) {
     const uint32_t in_batch =
         (uint32_t)(n - base < (uint64_t)kEstPerBlock ? n - base : (uint64_t)kEstPerBlock);
     if (threadIdx.x < in_batch) s_ip[threadIdx.x] = csip[base + threadIdx.x];
@@ -563,11 +577,29 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
       if (e >= (double)geo.theta) fl |= 1u;
       if (s_Wn[threadIdx.x] >= geo.t_re) fl |= 8u;   // carried by Algorithm 3
       cflags[gid] = fl;
-      out_ip[gid] = s_ip[threadIdx.x];
-      out_est[gid] = e;
-      out_flags[gid] = fl;
+      s_e[threadIdx.x] = e;
+      s_f[threadIdx.x] = fl;
       if (out_U) out_U[gid] = ucount;
       if (out_W) out_W[gid] = s_W[threadIdx.x];
+    }
+    lds_barrier();
+    // the batch's report entries leave in 16-byte pieces (ip: 64 lanes, est:
+    // 128 lanes, flags: 16 lanes), so the writes into host memory go out in
+    // whole lines; a partial batch at the end of the list is written entry
+    // by entry
+    if (in_batch == kEstPerBlock) {
+      const uint32_t t = threadIdx.x;
+      if (t < kEstPerBlock / 4)
+        reinterpret_cast<uint4*>(out_ip + base)[t] = reinterpret_cast<const uint4*>(s_ip)[t];
+      if (t < kEstPerBlock / 2)
+        reinterpret_cast<uint4*>(out_est + base)[t] = reinterpret_cast<const uint4*>(s_e)[t];
+      if (t < kEstPerBlock / 16)
+        reinterpret_cast<uint4*>(out_flags + base)[t] = reinterpret_cast<const uint4*>(s_f)[t];
+    } else if (threadIdx.x < in_batch) {
+      const uint64_t gid = base + threadIdx.x;
+      out_ip[gid] = s_ip[threadIdx.x];
+      out_est[gid] = s_e[threadIdx.x];
+      out_flags[gid] = s_f[threadIdx.x];
     }
     lds_barrier();
   }
@@ -607,8 +639,8 @@ static hipError_t launch_estimate_u(const uint32_t* csip, const Counters* cnt,
                                     hipStream_t st) {
   static const uint32_t grid = est_grid<kU, kWpl>();
   hipLaunchKernelGGL((k_estimate<kU, kWpl>), dim3(grid), dim3(kBlock), 0, st, csip, cnt, bitmap,
-                     act, up, row_fill, geo, l, cflags, out.ip, out.est, out.flags, out.U,
-                     out.W);
+                     act, up, row_fill, geo, l, cflags, out.ip, out.est, out.flags,
+                     out.U, out.W);
   return hipGetLastError();
 }
 
@@ -780,7 +812,8 @@ __global__ void k_begin_close(PipeState* __restrict__ ps, unsigned long long* __
                               uint32_t u, uint32_t p) {
   if (blockIdx.x != 0) return;
   if (threadIdx.x == 0) {
-    ps->t_close[p] = wall_clock64();
+    ps->t_close[p] = ps->scanned[p] ? ps->t_scan[p] : wall_clock64();
+    ps->scanned[p] = 0u;
     ps->snap = ps->snap % kStampPeriod + 1u;
   }
   for (uint32_t i = threadIdx.x; i < u; i += blockDim.x) row_fill[i] = 0ull;
@@ -789,6 +822,18 @@ __global__ void k_begin_close(PipeState* __restrict__ ps, unsigned long long* __
 hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t u,
                               uint32_t p, hipStream_t st) {
   hipLaunchKernelGGL(k_begin_close, dim3(1), dim3(64), 0, st, ps, row_fill, u, p);
+  return hipGetLastError();
+}
+
+__global__ void k_scan_end(PipeState* __restrict__ ps, uint32_t p) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ps->t_scan[p] = wall_clock64();   // every earlier kernel of the stream has finished
+    ps->scanned[p] = 1u;
+  }
+}
+
+hipError_t launch_scan_end(PipeState* ps, uint32_t p, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_end, dim3(1), dim3(64), 0, st, ps, p);
   return hipGetLastError();
 }
 

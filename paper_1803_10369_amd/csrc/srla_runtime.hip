@@ -81,7 +81,8 @@ bool config_ok(const srla_config_t* c) {
   if ((c->flags & ~(uint32_t)(SRLA_CFG_TIMING | SRLA_CFG_SCAN_XCD | SRLA_CFG_GRAPH |
                               SRLA_CFG_DISCRETE | SRLA_CFG_LEAN_REPORT |
                               SRLA_CFG_SCAN_DEDUP | SRLA_CFG_SCAN_LDS_FILTER |
-                              SRLA_CFG_OVERLAP_REPORT | SRLA_CFG_SCAN_PARTITION)) != 0)
+                              SRLA_CFG_OVERLAP_REPORT | SRLA_CFG_SCAN_PARTITION |
+                              SRLA_CFG_HOLD_SCANS)) != 0)
     return false;
   if ((c->flags & SRLA_CFG_DISCRETE) && c->window_slices != 1) return false;
   const uint64_t le = (uint64_t)g.u * g.v_le * g.g_le;
@@ -224,6 +225,7 @@ struct srla_monitor {
   bool dedup_scan = false;
   bool filter_scan = false;
   bool part_scan = false;
+  bool hold_scans = false;       // scans wait for the closed slice's report
   std::vector<TimedSpan> spans;
   std::vector<hipEvent_t> ev_pool;
   double acc_ms[ST_N] = {0, 0, 0, 0, 0, 0};
@@ -489,35 +491,47 @@ hipError_t enqueue_slide(srla_monitor* m, int p, hipStream_t st) {
   return e;
 }
 
-// The candidate work of the closing slice: candidate check of its sampled
-// sources (sorted first unless `sorted`), merge with the carried list and
-// Eq9 for every candidate (report entries to `out`); with `slide`, also
-// Algorithm 3's carried list and SI counters.
-hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hipStream_t st,
-                              bool sorted, bool slide) {
+// The candidate check of the closing slice's (sorted) sampled sources and
+// the merge of the new candidates with the carried list into CSIP.
+hipError_t enqueue_check(srla_monitor* m, int p, hipStream_t st) {
   const Geo& geo = m->geo;
   hipError_t e = hipSuccess;
   uint32_t* tc = m->tcount + p;
+  const uint64_t* re_act = m->discrete ? m->rebits[p] : m->act[p];
+  hipEvent_t ta = nullptr;
+  const bool spans = !m->use_graph;
+  if (spans) span_begin(m, st, &ta);
+  e = launch_finalize(m->touched[p], tc, re_act, m->si_cnt, geo, m->mark, m->cnt, st);
+  if (e == hipSuccess)
+    e = compact_u32(m->mark, 1u, m->touched[p], tc, m->touched_cap, m->news, &m->cnt->n_new,
+                    m->blockw, st);
+  if (e == hipSuccess)
+    e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
+  if (spans) span_end(m, st, ST_FINALIZE, ta);
+  return e;
+}
+
+// Eq9 for every candidate of CSIP, report entries to `out`.
+hipError_t enqueue_estimate(srla_monitor* m, int p, const ReportPtrs& out, hipStream_t st) {
   const uint64_t* le_act = m->discrete ? m->lebits[p] : m->bitmap[p];
   const uint64_t* re_act = m->discrete ? m->rebits[p] : m->act[p];
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
-  if (!sorted) e = enqueue_sort(m, p, st);
   if (spans) span_begin(m, st, &ta);
-  if (e == hipSuccess)
-    e = launch_finalize(m->touched[p], tc, re_act, m->si_cnt, geo, m->mark, m->cnt, st);
-  if (e == hipSuccess)
-    e = compact_u32(m->mark, 1u, m->touched[p], tc, m->touched_cap, m->news, &m->cnt->n_new,
-                    m->blockw, st);
-  if (spans) span_end(m, st, ST_FINALIZE, ta);
-  if (spans) span_begin(m, st, &ta);
-  if (e == hipSuccess)
-    e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
-  if (e == hipSuccess)
-    e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->up[p], m->row_fill[p], geo,
-                        m->cflags, out, st);
+  const hipError_t e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->up[p],
+                                       m->row_fill[p], m->geo, m->cflags, out, st);
   if (spans) span_end(m, st, ST_ESTIMATE, ta);
-  if (e == hipSuccess && slide) e = enqueue_slide(m, p, st);
+  return e;
+}
+
+// The whole candidate work of the closing slice (the overlapped-report form
+// runs it in one phase): sort, check and merge, Eq9 into `out`, then
+// Algorithm 3's carried list and SI counters.
+hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hipStream_t st) {
+  hipError_t e = enqueue_sort(m, p, st);
+  if (e == hipSuccess) e = enqueue_check(m, p, st);
+  if (e == hipSuccess) e = enqueue_estimate(m, p, out, st);
+  if (e == hipSuccess) e = enqueue_slide(m, p, st);
   return e;
 }
 
@@ -544,7 +558,7 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
   if (phase == PH_SNAPSHOT) {
     e = enqueue_snapshot(m, p, st);
     if (e == hipSuccess && m->overlap_report) {
-      e = enqueue_candidates(m, p, m->d_staging[p], st, false, true);
+      e = enqueue_candidates(m, p, m->d_staging[p], st);
       if (spans) span_begin(m, st, &ta);
       if (e == hipSuccess)
         e = launch_status(m->cnt, m->tcount + p, m->up[p], m->row_fill[p], m->geo.u, m->ps,
@@ -554,7 +568,10 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
     }
     return e;
   }
-  if (!m->overlap_report) e = enqueue_candidates(m, p, m->d_report[p], st, true, false);
+  if (!m->overlap_report) {
+    e = enqueue_check(m, p, st);
+    if (e == hipSuccess) e = enqueue_estimate(m, p, m->d_report[p], st);
+  }
   if (spans) span_begin(m, st, &ta);
   if (m->overlap_report) {
     // PH_FINISH_GO: the next slice (parity p ^ 1) has its first scan behind a mark
@@ -695,6 +712,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   m->filter_scan = (cfg->flags & SRLA_CFG_SCAN_LDS_FILTER) != 0;
   m->part_scan = (cfg->flags & SRLA_CFG_SCAN_PARTITION) != 0 && !m->discrete;
   m->overlap_report = (cfg->flags & SRLA_CFG_OVERLAP_REPORT) != 0;
+  m->hold_scans = (cfg->flags & SRLA_CFG_HOLD_SCANS) != 0 && !m->overlap_report;
 
   const srla_geometry_t& g = cfg->geom;
   Geo& geo = m->geo;
@@ -984,6 +1002,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     span_begin(m, m->stream, &a);
     HIP_TRY(m, enqueue_scan(m, pairs, n, p, mark));
     span_end(m, m->stream, ST_SCAN, a);
+    HIP_TRY(m, launch_scan_end(m->ps, (uint32_t)p, m->stream));
     m->slice_pairs[p] += n;
     if (m->timing) {
       m->scan_launches++;
@@ -1034,6 +1053,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     span_begin(m, m->stream, &a);
     HIP_TRY(m, enqueue_scan(m, m->d_stage[b], cnt, p, go ? mark : 0u));
     span_end(m, m->stream, ST_SCAN, a);
+    HIP_TRY(m, launch_scan_end(m->ps, (uint32_t)p, m->stream));
     if (go) {
       rc = enqueue_finish(m, true);
       if (rc) return rc;
@@ -1076,6 +1096,7 @@ int srla_scan_noalloc(srla_monitor_t* m, const uint32_t* pairs, uint64_t n) {
   HIP_TRY(m, launch_scan_partition(pairs, n, m->geo, stamp_code(m->slice), m->le, m->re,
                                    m->touched[p], m->tcount + p, entries, offs, marks,
                                    m->stream, kNoAllocChunks, kNoAllocSplit));
+  HIP_TRY(m, launch_scan_end(m->ps, (uint32_t)p, m->stream));
   m->slice_pairs[p] += n;
   return SRLA_OK;
 }
@@ -1124,7 +1145,13 @@ int srla_close_slice(srla_monitor_t* m) {
     m->finish_deferred = true;
     return SRLA_OK;
   }
-  return enqueue_finish(m, false);
+  rc = enqueue_finish(m, false);
+  if (rc) return rc;
+  // the next slice's scans start once this slice's report is in host memory:
+  // its end-of-slice work then has the GPU to itself (the scans overlap only
+  // Algorithm 3's carried list and SI update)
+  if (m->hold_scans) HIP_TRY(m, hipStreamWaitEvent(m->stream, m->ev_pub[p], 0));
+  return SRLA_OK;
 }
 
 int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
@@ -1350,6 +1377,8 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
       if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
     }
     for (srla_monitor* m : g->mons) {
+      const hipError_t e = launch_scan_end(m->ps, (uint32_t)(m->slice & 1), g->stream);
+      if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
       m->slice_pairs[m->slice & 1] += n;
       m->scan_launches++;
       m->scan_pairs += n;
@@ -1372,6 +1401,8 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
                                          g->scan_blocks, g->stream);
   if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
   for (srla_monitor* m : g->mons) {
+    const hipError_t e2 = launch_scan_end(m->ps, (uint32_t)(m->slice & 1), g->stream);
+    if (e2 != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e2));
     m->slice_pairs[m->slice & 1] += n;
     m->scan_launches++;
     m->scan_pairs += n;

@@ -27,6 +27,7 @@ SRLA_CFG_SCAN_DEDUP = 32
 SRLA_CFG_SCAN_LDS_FILTER = 64
 SRLA_CFG_OVERLAP_REPORT = 128
 SRLA_CFG_SCAN_PARTITION = 256
+SRLA_CFG_HOLD_SCANS = 1024
 
 
 class srla_geometry_t(ctypes.Structure):
@@ -256,14 +257,15 @@ class Monitor:
     def __init__(self, k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates=1 << 22,
                  timing=False, stream=None, scan_xcd=False, graph=False, scan_blocks=0,
                  discrete=False, lean_report=False, scan_dedup=False, scan_lds_filter=False,
-                 overlap_report=False, scan_partition=False):
+                 overlap_report=False, scan_partition=False, hold_scans=False):
         flags = ((SRLA_CFG_TIMING if timing else 0) | (SRLA_CFG_SCAN_XCD if scan_xcd else 0) |
                  (SRLA_CFG_GRAPH if graph else 0) | (SRLA_CFG_DISCRETE if discrete else 0) |
                  (SRLA_CFG_LEAN_REPORT if lean_report else 0) |
                  (SRLA_CFG_SCAN_DEDUP if scan_dedup else 0) |
                  (SRLA_CFG_SCAN_LDS_FILTER if scan_lds_filter else 0) |
                  (SRLA_CFG_OVERLAP_REPORT if overlap_report else 0) |
-                 (SRLA_CFG_SCAN_PARTITION if scan_partition else 0))
+                 (SRLA_CFG_SCAN_PARTITION if scan_partition else 0) |
+                 (SRLA_CFG_HOLD_SCANS if hold_scans else 0))
         self.cfg = make_config(k, theta, u, v_re, g, v_le, G, hash_seed, max_candidates, flags,
                                scan_blocks)
         self._h = None

@@ -87,7 +87,7 @@ def test_invalid_configs_are_rejected_without_a_device(P, bad):
 def test_bad_flags_and_capacity_rejected(P):
     cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, max_candidates=0)
     assert P.srla_create(cfg)[0] == -1
-    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=512)
+    cfg = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=4096)
     assert P.srla_create(cfg)[0] == -1
     lean = P.make_config(8, 1024, 4, 2048, 8, 16, 1024, 1, flags=P.srla.SRLA_CFG_LEAN_REPORT)
     assert P.srla_footprint_bytes(lean) > 0

@@ -122,14 +122,14 @@ def test_small_geometries(case, scan_xcd, graph):
 
 def _run_streaming(stream, mon, slices, max_candidates=1 << 16, graph=False, chunks=1,
                    discrete=False, scan_dedup=False, overlap_report=False, ahead=False,
-                   scan_partition=False):
+                   scan_partition=False, hold_scans=False):
     """The next slice is scanned before the previous slice's report is taken;
     ahead: it is also closed before that report is taken (two reports pending),
     and a collected report's arrays (views, no copy) must hold until the slice
     two after it is closed."""
     g = srla.Monitor(**mon, max_candidates=max_candidates, graph=graph, discrete=discrete,
                      scan_dedup=scan_dedup, overlap_report=overlap_report,
-                     scan_partition=scan_partition)
+                     scan_partition=scan_partition, hold_scans=hold_scans)
     o = oracle.Monitor(**mon)
     expected = []
     slices = list(slices)
@@ -783,3 +783,42 @@ def test_partition_monitors_in_a_group_mix_group_and_own_scans(all_partitioned):
     grp.close()
     for gm in gms:
         gm.close()
+
+
+# ------------------------------------------------------------ held scans
+# SRLA_CFG_HOLD_SCANS: the next slice's scans wait until the closed slice's
+# report is published; results are unchanged.
+
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("ahead", [False, True])
+def test_hold_scans_streaming_matches_oracle(graph, ahead):
+    stream, mon, n = workload("tiny")
+    _run_streaming(stream, mon, range(n), graph=graph, chunks=2, ahead=ahead, hold_scans=True)
+    _run_streaming(stream, mon, range(n), graph=graph, ahead=ahead, hold_scans=True,
+                   scan_partition=True)
+
+
+@pytest.mark.parametrize("case", [SMALL[0], SMALL[3], SMALL[6]])
+def test_hold_scans_small_geometries_and_discrete(case):
+    k, theta, u, v_re, g, v_le, G, n, n_src, slices = case
+    mon = dict(k=k, theta=theta, u=u, v_re=v_re, g=g, v_le=v_le, G=G, hash_seed=5100 + k + u)
+    _run_streaming(_rand_stream(k + u + 71, n, n_src, 3 * theta // 2), mon, range(slices),
+                   graph=True, ahead=True, hold_scans=True)
+    _run_streaming(_rand_stream(k + u + 72, n, n_src, 3 * theta // 2), dict(mon, k=1),
+                   range(slices), graph=True, discrete=True, ahead=True, hold_scans=True)
+
+
+def test_hold_scans_plain_and_backbone_full_size():
+    stream, mon, n = workload("tiny")
+    g = srla.Monitor(**mon, max_candidates=1 << 16, hold_scans=True, graph=True)
+    o = oracle.Monitor(**mon)
+    for s in range(n):
+        p = stream.slice(s)
+        g.scan(to_device(p))
+        o.scan(p)
+        compare_reports(g.estimate(), o.estimate(), mon["theta"], "plain %d" % s)
+    compare_dumps(g, o)
+    g.close()
+    stream, mon, _ = workload("backbone")
+    _run_streaming(stream, mon, range(3), max_candidates=1 << 22, graph=True, ahead=True,
+                   scan_partition=True, hold_scans=True)

@@ -53,7 +53,7 @@ def test_backbone_full_size_in_the_bench_configuration():
     st = torch.cuda.Stream()
     ds = DeviceStream(stream)
     g = srla.Monitor(**mon, max_candidates=1 << 25, timing=True, stream=st, graph=True,
-                     lean_report=True, scan_partition=True)
+                     lean_report=True, scan_partition=True, hold_scans=True)
     o = oracle.Monitor(**mon)
     ot = OracleThread()
     slices = 24
