@@ -779,6 +779,23 @@ def main():
         "ceiling_source": "measured: coalesced kernel stores into pinned host memory",
         "frac": rep_bytes / (est_ms * 1e-3) / pcie if est_ms > 0 else None}
 
+    # the snapshot's streaming sweeps: every LE and SRE DR read once, the
+    # activity bitmaps written (one bit per LE DR, two per SRE DR)
+    n_le = g["u"] * g["v_le"] * g["G"]
+    n_re = g["u"] * g["v_re"] * g["g"]
+    sweep_bytes = 2 * n_le + n_le / 8 + 2 * n_re + n_re / 4
+    sweep_ms = stages["sweep_ms"]
+    read_rate = probe.stream_read_rate(2 * (n_le + n_re))
+    out["roofline_sweep"] = {
+        "kernel": "k_sweep_le + k_sweep_re (the snapshot phase, k_begin_close included)",
+        "bound": level, "bytes_per_slice": sweep_bytes, "phase_ms": sweep_ms,
+        "achieved_GBps": sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None,
+        "ceiling_GBps": read_rate / 1e9,
+        "ceiling_source": "measured: streaming 16-byte reads over the DR arrays' footprint",
+        "frac": sweep_bytes / (sweep_ms * 1e-3) / read_rate if sweep_ms > 0 else None,
+        "frac_of_hbm_peak": sweep_bytes / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+        if sweep_ms > 0 else None}
+
     # ceilings at the scan's own footprint: random 2-byte stores (the flat
     # scan's pattern), and a streaming copy over the partitioned scan's working
     # set (its pairs, DR-index scratch and DR arrays)

@@ -9,6 +9,9 @@
 namespace srla {
 
 constexpr int kMaxU = 16;
+// partial sums per row of the LE sweep's row fills (blocks add to slot
+// block mod kFillSlots)
+constexpr uint32_t kFillSlots = 32;
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 
@@ -160,14 +163,17 @@ hipError_t launch_scan_group(const uint32_t* pairs, uint64_t n, const GroupMembe
                              uint32_t n_members, const GroupScanArgs& args, uint32_t max_blocks,
                              hipStream_t st);
 
-hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
+// |LDR(i)|^k by row into kFillSlots partial sums per row (fill_part, u x
+// kFillSlots, zero beforehand), the LE activity bitmap, the scrub
+hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* fill_part,
                            const Geo& geo, const PipeState* ps, hipStream_t st);
 
-// SRE DR activity bitmaps (inside the window now / after the slide) + scrub,
-// and Eq8 from the row fills (which the LE sweep has completed)
+// SRE DR activity bitmaps (inside the window now / after the slide) + scrub;
+// the row fills folded from the LE sweep's partial sums (when fill_part is
+// given; else row_fill is final already) and Eq8 from them
 hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act, const Geo& geo,
-                           const PipeState* ps, const unsigned long long* row_fill, double* up,
-                           hipStream_t st);
+                           const PipeState* ps, const unsigned long long* fill_part,
+                           unsigned long long* row_fill, double* up, hipStream_t st);
 
 // keys-only LSD radix sort of *n_dev uint32 keys (n_dev <= n_max), in place
 // (tmp is scratch).  block_hist needs radix_hist_words(n_max) words.
@@ -219,8 +225,8 @@ hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const C
 hipError_t launch_scan_end(PipeState* ps, uint32_t p, hipStream_t st);
 // takes the end of the last scan of the closing slice of parity p (or, without
 // scans, the device wall clock now) as the slice's end, advances the
-// snapshot's stamp code and clears the row fills
-hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t u,
+// snapshot's stamp code and clears n_clear words of the row-fill sums
+hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t n_clear,
                               uint32_t p, hipStream_t st);
 // records the device wall clock once the report is complete in host memory
 hipError_t launch_mark_done(HostStatus* out, hipStream_t st);

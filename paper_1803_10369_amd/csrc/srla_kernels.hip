@@ -38,15 +38,19 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t 
 // ------------------------------------------------------------------ sweep
 // |LDR(i)|^k of Section 4.2 for every row, the LE activity bitmap that the
 // estimate kernel ANDs across rows, and the scrub of stamps about to alias.
-// One thread reads 8 DRs (16 bytes); 8 neighbouring lanes OR their 8-bit
-// masks into one 64-bit bitmap word.  Grid: x = chunks of a row, y = row.
+// One thread reads 8 DRs (16 bytes) per step, all steps' loads first; 8
+// neighbouring lanes OR their 8-bit masks into one 64-bit bitmap word.  A
+// block's count goes to one of kFillSlots partial sums of its row (by block
+// index), so no more than a few blocks add to one address; the RE sweep
+// folds the partial sums into the row fills.  Grid: x = chunks of a row,
+// y = row.
 
-constexpr int kSweepSteps = 4;
+constexpr int kSweepSteps = 8;
 constexpr uint64_t kSweepTile = (uint64_t)kBlock * 8 * kSweepSteps;  // DRs per block
 
 __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
                                                     uint64_t* __restrict__ bitmap,
-                                                    unsigned long long* __restrict__ row_fill,
+                                                    unsigned long long* __restrict__ fill_part,
                                                     uint64_t row_cells,
                                                     const PipeState* __restrict__ ps,
                                                     uint32_t k) {
@@ -112,16 +116,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
   if (threadIdx.x == 0) {
     unsigned long long t = 0;
     for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
-    if (t) atomicAdd(&row_fill[row], t);
+    if (t) atomicAdd(&fill_part[(uint64_t)row * kFillSlots + (blockIdx.x % kFillSlots)], t);
   }
 }
 
-hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* row_fill,
+hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* fill_part,
                            const Geo& geo, const PipeState* ps, hipStream_t st) {
   const uint64_t row_cells = (uint64_t)geo.v_le * geo.G;
   const uint64_t bx = (row_cells + kSweepTile - 1) / kSweepTile;
   hipLaunchKernelGGL(k_sweep_le, dim3((uint32_t)bx, geo.u), dim3(kBlock), 0, st, le, bitmap,
-                     row_fill, row_cells, ps, geo.k);
+                     fill_part, row_cells, ps, geo.k);
   return hipGetLastError();
 }
 
@@ -143,25 +147,50 @@ __device__ __forceinline__ double eq8(const unsigned long long* __restrict__ row
   return p;
 }
 
-// The LE sweep has finished the row fills when this kernel starts (same
-// stream), so its first thread also evaluates Eq8.
+// The LE sweep has finished the partial row fills when this kernel starts
+// (same stream), so its first block folds them into the row fills and
+// evaluates Eq8.  One thread takes kReSteps groups of 8 DRs, their loads
+// issued first.
+constexpr int kReSteps = 4;
+
 __global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, uint64_t n,
                                                     uint64_t* __restrict__ act,
                                                     const PipeState* __restrict__ ps,
                                                     uint32_t k,
-                                                    const unsigned long long* __restrict__ row_fill,
+                                                    const unsigned long long* __restrict__ fill_part,
+                                                    unsigned long long* __restrict__ row_fill,
                                                     uint32_t u, uint32_t G, uint32_t v_le,
                                                     double* __restrict__ up) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *up = eq8(row_fill, u, G, v_le);
+  if (blockIdx.x == 0) {
+    if (fill_part) {
+      // one wave per row: lane l adds slot l
+      const uint32_t lane0 = threadIdx.x & (kWave - 1);
+      for (uint32_t r = threadIdx.x / kWave; r < u; r += kBlock / kWave) {
+        unsigned long long v = lane0 < kFillSlots ? fill_part[(uint64_t)r * kFillSlots + lane0] : 0ull;
+        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane0 == 0) row_fill[r] = v;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) *up = eq8(row_fill, u, G, v_le);
+  }
   const uint32_t now = ps->snap;   // the slice being snapshotted
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint64_t c8 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 8;
+  uint4 qs[kReSteps];
+#pragma unroll
+  for (int st8 = 0; st8 < kReSteps; ++st8) {
+    const uint64_t c8 = (((uint64_t)blockIdx.x * kReSteps + st8) * kBlock + threadIdx.x) * 8;
+    qs[st8] = c8 + 8 <= n ? *reinterpret_cast<const uint4*>(re + c8) : make_uint4(0u, 0u, 0u, 0u);
+  }
+#pragma unroll
+  for (int st8 = 0; st8 < kReSteps; ++st8) {
+  const uint64_t c8 = (((uint64_t)blockIdx.x * kReSteps + st8) * kBlock + threadIdx.x) * 8;
   uint32_t m_now = 0, m_next = 0;
   if (c8 < n) {
     uint32_t cell[8];
     const bool full = c8 + 8 <= n;
     if (full) {
-      const uint4 q = *reinterpret_cast<const uint4*>(re + c8);
+      const uint4 q = qs[st8];
       const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
       for (int j = 0; j < 4; ++j) { cell[2 * j] = w[j] & 0xFFFFu; cell[2 * j + 1] = w[j] >> 16; }
@@ -202,14 +231,16 @@ __global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, 
     act[2 * (c8 / 64)] = ((uint64_t)a_hi << 32) | a_lo;
     act[2 * (c8 / 64) + 1] = ((uint64_t)b_hi << 32) | b_lo;
   }
+  }
 }
 
 hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act, const Geo& geo,
-                           const PipeState* ps, const unsigned long long* row_fill, double* up,
-                           hipStream_t st) {
-  const uint64_t blocks = n ? (n + 8 * kBlock - 1) / (8 * kBlock) : 1;
+                           const PipeState* ps, const unsigned long long* fill_part,
+                           unsigned long long* row_fill, double* up, hipStream_t st) {
+  const uint64_t per = (uint64_t)8 * kBlock * kReSteps;
+  const uint64_t blocks = n ? (n + per - 1) / per : 1;
   hipLaunchKernelGGL(k_sweep_re, dim3((uint32_t)blocks), dim3(kBlock), 0, st, re, n, act, ps,
-                     geo.k, row_fill, geo.u, geo.G, geo.v_le, up);
+                     geo.k, fill_part, row_fill, geo.u, geo.G, geo.v_le, up);
   return hipGetLastError();
 }
 
@@ -809,19 +840,19 @@ hipError_t launch_mark_scan(uint32_t* started, uint32_t value, hipStream_t st) {
 }
 
 __global__ void k_begin_close(PipeState* __restrict__ ps, unsigned long long* __restrict__ row_fill,
-                              uint32_t u, uint32_t p) {
+                              uint32_t n_clear, uint32_t p) {
   if (blockIdx.x != 0) return;
   if (threadIdx.x == 0) {
     ps->t_close[p] = ps->scanned[p] ? ps->t_scan[p] : wall_clock64();
     ps->scanned[p] = 0u;
     ps->snap = ps->snap % kStampPeriod + 1u;
   }
-  for (uint32_t i = threadIdx.x; i < u; i += blockDim.x) row_fill[i] = 0ull;
+  for (uint32_t i = threadIdx.x; i < n_clear; i += blockDim.x) row_fill[i] = 0ull;
 }
 
-hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t u,
+hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t n_clear,
                               uint32_t p, hipStream_t st) {
-  hipLaunchKernelGGL(k_begin_close, dim3(1), dim3(64), 0, st, ps, row_fill, u, p);
+  hipLaunchKernelGGL(k_begin_close, dim3(1), dim3(64), 0, st, ps, row_fill, n_clear, p);
   return hipGetLastError();
 }
 

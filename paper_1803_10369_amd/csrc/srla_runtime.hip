@@ -148,6 +148,7 @@ struct srla_monitor {
   uint64_t* bitmap[2] = {nullptr, nullptr};   // LE DRs inside the window
   uint64_t* act[2] = {nullptr, nullptr};      // SRE DRs inside the window / after the slide
   unsigned long long* row_fill[2] = {nullptr, nullptr};
+  unsigned long long* fill_part[2] = {nullptr, nullptr};   // the LE sweep's partial sums
   double* up[2] = {nullptr, nullptr};
   Counters* cnt = nullptr;
   PipeState* ps = nullptr;
@@ -440,7 +441,8 @@ hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
-  e = launch_begin_close(m->ps, m->row_fill[p], geo.u, (uint32_t)p, st);
+  e = m->discrete ? launch_begin_close(m->ps, m->row_fill[p], geo.u, (uint32_t)p, st)
+                  : launch_begin_close(m->ps, m->fill_part[p], geo.u * kFillSlots, (uint32_t)p, st);
   if (e != hipSuccess) return e;
   if (m->discrete) {
     // the closing slice's bits are its activity maps already; the other
@@ -453,9 +455,10 @@ hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
       e = launch_fill_u32((uint32_t*)m->rebits[p ^ 1], 0u, 4 * bitmap_words(m->n_re), st);
   } else {
     if (e == hipSuccess)
-      e = launch_sweep_le(m->le, m->bitmap[p], m->row_fill[p], geo, m->ps, st);
+      e = launch_sweep_le(m->le, m->bitmap[p], m->fill_part[p], geo, m->ps, st);
     if (e == hipSuccess)
-      e = launch_sweep_re(m->re, m->n_re, m->act[p], geo, m->ps, m->row_fill[p], m->up[p], st);
+      e = launch_sweep_re(m->re, m->n_re, m->act[p], geo, m->ps, m->fill_part[p],
+                          m->row_fill[p], m->up[p], st);
   }
   if (spans) span_end(m, st, ST_SWEEP, ta);
   return e;
@@ -621,7 +624,7 @@ void release(srla_monitor* m) {
   dfree(m->part_entries); dfree(m->part_offs); dfree(m->part_marks);
   for (int i = 0; i < 2; ++i) { dfree(m->lebits[i]); dfree(m->rebits[i]); dfree(m->sset[i]); } 
   for (int i = 0; i < 2; ++i) { dfree(m->bitmap[i]); dfree(m->act[i]); }
-  for (int i = 0; i < 2; ++i) { dfree(m->row_fill[i]); dfree(m->up[i]); }
+  for (int i = 0; i < 2; ++i) { dfree(m->row_fill[i]); dfree(m->fill_part[i]); dfree(m->up[i]); }
   dfree(m->cnt); dfree(m->ps);
   dfree(m->tcount);
   dfree(m->claim);
@@ -679,7 +682,7 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
                                   4 * part_mark_words(le)
                             : 0;
   return part + staging_bytes(cfg) + 2 * le + 16 * bitmap_words(le) + 2 * (re + 8) +
-         32 * bitmap_words(re) + 64 * si + 16 * g.u + 16 + sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 +
+         32 * bitmap_words(re) + 64 * si + 16 * g.u + 16 * kFillSlots * g.u + 16 + sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 +
          candidate_bytes(cfg->max_candidates);
 }
 
@@ -798,6 +801,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
   if (!rc) nomem(dalloc(&m->si_cnt, 16 * m->n_si));
   for (int i = 0; i < 2 && !rc; ++i) {
     nomem(dalloc(&m->row_fill[i], g.u));
+    if (!rc && !m->discrete) nomem(dalloc(&m->fill_part[i], (uint64_t)g.u * kFillSlots));
     if (!rc) nomem(dalloc(&m->up[i], 1));
   }
   if (!rc) nomem(dalloc(&m->cnt, 1));
