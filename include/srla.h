@@ -170,10 +170,12 @@ typedef struct srla_monitor srla_monitor_t;
 /*
  * The report of one closed slice e, covering the window [e-k+1, e]
  * (window_full == 0 while e < k-1).  Arrays are pinned host memory owned by
- * the library, written by its kernels (two sets, used by alternate slices);
+ * the library, written by its kernels (three sets, used by slices in turn);
  * they stay valid until slice e+2 is closed (srla_close_slice or
  * srla_estimate) or srla_destroy.
- *   ip            the candidate list CSIP (Algorithms 2-3), ascending
+ *   ip            the candidate list CSIP = NCSIP + N (Algorithms 2-3): the
+ *                 candidates carried from slice e-1, ascending, then the new
+ *                 candidates of slice e (flag NEW), ascending
  *   est           Eq9 estimate of |OP(ip, e-k+1, k)| (FP64; +inf with SAT)
  *   flags         SRLA_FLAG_* of each candidate
  *   union_weight  |ULE(ip)|^k, union LE DRs inside the window (Algorithm 1)

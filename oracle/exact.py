@@ -186,7 +186,8 @@ class BruteForce:
                 usi &= si_start[i * self.v_re + self.h.col_re(i, touched)]
             bit_clear = ((usi >> self.h.si_idx(touched).astype(np.uint16)) & 1) == 0
             new = touched[(W_t >= self.t_re) & bit_clear]
-        csip = np.union1d(self.ncsip, new).astype(np.uint32)
+        # the carried list, then the new candidates, each ascending
+        csip = np.concatenate([self.ncsip, np.sort(new)]).astype(np.uint32)
 
         cells = self.v_le * self.G
         act = self._active(self.last_le, e)
@@ -216,7 +217,7 @@ class BruteForce:
         flags |= np.where(np.isin(csip, new), 4, 0).astype(np.uint8)
         keep = W_after >= self.t_re
         flags |= np.where(keep, 8, 0).astype(np.uint8)
-        self.ncsip = csip[keep]
+        self.ncsip = np.sort(csip[keep])
         return dict(slice=e, window_full=e >= self.k - 1, ip=csip, est=est,
                     flags=flags, union_weight=U, re_weight=W, row_fill=L, up=up,
                     n_touched=touched.size, n_new=new.size)

@@ -26,7 +26,9 @@
  *  candidates    Slice-synchronous: at the end of slice t every source with at
  *                least one sampled pair in t is checked once against the
  *                end-of-slice SRE and against SI as Algorithm 3 left it; the
- *                candidate list is kept in ascending order.  (With
+ *                candidate list CSIP_t = NCSIP_{t-1} + N_t (Algorithms 2-3) is
+ *                reported as the carried list, ascending, followed by the
+ *                new candidates, ascending.  (With
  *                cfg.sequential the check runs after every sampled pair in
  *                stream order instead, inserting and marking SI at once --
  *                Algorithm 2 taken literally; used to measure the reading.)
@@ -401,14 +403,15 @@ int orc_estimate(orc_monitor *m, orc_report *out)
         }
     }
 
-    /* CSIP of this slice: the carried list plus the new candidates */
+    /* CSIP of this slice: the carried list, then the new candidates (each
+       ascending; the two sets are disjoint, since a carried candidate's own
+       SI bit is set) */
     n = m->n_ncsip + n_new;
     if (n > m->cfg.max_candidates) { m->poisoned = 1; rc = -3; goto done; }
     if (reserve_report(m, n ? n : 1)) { rc = -2; goto done; }
     csip = m->r_ip;
     for (x = 0; x < m->n_ncsip; x++) csip[x] = m->ncsip[x];
     for (x = 0; x < n_new; x++) csip[m->n_ncsip + x] = news[x];
-    qsort(csip, n, sizeof(uint32_t), cmp_u32);
 
     /* insertion marks the candidate's SI bit in every row */
     for (x = 0; x < n_new; x++) set_si_bits(m, news[x]);
@@ -446,7 +449,7 @@ int orc_estimate(orc_monitor *m, orc_report *out)
             else est = -G * log(y);
         }
         if (est >= (double)m->cfg.theta) fl |= ORC_SUPER;
-        if (n_new && bsearch(&aip, news, n_new, sizeof(uint32_t), cmp_u32)) fl |= ORC_NEW;
+        if (x >= m->n_ncsip) fl |= ORC_NEW;
         m->r_est[x] = est;
         m->r_flags[x] = fl;
         m->r_U[x] = U;
@@ -474,6 +477,8 @@ int orc_estimate(orc_monitor *m, orc_report *out)
                 set_si_bits(m, csip[x]);
             }
         }
+        /* the carried list, ascending */
+        if (n_keep) qsort(keep, n_keep, sizeof(uint32_t), cmp_u32);
         free(m->ncsip);
         m->ncsip = keep;
         m->n_ncsip = n_keep;

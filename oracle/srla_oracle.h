@@ -50,7 +50,7 @@ typedef struct {
     uint64_t slice;               /* index of the slice just closed */
     uint32_t window_full;         /* slice >= k-1 */
     uint64_t n;                   /* |CSIP| */
-    const uint32_t *ip;           /* ascending */
+    const uint32_t *ip;           /* NCSIP of the previous slice ascending, then N_t ascending */
     const double *est;            /* Eq9 */
     const uint8_t *flags;
     const uint32_t *union_weight; /* |ULE(aip)|^k */

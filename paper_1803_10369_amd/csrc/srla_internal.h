@@ -79,7 +79,8 @@ struct Counters {
   uint32_t n_cand;       // |CSIP_t| (clamped to capacity)
   uint32_t n_keep;       // |NCSIP_t|
   uint32_t overflow;     // CSIP_t exceeded capacity
-  uint32_t pad[2];
+  uint32_t n_keep_a;     // carried candidates of CSIP_t that stay in NCSIP_t
+  uint32_t pad;
 };
 
 // Device-resident state the end-of-slice pipeline reads instead of host
@@ -94,6 +95,8 @@ struct PipeState {
   uint64_t t_scan[2];    // device wall clock at the end of the last scan of the
                          // open slice of each parity
   uint32_t scanned[2];   // that slice has had a scan
+  uint32_t scan_done[2]; // workgroups of the running scan's last kernel that have
+                         // finished (the last one reads the clock)
   uint32_t snap;         // stamp code of the slice snapshotted last (0: none yet);
                          // the snapshot keeps its own count so that it need not
                          // wait for the previous slice's candidate work
@@ -194,16 +197,30 @@ hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const 
                            const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
                            hipStream_t st);
 
-hipError_t launch_merge(const uint32_t* ncsip, const PipeState* ps, const uint32_t* news,
-                        Counters* cnt, uint64_t cap, uint32_t* csip, uint8_t* cflags,
-                        hipStream_t st);
+// CSIP_t = the carried list (the first ps->n_ncsip entries of cand) followed
+// by the cnt->n_new new candidates, appended to cand (capacity cap)
+hipError_t launch_join(const PipeState* ps, const uint32_t* news, Counters* cnt, uint64_t cap,
+                       uint32_t* cand, hipStream_t st);
+// cnt->n_keep_a += KEEP flags among the carried part of CSIP_t
+hipError_t launch_count_keep(const uint8_t* cflags, const PipeState* ps, Counters* cnt,
+                             hipStream_t st);
+// merges the ascending runs [0, *na) and [*na, *n) of in into out
+hipError_t launch_merge_runs(const uint32_t* in, const uint32_t* na, const uint32_t* n,
+                             uint32_t* out, hipStream_t st);
+// copies *n uint32 from src (device) to dst (pinned host memory, 16-byte aligned)
+hipError_t launch_ip_precopy(const uint32_t* src, const uint32_t* n, uint32_t* dst,
+                             hipStream_t st);
 
 hipError_t launch_union_prob(const unsigned long long* row_fill, const Geo& geo,
                              double* up, hipStream_t st);
 
-// Eq9 for every candidate; rows whose row fill is g' * v_le (every LE DR
-// inside the window) are not gathered
-hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
+// Eq9 for every candidate of CSIP (csip: the carried list, ps->n_ncsip
+// entries, then the new candidates); rows whose row fill is g' * v_le (every
+// LE DR inside the window) are not gathered.  skip_carried_ip: the report's
+// ip array holds the carried list already, only the new candidates' are
+// written
+hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const PipeState* ps,
+                           bool skip_carried_ip, const uint64_t* bitmap,
                            const uint64_t* act, const double* up,
                            const unsigned long long* row_fill, const Geo& geo, uint8_t* cflags,
                            const ReportPtrs& out, hipStream_t st);

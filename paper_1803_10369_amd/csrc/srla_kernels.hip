@@ -371,21 +371,16 @@ hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const 
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ merge
-// CSIP_t = NCSIP_{t-1} u N_t, both ascending and disjoint (every carried
-// candidate has its own SI bit set, so it cannot be new), by merge path:
-// thread q writes outputs [8q, 8q + 8); a binary search along its diagonal
-// finds how many of the first 8q outputs come from NCSIP (the search range is
-// at most |N_t| wide), then it merges its 8 outputs sequentially.
+// ------------------------------------------------------------------ join
+// CSIP_t = NCSIP_{t-1} + N_t (Algorithms 2-3), listed as the carried list
+// (ascending, already in `cand`) followed by the new candidates (ascending):
+// N_t is appended behind the carried list.  The two sets are disjoint (a
+// carried candidate's own SI bit is set, so it never passes the check).
 
-constexpr uint32_t kMergePer = 8;
-
-__global__ __launch_bounds__(kBlock) void k_merge(const uint32_t* __restrict__ ncsip,
-                                                 const PipeState* __restrict__ ps,
-                                                 const uint32_t* __restrict__ news,
-                                                 Counters* __restrict__ cnt, uint64_t cap,
-                                                 uint32_t* __restrict__ csip,
-                                                 uint8_t* __restrict__ cflags) {
+__global__ __launch_bounds__(kBlock) void k_join(const PipeState* __restrict__ ps,
+                                                const uint32_t* __restrict__ news,
+                                                Counters* __restrict__ cnt, uint64_t cap,
+                                                uint32_t* __restrict__ cand) {
   const uint64_t n_old = ps->n_ncsip;
   const uint64_t n_new = cnt->n_new;
   const uint64_t total = n_old + n_new;
@@ -394,36 +389,110 @@ __global__ __launch_bounds__(kBlock) void k_merge(const uint32_t* __restrict__ n
     cnt->n_cand = (uint32_t)m;
     cnt->overflow = total > cap ? 1u : 0u;
   }
+  for (uint64_t k = n_old + (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < m;
+       k += (uint64_t)gridDim.x * kBlock)
+    cand[k] = news[k - n_old];
+}
+
+hipError_t launch_join(const PipeState* ps, const uint32_t* news, Counters* cnt, uint64_t cap,
+                       uint32_t* cand, hipStream_t st) {
+  hipLaunchKernelGGL(k_join, dim3(kPipeBlocks), dim3(kBlock), 0, st, ps, news, cnt, cap, cand);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ carried list
+// NCSIP_t, ascending, from the candidates CSIP_t kept by Algorithm 3: their
+// compaction lists the kept carried candidates (ascending) and then the kept
+// new ones (ascending); k_count_keep counts the first run, and k_merge_runs
+// merges the two by merge path (each thread writes kMergePer outputs after
+// one binary search along its diagonal).
+
+__global__ __launch_bounds__(kBlock) void k_count_keep(const uint8_t* __restrict__ cflags,
+                                                      const PipeState* __restrict__ ps,
+                                                      Counters* __restrict__ cnt) {
+  const uint64_t n_c = ps->n_ncsip < cnt->n_cand ? ps->n_ncsip : cnt->n_cand;
+  uint32_t c = 0;
+  for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < n_c;
+       k += (uint64_t)gridDim.x * kBlock)
+    c += (cflags[k] & 8u) ? 1u : 0u;
+  for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  __shared__ uint32_t part[kBlock / kWave];
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+    if (t) atomicAdd(&cnt->n_keep_a, t);
+  }
+}
+
+hipError_t launch_count_keep(const uint8_t* cflags, const PipeState* ps, Counters* cnt,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_count_keep, dim3(kPipeBlocks), dim3(kBlock), 0, st, cflags, ps, cnt);
+  return hipGetLastError();
+}
+
+constexpr uint32_t kMergePer = 8;
+
+// runs [0, *na) and [*na, *n) of `in`, each ascending, merged into out
+__global__ __launch_bounds__(kBlock) void k_merge_runs(const uint32_t* __restrict__ in,
+                                                      const uint32_t* __restrict__ na_p,
+                                                      const uint32_t* __restrict__ n_p,
+                                                      uint32_t* __restrict__ out) {
+  const uint64_t m = *n_p;
+  const uint64_t na = *na_p < m ? *na_p : m;
+  const uint64_t nb = m - na;
+  const uint32_t* a = in;
+  const uint32_t* b = in + na;
   const uint64_t stride = (uint64_t)gridDim.x * kBlock * kMergePer;
   for (uint64_t k0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * kMergePer; k0 < m;
        k0 += stride) {
-    uint64_t lo = k0 > n_new ? k0 - n_new : 0, hi = k0 < n_old ? k0 : n_old;
+    uint64_t lo = k0 > nb ? k0 - nb : 0, hi = k0 < na ? k0 : na;
     while (lo < hi) {
       const uint64_t mid = (lo + hi) >> 1;
-      if (ncsip[mid] < news[k0 - mid - 1]) lo = mid + 1; else hi = mid;
+      if (a[mid] < b[k0 - mid - 1]) lo = mid + 1; else hi = mid;
     }
     uint64_t i = lo, j = k0 - lo;
     const uint64_t kend = k0 + kMergePer < m ? k0 + kMergePer : m;
     for (uint64_t k = k0; k < kend; ++k) {
-      // i + j = k < n_old + n_new, so with N_t used up NCSIP has one left
-      if (j >= n_new || (i < n_old && ncsip[i] < news[j])) {
-        csip[k] = ncsip[i++];
-        cflags[k] = 0;
-      } else {
-        csip[k] = news[j++];
-        cflags[k] = 4;   // SRLA_FLAG_NEW
-      }
+      // i + j = k < na + nb, so with run b used up run a has one left
+      if (j >= nb || (i < na && a[i] < b[j])) out[k] = a[i++];
+      else out[k] = b[j++];
     }
   }
 }
 
-hipError_t launch_merge(const uint32_t* ncsip, const PipeState* ps, const uint32_t* news,
-                        Counters* cnt, uint64_t cap, uint32_t* csip, uint8_t* cflags,
-                        hipStream_t st) {
+hipError_t launch_merge_runs(const uint32_t* in, const uint32_t* na, const uint32_t* n,
+                             uint32_t* out, hipStream_t st) {
   // twice the pipeline grid: every CU full, so more of the binary searches'
   // dependent loads are in flight at once
-  hipLaunchKernelGGL(k_merge, dim3(2 * kPipeBlocks), dim3(kBlock), 0, st, ncsip, ps, news, cnt,
-                     cap, csip, cflags);
+  hipLaunchKernelGGL(k_merge_runs, dim3(2 * kPipeBlocks), dim3(kBlock), 0, st, in, na, n, out);
+  return hipGetLastError();
+}
+
+// The carried list NCSIP_t is the head of the next slice's report: its *n
+// addresses go into that report's ip array (pinned host memory) now, beside
+// the next slice's scans, instead of after its candidate check.
+__global__ __launch_bounds__(kBlock) void k_ip_precopy(const uint32_t* __restrict__ src,
+                                                      const uint32_t* __restrict__ n_p,
+                                                      uint32_t* __restrict__ dst) {
+  const uint64_t n = *n_p;
+  const uint64_t n4 = n / 4;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (uint64_t i = t; i < n4; i += stride)
+    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
+  if (t < n - n4 * 4) dst[n4 * 4 + t] = src[n4 * 4 + t];
+}
+
+// a small grid: the copy runs beside the next slice's scans and is bound by
+// PCIe writes, which a few workgroups saturate (64 and 256 workgroups
+// measured alike on the backbone workload)
+constexpr uint32_t kPrecopyBlocks = 64;
+
+hipError_t launch_ip_precopy(const uint32_t* src, const uint32_t* n, uint32_t* dst,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_ip_precopy, dim3(kPrecopyBlocks), dim3(kBlock), 0, st, src, n, dst);
   return hipGetLastError();
 }
 
@@ -484,6 +553,7 @@ __device__ __forceinline__ void lds_barrier() {
 template <int kU, int kWpl>
 __global__ __launch_bounds__(kBlock) void k_estimate(
     const uint32_t* __restrict__ csip, const Counters* __restrict__ cnt,
+    const PipeState* __restrict__ ps, uint32_t skip_carried_ip,
     const uint64_t* __restrict__ bitmap, const uint64_t* __restrict__ act,
     const double* __restrict__ up_p, const unsigned long long* __restrict__ row_fill, Geo geo,
     uint32_t lg_log2, uint8_t* __restrict__ cflags, uint32_t* __restrict__ out_ip,
@@ -497,6 +567,11 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
   const uint32_t per_round = kBlock >> lg_log2;          // candidates per round
   const uint32_t sub = threadIdx.x & (lg - 1u);
   const uint32_t n = cnt->n_cand;
+  // CSIP is the carried list (its first n_c entries) and then the new
+  // candidates; with skip_carried_ip the carried addresses are in the
+  // report's ip array already
+  const uint64_t n_c = ps->n_ncsip;
+  const uint64_t ip_from = skip_carried_ip ? n_c : 0;
   const uint64_t gmask = geo.g == 64u ? ~0ull : ((1ull << geo.g) - 1ull);
   // rows whose every LE DR is inside the window (|LDR(i)|^k = g' * v): their
   // bitmap words are all ones, the identity of the AND, so they are not read
@@ -592,7 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
       const double num = (double)ucount - G * up;
       const double den = G * (1.0 - up);
       double e;
-      uint8_t fl = cflags[gid] & 4u;   // NEW, written by the merge
+      uint8_t fl = gid >= n_c ? 4u : 0u;   // NEW: listed behind the carried list
       if (den == 0.0) {
         e = __builtin_inf();
         fl |= 2u;
@@ -620,15 +695,19 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
     // by entry
     if (in_batch == kEstPerBlock) {
       const uint32_t t = threadIdx.x;
-      if (t < kEstPerBlock / 4)
-        reinterpret_cast<uint4*>(out_ip + base)[t] = reinterpret_cast<const uint4*>(s_ip)[t];
+      if (base >= ip_from) {
+        if (t < kEstPerBlock / 4)
+          reinterpret_cast<uint4*>(out_ip + base)[t] = reinterpret_cast<const uint4*>(s_ip)[t];
+      } else if (base + t >= ip_from) {
+        out_ip[base + t] = s_ip[t];
+      }
       if (t < kEstPerBlock / 2)
         reinterpret_cast<uint4*>(out_est + base)[t] = reinterpret_cast<const uint4*>(s_e)[t];
       if (t < kEstPerBlock / 16)
         reinterpret_cast<uint4*>(out_flags + base)[t] = reinterpret_cast<const uint4*>(s_f)[t];
     } else if (threadIdx.x < in_batch) {
       const uint64_t gid = base + threadIdx.x;
-      out_ip[gid] = s_ip[threadIdx.x];
+      if (gid >= ip_from) out_ip[gid] = s_ip[threadIdx.x];
       out_est[gid] = s_e[threadIdx.x];
       out_flags[gid] = s_f[threadIdx.x];
     }
@@ -664,12 +743,14 @@ static uint32_t est_grid() {
 
 template <int kU, int kWpl>
 static hipError_t launch_estimate_u(const uint32_t* csip, const Counters* cnt,
+                                    const PipeState* ps, uint32_t skip,
                                     const uint64_t* bitmap, const uint64_t* act, const double* up,
                                     const unsigned long long* row_fill, const Geo& geo,
                                     uint32_t l, uint8_t* cflags, const ReportPtrs& out,
                                     hipStream_t st) {
   static const uint32_t grid = est_grid<kU, kWpl>();
-  hipLaunchKernelGGL((k_estimate<kU, kWpl>), dim3(grid), dim3(kBlock), 0, st, csip, cnt, bitmap,
+  hipLaunchKernelGGL((k_estimate<kU, kWpl>), dim3(grid), dim3(kBlock), 0, st, csip, cnt, ps,
+                     skip, bitmap,
                      act, up, row_fill, geo, l, cflags, out.ip, out.est, out.flags,
                      out.U, out.W);
   return hipGetLastError();
@@ -677,17 +758,20 @@ static hipError_t launch_estimate_u(const uint32_t* csip, const Counters* cnt,
 
 template <int kU>
 static hipError_t launch_estimate_w(const uint32_t* csip, const Counters* cnt,
+                                    const PipeState* ps, uint32_t skip,
                                     const uint64_t* bitmap, const uint64_t* act, const double* up,
                                     const unsigned long long* row_fill, const Geo& geo,
                                     uint32_t l, uint8_t* cflags, const ReportPtrs& out,
                                     hipStream_t st) {
   if (est_wpl(geo) == 2)
-    return launch_estimate_u<kU, 2>(csip, cnt, bitmap, act, up, row_fill, geo, l, cflags, out,
-                                    st);
-  return launch_estimate_u<kU, 1>(csip, cnt, bitmap, act, up, row_fill, geo, l, cflags, out, st);
+    return launch_estimate_u<kU, 2>(csip, cnt, ps, skip, bitmap, act, up, row_fill, geo, l,
+                                    cflags, out, st);
+  return launch_estimate_u<kU, 1>(csip, cnt, ps, skip, bitmap, act, up, row_fill, geo, l, cflags,
+                                  out, st);
 }
 
-hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint64_t* bitmap,
+hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const PipeState* ps,
+                           bool skip_carried_ip, const uint64_t* bitmap,
                            const uint64_t* act, const double* up,
                            const unsigned long long* row_fill, const Geo& geo, uint8_t* cflags,
                            const ReportPtrs& out, hipStream_t st) {
@@ -695,10 +779,13 @@ hipError_t launch_estimate(const uint32_t* csip, const Counters* cnt, const uint
   const uint32_t l = est_lg_log2(geo);
   if (geo.u > (1u << l)) return hipErrorInvalidValue;
   if (geo.u <= 4)
-    return launch_estimate_w<4>(csip, cnt, bitmap, act, up, row_fill, geo, l, cflags, out, st);
+    return launch_estimate_w<4>(csip, cnt, ps, skip_carried_ip, bitmap, act, up, row_fill, geo, l,
+                                cflags, out, st);
   if (geo.u <= 8)
-    return launch_estimate_w<8>(csip, cnt, bitmap, act, up, row_fill, geo, l, cflags, out, st);
-  return launch_estimate_w<16>(csip, cnt, bitmap, act, up, row_fill, geo, l, cflags, out, st);
+    return launch_estimate_w<8>(csip, cnt, ps, skip_carried_ip, bitmap, act, up, row_fill, geo, l,
+                                cflags, out, st);
+  return launch_estimate_w<16>(csip, cnt, ps, skip_carried_ip, bitmap, act, up, row_fill, geo, l,
+                               cflags, out, st);
 }
 
 // ------------------------------------------------------------------ SI

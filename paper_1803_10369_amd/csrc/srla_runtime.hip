@@ -115,6 +115,9 @@ struct TimedSpan {
 };
 
 constexpr uint64_t kStageChunk = 1ull << 22;  // pairs per host-ingest chunk
+// host report sets (slice mod kSets) and the cycle of (parity, set) pairs
+constexpr int kSets = 3;
+constexpr int kCycle = 6;
 
 }  // namespace
 
@@ -168,26 +171,29 @@ struct srla_monitor {
   uint64_t touched_cap = 0;
   uint64_t slice_pairs[2] = {0, 0};
 
-  // candidate lists: slice parity p merges carried[p] and compacts into carried[p^1]
+  // candidate lists: slice parity p appends its new candidates to the carried
+  // list carried[p] (CSIP) and leaves its own carried list in carried[p^1];
+  // csip is scratch of that step
   uint32_t* csip = nullptr;
   uint32_t* carried[2] = {nullptr, nullptr};
   uint8_t* cflags = nullptr;
   uint32_t* cblockw = nullptr;
   uint64_t cap = 0;
 
-  // pinned host side, one set per slice parity, so that a slice can be closed
-  // before the previous slice's report is collected (the report arrays and
-  // the status blocks are written by kernels through their device-visible
-  // addresses)
-  HostStatus* h_status[2] = {nullptr, nullptr};
-  HostStatus* d_status[2] = {nullptr, nullptr};
-  uint64_t* h_row_fill64[2] = {nullptr, nullptr};
-  uint32_t* h_ip[2] = {nullptr, nullptr};
-  double* h_est[2] = {nullptr, nullptr};
-  uint8_t* h_flags[2] = {nullptr, nullptr};
-  uint32_t* h_U[2] = {nullptr, nullptr};
-  uint8_t* h_W[2] = {nullptr, nullptr};
-  ReportPtrs d_report[2] = {};
+  // pinned host side, one set per slice mod kSets (the report arrays and the
+  // status blocks are written by kernels through their device-visible
+  // addresses): a slice can be closed before the previous slice's report is
+  // collected, and a slice's carried list goes into the next slice's set while
+  // the host may still read the previous one
+  HostStatus* h_status[kSets] = {};
+  HostStatus* d_status[kSets] = {};
+  uint64_t* h_row_fill64[kSets] = {};
+  uint32_t* h_ip[kSets] = {};
+  double* h_est[kSets] = {};
+  uint8_t* h_flags[kSets] = {};
+  uint32_t* h_U[kSets] = {};
+  uint8_t* h_W[kSets] = {};
+  ReportPtrs d_report[kSets] = {};
   bool overlap_report = false;   // candidate work before the next slice's scans,
   ReportPtrs d_staging[2] = {};  // report staged here (by slice parity) and copied while
   uint32_t* report_n = nullptr;  // they run; [2] entries in each staged report
@@ -202,9 +208,9 @@ struct srla_monitor {
   int clock_khz = 0;              // rate of the device wall clock
   bool finish_deferred = false;   // the last closed slice's second phase is not enqueued yet
 
-  // replayable pipeline: [phase][parity]
+  // replayable pipeline: [phase][slice mod kCycle]
   bool use_graph = false;
-  hipGraphExec_t graph[PH_N][2] = {};
+  hipGraphExec_t graph[PH_N][kCycle] = {};
 
   // host-input ring: H2D copies on their own stream into two device chunks
   // (through two pinned bounce chunks when the caller's memory is pageable),
@@ -480,22 +486,30 @@ hipError_t enqueue_sort(srla_monitor* m, int p, hipStream_t st) {
 }
 
 // Algorithm 3 after the estimate of the slice of parity p: the carried list
-// (the candidates whose SRE is still inside the window after the slide, as
-// k_estimate flagged them) and the SI counters.
-hipError_t enqueue_slide(srla_monitor* m, int p, hipStream_t st) {
+// NCSIP (the candidates whose SRE is still inside the window after the
+// slide, as k_estimate flagged them), ascending, into carried[p ^ 1], and the
+// SI counters.  next_ip: the next slice's report ip array, which then gets
+// the carried list (the head of that report) at once.
+hipError_t enqueue_slide(srla_monitor* m, int p, hipStream_t st, uint32_t* next_ip) {
   hipError_t e = hipSuccess;
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
+  uint32_t* cand = m->carried[p];
   if (spans) span_begin(m, st, &ta);
-  e = compact_u32(m->cflags, 8u, m->csip, &m->cnt->n_cand, m->cap, m->carried[p ^ 1],
-                  &m->cnt->n_keep, m->cblockw, st);
-  if (e == hipSuccess) e = launch_si_update(m->csip, m->cflags, m->cnt, m->si_cnt, m->geo, st);
+  e = compact_u32(m->cflags, 8u, cand, &m->cnt->n_cand, m->cap, m->csip, &m->cnt->n_keep,
+                  m->cblockw, st);
+  if (e == hipSuccess) e = launch_count_keep(m->cflags, m->ps, m->cnt, st);
+  if (e == hipSuccess)
+    e = launch_merge_runs(m->csip, &m->cnt->n_keep_a, &m->cnt->n_keep, m->carried[p ^ 1], st);
+  if (e == hipSuccess) e = launch_si_update(cand, m->cflags, m->cnt, m->si_cnt, m->geo, st);
+  if (e == hipSuccess && next_ip)
+    e = launch_ip_precopy(m->carried[p ^ 1], &m->cnt->n_keep, next_ip, st);
   if (spans) span_end(m, st, ST_SLIDE, ta);
   return e;
 }
 
-// The candidate check of the closing slice's (sorted) sampled sources and
-// the merge of the new candidates with the carried list into CSIP.
+// The candidate check of the closing slice's (sorted) sampled sources, and
+// CSIP: the new candidates appended to the carried list.
 hipError_t enqueue_check(srla_monitor* m, int p, hipStream_t st) {
   const Geo& geo = m->geo;
   hipError_t e = hipSuccess;
@@ -508,33 +522,35 @@ hipError_t enqueue_check(srla_monitor* m, int p, hipStream_t st) {
   if (e == hipSuccess)
     e = compact_u32(m->mark, 1u, m->touched[p], tc, m->touched_cap, m->news, &m->cnt->n_new,
                     m->blockw, st);
-  if (e == hipSuccess)
-    e = launch_merge(m->carried[p], m->ps, m->news, m->cnt, m->cap, m->csip, m->cflags, st);
+  if (e == hipSuccess) e = launch_join(m->ps, m->news, m->cnt, m->cap, m->carried[p], st);
   if (spans) span_end(m, st, ST_FINALIZE, ta);
   return e;
 }
 
-// Eq9 for every candidate of CSIP, report entries to `out`.
-hipError_t enqueue_estimate(srla_monitor* m, int p, const ReportPtrs& out, hipStream_t st) {
+// Eq9 for every candidate of CSIP, report entries to `out` (whose ip array
+// holds the carried list already when skip_carried_ip).
+hipError_t enqueue_estimate(srla_monitor* m, int p, const ReportPtrs& out, hipStream_t st,
+                            bool skip_carried_ip) {
   const uint64_t* le_act = m->discrete ? m->lebits[p] : m->bitmap[p];
   const uint64_t* re_act = m->discrete ? m->rebits[p] : m->act[p];
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
-  const hipError_t e = launch_estimate(m->csip, m->cnt, le_act, re_act, m->up[p],
-                                       m->row_fill[p], m->geo, m->cflags, out, st);
+  const hipError_t e = launch_estimate(m->carried[p], m->cnt, m->ps, skip_carried_ip, le_act,
+                                       re_act, m->up[p], m->row_fill[p], m->geo, m->cflags, out,
+                                       st);
   if (spans) span_end(m, st, ST_ESTIMATE, ta);
   return e;
 }
 
 // The whole candidate work of the closing slice (the overlapped-report form
-// runs it in one phase): sort, check and merge, Eq9 into `out`, then
-// Algorithm 3's carried list and SI counters.
+// runs it in one phase, into device staging): sort, check, Eq9 into `out`,
+// then Algorithm 3's carried list and SI counters.
 hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hipStream_t st) {
   hipError_t e = enqueue_sort(m, p, st);
   if (e == hipSuccess) e = enqueue_check(m, p, st);
-  if (e == hipSuccess) e = enqueue_estimate(m, p, out, st);
-  if (e == hipSuccess) e = enqueue_slide(m, p, st);
+  if (e == hipSuccess) e = enqueue_estimate(m, p, out, st, false);
+  if (e == hipSuccess) e = enqueue_slide(m, p, st, nullptr);
   return e;
 }
 
@@ -547,14 +563,16 @@ hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hip
 // the report does not wait for.  With SRLA_CFG_OVERLAP_REPORT the first
 // phase also does the candidate work, into the parity's device staging
 // arrays, and the status, and only the PCIe copy of the report overlaps the
-// scans.
-hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
+// scans.  c: the slice's index mod kCycle, which fixes its parity (device
+// arrays) and its report set (host arrays).
+hipError_t enqueue_phase(srla_monitor* m, int phase, int c, hipStream_t st) {
   hipError_t e = hipSuccess;
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
+  const int p = c & 1, q = c % kSets, q_next = (c + 1) % kSets;
   if (phase == PH_SORT) return enqueue_sort(m, p, st);
   if (phase == PH_SLIDE) {
-    e = enqueue_slide(m, p, st);
+    e = enqueue_slide(m, p, st, m->d_report[q_next].ip);
     if (e == hipSuccess) e = launch_advance(m->cnt, m->tcount + p, m->ps, st);
     return e;
   }
@@ -566,43 +584,44 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
       if (e == hipSuccess)
         e = launch_status(m->cnt, m->tcount + p, m->up[p], m->row_fill[p], m->geo.u, m->ps,
                           (uint32_t)p,
-                          m->d_status[p], m->report_n + p, st);
+                          m->d_status[q], m->report_n + p, st);
       if (spans) span_end(m, st, ST_SLIDE, ta);
     }
     return e;
   }
   if (!m->overlap_report) {
     e = enqueue_check(m, p, st);
-    if (e == hipSuccess) e = enqueue_estimate(m, p, m->d_report[p], st);
+    if (e == hipSuccess) e = enqueue_estimate(m, p, m->d_report[q], st, true);
   }
   if (spans) span_begin(m, st, &ta);
   if (m->overlap_report) {
     // PH_FINISH_GO: the next slice (parity p ^ 1) has its first scan behind a mark
     const uint32_t expect = phase == PH_FINISH_GO ? (uint32_t)(p ^ 1) + 1u : 0u;
     if (e == hipSuccess)
-      e = launch_report_copy(m->report_n + p, m->d_staging[p], m->d_report[p], m->started, expect,
+      e = launch_report_copy(m->report_n + p, m->d_staging[p], m->d_report[q], m->started, expect,
                              st);
-    if (e == hipSuccess) e = launch_mark_done(m->d_status[p], st);
+    if (e == hipSuccess) e = launch_mark_done(m->d_status[q], st);
   } else if (e == hipSuccess) {
     e = launch_publish(m->cnt, m->tcount + p, m->up[p], m->row_fill[p], m->geo.u, m->ps,
-                       (uint32_t)p, m->d_status[p], st);
+                       (uint32_t)p, m->d_status[q], st);
   }
   if (spans) span_end(m, st, ST_REPORT, ta);
   return e;
 }
 
-// Runs one phase on stream st: directly, or through its graph (recorded on
-// first use, on the pipeline stream, and launched on st).
-int run_phase(srla_monitor* m, int phase, int p, hipStream_t st) {
+// Runs one phase of the slice with index mod kCycle c on stream st: directly,
+// or through its graph (recorded on first use, on the pipeline stream, and
+// launched on st).
+int run_phase(srla_monitor* m, int phase, int c, hipStream_t st) {
   if (!m->use_graph) {
-    HIP_TRY(m, enqueue_phase(m, phase, p, st));
+    HIP_TRY(m, enqueue_phase(m, phase, c, st));
     return SRLA_OK;
   }
-  hipGraphExec_t& exec = m->graph[phase][p];
+  hipGraphExec_t& exec = m->graph[phase][c];
   if (!exec) {
     hipGraph_t g = nullptr;
     HIP_TRY(m, hipStreamBeginCapture(m->pipe, hipStreamCaptureModeThreadLocal));
-    const hipError_t e = enqueue_phase(m, phase, p, m->pipe);
+    const hipError_t e = enqueue_phase(m, phase, c, m->pipe);
     const hipError_t ec = hipStreamEndCapture(m->pipe, &g);
     HIP_TRY(m, e);
     HIP_TRY(m, ec);
@@ -637,10 +656,12 @@ void release(srla_monitor* m) {
     dfree(sg.ip); dfree(sg.est); dfree(sg.flags); dfree(sg.U); dfree(sg.W);
   }
   dfree(m->report_n);
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < kSets; ++q) {
     hfree(m->h_status[q]); hfree(m->h_ip[q]); hfree(m->h_est[q]); hfree(m->h_flags[q]);
     hfree(m->h_U[q]); hfree(m->h_W[q]);
     delete[] m->h_row_fill64[q];
+  }
+  for (int q = 0; q < 2; ++q) {
     if (m->ev_done[q]) (void)hipEventDestroy(m->ev_done[q]);
     if (m->ev_pub[q]) (void)hipEventDestroy(m->ev_pub[q]);
   }
@@ -825,7 +846,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     }
   }
   const bool weights = (cfg->flags & SRLA_CFG_LEAN_REPORT) == 0;
-  for (int q = 0; q < 2 && !rc; ++q) {
+  for (int q = 0; q < kSets && !rc; ++q) {
     nomem(halloc(&m->h_status[q], 1));
     if (!rc) nomem(halloc(&m->h_ip[q], m->cap));
     if (!rc) nomem(halloc(&m->h_est[q], m->cap));
@@ -843,6 +864,8 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
                 (weights && dev_view(m->h_U[q], &m->d_report[q].U) != hipSuccess) ||
                 (weights && dev_view(m->h_W[q], &m->d_report[q].W) != hipSuccess)))
       rc = SRLA_E_DEVICE;
+  }
+  for (int q = 0; q < 2 && !rc; ++q) {
     if (!rc && hipEventCreateWithFlags(&m->ev_done[q], hipEventDisableTiming) != hipSuccess)
       rc = SRLA_E_DEVICE;
     if (!rc && hipEventCreateWithFlags(&m->ev_pub[q], hipEventDisableTiming) != hipSuccess)
@@ -917,7 +940,7 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
   if (m->part_scan)
     return launch_scan_partition(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                                  m->tcount + p, m->part_entries, m->part_offs, m->part_marks,
-                                 m->stream);
+                                 m->stream, kPartChunks, kPartSplit, m->ps, (uint32_t)p);
   if (m->dedup_scan)
     return launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                              m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream);
@@ -941,6 +964,7 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
 // behind those writes), so the scan has to be under way before the copy.
 int enqueue_finish(srla_monitor* m, bool go) {
   const int pc = (int)((m->slice - 1) & 1);   // parity of the closed slice
+  const int cc = (int)((m->slice - 1) % kCycle);
   // timed as the slice was when it was closed
   struct TimingAs {
     srla_monitor* m;
@@ -953,19 +977,19 @@ int enqueue_finish(srla_monitor* m, bool go) {
     // the sort needs the slice's scans only: it runs beside the snapshot
     HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_scanned, 0));
     if (m->use_graph) span_begin(m, m->pipe, &ta);
-    const int rs = run_phase(m, PH_SORT, pc, m->pipe);
+    const int rs = run_phase(m, PH_SORT, cc, m->pipe);
     if (rs) return rs;
     if (m->use_graph) span_end(m, m->pipe, ST_FINALIZE, ta);
   }
   HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_snap, 0));
   if (m->use_graph) span_begin(m, m->pipe, &ta);
-  int rc = run_phase(m, go ? PH_FINISH_GO : PH_FINISH, pc, m->pipe);
+  int rc = run_phase(m, go ? PH_FINISH_GO : PH_FINISH, cc, m->pipe);
   if (rc) return rc;
   if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
   HIP_TRY(m, hipEventRecord(m->ev_pub[pc], m->pipe));
   if (!m->overlap_report) {
     if (m->use_graph) span_begin(m, m->pipe, &ta);
-    rc = run_phase(m, PH_SLIDE, pc, m->pipe);
+    rc = run_phase(m, PH_SLIDE, cc, m->pipe);
     if (rc) return rc;
     if (m->use_graph) span_end(m, m->pipe, ST_SLIDE, ta);
   }
@@ -1006,7 +1030,9 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     span_begin(m, m->stream, &a);
     HIP_TRY(m, enqueue_scan(m, pairs, n, p, mark));
     span_end(m, m->stream, ST_SCAN, a);
-    HIP_TRY(m, launch_scan_end(m->ps, (uint32_t)p, m->stream));
+    // the partitioned scan records its own end; other forms get a marker
+    if (!m->part_scan || m->discrete)
+      HIP_TRY(m, launch_scan_end(m->ps, (uint32_t)p, m->stream));
     m->slice_pairs[p] += n;
     if (m->timing) {
       m->scan_launches++;
@@ -1057,7 +1083,8 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     span_begin(m, m->stream, &a);
     HIP_TRY(m, enqueue_scan(m, m->d_stage[b], cnt, p, go ? mark : 0u));
     span_end(m, m->stream, ST_SCAN, a);
-    HIP_TRY(m, launch_scan_end(m->ps, (uint32_t)p, m->stream));
+    if (!m->part_scan || m->discrete)
+      HIP_TRY(m, launch_scan_end(m->ps, (uint32_t)p, m->stream));
     if (go) {
       rc = enqueue_finish(m, true);
       if (rc) return rc;
@@ -1099,8 +1126,8 @@ int srla_scan_noalloc(srla_monitor_t* m, const uint32_t* pairs, uint64_t n) {
   uint16_t* offs = reinterpret_cast<uint16_t*>(base + kNoAllocEntryBytes + kNoAllocMarkBytes);
   HIP_TRY(m, launch_scan_partition(pairs, n, m->geo, stamp_code(m->slice), m->le, m->re,
                                    m->touched[p], m->tcount + p, entries, offs, marks,
-                                   m->stream, kNoAllocChunks, kNoAllocSplit));
-  HIP_TRY(m, launch_scan_end(m->ps, (uint32_t)p, m->stream));
+                                   m->stream, kNoAllocChunks, kNoAllocSplit, m->ps,
+                                   (uint32_t)p));
   m->slice_pairs[p] += n;
   return SRLA_OK;
 }
@@ -1132,7 +1159,7 @@ int srla_close_slice(srla_monitor_t* m) {
   // the second as the estimate (as the report copy when it overlaps)
   hipEvent_t ta;
   if (m->use_graph) span_begin(m, m->stream, &ta);
-  int rc = run_phase(m, PH_SNAPSHOT, p, m->stream);
+  int rc = run_phase(m, PH_SNAPSHOT, (int)(m->slice % kCycle), m->stream);
   if (rc) return rc;
   if (m->use_graph) span_end(m, m->stream, m->overlap_report ? ST_ESTIMATE : ST_SWEEP, ta);
   HIP_TRY(m, hipEventRecord(m->ev_snap, m->stream));
@@ -1162,15 +1189,17 @@ int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
   if (!m || !out) return m ? fail(m, SRLA_E_INVAL, "out is NULL") : SRLA_E_INVAL;
   if (m->poisoned) return fail(m, SRLA_E_STATE, "monitor is poisoned by an earlier error");
   if (!m->n_pending) return fail(m, SRLA_E_STATE, "no closed slice is waiting");
-  // the oldest closed slice whose report is not collected yet
-  const int q = (int)((m->slice - m->n_pending) & 1);
+  // the oldest closed slice whose report is not collected yet: its parity
+  // (events) and its report set
+  const uint64_t e_slice = m->slice - m->n_pending;
+  const int pe = (int)(e_slice & 1), q = (int)(e_slice % kSets);
   if (m->finish_deferred && m->n_pending == 1) {
     const int rc = enqueue_finish(m, false);
     if (rc) return rc;
   }
   // the report is complete once it is published; the carried list and SI
   // (ev_done) may still be in progress behind it
-  HIP_TRY(m, hipEventSynchronize(m->ev_pub[q]));
+  HIP_TRY(m, hipEventSynchronize(m->ev_pub[pe]));
   m->n_pending--;
   const HostStatus& hs = *m->h_status[q];
   const Counters c = hs.cnt;
@@ -1179,7 +1208,7 @@ int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
     collect_spans(m, false);
     return fail(m, SRLA_E_CAPACITY, "candidate list exceeds max_candidates");
   }
-  if (m->timed[q]) m->estimates++;
+  if (m->timed[pe]) m->estimates++;
   collect_spans(m, false);
   const Geo& geo = m->geo;
   for (uint32_t i = 0; i < geo.u; ++i) m->h_row_fill64[q][i] = hs.row_fill[i];

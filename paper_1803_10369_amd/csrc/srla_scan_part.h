@@ -36,12 +36,15 @@ inline uint64_t part_mark_words(uint64_t n_le) {
 // scratch serves fewer chunks per partition round (round_chunks <=
 // kPartChunks: round_chunks * kPartEntries entry words and (regions + 1) *
 // round_chunks offset words) and fewer marking workgroups per region (split
-// <= kPartSplit: regions * split * 1024 mark words).
+// <= kPartSplit: regions * split * 1024 mark words).  With ps, the last
+// workgroup of the scan's last kernel records the end of the scan (the
+// device clock) in ps->t_scan[parity].
 hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& geo,
                                  uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
                                  uint32_t* tcount, uint16_t* entries, uint16_t* offs,
                                  uint32_t* marks, hipStream_t st,
                                  uint32_t round_chunks = kPartChunks,
-                                 uint32_t split = kPartSplit);
+                                 uint32_t split = kPartSplit, PipeState* ps = nullptr,
+                                 uint32_t parity = 0);
 
 }  // namespace srla

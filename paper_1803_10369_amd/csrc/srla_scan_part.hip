@@ -277,7 +277,8 @@ __global__ __launch_bounds__(kApplyThreads) void k_scan_mark(
 __global__ __launch_bounds__(kApplyThreads) void k_scan_stamp(const uint32_t* __restrict__ marks,
                                                              uint32_t regions, uint32_t split,
                                                              uint16_t code,
-                                                             uint16_t* __restrict__ le) {
+                                                             uint16_t* __restrict__ le,
+                                                             PipeState* ps, uint32_t parity) {
   __shared__ uint32_t bm[kWords];
   const uint32_t tid = threadIdx.x, r = blockIdx.x;
   for (uint32_t w = tid; w < kWords; w += kApplyThreads) {
@@ -289,13 +290,26 @@ __global__ __launch_bounds__(kApplyThreads) void k_scan_stamp(const uint32_t* __
   const uint64_t base = (uint64_t)r << kPartLog;
   for (uint32_t c = tid; c < kPartRegion; c += kApplyThreads)
     if ((bm[c >> 5] >> (c & 31u)) & 1u) le[base + c] = code;
+  if (ps) {
+    // the workgroup that finishes last reads the clock: the end of the scan
+    __syncthreads();
+    if (tid == 0) {
+      __threadfence();
+      if (atomicAdd(&ps->scan_done[parity], 1u) == gridDim.x - 1u) {
+        ps->t_scan[parity] = wall_clock64();
+        ps->scanned[parity] = 1u;
+        ps->scan_done[parity] = 0u;
+      }
+    }
+  }
 }
 
 template <int U>
 hipError_t launch_part_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint16_t code,
                          uint16_t* le, uint16_t* re, uint32_t* touched, uint32_t* tcount,
                          uint16_t* entries, uint16_t* offs, uint32_t* marks,
-                         uint32_t round_chunks, uint32_t split, hipStream_t st) {
+                         uint32_t round_chunks, uint32_t split, PipeState* ps, uint32_t parity,
+                         hipStream_t st) {
   const uint64_t n_le = (uint64_t)geo.u * geo.v_le * geo.G;
   const uint32_t regions = (uint32_t)((n_le + kPartRegion - 1) >> kPartLog);
   const uint32_t ppc = kPartEntries / geo.u;
@@ -309,7 +323,7 @@ hipError_t launch_part_u(const uint32_t* pairs, uint64_t n, const Geo& geo, uint
     hipLaunchKernelGGL(k_scan_mark, dim3(regions, split), dim3(kApplyThreads), 0, st,
                        entries, offs, chunks, round_chunks, marks);
     hipLaunchKernelGGL(k_scan_stamp, dim3(regions), dim3(kApplyThreads), 0, st, marks, regions,
-                       split, code, le);
+                       split, code, le, p + per_round < n ? nullptr : ps, parity);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -322,7 +336,7 @@ hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& g
                                  uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
                                  uint32_t* tcount, uint16_t* entries, uint16_t* offs,
                                  uint32_t* marks, hipStream_t st, uint32_t round_chunks,
-                                 uint32_t split) {
+                                 uint32_t split, PipeState* ps, uint32_t parity) {
   if (n == 0) return hipSuccess;
   if (!part_scan_fits((uint64_t)geo.u * geo.v_le * geo.G)) return hipErrorInvalidValue;
   if (round_chunks == 0 || round_chunks > kPartChunks || split == 0 || split > kPartSplit)
@@ -330,16 +344,16 @@ hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& g
   switch (geo.u) {
     case 4:
       return launch_part_u<4>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks,
-                              round_chunks, split, st);
+                              round_chunks, split, ps, parity, st);
     case 8:
       return launch_part_u<8>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks,
-                              round_chunks, split, st);
+                              round_chunks, split, ps, parity, st);
     case 16:
       return launch_part_u<16>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks,
-                               round_chunks, split, st);
+                               round_chunks, split, ps, parity, st);
     default:
       return launch_part_u<0>(pairs, n, geo, code, le, re, touched, tcount, entries, offs, marks,
-                              round_chunks, split, st);
+                              round_chunks, split, ps, parity, st);
   }
 }
 

@@ -108,8 +108,9 @@ def test_carry_over_reports_a_quiet_super_point():
             bg = np.concatenate([bg, np.stack([np.full(part.size, aip, np.uint32), part], 1)])
         m.scan(bg)
         r = m.estimate()
-    x = np.searchsorted(r.ip, aip)
-    assert x < r.n and r.ip[x] == aip
+    hit = np.flatnonzero(r.ip == aip)     # the carried list comes first
+    assert hit.size == 1
+    x = int(hit[0])
     assert not (r.flags[x] & oracle.NEW)
     assert r.flags[x] & oracle.SUPER
     assert abs(r.est[x] - 2400) < 0.15 * 2400
@@ -167,10 +168,38 @@ def test_accuracy_against_precise_method_on_unsaturated_stream():
     ips, card = np.unique((key >> np.uint64(32)).astype(np.uint32), return_counts=True)
     truth = dict(zip(ips.tolist(), card.tolist()))
     for ip in stream.planted_ips().tolist():
-        x = np.searchsorted(r.ip, ip)
-        assert r.ip[x] == ip and truth[ip] == 2000
+        hit = np.flatnonzero(r.ip == ip)
+        assert hit.size == 1 and truth[ip] == 2000
+        x = int(hit[0])
         assert abs(r.est[x] - 2000) < 0.12 * 2000
     supers = [ip for ip, c in truth.items() if c >= mon["theta"]]
     detected = set(r.ip[(r.flags & oracle.SUPER) != 0].tolist())
     missed = [ip for ip in supers if ip not in detected]
     assert len(missed) <= max(1, len(supers) // 10)
+
+
+def test_report_lists_the_carried_candidates_then_the_new_ones():
+    """CSIP_t = NCSIP_{t-1} + N_t (Algorithms 2-3): the report lists the
+    candidates carried from the previous slice (its KEEP entries), ascending,
+    then the slice's new candidates (flag NEW), ascending; the two parts are
+    disjoint."""
+    cfg = dict(k=3, theta=64, u=2, v_re=256, g=8, v_le=32, G=128, hash_seed=31)
+    rng = np.random.default_rng(12)
+    m = oracle.Monitor(**cfg)
+    prev_keep = np.zeros(0, np.uint32)
+    seen_both = False
+    for s in range(8):
+        heavy = [_heavy(rng, 100 + 7 * h, 120) for h in range(s % 3, 12, 2)]
+        m.scan(np.concatenate([_rand_pairs(rng, 3000, 500)] + heavy))
+        r = m.estimate()
+        new = (r.flags & oracle.NEW) != 0
+        n_c = int((~new).sum())
+        assert not new[:n_c].any() and new[n_c:].all()
+        carried, news = r.ip[:n_c], r.ip[n_c:]
+        assert np.array_equal(carried, prev_keep)
+        assert np.all(np.diff(carried.astype(np.int64)) > 0)
+        assert np.all(np.diff(news.astype(np.int64)) > 0)
+        assert np.intersect1d(carried, news).size == 0
+        seen_both |= n_c > 0 and news.size > 0
+        prev_keep = np.sort(r.ip[(r.flags & oracle.KEEP) != 0])
+    assert seen_both

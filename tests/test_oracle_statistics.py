@@ -131,8 +131,9 @@ def test_union_noise_is_removed_by_eq9():
         dst = rng.choice(2 ** 32, size=n_op, replace=False).astype(np.uint32)
         m.scan(np.concatenate([bg, np.stack([np.full(n_op, aip, np.uint32), dst], 1)]))
         r = m.estimate()
-        x = int(np.searchsorted(r.ip, aip))
-        assert r.ip[x] == aip
+        hit = np.flatnonzero(r.ip == aip)
+        assert hit.size == 1
+        x = int(hit[0])
         assert 0.15 < r.up < 0.5
         corrected.append(r.est[x])
         plain.append(-G * math.log((G - r.union_weight[x]) / G))   # Eq7 without the correction
