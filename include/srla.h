@@ -105,10 +105,14 @@ enum {
                                   stamps the DRs named in it, so the LE
                                   stores fill whole cache lines instead of
                                   going out one 2-byte store at a time.
-                                  Results are identical.  Requires at most
-                                  2^25 LE DRs (u * v_le * g_le); costs 128
-                                  MiB of device scratch plus 68 KiB per
-                                  region.  Above every other scan form in
+                                  Results are identical.  Any LE: one of
+                                  more than 2^26 DRs (u * v_le * g_le) is
+                                  taken in bands of 2^26 DRs, one read of
+                                  the pairs per band.  Costs 128 MiB of
+                                  device scratch plus, for R = min(regions,
+                                  2048), 4 KiB * R (offsets) and 4 KiB * R *
+                                  min(16, 8192 / R) (bitmaps): at most 168
+                                  MiB.  Above every other scan form in
                                   precedence; no effect in the discrete
                                   form.  A group whose members all have it
                                   runs each member's partitioned scan over
@@ -283,16 +287,16 @@ int srla_scan(srla_monitor_t *m, const uint32_t *pairs, uint64_t n, int on_devic
  * memory (code under HIP stream capture, serving loops that forbid
  * hipMalloc): the same scan (results identical to srla_scan's), always in
  * the partitioned form, with its scratch -- DR-index blocks, region offsets,
- * marking bitmaps -- in one fixed library array of 24.3 MiB per device
+ * marking bitmaps -- in one fixed library array of 24.5 MiB per device
  * (allocated when the library is loaded, held until the process ends)
  * instead of memory the call or the monitor allocates.  It calls no
  * allocator, grows no buffer and records no timing events.
  * pairs: 2n uint32 values (aip, bip) in device memory readable on the
  *   monitor's stream, kept alive until the scan has run.
- * Limits (violations return SRLA_E_INVAL and change nothing): at most 2^25
- *   LE DRs (u * v_le * g_le); the slice's pairs so far plus n within the
- *   sampled-source capacity the monitor holds (2^20 pairs at creation;
- *   srla_scan grows it to the largest slice it has scanned); not for
+ * Limits (violations return SRLA_E_INVAL and change nothing): the slice's
+ *   pairs so far plus n within the sampled-source capacity the monitor
+ *   holds (2^20 pairs at creation; srla_scan grows it to the largest slice
+ *   it has scanned); any LE size (bands of 2^26 DRs as above); not for
  *   SRLA_CFG_DISCRETE or SRLA_CFG_OVERLAP_REPORT monitors.
  * All monitors on a device share its one scratch array and every call
  * leaves its own contents there: scans that overlap in time on one device

@@ -3,8 +3,7 @@
 The scan (Algorithm 2) has two knobs that never change its results: the
 kernel form (flat; per-XCD row ownership, SRLA_CFG_SCAN_XCD; read-before-write,
 SRLA_CFG_SCAN_DEDUP; both, per-XCD read-before-write; a workgroup filter of repeated
-stores, SRLA_CFG_SCAN_LDS_FILTER; the partitioned form, SRLA_CFG_SCAN_PARTITION,
-tried only where the LE has at most 2^25 DRs) and the
+stores, SRLA_CFG_SCAN_LDS_FILTER; the partitioned form, SRLA_CFG_SCAN_PARTITION) and the
 cap on its workgroups (srla_config_t.scan_blocks).
 tune_scan() times every candidate on a scratch monitor of the caller's
 geometry with the caller's pairs, one scan per slice (each timed scan meets
@@ -34,7 +33,6 @@ from . import srla
 # the trials).  They stay available as explicit options.
 DEFAULT_CANDIDATES = [("flat", 0), ("flat", 1024), ("flat", 512), ("dedup", 0),
                       ("partition", 0)]
-PARTITION_MAX_LE = 1 << 25
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "srla_autotune.json")
 
 
@@ -74,8 +72,6 @@ def tune_scan(cfg, pairs, candidates=None, repeats=3, cache=CACHE, refresh=False
         return table[key]
     results = {}
     for form, blocks in candidates or DEFAULT_CANDIDATES:
-        if form == "partition" and cfg["u"] * cfg["v_le"] * cfg["G"] > PARTITION_MAX_LE:
-            continue
         m = srla.Monitor(**cfg, max_candidates=min(1 << 22, 4 * n_pairs + 64), timing=True,
                          scan_xcd=form in ("xcd", "xcd_dedup"),
                          scan_dedup=form in ("dedup", "xcd_dedup"),

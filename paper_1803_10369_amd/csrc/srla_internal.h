@@ -83,6 +83,8 @@ struct Counters {
   uint32_t pad;
 };
 
+constexpr uint32_t kEndSlots = 64;
+
 // Device-resident state the end-of-slice pipeline reads instead of host
 // arguments, so one recorded pipeline serves every slice of a parity.
 struct PipeState {
@@ -93,14 +95,17 @@ struct PipeState {
                          // parity ended: its last scan finished (or, for a slice
                          // without scans, its end-of-slice work began)
   uint64_t t_scan[2];    // device wall clock at the end of the last scan of the
-                         // open slice of each parity
+                         // open slice of each parity (scans with a marker kernel)
   uint32_t scanned[2];   // that slice has had a scan
-  uint32_t scan_done[2]; // workgroups of the running scan's last kernel that have
-                         // finished (the last one reads the clock)
   uint32_t snap;         // stamp code of the slice snapshotted last (0: none yet);
                          // the snapshot keeps its own count so that it need not
                          // wait for the previous slice's candidate work
   uint32_t pad;
+  // the partitioned scan's last kernel: each workgroup raises slot
+  // blockIdx % kEndSlots to the clock when it is done (few workgroups per
+  // slot, so the atomics do not queue on one address); the end of the scan
+  // is the largest slot
+  unsigned long long t_end[2][kEndSlots];
 };
 
 // Pinned host block the status kernel fills at the end of every slice.

@@ -926,11 +926,25 @@ hipError_t launch_mark_scan(uint32_t* started, uint32_t value, hipStream_t st) {
   return hipGetLastError();
 }
 
+// one wavefront: the end of the closed slice's scans is the latest of the
+// marker's clock and the partitioned scan's slots, which start over at zero
 __global__ void k_begin_close(PipeState* __restrict__ ps, unsigned long long* __restrict__ row_fill,
                               uint32_t n_clear, uint32_t p) {
+  static_assert(kEndSlots == kWave, "one slot per lane");
   if (blockIdx.x != 0) return;
-  if (threadIdx.x == 0) {
-    ps->t_close[p] = ps->scanned[p] ? ps->t_scan[p] : wall_clock64();
+  const uint32_t lane = threadIdx.x;
+  unsigned long long t = ps->t_end[p][lane];
+  ps->t_end[p][lane] = 0ull;
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)t, d);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(t >> 32), d);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    t = o > t ? o : t;
+  }
+  if (lane == 0) {
+    const unsigned long long ts = ps->t_scan[p] > t ? ps->t_scan[p] : t;
+    ps->t_close[p] = ps->scanned[p] ? ts : wall_clock64();
+    ps->t_scan[p] = 0ull;
     ps->scanned[p] = 0u;
     ps->snap = ps->snap % kStampPeriod + 1u;
   }
@@ -939,7 +953,7 @@ __global__ void k_begin_close(PipeState* __restrict__ ps, unsigned long long* __
 
 hipError_t launch_begin_close(PipeState* ps, unsigned long long* row_fill, uint32_t n_clear,
                               uint32_t p, hipStream_t st) {
-  hipLaunchKernelGGL(k_begin_close, dim3(1), dim3(64), 0, st, ps, row_fill, n_clear, p);
+  hipLaunchKernelGGL(k_begin_close, dim3(1), dim3(kWave), 0, st, ps, row_fill, n_clear, p);
   return hipGetLastError();
 }
 

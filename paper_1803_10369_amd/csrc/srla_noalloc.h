@@ -4,17 +4,17 @@
 
 namespace srla {
 
-// Partition rounds of kNoAllocChunks chunks and kNoAllocSplit marking
-// workgroups per region: DR indices kNoAllocChunks * kPartEntries uint16
-// (8 MiB), region offsets (regions + 1) * kNoAllocChunks uint16 (at most
-// 257 KiB), marking bitmaps regions * kNoAllocSplit * 4 KiB (at most 16 MiB
-// for the 1024 regions of a 2^25-DR LE).
+// Partition rounds of kNoAllocChunks chunks: DR indices kNoAllocChunks *
+// kPartEntries uint16 (8 MiB), region offsets (band regions + 1) *
+// kNoAllocChunks uint16 (at most 512.3 KiB), the marking plan and unit
+// bitmaps (at most 2048 + 128 units of 8 KiB: 17 MiB); 25.5 MiB in all, for
+// an LE of any size.
 constexpr uint32_t kNoAllocChunks = 128;
-constexpr uint32_t kNoAllocSplit = 4;
-constexpr uint64_t kNoAllocEntryBytes = (uint64_t)kNoAllocChunks * kPartEntries * 2;
-constexpr uint64_t kNoAllocMarkBytes = (uint64_t)kPartMaxRegions * kNoAllocSplit * 4096;
-constexpr uint64_t kNoAllocOffsBytes = ((uint64_t)(kPartMaxRegions + 1) * kNoAllocChunks * 2 +
-                                        255) / 256 * 256;
+constexpr uint64_t kNoAllocLe = (uint64_t)kPartBandRegions << kPartLog;   // a full band
+constexpr uint64_t kNoAllocEntryBytes = part_entry_words(kNoAllocChunks) * 2;
+constexpr uint64_t kNoAllocMarkBytes = part_mark_words(kNoAllocLe, kNoAllocChunks) * 4;
+constexpr uint64_t kNoAllocOffsBytes =
+    (part_offset_words(kNoAllocLe, kNoAllocChunks) * 2 + 255) / 256 * 256;
 constexpr uint64_t kNoAllocScratchBytes = kNoAllocEntryBytes + kNoAllocMarkBytes +
                                           kNoAllocOffsBytes;
 

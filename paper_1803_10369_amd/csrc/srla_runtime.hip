@@ -89,9 +89,6 @@ bool config_ok(const srla_config_t* c) {
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   if (le / g.u / g.g_le != g.v_le || re / g.u / g.g != g.v_re) return false;
   if (le > (1ull << 40) || re > (1ull << 40)) return false;
-  if ((c->flags & SRLA_CFG_SCAN_PARTITION) && !(c->flags & SRLA_CFG_DISCRETE) &&
-      !part_scan_fits(le))
-    return false;
   return true;
 }
 
@@ -940,7 +937,7 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
   if (m->part_scan)
     return launch_scan_partition(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                                  m->tcount + p, m->part_entries, m->part_offs, m->part_marks,
-                                 m->stream, kPartChunks, kPartSplit, m->ps, (uint32_t)p);
+                                 m->stream, kPartChunks, m->ps, (uint32_t)p);
   if (m->dedup_scan)
     return launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                              m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream);
@@ -1113,8 +1110,6 @@ int srla_scan_noalloc(srla_monitor_t* m, const uint32_t* pairs, uint64_t n) {
   if (m->discrete || m->overlap_report)
     return fail(m, SRLA_E_INVAL,
                 "srla_scan_noalloc: not for discrete or overlapped-report monitors");
-  if (!part_scan_fits(m->n_le))
-    return fail(m, SRLA_E_INVAL, "srla_scan_noalloc: the LE has more than 2^25 DRs");
   const int p = (int)(m->slice & 1);
   if (m->slice_pairs[p] + n > m->touched_cap)
     return fail(m, SRLA_E_INVAL,
@@ -1126,8 +1121,7 @@ int srla_scan_noalloc(srla_monitor_t* m, const uint32_t* pairs, uint64_t n) {
   uint16_t* offs = reinterpret_cast<uint16_t*>(base + kNoAllocEntryBytes + kNoAllocMarkBytes);
   HIP_TRY(m, launch_scan_partition(pairs, n, m->geo, stamp_code(m->slice), m->le, m->re,
                                    m->touched[p], m->tcount + p, entries, offs, marks,
-                                   m->stream, kNoAllocChunks, kNoAllocSplit, m->ps,
-                                   (uint32_t)p));
+                                   m->stream, kNoAllocChunks, m->ps, (uint32_t)p));
   m->slice_pairs[p] += n;
   return SRLA_OK;
 }

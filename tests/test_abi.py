@@ -181,23 +181,33 @@ def test_admission_is_first_fit_under_the_budget(P):
     assert P.srla_admit([cfgs[0], bad], budget)[0] == -1
 
 
-def test_partition_scan_needs_a_small_enough_le(P):
-    """The partitioned scan takes at most 2^25 LE DRs (1024 regions of 2^15)
-    and counts its scratch in the footprint."""
+def test_partition_scan_scratch_in_the_footprint(P):
+    """The partitioned scan takes any LE, in bands of at most 2048 regions of
+    2^16 DRs, and counts its scratch in the footprint: 128 MiB of DR indices,
+    (R + 1) * 2048 16-bit region offsets for the R regions of the largest
+    band, the marking plan (2 * 2048 + 2 words, rounded up to 256 bytes) and
+    R + 2048 unit bitmaps of 8 KiB (a round of 2048 chunks makes at most
+    R + 2048 units)."""
     part = P.srla.SRLA_CFG_SCAN_PARTITION
-    plain = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1)
-    cfg = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1, flags=part)
-    extra = P.srla_footprint_bytes(cfg) - P.srla_footprint_bytes(plain)
-    assert extra == 2 * (2048 * 32768 + (512 + 1) * 2048) + 4 * 512 * 16 * 1024
-    big = P.make_config(300, 1024, 4, 65536, 8, 65536, 1024, 1, max_candidates=1, flags=part)
-    assert P.srla_footprint_bytes(big) == 0
-    # the limit itself: 2^25 LE DRs are accepted, one more LE is not
-    edge = P.make_config(3, 1024, 1, 64, 8, 32768, 1024, 1, max_candidates=1, flags=part)
-    assert P.srla_footprint_bytes(edge) > 0
-    over = P.make_config(3, 1024, 1, 64, 8, 32769, 1024, 1, max_candidates=1, flags=part)
-    assert P.srla_footprint_bytes(over) == 0
-    rc, h = P.srla_create(big)
-    assert rc == -1 and not h.value
+
+    def extra(*geo):
+        plain = P.make_config(*geo, max_candidates=1)
+        cfg = P.make_config(*geo, max_candidates=1, flags=part)
+        return P.srla_footprint_bytes(cfg) - P.srla_footprint_bytes(plain)
+
+    def scratch(regions):
+        return (2 * 2048 * 32768 + 2 * (regions + 1) * 2048 +
+                4 * (4160 + (regions + 2048) * 2048))
+
+    # backbone: 2^24 LE DRs, 256 regions in one band
+    assert extra(300, 1024, 8, 131072, 8, 2048, 1024, 1) == scratch(256)
+    # the paper's SEA: 2^28 LE DRs, two bands of 2048 regions
+    assert extra(300, 1024, 4, 65536, 8, 65536, 1024, 1) == scratch(2048)
+    # a ragged last region: 2^25 + 2^10 DRs in 513 regions
+    assert extra(3, 1024, 1, 64, 8, 32769, 1024, 1) == scratch(513)
+    # beyond 2^32 LE DRs
+    big = P.make_config(2, 1024, 2, 4096, 8, (1 << 21) + 3, 1024, 1, max_candidates=1, flags=part)
+    assert P.srla_footprint_bytes(big) > 2 * ((1 << 32) + 6144)
     # the discrete form has no LE stamps: the flag has no effect there
     disc = P.make_config(1, 1024, 4, 65536, 8, 65536, 1024, 1, max_candidates=1,
                          flags=part | P.srla.SRLA_CFG_DISCRETE)

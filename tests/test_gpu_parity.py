@@ -747,11 +747,19 @@ def test_partition_scan_backbone_full_size_and_expiry():
     _run(stream, mon, range(20), max_candidates=1 << 22, dump_every=7, scan_partition=True)
 
 
-def test_partition_scan_at_its_largest_le():
-    """2^25 LE DRs: the most regions (1024) the partitioned scan takes."""
-    mon = dict(k=3, theta=1024, u=8, v_re=4096, g=8, v_le=4096, G=1024, hash_seed=4242)
-    _run(_rand_stream(4242, 300_000, 50_000, 1536), mon, range(3), max_candidates=1 << 20,
-         scan_partition=True)
+@pytest.mark.parametrize("u,v_le,G", [
+    (8, 4096, 1024),           # 2^25 LE DRs: 512 regions in one band
+    (2, 65536, 1024),          # 2^27: one full band of 2048 regions
+    (4, 65536, 1024),          # the paper's SEA, 2^28: two bands of two rows
+    (3, (1 << 17) + 1, 512),   # 3 * (2^26 + 512): a row straddles the bands,
+                               # the second band has a ragged last region
+])
+def test_partition_scan_in_bands(u, v_le, G):
+    """LEs of one band and of several (2^27 DRs each): the rows reaching into
+    a band are hashed for it, the first band's pass does the SRE stores."""
+    mon = dict(k=3, theta=1024, u=u, v_re=4096, g=8, v_le=v_le, G=G, hash_seed=4242 + u)
+    _run(_rand_stream(4242, 300_000, 50_000, 1536), mon, range(4), max_candidates=1 << 20,
+         dump_every=2, scan_partition=True)
 
 
 @pytest.mark.parametrize("all_partitioned", [True, False])

@@ -10,7 +10,8 @@
   grid;
 * one member of each distinct geometry of the batched workload (16 monitors
   over one stream, both group scan forms) for 40 slices;
-* an LE of more than 2^32 DRs (64-bit DR indices) with the flat scan;
+* an LE of more than 2^32 DRs (64-bit DR indices) with the flat and the
+  partitioned scan;
 * discrete slices whose sampled sources overflow the source set.
 
 Pairs are produced by the device twin of the stream generator and copied
@@ -226,14 +227,16 @@ def test_batched_members_of_each_geometry_40_slices(scan_partition):
         gm.close()
 
 
-def test_le_beyond_2_32_drs_flat_scan():
+@pytest.mark.parametrize("scan_partition", [False, True])
+def test_le_beyond_2_32_drs(scan_partition):
     """u = 2 rows of (2^21 + 3) LEs of 1024 DRs: 2^32 + 6144 LE DRs, so DR
-    indices, the row fills and the activity bitmap need 64 bits."""
+    indices, the row fills and the activity bitmap need 64 bits; the flat
+    scan, and the partitioned scan in 33 bands (each row reaches into 17)."""
     mon = dict(k=2, theta=1024, u=2, v_re=4096, g=8, v_le=(1 << 21) + 3, G=1024,
                hash_seed=0x2_0000_0001)
     stream, _, _ = workload("tiny")
     stream = scaled(stream, 1_000_000)
-    g = srla.Monitor(**mon, max_candidates=1 << 20)
+    g = srla.Monitor(**mon, max_candidates=1 << 20, scan_partition=scan_partition)
     o = oracle.Monitor(**mon)
     ot = OracleThread()
     for s in range(3):

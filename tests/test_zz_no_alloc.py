@@ -47,10 +47,13 @@ def _same_state(ma, mb, ctx):
     # u = 8: 4096 pairs per chunk, 524,288 per partition round of the fixed
     # scratch, so the first call takes two rounds
     (8, 2048, [(900_000,), (200_000,)]),
-    # u = 3 (the generic row loop), 384 regions; a slice in two calls
+    # u = 3 (the generic row loop), 192 regions; a slice in two calls
     (3, 4096, [(700_000, 100_000), (50_000,)]),
-    # the largest LE the entry point takes: 2^25 DRs, 1024 regions
+    # 2^25 DRs, 512 regions in one band
     (4, 8192, [(1_000_000,), (300_000,)]),
+    # 2^28 + 2^12 DRs (the paper's SEA geometry plus one LE per row): three
+    # bands of up to 2048 regions, the last of one region; rows straddle bands
+    (4, 65537, [(600_000,), (200_000,)]),
 ])
 def test_noalloc_scan_matches_srla_scan(u, v_le, sizes):
     stream, _, _ = workload("tiny")
@@ -76,13 +79,10 @@ def test_noalloc_scan_matches_srla_scan(u, v_le, sizes):
 
 
 def test_noalloc_scan_rejects_what_it_cannot_hold():
-    """Beyond 2^25 LE DRs, beyond the sampled-source capacity, or on a
-    discrete monitor: SRLA_E_INVAL and nothing scanned."""
+    """Beyond the sampled-source capacity or on a discrete monitor:
+    SRLA_E_INVAL and nothing scanned."""
     stream, _, _ = workload("tiny")
     p = to_device(scaled(stream, 1000).slice(0))
-    big = srla.Monitor(k=2, theta=256, u=4, v_re=1024, g=8, v_le=8193, G=1024, hash_seed=1)
-    assert _noalloc(big, p) == srla.SRLA_E_INVAL
-    big.close()
     disc = srla.Monitor(k=1, theta=256, u=4, v_re=1024, g=8, v_le=64, G=1024, hash_seed=2,
                         discrete=True)
     assert _noalloc(disc, p) == srla.SRLA_E_INVAL
