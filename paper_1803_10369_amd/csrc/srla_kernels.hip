@@ -353,7 +353,15 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict_
     }
     firsts += (uint32_t)__popcll(__ballot(first));
   }
-  if (__lane_id() == 0 && firsts) atomicAdd(&cnt->n_unique, firsts);
+  // one add per workgroup to the shared counter
+  __shared__ uint32_t part[kBlock / kWave];
+  if (__lane_id() == 0) part[threadIdx.x / kWave] = firsts;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
+    if (t) atomicAdd(&cnt->n_unique, t);
+  }
 }
 
 hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const uint64_t* act,
@@ -407,14 +415,24 @@ hipError_t launch_join(const PipeState* ps, const uint32_t* news, Counters* cnt,
 // merges the two by merge path (each thread writes kMergePer outputs after
 // one binary search along its diagonal).
 
+// A few workgroups, 16 flags per load: every workgroup adds its count to
+// one counter, and such adds queue up behind each other.
+constexpr uint32_t kCountKeepBlocks = 64;
+
 __global__ __launch_bounds__(kBlock) void k_count_keep(const uint8_t* __restrict__ cflags,
                                                       const PipeState* __restrict__ ps,
                                                       Counters* __restrict__ cnt) {
   const uint64_t n_c = ps->n_ncsip < cnt->n_cand ? ps->n_ncsip : cnt->n_cand;
+  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   uint32_t c = 0;
-  for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < n_c;
-       k += (uint64_t)gridDim.x * kBlock)
-    c += (cflags[k] & 8u) ? 1u : 0u;
+  const uint4* f4 = reinterpret_cast<const uint4*>(cflags);
+  for (uint64_t q = t; q < n_c / 16; q += stride) {
+    const uint4 v = f4[q];
+    c += __popc(v.x & 0x08080808u) + __popc(v.y & 0x08080808u) + __popc(v.z & 0x08080808u) +
+         __popc(v.w & 0x08080808u);
+  }
+  for (uint64_t k = n_c / 16 * 16 + t; k < n_c; k += stride) c += (cflags[k] & 8u) ? 1u : 0u;
   for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
   __shared__ uint32_t part[kBlock / kWave];
   if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = c;
@@ -428,7 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_count_keep(const uint8_t* __restrict
 
 hipError_t launch_count_keep(const uint8_t* cflags, const PipeState* ps, Counters* cnt,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_count_keep, dim3(kPipeBlocks), dim3(kBlock), 0, st, cflags, ps, cnt);
+  hipLaunchKernelGGL(k_count_keep, dim3(kCountKeepBlocks), dim3(kBlock), 0, st, cflags, ps, cnt);
   return hipGetLastError();
 }
 
