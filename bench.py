@@ -604,7 +604,7 @@ def main():
             else:
                 ds.generate(first + i, out=seg_bufs[i], stream=st)
         torch.cuda.synchronize()
-        lat, host_lat, cands, full = [], [], [], []
+        lat, host_lat, cands, full, news = [], [], [], [], []
         r = None
         t0 = time.perf_counter()
         if mode == "plain":
@@ -616,6 +616,7 @@ def main():
                 host_lat.append((time.perf_counter() - ts) * 1e3)
                 lat.append(r.latency_ms)
                 cands.append(int(r.n))
+                news.append(int(r.n_new))
                 full.append(bool(r.window_full))
         else:
             # the host runs ahead: slice i is closed and slice i+1's scan is
@@ -633,22 +634,24 @@ def main():
                 r = m.wait_report(copy=False)
                 lat.append(r.latency_ms)
                 cands.append(int(r.n))
+                news.append(int(r.n_new))
                 full.append(bool(r.window_full))
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, lat, host_lat, cands, full, r
+        return time.perf_counter() - t0, lat, host_lat, cands, full, r, news
 
     class Timed:
         """What one form's timed slices add up to."""
 
         def __init__(self):
             self.total, self.lat, self.host_lat, self.cands, self.full = 0.0, [], [], [], []
-            self.r, self.tm, self.done, self.slices = None, {}, 0, []
+            self.r, self.tm, self.done, self.slices, self.news = None, {}, 0, [], []
 
-        def add(self, dt, l, hl, c, f, r, tm, first, n):
+        def add(self, dt, l, hl, c, f, r, tm, first, n, nw):
             self.total += dt
             self.lat += l
             self.host_lat += hl
             self.cands += c
+            self.news += nw
             self.full += f
             self.r = r
             for k, v in tm.items():
@@ -673,8 +676,8 @@ def main():
             if t.done >= steps:
                 continue
             n = min(args.block, args.segment, steps - t.done)
-            dt, l, hl, c, f, r = segment(mode, first, n)
-            t.add(dt, l, hl, c, f, r, m.timings(reset=True), first, n)
+            dt, l, hl, c, f, r, nw = segment(mode, first, n)
+            t.add(dt, l, hl, c, f, r, m.timings(reset=True), first, n, nw)
             first += n
             print("%s: timed %d/%d slices (%.2fs)" % (mode, t.done, steps, t.total),
                   file=sys.stderr, flush=True)
@@ -765,8 +768,13 @@ def main():
         out["p50_host_ms"] = float(np.percentile(host_lat, 50)) if len(host_lat) else None
 
     # the report's delivery: the candidate work's phase writes 13 (or 18) bytes
-    # per candidate into pinned host memory over PCIe
-    rep_bytes = (18 if args.full_report else 13) * float(np.mean(cands))
+    # per new candidate into pinned host memory over PCIe, and 9 (or 14) per
+    # carried one, whose address went to the host beside the slice's scans
+    # (all 13 / 18 in the overlapped-report form, which copies the whole report)
+    per_cand = 18 if args.full_report else 13
+    n_cand, n_new = float(np.mean(cands)), float(np.mean(main_run.news))
+    rep_bytes = (per_cand * n_cand if overlap else
+                 (per_cand - 4) * (n_cand - n_new) + per_cand * n_new)
     est_ms = stages["estimate_ms"]
     import probe
     pcie = probe.host_write_rate()
@@ -774,6 +782,7 @@ def main():
         "kernel": "k_estimate (Eq9, report into pinned host memory) with the candidate check "
                   "before it (one timed phase)",
         "bound": "pcie", "bytes_per_slice": rep_bytes, "phase_ms": est_ms,
+        "candidates_mean": n_cand, "new_candidates_mean": n_new,
         "achieved_GBps": rep_bytes / (est_ms * 1e-3) / 1e9 if est_ms > 0 else None,
         "ceiling_GBps": pcie / 1e9,
         "ceiling_source": "measured: coalesced kernel stores into pinned host memory",

@@ -101,17 +101,19 @@ enum {
                                   a group */,
     SRLA_CFG_SCAN_PARTITION = 256 /* scan in partitioned form: each chunk of
                                   pairs sorts its LE DR indices by region
-                                  of 2^15 DRs, then one workgroup per region
-                                  stamps the DRs named in it, so the LE
+                                  of 2^16 DRs, then workgroups (units of
+                                  about 32768 indices of one region) mark
+                                  the DRs named in them and one workgroup
+                                  per half region stamps them, so the LE
                                   stores fill whole cache lines instead of
                                   going out one 2-byte store at a time.
                                   Results are identical.  Any LE: one of
-                                  more than 2^26 DRs (u * v_le * g_le) is
-                                  taken in bands of 2^26 DRs, one read of
+                                  more than 2^27 DRs (u * v_le * g_le) is
+                                  taken in bands of 2^27 DRs, one read of
                                   the pairs per band.  Costs 128 MiB of
                                   device scratch plus, for R = min(regions,
-                                  2048), 4 KiB * R (offsets) and 4 KiB * R *
-                                  min(16, 8192 / R) (bitmaps): at most 168
+                                  2048), 4 KiB * (R + 1) (offsets) and 8 KiB
+                                  * (R + 2048) (unit bitmaps): at most 168
                                   MiB.  Above every other scan form in
                                   precedence; no effect in the discrete
                                   form.  A group whose members all have it
