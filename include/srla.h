@@ -159,8 +159,11 @@ typedef struct {
  *   flags           SRLA_CFG_* bits
  *   scan_blocks     launch-shape knob of the scan kernel: the most
  *                   workgroups one scan launch uses (they stride over the
- *                   pairs); 0 = one workgroup per tile of 2048 pairs.
- *                   Results do not depend on it.
+ *                   pairs); 0 = one workgroup per tile of 2048 pairs.  With
+ *                   SRLA_CFG_SCAN_PARTITION: the DR indices per marking unit
+ *                   (a power of two from 8192 to 131072; 0 = 32768), whose
+ *                   bitmaps (8 KiB each, at most R + 2^26 / unit of them)
+ *                   count in the scratch.  Results do not depend on it.
  */
 typedef struct {
     uint32_t window_slices;
@@ -178,7 +181,9 @@ typedef struct srla_monitor srla_monitor_t;
  * (window_full == 0 while e < k-1).  Arrays are pinned host memory owned by
  * the library, written by its kernels (three sets, used by slices in turn);
  * they stay valid until slice e+2 is closed (srla_close_slice or
- * srla_estimate) or srla_destroy.
+ * srla_estimate) or srla_destroy.  They are read-only for the caller: the
+ * library keeps a device copy of what each set's est and flags hold and
+ * writes only the entries that change (except with SRLA_CFG_OVERLAP_REPORT).
  *   ip            the candidate list CSIP = NCSIP + N (Algorithms 2-3): the
  *                 candidates carried from slice e-1, ascending, then the new
  *                 candidates of slice e (flag NEW), ascending

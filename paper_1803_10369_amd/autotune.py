@@ -31,8 +31,10 @@ from . import srla
 # (per-XCD: 985 us against 710 us for the flat form, as every pair is read
 # once per XCD group; the filter: 870 us against 720 us, though 1 % ahead in
 # the trials).  They stay available as explicit options.
+# for the partitioned form the knob is the marking unit (DR indices per
+# marking workgroup; 0 = 32768)
 DEFAULT_CANDIDATES = [("flat", 0), ("flat", 1024), ("flat", 512), ("dedup", 0),
-                      ("partition", 0)]
+                      ("partition", 0), ("partition", 16384), ("partition", 65536)]
 CACHE = os.path.join(os.path.expanduser("~"), ".cache", "srla_autotune.json")
 
 

@@ -118,13 +118,18 @@ struct HostStatus {
   uint64_t t_done;       //   and the report was complete in host memory
 };
 
-// Report arrays in pinned host memory, as device-visible pointers.
+// Report arrays in pinned host memory, as device-visible pointers.  With
+// mir_est / mir_flags (device copies of what the host arrays of this set
+// hold), the estimate writes into host memory only the 16-byte pieces whose
+// contents change.
 struct ReportPtrs {
   uint32_t* ip;
   double* est;
   uint8_t* flags;
   uint32_t* U;
   uint8_t* W;
+  double* mir_est;
+  uint8_t* mir_flags;
 };
 
 // One member of a monitor group, as the fused scan kernel sees it.

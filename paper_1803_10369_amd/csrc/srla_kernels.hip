@@ -576,7 +576,8 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
     const double* __restrict__ up_p, const unsigned long long* __restrict__ row_fill, Geo geo,
     uint32_t lg_log2, uint8_t* __restrict__ cflags, uint32_t* __restrict__ out_ip,
     double* __restrict__ out_est, uint8_t* __restrict__ out_flags, uint32_t* __restrict__ out_U,
-    uint8_t* __restrict__ out_W) {
+    uint8_t* __restrict__ out_W, double* __restrict__ mir_est,
+    uint8_t* __restrict__ mir_flags) {
   __shared__ uint32_t s_ip[kEstPerBlock], s_U[kEstPerBlock];
   __shared__ uint8_t s_W[kEstPerBlock], s_Wn[kEstPerBlock];
   __shared__ __align__(16) double s_e[kEstPerBlock];
@@ -719,15 +720,48 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
       } else if (base + t >= ip_from) {
         out_ip[base + t] = s_ip[t];
       }
-      if (t < kEstPerBlock / 2)
-        reinterpret_cast<uint4*>(out_est + base)[t] = reinterpret_cast<const uint4*>(s_e)[t];
-      if (t < kEstPerBlock / 16)
-        reinterpret_cast<uint4*>(out_flags + base)[t] = reinterpret_cast<const uint4*>(s_f)[t];
+      // with the mirrors, a piece goes to host memory only if it differs
+      // from what the host array holds there (the mirror), and the mirror
+      // follows
+      if (t < kEstPerBlock / 2) {
+        const uint4 v = reinterpret_cast<const uint4*>(s_e)[t];
+        if (mir_est) {
+          uint4* mp = reinterpret_cast<uint4*>(mir_est + base) + t;
+          const uint4 o = *mp;
+          if (o.x != v.x || o.y != v.y || o.z != v.z || o.w != v.w) {
+            reinterpret_cast<uint4*>(out_est + base)[t] = v;
+            *mp = v;
+          }
+        } else {
+          reinterpret_cast<uint4*>(out_est + base)[t] = v;
+        }
+      }
+      if (t < kEstPerBlock / 16) {
+        const uint4 v = reinterpret_cast<const uint4*>(s_f)[t];
+        if (mir_flags) {
+          uint4* mp = reinterpret_cast<uint4*>(mir_flags + base) + t;
+          const uint4 o = *mp;
+          if (o.x != v.x || o.y != v.y || o.z != v.z || o.w != v.w) {
+            reinterpret_cast<uint4*>(out_flags + base)[t] = v;
+            *mp = v;
+          }
+        } else {
+          reinterpret_cast<uint4*>(out_flags + base)[t] = v;
+        }
+      }
     } else if (threadIdx.x < in_batch) {
       const uint64_t gid = base + threadIdx.x;
       if (gid >= ip_from) out_ip[gid] = s_ip[threadIdx.x];
-      out_est[gid] = s_e[threadIdx.x];
-      out_flags[gid] = s_f[threadIdx.x];
+      const double e = s_e[threadIdx.x];
+      const uint8_t f = s_f[threadIdx.x];
+      if (!mir_est || __double_as_longlong(mir_est[gid]) != __double_as_longlong(e)) {
+        out_est[gid] = e;
+        if (mir_est) mir_est[gid] = e;
+      }
+      if (!mir_flags || mir_flags[gid] != f) {
+        out_flags[gid] = f;
+        if (mir_flags) mir_flags[gid] = f;
+      }
     }
     lds_barrier();
   }
@@ -770,7 +804,7 @@ static hipError_t launch_estimate_u(const uint32_t* csip, const Counters* cnt,
   hipLaunchKernelGGL((k_estimate<kU, kWpl>), dim3(grid), dim3(kBlock), 0, st, csip, cnt, ps,
                      skip, bitmap,
                      act, up, row_fill, geo, l, cflags, out.ip, out.est, out.flags,
-                     out.U, out.W);
+                     out.U, out.W, out.mir_est, out.mir_flags);
   return hipGetLastError();
 }
 

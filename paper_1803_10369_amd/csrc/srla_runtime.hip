@@ -89,7 +89,16 @@ bool config_ok(const srla_config_t* c) {
   const uint64_t re = (uint64_t)g.u * g.v_re * g.g;
   if (le / g.u / g.g_le != g.v_le || re / g.u / g.g != g.v_re) return false;
   if (le > (1ull << 40) || re > (1ull << 40)) return false;
+  // the partitioned form reads scan_blocks as its marking unit
+  if ((c->flags & SRLA_CFG_SCAN_PARTITION) && !(c->flags & SRLA_CFG_DISCRETE) &&
+      c->scan_blocks != 0 && !part_unit_ok(c->scan_blocks))
+    return false;
   return true;
+}
+
+// DR indices per marking unit of a partitioned-scan monitor
+uint32_t part_unit_of(const srla_config_t* c) {
+  return (c->flags & SRLA_CFG_SCAN_PARTITION) && c->scan_blocks ? c->scan_blocks : kPartUnit;
 }
 
 enum Stage { ST_SCAN, ST_SWEEP, ST_FINALIZE, ST_ESTIMATE, ST_SLIDE, ST_REPORT, ST_N };
@@ -123,6 +132,8 @@ struct srla_monitor {
   Geo geo{};
   hipStream_t stream = nullptr;  // scans
   hipStream_t pipe = nullptr;    // end-of-slice pipeline (library-owned)
+  hipStream_t pipe_use = nullptr;  // where the pipeline runs: pipe, or the
+                                   // stream a group's members share
   int device = -1;               // the HIP device the monitor was created on
   bool pipe_own = false, copy_own = false;   // on a hardware queue of their own
   bool own_stream = false;
@@ -188,6 +199,10 @@ struct srla_monitor {
   uint32_t* h_ip[kSets] = {};
   double* h_est[kSets] = {};
   uint8_t* h_flags[kSets] = {};
+  // device copies of what h_est / h_flags hold (not with the overlapped
+  // report): the estimate writes only the pieces that change
+  double* d_mir_est[kSets] = {};
+  uint8_t* d_mir_flags[kSets] = {};
   uint32_t* h_U[kSets] = {};
   uint8_t* h_W[kSets] = {};
   ReportPtrs d_report[kSets] = {};
@@ -230,6 +245,8 @@ struct srla_monitor {
   bool filter_scan = false;
   bool part_scan = false;
   bool hold_scans = false;       // scans wait for the closed slice's report
+  bool hold_pending = false;     // the next scan waits for ev_pub[hold_parity]
+  int hold_parity = 0;
   std::vector<TimedSpan> spans;
   std::vector<hipEvent_t> ev_pool;
   double acc_ms[ST_N] = {0, 0, 0, 0, 0, 0};
@@ -302,7 +319,21 @@ hipError_t wait_unless_done(hipStream_t st, hipEvent_t ev) {
   return hipStreamWaitEvent(st, ev, 0);
 }
 
+// SRLA_CFG_HOLD_SCANS: the first scan after a close waits (on stream st) for
+// the closed slice's report to be published
+hipError_t apply_hold(srla_monitor* m, hipStream_t st) {
+  if (!m->hold_pending) return hipSuccess;
+  m->hold_pending = false;
+  return hipStreamWaitEvent(st, m->ev_pub[m->hold_parity], 0);
+}
+
 uint64_t bitmap_words(uint64_t cells) { return (cells + 63) / 64 + 1; }
+
+// device copies of the host report sets' est and flags arrays (9 bytes per
+// candidate and set), except with the overlapped report
+uint64_t mirror_bytes(const srla_config_t* cfg) {
+  return (cfg->flags & SRLA_CFG_OVERLAP_REPORT) ? 0 : (uint64_t)kSets * cfg->max_candidates * 9;
+}
 
 // slots of the discrete form's sampled-source set: the power of two at least
 // twice max_candidates (a slice's distinct sampled sources are its new
@@ -418,7 +449,7 @@ int reserve_touched(srla_monitor* m, uint64_t need) {
   }
   // both streams idle: the pending pipeline may still read the other parity
   HIP_TRY(m, hipStreamSynchronize(m->stream));
-  HIP_TRY(m, hipStreamSynchronize(m->pipe));
+  HIP_TRY(m, hipStreamSynchronize(m->pipe_use));
   uint32_t* fresh[2] = {t0, t1};
   for (int p = 0; p < 2; ++p) {
     if (m->touched[p] && m->slice_pairs[p])
@@ -633,6 +664,7 @@ int run_phase(srla_monitor* m, int phase, int c, hipStream_t st) {
 void release(srla_monitor* m) {
   if (!m) return;
   if (m->stream) (void)hipStreamSynchronize(m->stream);
+  if (m->pipe_use && m->pipe_use != m->pipe) (void)hipStreamSynchronize(m->pipe_use);
   if (m->pipe) (void)hipStreamSynchronize(m->pipe);
   collect_spans(m, true);
   drop_graphs(m);
@@ -655,6 +687,7 @@ void release(srla_monitor* m) {
   dfree(m->report_n);
   for (int q = 0; q < kSets; ++q) {
     hfree(m->h_status[q]); hfree(m->h_ip[q]); hfree(m->h_est[q]); hfree(m->h_flags[q]);
+    dfree(m->d_mir_est[q]); dfree(m->d_mir_flags[q]);
     hfree(m->h_U[q]); hfree(m->h_W[q]);
     delete[] m->h_row_fill64[q];
   }
@@ -693,13 +726,14 @@ uint64_t srla_footprint_bytes(const srla_config_t* cfg) {
   if (cfg->flags & SRLA_CFG_DISCRETE)
     return 16 * bitmap_words(le) + 32 * bitmap_words(re) +
            16 * (uint64_t)source_set_slots(cfg->max_candidates) + 64 * si + 16 * g.u + 16 +
-           staging_bytes(cfg) +
+           staging_bytes(cfg) + mirror_bytes(cfg) +
            sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 + candidate_bytes(cfg->max_candidates);
   const uint64_t part = (cfg->flags & SRLA_CFG_SCAN_PARTITION)
                             ? 2 * (part_entry_words() + part_offset_words(le)) +
-                                  4 * part_mark_words(le)
+                                  4 * part_mark_words(le, kPartChunks, part_unit_of(cfg))
                             : 0;
-  return part + staging_bytes(cfg) + 2 * le + 16 * bitmap_words(le) + 2 * (re + 8) +
+  return part + staging_bytes(cfg) + mirror_bytes(cfg) + 2 * le + 16 * bitmap_words(le) +
+         2 * (re + 8) +
          32 * bitmap_words(re) + 64 * si + 16 * g.u + 16 * kFillSlots * g.u + 16 + sizeof(Counters) + sizeof(PipeState) + 8 + 8 + 8 +
          candidate_bytes(cfg->max_candidates);
 }
@@ -777,6 +811,7 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     release(m);
     return SRLA_E_DEVICE;
   }
+  m->pipe_use = m->pipe;
   {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {
@@ -814,7 +849,8 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     }
     if (!rc && m->part_scan) nomem(dalloc(&m->part_entries, part_entry_words()));
     if (!rc && m->part_scan) nomem(dalloc(&m->part_offs, part_offset_words(m->n_le)));
-    if (!rc && m->part_scan) nomem(dalloc(&m->part_marks, part_mark_words(m->n_le)));
+    if (!rc && m->part_scan)
+      nomem(dalloc(&m->part_marks, part_mark_words(m->n_le, kPartChunks, part_unit_of(&m->cfg))));
   }
   if (!rc) nomem(dalloc(&m->si_cnt, 16 * m->n_si));
   for (int i = 0; i < 2 && !rc; ++i) {
@@ -853,6 +889,20 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     if (!rc) {
       m->h_row_fill64[q] = new (std::nothrow) uint64_t[g.u];
       if (!m->h_row_fill64[q]) rc = SRLA_E_NOMEM;
+    }
+    // the host arrays and their device copies start out equal (all zero)
+    if (!rc) {
+      std::memset(m->h_est[q], 0, m->cap * sizeof(double));
+      std::memset(m->h_flags[q], 0, m->cap);
+    }
+    if (!rc && !m->overlap_report) {
+      nomem(dalloc(&m->d_mir_est[q], m->cap));
+      if (!rc) nomem(dalloc(&m->d_mir_flags[q], m->cap));
+      if (!rc && (hipMemset(m->d_mir_est[q], 0, m->cap * sizeof(double)) != hipSuccess ||
+                  hipMemset(m->d_mir_flags[q], 0, m->cap) != hipSuccess))
+        rc = SRLA_E_DEVICE;
+      m->d_report[q].mir_est = m->d_mir_est[q];
+      m->d_report[q].mir_flags = m->d_mir_flags[q];
     }
     if (!rc && (dev_view(m->h_status[q], &m->d_status[q]) != hipSuccess ||
                 dev_view(m->h_ip[q], &m->d_report[q].ip) != hipSuccess ||
@@ -937,7 +987,8 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
   if (m->part_scan)
     return launch_scan_partition(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                                  m->tcount + p, m->part_entries, m->part_offs, m->part_marks,
-                                 m->stream, kPartChunks, m->ps, (uint32_t)p);
+                                 m->stream, kPartChunks, m->ps, (uint32_t)p,
+                                 part_unit_of(&m->cfg));
   if (m->dedup_scan)
     return launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                              m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream);
@@ -972,25 +1023,25 @@ int enqueue_finish(srla_monitor* m, bool go) {
   hipEvent_t ta;
   if (!m->overlap_report) {
     // the sort needs the slice's scans only: it runs beside the snapshot
-    HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_scanned, 0));
-    if (m->use_graph) span_begin(m, m->pipe, &ta);
-    const int rs = run_phase(m, PH_SORT, cc, m->pipe);
+    HIP_TRY(m, hipStreamWaitEvent(m->pipe_use, m->ev_scanned, 0));
+    if (m->use_graph) span_begin(m, m->pipe_use, &ta);
+    const int rs = run_phase(m, PH_SORT, cc, m->pipe_use);
     if (rs) return rs;
-    if (m->use_graph) span_end(m, m->pipe, ST_FINALIZE, ta);
+    if (m->use_graph) span_end(m, m->pipe_use, ST_FINALIZE, ta);
   }
-  HIP_TRY(m, hipStreamWaitEvent(m->pipe, m->ev_snap, 0));
-  if (m->use_graph) span_begin(m, m->pipe, &ta);
-  int rc = run_phase(m, go ? PH_FINISH_GO : PH_FINISH, cc, m->pipe);
+  HIP_TRY(m, hipStreamWaitEvent(m->pipe_use, m->ev_snap, 0));
+  if (m->use_graph) span_begin(m, m->pipe_use, &ta);
+  int rc = run_phase(m, go ? PH_FINISH_GO : PH_FINISH, cc, m->pipe_use);
   if (rc) return rc;
-  if (m->use_graph) span_end(m, m->pipe, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
-  HIP_TRY(m, hipEventRecord(m->ev_pub[pc], m->pipe));
+  if (m->use_graph) span_end(m, m->pipe_use, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
+  HIP_TRY(m, hipEventRecord(m->ev_pub[pc], m->pipe_use));
   if (!m->overlap_report) {
-    if (m->use_graph) span_begin(m, m->pipe, &ta);
-    rc = run_phase(m, PH_SLIDE, cc, m->pipe);
+    if (m->use_graph) span_begin(m, m->pipe_use, &ta);
+    rc = run_phase(m, PH_SLIDE, cc, m->pipe_use);
     if (rc) return rc;
-    if (m->use_graph) span_end(m, m->pipe, ST_SLIDE, ta);
+    if (m->use_graph) span_end(m, m->pipe_use, ST_SLIDE, ta);
   }
-  HIP_TRY(m, hipEventRecord(m->ev_done[pc], m->pipe));
+  HIP_TRY(m, hipEventRecord(m->ev_done[pc], m->pipe_use));
   m->finish_deferred = false;
   return SRLA_OK;
 }
@@ -1017,6 +1068,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   const int p = (int)(m->slice & 1);
   int rc = reserve_touched(m, m->slice_pairs[p] + n);
   if (rc) return rc;
+  HIP_TRY(m, apply_hold(m, m->stream));
   // the first scan after an overlapped close sets the scan-start mark; the
   // deferred second phase of the closed slice is enqueued after it, and its
   // report copy waits for the mark (see enqueue_finish)
@@ -1116,6 +1168,7 @@ int srla_scan_noalloc(srla_monitor_t* m, const uint32_t* pairs, uint64_t n) {
                 "srla_scan_noalloc: the slice's pairs exceed the sampled-source capacity");
   uint8_t* base = static_cast<uint8_t*>(noalloc_scratch(m->device));
   if (!base) return fail(m, SRLA_E_DEVICE, "srla_scan_noalloc: no scratch on this device");
+  HIP_TRY(m, apply_hold(m, m->stream));
   uint16_t* entries = reinterpret_cast<uint16_t*>(base);
   uint32_t* marks = reinterpret_cast<uint32_t*>(base + kNoAllocEntryBytes);
   uint16_t* offs = reinterpret_cast<uint16_t*>(base + kNoAllocEntryBytes + kNoAllocMarkBytes);
@@ -1174,8 +1227,11 @@ int srla_close_slice(srla_monitor_t* m) {
   if (rc) return rc;
   // the next slice's scans start once this slice's report is in host memory:
   // its end-of-slice work then has the GPU to itself (the scans overlap only
-  // Algorithm 3's carried list and SI update)
-  if (m->hold_scans) HIP_TRY(m, hipStreamWaitEvent(m->stream, m->ev_pub[p], 0));
+  // Algorithm 3's carried list and SI update).  The wait goes on the stream
+  // with the next scan, not here, so that monitors sharing a stream (a group)
+  // close their slices back to back before any of them waits.
+  m->hold_pending = m->hold_scans;
+  m->hold_parity = p;
   return SRLA_OK;
 }
 
@@ -1236,7 +1292,7 @@ int srla_estimate(srla_monitor_t* m, srla_report_t* out) {
 int srla_dump_state(srla_monitor_t* m, int which, uint16_t* host_out, uint64_t cells) {
   if (!m || !host_out) return m ? fail(m, SRLA_E_INVAL, "host_out is NULL") : SRLA_E_INVAL;
   HIP_TRY(m, hipStreamSynchronize(m->stream));
-  HIP_TRY(m, hipStreamSynchronize(m->pipe));
+  HIP_TRY(m, hipStreamSynchronize(m->pipe_use));
   if (which == SRLA_DUMP_SI) {
     if (cells != m->n_si) return fail(m, SRLA_E_INVAL, "cells does not match the array size");
     std::vector<uint32_t> c(16 * m->n_si);
@@ -1297,7 +1353,7 @@ int srla_set_timing(srla_monitor_t* m, int enabled) {
 int srla_timings(srla_monitor_t* m, srla_timings_t* out, int reset) {
   if (!m || !out) return SRLA_E_INVAL;
   HIP_TRY(m, hipStreamSynchronize(m->stream));
-  HIP_TRY(m, hipStreamSynchronize(m->pipe));
+  HIP_TRY(m, hipStreamSynchronize(m->pipe_use));
   collect_spans(m, true);
   out->scan_ms = m->acc_ms[ST_SCAN];
   out->scan_launches = m->scan_launches;
@@ -1322,6 +1378,10 @@ int srla_timings(srla_monitor_t* m, srla_timings_t* out, int reset) {
 struct srla_group {
   std::vector<srla_monitor*> mons;
   hipStream_t stream = nullptr;
+  // the members' end-of-slice pipelines share one stream with a hardware
+  // queue of its own: a member's if one has it, else the group's own
+  hipStream_t pipe = nullptr;
+  bool pipe_created = false, pipe_own = false;
   GroupMember* d_members = nullptr;
   std::vector<GroupMember> uploaded;
   uint32_t scan_blocks = 0;
@@ -1357,6 +1417,28 @@ int srla_group_create(srla_monitor_t* const* monitors, uint32_t n, uint32_t scan
   g->mons.assign(monitors, monitors + n);
   g->stream = monitors[0]->stream;
   g->scan_blocks = scan_blocks;
+  // one pipeline stream for all members: with a stream each, more streams
+  // than hardware queues share queues, and a member's pipeline then waits
+  // in the scan stream's queue behind the next group scan
+  for (srla_monitor* m : g->mons)
+    if (!g->pipe && m->pipe_own) g->pipe = m->pipe;
+  if (!g->pipe) {
+    if (create_queue_stream(&g->pipe, &g->pipe_own) != hipSuccess) {
+      (void)hipGetLastError();
+      delete g;
+      return SRLA_E_DEVICE;
+    }
+    g->pipe_created = true;
+  }
+  for (srla_monitor* m : g->mons) {
+    if (hipStreamSynchronize(m->pipe_use) != hipSuccess) {
+      (void)hipGetLastError();
+      if (g->pipe_created) destroy_queue_stream(g->pipe, g->pipe_own);
+      delete g;
+      return SRLA_E_DEVICE;
+    }
+  }
+  for (srla_monitor* m : g->mons) m->pipe_use = g->pipe;
   if (hipMalloc((void**)&g->d_members, n * sizeof(GroupMember)) != hipSuccess) {
     (void)hipGetLastError();
     delete g;
@@ -1390,6 +1472,10 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
     args.code[i] = stamp_code(m->slice);
     args.parity |= (uint64_t)p << i;
   }
+  for (srla_monitor* m : g->mons) {
+    const hipError_t e = apply_hold(m, g->stream);
+    if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
+  }
   // members that all scan in partitioned form: each member's partitioned scan
   // over the pairs (the pairs are read once per member, the stores go out in
   // lines) instead of the fused kernel's random stores
@@ -1400,7 +1486,8 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
       const int p = (int)(m->slice & 1);
       const hipError_t e = launch_scan_partition(
           pairs, n, m->geo, stamp_code(m->slice), m->le, m->re, m->touched[p], m->tcount + p,
-          m->part_entries, m->part_offs, m->part_marks, g->stream);
+          m->part_entries, m->part_offs, m->part_marks, g->stream, kPartChunks, nullptr, 0,
+          part_unit_of(&m->cfg));
       if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
     }
     for (srla_monitor* m : g->mons) {
@@ -1440,6 +1527,9 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
 int srla_group_destroy(srla_group_t* g) {
   if (!g) return SRLA_OK;
   if (g->stream) (void)hipStreamSynchronize(g->stream);
+  if (g->pipe) (void)hipStreamSynchronize(g->pipe);
+  for (srla_monitor* m : g->mons) m->pipe_use = m->pipe;
+  if (g->pipe_created) destroy_queue_stream(g->pipe, g->pipe_own);
   if (g->d_members) (void)hipFree(g->d_members);
   delete g;
   return SRLA_OK;

@@ -15,8 +15,14 @@ static_assert((1ull << kPartBandLog) == ((uint64_t)kPartBandRegions << kPartLog)
 constexpr uint32_t kPartEntries = 32768;
 constexpr uint32_t kPartChunks = 2048;
 // DR indices per marking unit: a region's marking is cut into
-// ceil(indices / kPartUnit) units (workgroups), each with its own bitmap
+// ceil(indices / unit) units (workgroups), each with its own bitmap; unit is
+// a power of two in [kPartUnitMin, kPartUnitMax], kPartUnit by default
 constexpr uint32_t kPartUnit = 32768;
+constexpr uint32_t kPartUnitMin = 8192;
+constexpr uint32_t kPartUnitMax = 131072;
+constexpr bool part_unit_ok(uint32_t unit) {
+  return unit >= kPartUnitMin && unit <= kPartUnitMax && (unit & (unit - 1)) == 0;
+}
 // uint32 words of one region's bitmap
 constexpr uint32_t kPartRegionWords = (1u << kPartLog) / 32;
 
@@ -30,8 +36,9 @@ constexpr uint64_t part_band_regions(uint64_t n_le) {
   return r < kPartBandRegions ? r : kPartBandRegions;
 }
 // marking units of one partition round of round_chunks chunks, at most
-constexpr uint64_t part_mark_units(uint64_t n_le, uint32_t round_chunks) {
-  return part_band_regions(n_le) + (uint64_t)round_chunks * kPartEntries / kPartUnit;
+constexpr uint64_t part_mark_units(uint64_t n_le, uint32_t round_chunks,
+                                   uint32_t unit = kPartUnit) {
+  return part_band_regions(n_le) + (uint64_t)round_chunks * kPartEntries / unit;
 }
 // device scratch of the partitioned scan: DR indices (uint16) and region offsets (uint16)
 constexpr uint64_t part_entry_words(uint32_t round_chunks = kPartChunks) {
@@ -44,8 +51,9 @@ constexpr uint64_t part_offset_words(uint64_t n_le, uint32_t round_chunks = kPar
 // region and the regions' first units (rounded to 256 bytes, so that the
 // bitmaps start aligned)
 constexpr uint64_t part_plan_words(void) { return (2ull * kPartBandRegions + 2 + 63) / 64 * 64; }
-constexpr uint64_t part_mark_words(uint64_t n_le, uint32_t round_chunks = kPartChunks) {
-  return part_plan_words() + part_mark_units(n_le, round_chunks) * kPartRegionWords;
+constexpr uint64_t part_mark_words(uint64_t n_le, uint32_t round_chunks = kPartChunks,
+                                   uint32_t unit = kPartUnit) {
+  return part_plan_words() + part_mark_units(n_le, round_chunks, unit) * kPartRegionWords;
 }
 
 // Algorithm 2 for n pairs of the open slice (stamp code `code`), the LE
@@ -53,15 +61,16 @@ constexpr uint64_t part_mark_words(uint64_t n_le, uint32_t round_chunks = kPartC
 // launch_scan.  Device scratch, reused by every launch on the stream:
 // entries part_entry_words(round_chunks) and offs
 // part_offset_words(n_le, round_chunks) uint16 words, marks
-// part_mark_words(n_le, round_chunks) uint32 words, where round_chunks
+// part_mark_words(n_le, round_chunks, unit) uint32 words, where round_chunks
 // (<= kPartChunks) is the number of chunks per partition round (a smaller
-// scratch takes the pairs in more rounds).  With ps, the scan's last kernel
+// scratch takes the pairs in more rounds) and unit the DR indices per
+// marking unit (part_unit_ok).  With ps, the scan's last kernel
 // records the end of the scan (the device clock) in ps->t_end[parity].
 hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& geo,
                                  uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
                                  uint32_t* tcount, uint16_t* entries, uint16_t* offs,
                                  uint32_t* marks, hipStream_t st,
                                  uint32_t round_chunks = kPartChunks, PipeState* ps = nullptr,
-                                 uint32_t parity = 0);
+                                 uint32_t parity = 0, uint32_t unit = kPartUnit);
 
 }  // namespace srla

@@ -13,7 +13,8 @@
 // chunk's LE DR indices that fall in the band by region in LDS and writes
 // them out as one contiguous block of 16-bit offsets, with the chunk's region
 // offsets.  A small plan counts each region's indices and cuts its marking
-// into units of about 32768 indices; the marking kernel has one workgroup
+// into units of up to `unit` indices (32768 by default, a launch-shape knob
+// that leaves results unchanged); the marking kernel has one workgroup
 // per unit, which marks the DRs its share of the chunks names in an LDS
 // bitmap of the region, reading the segments in aligned 16-byte pieces.  The
 // stamping kernel ORs a region's unit bitmaps and stores the stamp into the
@@ -244,6 +245,7 @@ constexpr uint32_t kPlanThreads = 256;
 
 __global__ __launch_bounds__(kPlanThreads) void k_mark_count(const uint16_t* __restrict__ offs,
                                                              uint32_t chunks, uint32_t stride,
+                                                             uint32_t unit,
                                                              uint32_t* __restrict__ plan) {
   __shared__ uint32_t wsum[kPlanThreads / kWave];
   const uint32_t r = blockIdx.x, tid = threadIdx.x;
@@ -257,7 +259,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_mark_count(const uint16_t* __r
   if (tid == 0) {
     uint32_t t = 0;
     for (uint32_t w = 0; w < kPlanThreads / kWave; ++w) t += wsum[w];
-    plan[r] = (t + kPartUnit - 1) / kPartUnit;
+    plan[r] = (t + unit - 1) / unit;
   }
 }
 
@@ -446,7 +448,8 @@ template <int U>
 hipError_t launch_band(const uint32_t* pairs, uint64_t n, const Geo& geo, const Band& band,
                        uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
                        uint32_t* tcount, uint16_t* entries, uint16_t* offs, uint32_t* marks,
-                       uint32_t round_chunks, PipeState* ps, uint32_t parity, hipStream_t st) {
+                       uint32_t round_chunks, PipeState* ps, uint32_t parity, uint32_t unit,
+                       hipStream_t st) {
   // pairs per chunk: at most kPartEntries / 2 in the pass that samples, so
   // that the chunk's sampled sources fit its LDS entry array
   const uint32_t rows = band.row_hi - band.row_lo;
@@ -462,12 +465,12 @@ hipError_t launch_band(const uint32_t* pairs, uint64_t n, const Geo& geo, const 
     const uint64_t per_seg = (np * rows) / ((uint64_t)chunks * band.regions) + 1;
     uint32_t w_log = 0;
     while (w_log < 6 && (8ull << w_log) < per_seg) ++w_log;
-    const uint32_t units = band.regions + (uint32_t)((uint64_t)chunks * kPartEntries / kPartUnit);
+    const uint32_t units = band.regions + (uint32_t)((uint64_t)chunks * kPartEntries / unit);
     hipLaunchKernelGGL((k_scan_part<U>), dim3(chunks), dim3(kPartThreads), 0, st, pairs + 2 * p,
                        np, ppc, geo, code, re, touched, tcount, band, entries, offs,
                        round_chunks);
     hipLaunchKernelGGL(k_mark_count, dim3(band.regions), dim3(kPlanThreads), 0, st, offs,
-                       chunks, round_chunks, plan);
+                       chunks, round_chunks, unit, plan);
     hipLaunchKernelGGL(k_mark_prefix, dim3(1), dim3(kPrefixThreads), 0, st, band.regions, plan);
     hipLaunchKernelGGL(k_scan_mark, dim3(units), dim3(kMarkThreads), 0, st, entries, offs,
                        chunks, round_chunks, band.regions, w_log, plan, bitmaps);
@@ -486,10 +489,11 @@ hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& g
                                  uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
                                  uint32_t* tcount, uint16_t* entries, uint16_t* offs,
                                  uint32_t* marks, hipStream_t st, uint32_t round_chunks,
-                                 PipeState* ps, uint32_t parity) {
+                                 PipeState* ps, uint32_t parity, uint32_t unit) {
   if (n == 0) return hipSuccess;
   const uint64_t n_le = (uint64_t)geo.u * geo.v_le * geo.G;
-  if (round_chunks == 0 || round_chunks > kPartChunks || n_le == 0) return hipErrorInvalidValue;
+  if (round_chunks == 0 || round_chunks > kPartChunks || n_le == 0 || !part_unit_ok(unit))
+    return hipErrorInvalidValue;
   const uint64_t row = (uint64_t)geo.v_le * geo.G, band_span = 1ull << kPartBandLog;
   for (uint64_t lo = 0; lo < n_le; lo += band_span) {
     Band b;
@@ -504,14 +508,14 @@ hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& g
     hipError_t e;
     if (lo == 0 && last && (geo.u == 4 || geo.u == 8 || geo.u == 16)) {
       e = geo.u == 4 ? launch_band<4>(pairs, n, geo, b, code, le, re, touched, tcount, entries,
-                                      offs, marks, round_chunks, bps, parity, st)
+                                      offs, marks, round_chunks, bps, parity, unit, st)
         : geo.u == 8 ? launch_band<8>(pairs, n, geo, b, code, le, re, touched, tcount, entries,
-                                      offs, marks, round_chunks, bps, parity, st)
+                                      offs, marks, round_chunks, bps, parity, unit, st)
                      : launch_band<16>(pairs, n, geo, b, code, le, re, touched, tcount, entries,
-                                       offs, marks, round_chunks, bps, parity, st);
+                                       offs, marks, round_chunks, bps, parity, unit, st);
     } else {
       e = launch_band<0>(pairs, n, geo, b, code, le, re, touched, tcount, entries, offs, marks,
-                         round_chunks, bps, parity, st);
+                         round_chunks, bps, parity, unit, st);
     }
     if (e != hipSuccess) return e;
   }

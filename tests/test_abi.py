@@ -107,18 +107,20 @@ def test_footprint_counts_dr_arrays(P):
     # plus counters, row fills and the LE sweep's partial row sums (a few KiB)
     assert want <= fp < want + 8192
     big = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=1 << 20)
-    assert P.srla_footprint_bytes(big) - fp >= 13 * ((1 << 20) - 1)
+    assert P.srla_footprint_bytes(big) - fp >= (13 + 27) * ((1 << 20) - 1)
 
 
 def test_overlap_report_staging_is_counted(P):
     # two staging sets (by slice parity) of 13 (lean) or 18 bytes per candidate
-    # and the two staged counts
+    # and the two staged counts; the direct report instead keeps device copies
+    # of its three host sets' est and flags arrays (9 bytes per candidate each)
     n = 1 << 20
     for lean, per in ((P.srla.SRLA_CFG_LEAN_REPORT, 13), (0, 18)):
         base = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=n, flags=lean)
         ov = P.make_config(300, 1024, 8, 131072, 8, 2048, 1024, 1, max_candidates=n,
                            flags=lean | P.srla.SRLA_CFG_OVERLAP_REPORT)
-        assert P.srla_footprint_bytes(ov) - P.srla_footprint_bytes(base) == 2 * per * n + 8
+        assert P.srla_footprint_bytes(ov) - P.srla_footprint_bytes(base) == \
+            2 * per * n + 8 - 3 * 9 * n
 
 
 def test_discrete_footprint_is_bits(P):
@@ -205,6 +207,16 @@ def test_partition_scan_scratch_in_the_footprint(P):
     assert extra(300, 1024, 4, 65536, 8, 65536, 1024, 1) == scratch(2048)
     # a ragged last region: 2^25 + 2^10 DRs in 513 regions
     assert extra(3, 1024, 1, 64, 8, 32769, 1024, 1) == scratch(513)
+    # scan_blocks sets the marking unit: 2^26 / unit units beyond R
+    geo = (300, 1024, 8, 131072, 8, 2048, 1024, 1)
+    plain = P.srla_footprint_bytes(P.make_config(*geo, max_candidates=1))
+    for unit in (8192, 131072):
+        cfg = P.make_config(*geo, max_candidates=1, flags=part, scan_blocks=unit)
+        assert P.srla_footprint_bytes(cfg) - plain == \
+            scratch(256) + 4 * 2048 * ((1 << 26) // unit - 2048)
+    for bad in (4096, 12288, 262144):
+        assert P.srla_footprint_bytes(P.make_config(*geo, max_candidates=1, flags=part,
+                                                    scan_blocks=bad)) == 0
     # beyond 2^32 LE DRs
     big = P.make_config(2, 1024, 2, 4096, 8, (1 << 21) + 3, 1024, 1, max_candidates=1, flags=part)
     assert P.srla_footprint_bytes(big) > 2 * ((1 << 32) + 6144)

@@ -492,7 +492,8 @@ def test_autotuner_picks_a_valid_shape_and_results_do_not_change(tmp_path):
     pairs = to_device(stream.slice(0))
     cache = str(tmp_path / "tune.json")
     choice = autotune.tune_scan(mon, pairs, repeats=2, cache=cache)
-    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "dedup/0", "partition/0"}
+    assert set(choice["all"]) == {"flat/0", "flat/1024", "flat/512", "dedup/0", "partition/0",
+                                  "partition/16384", "partition/65536"}
     assert choice["ms"] == min(choice["all"].values()) > 0
     assert autotune.tune_scan(mon, pairs, cache=cache) == choice      # served from the cache
     _run(stream, mon, range(6), scan_xcd=choice["scan_xcd"], scan_dedup=choice["scan_dedup"],
@@ -745,6 +746,25 @@ def test_partition_scan_backbone_full_size_and_expiry():
     stream, mon, _ = workload("backbone_k16")
     stream = scaled(stream, 600_000)
     _run(stream, mon, range(20), max_candidates=1 << 22, dump_every=7, scan_partition=True)
+
+
+@pytest.mark.parametrize("unit", [8192, 131072])
+def test_partition_scan_marking_unit(unit):
+    """The marking unit (scan_blocks of a partitioned-scan monitor) changes
+    the launch shape only: a heavy source's region gets many units at 8192,
+    a whole round's indices fit one unit at 131072."""
+    mon = dict(k=3, theta=1024, u=8, v_re=4096, g=8, v_le=1024, G=1024, hash_seed=77)
+    g = srla.Monitor(**mon, max_candidates=1 << 20, scan_partition=True, scan_blocks=unit)
+    o = oracle.Monitor(**mon)
+    gen = _rand_stream(99, 400_000, 20_000, 4096)
+    for s in range(4):
+        p = gen(s)
+        print("slice", s, "unit", unit, flush=True)
+        g.scan(to_device(p))
+        o.scan(p)
+        compare_reports(g.estimate(), o.estimate(), mon["theta"], ctx="slice %d" % s)
+    compare_dumps(g, o, ctx="end")
+    g.close()
 
 
 @pytest.mark.parametrize("u,v_le,G", [
