@@ -610,7 +610,7 @@ def main():
             else:
                 ds.generate(first + i, out=seg_bufs[i], stream=st)
         torch.cuda.synchronize()
-        lat, host_lat, cands, full, news = [], [], [], [], []
+        lat, host_lat, cands, full, news, hbytes = [], [], [], [], [], []
         r = None
         t0 = time.perf_counter()
         if mode == "plain":
@@ -623,6 +623,7 @@ def main():
                 lat.append(r.latency_ms)
                 cands.append(int(r.n))
                 news.append(int(r.n_new))
+                hbytes.append(int(r.host_bytes))
                 full.append(bool(r.window_full))
         else:
             # the host runs ahead: slice i is closed and slice i+1's scan is
@@ -641,9 +642,10 @@ def main():
                 lat.append(r.latency_ms)
                 cands.append(int(r.n))
                 news.append(int(r.n_new))
+                hbytes.append(int(r.host_bytes))
                 full.append(bool(r.window_full))
         torch.cuda.synchronize()
-        return time.perf_counter() - t0, lat, host_lat, cands, full, r, news
+        return time.perf_counter() - t0, lat, host_lat, cands, full, r, (news, hbytes)
 
     class Timed:
         """What one form's timed slices add up to."""
@@ -651,13 +653,15 @@ def main():
         def __init__(self):
             self.total, self.lat, self.host_lat, self.cands, self.full = 0.0, [], [], [], []
             self.r, self.tm, self.done, self.slices, self.news = None, {}, 0, [], []
+            self.hbytes = []
 
         def add(self, dt, l, hl, c, f, r, tm, first, n, nw):
             self.total += dt
             self.lat += l
             self.host_lat += hl
             self.cands += c
-            self.news += nw
+            self.news += nw[0]
+            self.hbytes += nw[1]
             self.full += f
             self.r = r
             for k, v in tm.items():
@@ -773,14 +777,17 @@ def main():
     if args.host_ingest:
         out["p50_host_ms"] = float(np.percentile(host_lat, 50)) if len(host_lat) else None
 
-    # the report's delivery: the candidate work's phase writes 13 (or 18) bytes
-    # per new candidate into pinned host memory over PCIe, and 9 (or 14) per
-    # carried one, whose address went to the host beside the slice's scans
-    # (all 13 / 18 in the overlapped-report form, which copies the whole report)
+    # the report's delivery: its contents are 13 (or 18) bytes per new
+    # candidate and 9 (or 14) per carried one, whose address went to the host
+    # beside the slice's scans (all 13 / 18 in the overlapped-report form);
+    # what crosses PCIe in the candidate work's phase is what the estimate
+    # wrote: the pieces of est and flags that differ from what the host set
+    # held (each report carries the count)
     per_cand = 18 if args.full_report else 13
     n_cand, n_new = float(np.mean(cands)), float(np.mean(main_run.news))
-    rep_bytes = (per_cand * n_cand if overlap else
-                 (per_cand - 4) * (n_cand - n_new) + per_cand * n_new)
+    payload = (per_cand * n_cand if overlap else
+               (per_cand - 4) * (n_cand - n_new) + per_cand * n_new)
+    rep_bytes = float(np.mean(main_run.hbytes)) if main_run.hbytes else payload
     est_ms = stages["estimate_ms"]
     import probe
     pcie = probe.host_write_rate()
@@ -788,6 +795,8 @@ def main():
         "kernel": "k_estimate (Eq9, report into pinned host memory) with the candidate check "
                   "before it (one timed phase)",
         "bound": "pcie", "bytes_per_slice": rep_bytes, "phase_ms": est_ms,
+        "bytes_per_slice_source": "the reports' host_bytes (what the estimate wrote over PCIe)",
+        "report_payload_bytes_per_slice": payload,
         "candidates_mean": n_cand, "new_candidates_mean": n_new,
         "achieved_GBps": rep_bytes / (est_ms * 1e-3) / 1e9 if est_ms > 0 else None,
         "ceiling_GBps": pcie / 1e9,

@@ -199,6 +199,11 @@ typedef struct srla_monitor srla_monitor_t;
  *   latency_ms    device time from the end of e's last scan (for a slice
  *                 without scans: the start of its end-of-slice work) until
  *                 the report was complete in host memory (device wall clock)
+ *   host_bytes    bytes e's end-of-slice work wrote into the report arrays
+ *                 (est and flags pieces that changed, the new candidates'
+ *                 addresses, union_weight and re_weight; the carried
+ *                 candidates' addresses go in beside the scans and are not
+ *                 counted); with SRLA_CFG_OVERLAP_REPORT the staged bytes
  */
 typedef struct {
     uint64_t slice;
@@ -214,6 +219,7 @@ typedef struct {
     uint64_t n_touched;
     uint64_t n_new;
     double latency_ms;
+    uint64_t host_bytes;
 } srla_report_t;
 
 /* Accumulated stage times (milliseconds, HIP events on the stream each stage

@@ -106,6 +106,9 @@ struct PipeState {
   // slot, so the atomics do not queue on one address); the end of the scan
   // is the largest slot
   unsigned long long t_end[2][kEndSlots];
+  // bytes the estimate wrote into the host report arrays, in slots by
+  // workgroup (summed and cleared when the report is published)
+  unsigned long long rep_bytes[kEndSlots];
 };
 
 // Pinned host block the status kernel fills at the end of every slice.
@@ -116,6 +119,7 @@ struct HostStatus {
   uint64_t slice;
   uint64_t t_close;      // device wall clock: the slice's last scan ended
   uint64_t t_done;       //   and the report was complete in host memory
+  uint64_t host_bytes;   // bytes the estimate wrote into the report arrays
 };
 
 // Report arrays in pinned host memory, as device-visible pointers.  With
@@ -270,7 +274,7 @@ hipError_t launch_status(Counters* cnt, uint32_t* tcount, const double* up,
 // moves it to the next slice and clears the counters, once Algorithm 3's
 // carried list is final
 hipError_t launch_publish(const Counters* cnt, const uint32_t* tcount, const double* up,
-                          const unsigned long long* row_fill, uint32_t u, const PipeState* ps,
+                          const unsigned long long* row_fill, uint32_t u, PipeState* ps,
                           uint32_t p, HostStatus* out, hipStream_t st);
 hipError_t launch_advance(Counters* cnt, uint32_t* tcount, PipeState* ps, hipStream_t st);
 

@@ -577,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
     uint32_t lg_log2, uint8_t* __restrict__ cflags, uint32_t* __restrict__ out_ip,
     double* __restrict__ out_est, uint8_t* __restrict__ out_flags, uint32_t* __restrict__ out_U,
     uint8_t* __restrict__ out_W, double* __restrict__ mir_est,
-    uint8_t* __restrict__ mir_flags) {
+    uint8_t* __restrict__ mir_flags, unsigned long long* __restrict__ rep_bytes) {
   __shared__ uint32_t s_ip[kEstPerBlock], s_U[kEstPerBlock];
   __shared__ uint8_t s_W[kEstPerBlock], s_Wn[kEstPerBlock];
   __shared__ __align__(16) double s_e[kEstPerBlock];
@@ -605,6 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
   const uint32_t active =
       gather == 0u && gridDim.x > kEstBlocksNoGather ? kEstBlocksNoGather : gridDim.x;
   if (blockIdx.x >= active) return;
+  uint32_t wrote = 0;   // bytes this thread stores into the report arrays
   for (uint64_t base = (uint64_t)blockIdx.x * kEstPerBlock; base < n;
        base += (uint64_t)active * kEstPerBlock) {
     const uint32_t in_batch =
@@ -706,6 +707,7 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
       s_f[threadIdx.x] = fl;
       if (out_U) out_U[gid] = ucount;
       if (out_W) out_W[gid] = s_W[threadIdx.x];
+      wrote += (out_U ? 4u : 0u) + (out_W ? 1u : 0u);
     }
     lds_barrier();
     // the batch's report entries leave in 16-byte pieces (ip: 64 lanes, est:
@@ -715,10 +717,13 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
     if (in_batch == kEstPerBlock) {
       const uint32_t t = threadIdx.x;
       if (base >= ip_from) {
-        if (t < kEstPerBlock / 4)
+        if (t < kEstPerBlock / 4) {
           reinterpret_cast<uint4*>(out_ip + base)[t] = reinterpret_cast<const uint4*>(s_ip)[t];
+          wrote += 16u;
+        }
       } else if (base + t >= ip_from) {
         out_ip[base + t] = s_ip[t];
+        wrote += 4u;
       }
       // with the mirrors, a piece goes to host memory only if it differs
       // from what the host array holds there (the mirror), and the mirror
@@ -731,9 +736,11 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
           if (o.x != v.x || o.y != v.y || o.z != v.z || o.w != v.w) {
             reinterpret_cast<uint4*>(out_est + base)[t] = v;
             *mp = v;
+            wrote += 16u;
           }
         } else {
           reinterpret_cast<uint4*>(out_est + base)[t] = v;
+          wrote += 16u;
         }
       }
       if (t < kEstPerBlock / 16) {
@@ -744,26 +751,42 @@ __global__ __launch_bounds__(kBlock) void k_estimate(
           if (o.x != v.x || o.y != v.y || o.z != v.z || o.w != v.w) {
             reinterpret_cast<uint4*>(out_flags + base)[t] = v;
             *mp = v;
+            wrote += 16u;
           }
         } else {
           reinterpret_cast<uint4*>(out_flags + base)[t] = v;
+          wrote += 16u;
         }
       }
     } else if (threadIdx.x < in_batch) {
       const uint64_t gid = base + threadIdx.x;
-      if (gid >= ip_from) out_ip[gid] = s_ip[threadIdx.x];
+      if (gid >= ip_from) {
+        out_ip[gid] = s_ip[threadIdx.x];
+        wrote += 4u;
+      }
       const double e = s_e[threadIdx.x];
       const uint8_t f = s_f[threadIdx.x];
       if (!mir_est || __double_as_longlong(mir_est[gid]) != __double_as_longlong(e)) {
         out_est[gid] = e;
         if (mir_est) mir_est[gid] = e;
+        wrote += 8u;
       }
       if (!mir_flags || mir_flags[gid] != f) {
         out_flags[gid] = f;
         if (mir_flags) mir_flags[gid] = f;
+        wrote += 1u;
       }
     }
     lds_barrier();
+  }
+  // the workgroup's byte count into one of the slots
+  for (int off = kWave / 2; off > 0; off >>= 1) wrote += __shfl_xor(wrote, off);
+  if ((threadIdx.x & (kWave - 1)) == 0) s_U[threadIdx.x / kWave] = wrote;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long b = 0;
+    for (uint32_t w = 0; w < kBlock / kWave; ++w) b += s_U[w];
+    if (b) atomicAdd(&rep_bytes[blockIdx.x % kEndSlots], b);
   }
 }
 
@@ -804,7 +827,8 @@ static hipError_t launch_estimate_u(const uint32_t* csip, const Counters* cnt,
   hipLaunchKernelGGL((k_estimate<kU, kWpl>), dim3(grid), dim3(kBlock), 0, st, csip, cnt, ps,
                      skip, bitmap,
                      act, up, row_fill, geo, l, cflags, out.ip, out.est, out.flags,
-                     out.U, out.W, out.mir_est, out.mir_flags);
+                     out.U, out.W, out.mir_est, out.mir_flags,
+                     const_cast<PipeState*>(ps)->rep_bytes);
   return hipGetLastError();
 }
 
@@ -882,6 +906,19 @@ hipError_t launch_si_update(const uint32_t* csip, const uint8_t* cflags, const C
 // slice's counters (and the sampled-source count of its parity, which the
 // scans of the slice after next reuse) are cleared.
 
+// the estimate's byte count: slot t per lane, summed over the wavefront, the
+// slots cleared for the next slice
+__device__ __forceinline__ unsigned long long take_rep_bytes(PipeState* ps, uint32_t t) {
+  unsigned long long b = t < kEndSlots ? ps->rep_bytes[t] : 0ull;
+  if (t < kEndSlots) ps->rep_bytes[t] = 0ull;
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)b, d);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(b >> 32), d);
+    b += ((unsigned long long)hi << 32) | lo;
+  }
+  return b;
+}
+
 __global__ void k_status(Counters* __restrict__ cnt, uint32_t* __restrict__ tcount,
                          const double* __restrict__ up,
                          const unsigned long long* __restrict__ row_fill, uint32_t u,
@@ -889,6 +926,7 @@ __global__ void k_status(Counters* __restrict__ cnt, uint32_t* __restrict__ tcou
                          uint32_t* __restrict__ report_n) {
   if (blockIdx.x != 0) return;
   const uint32_t t = threadIdx.x;
+  const unsigned long long host_bytes = take_rep_bytes(ps, t);
   Counters c = *cnt;
   c.touched = *tcount;
   if (t < sizeof(Counters) / 4) ((uint32_t*)&out->cnt)[t] = ((const uint32_t*)&c)[t];
@@ -897,6 +935,7 @@ __global__ void k_status(Counters* __restrict__ cnt, uint32_t* __restrict__ tcou
     out->up = *up;
     out->slice = ps->slice;
     out->t_close = ps->t_close[p];
+    out->host_bytes = host_bytes;   // the staged report's bytes (its copy follows)
     out->t_done = wall_clock64();   // every earlier kernel of the report has finished
     if (report_n) *report_n = c.n_cand;
   }
@@ -1033,10 +1072,11 @@ hipError_t launch_mark_done(HostStatus* out, hipStream_t st) {
 __global__ void k_publish(const Counters* __restrict__ cnt, const uint32_t* __restrict__ tcount,
                           const double* __restrict__ up,
                           const unsigned long long* __restrict__ row_fill, uint32_t u,
-                          const PipeState* __restrict__ ps, uint32_t p,
+                          PipeState* __restrict__ ps, uint32_t p,
                           HostStatus* __restrict__ out) {
   if (blockIdx.x != 0) return;
   const uint32_t t = threadIdx.x;
+  const unsigned long long host_bytes = take_rep_bytes(ps, t);
   Counters c = *cnt;
   c.touched = *tcount;
   if (t < sizeof(Counters) / 4) ((uint32_t*)&out->cnt)[t] = ((const uint32_t*)&c)[t];
@@ -1045,6 +1085,7 @@ __global__ void k_publish(const Counters* __restrict__ cnt, const uint32_t* __re
     out->up = *up;
     out->slice = ps->slice;
     out->t_close = ps->t_close[p];
+    out->host_bytes = host_bytes;
     out->t_done = wall_clock64();   // every earlier kernel of the report has finished
   }
 }
@@ -1064,7 +1105,7 @@ __global__ void k_advance(Counters* __restrict__ cnt, uint32_t* __restrict__ tco
 }
 
 hipError_t launch_publish(const Counters* cnt, const uint32_t* tcount, const double* up,
-                          const unsigned long long* row_fill, uint32_t u, const PipeState* ps,
+                          const unsigned long long* row_fill, uint32_t u, PipeState* ps,
                           uint32_t p, HostStatus* out, hipStream_t st) {
   hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, st, cnt, tcount, up, row_fill, u, ps, p,
                      out);

@@ -1277,6 +1277,7 @@ int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
   out->latency_ms = m->clock_khz > 0 && hs.t_done >= hs.t_close
                         ? (double)(hs.t_done - hs.t_close) / (double)m->clock_khz
                         : 0.0;
+  out->host_bytes = hs.host_bytes;
   return SRLA_OK;
 }
 

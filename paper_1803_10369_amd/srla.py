@@ -52,7 +52,8 @@ class srla_report_t(ctypes.Structure):
                 ("re_weight", ctypes.POINTER(ctypes.c_uint8)),
                 ("row_fill", ctypes.POINTER(ctypes.c_uint64)),
                 ("up", ctypes.c_double), ("n_touched", ctypes.c_uint64),
-                ("n_new", ctypes.c_uint64), ("latency_ms", ctypes.c_double)]
+                ("n_new", ctypes.c_uint64), ("latency_ms", ctypes.c_double),
+                ("host_bytes", ctypes.c_uint64)]
 
 
 class srla_timings_t(ctypes.Structure):
@@ -245,6 +246,7 @@ class Report:
         self.n_touched = r.n_touched
         self.n_new = r.n_new
         self.latency_ms = r.latency_ms
+        self.host_bytes = r.host_bytes
 
 
 class Monitor:
