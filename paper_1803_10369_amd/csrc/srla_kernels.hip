@@ -503,10 +503,13 @@ __global__ __launch_bounds__(kBlock) void k_ip_precopy(const uint32_t* __restric
   if (t < n - n4 * 4) dst[n4 * 4 + t] = src[n4 * 4 + t];
 }
 
-// a small grid: the copy runs beside the next slice's scans and is bound by
-// PCIe writes, which a few workgroups saturate (64 and 256 workgroups
-// measured alike on the backbone workload)
-constexpr uint32_t kPrecopyBlocks = 64;
+// a small grid: the copy runs beside the next slice's scans, and while its
+// writes stream into host memory the scans' kernels start late (the command
+// processor's reads of their dispatch packets queue behind the writes).  On
+// the backbone workload (9 MB per slice) 16 workgroups gave 12.9 G packets/s
+// against 12.2 G with 64 (the scan 0.33 instead of 0.36 ms) and 12.7 G with
+// 4, whose copy no longer ends before the next slice's candidate work
+constexpr uint32_t kPrecopyBlocks = 16;
 
 hipError_t launch_ip_precopy(const uint32_t* src, const uint32_t* n, uint32_t* dst,
                              hipStream_t st) {
