@@ -214,6 +214,11 @@ struct srla_monitor {
   // scans; the second phase runs on the pipeline stream
   hipEvent_t ev_snap = nullptr;                 // after the last closed slice's snapshot phase
   hipEvent_t ev_scanned = nullptr;              // after the last closed slice's scans
+  // after the partitioned scan's sampled-source appends (before its marking
+  // and stamping); sampled_pending: the open slice's last scan recorded it
+  hipEvent_t ev_sampled = nullptr;
+  bool sampled_pending = false;
+  hipEvent_t ev_sort = nullptr;                 // what the closed slice's sort waits for
   hipEvent_t ev_done[2] = {nullptr, nullptr};   // after the whole pipeline, by slice parity
   hipEvent_t ev_pub[2] = {nullptr, nullptr};    // the report and status are in host memory
   uint32_t n_pending = 0;         // closed slices whose reports are not collected (<= 2)
@@ -704,6 +709,7 @@ void release(srla_monitor* m) {
   for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
   if (m->ev_snap) (void)hipEventDestroy(m->ev_snap);
   if (m->ev_scanned) (void)hipEventDestroy(m->ev_scanned);
+  if (m->ev_sampled) (void)hipEventDestroy(m->ev_sampled);
   if (m->pipe) destroy_queue_stream(m->pipe, m->pipe_own);
   if (m->copy) {
     (void)hipStreamSynchronize(m->copy);
@@ -918,6 +924,8 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     if (!rc && hipEventCreateWithFlags(&m->ev_pub[q], hipEventDisableTiming) != hipSuccess)
       rc = SRLA_E_DEVICE;
   }
+  if (!rc && hipEventCreateWithFlags(&m->ev_sampled, hipEventDisableTiming) != hipSuccess)
+    rc = SRLA_E_DEVICE;
   if (!rc && hipEventCreateWithFlags(&m->ev_scanned, hipEventDisableTiming) != hipSuccess)
     rc = SRLA_E_DEVICE;
   if (!rc && hipEventCreateWithFlags(&m->ev_snap, hipEventDisableTiming) != hipSuccess)
@@ -984,11 +992,13 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
     return launch_scan_bits(pairs, n, m->geo, m->lebits[p], m->rebits[p], m->sset[p],
                             m->set_slots, m->touched[p], m->tcount + p, m->cfg.scan_blocks,
                             m->stream);
+  m->sampled_pending = m->part_scan && !m->overlap_report;
   if (m->part_scan)
     return launch_scan_partition(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                                  m->tcount + p, m->part_entries, m->part_offs, m->part_marks,
                                  m->stream, kPartChunks, m->ps, (uint32_t)p,
-                                 part_unit_of(&m->cfg));
+                                 part_unit_of(&m->cfg),
+                                 m->sampled_pending ? m->ev_sampled : nullptr);
   if (m->dedup_scan)
     return launch_scan_dedup(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                              m->tcount + p, m->xcd_scan, m->cfg.scan_blocks, m->stream);
@@ -1023,7 +1033,7 @@ int enqueue_finish(srla_monitor* m, bool go) {
   hipEvent_t ta;
   if (!m->overlap_report) {
     // the sort needs the slice's scans only: it runs beside the snapshot
-    HIP_TRY(m, hipStreamWaitEvent(m->pipe_use, m->ev_scanned, 0));
+    HIP_TRY(m, hipStreamWaitEvent(m->pipe_use, m->ev_sort, 0));
     if (m->use_graph) span_begin(m, m->pipe_use, &ta);
     const int rs = run_phase(m, PH_SORT, cc, m->pipe_use);
     if (rs) return rs;
@@ -1172,9 +1182,11 @@ int srla_scan_noalloc(srla_monitor_t* m, const uint32_t* pairs, uint64_t n) {
   uint16_t* entries = reinterpret_cast<uint16_t*>(base);
   uint32_t* marks = reinterpret_cast<uint32_t*>(base + kNoAllocEntryBytes);
   uint16_t* offs = reinterpret_cast<uint16_t*>(base + kNoAllocEntryBytes + kNoAllocMarkBytes);
+  m->sampled_pending = true;
   HIP_TRY(m, launch_scan_partition(pairs, n, m->geo, stamp_code(m->slice), m->le, m->re,
                                    m->touched[p], m->tcount + p, entries, offs, marks,
-                                   m->stream, kNoAllocChunks, m->ps, (uint32_t)p));
+                                   m->stream, kNoAllocChunks, m->ps, (uint32_t)p, kPartUnit,
+                                   m->ev_sampled));
   m->slice_pairs[p] += n;
   return SRLA_OK;
 }
@@ -1197,8 +1209,18 @@ int srla_close_slice(srla_monitor_t* m) {
     const int rc = enqueue_finish(m, false);
     if (rc) return rc;
   }
-  // the slice's scans are done: the pipeline stream may sort its sampled sources
-  if (!m->overlap_report) HIP_TRY(m, hipEventRecord(m->ev_scanned, m->stream));
+  // the slice's sampled sources are all appended (after the partitioned
+  // scan's partition kernel, so the sort runs beside its marking and
+  // stamping; else after the scans): the pipeline stream may sort them
+  if (!m->overlap_report) {
+    if (m->sampled_pending) {
+      m->ev_sort = m->ev_sampled;
+    } else {
+      HIP_TRY(m, hipEventRecord(m->ev_scanned, m->stream));
+      m->ev_sort = m->ev_scanned;
+    }
+  }
+  m->sampled_pending = false;
   if (m->overlap_report ? m->slice >= 2 : (m->discrete && m->slice >= 1))
     HIP_TRY(m, wait_unless_done(m->stream, m->ev_done[m->overlap_report ? p : p ^ 1]));
   // with graphs, each phase is timed as a whole: the first as the sweeps
@@ -1485,10 +1507,11 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
   if (all_part) {
     for (srla_monitor* m : g->mons) {
       const int p = (int)(m->slice & 1);
+      m->sampled_pending = true;
       const hipError_t e = launch_scan_partition(
           pairs, n, m->geo, stamp_code(m->slice), m->le, m->re, m->touched[p], m->tcount + p,
           m->part_entries, m->part_offs, m->part_marks, g->stream, kPartChunks, nullptr, 0,
-          part_unit_of(&m->cfg));
+          part_unit_of(&m->cfg), m->ev_sampled);
       if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
     }
     for (srla_monitor* m : g->mons) {
@@ -1500,6 +1523,7 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
     }
     return SRLA_OK;
   }
+  for (srla_monitor* m : g->mons) m->sampled_pending = false;
   bool changed = g->uploaded.size() != table.size();
   for (size_t i = 0; !changed && i < table.size(); ++i)
     changed = !same_member(table[i], g->uploaded[i]);

@@ -65,12 +65,16 @@ constexpr uint64_t part_mark_words(uint64_t n_le, uint32_t round_chunks = kPartC
 // (<= kPartChunks) is the number of chunks per partition round (a smaller
 // scratch takes the pairs in more rounds) and unit the DR indices per
 // marking unit (part_unit_ok).  With ps, the scan's last kernel
-// records the end of the scan (the device clock) in ps->t_end[parity].
+// records the end of the scan (the device clock) in ps->t_end[parity].  With sampled, the
+// event is recorded on st as soon as every sampled source of the pairs is
+// appended (after the first band's last partition kernel), before the
+// marking and stamping.
 hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& geo,
                                  uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
                                  uint32_t* tcount, uint16_t* entries, uint16_t* offs,
                                  uint32_t* marks, hipStream_t st,
                                  uint32_t round_chunks = kPartChunks, PipeState* ps = nullptr,
-                                 uint32_t parity = 0, uint32_t unit = kPartUnit);
+                                 uint32_t parity = 0, uint32_t unit = kPartUnit,
+                                 hipEvent_t sampled = nullptr);
 
 }  // namespace srla

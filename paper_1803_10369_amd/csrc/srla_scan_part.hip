@@ -449,7 +449,7 @@ hipError_t launch_band(const uint32_t* pairs, uint64_t n, const Geo& geo, const 
                        uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
                        uint32_t* tcount, uint16_t* entries, uint16_t* offs, uint32_t* marks,
                        uint32_t round_chunks, PipeState* ps, uint32_t parity, uint32_t unit,
-                       hipStream_t st) {
+                       hipEvent_t sampled, hipStream_t st) {
   // pairs per chunk: at most kPartEntries / 2 in the pass that samples, so
   // that the chunk's sampled sources fit its LDS entry array
   const uint32_t rows = band.row_hi - band.row_lo;
@@ -469,6 +469,10 @@ hipError_t launch_band(const uint32_t* pairs, uint64_t n, const Geo& geo, const 
     hipLaunchKernelGGL((k_scan_part<U>), dim3(chunks), dim3(kPartThreads), 0, st, pairs + 2 * p,
                        np, ppc, geo, code, re, touched, tcount, band, entries, offs,
                        round_chunks);
+    if (sampled && band.sre && p + per_round >= n) {
+      const hipError_t er = hipEventRecord(sampled, st);
+      if (er != hipSuccess) return er;
+    }
     hipLaunchKernelGGL(k_mark_count, dim3(band.regions), dim3(kPlanThreads), 0, st, offs,
                        chunks, round_chunks, unit, plan);
     hipLaunchKernelGGL(k_mark_prefix, dim3(1), dim3(kPrefixThreads), 0, st, band.regions, plan);
@@ -489,7 +493,8 @@ hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& g
                                  uint16_t code, uint16_t* le, uint16_t* re, uint32_t* touched,
                                  uint32_t* tcount, uint16_t* entries, uint16_t* offs,
                                  uint32_t* marks, hipStream_t st, uint32_t round_chunks,
-                                 PipeState* ps, uint32_t parity, uint32_t unit) {
+                                 PipeState* ps, uint32_t parity, uint32_t unit,
+                                 hipEvent_t sampled) {
   if (n == 0) return hipSuccess;
   const uint64_t n_le = (uint64_t)geo.u * geo.v_le * geo.G;
   if (round_chunks == 0 || round_chunks > kPartChunks || n_le == 0 || !part_unit_ok(unit))
@@ -508,14 +513,14 @@ hipError_t launch_scan_partition(const uint32_t* pairs, uint64_t n, const Geo& g
     hipError_t e;
     if (lo == 0 && last && (geo.u == 4 || geo.u == 8 || geo.u == 16)) {
       e = geo.u == 4 ? launch_band<4>(pairs, n, geo, b, code, le, re, touched, tcount, entries,
-                                      offs, marks, round_chunks, bps, parity, unit, st)
+                                      offs, marks, round_chunks, bps, parity, unit, sampled, st)
         : geo.u == 8 ? launch_band<8>(pairs, n, geo, b, code, le, re, touched, tcount, entries,
-                                      offs, marks, round_chunks, bps, parity, unit, st)
+                                      offs, marks, round_chunks, bps, parity, unit, sampled, st)
                      : launch_band<16>(pairs, n, geo, b, code, le, re, touched, tcount, entries,
-                                       offs, marks, round_chunks, bps, parity, unit, st);
+                                       offs, marks, round_chunks, bps, parity, unit, sampled, st);
     } else {
       e = launch_band<0>(pairs, n, geo, b, code, le, re, touched, tcount, entries, offs, marks,
-                         round_chunks, bps, parity, unit, st);
+                         round_chunks, bps, parity, unit, sampled, st);
     }
     if (e != hipSuccess) return e;
   }
