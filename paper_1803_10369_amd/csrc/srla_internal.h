@@ -180,17 +180,13 @@ hipError_t launch_scan_group(const uint32_t* pairs, uint64_t n, const GroupMembe
                              uint32_t n_members, const GroupScanArgs& args, uint32_t max_blocks,
                              hipStream_t st);
 
-// |LDR(i)|^k by row into kFillSlots partial sums per row (fill_part, u x
-// kFillSlots, zero beforehand), the LE activity bitmap, the scrub
-hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* fill_part,
-                           const Geo& geo, const PipeState* ps, hipStream_t st);
-
-// SRE DR activity bitmaps (inside the window now / after the slide) + scrub;
-// the row fills folded from the LE sweep's partial sums (when fill_part is
-// given; else row_fill is final already) and Eq8 from them
-hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act, const Geo& geo,
-                           const PipeState* ps, const unsigned long long* fill_part,
-                           unsigned long long* row_fill, double* up, hipStream_t st);
+// The snapshot's sweeps in one launch: |LDR(i)|^k by row into kFillSlots
+// partial sums per row (fill_part, u x kFillSlots, zero beforehand), the LE
+// activity bitmap and scrub; the SRE activity maps (inside the window now /
+// after the slide) and scrub
+hipError_t launch_sweep(uint16_t* le, uint64_t* bitmap, unsigned long long* fill_part,
+                        uint16_t* re, uint64_t n_re, uint64_t* act, const Geo& geo,
+                        const PipeState* ps, hipStream_t st);
 
 // keys-only LSD radix sort of *n_dev uint32 keys (n_dev <= n_max), in place
 // (tmp is scratch).  block_hist needs radix_hist_words(n_max) words.
@@ -207,9 +203,12 @@ hipError_t compact_u32(const uint8_t* flags, uint8_t mask, const uint32_t* vals,
                        const uint32_t* n_dev, uint64_t n_max, uint32_t* out,
                        uint32_t* out_count, uint32_t* block_words, hipStream_t st);
 
+// (with fill_part: its first block folds the sweep's partial sums into
+// row_fill and evaluates Eq8 into *up first)
 hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const uint64_t* act,
                            const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
-                           hipStream_t st);
+                           const unsigned long long* fill_part, unsigned long long* row_fill,
+                           double* up, hipStream_t st);
 
 // CSIP_t = the carried list (the first ps->n_ncsip entries of cand) followed
 // by the cnt->n_new new candidates, appended to cand (capacity cap)

@@ -48,13 +48,12 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t 
 constexpr int kSweepSteps = 8;
 constexpr uint64_t kSweepTile = (uint64_t)kBlock * 8 * kSweepSteps;  // DRs per block
 
-__global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
-                                                    uint64_t* __restrict__ bitmap,
-                                                    unsigned long long* __restrict__ fill_part,
-                                                    uint64_t row_cells,
-                                                    const PipeState* __restrict__ ps,
-                                                    uint32_t k) {
-  const uint32_t now = ps->snap;   // the slice being snapshotted
+// LE tile bx of row `row`
+__device__ __forceinline__ void sweep_le_tile(uint16_t* __restrict__ le,
+                                              uint64_t* __restrict__ bitmap,
+                                              unsigned long long* __restrict__ fill_part,
+                                              uint64_t row_cells, uint32_t now, uint32_t k,
+                                              uint32_t bx, uint32_t row, uint32_t* part) {
   // The window's stamp codes form one interval on the circle of codes: a
   // nonzero cell c is inside iff (c - lo) mod 2^16 <= w, with lo the code of
   // slice e-k+1 (the interval may pass over the unused code 0, which widens w
@@ -64,7 +63,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
   const uint32_t lo_s =
       now > kScrubAge - 1u ? now - (kScrubAge - 1u) : now + kStampPeriod - (kScrubAge - 1u);
   const uint32_t w_s = (now - lo_s) & 0xFFFFu;
-  const uint32_t row = blockIdx.y;
   uint16_t* rowp = le + (uint64_t)row * row_cells;
   uint64_t* bmp = bitmap + (uint64_t)row * (row_cells / 64);
   const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -74,12 +72,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
   uint4 qs[kSweepSteps];
 #pragma unroll
   for (int s = 0; s < kSweepSteps; ++s) {
-    const uint64_t c8 = ((uint64_t)blockIdx.x * kSweepTile) + ((uint64_t)s * kBlock + threadIdx.x) * 8;
+    const uint64_t c8 = ((uint64_t)bx * kSweepTile) + ((uint64_t)s * kBlock + threadIdx.x) * 8;
     qs[s] = *reinterpret_cast<const uint4*>(rowp + (c8 < row_cells ? c8 : 0));
   }
 #pragma unroll
   for (int s = 0; s < kSweepSteps; ++s) {
-    const uint64_t c8 = ((uint64_t)blockIdx.x * kSweepTile) + ((uint64_t)s * kBlock + threadIdx.x) * 8;
+    const uint64_t c8 = ((uint64_t)bx * kSweepTile) + ((uint64_t)s * kBlock + threadIdx.x) * 8;
     const bool valid = c8 < row_cells;
     uint32_t m8 = 0;
     if (valid) {
@@ -110,23 +108,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep_le(uint16_t* __restrict__ le,
   }
   // block total -> one 64-bit atomic per block
   for (int off = kWave / 2; off > 0; off >>= 1) count += __shfl_xor(count, off);
-  __shared__ uint32_t part[kBlock / kWave];
   if (lane == 0) part[threadIdx.x / kWave] = count;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long t = 0;
     for (int w = 0; w < kBlock / kWave; ++w) t += part[w];
-    if (t) atomicAdd(&fill_part[(uint64_t)row * kFillSlots + (blockIdx.x % kFillSlots)], t);
+    if (t) atomicAdd(&fill_part[(uint64_t)row * kFillSlots + (bx % kFillSlots)], t);
   }
-}
-
-hipError_t launch_sweep_le(uint16_t* le, uint64_t* bitmap, unsigned long long* fill_part,
-                           const Geo& geo, const PipeState* ps, hipStream_t st) {
-  const uint64_t row_cells = (uint64_t)geo.v_le * geo.G;
-  const uint64_t bx = (row_cells + kSweepTile - 1) / kSweepTile;
-  hipLaunchKernelGGL(k_sweep_le, dim3((uint32_t)bx, geo.u), dim3(kBlock), 0, st, le, bitmap,
-                     fill_part, row_cells, ps, geo.k);
-  return hipGetLastError();
 }
 
 
@@ -147,44 +135,23 @@ __device__ __forceinline__ double eq8(const unsigned long long* __restrict__ row
   return p;
 }
 
-// The LE sweep has finished the partial row fills when this kernel starts
-// (same stream), so its first block folds them into the row fills and
-// evaluates Eq8.  One thread takes kReSteps groups of 8 DRs, their loads
+// One thread takes kReSteps groups of 8 DRs of RE tile bx, their loads
 // issued first.
 constexpr int kReSteps = 4;
 
-__global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, uint64_t n,
-                                                    uint64_t* __restrict__ act,
-                                                    const PipeState* __restrict__ ps,
-                                                    uint32_t k,
-                                                    const unsigned long long* __restrict__ fill_part,
-                                                    unsigned long long* __restrict__ row_fill,
-                                                    uint32_t u, uint32_t G, uint32_t v_le,
-                                                    double* __restrict__ up) {
-  if (blockIdx.x == 0) {
-    if (fill_part) {
-      // one wave per row: lane l adds slot l
-      const uint32_t lane0 = threadIdx.x & (kWave - 1);
-      for (uint32_t r = threadIdx.x / kWave; r < u; r += kBlock / kWave) {
-        unsigned long long v = lane0 < kFillSlots ? fill_part[(uint64_t)r * kFillSlots + lane0] : 0ull;
-        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane0 == 0) row_fill[r] = v;
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) *up = eq8(row_fill, u, G, v_le);
-  }
-  const uint32_t now = ps->snap;   // the slice being snapshotted
+__device__ __forceinline__ void sweep_re_tile(uint16_t* __restrict__ re, uint64_t n,
+                                              uint64_t* __restrict__ act, uint32_t now,
+                                              uint32_t k, uint32_t bx) {
   const uint32_t lane = threadIdx.x & (kWave - 1);
   uint4 qs[kReSteps];
 #pragma unroll
   for (int st8 = 0; st8 < kReSteps; ++st8) {
-    const uint64_t c8 = (((uint64_t)blockIdx.x * kReSteps + st8) * kBlock + threadIdx.x) * 8;
+    const uint64_t c8 = (((uint64_t)bx * kReSteps + st8) * kBlock + threadIdx.x) * 8;
     qs[st8] = c8 + 8 <= n ? *reinterpret_cast<const uint4*>(re + c8) : make_uint4(0u, 0u, 0u, 0u);
   }
 #pragma unroll
   for (int st8 = 0; st8 < kReSteps; ++st8) {
-  const uint64_t c8 = (((uint64_t)blockIdx.x * kReSteps + st8) * kBlock + threadIdx.x) * 8;
+  const uint64_t c8 = (((uint64_t)bx * kReSteps + st8) * kBlock + threadIdx.x) * 8;
   uint32_t m_now = 0, m_next = 0;
   if (c8 < n) {
     uint32_t cell[8];
@@ -234,14 +201,52 @@ __global__ __launch_bounds__(kBlock) void k_sweep_re(uint16_t* __restrict__ re, 
   }
 }
 
-hipError_t launch_sweep_re(uint16_t* re, uint64_t n, uint64_t* act, const Geo& geo,
-                           const PipeState* ps, const unsigned long long* fill_part,
-                           unsigned long long* row_fill, double* up, hipStream_t st) {
+// The snapshot's sweeps in one launch: blocks [0, u * le_tiles) take the LE
+// tiles (row by row), the rest the RE tiles, side by side.
+__global__ __launch_bounds__(kBlock) void k_sweep(uint16_t* __restrict__ le,
+                                                 uint64_t* __restrict__ bitmap,
+                                                 unsigned long long* __restrict__ fill_part,
+                                                 uint64_t row_cells, uint32_t le_tiles,
+                                                 uint32_t u, uint16_t* __restrict__ re,
+                                                 uint64_t n_re, uint64_t* __restrict__ act,
+                                                 const PipeState* __restrict__ ps, uint32_t k) {
+  __shared__ uint32_t part[kBlock / kWave];
+  const uint32_t now = ps->snap;   // the slice being snapshotted
+  const uint32_t b = blockIdx.x, n_le_blocks = le_tiles * u;
+  if (b < n_le_blocks)
+    sweep_le_tile(le, bitmap, fill_part, row_cells, now, k, b % le_tiles, b / le_tiles, part);
+  else
+    sweep_re_tile(re, n_re, act, now, k, b - n_le_blocks);
+}
+
+hipError_t launch_sweep(uint16_t* le, uint64_t* bitmap, unsigned long long* fill_part,
+                        uint16_t* re, uint64_t n_re, uint64_t* act, const Geo& geo,
+                        const PipeState* ps, hipStream_t st) {
+  const uint64_t row_cells = (uint64_t)geo.v_le * geo.G;
+  const uint64_t le_tiles = (row_cells + kSweepTile - 1) / kSweepTile;
   const uint64_t per = (uint64_t)8 * kBlock * kReSteps;
-  const uint64_t blocks = n ? (n + per - 1) / per : 1;
-  hipLaunchKernelGGL(k_sweep_re, dim3((uint32_t)blocks), dim3(kBlock), 0, st, re, n, act, ps,
-                     geo.k, fill_part, row_fill, geo.u, geo.G, geo.v_le, up);
+  const uint64_t re_tiles = n_re ? (n_re + per - 1) / per : 1;
+  const uint64_t blocks = le_tiles * geo.u + re_tiles;
+  if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sweep, dim3((uint32_t)blocks), dim3(kBlock), 0, st, le, bitmap, fill_part,
+                     row_cells, (uint32_t)le_tiles, geo.u, re, n_re, act, ps, geo.k);
   return hipGetLastError();
+}
+
+// |LDR(i)|^k from the LE sweep's partial sums and Eq8, by one block
+__device__ __forceinline__ void fold_row_fills(const unsigned long long* __restrict__ fill_part,
+                                               unsigned long long* __restrict__ row_fill,
+                                               uint32_t u, uint32_t G, uint32_t v_le,
+                                               double* __restrict__ up) {
+  // one wave per row: lane l adds slot l
+  const uint32_t lane0 = threadIdx.x & (kWave - 1);
+  for (uint32_t r = threadIdx.x / kWave; r < u; r += kBlock / kWave) {
+    unsigned long long v = lane0 < kFillSlots ? fill_part[(uint64_t)r * kFillSlots + lane0] : 0ull;
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane0 == 0) row_fill[r] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *up = eq8(row_fill, u, G, v_le);
 }
 
 // The g "now" and g "next" activity bits of the SRE in row r, column col
@@ -312,7 +317,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict_
                                                     const uint64_t* __restrict__ act,
                                                     const uint32_t* __restrict__ si_cnt,
                                                     Geo geo, uint8_t* __restrict__ mark,
-                                                    Counters* __restrict__ cnt) {
+                                                    Counters* __restrict__ cnt,
+                                                    const unsigned long long* __restrict__ fill_part,
+                                                    unsigned long long* __restrict__ row_fill,
+                                                    double* __restrict__ up) {
+  // the snapshot's LE sweep left partial row sums: block 0 folds them and
+  // evaluates Eq8 for the estimate that follows
+  if (fill_part && blockIdx.x == 0) fold_row_fills(fill_part, row_fill, geo.u, geo.G, geo.v_le, up);
   const uint32_t n = *n_dev;
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   uint32_t firsts = 0;
@@ -366,16 +377,17 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const uint32_t* __restrict_
 
 hipError_t launch_finalize(const uint32_t* sorted, const uint32_t* n_dev, const uint64_t* act,
                            const uint32_t* si_cnt, const Geo& geo, uint8_t* mark, Counters* cnt,
-                           hipStream_t st) {
+                           const unsigned long long* fill_part, unsigned long long* row_fill,
+                           double* up, hipStream_t st) {
   if (geo.u <= 4)
     hipLaunchKernelGGL(k_finalize<4>, dim3(kPipeBlocks), dim3(kBlock), 0, st, sorted, n_dev, act,
-                       si_cnt, geo, mark, cnt);
+                       si_cnt, geo, mark, cnt, fill_part, row_fill, up);
   else if (geo.u <= 8)
     hipLaunchKernelGGL(k_finalize<8>, dim3(kPipeBlocks), dim3(kBlock), 0, st, sorted, n_dev, act,
-                       si_cnt, geo, mark, cnt);
+                       si_cnt, geo, mark, cnt, fill_part, row_fill, up);
   else
     hipLaunchKernelGGL(k_finalize<16>, dim3(kPipeBlocks), dim3(kBlock), 0, st, sorted, n_dev,
-                       act, si_cnt, geo, mark, cnt);
+                       act, si_cnt, geo, mark, cnt, fill_part, row_fill, up);
   return hipGetLastError();
 }
 

@@ -473,7 +473,8 @@ int reserve_touched(srla_monitor* m, uint64_t need) {
 // Enqueues one phase of the end-of-slice pipeline of parity p on stream st.
 // Every argument is fixed per (phase, parity), so the sequence can also be
 // recorded once into a graph.
-// The snapshot: |LDR(i)|^k, Eq8 and the activity maps of the closing slice.
+// The snapshot: the partial sums of |LDR(i)|^k and the activity maps of the
+// closing slice (the discrete form: the row fills and Eq8 as well).
 hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
   const Geo& geo = m->geo;
   hipError_t e = hipSuccess;
@@ -493,11 +494,11 @@ hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
     if (e == hipSuccess)
       e = launch_fill_u32((uint32_t*)m->rebits[p ^ 1], 0u, 4 * bitmap_words(m->n_re), st);
   } else {
+    // the row fills and Eq8 are folded from the partial sums by the
+    // candidate check's first kernel
     if (e == hipSuccess)
-      e = launch_sweep_le(m->le, m->bitmap[p], m->fill_part[p], geo, m->ps, st);
-    if (e == hipSuccess)
-      e = launch_sweep_re(m->re, m->n_re, m->act[p], geo, m->ps, m->fill_part[p],
-                          m->row_fill[p], m->up[p], st);
+      e = launch_sweep(m->le, m->bitmap[p], m->fill_part[p], m->re, m->n_re, m->act[p], geo,
+                       m->ps, st);
   }
   if (spans) span_end(m, st, ST_SWEEP, ta);
   return e;
@@ -551,7 +552,8 @@ hipError_t enqueue_check(srla_monitor* m, int p, hipStream_t st) {
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
-  e = launch_finalize(m->touched[p], tc, re_act, m->si_cnt, geo, m->mark, m->cnt, st);
+  e = launch_finalize(m->touched[p], tc, re_act, m->si_cnt, geo, m->mark, m->cnt,
+                      m->discrete ? nullptr : m->fill_part[p], m->row_fill[p], m->up[p], st);
   if (e == hipSuccess)
     e = compact_u32(m->mark, 1u, m->touched[p], tc, m->touched_cap, m->news, &m->cnt->n_new,
                     m->blockw, st);
