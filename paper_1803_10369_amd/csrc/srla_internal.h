@@ -101,6 +101,9 @@ struct PipeState {
                          // the snapshot keeps its own count so that it need not
                          // wait for the previous slice's candidate work
   uint32_t pad;
+  uint32_t snap_code[2]; // the same for the sweep of the stamp arrays, by the
+                         // parity of the slice snapshotted (the sweep of parity
+                         // p reads the code of p ^ 1 and writes that of p)
   // the partitioned scan's last kernel: each workgroup raises slot
   // blockIdx % kEndSlots to the clock when it is done (few workgroups per
   // slot, so the atomics do not queue on one address); the end of the scan
@@ -180,13 +183,15 @@ hipError_t launch_scan_group(const uint32_t* pairs, uint64_t n, const GroupMembe
                              uint32_t n_members, const GroupScanArgs& args, uint32_t max_blocks,
                              hipStream_t st);
 
-// The snapshot's sweeps in one launch: |LDR(i)|^k by row into kFillSlots
-// partial sums per row (fill_part, u x kFillSlots, zero beforehand), the LE
+// The snapshot in one launch (slice parity p): the slice's close (the end of
+// its scans, its stamp code), |LDR(i)|^k by row into kFillSlots partial sums
+// per row (fill_part, u x kFillSlots, zero beforehand; the fold clears it
+// again), the LE
 // activity bitmap and scrub; the SRE activity maps (inside the window now /
 // after the slide) and scrub
 hipError_t launch_sweep(uint16_t* le, uint64_t* bitmap, unsigned long long* fill_part,
                         uint16_t* re, uint64_t n_re, uint64_t* act, const Geo& geo,
-                        const PipeState* ps, hipStream_t st);
+                        PipeState* ps, uint32_t p, hipStream_t st);
 
 // keys-only LSD radix sort of *n_dev uint32 keys (n_dev <= n_max), in place
 // (tmp is scratch).  block_hist needs radix_hist_words(n_max) words.

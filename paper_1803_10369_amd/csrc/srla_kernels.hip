@@ -48,6 +48,29 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, uint64_t n, hipStream_t 
 constexpr int kSweepSteps = 8;
 constexpr uint64_t kSweepTile = (uint64_t)kBlock * 8 * kSweepSteps;  // DRs per block
 
+// The slice's close, by one wavefront: the end of its scans is the latest of
+// the marker's clock and the partitioned scan's slots, which start over at
+// zero (a slice without scans: now); the snapshot's stamp code is recorded
+// for the other parity's next snapshot.
+__device__ __forceinline__ void close_slice_clock(PipeState* __restrict__ ps, uint32_t p,
+                                                  uint32_t lane, uint32_t now) {
+  unsigned long long t = ps->t_end[p][lane];
+  ps->t_end[p][lane] = 0ull;
+  for (int d = kWave / 2; d >= 1; d >>= 1) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)t, d);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(t >> 32), d);
+    const unsigned long long o = ((unsigned long long)hi << 32) | lo;
+    t = o > t ? o : t;
+  }
+  if (lane == 0) {
+    const unsigned long long ts = ps->t_scan[p] > t ? ps->t_scan[p] : t;
+    ps->t_close[p] = ps->scanned[p] ? ts : wall_clock64();
+    ps->t_scan[p] = 0ull;
+    ps->scanned[p] = 0u;
+    ps->snap_code[p] = now;
+  }
+}
+
 // LE tile bx of row `row`
 __device__ __forceinline__ void sweep_le_tile(uint16_t* __restrict__ le,
                                               uint64_t* __restrict__ bitmap,
@@ -209,10 +232,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep(uint16_t* __restrict__ le,
                                                  uint64_t row_cells, uint32_t le_tiles,
                                                  uint32_t u, uint16_t* __restrict__ re,
                                                  uint64_t n_re, uint64_t* __restrict__ act,
-                                                 const PipeState* __restrict__ ps, uint32_t k) {
+                                                 PipeState* __restrict__ ps, uint32_t p,
+                                                 uint32_t k) {
   __shared__ uint32_t part[kBlock / kWave];
-  const uint32_t now = ps->snap;   // the slice being snapshotted
+  // the slice being snapshotted: the code after the other parity's
+  const uint32_t now = ps->snap_code[p ^ 1u] % kStampPeriod + 1u;
   const uint32_t b = blockIdx.x, n_le_blocks = le_tiles * u;
+  if (b == 0 && threadIdx.x < kWave) close_slice_clock(ps, p, threadIdx.x, now);
   if (b < n_le_blocks)
     sweep_le_tile(le, bitmap, fill_part, row_cells, now, k, b % le_tiles, b / le_tiles, part);
   else
@@ -221,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(uint16_t* __restrict__ le,
 
 hipError_t launch_sweep(uint16_t* le, uint64_t* bitmap, unsigned long long* fill_part,
                         uint16_t* re, uint64_t n_re, uint64_t* act, const Geo& geo,
-                        const PipeState* ps, hipStream_t st) {
+                        PipeState* ps, uint32_t p, hipStream_t st) {
   const uint64_t row_cells = (uint64_t)geo.v_le * geo.G;
   const uint64_t le_tiles = (row_cells + kSweepTile - 1) / kSweepTile;
   const uint64_t per = (uint64_t)8 * kBlock * kReSteps;
@@ -229,7 +255,7 @@ hipError_t launch_sweep(uint16_t* le, uint64_t* bitmap, unsigned long long* fill
   const uint64_t blocks = le_tiles * geo.u + re_tiles;
   if (blocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sweep, dim3((uint32_t)blocks), dim3(kBlock), 0, st, le, bitmap, fill_part,
-                     row_cells, (uint32_t)le_tiles, geo.u, re, n_re, act, ps, geo.k);
+                     row_cells, (uint32_t)le_tiles, geo.u, re, n_re, act, ps, p, geo.k);
   return hipGetLastError();
 }
 
@@ -238,10 +264,15 @@ __device__ __forceinline__ void fold_row_fills(const unsigned long long* __restr
                                                unsigned long long* __restrict__ row_fill,
                                                uint32_t u, uint32_t G, uint32_t v_le,
                                                double* __restrict__ up) {
-  // one wave per row: lane l adds slot l
+  // one wave per row: lane l adds slot l and clears it for the parity's
+  // next snapshot
   const uint32_t lane0 = threadIdx.x & (kWave - 1);
   for (uint32_t r = threadIdx.x / kWave; r < u; r += kBlock / kWave) {
-    unsigned long long v = lane0 < kFillSlots ? fill_part[(uint64_t)r * kFillSlots + lane0] : 0ull;
+    unsigned long long v = 0ull;
+    if (lane0 < kFillSlots) {
+      v = fill_part[(uint64_t)r * kFillSlots + lane0];
+      const_cast<unsigned long long*>(fill_part)[(uint64_t)r * kFillSlots + lane0] = 0ull;
+    }
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if (lane0 == 0) row_fill[r] = v;
   }

@@ -481,10 +481,9 @@ hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
   hipEvent_t ta = nullptr;
   const bool spans = !m->use_graph;
   if (spans) span_begin(m, st, &ta);
-  e = m->discrete ? launch_begin_close(m->ps, m->row_fill[p], geo.u, (uint32_t)p, st)
-                  : launch_begin_close(m->ps, m->fill_part[p], geo.u * kFillSlots, (uint32_t)p, st);
-  if (e != hipSuccess) return e;
   if (m->discrete) {
+    e = launch_begin_close(m->ps, m->row_fill[p], geo.u, (uint32_t)p, st);
+    if (e != hipSuccess) return e;
     // the closing slice's bits are its activity maps already; the other
     // parity's (the previous slice's) are cleared for the next slice's scans
     if (e == hipSuccess) e = launch_row_popcount(m->lebits[p], m->row_fill[p], geo, st);
@@ -494,11 +493,10 @@ hipError_t enqueue_snapshot(srla_monitor* m, int p, hipStream_t st) {
     if (e == hipSuccess)
       e = launch_fill_u32((uint32_t*)m->rebits[p ^ 1], 0u, 4 * bitmap_words(m->n_re), st);
   } else {
-    // the row fills and Eq8 are folded from the partial sums by the
-    // candidate check's first kernel
-    if (e == hipSuccess)
-      e = launch_sweep(m->le, m->bitmap[p], m->fill_part[p], m->re, m->n_re, m->act[p], geo,
-                       m->ps, st);
+    // one launch: the close, the sweeps; the row fills and Eq8 are folded
+    // from the partial sums by the candidate check's first kernel
+    e = launch_sweep(m->le, m->bitmap[p], m->fill_part[p], m->re, m->n_re, m->act[p], geo, m->ps,
+                     (uint32_t)p, st);
   }
   if (spans) span_end(m, st, ST_SWEEP, ta);
   return e;
@@ -953,6 +951,8 @@ int srla_create(const srla_config_t* cfg, void* hip_stream, srla_monitor_t** out
     if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->re, 0u, (m->n_re + 8) / 2, m->stream);
   }
   if (e == hipSuccess) e = launch_fill_u32(m->si_cnt, 0u, 16 * m->n_si, m->stream);
+  for (int i = 0; i < 2 && e == hipSuccess && !m->discrete; ++i)
+    e = launch_fill_u32((uint32_t*)m->fill_part[i], 0u, 2ull * m->geo.u * kFillSlots, m->stream);
   if (e == hipSuccess) e = launch_fill_u32((uint32_t*)m->cnt, 0u, sizeof(Counters) / 4, m->stream);
   if (e == hipSuccess) e = launch_fill_u32(m->tcount, 0u, 2, m->stream);
   if (e == hipSuccess) e = launch_fill_u32(m->claim, 0u, 2, m->stream);
