@@ -811,7 +811,8 @@ def main():
     sweep_ms = stages["sweep_ms"]
     read_rate = probe.stream_read_rate(2 * (n_le + n_re))
     out["roofline_sweep"] = {
-        "kernel": "k_sweep_le + k_sweep_re (the snapshot phase, k_begin_close included)",
+        "kernel": "k_sweep (the snapshot phase: the slice's close, the LE and SRE sweeps in "
+                  "one launch)",
         "bound": level, "bytes_per_slice": sweep_bytes, "phase_ms": sweep_ms,
         "achieved_GBps": sweep_bytes / (sweep_ms * 1e-3) / 1e9 if sweep_ms > 0 else None,
         "ceiling_GBps": read_rate / 1e9,
