@@ -470,6 +470,10 @@ def main():
     ap.add_argument("--segment", type=int, default=200,
                     help="timed slices whose inputs are generated into HBM at a time")
     ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--stage-steps", type=int, default=20,
+                    help="untimed slices after the timed ones with every stage timed (the "
+                         "timed slices time their scans only: each timed stage costs event "
+                         "records on the critical path)")
     ap.add_argument("--warmup", type=int, default=5,
                     help="untimed slices in the measured form before the timed ones (after "
                          "the k - 1 slices that fill the window)")
@@ -679,6 +683,10 @@ def main():
     compare = args.mode == "streaming" and args.compare_steps > 0
     runs = {args.mode: Timed(), "plain": Timed()}
     turns = [(args.mode, args.steps)] + ([("plain", args.compare_steps)] if compare else [])
+    # the timed slices time only their scans (the roofline's launch time): a
+    # timed stage costs two event records on its stream, about 8 % of the
+    # throughput when every stage of every slice is timed
+    m.set_timing(srla.SRLA_TIMING_SCANS)
     m.timings(reset=True)
     while any(runs[mode].done < steps for mode, steps in turns):
         for mode, steps in turns:
@@ -695,6 +703,15 @@ def main():
     total_s, lat, host_lat = main_run.total, np.array(main_run.lat), np.array(main_run.host_lat)
     cands, full, r, tm = main_run.cands, main_run.full, main_run.r, main_run.tm
     timed_slices = main_run.slices
+    # the stage breakdown: more slices of the measured form, every stage timed
+    m.set_timing(True)
+    m.timings(reset=True)
+    stage_tm, stage_slices = {}, []
+    if args.stage_steps > 0:
+        segment(args.mode, first, args.stage_steps)
+        stage_tm = m.timings(reset=True)
+        stage_slices = [first, first + args.stage_steps - 1]
+        first += args.stage_steps
 
     pairs = args.steps * n_pairs
     value = pairs / total_s
@@ -709,7 +726,7 @@ def main():
                    "k_scan_dedup" if args.scan_dedup else
                    "k_scan_lds_filter" if args.scan_lds_filter else
                    "k_scan_xcd" if args.scan_xcd else "k_scan_flat")
-    stages = {k: tm[k] / max(1, tm["estimates"]) for k in
+    stages = {k: stage_tm.get(k, 0.0) / max(1, stage_tm.get("estimates", 0)) for k in
               ("scan_ms", "sweep_ms", "finalize_ms", "estimate_ms", "slide_ms", "report_ms")}
     # the DR arrays the scan stores into: in the 256 MB last-level cache
     # (Infinity Cache) or beyond it in HBM
@@ -753,6 +770,9 @@ def main():
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "stage_ms_per_slice": stages,
+        "stage_timing": ("slices %s after the timed ones, every stage timed (HIP events "
+                         "around each stage); the timed slices time their scans only"
+                         % (stage_slices,)),
         "state": {"window_full": bool(all(full)),
                   "candidates": [min(cands), max(cands)],
                   "up": r.up,

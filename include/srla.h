@@ -126,11 +126,15 @@ enum {
                                   without a scan beside it (the scans
                                   overlap only Algorithm 3's carried list
                                   and SI update, which the report does not
-                                  wait for).  The host can still close e
-                                  and issue e+1's scans at once, so no host
-                                  round trip separates a slice's scans from
-                                  its end-of-slice work.  Results are
-                                  identical; no effect with
+                                  wait for).  The sort, the candidate check,
+                                  the estimate and the report then run on
+                                  the monitor's (scan) stream, in order
+                                  after the scans, and the next scans
+                                  follow them there.  The host can still
+                                  close e and issue e+1's scans at once, so
+                                  no host round trip separates a slice's
+                                  scans from its end-of-slice work.
+                                  Results are identical; no effect with
                                   SRLA_CFG_OVERLAP_REPORT */
 };
 
@@ -370,10 +374,14 @@ int srla_timings(srla_monitor_t *m, srla_timings_t *out, int reset);
  * Switches the per-stage timing on (enabled != 0) or off for the calls that
  * follow: scans issued and slices closed while it is on are timed (a closed
  * slice's stages are timed as it was when it was closed).  Each timed stage
- * costs two HIP event records on its stream, so a caller that needs the
- * times but not for every slice can time a sample of the slices.  Totals
- * are kept across switches.  Errors: SRLA_E_INVAL (NULL monitor).
+ * costs two HIP event records on its stream, and a record costs the stream
+ * some microseconds (a backbone slice: 14.4 G packets/s with every stage
+ * timed, 15.6 G untimed), so a caller that needs the times but not for every
+ * slice can time a sample of the slices.  enabled == SRLA_TIMING_SCANS times
+ * the scans only (scan_ms, scan_launches, scan_pairs).  Totals are kept
+ * across switches.  Errors: SRLA_E_INVAL (NULL monitor).
  */
+#define SRLA_TIMING_SCANS 2
 int srla_set_timing(srla_monitor_t *m, int enabled);
 
 /*

@@ -12,4 +12,4 @@ from .srla import (Monitor, Report, SrlaError, Group, srla_group_create, srla_gr
                    srla_dump_state, srla_estimate, srla_footprint_bytes, srla_last_error,
                    srla_scan, srla_scan_noalloc, srla_timings, SRLA_DUMP_LE, SRLA_DUMP_RE, SRLA_DUMP_SI,
                    SRLA_FLAG_SUPER, SRLA_FLAG_SAT, SRLA_FLAG_NEW, SRLA_FLAG_KEEP, EXPORTS,
-                   SRLA_OK, SRLA_E_INVAL, SRLA_E_CAPACITY, SRLA_E_STATE)
+                   SRLA_OK, SRLA_E_INVAL, SRLA_E_CAPACITY, SRLA_E_STATE, SRLA_TIMING_SCANS)

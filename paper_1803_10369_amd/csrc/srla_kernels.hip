@@ -534,29 +534,43 @@ hipError_t launch_merge_runs(const uint32_t* in, const uint32_t* na, const uint3
 // The carried list NCSIP_t is the head of the next slice's report: its *n
 // addresses go into that report's ip array (pinned host memory) now, beside
 // the next slice's scans, instead of after its candidate check.
+//
+// Stores into host memory go out over PCIe, far slower than HBM, and they
+// hold up the other traffic of the caches they pass: from workgroups spread
+// over the XCDs, with ordinary stores, the next slice's partition kernel ran
+// 262 instead of 133 us beside the copy.  So the copy runs on one XCD only
+// (workgroups are dispatched to the XCDs round-robin: only the blocks with
+// blockIdx % kPrecopyXcds == 0 work, the others return at once) and with
+// non-temporal stores, which still fill the link (9 MB in about 170 us) but
+// leave that kernel almost untouched (a standalone copy of 9 MB beside the
+// partition kernel: 139 us alone, 139 us beside 8 such workgroups, 188 us
+// beside 16 ordinary spread ones).
+constexpr uint32_t kPrecopyXcds = 8;
+constexpr uint32_t kPrecopyBlocks = 8;   // working workgroups, all on one XCD
+
 __global__ __launch_bounds__(kBlock) void k_ip_precopy(const uint32_t* __restrict__ src,
                                                       const uint32_t* __restrict__ n_p,
                                                       uint32_t* __restrict__ dst) {
+  if (blockIdx.x % kPrecopyXcds) return;
   const uint64_t n = *n_p;
   const uint64_t n4 = n / 4;
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  const uint64_t t = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  for (uint64_t i = t; i < n4; i += stride)
-    reinterpret_cast<uint4*>(dst)[i] = reinterpret_cast<const uint4*>(src)[i];
-  if (t < n - n4 * 4) dst[n4 * 4 + t] = src[n4 * 4 + t];
+  const uint64_t stride = (uint64_t)(gridDim.x / kPrecopyXcds) * kBlock;
+  const uint64_t t = (uint64_t)(blockIdx.x / kPrecopyXcds) * kBlock + threadIdx.x;
+  for (uint64_t i = t; i < n4; i += stride) {
+    const uint4 v = reinterpret_cast<const uint4*>(src)[i];
+    uint32_t* d = dst + 4 * i;   // one 16-byte non-temporal store
+    __builtin_nontemporal_store(v.x, d);
+    __builtin_nontemporal_store(v.y, d + 1);
+    __builtin_nontemporal_store(v.z, d + 2);
+    __builtin_nontemporal_store(v.w, d + 3);
+  }
+  if (t < n - n4 * 4) __builtin_nontemporal_store(src[n4 * 4 + t], dst + n4 * 4 + t);
 }
-
-// a small grid: the copy runs beside the next slice's scans, and while its
-// writes stream into host memory the scans' kernels start late (the command
-// processor's reads of their dispatch packets queue behind the writes).  On
-// the backbone workload (9 MB per slice) 16 workgroups gave 12.9 G packets/s
-// against 12.2 G with 64 (the scan 0.33 instead of 0.36 ms) and 12.7 G with
-// 4, whose copy no longer ends before the next slice's candidate work
-constexpr uint32_t kPrecopyBlocks = 16;
 
 hipError_t launch_ip_precopy(const uint32_t* src, const uint32_t* n, uint32_t* dst,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_ip_precopy, dim3(kPrecopyBlocks), dim3(kBlock), 0, st, src, n, dst);
+  hipLaunchKernelGGL(k_ip_precopy, dim3(kPrecopyXcds * kPrecopyBlocks), dim3(kBlock), 0, st, src,
+                     n, dst);
   return hipGetLastError();
 }
 

@@ -242,16 +242,15 @@ struct srla_monitor {
   int stage_next = 0;
 
   // timing (switched per call by srla_set_timing); timed[p]: the slice of
-  // parity p was closed with timing on
+  // parity p was closed with timing on; time_scans: only the scans are timed
   bool timing = false;
+  bool time_scans = false;
   bool timed[2] = {false, false};
   bool xcd_scan = false;
   bool dedup_scan = false;
   bool filter_scan = false;
   bool part_scan = false;
   bool hold_scans = false;       // scans wait for the closed slice's report
-  bool hold_pending = false;     // the next scan waits for ev_pub[hold_parity]
-  int hold_parity = 0;
   std::vector<TimedSpan> spans;
   std::vector<hipEvent_t> ev_pool;
   double acc_ms[ST_N] = {0, 0, 0, 0, 0, 0};
@@ -324,14 +323,6 @@ hipError_t wait_unless_done(hipStream_t st, hipEvent_t ev) {
   return hipStreamWaitEvent(st, ev, 0);
 }
 
-// SRLA_CFG_HOLD_SCANS: the first scan after a close waits (on stream st) for
-// the closed slice's report to be published
-hipError_t apply_hold(srla_monitor* m, hipStream_t st) {
-  if (!m->hold_pending) return hipSuccess;
-  m->hold_pending = false;
-  return hipStreamWaitEvent(st, m->ev_pub[m->hold_parity], 0);
-}
-
 uint64_t bitmap_words(uint64_t cells) { return (cells + 63) / 64 + 1; }
 
 // device copies of the host report sets' est and flags arrays (9 bytes per
@@ -391,15 +382,16 @@ hipEvent_t pooled_event(srla_monitor* m) {
   return e;
 }
 
-void span_begin(srla_monitor* m, hipStream_t st, hipEvent_t* a) {
+void span_begin(srla_monitor* m, hipStream_t st, hipEvent_t* a, bool scan = false) {
   *a = nullptr;
-  if (!m->timing) return;
+  if (!m->timing && !(scan && m->time_scans)) return;
   *a = pooled_event(m);
   if (*a) (void)hipEventRecord(*a, st);
 }
 
+// a: what span_begin returned (null: the span is not timed)
 void span_end(srla_monitor* m, hipStream_t st, int stage, hipEvent_t a) {
-  if (!m->timing || !a) return;
+  if (!a) return;
   hipEvent_t b = pooled_event(m);
   if (!b) { m->ev_pool.push_back(a); return; }
   (void)hipEventRecord(b, st);
@@ -994,7 +986,7 @@ hipError_t enqueue_scan(srla_monitor* m, const uint32_t* pairs, uint64_t n, int 
     return launch_scan_bits(pairs, n, m->geo, m->lebits[p], m->rebits[p], m->sset[p],
                             m->set_slots, m->touched[p], m->tcount + p, m->cfg.scan_blocks,
                             m->stream);
-  m->sampled_pending = m->part_scan && !m->overlap_report;
+  m->sampled_pending = m->part_scan && !m->overlap_report && !m->hold_scans;
   if (m->part_scan)
     return launch_scan_partition(pairs, n, m->geo, code, m->le, m->re, m->touched[p],
                                  m->tcount + p, m->part_entries, m->part_offs, m->part_marks,
@@ -1033,7 +1025,7 @@ int enqueue_finish(srla_monitor* m, bool go) {
     ~TimingAs() { m->timing = saved; }
   } timing_as(m, m->timed[pc]);
   hipEvent_t ta;
-  if (!m->overlap_report) {
+  if (!m->overlap_report && !m->hold_scans) {
     // the sort needs the slice's scans only: it runs beside the snapshot
     HIP_TRY(m, hipStreamWaitEvent(m->pipe_use, m->ev_sort, 0));
     if (m->use_graph) span_begin(m, m->pipe_use, &ta);
@@ -1041,13 +1033,21 @@ int enqueue_finish(srla_monitor* m, bool go) {
     if (rs) return rs;
     if (m->use_graph) span_end(m, m->pipe_use, ST_FINALIZE, ta);
   }
-  HIP_TRY(m, hipStreamWaitEvent(m->pipe_use, m->ev_snap, 0));
-  if (m->use_graph) span_begin(m, m->pipe_use, &ta);
-  int rc = run_phase(m, go ? PH_FINISH_GO : PH_FINISH, cc, m->pipe_use);
+  // with held scans the candidate work and the report run on the scan
+  // stream, in order after the snapshot, and the next slice's scans follow
+  // them there: no wait between streams on the way from the last scan to the
+  // report and on to the next scan, and the end-of-slice work has the GPU to
+  // itself (the scans overlap only Algorithm 3's carried list and SI update
+  // on the pipeline stream)
+  hipStream_t fs = m->hold_scans ? m->stream : m->pipe_use;
+  if (!m->hold_scans) HIP_TRY(m, hipStreamWaitEvent(m->pipe_use, m->ev_snap, 0));
+  if (m->use_graph) span_begin(m, fs, &ta);
+  int rc = run_phase(m, go ? PH_FINISH_GO : PH_FINISH, cc, fs);
   if (rc) return rc;
-  if (m->use_graph) span_end(m, m->pipe_use, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
-  HIP_TRY(m, hipEventRecord(m->ev_pub[pc], m->pipe_use));
+  if (m->use_graph) span_end(m, fs, m->overlap_report ? ST_REPORT : ST_ESTIMATE, ta);
+  HIP_TRY(m, hipEventRecord(m->ev_pub[pc], fs));
   if (!m->overlap_report) {
+    if (m->hold_scans) HIP_TRY(m, hipStreamWaitEvent(m->pipe_use, m->ev_pub[pc], 0));
     if (m->use_graph) span_begin(m, m->pipe_use, &ta);
     rc = run_phase(m, PH_SLIDE, cc, m->pipe_use);
     if (rc) return rc;
@@ -1080,7 +1080,6 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   const int p = (int)(m->slice & 1);
   int rc = reserve_touched(m, m->slice_pairs[p] + n);
   if (rc) return rc;
-  HIP_TRY(m, apply_hold(m, m->stream));
   // the first scan after an overlapped close sets the scan-start mark; the
   // deferred second phase of the closed slice is enqueued after it, and its
   // report copy waits for the mark (see enqueue_finish)
@@ -1088,14 +1087,14 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
   const uint32_t mark = go ? (uint32_t)p + 1u : 0u;
   if (on_device) {
     hipEvent_t a;
-    span_begin(m, m->stream, &a);
+    span_begin(m, m->stream, &a, true);
     HIP_TRY(m, enqueue_scan(m, pairs, n, p, mark));
     span_end(m, m->stream, ST_SCAN, a);
     // the partitioned scan records its own end; other forms get a marker
     if (!m->part_scan || m->discrete)
       HIP_TRY(m, launch_scan_end(m->ps, (uint32_t)p, m->stream));
     m->slice_pairs[p] += n;
-    if (m->timing) {
+    if (m->timing || m->time_scans) {
       m->scan_launches++;
       m->scan_pairs += n;
     }
@@ -1141,7 +1140,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     m->stage_busy[b] = true;
     HIP_TRY(m, hipStreamWaitEvent(m->stream, m->stage_ev[b], 0));
     hipEvent_t a;
-    span_begin(m, m->stream, &a);
+    span_begin(m, m->stream, &a, true);
     HIP_TRY(m, enqueue_scan(m, m->d_stage[b], cnt, p, go ? mark : 0u));
     span_end(m, m->stream, ST_SCAN, a);
     if (!m->part_scan || m->discrete)
@@ -1154,7 +1153,7 @@ int srla_scan(srla_monitor_t* m, const uint32_t* pairs, uint64_t n, int on_devic
     HIP_TRY(m, hipEventRecord(m->scanned_ev[b], m->stream));
     m->scanned_set[b] = true;
     m->slice_pairs[p] += cnt;
-    if (m->timing) {
+    if (m->timing || m->time_scans) {
       m->scan_launches++;
       m->scan_pairs += cnt;
     }
@@ -1180,15 +1179,14 @@ int srla_scan_noalloc(srla_monitor_t* m, const uint32_t* pairs, uint64_t n) {
                 "srla_scan_noalloc: the slice's pairs exceed the sampled-source capacity");
   uint8_t* base = static_cast<uint8_t*>(noalloc_scratch(m->device));
   if (!base) return fail(m, SRLA_E_DEVICE, "srla_scan_noalloc: no scratch on this device");
-  HIP_TRY(m, apply_hold(m, m->stream));
   uint16_t* entries = reinterpret_cast<uint16_t*>(base);
   uint32_t* marks = reinterpret_cast<uint32_t*>(base + kNoAllocEntryBytes);
   uint16_t* offs = reinterpret_cast<uint16_t*>(base + kNoAllocEntryBytes + kNoAllocMarkBytes);
-  m->sampled_pending = true;
+  m->sampled_pending = !m->hold_scans;
   HIP_TRY(m, launch_scan_partition(pairs, n, m->geo, stamp_code(m->slice), m->le, m->re,
                                    m->touched[p], m->tcount + p, entries, offs, marks,
                                    m->stream, kNoAllocChunks, m->ps, (uint32_t)p, kPartUnit,
-                                   m->ev_sampled));
+                                   m->sampled_pending ? m->ev_sampled : nullptr));
   m->slice_pairs[p] += n;
   return SRLA_OK;
 }
@@ -1214,7 +1212,7 @@ int srla_close_slice(srla_monitor_t* m) {
   // the slice's sampled sources are all appended (after the partitioned
   // scan's partition kernel, so the sort runs beside its marking and
   // stamping; else after the scans): the pipeline stream may sort them
-  if (!m->overlap_report) {
+  if (!m->overlap_report && !m->hold_scans) {
     if (m->sampled_pending) {
       m->ev_sort = m->ev_sampled;
     } else {
@@ -1229,13 +1227,24 @@ int srla_close_slice(srla_monitor_t* m) {
   // (with the candidate work when the report copy overlaps the next scans),
   // the second as the estimate (as the report copy when it overlaps)
   hipEvent_t ta;
+  if (m->hold_scans) {
+    // the scans wait for the report anyway: the sort follows them on their
+    // stream, where it neither waits for an event nor queues behind the
+    // previous slice's carried list on the pipeline stream
+    if (m->use_graph) span_begin(m, m->stream, &ta);
+    const int rs = run_phase(m, PH_SORT, (int)(m->slice % kCycle), m->stream);
+    if (rs) return rs;
+    if (m->use_graph) span_end(m, m->stream, ST_FINALIZE, ta);
+  }
   if (m->use_graph) span_begin(m, m->stream, &ta);
   int rc = run_phase(m, PH_SNAPSHOT, (int)(m->slice % kCycle), m->stream);
   if (rc) return rc;
   if (m->use_graph) span_end(m, m->stream, m->overlap_report ? ST_ESTIMATE : ST_SWEEP, ta);
-  HIP_TRY(m, hipEventRecord(m->ev_snap, m->stream));
+  if (!m->hold_scans) HIP_TRY(m, hipEventRecord(m->ev_snap, m->stream));
   // the next slice's scans reuse the sampled-source list and count of the
-  // previous slice's parity: they wait for its second phase
+  // previous slice's parity: they wait for its second phase (with held
+  // scans this slice's candidate work, next on this stream, needs it too:
+  // Algorithm 3's carried list and SI counters of the previous slice)
   if (!m->overlap_report && !m->discrete && m->slice >= 1)
     HIP_TRY(m, wait_unless_done(m->stream, m->ev_done[p ^ 1]));
   m->n_pending++;
@@ -1247,16 +1256,7 @@ int srla_close_slice(srla_monitor_t* m) {
     m->finish_deferred = true;
     return SRLA_OK;
   }
-  rc = enqueue_finish(m, false);
-  if (rc) return rc;
-  // the next slice's scans start once this slice's report is in host memory:
-  // its end-of-slice work then has the GPU to itself (the scans overlap only
-  // Algorithm 3's carried list and SI update).  The wait goes on the stream
-  // with the next scan, not here, so that monitors sharing a stream (a group)
-  // close their slices back to back before any of them waits.
-  m->hold_pending = m->hold_scans;
-  m->hold_parity = p;
-  return SRLA_OK;
+  return enqueue_finish(m, false);
 }
 
 int srla_wait_report(srla_monitor_t* m, srla_report_t* out) {
@@ -1371,7 +1371,8 @@ int srla_dump_state(srla_monitor_t* m, int which, uint16_t* host_out, uint64_t c
 
 int srla_set_timing(srla_monitor_t* m, int enabled) {
   if (!m) return SRLA_E_INVAL;
-  m->timing = enabled != 0;
+  m->timing = enabled != 0 && enabled != SRLA_TIMING_SCANS;
+  m->time_scans = enabled == SRLA_TIMING_SCANS;
   return SRLA_OK;
 }
 
@@ -1497,10 +1498,6 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
     args.code[i] = stamp_code(m->slice);
     args.parity |= (uint64_t)p << i;
   }
-  for (srla_monitor* m : g->mons) {
-    const hipError_t e = apply_hold(m, g->stream);
-    if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
-  }
   // members that all scan in partitioned form: each member's partitioned scan
   // over the pairs (the pairs are read once per member, the stores go out in
   // lines) instead of the fused kernel's random stores
@@ -1509,11 +1506,11 @@ int srla_group_scan(srla_group_t* g, const uint32_t* pairs, uint64_t n, int on_d
   if (all_part) {
     for (srla_monitor* m : g->mons) {
       const int p = (int)(m->slice & 1);
-      m->sampled_pending = true;
+      m->sampled_pending = !m->hold_scans;
       const hipError_t e = launch_scan_partition(
           pairs, n, m->geo, stamp_code(m->slice), m->le, m->re, m->touched[p], m->tcount + p,
           m->part_entries, m->part_offs, m->part_marks, g->stream, kPartChunks, nullptr, 0,
-          part_unit_of(&m->cfg), m->ev_sampled);
+          part_unit_of(&m->cfg), m->sampled_pending ? m->ev_sampled : nullptr);
       if (e != hipSuccess) return group_fail(g, SRLA_E_DEVICE, hipGetErrorString(e));
     }
     for (srla_monitor* m : g->mons) {

@@ -19,6 +19,7 @@ SRLA_OK, SRLA_E_INVAL, SRLA_E_NOMEM, SRLA_E_CAPACITY, SRLA_E_STATE, SRLA_E_DEVIC
 SRLA_DUMP_LE, SRLA_DUMP_RE, SRLA_DUMP_SI = 0, 1, 2
 SRLA_FLAG_SUPER, SRLA_FLAG_SAT, SRLA_FLAG_NEW, SRLA_FLAG_KEEP = 1, 2, 4, 8
 SRLA_CFG_TIMING = 1
+SRLA_TIMING_SCANS = 2   # srla_set_timing: time the scans only
 SRLA_CFG_SCAN_XCD = 2
 SRLA_CFG_GRAPH = 4
 SRLA_CFG_DISCRETE = 8
@@ -340,8 +341,9 @@ class Monitor:
         return out
 
     def set_timing(self, enabled):
-        """Times the following scans and closed slices (or not)."""
-        self._check(srla_set_timing(self._h, enabled))
+        """Times the following scans and closed slices (True), the scans only
+        (SRLA_TIMING_SCANS), or nothing (False)."""
+        self._check(srla_set_timing(self._h, int(enabled)))
 
     def timings(self, reset=False):
         t = srla_timings_t()

@@ -400,6 +400,27 @@ def test_timing_can_be_sampled(graph, overlap):
     g.close()
 
 
+def test_timing_scans_only():
+    """SRLA_TIMING_SCANS times the scans and no stage of the slices' ends;
+    switched back to full timing, the stages are counted again."""
+    stream, mon, _ = workload("tiny")
+    g = srla.Monitor(**mon, max_candidates=1 << 16, graph=True, hold_scans=True,
+                     scan_partition=True)
+    o = oracle.Monitor(**mon)
+    g.set_timing(srla.SRLA_TIMING_SCANS)
+    for s in range(4):
+        if s == 3:
+            g.set_timing(True)
+        p = stream.slice(s)
+        g.scan(to_device(p))
+        o.scan(p)
+        compare_reports(g.estimate(), o.estimate(), mon["theta"], "slice %d" % s)
+    t = g.timings(reset=True)
+    assert t["scan_launches"] == 4 and t["scan_pairs"] == 4 * len(stream.slice(0))
+    assert t["scan_ms"] > 0 and t["estimates"] == 1 and t["estimate_ms"] > 0
+    g.close()
+
+
 GROUP = [
     # k, theta, u, v_re, g, v_le, G
     (3, 64, 3, 64, 8, 8, 128),
