@@ -193,11 +193,12 @@ hipError_t launch_sweep(uint16_t* le, uint64_t* bitmap, unsigned long long* fill
                         uint16_t* re, uint64_t n_re, uint64_t* act, const Geo& geo,
                         PipeState* ps, uint32_t p, hipStream_t st);
 
-// keys-only LSD radix sort of *n_dev uint32 keys (n_dev <= n_max), in place
-// (tmp is scratch).  block_hist needs radix_hist_words(n_max) words.
-uint64_t radix_hist_words(uint64_t n);
-hipError_t radix_sort_u32(uint32_t* keys, uint32_t* tmp, const uint32_t* n_dev, uint64_t n_max,
-                          uint32_t* block_hist, hipStream_t st);
+// keys-only ascending sort of *n_dev uint32 keys, in place (tmp is scratch of
+// at least *n_dev words); aux: sort_aux_words() words, zero before the first
+// sort (each sort leaves them so).
+uint64_t sort_aux_words();
+hipError_t sort_u32(uint32_t* keys, uint32_t* tmp, const uint32_t* n_dev, uint32_t* aux,
+                    hipStream_t st);
 
 // exclusive-scan helper storage for compaction of up to n elements
 uint64_t compact_block_words(uint64_t n);

@@ -438,7 +438,7 @@ int reserve_touched(srla_monitor* m, uint64_t need) {
   uint8_t* mk = nullptr;
   if (dalloc(&t0, cap) != hipSuccess || dalloc(&t1, cap) != hipSuccess ||
       dalloc(&tt, cap) != hipSuccess || dalloc(&nw, cap) != hipSuccess ||
-      dalloc(&mk, cap) != hipSuccess || dalloc(&h, radix_hist_words(cap)) != hipSuccess ||
+      dalloc(&mk, cap) != hipSuccess || dalloc(&h, sort_aux_words()) != hipSuccess ||
       dalloc(&bw, compact_block_words(cap)) != hipSuccess) {
     dfree(t0); dfree(t1); dfree(tt); dfree(nw); dfree(mk); dfree(h); dfree(bw);
     (void)hipGetLastError();
@@ -447,6 +447,7 @@ int reserve_touched(srla_monitor* m, uint64_t need) {
   // both streams idle: the pending pipeline may still read the other parity
   HIP_TRY(m, hipStreamSynchronize(m->stream));
   HIP_TRY(m, hipStreamSynchronize(m->pipe_use));
+  HIP_TRY(m, hipMemset(h, 0, sort_aux_words() * sizeof(uint32_t)));   // the sort's counters
   uint32_t* fresh[2] = {t0, t1};
   for (int p = 0; p < 2; ++p) {
     if (m->touched[p] && m->slice_pairs[p])
@@ -504,7 +505,7 @@ hipError_t enqueue_sort(srla_monitor* m, int p, hipStream_t st) {
   if (spans) span_begin(m, st, &ta);
   if (m->discrete) e = launch_drain_set(m->sset[p], m->set_slots, m->touched[p], tc, st);
   if (e == hipSuccess)
-    e = radix_sort_u32(m->touched[p], m->touched_tmp, tc, m->touched_cap, m->hist, st);
+    e = sort_u32(m->touched[p], m->touched_tmp, tc, m->hist, st);
   if (spans) span_end(m, st, ST_FINALIZE, ta);
   return e;
 }

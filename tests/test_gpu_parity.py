@@ -834,6 +834,48 @@ def test_partition_monitors_in_a_group_mix_group_and_own_scans(all_partitioned):
         gm.close()
 
 
+# ------------------------------------------------------------ the sort
+# The sampled sources are sorted by their top 8 bits into 256 buckets, then
+# each bucket in LDS (up to 12288 keys) or in global memory (more).  With
+# tau = 0 every pair is sampled: one source sending 20000 pairs fills one
+# bucket past the LDS capacity; empty slices, a single pair and sources
+# spread over every bucket cover the rest.
+
+def _sort_stream(seed):
+    def gen(s):
+        rng = np.random.default_rng(seed * 1000 + s)
+        if s == 1:
+            return np.zeros((0, 2), np.uint32)
+        if s == 2:
+            return np.array([[0xFFFFFFFF, 5]], np.uint32)
+        heavy = np.stack([np.full(20000, 0x80000001 + s, np.uint32),
+                          rng.integers(0, 2 ** 32, size=20000, dtype=np.uint64).astype(np.uint32)], 1)
+        spread = rng.integers(0, 2 ** 32, size=(15000, 2), dtype=np.uint64).astype(np.uint32)
+        # duplicates of a few sources in other buckets
+        dup = np.stack([rng.integers(0, 16, size=5000).astype(np.uint32) << np.uint32(28),
+                        rng.integers(0, 2 ** 32, size=5000, dtype=np.uint64).astype(np.uint32)], 1)
+        p = np.concatenate([heavy, spread, dup])
+        return p[rng.permutation(len(p))]
+    return gen
+
+
+@pytest.mark.parametrize("hold", [False, True])
+def test_sort_heavy_bucket_and_edges(hold):
+    mon = dict(k=3, theta=4, u=4, v_re=128, g=8, v_le=32, G=64, hash_seed=8801)
+    _run_streaming(_sort_stream(31), mon, range(6), graph=True, ahead=True, hold_scans=hold,
+                   scan_partition=True)
+    g = srla.Monitor(**mon, max_candidates=1 << 16)
+    o = oracle.Monitor(**mon)
+    gen = _sort_stream(32)
+    for s in range(6):
+        p = gen(s)
+        if len(p):
+            g.scan(to_device(p))
+        o.scan(p)
+        compare_reports(g.estimate(), o.estimate(), mon["theta"], "plain %d" % s)
+    g.close()
+
+
 # ------------------------------------------------------------ held scans
 # SRLA_CFG_HOLD_SCANS: the next slice's scans wait until the closed slice's
 # report is published; results are unchanged.
