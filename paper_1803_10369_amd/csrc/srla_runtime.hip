@@ -112,8 +112,10 @@ enum Stage { ST_SCAN, ST_SWEEP, ST_FINALIZE, ST_ESTIMATE, ST_SLIDE, ST_REPORT, S
 // PH_SLIDE: without the overlapped report, the tail of the second phase that
 // the report does not wait for: Algorithm 3's carried list and SI counters,
 // and the state moved to the next slice
+// PH_SORT_SNAPSHOT: with held scans and no stage timing, PH_SORT and
+// PH_SNAPSHOT in one launch (a launch boundary costs the stream ~20 us)
 enum Phase { PH_SNAPSHOT = 0, PH_FINISH = 1, PH_FINISH_GO = 2, PH_SORT = 3, PH_SLIDE = 4,
-             PH_N = 5 };
+             PH_SORT_SNAPSHOT = 5, PH_N = 6 };
 
 struct TimedSpan {
   int stage;
@@ -597,6 +599,10 @@ hipError_t enqueue_phase(srla_monitor* m, int phase, int c, hipStream_t st) {
   const bool spans = !m->use_graph;
   const int p = c & 1, q = c % kSets, q_next = (c + 1) % kSets;
   if (phase == PH_SORT) return enqueue_sort(m, p, st);
+  if (phase == PH_SORT_SNAPSHOT) {
+    e = enqueue_sort(m, p, st);
+    return e == hipSuccess ? enqueue_snapshot(m, p, st) : e;
+  }
   if (phase == PH_SLIDE) {
     e = enqueue_slide(m, p, st, m->d_report[q_next].ip);
     if (e == hipSuccess) e = launch_advance(m->cnt, m->tcount + p, m->ps, st);
@@ -1228,19 +1234,26 @@ int srla_close_slice(srla_monitor_t* m) {
   // (with the candidate work when the report copy overlaps the next scans),
   // the second as the estimate (as the report copy when it overlaps)
   hipEvent_t ta;
-  if (m->hold_scans) {
+  int rc = SRLA_OK;
+  if (m->hold_scans && !m->timing) {
     // the scans wait for the report anyway: the sort follows them on their
     // stream, where it neither waits for an event nor queues behind the
-    // previous slice's carried list on the pipeline stream
+    // previous slice's carried list on the pipeline stream; with the
+    // snapshot in the same launch
+    rc = run_phase(m, PH_SORT_SNAPSHOT, (int)(m->slice % kCycle), m->stream);
+    if (rc) return rc;
+  } else {
+    if (m->hold_scans) {
+      if (m->use_graph) span_begin(m, m->stream, &ta);
+      rc = run_phase(m, PH_SORT, (int)(m->slice % kCycle), m->stream);
+      if (rc) return rc;
+      if (m->use_graph) span_end(m, m->stream, ST_FINALIZE, ta);
+    }
     if (m->use_graph) span_begin(m, m->stream, &ta);
-    const int rs = run_phase(m, PH_SORT, (int)(m->slice % kCycle), m->stream);
-    if (rs) return rs;
-    if (m->use_graph) span_end(m, m->stream, ST_FINALIZE, ta);
+    rc = run_phase(m, PH_SNAPSHOT, (int)(m->slice % kCycle), m->stream);
+    if (rc) return rc;
+    if (m->use_graph) span_end(m, m->stream, m->overlap_report ? ST_ESTIMATE : ST_SWEEP, ta);
   }
-  if (m->use_graph) span_begin(m, m->stream, &ta);
-  int rc = run_phase(m, PH_SNAPSHOT, (int)(m->slice % kCycle), m->stream);
-  if (rc) return rc;
-  if (m->use_graph) span_end(m, m->stream, m->overlap_report ? ST_ESTIMATE : ST_SWEEP, ta);
   if (!m->hold_scans) HIP_TRY(m, hipEventRecord(m->ev_snap, m->stream));
   // the next slice's scans reuse the sampled-source list and count of the
   // previous slice's parity: they wait for its second phase (with held

@@ -186,7 +186,20 @@ __device__ __forceinline__ void sort_pass(const uint32_t* src, uint32_t* dst, ui
   const uint32_t t = threadIdx.x, lane = t & (kWave - 1), wave = t / kWave;
   if (t < kBuckets) hc[t] = 0;
   __syncthreads();
-  for (uint32_t i = t; i < s; i += kSortThreads) atomicAdd(&hc[(src[i] >> shift) & 255u], 1u);
+  // the digit counts, one LDS add per digit and wave: a heavy source's
+  // thousands of equal keys would otherwise queue on one counter
+  for (uint32_t r = 0; r < s; r += kSortThreads) {
+    const uint32_t i = r + t;
+    const bool valid = i < s;
+    const uint32_t d = valid ? (src[i] >> shift) & 255u : 0u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bal = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    if (valid && lane_rank(peers) == 0) atomicAdd(&hc[d], (uint32_t)__popcll(peers));
+  }
   __syncthreads();
   // exclusive scan of hc over the first four waves
   uint32_t v = 0, x = 0;
