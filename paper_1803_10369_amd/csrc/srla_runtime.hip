@@ -379,7 +379,12 @@ hipEvent_t pooled_event(srla_monitor* m) {
     m->ev_pool.pop_back();
     return e;
   }
+  // a stage's timing events: only their timestamps are read, so their records
+  // skip the system-scope release (a write-back of the caches that the next
+  // kernel on the stream would wait for)
   hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) == hipSuccess) return e;
+  (void)hipGetLastError();
   if (hipEventCreate(&e) != hipSuccess) return nullptr;
   return e;
 }
