@@ -107,8 +107,10 @@ enum Stage { ST_SCAN, ST_SWEEP, ST_FINALIZE, ST_ESTIMATE, ST_SLIDE, ST_REPORT, S
 // PH_FINISH_GO: the second phase when the next slice's first scan is enqueued
 // behind a scan-start mark (the report copy then waits for that mark)
 // PH_SORT: without the overlapped report, the sort of the closed slice's
-// sampled sources, which the pipeline stream runs as soon as the slice's
-// scans end (beside the snapshot), ahead of the rest of the second phase
+// sampled sources: with held scans on the scan stream after the slice's
+// scans, else on the pipeline stream as soon as they have appended every
+// sampled source (beside the rest of the scan and the snapshot), ahead of
+// the rest of the second phase
 // PH_SLIDE: without the overlapped report, the tail of the second phase that
 // the report does not wait for: Algorithm 3's carried list and SI counters,
 // and the state moved to the next slice
@@ -593,7 +595,10 @@ hipError_t enqueue_candidates(srla_monitor* m, int p, const ReportPtrs& out, hip
 // candidate work, the report (written by the estimate kernel straight into
 // host memory) and the status follow on the pipeline stream, beside those
 // scans, and after them (PH_SLIDE) Algorithm 3's carried list and SI, which
-// the report does not wait for.  With SRLA_CFG_OVERLAP_REPORT the first
+// the report does not wait for; with held scans the sort, the candidate work
+// and the report run on the scan stream as well (the next scans wait for
+// them anyway), and only PH_SLIDE on the pipeline stream.  With
+// SRLA_CFG_OVERLAP_REPORT the first
 // phase also does the candidate work, into the parity's device staging
 // arrays, and the status, and only the PCIe copy of the report overlaps the
 // scans.  c: the slice's index mod kCycle, which fixes its parity (device
