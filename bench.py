@@ -9,15 +9,18 @@ the warm-up slices run, so every warm-up and timed slice closes a full
 window; the timed slices' pairs are generated into device memory before each
 timed segment starts.
 
---mode streaming (default): slice t's DR activity is snapshotted right after
-  its last scan, then the scan of slice t+1 runs on the GPU beside slice t's
-  candidate check and estimate, which write the report to host memory (two
-  HIP streams, the end-of-slice pipeline replayed as HIP graphs; the host
-  closes slice t+1 before it collects the report of slice t).  With a scan
-  form other than the partitioned one (the autotuner picks it), the
-  candidate work runs first (into device memory) and only the report's copy
-  runs beside the next scan (--overlap-report).  The same number of slices
-  then runs in the plain form on the same monitor (`plain` in the output).
+--mode streaming (default): the host closes slice t and issues slice t+1's
+  scans before it collects the report of slice t.  With the partitioned scan
+  (the autotuner's pick on the backbone workloads) slice t+1's scans wait on
+  the device until slice t's report is in host memory (--hold-scans): slice
+  t's sort, DR snapshot, candidate check and estimate follow its scans on the
+  scan stream, and only Algorithm 3's slide of slice t (with the copy of the
+  carried list into the next report) runs beside slice t+1's scans, on a
+  second HIP stream.  With another scan form the candidate work runs first
+  (into device memory) and only the report's copy runs beside the next scan
+  (--overlap-report), its pipeline replayed as HIP graphs.  The same number
+  of slices then runs in the plain form on the same monitor (`plain` in the
+  output).
 --mode plain: each slice is scanned, then estimated.
 
 In both forms the latency is the device time from the start of a slice's
@@ -460,7 +463,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--mode", choices=("plain", "streaming", "batched"), default="streaming")
     ap.add_argument("--graph", type=int, default=-1,
-                    help="replay the end-of-slice pipeline as HIP graphs (default: streaming only)")
+                    help="replay the end-of-slice pipeline as HIP graphs (default: the streaming "
+                         "form without held scans only)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="pick the scan kernel's form and workgroup cap by timing them first")
     ap.add_argument("--scan-blocks", type=int, default=0,
@@ -549,7 +553,6 @@ def main():
 
     if args.calib_copy_mb:
         calibration_copy(args.calib_copy_mb)
-    graph = (args.mode == "streaming") if args.graph < 0 else bool(args.graph)
     buf = torch.empty(2 * n_pairs, dtype=torch.int32, device="cuda")
     tuned = None
     if args.autotune:
@@ -574,6 +577,11 @@ def main():
     # report is in host memory (its end-of-slice work then runs alone)
     hold = (args.mode == "streaming" and not overlap) if args.hold_scans < 0 \
         else bool(args.hold_scans)
+    # HIP graphs for the overlapped-report form's pipeline; with held scans
+    # the slice end runs on the scan stream, where kernels launched one by
+    # one follow each other with no gap, while each graph launch leaves ~10-20
+    # us (16.5 against 16.0-16.1 G packets/s on the backbone workload)
+    graph = (args.mode == "streaming" and not hold) if args.graph < 0 else bool(args.graph)
     m = srla.Monitor(**mon, max_candidates=args.max_candidates, timing=True, stream=st,
                      scan_xcd=args.scan_xcd, graph=graph, scan_blocks=args.scan_blocks,
                      lean_report=not args.full_report, scan_dedup=args.scan_dedup,
