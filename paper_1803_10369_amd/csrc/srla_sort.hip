@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_words(uint32_t* __restric
 
 // ------------------------------------------------------------------ sort
 // Keys-only ascending sort in three launches, whatever the count (read on
-// the device): the slice's few 10^4 sampled sources take about 20 us instead
+// the device): the slice's few 10^4 sampled sources take about 30 us instead
 // of the 70 us of a four-pass LSD radix sort's twelve small launches.
 //   k_bucket_count: how many keys have each value of the top 8 bits (256
 //     buckets), added into cnt[];
@@ -108,8 +108,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_words(uint32_t* __restric
 //     atomic add on cur[]) and scatters its keys there, in no particular
 //     order; block 0 writes the buckets' starts;
 //   k_bucket_sort: one workgroup per bucket sorts it by the low 24 bits in
-//     three stable 8-bit counting passes, in LDS when it fits and in place in
-//     global memory when it does not (a heavy source can fill one bucket),
+//     three stable 8-bit counting passes, in LDS when it fits (the copies of
+//     a key that fills a quarter of the bucket set aside first) and in place
+//     in global memory when it does not (a heavy source can fill one bucket),
 //     then clears its bucket's counters for the next sort.
 // The 768-word scratch `aux` holds cnt[256], cur[256] and start[256]; cnt and
 // cur are zero between sorts (cleared when the scratch is allocated).
@@ -257,6 +258,7 @@ __global__ __launch_bounds__(kSortThreads) void k_bucket_sort(uint32_t* __restri
   __shared__ uint32_t la[kSortLds], lb[kSortLds];
   __shared__ uint32_t hc[kBuckets], base[kBuckets], w16[kSortWaves];
   __shared__ uint32_t wcnt[kSortWaves][kBuckets];
+  __shared__ uint32_t n_eq, n_oth;
   const uint32_t b = blockIdx.x, t = threadIdx.x;
   const uint32_t s = aux[b];
   const uint32_t start = aux[2 * kBuckets + b];
@@ -274,11 +276,57 @@ __global__ __launch_bounds__(kSortThreads) void k_bucket_sort(uint32_t* __restri
   }
   if (s <= kSortLds) {
     for (uint32_t i = t; i < s; i += kSortThreads) la[i] = tmp[start + i];
+    if (t == 0) {
+      n_eq = 0u;
+      n_oth = 0u;
+    }
     __syncthreads();
-    sort_pass(la, lb, s, 0, hc, base, wcnt, w16);
-    sort_pass(lb, la, s, 8, hc, base, wcnt, w16);
-    sort_pass(la, lb, s, 16, hc, base, wcnt, w16);
-    for (uint32_t i = t; i < s; i += kSortThreads) keys[start + i] = lb[i];
+    // A heavy source fills its bucket with one key: the keys equal to a
+    // pivot (the bucket's middle entry, in no particular order after the
+    // scatter) are set aside and only the others sorted, when the pivot
+    // holds at least a quarter of the bucket.  Correct for any pivot.
+    const uint32_t pivot = la[s / 2];
+    const uint32_t lane = t & (kWave - 1);
+    for (uint32_t r = 0; r < s; r += kSortThreads) {   // uniform trip count
+      const uint32_t i = r + t;
+      const bool valid = i < s;
+      const uint32_t key = valid ? la[i] : 0u;
+      const uint64_t eq = __ballot(valid && key == pivot);
+      const uint64_t oth = __ballot(valid && key != pivot);
+      uint32_t at = 0;
+      if (lane == 0) {
+        if (eq) atomicAdd(&n_eq, (uint32_t)__popcll(eq));
+        if (oth) at = atomicAdd(&n_oth, (uint32_t)__popcll(oth));
+      }
+      at = __shfl(at, 0);
+      if (valid && key != pivot) lb[at + lane_rank(oth)] = key;
+    }
+    __syncthreads();
+    const uint32_t c_eq = n_eq, c_oth = n_oth;
+    if (4u * c_eq >= s) {
+      // the others: lb -> la -> lb -> la, then the pivot's run where it
+      // belongs among them
+      sort_pass(lb, la, c_oth, 0, hc, base, wcnt, w16);
+      sort_pass(la, lb, c_oth, 8, hc, base, wcnt, w16);
+      sort_pass(lb, la, c_oth, 16, hc, base, wcnt, w16);
+      if (t == 0) {
+        uint32_t lo = 0, hi = c_oth;   // first index whose key is not below the pivot
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) / 2;
+          if (la[mid] < pivot) lo = mid + 1; else hi = mid;
+        }
+        n_eq = lo;   // reused: the count of others below the pivot
+      }
+      __syncthreads();
+      const uint32_t below = n_eq;
+      for (uint32_t i = t; i < s; i += kSortThreads)
+        keys[start + i] = i < below ? la[i] : i < below + c_eq ? pivot : la[i - c_eq];
+    } else {
+      sort_pass(la, lb, s, 0, hc, base, wcnt, w16);
+      sort_pass(lb, la, s, 8, hc, base, wcnt, w16);
+      sort_pass(la, lb, s, 16, hc, base, wcnt, w16);
+      for (uint32_t i = t; i < s; i += kSortThreads) keys[start + i] = lb[i];
+    }
   } else {
     // in place: tmp -> keys -> tmp -> keys over the bucket's own ranges
     sort_pass(tmp + start, keys + start, s, 0, hc, base, wcnt, w16);

@@ -836,10 +836,12 @@ def test_partition_monitors_in_a_group_mix_group_and_own_scans(all_partitioned):
 
 # ------------------------------------------------------------ the sort
 # The sampled sources are sorted by their top 8 bits into 256 buckets, then
-# each bucket in LDS (up to 12288 keys) or in global memory (more).  With
-# tau = 0 every pair is sampled: one source sending 20000 pairs fills one
-# bucket past the LDS capacity; empty slices, a single pair and sources
-# spread over every bucket cover the rest.
+# each bucket in LDS (up to 12288 keys; when one key fills at least a quarter
+# of the bucket, only the other keys are sorted) or in global memory (more).
+# With tau = 0 every pair is sampled: one source sending 20000 pairs fills
+# one bucket past the LDS capacity, 8000 pairs leave it in LDS beside 3000
+# other keys of the same bucket, below and above it; empty slices, a single
+# pair and sources spread over every bucket cover the rest.
 
 def _sort_stream(seed):
     def gen(s):
@@ -848,8 +850,12 @@ def _sort_stream(seed):
             return np.zeros((0, 2), np.uint32)
         if s == 2:
             return np.array([[0xFFFFFFFF, 5]], np.uint32)
-        heavy = np.stack([np.full(20000, 0x80000001 + s, np.uint32),
-                          rng.integers(0, 2 ** 32, size=20000, dtype=np.uint64).astype(np.uint32)], 1)
+        n_heavy = 20000 if s % 2 == 0 else 8000
+        heavy = np.stack([np.full(n_heavy, 0x80800001 + s, np.uint32),
+                          rng.integers(0, 2 ** 32, size=n_heavy, dtype=np.uint64).astype(np.uint32)], 1)
+        same = np.stack([np.uint32(0x80000000) | rng.integers(0, 2 ** 24, size=3000).astype(np.uint32),
+                         rng.integers(0, 2 ** 32, size=3000, dtype=np.uint64).astype(np.uint32)], 1)
+        heavy = np.concatenate([heavy, same])
         spread = rng.integers(0, 2 ** 32, size=(15000, 2), dtype=np.uint64).astype(np.uint32)
         # duplicates of a few sources in other buckets
         dup = np.stack([rng.integers(0, 16, size=5000).astype(np.uint32) << np.uint32(28),
