@@ -57,7 +57,13 @@ enum {
                               either way, only the speed differs */
     SRLA_CFG_GRAPH = 4,    /* record the end-of-slice pipeline once per slice
                               parity as HIP graphs and replay them; results
-                              are identical either way */
+                              are identical either way.  Graphs save the host
+                              the launches; on the device each graph launch
+                              leaves a gap of 10-20 us, which kernels
+                              launched one by one on the same stream do not,
+                              so with SRLA_CFG_HOLD_SCANS (the slice end on
+                              the scan stream) launching kernel by kernel was
+                              faster (16.5 against 16.0 G packets/s) */
     SRLA_CFG_DISCRETE = 8, /* the discrete-window form (Section 3.2: with
                               k = 1 a one-bit DR suffices; Section 5.1 runs
                               it with z = 1): every DR is one bit, set by the
