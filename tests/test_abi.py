@@ -68,6 +68,28 @@ int main(void) {
     assert [int(x) for x in out] == want
 
 
+def test_binding_constants_match_header(P, tmp_path):
+    """The binding's config flags, dump selectors, report flags and timing
+    mode against what a C compiler makes of include/srla.h."""
+    import subprocess
+    names = ["SRLA_CFG_TIMING", "SRLA_CFG_SCAN_XCD", "SRLA_CFG_GRAPH", "SRLA_CFG_DISCRETE",
+             "SRLA_CFG_LEAN_REPORT", "SRLA_CFG_SCAN_DEDUP", "SRLA_CFG_SCAN_LDS_FILTER",
+             "SRLA_CFG_OVERLAP_REPORT", "SRLA_CFG_SCAN_PARTITION", "SRLA_CFG_HOLD_SCANS",
+             "SRLA_DUMP_LE", "SRLA_DUMP_RE", "SRLA_DUMP_SI", "SRLA_FLAG_SUPER", "SRLA_FLAG_SAT",
+             "SRLA_FLAG_NEW", "SRLA_FLAG_KEEP", "SRLA_TIMING_SCANS"]
+    names = [n for n in names if hasattr(P.srla, n)]
+    assert "SRLA_TIMING_SCANS" in names and "SRLA_CFG_HOLD_SCANS" in names
+    src = tmp_path / "consts.c"
+    src.write_text('#include <stdio.h>\n#include "srla.h"\nint main(void) {\n' +
+                   "".join('  printf("%%ld\\n", (long)(%s));\n' % n for n in names) +
+                   "  return 0;\n}\n")
+    exe = tmp_path / "consts"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    assert [int(x) for x in out] == [getattr(P.srla, n) for n in names]
+
+
 BAD = [
     dict(k=0), dict(k=32768), dict(theta=0), dict(u=0), dict(u=17), dict(g=0), dict(g=65),
     dict(G=0), dict(G=100), dict(G=32), dict(v_re=0), dict(v_le=0),
