@@ -469,6 +469,41 @@ def test_group_fused_scan_matches_each_members_oracle(streaming):
         gm.close()
 
 
+@pytest.mark.parametrize("partitioned", [False, True])
+def test_group_with_held_scans_matches_each_members_oracle(partitioned):
+    """Members with SRLA_CFG_HOLD_SCANS: each member's slice end runs on the
+    group's scan stream, in order, the slides on the shared pipeline stream,
+    and the next group scan follows them; the host runs a slice ahead."""
+    st = torch.cuda.Stream()
+    mons = [dict(k=k, theta=t, u=u, v_re=vr, g=g, v_le=vl, G=G, hash_seed=91 + i)
+            for i, (k, t, u, vr, g, vl, G) in enumerate(GROUP)]
+    gms = [srla.Monitor(**m, max_candidates=1 << 16, stream=st, graph=bool(i % 2),
+                        hold_scans=True, scan_partition=partitioned)
+           for i, m in enumerate(mons)]
+    oms = [oracle.Monitor(**m) for m in mons]
+    grp = srla.Group(gms, scan_blocks=0)
+    gen = _rand_stream(9, 30_000, 2500, 400)
+    expected = None
+    for s in range(7):
+        p = gen(s)
+        grp.scan(to_device(p))
+        for o in oms:
+            o.scan(p)
+        if expected is not None:
+            for gm, e, m in zip(gms, expected, mons):
+                compare_reports(gm.wait_report(), e, m["theta"], "slice %d" % (s - 1))
+        expected = [o.estimate() for o in oms]
+        for gm in gms:
+            gm.close_slice()
+    for gm, e, m in zip(gms, expected, mons):
+        compare_reports(gm.wait_report(), e, m["theta"], "last slice")
+    for gm, o in zip(gms, oms):
+        compare_dumps(gm, o)
+    grp.close()
+    for gm in gms:
+        gm.close()
+
+
 def test_group_rejects_mixed_streams_and_duplicates():
     stream, mon, _ = workload("tiny")
     a = srla.Monitor(**mon, max_candidates=1 << 10)
